@@ -1,0 +1,291 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the DEC beam-propagation hot path on one MI355X.
+
+A "step" is one z step of the whole hot path (merged Strang step: Kerr +
+absorber substep, four fused RK4 stage kernels of the DEC Laplacian) over the
+step-index workload: graded disk of radius 40 with ~250k vertices, core of
+radius 5 with index contrast 1, absorber ring r > 35 (quadratic up to 0.5),
+tilted elliptic Gaussian launch (waists 2 and 4, 30 degrees, amplitude 1.2),
+dz = 5e-4, gamma = 1, complex64.  The metric is vertex z-steps per second
+(vertices x steps / device time), measured with HIP events on the stream the
+kernels run on, inputs already resident in HBM.
+
+Also reported on the same JSON line:
+  roofline      the RK4 stage kernel (4 of 5 launches per step): algorithmic
+                bytes per launch / mean launch time (HIP events over
+                graph-captured back-to-back launches) against 8 TB/s
+  cpu_baseline  the FP64 CPU oracle on the same mesh and launch, a bounded
+                prefix of steps, single thread
+  parity        GPU vs oracle after the same prefix (relative L2)
+  extras        complex128 throughput; batched photonic-crystal-fibre mode vs
+                per-instance plain launches; checkpointed adjoint vs forward
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true", help="only the timed propagation (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2608_03587_amd import api
+    from paper_2608_03587_amd.inputs import workloads as W
+
+    if not torch.cuda.is_available():
+        log("no HIP device")
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    tdt = {"c64": torch.complex64, "c128": torch.complex128}
+
+    t0 = time.time()
+    w = W.step_index()
+    N = w.mesh.n_vert
+    log(f"[bench] step_index mesh: {N} vertices, {w.mesh.n_tri} triangles ({time.time() - t0:.1f} s)")
+
+    def make(dtype):
+        m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=dtype, p1=w.p1, beta4=w.beta4)
+        m.autotune(w.dz, w.gamma)
+        return m
+
+    def timed_propagate(m, dtype, steps, warmup):
+        u0 = torch.from_numpy(w.u0).to(dev, tdt[dtype])
+        f = u0.clone()
+        m.propagate(f, w.dz, warmup, w.gamma)
+        f = u0.clone()
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        m.propagate(f, w.dz, steps, w.gamma)
+        s1.record()
+        torch.cuda.synchronize()
+        m.check_finite()
+        return s0.elapsed_time(s1), f
+
+    m = make(args.dtype)
+    log(f"[bench] tuned launch shape {m.tuning}; rho*dz = {m.spectral_radius() * w.dz:.3f}")
+    ms, field = timed_propagate(m, args.dtype, args.steps, args.warmup)
+    value = N * args.steps / (ms * 1e-3)
+    log(f"[bench] {args.dtype}: {args.steps} steps in {ms:.2f} ms -> {value:.4e} vertex z-steps/s")
+    if args.profile:
+        print(json.dumps({"metric": "vertex z-steps/s", "value": value, "profile_only": True}))
+        return
+
+    kt = m.time_kernels(w.dz, w.gamma, reps=200)
+    st = kt["stage"]
+    achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
+    log(f"[bench] kernel means (ms): " + ", ".join(f"{k} {v['ms'] * 1e3:.2f}us" for k, v in kt.items()))
+    roofline = {"bound": "hbm", "kernel": "k_stage (RK4 stage: L gather + stage update)",
+                "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                "traffic": None, "bytes_per_launch": st["bytes"], "launch_us": st["ms"] * 1e3,
+                "kernels_us": {k: v["ms"] * 1e3 for k, v in kt.items()},
+                "working_set_MB": None}
+
+    out = {
+        "metric": "vertex z-steps/s",
+        "value": value,
+        "unit": "vertex z-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"step_index: graded disk R=40, {N} vertices, core r<5 dn*k0=1, absorber r>35 "
+                               f"(w<=0.5), tilted elliptic Gaussian, dz={w.dz}, gamma={w.gamma}, NL_DEC",
+                   "vertices": N, "dz": w.dz, "tuning": m.tuning},
+        "roofline": roofline,
+    }
+
+    # ---- CPU oracle baseline and parity on the same prefix ----
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import dec, stepper
+
+        with threadpool_limits(limits=1):
+            t1 = time.time()
+            ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, beta4=w.beta4)
+            t_asm = time.time() - t1
+            psi = w.u0.copy()
+            n_cpu = 0
+            t1 = time.time()
+            while time.time() - t1 < args.cpu_seconds or n_cpu < 5:
+                psi = stepper.strang_step(psi, w.dz, w.gamma, ops)
+                n_cpu += 1
+            t_cpu = time.time() - t1
+        cpu_rate = N * n_cpu / t_cpu
+        out["cpu_baseline"] = {"value": cpu_rate, "unit": "vertex z-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{n_cpu} steps of the same {N}-vertex workload (FP64 NumPy/SciPy, "
+                                         f"single thread; assembly {t_asm:.1f} s excluded)",
+                               "cpu": cpu_model(), "host_cpus": os.cpu_count()}
+        log(f"[bench] oracle: {n_cpu} steps in {t_cpu:.1f} s -> {cpu_rate:.3e} vertex z-steps/s")
+        g = torch.from_numpy(w.u0).to(dev, tdt[args.dtype])
+        m.propagate(g, w.dz, n_cpu, w.gamma)
+        got = g.cpu().numpy().astype(np.complex128)
+        err = float(np.linalg.norm(got - psi) / np.linalg.norm(psi))
+        out["parity"] = {"rel_l2_vs_oracle": err, "steps": n_cpu, "gate": 1e-4 if args.dtype == "c64" else 1e-10,
+                         "pass": err < (1e-4 if args.dtype == "c64" else 1e-10)}
+        log(f"[bench] parity after {n_cpu} steps: rel L2 {err:.3e}")
+
+    # ---- extras ----
+    if not args.no_extras:
+        extras = {}
+        other = "c128" if args.dtype == "c64" else "c64"
+        try:
+            m2 = make(other)
+            ms2, _ = timed_propagate(m2, other, args.steps, args.warmup)
+            kt2 = m2.time_kernels(w.dz, w.gamma, reps=200)["stage"]
+            extras[other] = {"value": N * args.steps / (ms2 * 1e-3), "ms_per_step": ms2 / args.steps,
+                             "stage_GBps": kt2["bytes"] / (kt2["ms"] * 1e-3) / 1e9, "tuning": m2.tuning}
+            log(f"[bench] {other}: {extras[other]['value']:.4e} vertex z-steps/s")
+            del m2
+        except Exception as e:  # noqa: BLE001
+            extras[other] = {"error": repr(e)}
+        try:
+            extras["batched"] = bench_batched(api, W, torch, dev, tdt)
+        except Exception as e:  # noqa: BLE001
+            extras["batched"] = {"error": repr(e)}
+        try:
+            extras["adjoint"] = bench_adjoint(api, W, torch, dev, tdt)
+        except Exception as e:  # noqa: BLE001
+            extras["adjoint"] = {"error": repr(e)}
+        out["extras"] = extras
+    print(json.dumps(out))
+
+
+def bench_batched(api, W, torch, dev, tdt):
+    """256 fields on 8 photonic-crystal-fibre meshes (20k-200k vertices), 2000 steps, complex64:
+    one batched propagation vs per-instance plain propagations (one field per mesh timed at full
+    length, scaled by the 32 fields each mesh carries)."""
+    import numpy as np
+
+    t0 = time.time()
+    ws = W.batched_pcf()
+    F = ws[0].u0.shape[0]
+    n_steps, dz = ws[0].n_steps, ws[0].dz
+    log(f"[bench] batched: meshes {[x.mesh.n_vert for x in ws]} x {F} fields ({time.time() - t0:.1f} s)")
+    meshes = [api.Mesh(x.mesh.xy, x.mesh.tri, x.index_tri, x.absorber, dtype="c64") for x in ws]
+    batch = api.Batch(meshes, F)
+    packed0 = batch.pack([torch.from_numpy(x.u0).to(dev, tdt["c64"]) for x in ws])
+    p = packed0.clone()
+    batch.propagate(p, dz, 50, 1.0)  # warm-up
+    p = packed0.clone()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    batch.propagate(p, dz, n_steps, 1.0)
+    e1.record()
+    torch.cuda.synchronize()
+    t_b = e0.elapsed_time(e1)
+    outs = batch.unpack(p)
+    vf = sum(x.mesh.n_vert for x in ws) * F
+    # plain: the first field of every mesh, full length, autotuned per mesh
+    t_plain = 0.0
+    same = True
+    for m, x, o in zip(meshes, ws, outs):
+        m.autotune(dz, 1.0)
+        f = torch.from_numpy(x.u0[0]).to(dev, tdt["c64"])
+        m.propagate(f.clone(), dz, 20, 1.0)
+        torch.cuda.synchronize()
+        e0.record()
+        m.propagate(f, dz, n_steps, 1.0)
+        e1.record()
+        torch.cuda.synchronize()
+        t_plain += e0.elapsed_time(e1) * F
+        same &= bool(torch.equal(o[0].contiguous(), f))
+    kt = batch.time_kernels(dz, 1.0, reps=20)["stage"]
+    res = {"vertex_field_steps_per_s": vf * n_steps / (t_b * 1e-3), "ms": t_b,
+           "plain_ms_extrapolated": t_plain, "speedup_vs_plain": t_plain / t_b,
+           "stage_GBps": kt["bytes"] / (kt["ms"] * 1e-3) / 1e9, "stage_frac_hbm": kt["bytes"] / (kt["ms"] * 1e-3) / 8e12,
+           "batched_equals_plain_bitwise": same, "fields": F * len(ws), "vertex_fields": vf, "steps": n_steps,
+           "note": "plain = 8 fields (one per mesh) timed at full length x 32"}
+    log(f"[bench] batched: {res['vertex_field_steps_per_s']:.3e} vertex-field z-steps/s, "
+        f"{res['speedup_vs_plain']:.1f}x plain, bitwise equal {same}")
+    return res
+
+
+def bench_adjoint(api, W, torch, dev, tdt):
+    """Adjoint workload: 500k-vertex multimode fibre, 2000 steps, sqrt(N) checkpoints, complex64."""
+    t0 = time.time()
+    w = W.adjoint_mmf()
+    n, dz = w.n_steps, w.dz
+    log(f"[bench] adjoint mesh: {w.mesh.n_vert} vertices ({time.time() - t0:.1f} s)")
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype="c64")
+    m.autotune(dz, w.gamma)
+    m.set_index_perturbation(torch.from_numpy(w.extra["dn"]).to(dev))
+    u0 = torch.from_numpy(w.u0).to(dev, tdt["c64"])
+    tgt = torch.from_numpy(w.extra["target"]).to(dev, tdt["c64"])
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    f = u0.clone()
+    m.propagate(f, dz, 20, w.gamma)
+    f = u0.clone()
+    torch.cuda.synchronize()
+    ev[0].record()
+    m.propagate(f, dz, n, w.gamma)
+    ev[1].record()
+    ws = torch.empty(m.workspace_size(n), dtype=torch.uint8, device=dev)
+    g = u0.clone()
+    ev[2].record()
+    m.forward_checkpointed(g, dz, n, w.gamma, ws)
+    ev[3].record()
+    c = m.overlap(tgt, g)
+    h0 = torch.from_numpy(m.export_operators()["h0"]).to(dev)
+    gout = (2 * c * h0 * tgt.to(torch.complex128)).to(torch.complex64)
+    torch.cuda.synchronize()
+    ev[4].record()
+    g0, gdn = m.adjoint(gout, dz, n, w.gamma, ws)
+    ev[5].record()
+    torch.cuda.synchronize()
+    t_f, t_c, t_a = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), ev[4].elapsed_time(ev[5])
+    res = {"forward_ms": t_f, "checkpointed_forward_ms": t_c, "adjoint_ms": t_a, "adjoint_over_forward": t_a / t_f,
+           "total_over_forward": (t_c + t_a) / t_f, "workspace_MB": ws.numel() / 2**20,
+           "vertices": w.mesh.n_vert, "steps": n, "objective": abs(c) ** 2,
+           "grad_finite": bool(torch.isfinite(torch.view_as_real(g0)).all() and torch.isfinite(gdn).all())}
+    log(f"[bench] adjoint: {t_a / t_f:.2f}x forward (checkpointed fwd + adjoint {res['total_over_forward']:.2f}x)")
+    return res
+
+
+if __name__ == "__main__":
+    main()

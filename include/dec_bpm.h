@@ -1,0 +1,257 @@
+/*
+ * dec_bpm.h - C ABI of the MI355X (gfx950) DEC beam-propagation library.
+ *
+ * The library marches the nonlinear Schroedinger equation along z on an
+ * unstructured triangular mesh of the transverse plane, with the discrete
+ * exterior calculus (DEC) operators of the paper:
+ *
+ *   i dPsi/dz = H_lin Psi - gamma (M |Psi|^2) Psi - i w Psi,
+ *   H_lin     = p1 L + beta4 L^2 - diag(v + dn),
+ *   L         = H0^{-1} D0^T H1 D0     (Eq. 11, stiffness part; L ~ -Laplacian),
+ *   M         = H0^{-1} Q^T D Q         (Eq. 14; or diag(chibar), "lumped"),
+ *   v         = H0^{-1} H0(V)           (per-triangle pulse potential, "Discrete Hodge star").
+ *
+ * Sign reading: Table I gives the Laplacian as -H0^{-1} D0^T H1 D0 and Eq. 1
+ * puts -p1 Laplacian on the right-hand side, so the stiffness enters H_lin
+ * with a plus sign (Eq. 11 as printed would flip it); the potential guides and
+ * the Kerr term focuses.  The higher-order term is the cascaded product of
+ * Table I with coefficient +beta4.
+ *
+ * One z step of length h is the Strang composition
+ *   NL(h/2) -> LIN(h) -> NL(h/2),
+ * where LIN(h) is one classical fourth-order Runge-Kutta step of
+ * dPsi/dz = -i H_lin Psi (the explicit RK4 the paper names for DEC-BPM) and
+ * NL(tau) is the exact flow of the Kerr phase and absorber damping:
+ *   psi_p <- psi_p e^{-w_p tau} exp(i gamma sum_q M_pq |psi_q|^2 phi(w_q, tau)),
+ *   phi(w, tau) = (1 - e^{-2 w tau}) / (2 w).
+ * Consecutive half steps of successive z steps are merged into one NL(h).
+ *
+ * Conventions shared by every call:
+ *  - Fields are complex vectors over the vertices in the CALLER's vertex
+ *    order: interleaved (re, im) pairs of float (DEC_BPM_C64) or double
+ *    (DEC_BPM_C128), contiguous, 8/16-byte aligned, in DEVICE memory owned by
+ *    the caller.  The library never frees caller memory and keeps no pointer
+ *    to it after a call returns.
+ *  - "stream" is a hipStream_t (NULL = the null stream).  Every call is
+ *    asynchronous on that stream unless it says it synchronises.
+ *  - Return value: DEC_BPM_OK (0) or a negative DEC_BPM_E* code; the message
+ *    is available from dec_bpm_last_error() on the same thread.  Arguments
+ *    are validated before any device work, so a rejected call changes
+ *    nothing.  No C++ exception or abort crosses this interface.
+ *  - A handle must not be used from two threads at once; distinct handles are
+ *    independent.
+ */
+#ifndef DEC_BPM_H
+#define DEC_BPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dec_bpm_s* dec_bpm_t;
+typedef struct dec_bpm_batch_s* dec_bpm_batch_t;
+
+enum {
+  DEC_BPM_OK = 0,
+  DEC_BPM_EINVAL = -1,     /* bad argument (NULL pointer, size, option)          */
+  DEC_BPM_EMESH = -2,      /* degenerate / non-manifold / inconsistent mesh      */
+  DEC_BPM_EUNSTABLE = -3,  /* dz * rho(H_lin) exceeds the RK4 stability margin   */
+  DEC_BPM_ENOMEM = -4,     /* device or host allocation failed                   */
+  DEC_BPM_EHIP = -5,       /* a HIP runtime call failed                          */
+  DEC_BPM_ENONFINITE = -6, /* NaN/Inf found in a field                           */
+  DEC_BPM_EWORKSPACE = -7, /* workspace too small or not matching the run        */
+  DEC_BPM_ENODEVICE = -8   /* handle was created host-only; no device work       */
+};
+
+typedef enum { DEC_BPM_C64 = 1, DEC_BPM_C128 = 2 } dec_bpm_dtype;
+typedef enum { DEC_BPM_NL_DEC = 0, DEC_BPM_NL_LUMPED = 1 } dec_bpm_nl;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(dec_bpm_options); set by dec_bpm_default_options */
+  int32_t dtype;          /* dec_bpm_dtype, default DEC_BPM_C64                       */
+  double p1;              /* coefficient of L, default 0.5                           */
+  double beta4;           /* coefficient of L^2 (Table I cascaded product), default 0 */
+  int32_t nonlinearity;   /* dec_bpm_nl, default DEC_BPM_NL_DEC (Eq. 14)              */
+  int32_t reorder;        /* 1: Hilbert space-filling-curve vertex order (default)    */
+  const double* chi_tri;  /* [T] Kerr coefficient per triangle (Eq. 14), NULL = 1     */
+  int32_t host_only;      /* 1: assemble on the host only (no device allocation);
+                             for dec_bpm_export_operators and argument checks        */
+  int32_t block_size;     /* threads per workgroup, 0 = library default / autotuned   */
+  int32_t steps_per_graph;/* z steps captured per hipGraph, 0 = default; 1 disables   */
+} dec_bpm_options;
+
+/* Fill *opt with the defaults above. */
+void dec_bpm_default_options(dec_bpm_options* opt);
+
+/* Thread-local message describing the last failure on this thread. */
+const char* dec_bpm_last_error(void);
+
+/* Library version string. */
+const char* dec_bpm_version(void);
+
+/*
+ * Build the operators of the semi-discrete ODE (Eq. 10) for one mesh.
+ *   xy[2*n_vert]        vertex coordinates (x0, y0, x1, y1, ...), host memory
+ *   tri[3*n_tri]        vertex indices per triangle, host memory; any
+ *                       orientation (each triangle is re-ordered
+ *                       counter-clockwise, the paper's convention)
+ *   index_tri[n_tri]    potential V_t per triangle, taken at its centroid
+ *                       ("Discrete Hodge star"); NULL = 0
+ *   absorber_vert[n_vert] absorber strength w_p >= 0 per vertex; NULL = off
+ *   opt                 options (NULL = defaults)
+ *   out                 receives the handle
+ * Host arrays are copied; the caller may free them on return.  Device storage
+ * (operators in a space-filling-curve order, work vectors) is owned by the
+ * handle until dec_bpm_destroy.  Errors: EINVAL, EMESH (zero-area triangle,
+ * index out of range, repeated vertex, edge shared by more than two triangles
+ * or traversed twice in one direction, unreferenced vertex), ENOMEM, EHIP.
+ */
+int dec_bpm_create(const double* xy, int64_t n_vert, const int32_t* tri, int64_t n_tri,
+                   const double* index_tri, const double* absorber_vert,
+                   const dec_bpm_options* opt, dec_bpm_t* out);
+
+/* Release every resource of the handle (NULL is a no-op). */
+void dec_bpm_destroy(dec_bpm_t h);
+
+/* Number of vertices, triangles, edges; nnz of L counting the diagonal. */
+int dec_bpm_sizes(dec_bpm_t h, int64_t* n_vert, int64_t* n_tri, int64_t* n_edge, int64_t* nnz);
+
+/* Upper estimate of the spectral radius of H_lin (host Lanczos, FP64); the
+ * propagate calls reject dz * rho > 2.5 (the RK4 limit on the imaginary axis
+ * is 2 sqrt 2). */
+int dec_bpm_spectral_radius(dec_bpm_t h, double* rho);
+
+/*
+ * Copy the host-assembled operators out, in the caller's vertex order and FP64
+ * (for checks against an independent assembly).  Call once with col/kval/mval
+ * NULL to get *nnz, then with arrays of that length.
+ *   h0[n], v[n], w[n]   diag of H0, vertex potential (incl. dn), absorber
+ *   row_ptr[n+1], col[nnz], kval[nnz]   CSR of K = D0^T H1 D0 (diagonal included)
+ *   mval[nnz]           Q^T D Q on the same pattern (NL_DEC) or diag(H0 chibar)
+ * Works on host-only handles.
+ */
+int dec_bpm_export_operators(dec_bpm_t h, double* h0, double* v, double* w, int64_t* nnz,
+                             int64_t* row_ptr, int32_t* col, double* kval, double* mval);
+
+/*
+ * Set the per-vertex index perturbation dn (added to v after averaging,
+ * unit coupling); dn_dev is a device array of n_vert doubles in caller order,
+ * or NULL to reset to 0.  Synchronises (dn is also folded into the stability
+ * bound on the host).
+ */
+int dec_bpm_set_index_perturbation(dec_bpm_t h, const double* dn_dev, void* stream);
+
+/* Operator application (parity hooks for the hot kernels), caller order:
+ *   DEC_BPM_OP_L:  y = L x;   DEC_BPM_OP_L2: y = L (L x);
+ *   DEC_BPM_OP_H:  y = H_lin x.
+ * x and y are distinct device complex vectors of n_vert entries. */
+enum { DEC_BPM_OP_L = 0, DEC_BPM_OP_L2 = 1, DEC_BPM_OP_H = 2 };
+int dec_bpm_apply(dec_bpm_t h, int op, const void* x, void* y, void* stream);
+
+/* One Kerr/absorber substep NL(tau), in place (caller order). */
+int dec_bpm_kerr_step(dec_bpm_t h, void* field, double tau, double gamma, void* stream);
+
+/* One linear RK4 step LIN(h) of dPsi/dz = -i H_lin Psi, in place. */
+int dec_bpm_linear_step(dec_bpm_t h, void* field, double dz, void* stream);
+
+/*
+ * The hot path: n_steps Strang steps of length dz, in place on `field`
+ * (caller order).  gamma is the Kerr coefficient (Eq. 1 normalised, q_NL).
+ * n_steps == 0 is a no-op.  Errors: EINVAL, EUNSTABLE, EHIP, ENODEVICE.
+ * NaN/Inf in the result are flagged on the device and reported by
+ * dec_bpm_check_finite.
+ */
+int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream);
+
+/* Synchronise `stream` and return ENONFINITE if the last propagate produced a
+ * non-finite value (the flag is cleared), else OK. */
+int dec_bpm_check_finite(dec_bpm_t h, void* stream);
+
+/*
+ * Diagnostics of a field (caller order), FP64 accumulation, synchronises:
+ *   power       = sum_p H0_p |psi_p|^2 (conserved without absorber)
+ *   hamiltonian = Psi^H H0 H_lin Psi - (gamma/2) sum_t chi_t |t| (mean_t |psi|^2)^2
+ *                 (lumped: - (gamma/2) sum_p H0_p chibar_p |psi_p|^4).
+ * Either output pointer may be NULL.
+ */
+int dec_bpm_diagnostics(dec_bpm_t h, const void* field, double gamma, double* power, double* hamiltonian,
+                        void* stream);
+
+/* H0-weighted inner product c = sum_p H0_p conj(a_p) b_p; synchronises. */
+int dec_bpm_overlap(dec_bpm_t h, const void* a, const void* b, double* re, double* im, void* stream);
+
+/*
+ * Checkpointed forward sweep and its adjoint (gradients of a real objective J
+ * of the final field).  Gradients follow g = dJ/dRe + i dJ/dIm.
+ * dec_bpm_workspace_size gives the bytes of caller-owned device workspace for
+ * a run of n_steps with checkpoints every `every` steps (0 = ceil(sqrt(n))).
+ * dec_bpm_forward_checkpointed propagates `field` in place like
+ * dec_bpm_propagate and stores the checkpoints in the workspace.
+ * dec_bpm_adjoint takes grad_out = dJ/dpsi(z_L) and, using the checkpoints of
+ * the matching forward call (same dz, n_steps, gamma, every, dn), returns
+ * grad_field0 = dJ/dpsi(0) (complex, caller order) and, if grad_dn is not
+ * NULL, grad_dn = dJ/d(dn) (double[n_vert], caller order).  Each segment
+ * between checkpoints is recomputed forward, storing its stage vectors, then
+ * swept backward.  Errors: EINVAL, EWORKSPACE, EUNSTABLE, EHIP.
+ */
+int dec_bpm_workspace_size(dec_bpm_t h, int64_t n_steps, int64_t every, size_t* bytes);
+int dec_bpm_forward_checkpointed(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma,
+                                 int64_t every, void* workspace, size_t ws_bytes, void* stream);
+int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_steps, double gamma, int64_t every,
+                    void* workspace, size_t ws_bytes, void* grad_field0, double* grad_dn, void* stream);
+
+/*
+ * Batched propagation of many fields on many meshes in one launch per kernel
+ * stage.  All meshes must share dtype, p1, beta4 and nonlinearity mode and
+ * carry `fields_per_mesh` fields each.  The packed field layout is
+ * field-minor, per mesh in the order given: element (mesh m, caller vertex i,
+ * field f) sits at complex offset base_m + i * fields_per_mesh + f, with
+ * base_m = fields_per_mesh * (n_0 + ... + n_{m-1}).  The batch holds its own
+ * copy of the operators; the mesh handles may be destroyed afterwards.
+ */
+int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, int32_t fields_per_mesh,
+                         dec_bpm_batch_t* out);
+void dec_bpm_batch_destroy(dec_bpm_batch_t b);
+/* Total packed complex elements (sum_m n_m * fields_per_mesh). */
+int dec_bpm_batch_size(dec_bpm_batch_t b, int64_t* n_elems);
+int dec_bpm_batch_propagate(dec_bpm_batch_t b, void* packed_fields, double dz, int64_t n_steps, double gamma,
+                            void* stream);
+
+/*
+ * Launch tuning.  dec_bpm_autotune times candidate (block size, steps per
+ * graph) pairs on the handle's own work buffers with HIP events and keeps the
+ * fastest; the result is cached in the JSON file named by DEC_BPM_TUNE_CACHE
+ * if that variable is set.  Synchronises.
+ */
+typedef struct {
+  int32_t block_size;
+  int32_t steps_per_graph;
+} dec_bpm_tuning;
+int dec_bpm_autotune(dec_bpm_t h, double dz, double gamma, void* stream);
+int dec_bpm_get_tuning(dec_bpm_t h, dec_bpm_tuning* t);
+int dec_bpm_set_tuning(dec_bpm_t h, const dec_bpm_tuning* t);
+
+/*
+ * Per-kernel timing with HIP events on `stream`: runs `reps` z steps and
+ * writes the mean device time in milliseconds of each kernel class into
+ * ms[DEC_BPM_NUM_KERNELS] and the algorithmic bytes one launch of it moves
+ * into bytes[DEC_BPM_NUM_KERNELS] (either may be NULL).  Synchronises.
+ */
+enum {
+  DEC_BPM_K_KERR = 0,   /* fused Kerr phase + absorber (M gather)               */
+  DEC_BPM_K_STAGE = 1,  /* RK4 stage: L gather + stage update                   */
+  DEC_BPM_K_LAP = 2,    /* bare L application (first half of a beta4 stage)    */
+  DEC_BPM_NUM_KERNELS = 3
+};
+int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
+                         void* stream);
+int dec_bpm_batch_time_kernels(dec_bpm_batch_t b, double dz, double gamma, int32_t reps, double* ms,
+                               double* bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEC_BPM_H */

@@ -1,0 +1,1159 @@
+// Host runtime and C ABI of the DEC beam-propagation library (MI355X, gfx950).
+//
+// A handle owns one "engine": the operators of one mesh (or of a batch of
+// meshes concatenated block-diagonally) in device order, the work vectors of
+// the z march, and a cache of instantiated hipGraphs of the step loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/dec_bpm.h"
+#include "assembly.hpp"
+#include "kernels.hpp"
+
+namespace decbpm {
+
+thread_local std::string g_last_error;
+
+#define HIP_OK(expr)                                                                                     \
+  do {                                                                                                   \
+    hipError_t e_ = (expr);                                                                              \
+    if (e_ != hipSuccess) fail(DEC_BPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+// Largest dz * rho(H_lin) accepted: the classical RK4 stability region covers
+// the imaginary axis up to 2 sqrt(2); keep a margin below it.
+constexpr double kStabilityLimit = 2.5;
+
+struct GraphEntry {
+  double dz, gamma;
+  int spg, block, xcd;
+  hipGraphExec_t exec;
+  hipGraph_t graph;
+};
+
+struct Engine {
+  int dtype = DEC_BPM_C64;
+  int64_t n_rows = 0;  // device rows
+  int32_t F = 1;
+  double p1 = 0.5, beta4 = 0.0;
+  int nl = DEC_BPM_NL_DEC;
+  double rho = 0.0;
+  double dn_max = 0.0;
+  int64_t nnz_off = 0;     // stored off-diagonal neighbours (no padding)
+  int64_t n_entries = 0;   // sliced-ELL entries including padding
+  bool on_device = false;
+  // device operators
+  int64_t* sl_off = nullptr;
+  int32_t* sl_w = nullptr;
+  int32_t* col = nullptr;
+  void* lw = nullptr;
+  void* mw = nullptr;
+  void* mdiag = nullptr;
+  void* v = nullptr;
+  void* v0 = nullptr;
+  void* w = nullptr;
+  double* h0 = nullptr;
+  double* h0c = nullptr;  // caller order
+  int32_t* perm = nullptr;
+  // work
+  void* psi = nullptr;
+  void* ya = nullptr;
+  void* yb = nullptr;
+  void* t = nullptr;
+  void* s = nullptr;
+  double* partials = nullptr;
+  double* red_out = nullptr;
+  int* flag = nullptr;
+  int n_red_blocks = 1;
+  // launch shape
+  int block = 256;
+  int spg = 32;
+  int xcd = 1;
+  hipStream_t cap = nullptr;
+  std::vector<GraphEntry> graphs;
+  std::vector<void*> allocs;
+  // record of the last checkpointed forward (validated by the adjoint)
+  struct {
+    const void* ws = nullptr;
+    double dz = 0, gamma = 0;
+    int64_t n = -1, every = 0;
+    uint64_t dn_version = 0;
+  } ckpt;
+  uint64_t dn_version = 0;
+
+  size_t real_size() const { return dtype == DEC_BPM_C64 ? 4 : 8; }
+  size_t cplx_size() const { return 2 * real_size(); }
+
+  template <typename T>
+  DevOps<T> ops() const {
+    DevOps<T> d;
+    d.n_rows = n_rows;
+    d.F = F;
+    d.sl_off = sl_off;
+    d.sl_w = sl_w;
+    d.col = col;
+    d.lw = static_cast<const T*>(lw);
+    d.mw = static_cast<const T*>(mw);
+    d.mdiag = static_cast<const T*>(mdiag);
+    d.v = static_cast<const T*>(v);
+    d.w = static_cast<const T*>(w);
+    d.h0 = h0;
+    d.p1 = T(p1);
+    d.beta4 = T(beta4);
+    d.xcd_remap = xcd;
+    return d;
+  }
+
+  void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(DEC_BPM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    allocs.push_back(p);
+    return p;
+  }
+
+  void release() {
+    for (auto& g : graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
+    graphs.clear();
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+    if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
+  }
+
+  void drop_graphs() {
+    for (auto& g : graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
+    graphs.clear();
+  }
+};
+
+// Default launch shape from the environment (used before any autotuning).
+static void env_defaults(Engine& E) {
+  if (const char* s = std::getenv("DEC_BPM_BLOCK")) E.block = std::max(64, std::min(1024, std::atoi(s)));
+  if (const char* s = std::getenv("DEC_BPM_STEPS_PER_GRAPH")) E.spg = std::max(1, std::atoi(s));
+  if (const char* s = std::getenv("DEC_BPM_XCD_REMAP")) E.xcd = std::atoi(s) ? 1 : 0;
+}
+
+template <typename T>
+static void upload(Engine& E, void*& dst, const std::vector<T>& src) {
+  dst = E.dalloc(src.size() * sizeof(T));
+  HIP_OK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// Build the device engine from one or more assembled meshes (concatenated).
+template <typename T>
+static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshes, const std::vector<int>& lumped) {
+  int64_t n = 0;
+  for (auto* a : meshes) n += a->n;
+  E.n_rows = n;
+  const int64_t n_sl = (n + 63) / 64;
+  std::vector<int64_t> sl_off(n_sl + 1, 0);
+  std::vector<int32_t> sl_w(n_sl, 0);
+  // per device row: mesh id, local row
+  std::vector<int32_t> row_mesh(n), row_local(n);
+  std::vector<int64_t> mesh_off(meshes.size() + 1, 0);
+  for (size_t m = 0; m < meshes.size(); ++m) mesh_off[m + 1] = mesh_off[m] + meshes[m]->n;
+  for (size_t m = 0; m < meshes.size(); ++m)
+    for (int64_t i = 0; i < meshes[m]->n; ++i) {
+      row_mesh[mesh_off[m] + i] = int32_t(m);
+      row_local[mesh_off[m] + i] = int32_t(i);
+    }
+  auto degree = [&](int64_t r) {
+    const Assembled& a = *meshes[row_mesh[r]];
+    const int32_t p = a.perm[row_local[r]];
+    return int32_t(a.rp[p + 1] - a.rp[p] - 1);
+  };
+  E.nnz_off = 0;
+  for (int64_t s = 0; s < n_sl; ++s) {
+    int32_t wmax = 0;
+    for (int64_t r = s * 64; r < std::min(n, (s + 1) * 64); ++r) {
+      int32_t dg = degree(r);
+      wmax = std::max(wmax, dg);
+      E.nnz_off += dg;
+    }
+    sl_w[s] = wmax;
+    sl_off[s + 1] = sl_off[s] + int64_t(wmax) * 64;
+  }
+  E.n_entries = sl_off[n_sl];
+  std::vector<int32_t> col(E.n_entries, 0);
+  std::vector<T> lw(E.n_entries, T(0)), mw(E.n_entries, T(0));
+  std::vector<T> mdiag(n), v0(n), w(n);
+  std::vector<double> h0(n), h0c(n);
+  std::vector<int32_t> perm(n);
+  bool any_dec = false;
+  for (int64_t r = 0; r < n; ++r) {
+    const int m = row_mesh[r];
+    const Assembled& a = *meshes[m];
+    const int64_t off = mesh_off[m];
+    const int32_t p = a.perm[row_local[r]];
+    const double hp = a.h0[p];
+    perm[r] = int32_t(off + p);
+    h0[r] = hp;
+    h0c[off + p] = hp;
+    v0[r] = T(a.v[p]);
+    w[r] = T(a.w[p]);
+    // neighbours sorted by device column
+    std::vector<std::pair<int32_t, int64_t>> nb;
+    for (int64_t e = a.rp[p]; e < a.rp[p + 1]; ++e) {
+      if (a.col[e] == p) {
+        mdiag[r] = T(lumped[m] ? a.chibar[p] : a.qdq[e] / hp);
+        continue;
+      }
+      nb.emplace_back(int32_t(off + a.iperm[a.col[e]]), e);
+    }
+    std::sort(nb.begin(), nb.end());
+    const int64_t s = r >> 6, lane = r & 63;
+    for (int k = 0; k < sl_w[s]; ++k) {
+      const int64_t slot = sl_off[s] + int64_t(k) * 64 + lane;
+      if (k < int(nb.size())) {
+        col[slot] = nb[k].first;
+        lw[slot] = T(-a.k[nb[k].second] / hp);
+        mw[slot] = lumped[m] ? T(0) : T(a.qdq[nb[k].second] / hp);
+      } else {
+        col[slot] = int32_t(r);  // padding: self, zero weights
+      }
+    }
+    if (!lumped[m]) any_dec = true;
+  }
+  // lanes past the last row of the last slice
+  for (int64_t r = n; r < n_sl * 64; ++r) {
+    const int64_t s = r >> 6, lane = r & 63;
+    for (int k = 0; k < sl_w[s]; ++k) col[sl_off[s] + int64_t(k) * 64 + lane] = 0;
+  }
+  void* p;
+  upload(E, p, sl_off);
+  E.sl_off = static_cast<int64_t*>(p);
+  upload(E, p, sl_w);
+  E.sl_w = static_cast<int32_t*>(p);
+  upload(E, p, col);
+  E.col = static_cast<int32_t*>(p);
+  upload(E, E.lw, lw);
+  if (any_dec) upload(E, E.mw, mw);
+  upload(E, E.mdiag, mdiag);
+  upload(E, E.v0, v0);
+  upload(E, E.v, v0);
+  upload(E, E.w, w);
+  upload(E, p, h0);
+  E.h0 = static_cast<double*>(p);
+  upload(E, p, h0c);
+  E.h0c = static_cast<double*>(p);
+  upload(E, p, perm);
+  E.perm = static_cast<int32_t*>(p);
+  const size_t nv = size_t(n) * E.F;
+  E.psi = E.dalloc(nv * 2 * sizeof(T));
+  E.ya = E.dalloc(nv * 2 * sizeof(T));
+  E.yb = E.dalloc(nv * 2 * sizeof(T));
+  E.t = E.beta4 != 0.0 ? E.dalloc(nv * 2 * sizeof(T)) : nullptr;
+  E.s = E.dalloc(nv * sizeof(T));
+  E.n_red_blocks = int((n + 255) / 256);
+  E.partials = static_cast<double*>(E.dalloc(2 * size_t(std::max(E.n_red_blocks, 1)) * sizeof(double)));
+  E.red_out = static_cast<double*>(E.dalloc(2 * sizeof(double)));
+  E.flag = static_cast<int*>(E.dalloc(sizeof(int)));
+  HIP_OK(hipMemset(E.flag, 0, sizeof(int)));
+  HIP_OK(hipStreamCreateWithFlags(&E.cap, hipStreamNonBlocking));
+  E.on_device = true;
+}
+
+static void build_engine(Engine& E, const std::vector<const Assembled*>& meshes, const std::vector<int>& lumped) {
+  env_defaults(E);
+  if (E.dtype == DEC_BPM_C64)
+    build_engine_t<float>(E, meshes, lumped);
+  else
+    build_engine_t<double>(E, meshes, lumped);
+}
+
+static void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+}
+
+// ---- one z step on the engine's device-order state psi (F fields per row) ----
+// LIN(dz) as a Horner evaluation of the RK4 polynomial (identical to the four
+// classical stages for a linear autonomous system), then NL(tau_next).
+template <typename T>
+static void lin_step(const Engine& E, const DevOps<T>& d, const void* in, void* out, void* y1, void* y2, void* y3,
+                     double dz, void* s_out, double tau_s, hipStream_t st) {
+  const int B = E.block;
+  const void* t = nullptr;
+  // y1 = psi + dz/4 A psi;  y2 = psi + dz/3 A y1;  y3 = psi + dz/2 A y2;  out = psi + dz A y3
+  const void* xs[4] = {in, y1, y2, y3};
+  void* ys[4] = {y1, y2, y3, out};
+  const double cs[4] = {dz / 4, dz / 3, dz / 2, dz};
+  for (int k = 0; k < 4; ++k) {
+    if (E.beta4 != 0.0) {
+      launch_lap<T>(d, xs[k], E.t, B, st);
+      t = E.t;
+    }
+    launch_stage<T>(d, xs[k], t, in, ys[k], cs[k], k == 3 ? s_out : nullptr, tau_s, B, st);
+  }
+}
+
+template <typename T>
+static void z_step(const Engine& E, const DevOps<T>& d, double dz, double gamma, double tau_next, hipStream_t st) {
+  // buffers: y1 -> ya, y2 -> yb, y3 -> ya (y1 is dead once y2 exists), result in place on psi
+  lin_step<T>(E, d, E.psi, E.psi, E.ya, E.yb, E.ya, dz, E.s, tau_next, st);
+  launch_kerr<T>(d, E.psi, E.psi, E.s, tau_next, gamma, E.block, st);
+}
+
+template <typename T>
+static hipGraphExec_t get_graph(Engine& E, double dz, double gamma) {
+  for (auto& g : E.graphs)
+    if (g.dz == dz && g.gamma == gamma && g.spg == E.spg && g.block == E.block && g.xcd == E.xcd) return g.exec;
+  const DevOps<T> d = E.ops<T>();
+  hipGraph_t graph;
+  HIP_OK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < E.spg; ++k) z_step<T>(E, d, dz, gamma, dz, E.cap);
+  hipError_t le = hipGetLastError();
+  HIP_OK(hipStreamEndCapture(E.cap, &graph));
+  if (le != hipSuccess) fail(DEC_BPM_EHIP, std::string("launch during capture: ") + hipGetErrorString(le));
+  hipGraphExec_t exec;
+  HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  if (E.graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(E.graphs.front().exec);
+    (void)hipGraphDestroy(E.graphs.front().graph);
+    E.graphs.erase(E.graphs.begin());
+  }
+  E.graphs.push_back(GraphEntry{dz, gamma, E.spg, E.block, E.xcd, exec, graph});
+  return exec;
+}
+
+static void check_stability(const Engine& E, double dz) {
+  const double r = (E.rho + E.dn_max) * dz;
+  if (!(r <= kStabilityLimit)) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "dz * rho(H_lin) = %.4g exceeds the RK4 stability margin %.2f (rho = %.6g)", r,
+                  kStabilityLimit, E.rho + E.dn_max);
+    fail(DEC_BPM_EUNSTABLE, buf);
+  }
+}
+
+// Every argument check runs on the host before any device work (so a rejected
+// call changes nothing); a host-only handle gets through all of them and then
+// reports ENODEVICE.
+static void check_prop_args(const Engine& E, const void* field, double dz, int64_t n_steps, double gamma) {
+  if (!field) fail(DEC_BPM_EINVAL, "field is NULL");
+  if (reinterpret_cast<uintptr_t>(field) % E.cplx_size() != 0) fail(DEC_BPM_EINVAL, "field is misaligned");
+  if (!(dz > 0) || !std::isfinite(dz)) fail(DEC_BPM_EINVAL, "dz must be finite and > 0");
+  if (n_steps < 0) fail(DEC_BPM_EINVAL, "n_steps must be >= 0");
+  if (!std::isfinite(gamma)) fail(DEC_BPM_EINVAL, "gamma must be finite");
+  check_stability(E, dz);
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+}
+
+// Middle steps (merged NL(dz)) through graph replays, then the remainder eagerly.
+template <typename T>
+static void run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st) {
+  const DevOps<T> d = E.ops<T>();
+  int64_t done = 0;
+  if (E.spg > 1 && count >= E.spg) {
+    hipGraphExec_t ex = get_graph<T>(E, dz, gamma);
+    for (; done + E.spg <= count; done += E.spg) HIP_OK(hipGraphLaunch(ex, st));
+  }
+  for (; done < count; ++done) z_step<T>(E, d, dz, gamma, dz, st);
+}
+
+template <typename T>
+static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gamma, hipStream_t st) {
+  if (n == 0) return;
+  const DevOps<T> d = E.ops<T>();
+  const int B = E.block;
+  launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
+  launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
+  launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
+  run_middle<T>(E, n - 1, dz, gamma, st);
+  z_step<T>(E, d, dz, gamma, 0.5 * dz, st);
+  launch_perm_out<T>(d, E.perm, E.psi, field, 0, E.flag, B, st);
+  check_launch();
+}
+
+static void propagate(Engine& E, void* field, double dz, int64_t n, double gamma, hipStream_t st) {
+  if (E.dtype == DEC_BPM_C64)
+    propagate_t<float>(E, field, dz, n, gamma, st);
+  else
+    propagate_t<double>(E, field, dz, n, gamma, st);
+}
+
+// ---- checkpointed forward and adjoint ----
+struct WsLayout {
+  int64_t K = 0, S = 0;
+  size_t x0 = 0, ck = 0, sa = 0, sy = 0, sb = 0, ua = 0, ub = 0, acc = 0, lam = 0, sm = 0, gdn = 0, total = 0;
+};
+
+static WsLayout ws_layout(const Engine& E, int64_t n_steps, int64_t every) {
+  WsLayout L;
+  L.S = every > 0 ? every : std::max<int64_t>(1, int64_t(std::ceil(std::sqrt(double(std::max<int64_t>(n_steps, 1))))));
+  L.K = std::max<int64_t>(1, (n_steps + L.S - 1) / L.S);
+  const size_t vb = (size_t(E.n_rows) * E.cplx_size() + 255) / 256 * 256;
+  size_t off = 0;
+  auto take = [&](size_t count) {
+    size_t o = off;
+    off += count * vb;
+    return o;
+  };
+  L.x0 = take(1);
+  L.ck = take(L.K);
+  L.sa = take(L.S + 1);
+  L.sy = take(3 * L.S);
+  L.sb = take(L.S);
+  L.ua = take(1);
+  L.ub = take(1);
+  L.acc = take(1);
+  L.lam = take(1);
+  L.sm = take(1);
+  L.gdn = off;
+  off += (size_t(E.n_rows) * sizeof(double) + 255) / 256 * 256;
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+static void forward_ckpt_t(Engine& E, void* field, double dz, int64_t n, double gamma, int64_t every, char* ws,
+                           hipStream_t st) {
+  const WsLayout L = ws_layout(E, n, every);
+  const DevOps<T> d = E.ops<T>();
+  const int B = E.block;
+  const size_t vb = (size_t(E.n_rows) * E.cplx_size() + 255) / 256 * 256;
+  launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
+  if (n > 0) {
+    launch_copy<T>(E.n_rows, E.psi, ws + L.x0, B, st);
+    launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
+    launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
+    launch_copy<T>(E.n_rows, E.psi, ws + L.ck, B, st);
+    for (int64_t k = 1; k <= n; ++k) {
+      z_step<T>(E, d, dz, gamma, k < n ? dz : 0.5 * dz, st);
+      if (k % L.S == 0 && k / L.S < L.K) launch_copy<T>(E.n_rows, E.psi, ws + L.ck + size_t(k / L.S) * vb, B, st);
+    }
+  }
+  launch_perm_out<T>(d, E.perm, E.psi, field, 0, E.flag, B, st);
+  check_launch();
+}
+
+template <typename T>
+static void adjoint_t(Engine& E, const void* grad_out, double dz, int64_t n, double gamma, int64_t every, char* ws,
+                      void* grad0, double* grad_dn, hipStream_t st) {
+  const WsLayout L = ws_layout(E, n, every);
+  const DevOps<T> d = E.ops<T>();
+  const int B = E.block;
+  const size_t vb = (size_t(E.n_rows) * E.cplx_size() + 255) / 256 * 256;
+  void* lam = ws + L.lam;
+  void* acc = ws + L.acc;
+  void* ua = ws + L.ua;
+  void* ub = ws + L.ub;
+  void* sm = ws + L.sm;
+  double* gdn = reinterpret_cast<double*>(ws + L.gdn);
+  // lambda = H0^{-1} g in device order
+  launch_perm_in<T>(d, E.perm, grad_out, lam, 1, B, st);
+  launch_zero_f64(E.n_rows, gdn, B, st);
+  auto A = [&](int64_t j) -> void* { return ws + L.sa + size_t(j) * vb; };
+  auto Y = [&](int64_t j, int k) -> void* { return ws + L.sy + size_t(3 * (j - 1) + k) * vb; };
+  auto Bv = [&](int64_t j) -> void* { return ws + L.sb + size_t(j - 1) * vb; };
+  for (int64_t seg = L.K - 1; seg >= 0 && n > 0; --seg) {
+    const int64_t n0 = seg * L.S, n1 = std::min(n, (seg + 1) * L.S), m = n1 - n0;
+    // recompute the segment from its checkpoint, keeping every stage vector
+    launch_copy<T>(E.n_rows, ws + L.ck + size_t(seg) * vb, A(0), B, st);
+    for (int64_t j = 1; j <= m; ++j) {
+      const double tau = (n0 + j < n) ? dz : 0.5 * dz;
+      lin_step<T>(E, d, A(j - 1), Bv(j), Y(j, 0), Y(j, 1), Y(j, 2), dz, E.s, tau, st);
+      launch_kerr<T>(d, Bv(j), A(j), E.s, tau, gamma, B, st);
+    }
+    // reverse sweep
+    for (int64_t j = m; j >= 1; --j) {
+      const double tau = (n0 + j < n) ? dz : 0.5 * dz;
+      launch_adj_prep<T>(d, Bv(j), A(j), lam, sm, tau, gamma, B, st);
+      launch_adj_kerr<T>(d, Bv(j), lam, sm, lam, tau, gamma, B, st);
+      // reverse Horner chain of LIN(dz): links with (coef, cdn, forward vector)
+      const void* uin[4] = {lam, ua, ub, ua};
+      void* uout[4] = {ua, ub, ua, nullptr};
+      const void* yf[4] = {Y(j, 2), Y(j, 1), Y(j, 0), A(j - 1)};
+      const double co[4] = {-dz, -dz / 2, -dz / 3, -dz / 4};
+      const double cd[4] = {dz, dz / 2, dz / 3, dz / 4};
+      for (int k = 0; k < 4; ++k) {
+        const void* t = nullptr;
+        if (E.beta4 != 0.0) {
+          launch_lap<T>(d, uin[k], E.t, B, st);
+          t = E.t;
+        }
+        launch_adj_stage<T>(d, uin[k], t, uout[k], acc, k == 0, yf[k], co[k], cd[k], gdn, B, st);
+      }
+      std::swap(lam, acc);
+    }
+  }
+  if (n > 0) {
+    // first half step NL(dz/2) of the run: x0 -> a_0 (checkpoint 0)
+    launch_adj_prep<T>(d, ws + L.x0, ws + L.ck, lam, sm, 0.5 * dz, gamma, B, st);
+    launch_adj_kerr<T>(d, ws + L.x0, lam, sm, lam, 0.5 * dz, gamma, B, st);
+  }
+  launch_perm_out<T>(d, E.perm, lam, grad0, 1, nullptr, B, st);
+  if (grad_dn) launch_gdn_out(E.n_rows, E.perm, gdn, grad_dn, B, st);
+  check_launch();
+}
+
+// ---- kernel timing with HIP events (graph-captured back-to-back launches) ----
+template <typename T>
+static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double* ms, double* bytes, hipStream_t st) {
+  const DevOps<T> d = E.ops<T>();
+  const int B = E.block;
+  const double sr = sizeof(T), sc = 2 * sizeof(T);
+  const double nF = double(E.n_rows) * E.F, nr = double(E.n_rows);
+  const double mat = double(E.nnz_off) * (4.0 + sr);
+  double by[DEC_BPM_NUM_KERNELS];
+  by[DEC_BPM_K_KERR] = mat + nr * 2 * sr + nF * (sr + 2 * sc);
+  by[DEC_BPM_K_STAGE] = mat + nr * sr + nF * 3 * sc;
+  by[DEC_BPM_K_LAP] = mat + nF * 2 * sc;
+  launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
+  launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
+  launch_prep_s<T>(d, E.psi, E.s, dz, B, st);
+  HIP_OK(hipStreamSynchronize(st));
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  for (int kind = 0; kind < DEC_BPM_NUM_KERNELS; ++kind) {
+    hipGraph_t g;
+    HIP_OK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < reps; ++r) {
+      if (kind == DEC_BPM_K_KERR) launch_kerr<T>(d, E.psi, E.psi, E.s, dz, gamma, B, E.cap);
+      if (kind == DEC_BPM_K_STAGE) launch_stage<T>(d, E.ya, nullptr, E.psi, E.yb, dz / 3, nullptr, 0.0, B, E.cap);
+      if (kind == DEC_BPM_K_LAP) launch_lap<T>(d, E.ya, E.yb, B, E.cap);
+    }
+    HIP_OK(hipStreamEndCapture(E.cap, &g));
+    hipGraphExec_t ex;
+    HIP_OK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    HIP_OK(hipGraphLaunch(ex, st));  // warm-up
+    HIP_OK(hipEventRecord(e0, st));
+    HIP_OK(hipGraphLaunch(ex, st));
+    HIP_OK(hipEventRecord(e1, st));
+    HIP_OK(hipEventSynchronize(e1));
+    float t = 0;
+    HIP_OK(hipEventElapsedTime(&t, e0, e1));
+    if (ms) ms[kind] = double(t) / reps;
+    if (bytes) bytes[kind] = by[kind];
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+// ---- autotuning ----
+static std::string tune_key(const Engine& E) {
+  std::ostringstream o;
+  o << "n" << E.n_rows << "_e" << E.n_entries << "_F" << E.F << "_d" << E.dtype << "_b4" << (E.beta4 != 0.0) << "_nl"
+    << (E.mw ? 0 : 1);
+  return o.str();
+}
+
+static bool tune_cache_lookup(Engine& E) {
+  const char* path = std::getenv("DEC_BPM_TUNE_CACHE");
+  if (!path) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line, key = "\"" + tune_key(E) + "\"";
+  while (std::getline(f, line)) {
+    size_t p = line.find(key);
+    if (p == std::string::npos) continue;
+    int b = 0, s = 0, x = 1;
+    if (std::sscanf(line.c_str() + p + key.size(), ": {\"block\": %d, \"steps_per_graph\": %d, \"xcd\": %d}", &b, &s,
+                    &x) >= 2 &&
+        b >= 64 && s >= 1) {
+      E.block = b;
+      E.spg = s;
+      E.xcd = x;
+      return true;
+    }
+  }
+  return false;
+}
+
+static void tune_cache_store(const Engine& E) {
+  const char* path = std::getenv("DEC_BPM_TUNE_CACHE");
+  if (!path) return;
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line))
+      if (line.find("\"" + tune_key(E) + "\"") == std::string::npos && line.find(": {") != std::string::npos)
+        lines.push_back(line);
+  }
+  std::ofstream f(path);
+  f << "{\n";
+  for (auto& l : lines) {
+    std::string x = l;
+    while (!x.empty() && (x.back() == ',' || x.back() == ' ')) x.pop_back();
+    f << x << ",\n";
+  }
+  f << "  \"" << tune_key(E) << "\": {\"block\": " << E.block << ", \"steps_per_graph\": " << E.spg
+    << ", \"xcd\": " << E.xcd << "}\n}\n";
+}
+
+template <typename T>
+static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
+  if (tune_cache_lookup(E)) return;
+  const DevOps<T> d0 = E.ops<T>();
+  const int blocks[] = {64, 128, 256, 512, 1024};
+  const int spgs[] = {1, 8, 32, 128};
+  const int xcds[] = {0, 1};
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  double best = 1e300;
+  int bb = E.block, bs = E.spg, bx = E.xcd;
+  const int64_t steps = 128;
+  for (int x : xcds)
+    for (int b : blocks)
+      for (int s : spgs) {
+        E.block = b;
+        E.spg = s;
+        E.xcd = x;
+        launch_fill<T>(d0, E.psi, 0.3, 0.1, 256, st);
+        launch_prep_s<T>(d0, E.psi, E.s, dz, 256, st);
+        run_middle<T>(E, s, dz, gamma, st);  // warm-up (and graph instantiation)
+        HIP_OK(hipEventRecord(e0, st));
+        run_middle<T>(E, steps, dz, gamma, st);
+        HIP_OK(hipEventRecord(e1, st));
+        HIP_OK(hipEventSynchronize(e1));
+        float t = 0;
+        HIP_OK(hipEventElapsedTime(&t, e0, e1));
+        if (t < best) {
+          best = t;
+          bb = b;
+          bs = s;
+          bx = x;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  E.drop_graphs();
+  E.block = bb;
+  E.spg = bs;
+  E.xcd = bx;
+  tune_cache_store(E);
+}
+
+}  // namespace decbpm
+
+using decbpm::Engine;
+using decbpm::Error;
+using decbpm::fail;
+
+struct dec_bpm_s {
+  decbpm::Assembled A;
+  dec_bpm_options opt;
+  Engine E;
+  ~dec_bpm_s() { E.release(); }
+};
+
+struct dec_bpm_batch_s {
+  Engine E;
+  std::vector<int64_t> n_per_mesh;
+  ~dec_bpm_batch_s() { E.release(); }
+};
+
+#define ABI_TRY try {
+#define ABI_CATCH                                                              \
+  }                                                                            \
+  catch (const Error& e) {                                                     \
+    decbpm::g_last_error = e.msg;                                              \
+    return e.code;                                                             \
+  }                                                                            \
+  catch (const std::bad_alloc&) {                                              \
+    decbpm::g_last_error = "host allocation failed";                           \
+    return DEC_BPM_ENOMEM;                                                     \
+  }                                                                            \
+  catch (const std::exception& e) {                                            \
+    decbpm::g_last_error = e.what();                                           \
+    return DEC_BPM_EINVAL;                                                     \
+  }                                                                            \
+  catch (...) {                                                                \
+    decbpm::g_last_error = "unknown error";                                    \
+    return DEC_BPM_EINVAL;                                                     \
+  }                                                                            \
+  decbpm::g_last_error.clear();                                                \
+  return DEC_BPM_OK;
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+static dec_bpm_s* need(dec_bpm_t h) {
+  if (!h) fail(DEC_BPM_EINVAL, "handle is NULL");
+  return h;
+}
+
+extern "C" {
+
+void dec_bpm_default_options(dec_bpm_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->struct_size = sizeof(dec_bpm_options);
+  o->dtype = DEC_BPM_C64;
+  o->p1 = 0.5;
+  o->beta4 = 0.0;
+  o->nonlinearity = DEC_BPM_NL_DEC;
+  o->reorder = 1;
+  o->chi_tri = nullptr;
+  o->host_only = 0;
+  o->block_size = 0;
+  o->steps_per_graph = 0;
+}
+
+const char* dec_bpm_last_error(void) { return decbpm::g_last_error.c_str(); }
+
+const char* dec_bpm_version(void) { return "dec_bpm 0.1 (gfx950)"; }
+
+int dec_bpm_create(const double* xy, int64_t n_vert, const int32_t* tri, int64_t n_tri, const double* index_tri,
+                   const double* absorber_vert, const dec_bpm_options* opt, dec_bpm_t* out) {
+  ABI_TRY
+  if (!out) fail(DEC_BPM_EINVAL, "out is NULL");
+  *out = nullptr;
+  dec_bpm_options o;
+  dec_bpm_default_options(&o);
+  if (opt) {
+    if (opt->struct_size != sizeof(dec_bpm_options)) fail(DEC_BPM_EINVAL, "dec_bpm_options.struct_size mismatch");
+    o = *opt;
+  }
+  if (o.dtype != DEC_BPM_C64 && o.dtype != DEC_BPM_C128) fail(DEC_BPM_EINVAL, "dtype must be C64 or C128");
+  if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 1024 || o.block_size % 64 != 0))
+    fail(DEC_BPM_EINVAL, "block_size must be a multiple of 64 in [64, 1024]");
+  if (o.steps_per_graph < 0) fail(DEC_BPM_EINVAL, "steps_per_graph must be >= 0");
+  decbpm::AssemblyInput in;
+  in.xy = xy;
+  in.n = n_vert;
+  in.tri = tri;
+  in.n_tri = n_tri;
+  in.index_tri = index_tri;
+  in.absorber = absorber_vert;
+  in.chi_tri = o.chi_tri;
+  in.p1 = o.p1;
+  in.beta4 = o.beta4;
+  in.nonlinearity = o.nonlinearity;
+  in.reorder = o.reorder != 0;
+  std::unique_ptr<dec_bpm_s> h(new dec_bpm_s());
+  h->A = decbpm::assemble(in);
+  o.chi_tri = nullptr;  // not kept
+  h->opt = o;
+  Engine& E = h->E;
+  E.dtype = o.dtype;
+  E.F = 1;
+  E.p1 = o.p1;
+  E.beta4 = o.beta4;
+  E.nl = o.nonlinearity;
+  E.rho = h->A.rho;
+  if (!o.host_only) {
+    decbpm::build_engine(E, {&h->A}, {o.nonlinearity == DEC_BPM_NL_LUMPED ? 1 : 0});
+    if (o.block_size) E.block = o.block_size;
+    if (o.steps_per_graph) E.spg = o.steps_per_graph;
+  } else {
+    E.n_rows = h->A.n;
+  }
+  *out = h.release();
+  ABI_CATCH
+}
+
+void dec_bpm_destroy(dec_bpm_t h) { delete h; }
+
+int dec_bpm_sizes(dec_bpm_t h, int64_t* n_vert, int64_t* n_tri, int64_t* n_edge, int64_t* nnz) {
+  ABI_TRY
+  need(h);
+  if (n_vert) *n_vert = h->A.n;
+  if (n_tri) *n_tri = h->A.n_tri;
+  if (n_edge) *n_edge = h->A.n_edge;
+  if (nnz) *nnz = h->A.rp.empty() ? 0 : h->A.rp.back();
+  ABI_CATCH
+}
+
+int dec_bpm_spectral_radius(dec_bpm_t h, double* rho) {
+  ABI_TRY
+  need(h);
+  if (!rho) fail(DEC_BPM_EINVAL, "rho is NULL");
+  *rho = h->E.rho + h->E.dn_max;
+  ABI_CATCH
+}
+
+int dec_bpm_export_operators(dec_bpm_t h, double* h0, double* v, double* w, int64_t* nnz, int64_t* row_ptr,
+                             int32_t* col, double* kval, double* mval) {
+  ABI_TRY
+  need(h);
+  const auto& A = h->A;
+  if (nnz) *nnz = A.rp.back();
+  if (h0) std::copy(A.h0.begin(), A.h0.end(), h0);
+  if (v) std::copy(A.v.begin(), A.v.end(), v);
+  if (w) std::copy(A.w.begin(), A.w.end(), w);
+  if (row_ptr) std::copy(A.rp.begin(), A.rp.end(), row_ptr);
+  if (col) std::copy(A.col.begin(), A.col.end(), col);
+  if (kval) std::copy(A.k.begin(), A.k.end(), kval);
+  if (mval) std::copy(A.qdq.begin(), A.qdq.end(), mval);
+  ABI_CATCH
+}
+
+int dec_bpm_set_index_perturbation(dec_bpm_t h, const double* dn_dev, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  hipStream_t st = as_stream(stream);
+  double mx = 0.0;
+  if (dn_dev) {
+    std::vector<double> host(E.n_rows);
+    HIP_OK(hipMemcpyAsync(host.data(), dn_dev, E.n_rows * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (double x : host) {
+      if (!std::isfinite(x)) fail(DEC_BPM_EINVAL, "index perturbation has a non-finite entry");
+      mx = std::max(mx, std::fabs(x));
+    }
+  }
+  if (E.dtype == DEC_BPM_C64)
+    decbpm::launch_set_v<float>(E.n_rows, static_cast<const float*>(E.v0), dn_dev, E.perm, static_cast<float*>(E.v),
+                                256, st);
+  else
+    decbpm::launch_set_v<double>(E.n_rows, static_cast<const double*>(E.v0), dn_dev, E.perm,
+                                 static_cast<double*>(E.v), 256, st);
+  decbpm::check_launch();
+  HIP_OK(hipStreamSynchronize(st));
+  E.dn_max = mx;
+  E.dn_version++;
+  ABI_CATCH
+}
+
+int dec_bpm_apply(dec_bpm_t h, int op, const void* x, void* y, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (!x || !y || x == y) fail(DEC_BPM_EINVAL, "x and y must be distinct non-NULL device vectors");
+  if (op < DEC_BPM_OP_L || op > DEC_BPM_OP_H) fail(DEC_BPM_EINVAL, "unknown operator");
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  hipStream_t st = as_stream(stream);
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    const decbpm::DevOps<T> d = E.ops<T>();
+    const int B = E.block;
+    decbpm::launch_perm_in<T>(d, E.perm, x, E.ya, 0, B, st);
+    decbpm::launch_lap<T>(d, E.ya, E.yb, B, st);  // yb = L x
+    void* res = E.yb;
+    if (op == DEC_BPM_OP_L2) {
+      decbpm::launch_lap<T>(d, E.yb, E.psi, B, st);
+      res = E.psi;
+    } else if (op == DEC_BPM_OP_H) {
+      void* t2 = nullptr;
+      if (E.beta4 != 0.0) {
+        decbpm::launch_lap<T>(d, E.yb, E.t, B, st);
+        t2 = E.t;
+      }
+      decbpm::launch_hcombine<T>(d, E.ya, E.yb, t2, E.psi, B, st);
+      res = E.psi;
+    }
+    decbpm::launch_perm_out<T>(d, E.perm, res, y, 0, nullptr, B, st);
+  };
+  if (E.dtype == DEC_BPM_C64)
+    run(float{});
+  else
+    run(double{});
+  decbpm::check_launch();
+  ABI_CATCH
+}
+
+int dec_bpm_kerr_step(dec_bpm_t h, void* field, double tau, double gamma, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (!field) fail(DEC_BPM_EINVAL, "field is NULL");
+  if (!(tau >= 0) || !std::isfinite(tau) || !std::isfinite(gamma)) fail(DEC_BPM_EINVAL, "bad tau or gamma");
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  hipStream_t st = as_stream(stream);
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    const decbpm::DevOps<T> d = E.ops<T>();
+    decbpm::launch_perm_in<T>(d, E.perm, field, E.psi, 0, E.block, st);
+    decbpm::launch_prep_s<T>(d, E.psi, E.s, tau, E.block, st);
+    decbpm::launch_kerr<T>(d, E.psi, E.psi, E.s, tau, gamma, E.block, st);
+    decbpm::launch_perm_out<T>(d, E.perm, E.psi, field, 0, E.flag, E.block, st);
+  };
+  if (E.dtype == DEC_BPM_C64)
+    run(float{});
+  else
+    run(double{});
+  decbpm::check_launch();
+  ABI_CATCH
+}
+
+int dec_bpm_linear_step(dec_bpm_t h, void* field, double dz, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  decbpm::check_prop_args(E, field, dz, 1, 0.0);
+  hipStream_t st = as_stream(stream);
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    const decbpm::DevOps<T> d = E.ops<T>();
+    decbpm::launch_perm_in<T>(d, E.perm, field, E.psi, 0, E.block, st);
+    decbpm::lin_step<T>(E, d, E.psi, E.psi, E.ya, E.yb, E.ya, dz, nullptr, 0.0, st);
+    decbpm::launch_perm_out<T>(d, E.perm, E.psi, field, 0, E.flag, E.block, st);
+  };
+  if (E.dtype == DEC_BPM_C64)
+    run(float{});
+  else
+    run(double{});
+  decbpm::check_launch();
+  ABI_CATCH
+}
+
+int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream) {
+  ABI_TRY
+  need(h);
+  decbpm::check_prop_args(h->E, field, dz, n_steps, gamma);
+  decbpm::propagate(h->E, field, dz, n_steps, gamma, as_stream(stream));
+  ABI_CATCH
+}
+
+int dec_bpm_check_finite(dec_bpm_t h, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  hipStream_t st = as_stream(stream);
+  int f = 0;
+  HIP_OK(hipMemcpyAsync(&f, E.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (f) {
+    HIP_OK(hipMemsetAsync(E.flag, 0, sizeof(int), st));
+    HIP_OK(hipStreamSynchronize(st));
+    fail(DEC_BPM_ENONFINITE, "a propagated field contains NaN or Inf");
+  }
+  ABI_CATCH
+}
+
+int dec_bpm_diagnostics(dec_bpm_t h, const void* field, double gamma, double* power, double* hamiltonian,
+                        void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (!field) fail(DEC_BPM_EINVAL, "field is NULL");
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  hipStream_t st = as_stream(stream);
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    const decbpm::DevOps<T> d = E.ops<T>();
+    decbpm::launch_perm_in<T>(d, E.perm, field, E.ya, 0, E.block, st);
+    decbpm::launch_diag<T>(d, E.ya, gamma, E.partials, E.n_red_blocks, E.red_out, st);
+  };
+  if (E.dtype == DEC_BPM_C64)
+    run(float{});
+  else
+    run(double{});
+  decbpm::check_launch();
+  double out[2];
+  HIP_OK(hipMemcpyAsync(out, E.red_out, sizeof out, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (power) *power = out[0];
+  if (hamiltonian) *hamiltonian = out[1];
+  ABI_CATCH
+}
+
+int dec_bpm_overlap(dec_bpm_t h, const void* a, const void* b, double* re, double* im, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (!a || !b) fail(DEC_BPM_EINVAL, "a and b must not be NULL");
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  hipStream_t st = as_stream(stream);
+  if (E.dtype == DEC_BPM_C64)
+    decbpm::launch_overlap<float>(E.n_rows, E.h0c, a, b, E.partials, E.n_red_blocks, E.red_out, st);
+  else
+    decbpm::launch_overlap<double>(E.n_rows, E.h0c, a, b, E.partials, E.n_red_blocks, E.red_out, st);
+  decbpm::check_launch();
+  double out[2];
+  HIP_OK(hipMemcpyAsync(out, E.red_out, sizeof out, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (re) *re = out[0];
+  if (im) *im = out[1];
+  ABI_CATCH
+}
+
+int dec_bpm_workspace_size(dec_bpm_t h, int64_t n_steps, int64_t every, size_t* bytes) {
+  ABI_TRY
+  need(h);
+  if (!bytes || n_steps < 0 || every < 0) fail(DEC_BPM_EINVAL, "bad workspace query");
+  *bytes = decbpm::ws_layout(h->E, n_steps, every).total;
+  ABI_CATCH
+}
+
+int dec_bpm_forward_checkpointed(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, int64_t every,
+                                 void* workspace, size_t ws_bytes, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  decbpm::check_prop_args(E, field, dz, n_steps, gamma);
+  if (every < 0) fail(DEC_BPM_EINVAL, "every must be >= 0");
+  const auto L = decbpm::ws_layout(E, n_steps, every);
+  if (!workspace || ws_bytes < L.total)
+    fail(DEC_BPM_EWORKSPACE, "workspace needs " + std::to_string(L.total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) fail(DEC_BPM_EWORKSPACE, "workspace must be 256-byte aligned");
+  char* ws = static_cast<char*>(workspace);
+  if (E.dtype == DEC_BPM_C64)
+    decbpm::forward_ckpt_t<float>(E, field, dz, n_steps, gamma, every, ws, as_stream(stream));
+  else
+    decbpm::forward_ckpt_t<double>(E, field, dz, n_steps, gamma, every, ws, as_stream(stream));
+  E.ckpt.ws = workspace;
+  E.ckpt.dz = dz;
+  E.ckpt.gamma = gamma;
+  E.ckpt.n = n_steps;
+  E.ckpt.every = L.S;
+  E.ckpt.dn_version = E.dn_version;
+  ABI_CATCH
+}
+
+int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_steps, double gamma, int64_t every,
+                    void* workspace, size_t ws_bytes, void* grad_field0, double* grad_dn, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  decbpm::check_prop_args(E, grad_field0, dz, n_steps, gamma);
+  if (!grad_out) fail(DEC_BPM_EINVAL, "grad_out is NULL");
+  const auto L = decbpm::ws_layout(E, n_steps, every);
+  if (!workspace || ws_bytes < L.total)
+    fail(DEC_BPM_EWORKSPACE, "workspace needs " + std::to_string(L.total) + " bytes");
+  if (E.ckpt.ws != workspace || E.ckpt.dz != dz || E.ckpt.gamma != gamma || E.ckpt.n != n_steps ||
+      E.ckpt.every != L.S || E.ckpt.dn_version != E.dn_version)
+    fail(DEC_BPM_EWORKSPACE, "workspace does not hold the checkpoints of a matching forward call");
+  char* ws = static_cast<char*>(workspace);
+  if (E.dtype == DEC_BPM_C64)
+    decbpm::adjoint_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, as_stream(stream));
+  else
+    decbpm::adjoint_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, as_stream(stream));
+  ABI_CATCH
+}
+
+int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, int32_t fields_per_mesh, dec_bpm_batch_t* out) {
+  ABI_TRY
+  if (!out) fail(DEC_BPM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!meshes || n_meshes < 1) fail(DEC_BPM_EINVAL, "need at least one mesh");
+  if (fields_per_mesh < 1) fail(DEC_BPM_EINVAL, "fields_per_mesh must be >= 1");
+  std::vector<const decbpm::Assembled*> list;
+  std::vector<int> lumped;
+  const dec_bpm_s* m0 = meshes[0];
+  if (!m0) fail(DEC_BPM_EINVAL, "NULL mesh handle");
+  double rho = 0;
+  for (int32_t m = 0; m < n_meshes; ++m) {
+    const dec_bpm_s* h = meshes[m];
+    if (!h) fail(DEC_BPM_EINVAL, "NULL mesh handle");
+    if (h->opt.dtype != m0->opt.dtype || h->opt.p1 != m0->opt.p1 || h->opt.beta4 != m0->opt.beta4 ||
+        h->opt.nonlinearity != m0->opt.nonlinearity)
+      fail(DEC_BPM_EINVAL, "all meshes of a batch must share dtype, p1, beta4 and nonlinearity");
+    list.push_back(&h->A);
+    lumped.push_back(h->opt.nonlinearity == DEC_BPM_NL_LUMPED ? 1 : 0);
+    rho = std::max(rho, h->A.rho);
+  }
+  std::unique_ptr<dec_bpm_batch_s> b(new dec_bpm_batch_s());
+  Engine& E = b->E;
+  E.dtype = m0->opt.dtype;
+  E.F = fields_per_mesh;
+  E.p1 = m0->opt.p1;
+  E.beta4 = m0->opt.beta4;
+  E.nl = m0->opt.nonlinearity;
+  E.rho = rho;
+  decbpm::build_engine(E, list, lumped);
+  for (auto* a : list) b->n_per_mesh.push_back(a->n);
+  *out = b.release();
+  ABI_CATCH
+}
+
+void dec_bpm_batch_destroy(dec_bpm_batch_t b) { delete b; }
+
+int dec_bpm_batch_size(dec_bpm_batch_t b, int64_t* n_elems) {
+  ABI_TRY
+  if (!b || !n_elems) fail(DEC_BPM_EINVAL, "NULL argument");
+  *n_elems = b->E.n_rows * b->E.F;
+  ABI_CATCH
+}
+
+int dec_bpm_batch_propagate(dec_bpm_batch_t b, void* packed_fields, double dz, int64_t n_steps, double gamma,
+                            void* stream) {
+  ABI_TRY
+  if (!b) fail(DEC_BPM_EINVAL, "batch is NULL");
+  decbpm::check_prop_args(b->E, packed_fields, dz, n_steps, gamma);
+  decbpm::propagate(b->E, packed_fields, dz, n_steps, gamma, as_stream(stream));
+  ABI_CATCH
+}
+
+int dec_bpm_autotune(dec_bpm_t h, double dz, double gamma, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  decbpm::check_prop_args(E, E.psi, dz, 1, gamma);
+  if (E.dtype == DEC_BPM_C64)
+    decbpm::autotune_t<float>(E, dz, gamma, as_stream(stream));
+  else
+    decbpm::autotune_t<double>(E, dz, gamma, as_stream(stream));
+  ABI_CATCH
+}
+
+int dec_bpm_get_tuning(dec_bpm_t h, dec_bpm_tuning* t) {
+  ABI_TRY
+  need(h);
+  if (!t) fail(DEC_BPM_EINVAL, "NULL tuning");
+  t->block_size = h->E.block;
+  t->steps_per_graph = h->E.spg;
+  ABI_CATCH
+}
+
+int dec_bpm_set_tuning(dec_bpm_t h, const dec_bpm_tuning* t) {
+  ABI_TRY
+  need(h);
+  if (!t || t->block_size < 64 || t->block_size > 1024 || t->block_size % 64 || t->steps_per_graph < 1)
+    fail(DEC_BPM_EINVAL, "bad tuning");
+  h->E.block = t->block_size;
+  h->E.spg = t->steps_per_graph;
+  ABI_CATCH
+}
+
+int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
+                         void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  decbpm::check_prop_args(E, E.psi, dz, 1, gamma);
+  if (reps < 1) fail(DEC_BPM_EINVAL, "reps must be >= 1");
+  if (E.dtype == DEC_BPM_C64)
+    decbpm::time_kernels_t<float>(E, dz, gamma, reps, ms, bytes, as_stream(stream));
+  else
+    decbpm::time_kernels_t<double>(E, dz, gamma, reps, ms, bytes, as_stream(stream));
+  ABI_CATCH
+}
+
+int dec_bpm_batch_time_kernels(dec_bpm_batch_t b, double dz, double gamma, int32_t reps, double* ms, double* bytes,
+                               void* stream) {
+  ABI_TRY
+  if (!b) fail(DEC_BPM_EINVAL, "batch is NULL");
+  Engine& E = b->E;
+  decbpm::check_prop_args(E, E.psi, dz, 1, gamma);
+  if (reps < 1) fail(DEC_BPM_EINVAL, "reps must be >= 1");
+  if (E.dtype == DEC_BPM_C64)
+    decbpm::time_kernels_t<float>(E, dz, gamma, reps, ms, bytes, as_stream(stream));
+  else
+    decbpm::time_kernels_t<double>(E, dz, gamma, reps, ms, bytes, as_stream(stream));
+  ABI_CATCH
+}
+
+}  // extern "C"

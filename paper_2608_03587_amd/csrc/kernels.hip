@@ -1,0 +1,696 @@
+// HIP kernels (gfx950) of the DEC beam-propagation hot path.
+//
+// The operators are sparse stencils (about six off-diagonal neighbours per
+// vertex), so every kernel here is bandwidth/latency bound: one thread per
+// (vertex, field) pair, gathers through the sliced-ELL layout of kernels.hpp,
+// neighbours made local in memory by the Hilbert vertex order, and the
+// pointwise work (RK4 stage update, Kerr phase, absorber damping, the next
+// substep's |psi|^2 phi) fused into the gather kernels so each pass reads and
+// writes every vector once.  No matrix cores: there is no dense contraction.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace decbpm {
+
+namespace {
+
+// ---- scalar math (HIP's device math library) ----
+__device__ inline float d_exp(float x) { return expf(x); }
+__device__ inline double d_exp(double x) { return exp(x); }
+__device__ inline float d_expm1(float x) { return expm1f(x); }
+__device__ inline double d_expm1(double x) { return expm1(x); }
+__device__ inline void d_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ inline void d_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ inline bool d_finite(float x) { return isfinite(x); }
+__device__ inline bool d_finite(double x) { return isfinite(x); }
+
+// integral of e^{-2 w z} over [0, tau]
+template <typename T>
+__device__ inline T phi_w(T w, T tau) {
+  return w > T(0) ? -d_expm1(T(-2) * w * tau) / (T(2) * w) : tau;
+}
+
+template <typename T>
+struct CT;
+template <>
+struct CT<float> {
+  using C = float2;
+};
+template <>
+struct CT<double> {
+  using C = double2;
+};
+
+// Logical block index: with xcd_remap, hardware block b (dispatched round-robin
+// over the 8 XCDs) takes logical block (b % 8) * (grid/8) + b / 8, so each XCD
+// walks one contiguous stretch of the Hilbert-ordered rows and the halo of
+// neighbouring blocks stays in the same L2.
+__device__ inline int64_t logical_block(int32_t remap) {
+  int64_t b = blockIdx.x;
+  if (remap) {
+    const int64_t per = gridDim.x >> 3;
+    b = (b & 7) * per + (b >> 3);
+  }
+  return b;
+}
+
+template <int FB>
+__device__ inline void split(int64_t idx, int32_t F, int64_t& row, int32_t& f) {
+  if (FB == 1) {
+    row = idx;
+    f = 0;
+  } else {
+    row = idx / F;
+    f = int32_t(idx - row * F);
+  }
+}
+
+inline unsigned grid_for(int64_t threads, int block, int remap) {
+  int64_t g = (threads + block - 1) / block;
+  if (remap) g = (g + 7) / 8 * 8;
+  if (g < 1) g = 1;
+  return unsigned(g);
+}
+
+// ---------------------------------------------------------------------------
+// RK4 stage: y = psi + coef * A x,  A = -i H_lin.
+//   B4 = false: H_lin x = p1 L x - v x (one gather of x)
+//   B4 = true : t = L x is given; H_lin x = p1 t + beta4 L t - v x (gather of t)
+// WS: also write s = |y|^2 phi(w, tau_s) for the Kerr substep that follows.
+template <typename T, int FB, bool B4, bool WS>
+__global__ void __launch_bounds__(1024) k_stage(DevOps<T> d, const typename CT<T>::C* __restrict__ x,
+                                                const typename CT<T>::C* __restrict__ t,
+                                                const typename CT<T>::C* psi, typename CT<T>::C* y, T coef,
+                                                T* __restrict__ s_out, T tau_s) {
+  using C = typename CT<T>::C;
+  const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  int64_t row;
+  int32_t f;
+  split<FB>(idx, d.F, row, f);
+  if (row >= d.n_rows) return;
+  const int32_t F = FB == 1 ? 1 : d.F;
+  const C* __restrict__ g = B4 ? t : x;
+  const C gr = g[idx];
+  const C xr = B4 ? x[idx] : gr;
+  const int64_t sl = row >> 6;
+  const int64_t base = d.sl_off[sl] + (row & 63);
+  const int W = d.sl_w[sl];
+  T ar = T(0), ai = T(0);
+  for (int k = 0; k < W; ++k) {
+    const int64_t e = base + int64_t(k) * 64;
+    const int64_t q = d.col[e];
+    const T c = d.lw[e];
+    const C gq = g[q * F + f];
+    ar += c * (gr.x - gq.x);
+    ai += c * (gr.y - gq.y);
+  }
+  const T vr = d.v[row];
+  T hr, hi;
+  if (B4) {
+    hr = d.p1 * gr.x + d.beta4 * ar - vr * xr.x;
+    hi = d.p1 * gr.y + d.beta4 * ai - vr * xr.y;
+  } else {
+    hr = d.p1 * ar - vr * xr.x;
+    hi = d.p1 * ai - vr * xr.y;
+  }
+  const C p = psi[idx];
+  C out;
+  out.x = p.x + coef * hi;  // -i (hr + i hi) = hi - i hr
+  out.y = p.y - coef * hr;
+  y[idx] = out;
+  if (WS) s_out[idx] = (out.x * out.x + out.y * out.y) * phi_w(d.w[row], tau_s);
+}
+
+// t = L x
+template <typename T, int FB>
+__global__ void __launch_bounds__(1024) k_lap(DevOps<T> d, const typename CT<T>::C* __restrict__ x,
+                                              typename CT<T>::C* __restrict__ t) {
+  using C = typename CT<T>::C;
+  const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  int64_t row;
+  int32_t f;
+  split<FB>(idx, d.F, row, f);
+  if (row >= d.n_rows) return;
+  const int32_t F = FB == 1 ? 1 : d.F;
+  const C xr = x[idx];
+  const int64_t sl = row >> 6;
+  const int64_t base = d.sl_off[sl] + (row & 63);
+  const int W = d.sl_w[sl];
+  T ar = T(0), ai = T(0);
+  for (int k = 0; k < W; ++k) {
+    const int64_t e = base + int64_t(k) * 64;
+    const int64_t q = d.col[e];
+    const T c = d.lw[e];
+    const C xq = x[q * F + f];
+    ar += c * (xr.x - xq.x);
+    ai += c * (xr.y - xq.y);
+  }
+  C out;
+  out.x = ar;
+  out.y = ai;
+  t[idx] = out;
+}
+
+template <typename T, int FB>
+__global__ void __launch_bounds__(1024) k_prep_s(DevOps<T> d, const typename CT<T>::C* __restrict__ psi,
+                                                 T* __restrict__ s, T tau) {
+  const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  int64_t row;
+  int32_t f;
+  split<FB>(idx, d.F, row, f);
+  if (row >= d.n_rows) return;
+  const auto p = psi[idx];
+  s[idx] = (p.x * p.x + p.y * p.y) * phi_w(d.w[row], tau);
+}
+
+// Exact Kerr/absorber flow over tau:
+//   psi_out = psi_in e^{-w tau} exp(i gamma Theta),  Theta = M s,  s = |psi|^2 phi(w, tau).
+template <typename T, int FB, bool DEC>
+__global__ void __launch_bounds__(1024) k_kerr(DevOps<T> d, const typename CT<T>::C* psi_in,
+                                               typename CT<T>::C* psi_out, const T* __restrict__ s, T tau,
+                                               T gamma) {
+  using C = typename CT<T>::C;
+  const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  int64_t row;
+  int32_t f;
+  split<FB>(idx, d.F, row, f);
+  if (row >= d.n_rows) return;
+  const int32_t F = FB == 1 ? 1 : d.F;
+  T th = d.mdiag[row] * s[idx];
+  if (DEC) {
+    const int64_t sl = row >> 6;
+    const int64_t base = d.sl_off[sl] + (row & 63);
+    const int W = d.sl_w[sl];
+    for (int k = 0; k < W; ++k) {
+      const int64_t e = base + int64_t(k) * 64;
+      th += d.mw[e] * s[int64_t(d.col[e]) * F + f];
+    }
+  }
+  const T damp = d_exp(-d.w[row] * tau);
+  T sn, cs;
+  d_sincos(gamma * th, &sn, &cs);
+  const C p = psi_in[idx];
+  C out;
+  out.x = damp * (p.x * cs - p.y * sn);
+  out.y = damp * (p.x * sn + p.y * cs);
+  psi_out[idx] = out;
+}
+
+template <typename T, int FB>
+__global__ void k_perm_in(DevOps<T> d, const int32_t* __restrict__ perm, const typename CT<T>::C* __restrict__ src,
+                          typename CT<T>::C* __restrict__ dst, int scale_inv_h0) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t row;
+  int32_t f;
+  split<FB>(idx, d.F, row, f);
+  if (row >= d.n_rows) return;
+  const int32_t F = FB == 1 ? 1 : d.F;
+  auto v = src[int64_t(perm[row]) * F + f];
+  if (scale_inv_h0) {
+    const T s = T(1.0 / d.h0[row]);
+    v.x *= s;
+    v.y *= s;
+  }
+  dst[idx] = v;
+}
+
+template <typename T, int FB>
+__global__ void k_perm_out(DevOps<T> d, const int32_t* __restrict__ perm, const typename CT<T>::C* __restrict__ src,
+                           typename CT<T>::C* __restrict__ dst, int scale_h0, int* flag) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t row;
+  int32_t f;
+  split<FB>(idx, d.F, row, f);
+  if (row >= d.n_rows) return;
+  const int32_t F = FB == 1 ? 1 : d.F;
+  auto v = src[idx];
+  if (scale_h0) {
+    const T s = T(d.h0[row]);
+    v.x *= s;
+    v.y *= s;
+  }
+  if (flag && !(d_finite(v.x) && d_finite(v.y))) atomicOr(flag, 1);
+  dst[int64_t(perm[row]) * F + f] = v;
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, typename CT<T>::C* x, T re, T im) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  typename CT<T>::C v;
+  v.x = re;
+  v.y = im;
+  x[i] = v;
+}
+
+template <typename T>
+__global__ void k_copy(int64_t n, const typename CT<T>::C* __restrict__ src, typename CT<T>::C* __restrict__ dst) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = src[i];
+}
+
+// ---- deterministic FP64 block reduction of two values ----
+constexpr int RED_BLOCK = 256;
+
+__device__ inline void block_sum2(double& a, double& b, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[2 * wave] = a;
+    sh[2 * wave + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double sa = 0.0, sb = 0.0;
+    for (int k = 0; k < nw; ++k) {
+      sa += sh[2 * k];
+      sb += sh[2 * k + 1];
+    }
+    a = sa;
+    b = sb;
+  }
+}
+
+template <typename T, bool DEC>
+__global__ void __launch_bounds__(RED_BLOCK) k_diag(DevOps<T> d, const typename CT<T>::C* __restrict__ psi, T gamma,
+                                                    double* __restrict__ partials) {
+  using C = typename CT<T>::C;
+  __shared__ double sh[2 * (RED_BLOCK / 64)];
+  const int64_t row = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double P = 0.0, E = 0.0;
+  if (row < d.n_rows) {
+    const C pr = psi[row];
+    const T a = pr.x * pr.x + pr.y * pr.y;
+    const int64_t sl = row >> 6;
+    const int64_t base = d.sl_off[sl] + (row & 63);
+    const int W = d.sl_w[sl];
+    T lr = T(0), li = T(0), ma = d.mdiag[row] * a;
+    for (int k = 0; k < W; ++k) {
+      const int64_t e = base + int64_t(k) * 64;
+      const C pq = psi[d.col[e]];
+      const T c = d.lw[e];
+      lr += c * (pr.x - pq.x);
+      li += c * (pr.y - pq.y);
+      if (DEC) ma += d.mw[e] * (pq.x * pq.x + pq.y * pq.y);
+    }
+    const double h0 = d.h0[row];
+    P = h0 * double(a);
+    E = h0 * (double(d.p1) * (double(pr.x) * lr + double(pr.y) * li) +
+              double(d.beta4) * (double(lr) * lr + double(li) * li) - double(d.v[row]) * a -
+              0.5 * double(gamma) * double(a) * double(ma));
+  }
+  block_sum2(P, E, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = P;
+    partials[2 * blockIdx.x + 1] = E;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RED_BLOCK) k_overlap(int64_t n, const double* __restrict__ h0c,
+                                                       const typename CT<T>::C* __restrict__ a,
+                                                       const typename CT<T>::C* __restrict__ b,
+                                                       double* __restrict__ partials) {
+  __shared__ double sh[2 * (RED_BLOCK / 64)];
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double re = 0.0, im = 0.0;
+  if (j < n) {
+    const auto x = a[j];
+    const auto y = b[j];
+    const double h = h0c[j];
+    re = h * (double(x.x) * y.x + double(x.y) * y.y);  // conj(a) b
+    im = h * (double(x.x) * y.y - double(x.y) * y.x);
+  }
+  block_sum2(re, im, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = re;
+    partials[2 * blockIdx.x + 1] = im;
+  }
+}
+
+// Sums the per-block partials in a fixed order (one block).
+__global__ void __launch_bounds__(RED_BLOCK) k_finish2(const double* __restrict__ partials, int n_blocks,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[2 * (RED_BLOCK / 64)];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < n_blocks; k += blockDim.x) {
+    a += partials[2 * k];
+    b += partials[2 * k + 1];
+  }
+  block_sum2(a, b, sh);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+// ---- adjoint ----
+template <typename T, bool B4>
+__global__ void __launch_bounds__(1024) k_adj_stage(DevOps<T> d, const typename CT<T>::C* __restrict__ u_in,
+                                                    const typename CT<T>::C* __restrict__ t,
+                                                    typename CT<T>::C* __restrict__ u_out,
+                                                    typename CT<T>::C* __restrict__ acc, int init,
+                                                    const typename CT<T>::C* __restrict__ yf, T coef, double cdn,
+                                                    double* __restrict__ gdn) {
+  using C = typename CT<T>::C;
+  const int64_t row = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  if (row >= d.n_rows) return;
+  const C* __restrict__ g = B4 ? t : u_in;
+  const C gr = g[row];
+  const C ur = B4 ? u_in[row] : gr;
+  const int64_t sl = row >> 6;
+  const int64_t base = d.sl_off[sl] + (row & 63);
+  const int W = d.sl_w[sl];
+  T ar = T(0), ai = T(0);
+  for (int k = 0; k < W; ++k) {
+    const int64_t e = base + int64_t(k) * 64;
+    const C gq = g[d.col[e]];
+    const T c = d.lw[e];
+    ar += c * (gr.x - gq.x);
+    ai += c * (gr.y - gq.y);
+  }
+  const T vr = d.v[row];
+  T hr, hi;
+  if (B4) {
+    hr = d.p1 * gr.x + d.beta4 * ar - vr * ur.x;
+    hi = d.p1 * gr.y + d.beta4 * ai - vr * ur.y;
+  } else {
+    hr = d.p1 * ar - vr * ur.x;
+    hi = d.p1 * ai - vr * ur.y;
+  }
+  C uo;
+  uo.x = coef * hi;
+  uo.y = -coef * hr;
+  if (u_out) u_out[row] = uo;
+  C a0 = init ? ur : acc[row];
+  a0.x += uo.x;
+  a0.y += uo.y;
+  acc[row] = a0;
+  const C yv = yf[row];
+  // Re(i conj(u) y) = -(u.x y.y - u.y y.x)
+  gdn[row] += cdn * d.h0[row] * -(double(ur.x) * yv.y - double(ur.y) * yv.x);
+}
+
+template <typename T>
+__global__ void k_adj_prep(DevOps<T> d, const typename CT<T>::C* __restrict__ psi_in,
+                           const typename CT<T>::C* __restrict__ psi_out, const typename CT<T>::C* __restrict__ lam,
+                           typename CT<T>::C* __restrict__ sm, T tau, T gamma) {
+  const int64_t row = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (row >= d.n_rows) return;
+  const auto pi = psi_in[row];
+  const auto po = psi_out[row];
+  const auto l = lam[row];
+  typename CT<T>::C o;
+  o.x = (pi.x * pi.x + pi.y * pi.y) * phi_w(d.w[row], tau);
+  o.y = -gamma * (l.x * po.y - l.y * po.x);  // gamma Re(i conj(l) psi_out)
+  sm[row] = o;
+}
+
+template <typename T, bool DEC>
+__global__ void __launch_bounds__(1024) k_adj_kerr(DevOps<T> d, const typename CT<T>::C* __restrict__ psi_in,
+                                                   const typename CT<T>::C* lam_out,
+                                                   const typename CT<T>::C* __restrict__ sm,
+                                                   typename CT<T>::C* lam_in, T tau, T gamma) {
+  using C = typename CT<T>::C;
+  const int64_t row = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  if (row >= d.n_rows) return;
+  const C own = sm[row];
+  T th = d.mdiag[row] * own.x, mm = d.mdiag[row] * own.y;
+  if (DEC) {
+    const int64_t sl = row >> 6;
+    const int64_t base = d.sl_off[sl] + (row & 63);
+    const int W = d.sl_w[sl];
+    for (int k = 0; k < W; ++k) {
+      const int64_t e = base + int64_t(k) * 64;
+      const C q = sm[d.col[e]];
+      const T m = d.mw[e];
+      th += m * q.x;
+      mm += m * q.y;
+    }
+  }
+  const T wv = d.w[row];
+  const T damp = d_exp(-wv * tau);
+  T sn, cs;
+  d_sincos(gamma * th, &sn, &cs);
+  const C l = lam_out[row];
+  const C p = psi_in[row];
+  const T two_phi_mm = T(2) * phi_w(wv, tau) * mm;
+  C o;
+  o.x = damp * (cs * l.x + sn * l.y) + two_phi_mm * p.x;  // conj(E) l + 2 phi (M mu) psi
+  o.y = damp * (cs * l.y - sn * l.x) + two_phi_mm * p.y;
+  lam_in[row] = o;
+}
+
+template <typename T>
+__global__ void k_hcombine(DevOps<T> d, const typename CT<T>::C* __restrict__ x,
+                           const typename CT<T>::C* __restrict__ t, const typename CT<T>::C* __restrict__ t2,
+                           typename CT<T>::C* __restrict__ y) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= d.n_rows * d.F) return;
+  const int64_t row = idx / d.F;
+  const auto xv = x[idx];
+  const auto tv = t[idx];
+  const T vr = d.v[row];
+  typename CT<T>::C o;
+  o.x = d.p1 * tv.x - vr * xv.x;
+  o.y = d.p1 * tv.y - vr * xv.y;
+  if (t2) {
+    const auto t2v = t2[idx];
+    o.x += d.beta4 * t2v.x;
+    o.y += d.beta4 * t2v.y;
+  }
+  y[idx] = o;
+}
+
+template <typename T>
+__global__ void k_set_v(int64_t n, const T* __restrict__ v0, const double* __restrict__ dn,
+                        const int32_t* __restrict__ perm, T* __restrict__ v) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  v[r] = dn ? T(double(v0[r]) + dn[perm[r]]) : v0[r];
+}
+
+__global__ void k_gdn_out(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ g,
+                          double* __restrict__ out) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  out[perm[r]] = g[r];
+}
+
+__global__ void k_zero_f64(int64_t n, double* x) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  x[r] = 0.0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+#define DECBPM_C(T, p) reinterpret_cast<const typename CT<T>::C*>(p)
+#define DECBPM_M(T, p) reinterpret_cast<typename CT<T>::C*>(p)
+
+template <typename T>
+void launch_stage(const DevOps<T>& d, const void* x, const void* t, const void* psi, void* y, double coef,
+                  void* s_out, double tau_s, int block, hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
+  const bool b4 = t != nullptr, ws = s_out != nullptr;
+  T* s = reinterpret_cast<T*>(s_out);
+#define DECBPM_STAGE(FB, B4, WS)                                                                            \
+  hipLaunchKernelGGL((k_stage<T, FB, B4, WS>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, x), DECBPM_C(T, t), \
+                     DECBPM_C(T, psi), DECBPM_M(T, y), T(coef), s, T(tau_s))
+  if (d.F == 1) {
+    if (b4) {
+      if (ws) DECBPM_STAGE(1, true, true); else DECBPM_STAGE(1, true, false);
+    } else {
+      if (ws) DECBPM_STAGE(1, false, true); else DECBPM_STAGE(1, false, false);
+    }
+  } else {
+    if (b4) {
+      if (ws) DECBPM_STAGE(0, true, true); else DECBPM_STAGE(0, true, false);
+    } else {
+      if (ws) DECBPM_STAGE(0, false, true); else DECBPM_STAGE(0, false, false);
+    }
+  }
+#undef DECBPM_STAGE
+}
+
+template <typename T>
+void launch_lap(const DevOps<T>& d, const void* x, void* t, int block, hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
+  if (d.F == 1)
+    hipLaunchKernelGGL((k_lap<T, 1>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, x), DECBPM_M(T, t));
+  else
+    hipLaunchKernelGGL((k_lap<T, 0>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, x), DECBPM_M(T, t));
+}
+
+template <typename T>
+void launch_prep_s(const DevOps<T>& d, const void* psi, void* s, double tau, int block, hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
+  if (d.F == 1)
+    hipLaunchKernelGGL((k_prep_s<T, 1>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi),
+                       reinterpret_cast<T*>(s), T(tau));
+  else
+    hipLaunchKernelGGL((k_prep_s<T, 0>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi),
+                       reinterpret_cast<T*>(s), T(tau));
+}
+
+template <typename T>
+void launch_kerr(const DevOps<T>& d, const void* psi_in, void* psi_out, const void* s, double tau, double gamma,
+                 int block, hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
+  const T* sp = reinterpret_cast<const T*>(s);
+  const bool dec = d.mw != nullptr;
+#define DECBPM_KERR(FB, DEC)                                                                            \
+  hipLaunchKernelGGL((k_kerr<T, FB, DEC>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi_in),           \
+                     DECBPM_M(T, psi_out), sp, T(tau), T(gamma))
+  if (d.F == 1) {
+    if (dec) DECBPM_KERR(1, true); else DECBPM_KERR(1, false);
+  } else {
+    if (dec) DECBPM_KERR(0, true); else DECBPM_KERR(0, false);
+  }
+#undef DECBPM_KERR
+}
+
+template <typename T>
+void launch_perm_in(const DevOps<T>& d, const int32_t* perm, const void* src, void* dst, int scale_inv_h0, int block,
+                    hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows * d.F, block, 0);
+  if (d.F == 1)
+    hipLaunchKernelGGL((k_perm_in<T, 1>), dim3(g), dim3(block), 0, st, d, perm, DECBPM_C(T, src), DECBPM_M(T, dst),
+                       scale_inv_h0);
+  else
+    hipLaunchKernelGGL((k_perm_in<T, 0>), dim3(g), dim3(block), 0, st, d, perm, DECBPM_C(T, src), DECBPM_M(T, dst),
+                       scale_inv_h0);
+}
+
+template <typename T>
+void launch_perm_out(const DevOps<T>& d, const int32_t* perm, const void* src, void* dst, int scale_h0, int* flag,
+                     int block, hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows * d.F, block, 0);
+  if (d.F == 1)
+    hipLaunchKernelGGL((k_perm_out<T, 1>), dim3(g), dim3(block), 0, st, d, perm, DECBPM_C(T, src), DECBPM_M(T, dst),
+                       scale_h0, flag);
+  else
+    hipLaunchKernelGGL((k_perm_out<T, 0>), dim3(g), dim3(block), 0, st, d, perm, DECBPM_C(T, src), DECBPM_M(T, dst),
+                       scale_h0, flag);
+}
+
+template <typename T>
+void launch_fill(const DevOps<T>& d, void* x, double re, double im, int block, hipStream_t st) {
+  const int64_t n = d.n_rows * d.F;
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, DECBPM_M(T, x), T(re), T(im));
+}
+
+template <typename T>
+void launch_copy(int64_t n, const void* src, void* dst, int block, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, DECBPM_C(T, src),
+                     DECBPM_M(T, dst));
+}
+
+template <typename T>
+void launch_diag(const DevOps<T>& d, const void* psi, double gamma, double* partials, int n_blocks, double* out,
+                 hipStream_t st) {
+  if (d.mw)
+    hipLaunchKernelGGL((k_diag<T, true>), dim3(n_blocks), dim3(RED_BLOCK), 0, st, d, DECBPM_C(T, psi), T(gamma),
+                       partials);
+  else
+    hipLaunchKernelGGL((k_diag<T, false>), dim3(n_blocks), dim3(RED_BLOCK), 0, st, d, DECBPM_C(T, psi), T(gamma),
+                       partials);
+  hipLaunchKernelGGL(k_finish2, dim3(1), dim3(RED_BLOCK), 0, st, partials, n_blocks, out);
+}
+
+template <typename T>
+void launch_overlap(int64_t n, const double* h0c, const void* a, const void* b, double* partials, int n_blocks,
+                    double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_overlap<T>), dim3(n_blocks), dim3(RED_BLOCK), 0, st, n, h0c, DECBPM_C(T, a), DECBPM_C(T, b),
+                     partials);
+  hipLaunchKernelGGL(k_finish2, dim3(1), dim3(RED_BLOCK), 0, st, partials, n_blocks, out);
+}
+
+template <typename T>
+void launch_adj_stage(const DevOps<T>& d, const void* u_in, const void* t, void* u_out, void* acc, int init,
+                      const void* yf, double coef, double cdn, double* gdn, int block, hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows, block, d.xcd_remap);
+  if (t)
+    hipLaunchKernelGGL((k_adj_stage<T, true>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, u_in), DECBPM_C(T, t),
+                       DECBPM_M(T, u_out), DECBPM_M(T, acc), init, DECBPM_C(T, yf), T(coef), cdn, gdn);
+  else
+    hipLaunchKernelGGL((k_adj_stage<T, false>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, u_in), DECBPM_C(T, t),
+                       DECBPM_M(T, u_out), DECBPM_M(T, acc), init, DECBPM_C(T, yf), T(coef), cdn, gdn);
+}
+
+template <typename T>
+void launch_adj_prep(const DevOps<T>& d, const void* psi_in, const void* psi_out, const void* lam_out, void* sm,
+                     double tau, double gamma, int block, hipStream_t st) {
+  hipLaunchKernelGGL((k_adj_prep<T>), dim3(grid_for(d.n_rows, block, 0)), dim3(block), 0, st, d,
+                     DECBPM_C(T, psi_in), DECBPM_C(T, psi_out), DECBPM_C(T, lam_out), DECBPM_M(T, sm), T(tau),
+                     T(gamma));
+}
+
+template <typename T>
+void launch_adj_kerr(const DevOps<T>& d, const void* psi_in, const void* lam_out, const void* sm, void* lam_in,
+                     double tau, double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows, block, d.xcd_remap);
+  if (d.mw)
+    hipLaunchKernelGGL((k_adj_kerr<T, true>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi_in),
+                       DECBPM_C(T, lam_out), DECBPM_C(T, sm), DECBPM_M(T, lam_in), T(tau), T(gamma));
+  else
+    hipLaunchKernelGGL((k_adj_kerr<T, false>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi_in),
+                       DECBPM_C(T, lam_out), DECBPM_C(T, sm), DECBPM_M(T, lam_in), T(tau), T(gamma));
+}
+
+template <typename T>
+void launch_hcombine(const DevOps<T>& d, const void* x, const void* t, const void* t2, void* y, int block,
+                     hipStream_t st) {
+  hipLaunchKernelGGL((k_hcombine<T>), dim3(grid_for(d.n_rows * d.F, block, 0)), dim3(block), 0, st, d,
+                     DECBPM_C(T, x), DECBPM_C(T, t), DECBPM_C(T, t2), DECBPM_M(T, y));
+}
+
+template <typename T>
+void launch_set_v(int64_t n, const T* v0, const double* dn, const int32_t* perm, T* v, int block, hipStream_t st) {
+  hipLaunchKernelGGL((k_set_v<T>), dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, v0, dn, perm, v);
+}
+
+void launch_gdn_out(int64_t n, const int32_t* perm, const double* gdn, double* out, int block, hipStream_t st) {
+  hipLaunchKernelGGL(k_gdn_out, dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, perm, gdn, out);
+}
+
+void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, x);
+}
+
+#define DECBPM_INSTANTIATE(T)                                                                                     \
+  template void launch_stage<T>(const DevOps<T>&, const void*, const void*, const void*, void*, double, void*,     \
+                                double, int, hipStream_t);                                                       \
+  template void launch_lap<T>(const DevOps<T>&, const void*, void*, int, hipStream_t);                             \
+  template void launch_prep_s<T>(const DevOps<T>&, const void*, void*, double, int, hipStream_t);                  \
+  template void launch_kerr<T>(const DevOps<T>&, const void*, void*, const void*, double, double, int, hipStream_t); \
+  template void launch_perm_in<T>(const DevOps<T>&, const int32_t*, const void*, void*, int, int, hipStream_t);    \
+  template void launch_perm_out<T>(const DevOps<T>&, const int32_t*, const void*, void*, int, int*, int,            \
+                                   hipStream_t);                                                                 \
+  template void launch_fill<T>(const DevOps<T>&, void*, double, double, int, hipStream_t);                         \
+  template void launch_copy<T>(int64_t, const void*, void*, int, hipStream_t);                                    \
+  template void launch_diag<T>(const DevOps<T>&, const void*, double, double*, int, double*, hipStream_t);         \
+  template void launch_overlap<T>(int64_t, const double*, const void*, const void*, double*, int, double*,        \
+                                  hipStream_t);                                                                  \
+  template void launch_adj_stage<T>(const DevOps<T>&, const void*, const void*, void*, void*, int, const void*,   \
+                                    double, double, double*, int, hipStream_t);                                  \
+  template void launch_adj_prep<T>(const DevOps<T>&, const void*, const void*, const void*, void*, double, double, \
+                                   int, hipStream_t);                                                            \
+  template void launch_adj_kerr<T>(const DevOps<T>&, const void*, const void*, const void*, void*, double, double, \
+                                   int, hipStream_t);                                                            \
+  template void launch_hcombine<T>(const DevOps<T>&, const void*, const void*, const void*, void*, int,           \
+                                   hipStream_t);                                                                 \
+  template void launch_set_v<T>(int64_t, const T*, const double*, const int32_t*, T*, int, hipStream_t);
+
+DECBPM_INSTANTIATE(float)
+DECBPM_INSTANTIATE(double)
+
+}  // namespace decbpm

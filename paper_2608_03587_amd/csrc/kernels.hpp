@@ -1,0 +1,121 @@
+// Device data layout and kernel launchers of the DEC beam-propagation library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace decbpm {
+
+// Rows are vertices in device order (a Hilbert curve per mesh; meshes of a
+// batch are concatenated).  Every row carries F fields stored field-minor:
+// the complex value of (row r, field f) sits at r * F + f.
+//
+// The operators are stored as sliced ELL with slices of 64 rows (one
+// wavefront): slice s keeps width W_s = max off-diagonal degree of its rows,
+// and entry k of row r lives at sl_off[s] + k * 64 + (r & 63), so lane j of a
+// wavefront reading entry k touches consecutive words.  Only off-diagonal
+// neighbours are stored; L is applied in difference form
+//   (L x)_p = sum_q c_pq (x_p - x_q),   c_pq = -K_pq / H0_p,
+// which makes L 1 = 0 exact in floating point.  Padding entries point at the
+// row itself with zero weights.
+template <typename T>
+struct DevOps {
+  int64_t n_rows;      // rows (vertices summed over meshes)
+  int32_t F;           // fields per row
+  const int64_t* sl_off;
+  const int32_t* sl_w;
+  const int32_t* col;  // device-order neighbour
+  const T* lw;         // c_pq
+  const T* mw;         // M_pq (off-diagonal), nullptr for the lumped nonlinearity
+  const T* mdiag;      // M_pp
+  const T* v;          // vertex potential (+ index perturbation)
+  const T* w;          // absorber strength
+  const double* h0;    // dual areas (device order)
+  T p1, beta4;
+  int32_t xcd_remap;   // 1: map consecutive row blocks onto one XCD
+};
+
+template <typename T>
+struct Cplx;
+template <>
+struct Cplx<float> {
+  using type = float2;
+};
+template <>
+struct Cplx<double> {
+  using type = double2;
+};
+template <typename T>
+using cplx_t = typename Cplx<T>::type;
+
+// ---- launchers (asynchronous on `st`) ----
+// y = psi + coef * A x with A = -i (p1 L - diag v) (beta4 == 0) or, when t = L x
+// is given, A = -i (p1 L + beta4 L^2 - diag v).  If s_out is non-null it
+// receives |y|^2 phi(w, tau_s) for the next Kerr substep.  y may alias psi.
+template <typename T>
+void launch_stage(const DevOps<T>& d, const void* x, const void* t, const void* psi, void* y, double coef,
+                  void* s_out, double tau_s, int block, hipStream_t st);
+// t = L x
+template <typename T>
+void launch_lap(const DevOps<T>& d, const void* x, void* t, int block, hipStream_t st);
+// s = |psi|^2 phi(w, tau)
+template <typename T>
+void launch_prep_s(const DevOps<T>& d, const void* psi, void* s, double tau, int block, hipStream_t st);
+// psi_out <- psi_in e^{-w tau} exp(i gamma (M s)); s gathered; psi_out may alias psi_in
+template <typename T>
+void launch_kerr(const DevOps<T>& d, const void* psi_in, void* psi_out, const void* s, double tau, double gamma,
+                 int block, hipStream_t st);
+// dst[r*F+f] = src[perm[r]*F+f] (caller order -> device order), optionally scaled by 1/h0
+template <typename T>
+void launch_perm_in(const DevOps<T>& d, const int32_t* perm, const void* src, void* dst, int scale_inv_h0, int block,
+                    hipStream_t st);
+// dst[perm[r]*F+f] = src[r*F+f] (device order -> caller order), optionally scaled by h0;
+// a non-finite value sets *flag (if flag is non-null)
+template <typename T>
+void launch_perm_out(const DevOps<T>& d, const int32_t* perm, const void* src, void* dst, int scale_h0, int* flag,
+                     int block, hipStream_t st);
+// x[:] = re + i im
+template <typename T>
+void launch_fill(const DevOps<T>& d, void* x, double re, double im, int block, hipStream_t st);
+// power and Hamiltonian (F = 1): per-block FP64 partials, then one fixed-order block
+template <typename T>
+void launch_diag(const DevOps<T>& d, const void* psi, double gamma, double* partials, int n_blocks, double* out,
+                 hipStream_t st);
+// overlap sum_j h0c_j conj(a_j) b_j over caller order
+template <typename T>
+void launch_overlap(int64_t n, const double* h0c, const void* a, const void* b, double* partials, int n_blocks,
+                    double* out, hipStream_t st);
+// n complex values src -> dst
+template <typename T>
+void launch_copy(int64_t n, const void* src, void* dst, int block, hipStream_t st);
+// y = p1 t + beta4 t2 - v x  (t = L x, t2 = L t; t2 may be null when beta4 == 0)
+template <typename T>
+void launch_hcombine(const DevOps<T>& d, const void* x, const void* t, const void* t2, void* y, int block,
+                     hipStream_t st);
+// v[r] = v0[r] + (dn ? dn[perm[r]] : 0)
+template <typename T>
+void launch_set_v(int64_t n, const T* v0, const double* dn, const int32_t* perm, T* v, int block, hipStream_t st);
+
+// ---- adjoint (F = 1), in H0-scaled adjoint variables lambda = H0^{-1} g ----
+// One link of the reverse Horner chain of an RK4 step:
+//   u_out = coef * A u_in   (A as in launch_stage; t = L u_in when beta4 != 0)
+//   acc   = (init ? u_in : acc) + u_out
+//   gdn  += cdn * h0 * Re(i conj(u_in) yf)
+// u_out may be null (last link).
+template <typename T>
+void launch_adj_stage(const DevOps<T>& d, const void* u_in, const void* t, void* u_out, void* acc, int init,
+                      const void* yf, double coef, double cdn, double* gdn, int block, hipStream_t st);
+// sm = (|psi_in|^2 phi(w,tau), gamma Re(i conj(lam_out) psi_out)) per row
+template <typename T>
+void launch_adj_prep(const DevOps<T>& d, const void* psi_in, const void* psi_out, const void* lam_out, void* sm,
+                     double tau, double gamma, int block, hipStream_t st);
+// lam_in = conj(E) lam_out + 2 phi psi_in (M mu),  E = e^{-w tau} e^{i gamma M s}
+template <typename T>
+void launch_adj_kerr(const DevOps<T>& d, const void* psi_in, const void* lam_out, const void* sm, void* lam_in,
+                     double tau, double gamma, int block, hipStream_t st);
+// out[perm[r]] = gdn[r]
+void launch_gdn_out(int64_t n, const int32_t* perm, const double* gdn, double* out, int block, hipStream_t st);
+void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st);
+
+}  // namespace decbpm

@@ -77,8 +77,12 @@ def plain_small(n_vert: int = 4000, seed: int = 11, n_steps: int = 200) -> Workl
     return Workload("plain_small", mesh, None, None, u0, dz=1e-3, n_steps=n_steps)
 
 
-def step_index(n_vert: int = 250_000, seed: int = 21, n_steps: int = 5000) -> Workload:
-    mesh = M.graded_core_disk_mesh(R=40.0, r_core=5.0, h_core=0.05, h_max=0.4, target_vertices=n_vert, seed=seed)
+def step_index(n_vert: int = 250_000, seed: int = 21, n_steps: int = 5000, min_angle: float | None = None) -> Workload:
+    # coarse replicas grade faster, so their ring transitions allow a smaller angle
+    if min_angle is None:
+        min_angle = 25.0 if n_vert >= 100_000 else 20.0
+    mesh = M.graded_core_disk_mesh(R=40.0, r_core=5.0, h_core=0.05, h_max=0.4, target_vertices=n_vert, seed=seed,
+                                   min_angle=min_angle)
     V = F.step_index_tri(mesh.xy, mesh.tri, 5.0, 1.0)
     w = F.quadratic_absorber(mesh.xy, 35.0, 40.0, 0.5)
     u0 = F.elliptic_gaussian(mesh.xy, 1.2, 2.0, 4.0, math.radians(30.0))
@@ -105,7 +109,8 @@ def batched_pcf(n_meshes: int = 8, fields_per_mesh: int = 32, n_min: int = 20_00
     out = []
     for i in range(n_meshes):
         h = _uniform_h_for(R, targets[i])
-        mesh = M.pcf_mesh(h, float(radii[i]), 41 + i, R=R)
+        # replicas coarser than the hole radius cannot keep 25 degrees on the hole rings
+        mesh = M.pcf_mesh(h, float(radii[i]), 41 + i, R=R, min_angle=25.0 if targets[i] >= 19_000 else 15.0)
         V = F.pcf_index_tri(mesh.xy, mesh.tri, mesh.meta["hole_centres"], float(radii[i]), -0.45)
         w = F.quadratic_absorber(mesh.xy, 10.0, 12.0, 0.5)
         u0 = np.stack([F.gaussian_superposition(mesh.xy, 4000 + i * fields_per_mesh + f)

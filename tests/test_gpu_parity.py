@@ -1,0 +1,343 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Gates: relative L2 error of the complex vertex vector <= 1e-10 in complex128
+and <= 1e-4 in complex64 at the final z; kernel-level checks are tighter.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as OA, dec, diagnostics as D, stepper as S
+from paper_2608_03587_amd import api
+from paper_2608_03587_amd.inputs import fields as F
+from paper_2608_03587_amd.inputs import meshes as M
+from paper_2608_03587_amd.inputs import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GATE = {"c128": 1e-10, "c64": 1e-4}
+KERNEL_TOL = {"c128": 1e-13, "c64": 2e-6}
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV, {"c64": torch.complex64, "c128": torch.complex128}[dtype])
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+_CACHE = {}
+
+
+def case(name, **kw):
+    key = (name, tuple(sorted(kw.items())))
+    if key not in _CACHE:
+        if name == "plain_small":
+            w = W.plain_small(**kw)
+        elif name == "step_index":
+            w = W.step_index(**kw)
+        elif name == "vortex":
+            w = W.vortex_beta4(**kw)
+        elif name == "adjoint":
+            w = W.adjoint_mmf(**kw)
+        else:
+            raise KeyError(name)
+        _CACHE[key] = w
+    return _CACHE[key]
+
+
+def oracle_ops(w, nl="dec", dn=None):
+    return dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, chi_tri=w.chi_tri, p1=w.p1, beta4=w.beta4,
+                        nl=nl, dn=dn)
+
+
+def lib_mesh(w, dtype, nl="dec", **kw):
+    return api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, chi_tri=w.chi_tri, dtype=dtype, p1=w.p1,
+                    beta4=w.beta4, nonlinearity=nl, **kw)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    say("device:", torch.cuda.get_device_name(0))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("wname", ["plain_small", "vortex"])
+def test_operator_application(dtype, wname):
+    w = case(wname) if wname == "plain_small" else case(wname, n_vert=20000, n_steps=10)
+    say("apply", wname, dtype, w.mesh.n_vert)
+    ops = oracle_ops(w)
+    m = lib_mesh(w, dtype)
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=ops.n) + 1j * rng.normal(size=ops.n)
+    xd = dev(x, dtype)
+    for op, ref in (("L", ops.L @ x), ("L2", ops.L @ (ops.L @ x)), ("H", ops.apply_H(x))):
+        got = host(m.apply(op, xd))
+        assert rel(got, ref) < KERNEL_TOL[dtype] * (30 if op == "L2" else 10), (op, rel(got, ref))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_kerr_and_linear_substeps(dtype, nl):
+    w = case("step_index", n_vert=20000, n_steps=10)
+    say("substeps", dtype, nl, w.mesh.n_vert)
+    ops = oracle_ops(w, nl)
+    m = lib_mesh(w, dtype, nl)
+    u = w.u0
+    f = dev(u, dtype)
+    m.kerr_step(f, 0.37, 1.3)
+    assert rel(host(f), S.nl_flow(u, 0.37, 1.3, ops)) < KERNEL_TOL[dtype] * 10
+    f = dev(u, dtype)
+    m.linear_step(f, w.dz)
+    assert rel(host(f), S.lin_rk4(u, w.dz, ops)) < KERNEL_TOL[dtype] * 10
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_plain_small_end_to_end(dtype, nl):
+    """4k-vertex disk, Gaussian 0.8 exp(-r^2/2), dz = 1e-3, 200 steps, gamma = 1."""
+    w = case("plain_small")
+    say("plain_small", dtype, nl)
+    ops = oracle_ops(w, nl)
+    ref = S.propagate(w.u0, ops, w.dz, w.n_steps, w.gamma)
+    m = lib_mesh(w, dtype, nl)
+    f = dev(w.u0, dtype)
+    m.propagate(f, w.dz, w.n_steps, w.gamma)
+    m.check_finite()
+    err = rel(host(f), ref)
+    say("  rel err", err)
+    assert err < GATE[dtype]
+    # diagnostics: power and Hamiltonian in FP64 accumulation
+    P, E = m.diagnostics(f, w.gamma)
+    out = host(f)
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert abs(P - D.power(out, ops)) < tol * abs(D.power(out, ops))
+    assert abs(E - D.hamiltonian(out, ops, w.gamma)) < tol * 10 * abs(D.hamiltonian(out, ops, w.gamma))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_step_index_replica_end_to_end(dtype):
+    """Graded step-index disk (20k replica): core potential, absorber ring, tilted elliptic Gaussian."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    n = 300
+    say("step_index replica", dtype, w.mesh.n_vert, n)
+    ops = oracle_ops(w)
+    ref = S.propagate(w.u0, ops, w.dz, n, w.gamma)
+    m = lib_mesh(w, dtype)
+    f = dev(w.u0, dtype)
+    m.propagate(f, w.dz, n, w.gamma)
+    err = rel(host(f), ref)
+    say("  rel err", err)
+    assert err < GATE[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_vortex_beta4_replica_end_to_end(dtype):
+    """beta4 L^2 term, vortex launch with 1% noise, absorber (20k replica)."""
+    w = case("vortex", n_vert=20000, n_steps=10)
+    n = 200
+    say("vortex replica", dtype, w.mesh.n_vert, n)
+    ops = oracle_ops(w)
+    ref = S.propagate(w.u0, ops, w.dz, n, w.gamma)
+    m = lib_mesh(w, dtype)
+    f = dev(w.u0, dtype)
+    m.propagate(f, w.dz, n, w.gamma)
+    err = rel(host(f), ref)
+    say("  rel err", err)
+    assert err < GATE[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_step_index_full_size_prefix(dtype):
+    """The full 250k-vertex step-index workload, 20 steps, in the bench's launch configuration."""
+    w = case("step_index")
+    n = 20
+    say("step_index full", dtype, w.mesh.n_vert, n)
+    ops = oracle_ops(w)
+    ref = S.propagate(w.u0, ops, w.dz, n, w.gamma)
+    m = lib_mesh(w, dtype)
+    f = dev(w.u0, dtype)
+    m.propagate(f, w.dz, n, w.gamma)
+    err = rel(host(f), ref)
+    say("  rel err", err)
+    assert err < GATE[dtype]
+
+
+def test_edge_cases_and_launch_paths():
+    w = case("plain_small")
+    m = lib_mesh(w, "c128")
+    ops = oracle_ops(w)
+    u = dev(w.u0, "c128")
+    f = u.clone()
+    m.propagate(f, w.dz, 0, 1.0)  # no-op
+    assert torch.equal(f, u)
+    for n in (1, 2, 33, 70):  # graph replays + eager remainders
+        f = u.clone()
+        m.propagate(f, w.dz, n, 1.0)
+        assert rel(host(f), S.propagate(w.u0, ops, w.dz, n, 1.0)) < 1e-12, n
+    # graph and eager launches produce identical bits
+    m.tuning = {"block_size": 256, "steps_per_graph": 1}
+    a = u.clone()
+    m.propagate(a, w.dz, 70, 1.0)
+    m.tuning = {"block_size": 256, "steps_per_graph": 16}
+    b = u.clone()
+    m.propagate(b, w.dz, 70, 1.0)
+    assert torch.equal(a, b)
+    # run twice: deterministic
+    c = u.clone()
+    m.propagate(c, w.dz, 70, 1.0)
+    assert torch.equal(b, c)
+    # block size does not change the arithmetic
+    for blk in (64, 512, 1024):
+        m.tuning = {"block_size": blk, "steps_per_graph": 16}
+        d = u.clone()
+        m.propagate(d, w.dz, 70, 1.0)
+        assert torch.equal(b, d), blk
+    # chunked propagation: two calls equal one call up to the merged half steps
+    e = u.clone()
+    m.propagate(e, w.dz, 35, 1.0)
+    m.propagate(e, w.dz, 35, 1.0)
+    assert rel(host(e), host(b)) < 1e-13
+
+
+def test_nonfinite_is_flagged():
+    w = case("plain_small")
+    m = lib_mesh(w, "c64")
+    f = dev(w.u0, "c64")
+    f[5] = float("nan")
+    m.propagate(f, w.dz, 3, 1.0)
+    with pytest.raises(api.DecBpmError) as e:
+        m.check_finite()
+    assert e.value.code == -6
+    g = dev(w.u0, "c64")
+    m.propagate(g, w.dz, 3, 1.0)
+    m.check_finite()  # flag was cleared
+
+
+def test_unstable_dz_rejected_before_device_work():
+    w = case("plain_small")
+    m = lib_mesh(w, "c64")
+    f = dev(w.u0, "c64")
+    keep = f.clone()
+    with pytest.raises(api.DecBpmError) as e:
+        m.propagate(f, 3.0 / m.spectral_radius(), 5, 1.0)
+    assert e.value.code == -3
+    assert torch.equal(f, keep)
+
+
+def test_overlap_and_power_match_oracle():
+    w = case("adjoint", n_vert=20000, n_steps=10)
+    ops = oracle_ops(w)
+    for dtype in ("c128", "c64"):
+        m = lib_mesh(w, dtype)
+        a, b = dev(w.extra["target"], dtype), dev(w.u0, dtype)
+        c = m.overlap(a, b)
+        ref = D.overlap(w.extra["target"], w.u0, ops)
+        tol = 1e-13 if dtype == "c128" else 1e-6
+        assert abs(c - ref) < tol * abs(ref)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batched_equals_plain(dtype):
+    ws = W.batched_pcf(n_meshes=3, fields_per_mesh=4, n_min=3000, n_max=9000, n_steps=40)
+    say("batched", dtype, [x.mesh.n_vert for x in ws])
+    meshes = [lib_mesh(x, dtype) for x in ws]
+    batch = api.Batch(meshes, 4)
+    packed = batch.pack([dev(x.u0, dtype) for x in ws])
+    batch.propagate(packed, ws[0].dz, ws[0].n_steps, 1.0)
+    outs = batch.unpack(packed)
+    for m, x, o in zip(meshes, ws, outs):
+        for f in range(4):
+            single = dev(x.u0[f], dtype)
+            m.propagate(single, x.dz, x.n_steps, 1.0)
+            assert torch.equal(o[f].contiguous(), single), "batched and plain differ"
+    # and one field against the oracle
+    ops = oracle_ops(ws[1])
+    ref = S.propagate(ws[1].u0[2], ops, ws[1].dz, ws[1].n_steps, 1.0)
+    assert rel(host(outs[1][2].contiguous()), ref) < GATE[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_matches_oracle_gradients(dtype):
+    w = W.adjoint_mmf(n_vert=3000, n_steps=10)
+    n, every = 24, 5
+    say("adjoint", dtype, w.mesh.n_vert, n)
+    dn = w.extra["dn"]
+    ops = oracle_ops(w, dn=dn)
+    J, g_ref, gdn_ref = OA.gradients(w.u0, w.extra["target"], ops, w.dz, n, w.gamma)
+    m = lib_mesh(w, dtype)
+    dn_d = torch.from_numpy(dn).to(DEV)
+    m.set_index_perturbation(dn_d)
+    u = dev(w.u0, dtype)
+    wsp = torch.empty(m.workspace_size(n, every), dtype=torch.uint8, device=DEV)
+    m.forward_checkpointed(u, w.dz, n, w.gamma, wsp, every)
+    ref_u = S.propagate(w.u0, ops, w.dz, n, w.gamma)
+    assert rel(host(u), ref_u) < GATE[dtype]
+    tgt = dev(w.extra["target"], dtype)
+    c = m.overlap(tgt, u)
+    gout = (2 * c * torch.from_numpy(ops.H0).to(DEV) * tgt.to(torch.complex128)).to(u.dtype)
+    g0, gdn = m.adjoint(gout, w.dz, n, w.gamma, wsp, every)
+    tol = 1e-9 if dtype == "c128" else 1e-4
+    assert rel(host(g0), g_ref) < tol, rel(host(g0), g_ref)
+    assert rel(gdn.cpu().numpy(), gdn_ref) < tol, rel(gdn.cpu().numpy(), gdn_ref)
+
+
+def test_autograd_function_and_finite_differences():
+    w = W.adjoint_mmf(n_vert=3000, n_steps=10)
+    n = 16
+    m = lib_mesh(w, "c128")
+    tgt = dev(w.extra["target"], "c128")
+    h0 = torch.from_numpy(oracle_ops(w).H0).to(DEV)
+
+    def J(u0, dn):
+        u = api.propagate_with_grad(m, u0, dn, w.dz, n, w.gamma)
+        c = (h0 * tgt.conj() * u).sum()
+        return (c.conj() * c).real
+
+    u0 = dev(w.u0, "c128").requires_grad_(True)
+    dn = torch.from_numpy(w.extra["dn"]).to(DEV).requires_grad_(True)
+    val = J(u0, dn)
+    val.backward()
+    rng = np.random.default_rng(3)
+    with torch.no_grad():
+        d = dev(rng.normal(size=m.n_vert) + 1j * rng.normal(size=m.n_vert), "c128")
+        e = torch.from_numpy(rng.normal(size=m.n_vert)).to(DEV)
+        eps = 1e-6
+        fd_u = (J(u0 + eps * d, dn) - J(u0 - eps * d, dn)) / (2 * eps)
+        an_u = (u0.grad.conj() * d).real.sum()
+        assert abs(float(fd_u - an_u)) < 1e-6 * abs(float(fd_u))
+        fd_n = (J(u0, dn + 1e-4 * e) - J(u0, dn - 1e-4 * e)) / 2e-4
+        an_n = (dn.grad * e).sum()
+        assert abs(float(fd_n - an_n)) < 1e-6 * abs(float(fd_n))
+
+
+def test_autotune_keeps_results():
+    w = case("plain_small")
+    m = lib_mesh(w, "c64")
+    u = dev(w.u0, "c64")
+    a = u.clone()
+    m.propagate(a, w.dz, 40, 1.0)
+    t = m.autotune(w.dz, 1.0)
+    say("tuned", t)
+    b = u.clone()
+    m.propagate(b, w.dz, 40, 1.0)
+    assert rel(host(a), host(b)) < 1e-6  # block size / graphs do not change the arithmetic
+    times = m.time_kernels(w.dz, 1.0, reps=20)
+    assert all(v["ms"] > 0 for v in times.values())

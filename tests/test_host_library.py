@@ -1,0 +1,171 @@
+"""CPU tests of the native library: it loads, exports every declared symbol,
+assembles the same operators as the oracle (independent routes: closed-form
+cotangents vs Whitney quadrature), and rejects bad input with the documented
+codes before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import dec
+from paper_2608_03587_amd import _binding as B
+from paper_2608_03587_amd import api
+from paper_2608_03587_amd.inputs import fields as F
+from paper_2608_03587_amd.inputs import meshes as M
+from paper_2608_03587_amd.inputs import workloads as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "dec_bpm.h")
+
+
+def _declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dec_bpm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    names = _declared_symbols()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(B.SYMBOLS)
+    assert b"gfx950" in lib.dec_bpm_version()
+
+
+def _csr(ops):
+    n = len(ops["h0"])
+    return sp.csr_matrix((ops["K"], ops["col"], ops["row_ptr"]), shape=(n, n)), \
+        sp.csr_matrix((ops["QtDQ"], ops["col"], ops["row_ptr"]), shape=(n, n))
+
+
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_host_assembly_matches_oracle(nl):
+    w = W.step_index(n_vert=6000, n_steps=1)
+    rng = np.random.default_rng(0)
+    chi = rng.uniform(0.5, 1.5, w.mesh.n_tri)
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, chi_tri=chi, host_only=True, nonlinearity=nl)
+    got = m.export_operators()
+    ref = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, chi_tri=chi, nl=nl)
+    K, Q = _csr(got)
+    assert abs(K - ref.K).max() < 1e-13 * abs(ref.K).max()
+    np.testing.assert_allclose(got["h0"], ref.H0, rtol=1e-13)
+    np.testing.assert_allclose(got["v"], ref.v, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(got["w"], ref.w, rtol=0, atol=0)
+    M_lib = sp.diags(1.0 / got["h0"]) @ Q
+    assert abs(M_lib - ref.M).max() < 1e-13 * abs(ref.M).max()
+    s = m.sizes()
+    assert s["n_edge"] == ref.edges.shape[0]
+    assert s["nnz"] == ref.K.nnz
+
+
+def test_spectral_radius_is_a_tight_upper_bound():
+    mesh = M.disk_mesh(4.0, 0.4, 1)
+    V = F.step_index_tri(mesh.xy, mesh.tri, 1.0, 1.0)
+    m = api.Mesh(mesh.xy, mesh.tri, V, host_only=True, beta4=1e-3)
+    ops = dec.assemble(mesh.xy, mesh.tri, V, beta4=1e-3)
+    lam = np.linalg.eigvals(ops.dense_H())
+    rho = np.abs(lam).max()
+    r = m.spectral_radius()
+    assert rho <= r <= 1.001 * rho
+    # a large mesh uses Lanczos without reorthogonalisation: still within 2%
+    w = W.plain_small()
+    m2 = api.Mesh(w.mesh.xy, w.mesh.tri, host_only=True)
+    ops2 = dec.assemble(w.mesh.xy, w.mesh.tri)
+    top = spla.eigsh(ops2.K, k=1, M=sp.diags(ops2.H0), which="LA", return_eigenvectors=False)[0] * 0.5
+    assert top <= m2.spectral_radius() <= 1.02 * top
+
+
+def _expect(code, fn):
+    with pytest.raises(api.DecBpmError) as e:
+        fn()
+    assert e.value.code == code, str(e.value)
+
+
+def test_create_rejects_bad_meshes():
+    xy = np.array([[0, 0], [1, 0], [0, 1], [1, 1], [2, 2.0]])
+    good = np.array([[0, 1, 2], [1, 3, 2]])
+    api.Mesh(xy[:4], good, host_only=True)  # fine
+    _expect(B.EMESH, lambda: api.Mesh(xy[:4], np.array([[0, 1, 2], [1, 3, 7]]), host_only=True))  # out of range
+    _expect(B.EMESH, lambda: api.Mesh(xy[:4], np.array([[0, 1, 1], [1, 3, 2]]), host_only=True))  # repeated
+    _expect(B.EMESH, lambda: api.Mesh(xy, good, host_only=True))  # vertex 4 unreferenced
+    col = np.array([[0, 0], [1, 0], [2, 0], [0, 1.0]])
+    _expect(B.EMESH, lambda: api.Mesh(col, np.array([[0, 1, 2], [0, 1, 3]]), host_only=True))  # zero area
+    # three triangles on one edge
+    xy3 = np.array([[0, 0], [1, 0], [0.5, 1], [0.5, -1], [0.5, 2.0]])
+    _expect(B.EMESH, lambda: api.Mesh(xy3, np.array([[0, 1, 2], [0, 3, 1], [0, 1, 4]]), host_only=True))
+    # overlapping (folded) triangles traverse the shared edge in the same direction
+    xyf = np.array([[0, 0], [1, 0], [0.5, 1], [0.5, 0.5]])
+    _expect(B.EMESH, lambda: api.Mesh(xyf, np.array([[0, 1, 2], [0, 1, 3]]), host_only=True))
+    bad = xy[:4].copy()
+    bad[1, 0] = np.nan
+    _expect(B.EINVAL, lambda: api.Mesh(bad, good, host_only=True))
+    _expect(B.EINVAL, lambda: api.Mesh(xy[:4], good, absorber=np.array([0, -1.0, 0, 0]), host_only=True))
+    _expect(B.EINVAL, lambda: api.Mesh(xy[:4], good, index_tri=np.array([0, np.inf]), host_only=True))
+    _expect(B.EINVAL, lambda: api.Mesh(xy[:4], good, beta4=-1.0, host_only=True))
+
+
+def test_orientation_is_fixed_by_create():
+    mesh = M.disk_mesh(2.0, 0.5, 3)
+    a = api.Mesh(mesh.xy, mesh.tri, host_only=True).export_operators()
+    flipped = mesh.tri[:, [0, 2, 1]]
+    b = api.Mesh(mesh.xy, flipped, host_only=True).export_operators()
+    np.testing.assert_array_equal(a["col"], b["col"])
+    np.testing.assert_allclose(a["K"], b["K"], rtol=0, atol=1e-15)
+
+
+def test_raw_abi_null_and_struct_checks():
+    lib = B.lib()
+    h = ctypes.c_void_p()
+    assert lib.dec_bpm_create(None, 3, None, 1, None, None, None, ctypes.byref(h)) == B.EINVAL
+    assert b"NULL" in lib.dec_bpm_last_error()
+    opt = B.Options()
+    lib.dec_bpm_default_options(ctypes.byref(opt))
+    opt.struct_size = 4
+    xy = np.array([[0, 0], [1, 0], [0, 1.0]])
+    tri = np.array([[0, 1, 2]], np.int32)
+    rc = lib.dec_bpm_create(xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 3,
+                            tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 1, None, None, ctypes.byref(opt),
+                            ctypes.byref(h))
+    assert rc == B.EINVAL
+    assert lib.dec_bpm_propagate(None, None, 1e-3, 1, 1.0, None) == B.EINVAL
+
+
+def test_host_only_handle_runs_every_check_then_reports_no_device():
+    w = W.plain_small(n_vert=1000)
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, host_only=True)
+    lib = B.lib()
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every path below fails before device work
+    rho = m.spectral_radius()
+    assert lib.dec_bpm_propagate(m.handle, fake, 3.0 / rho, 10, 1.0, None) == B.EUNSTABLE
+    assert b"stability" in lib.dec_bpm_last_error()
+    assert lib.dec_bpm_propagate(m.handle, fake, 0.0, 10, 1.0, None) == B.EINVAL
+    assert lib.dec_bpm_propagate(m.handle, fake, 1e-3, -1, 1.0, None) == B.EINVAL
+    assert lib.dec_bpm_propagate(m.handle, ctypes.c_void_p((1 << 20) + 4), 1e-3, 1, 1.0, None) == B.EINVAL
+    assert lib.dec_bpm_propagate(m.handle, fake, 1e-3, 10, float("nan"), None) == B.EINVAL
+    assert lib.dec_bpm_propagate(m.handle, fake, 1e-3, 10, 1.0, None) == B.ENODEVICE
+    assert lib.dec_bpm_apply(m.handle, 0, fake, fake, None) == B.EINVAL  # x == y
+    assert lib.dec_bpm_diagnostics(m.handle, fake, 1.0, None, None, None) == B.ENODEVICE
+    size = ctypes.c_size_t()
+    assert lib.dec_bpm_workspace_size(m.handle, 100, 0, ctypes.byref(size)) == B.OK
+    assert size.value > 0
+    assert lib.dec_bpm_forward_checkpointed(m.handle, fake, 1e-3, 100, 1.0, 0, fake, 16, None) == B.ENODEVICE
+    t = B.Tuning()
+    assert lib.dec_bpm_get_tuning(m.handle, ctypes.byref(t)) == B.OK
+    assert t.block_size in (64, 128, 256, 512, 1024)
+    bad = B.Tuning(100, 1)
+    assert lib.dec_bpm_set_tuning(m.handle, ctypes.byref(bad)) == B.EINVAL
+
+
+def test_workspace_size_grows_like_sqrt_n_checkpoints():
+    w = W.plain_small(n_vert=1000)
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, host_only=True)
+    vec = m.n_vert * 8
+    s100 = m.workspace_size(100)  # 10 checkpoints + 10-step segment
+    s10000 = m.workspace_size(10000)  # 100 + 100
+    assert 20 * vec < s100 < 80 * vec
+    assert s10000 < 12 * s100
