@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="only the timed propagation (for rocprofv3)")
+    ap.add_argument("--block", type=int, default=0, help="fixed block size (skips autotuning)")
+    ap.add_argument("--spg", type=int, default=0, help="fixed steps per graph (with --block)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -83,7 +85,10 @@ def main():
 
     def make(dtype):
         m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=dtype, p1=w.p1, beta4=w.beta4)
-        m.autotune(w.dz, w.gamma)
+        if args.block:
+            m.tuning = {"block_size": args.block, "steps_per_graph": args.spg or 128}
+        else:
+            m.autotune(w.dz, w.gamma)
         return m
 
     def timed_propagate(m, dtype, steps, warmup):
@@ -209,6 +214,7 @@ def bench_batched(api, W, torch, dev, tdt):
     meshes = [api.Mesh(x.mesh.xy, x.mesh.tri, x.index_tri, x.absorber, dtype="c64") for x in ws]
     batch = api.Batch(meshes, F)
     packed0 = batch.pack([torch.from_numpy(x.u0).to(dev, tdt["c64"]) for x in ws])
+    batch.autotune(dz, 1.0)
     p = packed0.clone()
     batch.propagate(p, dz, 50, 1.0)  # warm-up
     p = packed0.clone()

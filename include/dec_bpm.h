@@ -231,6 +231,7 @@ typedef struct {
   int32_t steps_per_graph;
 } dec_bpm_tuning;
 int dec_bpm_autotune(dec_bpm_t h, double dz, double gamma, void* stream);
+int dec_bpm_batch_autotune(dec_bpm_batch_t b, double dz, double gamma, void* stream);
 int dec_bpm_get_tuning(dec_bpm_t h, dec_bpm_tuning* t);
 int dec_bpm_set_tuning(dec_bpm_t h, const dec_bpm_tuning* t);
 

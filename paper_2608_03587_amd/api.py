@@ -271,6 +271,9 @@ class Batch:
     def time_kernels(self, dz, gamma=1.0, reps=20, stream=None):
         return _time_kernels(B.lib().dec_bpm_batch_time_kernels, self._h, dz, gamma, reps, stream)
 
+    def autotune(self, dz, gamma=1.0, stream=None):
+        B.check(B.lib().dec_bpm_batch_autotune(self._h, float(dz), float(gamma), _stream(stream)))
+
 
 class DecBpmFunction(torch.autograd.Function):
     """``u(z_L) = propagate(u0; dn)`` with gradients for ``u0`` and ``dn``.

@@ -54,8 +54,8 @@ struct Engine {
   int64_t n_entries = 0;   // sliced-ELL entries including padding
   bool on_device = false;
   // device operators
-  int64_t* sl_off = nullptr;
-  int32_t* sl_w = nullptr;
+  int64_t* sl_info = nullptr;
+  int32_t wmax = 0;
   int32_t* col = nullptr;
   void* lw = nullptr;
   void* mw = nullptr;
@@ -100,8 +100,11 @@ struct Engine {
     DevOps<T> d;
     d.n_rows = n_rows;
     d.F = F;
-    d.sl_off = sl_off;
-    d.sl_w = sl_w;
+    d.lgF = -1;
+    for (int k = 0; k < 31; ++k)
+      if ((int64_t(1) << k) == int64_t(F)) d.lgF = k;
+    d.wmax = wmax;
+    d.sl_info = sl_info;
     d.col = col;
     d.lw = static_cast<const T*>(lw);
     d.mw = static_cast<const T*>(mw);
@@ -241,11 +244,16 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
     const int64_t s = r >> 6, lane = r & 63;
     for (int k = 0; k < sl_w[s]; ++k) col[sl_off[s] + int64_t(k) * 64 + lane] = 0;
   }
+  std::vector<int64_t> sl_info(n_sl);
+  E.wmax = 0;
+  for (int64_t s = 0; s < n_sl; ++s) {
+    if (sl_w[s] > 255) fail(DEC_BPM_EMESH, "a vertex has more than 255 neighbours");
+    sl_info[s] = (sl_off[s] << 8) | int64_t(sl_w[s]);
+    E.wmax = std::max(E.wmax, sl_w[s]);
+  }
   void* p;
-  upload(E, p, sl_off);
-  E.sl_off = static_cast<int64_t*>(p);
-  upload(E, p, sl_w);
-  E.sl_w = static_cast<int32_t*>(p);
+  upload(E, p, sl_info);
+  E.sl_info = static_cast<int64_t*>(p);
   upload(E, p, col);
   E.col = static_cast<int32_t*>(p);
   upload(E, E.lw, lw);
@@ -1100,6 +1108,18 @@ int dec_bpm_autotune(dec_bpm_t h, double dz, double gamma, void* stream) {
   need(h);
   Engine& E = h->E;
   if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  decbpm::check_prop_args(E, E.psi, dz, 1, gamma);
+  if (E.dtype == DEC_BPM_C64)
+    decbpm::autotune_t<float>(E, dz, gamma, as_stream(stream));
+  else
+    decbpm::autotune_t<double>(E, dz, gamma, as_stream(stream));
+  ABI_CATCH
+}
+
+int dec_bpm_batch_autotune(dec_bpm_batch_t b, double dz, double gamma, void* stream) {
+  ABI_TRY
+  if (!b) fail(DEC_BPM_EINVAL, "batch is NULL");
+  Engine& E = b->E;
   decbpm::check_prop_args(E, E.psi, dz, 1, gamma);
   if (E.dtype == DEC_BPM_C64)
     decbpm::autotune_t<float>(E, dz, gamma, as_stream(stream));

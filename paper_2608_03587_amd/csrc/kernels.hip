@@ -55,14 +55,17 @@ __device__ inline int64_t logical_block(int32_t remap) {
   return b;
 }
 
-template <int FB>
-__device__ inline void split(int64_t idx, int32_t F, int64_t& row, int32_t& f) {
-  if (FB == 1) {
+template <int FB, typename T>
+__device__ inline void split(int64_t idx, const DevOps<T>& d, int64_t& row, int32_t& f) {
+  if (FB == 1) {  // one field per row
     row = idx;
     f = 0;
+  } else if (FB == 2) {  // power-of-two field count
+    row = idx >> d.lgF;
+    f = int32_t(idx & ((int64_t(1) << d.lgF) - 1));
   } else {
-    row = idx / F;
-    f = int32_t(idx - row * F);
+    row = idx / d.F;
+    f = int32_t(idx - row * d.F);
   }
 }
 
@@ -73,12 +76,42 @@ inline unsigned grid_for(int64_t threads, int block, int remap) {
   return unsigned(g);
 }
 
+// Visit the stored neighbours (q, weight) of `row`.  With KMAX > 0 every
+// index and weight of the row is loaded before the first use, so a thread
+// has all its gathers in flight at once instead of a chain of W dependent
+// index -> value round trips.
+template <int KMAX, typename T, typename W_t, typename Fn>
+__device__ inline void for_neighbours(const DevOps<T>& d, const W_t* __restrict__ wt, int64_t row, Fn&& fn) {
+  const int64_t info = d.sl_info[row >> 6];
+  const int W = int(info & 0xff);
+  const int64_t base = (info >> 8) + (row & 63);
+  if constexpr (KMAX > 0) {
+    int32_t q[KMAX];
+    W_t c[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < W) {
+        q[k] = d.col[base + 64 * k];
+        c[k] = wt[base + 64 * k];
+      } else {
+        q[k] = 0;
+        c[k] = W_t(0);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < W) fn(q[k], c[k]);
+  } else {
+    for (int k = 0; k < W; ++k) fn(d.col[base + 64 * k], wt[base + 64 * k]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // RK4 stage: y = psi + coef * A x,  A = -i H_lin.
 //   B4 = false: H_lin x = p1 L x - v x (one gather of x)
 //   B4 = true : t = L x is given; H_lin x = p1 t + beta4 L t - v x (gather of t)
 // WS: also write s = |y|^2 phi(w, tau_s) for the Kerr substep that follows.
-template <typename T, int FB, bool B4, bool WS>
+template <typename T, int FB, int KMAX, bool B4, bool WS>
 __global__ void __launch_bounds__(1024) k_stage(DevOps<T> d, const typename CT<T>::C* __restrict__ x,
                                                 const typename CT<T>::C* __restrict__ t,
                                                 const typename CT<T>::C* psi, typename CT<T>::C* y, T coef,
@@ -87,25 +120,20 @@ __global__ void __launch_bounds__(1024) k_stage(DevOps<T> d, const typename CT<T
   const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
   int64_t row;
   int32_t f;
-  split<FB>(idx, d.F, row, f);
+  split<FB>(idx, d, row, f);
   if (row >= d.n_rows) return;
-  const int32_t F = FB == 1 ? 1 : d.F;
   const C* __restrict__ g = B4 ? t : x;
   const C gr = g[idx];
   const C xr = B4 ? x[idx] : gr;
-  const int64_t sl = row >> 6;
-  const int64_t base = d.sl_off[sl] + (row & 63);
-  const int W = d.sl_w[sl];
+  const C p = psi[idx];
+  const T vr = d.v[row];
   T ar = T(0), ai = T(0);
-  for (int k = 0; k < W; ++k) {
-    const int64_t e = base + int64_t(k) * 64;
-    const int64_t q = d.col[e];
-    const T c = d.lw[e];
-    const C gq = g[q * F + f];
+  const int64_t FF = FB == 1 ? 1 : d.F;
+  for_neighbours<KMAX>(d, d.lw, row, [&](int32_t q, T c) {
+    const C gq = g[int64_t(q) * FF + f];
     ar += c * (gr.x - gq.x);
     ai += c * (gr.y - gq.y);
-  }
-  const T vr = d.v[row];
+  });
   T hr, hi;
   if (B4) {
     hr = d.p1 * gr.x + d.beta4 * ar - vr * xr.x;
@@ -114,7 +142,6 @@ __global__ void __launch_bounds__(1024) k_stage(DevOps<T> d, const typename CT<T
     hr = d.p1 * ar - vr * xr.x;
     hi = d.p1 * ai - vr * xr.y;
   }
-  const C p = psi[idx];
   C out;
   out.x = p.x + coef * hi;  // -i (hr + i hi) = hi - i hr
   out.y = p.y - coef * hr;
@@ -123,29 +150,23 @@ __global__ void __launch_bounds__(1024) k_stage(DevOps<T> d, const typename CT<T
 }
 
 // t = L x
-template <typename T, int FB>
+template <typename T, int FB, int KMAX>
 __global__ void __launch_bounds__(1024) k_lap(DevOps<T> d, const typename CT<T>::C* __restrict__ x,
                                               typename CT<T>::C* __restrict__ t) {
   using C = typename CT<T>::C;
   const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
   int64_t row;
   int32_t f;
-  split<FB>(idx, d.F, row, f);
+  split<FB>(idx, d, row, f);
   if (row >= d.n_rows) return;
-  const int32_t F = FB == 1 ? 1 : d.F;
   const C xr = x[idx];
-  const int64_t sl = row >> 6;
-  const int64_t base = d.sl_off[sl] + (row & 63);
-  const int W = d.sl_w[sl];
   T ar = T(0), ai = T(0);
-  for (int k = 0; k < W; ++k) {
-    const int64_t e = base + int64_t(k) * 64;
-    const int64_t q = d.col[e];
-    const T c = d.lw[e];
-    const C xq = x[q * F + f];
+  const int64_t FF = FB == 1 ? 1 : d.F;
+  for_neighbours<KMAX>(d, d.lw, row, [&](int32_t q, T c) {
+    const C xq = x[int64_t(q) * FF + f];
     ar += c * (xr.x - xq.x);
     ai += c * (xr.y - xq.y);
-  }
+  });
   C out;
   out.x = ar;
   out.y = ai;
@@ -158,7 +179,7 @@ __global__ void __launch_bounds__(1024) k_prep_s(DevOps<T> d, const typename CT<
   const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
   int64_t row;
   int32_t f;
-  split<FB>(idx, d.F, row, f);
+  split<FB>(idx, d, row, f);
   if (row >= d.n_rows) return;
   const auto p = psi[idx];
   s[idx] = (p.x * p.x + p.y * p.y) * phi_w(d.w[row], tau);
@@ -166,7 +187,7 @@ __global__ void __launch_bounds__(1024) k_prep_s(DevOps<T> d, const typename CT<
 
 // Exact Kerr/absorber flow over tau:
 //   psi_out = psi_in e^{-w tau} exp(i gamma Theta),  Theta = M s,  s = |psi|^2 phi(w, tau).
-template <typename T, int FB, bool DEC>
+template <typename T, int FB, int KMAX, bool DEC>
 __global__ void __launch_bounds__(1024) k_kerr(DevOps<T> d, const typename CT<T>::C* psi_in,
                                                typename CT<T>::C* psi_out, const T* __restrict__ s, T tau,
                                                T gamma) {
@@ -174,23 +195,18 @@ __global__ void __launch_bounds__(1024) k_kerr(DevOps<T> d, const typename CT<T>
   const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
   int64_t row;
   int32_t f;
-  split<FB>(idx, d.F, row, f);
+  split<FB>(idx, d, row, f);
   if (row >= d.n_rows) return;
-  const int32_t F = FB == 1 ? 1 : d.F;
+  const C p = psi_in[idx];
+  const T wv = d.w[row];
   T th = d.mdiag[row] * s[idx];
   if (DEC) {
-    const int64_t sl = row >> 6;
-    const int64_t base = d.sl_off[sl] + (row & 63);
-    const int W = d.sl_w[sl];
-    for (int k = 0; k < W; ++k) {
-      const int64_t e = base + int64_t(k) * 64;
-      th += d.mw[e] * s[int64_t(d.col[e]) * F + f];
-    }
+    const int64_t FF = FB == 1 ? 1 : d.F;
+    for_neighbours<KMAX>(d, d.mw, row, [&](int32_t q, T m) { th += m * s[int64_t(q) * FF + f]; });
   }
-  const T damp = d_exp(-d.w[row] * tau);
+  const T damp = d_exp(-wv * tau);
   T sn, cs;
   d_sincos(gamma * th, &sn, &cs);
-  const C p = psi_in[idx];
   C out;
   out.x = damp * (p.x * cs - p.y * sn);
   out.y = damp * (p.x * sn + p.y * cs);
@@ -203,9 +219,9 @@ __global__ void k_perm_in(DevOps<T> d, const int32_t* __restrict__ perm, const t
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int64_t row;
   int32_t f;
-  split<FB>(idx, d.F, row, f);
+  split<FB>(idx, d, row, f);
   if (row >= d.n_rows) return;
-  const int32_t F = FB == 1 ? 1 : d.F;
+  const int64_t F = FB == 1 ? 1 : d.F;
   auto v = src[int64_t(perm[row]) * F + f];
   if (scale_inv_h0) {
     const T s = T(1.0 / d.h0[row]);
@@ -221,9 +237,9 @@ __global__ void k_perm_out(DevOps<T> d, const int32_t* __restrict__ perm, const 
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int64_t row;
   int32_t f;
-  split<FB>(idx, d.F, row, f);
+  split<FB>(idx, d, row, f);
   if (row >= d.n_rows) return;
-  const int32_t F = FB == 1 ? 1 : d.F;
+  const int64_t F = FB == 1 ? 1 : d.F;
   auto v = src[idx];
   if (scale_h0) {
     const T s = T(d.h0[row]);
@@ -287,9 +303,9 @@ __global__ void __launch_bounds__(RED_BLOCK) k_diag(DevOps<T> d, const typename 
   if (row < d.n_rows) {
     const C pr = psi[row];
     const T a = pr.x * pr.x + pr.y * pr.y;
-    const int64_t sl = row >> 6;
-    const int64_t base = d.sl_off[sl] + (row & 63);
-    const int W = d.sl_w[sl];
+    const int64_t info = d.sl_info[row >> 6];
+    const int W = int(info & 0xff);
+    const int64_t base = (info >> 8) + (row & 63);
     T lr = T(0), li = T(0), ma = d.mdiag[row] * a;
     for (int k = 0; k < W; ++k) {
       const int64_t e = base + int64_t(k) * 64;
@@ -351,7 +367,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_finish2(const double* __restrict_
 }
 
 // ---- adjoint ----
-template <typename T, bool B4>
+template <typename T, int KMAX, bool B4>
 __global__ void __launch_bounds__(1024) k_adj_stage(DevOps<T> d, const typename CT<T>::C* __restrict__ u_in,
                                                     const typename CT<T>::C* __restrict__ t,
                                                     typename CT<T>::C* __restrict__ u_out,
@@ -364,18 +380,14 @@ __global__ void __launch_bounds__(1024) k_adj_stage(DevOps<T> d, const typename 
   const C* __restrict__ g = B4 ? t : u_in;
   const C gr = g[row];
   const C ur = B4 ? u_in[row] : gr;
-  const int64_t sl = row >> 6;
-  const int64_t base = d.sl_off[sl] + (row & 63);
-  const int W = d.sl_w[sl];
+  const C yv = yf[row];
+  const T vr = d.v[row];
   T ar = T(0), ai = T(0);
-  for (int k = 0; k < W; ++k) {
-    const int64_t e = base + int64_t(k) * 64;
-    const C gq = g[d.col[e]];
-    const T c = d.lw[e];
+  for_neighbours<KMAX>(d, d.lw, row, [&](int32_t q, T c) {
+    const C gq = g[q];
     ar += c * (gr.x - gq.x);
     ai += c * (gr.y - gq.y);
-  }
-  const T vr = d.v[row];
+  });
   T hr, hi;
   if (B4) {
     hr = d.p1 * gr.x + d.beta4 * ar - vr * ur.x;
@@ -392,7 +404,6 @@ __global__ void __launch_bounds__(1024) k_adj_stage(DevOps<T> d, const typename 
   a0.x += uo.x;
   a0.y += uo.y;
   acc[row] = a0;
-  const C yv = yf[row];
   // Re(i conj(u) y) = -(u.x y.y - u.y y.x)
   gdn[row] += cdn * d.h0[row] * -(double(ur.x) * yv.y - double(ur.y) * yv.x);
 }
@@ -412,7 +423,7 @@ __global__ void k_adj_prep(DevOps<T> d, const typename CT<T>::C* __restrict__ ps
   sm[row] = o;
 }
 
-template <typename T, bool DEC>
+template <typename T, int KMAX, bool DEC>
 __global__ void __launch_bounds__(1024) k_adj_kerr(DevOps<T> d, const typename CT<T>::C* __restrict__ psi_in,
                                                    const typename CT<T>::C* lam_out,
                                                    const typename CT<T>::C* __restrict__ sm,
@@ -421,25 +432,19 @@ __global__ void __launch_bounds__(1024) k_adj_kerr(DevOps<T> d, const typename C
   const int64_t row = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
   if (row >= d.n_rows) return;
   const C own = sm[row];
-  T th = d.mdiag[row] * own.x, mm = d.mdiag[row] * own.y;
-  if (DEC) {
-    const int64_t sl = row >> 6;
-    const int64_t base = d.sl_off[sl] + (row & 63);
-    const int W = d.sl_w[sl];
-    for (int k = 0; k < W; ++k) {
-      const int64_t e = base + int64_t(k) * 64;
-      const C q = sm[d.col[e]];
-      const T m = d.mw[e];
-      th += m * q.x;
-      mm += m * q.y;
-    }
-  }
+  const C l = lam_out[row];
+  const C p = psi_in[row];
   const T wv = d.w[row];
+  T th = d.mdiag[row] * own.x, mm = d.mdiag[row] * own.y;
+  if (DEC)
+    for_neighbours<KMAX>(d, d.mw, row, [&](int32_t q, T m) {
+      const C v = sm[q];
+      th += m * v.x;
+      mm += m * v.y;
+    });
   const T damp = d_exp(-wv * tau);
   T sn, cs;
   d_sincos(gamma * th, &sn, &cs);
-  const C l = lam_out[row];
-  const C p = psi_in[row];
   const T two_phi_mm = T(2) * phi_w(wv, tau) * mm;
   C o;
   o.x = damp * (cs * l.x + sn * l.y) + two_phi_mm * p.x;  // conj(E) l + 2 phi (M mu) psi
@@ -497,48 +502,67 @@ __global__ void k_zero_f64(int64_t n, double* x) {
 #define DECBPM_M(T, p) reinterpret_cast<typename CT<T>::C*>(p)
 
 template <typename T>
+inline int fb_of(const DevOps<T>& d) {
+  return d.F == 1 ? 1 : (d.lgF >= 0 ? 2 : 0);
+}
+inline int kmax_of(int wmax) { return wmax <= 8 ? 8 : (wmax <= 12 ? 12 : 0); }
+
+// Expand BODY for the (rows-per-field mode, unroll) pair of `d`.
+#define DECBPM_DISPATCH_FB_K(d, BODY)            \
+  switch (fb_of(d) * 100 + kmax_of((d).wmax)) {  \
+    case 108: { constexpr int FB = 1, KM = 8; BODY; } break;   \
+    case 112: { constexpr int FB = 1, KM = 12; BODY; } break;  \
+    case 100: { constexpr int FB = 1, KM = 0; BODY; } break;   \
+    case 208: { constexpr int FB = 2, KM = 8; BODY; } break;   \
+    case 212: { constexpr int FB = 2, KM = 12; BODY; } break;  \
+    case 200: { constexpr int FB = 2, KM = 0; BODY; } break;   \
+    case 8: { constexpr int FB = 0, KM = 8; BODY; } break;     \
+    case 12: { constexpr int FB = 0, KM = 12; BODY; } break;   \
+    default: { constexpr int FB = 0, KM = 0; BODY; } break;    \
+  }
+#define DECBPM_DISPATCH_K(d, BODY)                               \
+  switch (kmax_of((d).wmax)) {                                   \
+    case 8: { constexpr int KM = 8; BODY; } break;               \
+    case 12: { constexpr int KM = 12; BODY; } break;             \
+    default: { constexpr int KM = 0; BODY; } break;              \
+  }
+#define DECBPM_DISPATCH_FB(d, BODY)                               \
+  switch (fb_of(d)) {                                             \
+    case 1: { constexpr int FB = 1; BODY; } break;                \
+    case 2: { constexpr int FB = 2; BODY; } break;                \
+    default: { constexpr int FB = 0; BODY; } break;               \
+  }
+
+template <typename T>
 void launch_stage(const DevOps<T>& d, const void* x, const void* t, const void* psi, void* y, double coef,
                   void* s_out, double tau_s, int block, hipStream_t st) {
   const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
-  const bool b4 = t != nullptr, ws = s_out != nullptr;
   T* s = reinterpret_cast<T*>(s_out);
-#define DECBPM_STAGE(FB, B4, WS)                                                                            \
-  hipLaunchKernelGGL((k_stage<T, FB, B4, WS>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, x), DECBPM_C(T, t), \
-                     DECBPM_C(T, psi), DECBPM_M(T, y), T(coef), s, T(tau_s))
-  if (d.F == 1) {
-    if (b4) {
-      if (ws) DECBPM_STAGE(1, true, true); else DECBPM_STAGE(1, true, false);
-    } else {
-      if (ws) DECBPM_STAGE(1, false, true); else DECBPM_STAGE(1, false, false);
-    }
-  } else {
-    if (b4) {
-      if (ws) DECBPM_STAGE(0, true, true); else DECBPM_STAGE(0, true, false);
-    } else {
-      if (ws) DECBPM_STAGE(0, false, true); else DECBPM_STAGE(0, false, false);
-    }
-  }
+#define DECBPM_STAGE(B4, WS)                                                                                 \
+  hipLaunchKernelGGL((k_stage<T, FB, KM, B4, WS>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, x),            \
+                     DECBPM_C(T, t), DECBPM_C(T, psi), DECBPM_M(T, y), T(coef), s, T(tau_s))
+  const int mode = (t != nullptr) * 2 + (s_out != nullptr);
+  DECBPM_DISPATCH_FB_K(d, {
+    if (mode == 0) DECBPM_STAGE(false, false);
+    else if (mode == 1) DECBPM_STAGE(false, true);
+    else if (mode == 2) DECBPM_STAGE(true, false);
+    else DECBPM_STAGE(true, true);
+  })
 #undef DECBPM_STAGE
 }
 
 template <typename T>
 void launch_lap(const DevOps<T>& d, const void* x, void* t, int block, hipStream_t st) {
   const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
-  if (d.F == 1)
-    hipLaunchKernelGGL((k_lap<T, 1>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, x), DECBPM_M(T, t));
-  else
-    hipLaunchKernelGGL((k_lap<T, 0>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, x), DECBPM_M(T, t));
+  DECBPM_DISPATCH_FB_K(d, hipLaunchKernelGGL((k_lap<T, FB, KM>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, x),
+                                             DECBPM_M(T, t)))
 }
 
 template <typename T>
 void launch_prep_s(const DevOps<T>& d, const void* psi, void* s, double tau, int block, hipStream_t st) {
   const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
-  if (d.F == 1)
-    hipLaunchKernelGGL((k_prep_s<T, 1>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi),
-                       reinterpret_cast<T*>(s), T(tau));
-  else
-    hipLaunchKernelGGL((k_prep_s<T, 0>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi),
-                       reinterpret_cast<T*>(s), T(tau));
+  DECBPM_DISPATCH_FB(d, hipLaunchKernelGGL((k_prep_s<T, FB>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi),
+                                           reinterpret_cast<T*>(s), T(tau)))
 }
 
 template <typename T>
@@ -546,40 +570,29 @@ void launch_kerr(const DevOps<T>& d, const void* psi_in, void* psi_out, const vo
                  int block, hipStream_t st) {
   const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
   const T* sp = reinterpret_cast<const T*>(s);
-  const bool dec = d.mw != nullptr;
-#define DECBPM_KERR(FB, DEC)                                                                            \
-  hipLaunchKernelGGL((k_kerr<T, FB, DEC>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi_in),           \
-                     DECBPM_M(T, psi_out), sp, T(tau), T(gamma))
-  if (d.F == 1) {
-    if (dec) DECBPM_KERR(1, true); else DECBPM_KERR(1, false);
+  if (d.mw) {
+    DECBPM_DISPATCH_FB_K(d, hipLaunchKernelGGL((k_kerr<T, FB, KM, true>), dim3(g), dim3(block), 0, st, d,
+                                               DECBPM_C(T, psi_in), DECBPM_M(T, psi_out), sp, T(tau), T(gamma)))
   } else {
-    if (dec) DECBPM_KERR(0, true); else DECBPM_KERR(0, false);
+    DECBPM_DISPATCH_FB(d, hipLaunchKernelGGL((k_kerr<T, FB, 0, false>), dim3(g), dim3(block), 0, st, d,
+                                             DECBPM_C(T, psi_in), DECBPM_M(T, psi_out), sp, T(tau), T(gamma)))
   }
-#undef DECBPM_KERR
 }
 
 template <typename T>
 void launch_perm_in(const DevOps<T>& d, const int32_t* perm, const void* src, void* dst, int scale_inv_h0, int block,
                     hipStream_t st) {
   const unsigned g = grid_for(d.n_rows * d.F, block, 0);
-  if (d.F == 1)
-    hipLaunchKernelGGL((k_perm_in<T, 1>), dim3(g), dim3(block), 0, st, d, perm, DECBPM_C(T, src), DECBPM_M(T, dst),
-                       scale_inv_h0);
-  else
-    hipLaunchKernelGGL((k_perm_in<T, 0>), dim3(g), dim3(block), 0, st, d, perm, DECBPM_C(T, src), DECBPM_M(T, dst),
-                       scale_inv_h0);
+  DECBPM_DISPATCH_FB(d, hipLaunchKernelGGL((k_perm_in<T, FB>), dim3(g), dim3(block), 0, st, d, perm,
+                                           DECBPM_C(T, src), DECBPM_M(T, dst), scale_inv_h0))
 }
 
 template <typename T>
 void launch_perm_out(const DevOps<T>& d, const int32_t* perm, const void* src, void* dst, int scale_h0, int* flag,
                      int block, hipStream_t st) {
   const unsigned g = grid_for(d.n_rows * d.F, block, 0);
-  if (d.F == 1)
-    hipLaunchKernelGGL((k_perm_out<T, 1>), dim3(g), dim3(block), 0, st, d, perm, DECBPM_C(T, src), DECBPM_M(T, dst),
-                       scale_h0, flag);
-  else
-    hipLaunchKernelGGL((k_perm_out<T, 0>), dim3(g), dim3(block), 0, st, d, perm, DECBPM_C(T, src), DECBPM_M(T, dst),
-                       scale_h0, flag);
+  DECBPM_DISPATCH_FB(d, hipLaunchKernelGGL((k_perm_out<T, FB>), dim3(g), dim3(block), 0, st, d, perm,
+                                           DECBPM_C(T, src), DECBPM_M(T, dst), scale_h0, flag))
 }
 
 template <typename T>
@@ -618,12 +631,15 @@ template <typename T>
 void launch_adj_stage(const DevOps<T>& d, const void* u_in, const void* t, void* u_out, void* acc, int init,
                       const void* yf, double coef, double cdn, double* gdn, int block, hipStream_t st) {
   const unsigned g = grid_for(d.n_rows, block, d.xcd_remap);
-  if (t)
-    hipLaunchKernelGGL((k_adj_stage<T, true>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, u_in), DECBPM_C(T, t),
-                       DECBPM_M(T, u_out), DECBPM_M(T, acc), init, DECBPM_C(T, yf), T(coef), cdn, gdn);
-  else
-    hipLaunchKernelGGL((k_adj_stage<T, false>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, u_in), DECBPM_C(T, t),
-                       DECBPM_M(T, u_out), DECBPM_M(T, acc), init, DECBPM_C(T, yf), T(coef), cdn, gdn);
+  if (t) {
+    DECBPM_DISPATCH_K(d, hipLaunchKernelGGL((k_adj_stage<T, KM, true>), dim3(g), dim3(block), 0, st, d,
+                                            DECBPM_C(T, u_in), DECBPM_C(T, t), DECBPM_M(T, u_out), DECBPM_M(T, acc),
+                                            init, DECBPM_C(T, yf), T(coef), cdn, gdn))
+  } else {
+    DECBPM_DISPATCH_K(d, hipLaunchKernelGGL((k_adj_stage<T, KM, false>), dim3(g), dim3(block), 0, st, d,
+                                            DECBPM_C(T, u_in), DECBPM_C(T, t), DECBPM_M(T, u_out), DECBPM_M(T, acc),
+                                            init, DECBPM_C(T, yf), T(coef), cdn, gdn))
+  }
 }
 
 template <typename T>
@@ -638,12 +654,14 @@ template <typename T>
 void launch_adj_kerr(const DevOps<T>& d, const void* psi_in, const void* lam_out, const void* sm, void* lam_in,
                      double tau, double gamma, int block, hipStream_t st) {
   const unsigned g = grid_for(d.n_rows, block, d.xcd_remap);
-  if (d.mw)
-    hipLaunchKernelGGL((k_adj_kerr<T, true>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi_in),
+  if (d.mw) {
+    DECBPM_DISPATCH_K(d, hipLaunchKernelGGL((k_adj_kerr<T, KM, true>), dim3(g), dim3(block), 0, st, d,
+                                            DECBPM_C(T, psi_in), DECBPM_C(T, lam_out), DECBPM_C(T, sm),
+                                            DECBPM_M(T, lam_in), T(tau), T(gamma)))
+  } else {
+    hipLaunchKernelGGL((k_adj_kerr<T, 0, false>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi_in),
                        DECBPM_C(T, lam_out), DECBPM_C(T, sm), DECBPM_M(T, lam_in), T(tau), T(gamma));
-  else
-    hipLaunchKernelGGL((k_adj_kerr<T, false>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi_in),
-                       DECBPM_C(T, lam_out), DECBPM_C(T, sm), DECBPM_M(T, lam_in), T(tau), T(gamma));
+  }
 }
 
 template <typename T>

@@ -13,9 +13,10 @@ namespace decbpm {
 //
 // The operators are stored as sliced ELL with slices of 64 rows (one
 // wavefront): slice s keeps width W_s = max off-diagonal degree of its rows,
-// and entry k of row r lives at sl_off[s] + k * 64 + (r & 63), so lane j of a
-// wavefront reading entry k touches consecutive words.  Only off-diagonal
-// neighbours are stored; L is applied in difference form
+// and entry k of row r lives at off_s + k * 64 + (r & 63), so lane j of a
+// wavefront reading entry k touches consecutive words.  One 64-bit word per
+// slice packs sl_info[s] = (off_s << 8) | W_s.  Only off-diagonal neighbours
+// are stored; L is applied in difference form
 //   (L x)_p = sum_q c_pq (x_p - x_q),   c_pq = -K_pq / H0_p,
 // which makes L 1 = 0 exact in floating point.  Padding entries point at the
 // row itself with zero weights.
@@ -23,8 +24,9 @@ template <typename T>
 struct DevOps {
   int64_t n_rows;      // rows (vertices summed over meshes)
   int32_t F;           // fields per row
-  const int64_t* sl_off;
-  const int32_t* sl_w;
+  int32_t lgF;         // log2(F) when F is a power of two, else -1
+  int32_t wmax;        // largest slice width
+  const int64_t* sl_info;
   const int32_t* col;  // device-order neighbour
   const T* lw;         // c_pq
   const T* mw;         // M_pq (off-diagonal), nullptr for the lumped nonlinearity
