@@ -58,8 +58,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="only the timed propagation (for rocprofv3)")
-    ap.add_argument("--block", type=int, default=0, help="fixed block size (skips autotuning)")
-    ap.add_argument("--spg", type=int, default=0, help="fixed steps per graph (with --block)")
+    ap.add_argument("--tuning", default="", help="fixed launch shape as JSON (skips autotuning), e.g. the "
+                                                 "config.tuning of a previous run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -85,8 +85,8 @@ def main():
 
     def make(dtype):
         m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=dtype, p1=w.p1, beta4=w.beta4)
-        if args.block:
-            m.tuning = {"block_size": args.block, "steps_per_graph": args.spg or 128}
+        if args.tuning:
+            m.tuning = json.loads(args.tuning)
         else:
             m.autotune(w.dz, w.gamma)
         return m
@@ -230,6 +230,7 @@ def bench_batched(api, W, torch, dev, tdt):
     # plain: the first field of every mesh, full length, autotuned per mesh
     t_plain = 0.0
     same = True
+    max_rel = max_rel_unfused = 0.0
     for m, x, o in zip(meshes, ws, outs):
         m.autotune(dz, 1.0)
         f = torch.from_numpy(x.u0[0]).to(dev, tdt["c64"])
@@ -240,12 +241,20 @@ def bench_batched(api, W, torch, dev, tdt):
         e1.record()
         torch.cuda.synchronize()
         t_plain += e0.elapsed_time(e1) * F
-        same &= bool(torch.equal(o[0].contiguous(), f))
+        ref = o[0].contiguous()
+        max_rel = max(max_rel, float(torch.linalg.norm(ref - f) / torch.linalg.norm(ref)))
+        # the unfused plain kernels use the same per-row formulas as the batched kernels
+        m.tuning = {"fused": 0}
+        g = torch.from_numpy(x.u0[0]).to(dev, tdt["c64"])
+        m.propagate(g, dz, n_steps, 1.0)
+        same &= bool(torch.equal(ref, g))
+        max_rel_unfused = max(max_rel_unfused, float(torch.linalg.norm(ref - g) / torch.linalg.norm(ref)))
     kt = batch.time_kernels(dz, 1.0, reps=20)["stage"]
     res = {"vertex_field_steps_per_s": vf * n_steps / (t_b * 1e-3), "ms": t_b,
            "plain_ms_extrapolated": t_plain, "speedup_vs_plain": t_plain / t_b,
            "stage_GBps": kt["bytes"] / (kt["ms"] * 1e-3) / 1e9, "stage_frac_hbm": kt["bytes"] / (kt["ms"] * 1e-3) / 8e12,
-           "batched_equals_plain_bitwise": same, "fields": F * len(ws), "vertex_fields": vf, "steps": n_steps,
+           "batched_equals_unfused_plain_bitwise": same, "max_rel_vs_unfused_plain": max_rel_unfused,
+           "max_rel_vs_tuned_plain": max_rel, "fields": F * len(ws), "vertex_fields": vf, "steps": n_steps,
            "note": "plain = 8 fields (one per mesh) timed at full length x 32"}
     log(f"[bench] batched: {res['vertex_field_steps_per_s']:.3e} vertex-field z-steps/s, "
         f"{res['speedup_vs_plain']:.1f}x plain, bitwise equal {same}")

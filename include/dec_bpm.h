@@ -221,14 +221,21 @@ int dec_bpm_batch_propagate(dec_bpm_batch_t b, void* packed_fields, double dz, i
                             void* stream);
 
 /*
- * Launch tuning.  dec_bpm_autotune times candidate (block size, steps per
- * graph) pairs on the handle's own work buffers with HIP events and keeps the
- * fastest; the result is cached in the JSON file named by DEC_BPM_TUNE_CACHE
- * if that variable is set.  Synchronises.
+ * Launch tuning.  dec_bpm_autotune times candidate launch shapes (unfused:
+ * block size; fused LDS-tiled path: threads per tile; both: z steps per
+ * hipGraph and the XCD-aware block mapping) on the handle's own work buffers
+ * with HIP events and keeps the fastest; the result is cached in the JSON file
+ * named by DEC_BPM_TUNE_CACHE if that variable is set.  Synchronises.  The
+ * fused path (two kernels per z step: stages 2+3, and stage 4 + Kerr/absorber
+ * + next stage 1, each on a tile of rows with its halo rings in LDS) exists
+ * for one-field handles without the beta4 term.
  */
 typedef struct {
-  int32_t block_size;
-  int32_t steps_per_graph;
+  int32_t block_size;       /* threads per workgroup of the unfused kernels      */
+  int32_t steps_per_graph;  /* z steps per captured hipGraph (1 = no graph)      */
+  int32_t fused;            /* 1: fused tile kernels (if available)              */
+  int32_t tile_block;       /* threads per workgroup of the fused kernels        */
+  int32_t xcd_remap;        /* 1: consecutive row blocks on one XCD               */
 } dec_bpm_tuning;
 int dec_bpm_autotune(dec_bpm_t h, double dz, double gamma, void* stream);
 int dec_bpm_batch_autotune(dec_bpm_batch_t b, double dz, double gamma, void* stream);
@@ -236,16 +243,19 @@ int dec_bpm_get_tuning(dec_bpm_t h, dec_bpm_tuning* t);
 int dec_bpm_set_tuning(dec_bpm_t h, const dec_bpm_tuning* t);
 
 /*
- * Per-kernel timing with HIP events on `stream`: runs `reps` z steps and
- * writes the mean device time in milliseconds of each kernel class into
- * ms[DEC_BPM_NUM_KERNELS] and the algorithmic bytes one launch of it moves
- * into bytes[DEC_BPM_NUM_KERNELS] (either may be NULL).  Synchronises.
+ * Per-kernel timing with HIP events on `stream`: each kernel class is
+ * captured `reps` times back to back in a hipGraph and timed; the mean device
+ * time per launch in milliseconds goes to ms[DEC_BPM_NUM_KERNELS] and the
+ * algorithmic bytes one launch moves to bytes[DEC_BPM_NUM_KERNELS] (either may
+ * be NULL; classes a handle does not use report 0).  Synchronises.
  */
 enum {
-  DEC_BPM_K_KERR = 0,   /* fused Kerr phase + absorber (M gather)               */
-  DEC_BPM_K_STAGE = 1,  /* RK4 stage: L gather + stage update                   */
-  DEC_BPM_K_LAP = 2,    /* bare L application (first half of a beta4 stage)    */
-  DEC_BPM_NUM_KERNELS = 3
+  DEC_BPM_K_KERR = 0,     /* fused Kerr phase + absorber (M gather)               */
+  DEC_BPM_K_STAGE = 1,    /* RK4 stage: L gather + stage update                   */
+  DEC_BPM_K_LAP = 2,      /* bare L application (first half of a beta4 stage)    */
+  DEC_BPM_K_TILE_A = 3,   /* fused tile kernel: stage 4 + Kerr/absorber + stage 1 */
+  DEC_BPM_K_TILE_B = 4,   /* fused tile kernel: stages 2 + 3                      */
+  DEC_BPM_NUM_KERNELS = 5
 };
 int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
                          void* stream);

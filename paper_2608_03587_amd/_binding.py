@@ -20,7 +20,7 @@ OK, EINVAL, EMESH, EUNSTABLE, ENOMEM, EHIP, ENONFINITE, EWORKSPACE, ENODEVICE = 
 C64, C128 = 1, 2
 NL_DEC, NL_LUMPED = 0, 1
 OP_L, OP_L2, OP_H = 0, 1, 2
-K_KERR, K_STAGE, K_LAP, NUM_KERNELS = 0, 1, 2, 3
+K_KERR, K_STAGE, K_LAP, K_TILE_A, K_TILE_B, NUM_KERNELS = 0, 1, 2, 3, 4, 5
 
 ERROR_NAMES = {EINVAL: "EINVAL", EMESH: "EMESH", EUNSTABLE: "EUNSTABLE", ENOMEM: "ENOMEM", EHIP: "EHIP",
                ENONFINITE: "ENONFINITE", EWORKSPACE: "EWORKSPACE", ENODEVICE: "ENODEVICE"}
@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("block_size", c_i32), ("steps_per_graph", c_i32)]
+    _fields_ = [("block_size", c_i32), ("steps_per_graph", c_i32), ("fused", c_i32), ("tile_block", c_i32),
+                ("xcd_remap", c_i32)]
 
 
 class DecBpmError(RuntimeError):

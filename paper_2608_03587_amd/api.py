@@ -206,11 +206,13 @@ class Mesh:
     def tuning(self):
         t = B.Tuning()
         B.check(B.lib().dec_bpm_get_tuning(self._h, ctypes.byref(t)))
-        return {"block_size": t.block_size, "steps_per_graph": t.steps_per_graph}
+        return {f: getattr(t, f) for f, _ in B.Tuning._fields_}
 
     @tuning.setter
     def tuning(self, value):
-        t = B.Tuning(int(value["block_size"]), int(value["steps_per_graph"]))
+        cur = self.tuning
+        cur.update(value)
+        t = B.Tuning(*[int(cur[f]) for f, _ in B.Tuning._fields_])
         B.check(B.lib().dec_bpm_set_tuning(self._h, ctypes.byref(t)))
 
     def time_kernels(self, dz, gamma=1.0, reps=50, stream=None):
@@ -221,7 +223,7 @@ def _time_kernels(fn, h, dz, gamma, reps, stream):
     ms = (ctypes.c_double * B.NUM_KERNELS)()
     by = (ctypes.c_double * B.NUM_KERNELS)()
     B.check(fn(h, float(dz), float(gamma), int(reps), ms, by, _stream(stream)))
-    names = {B.K_KERR: "kerr", B.K_STAGE: "stage", B.K_LAP: "lap"}
+    names = {B.K_KERR: "kerr", B.K_STAGE: "stage", B.K_LAP: "lap", B.K_TILE_A: "tile_a", B.K_TILE_B: "tile_b"}
     return {names[k]: {"ms": ms[k], "bytes": by[k]} for k in range(B.NUM_KERNELS)}
 
 

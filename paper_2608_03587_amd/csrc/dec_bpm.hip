@@ -37,7 +37,7 @@ constexpr double kStabilityLimit = 2.5;
 
 struct GraphEntry {
   double dz, gamma;
-  int spg, block, xcd;
+  int spg, block, xcd, fused, tile_block;
   hipGraphExec_t exec;
   hipGraph_t graph;
 };
@@ -66,6 +66,21 @@ struct Engine {
   double* h0 = nullptr;
   double* h0c = nullptr;  // caller order
   int32_t* perm = nullptr;
+  // tiles of the fused path (F = 1, beta4 = 0)
+  bool has_tiles = false;
+  int fused = 1;      // use the fused kernels when tiles exist
+  int tile_size = 512;
+  int tile_block = 256;
+  int32_t n_tiles = 0, max_slots = 0, max_compute = 0;
+  int32_t* t_hdr = nullptr;
+  int64_t* t_ent = nullptr;
+  int32_t* t_ext = nullptr;
+  int32_t* t_lsl = nullptr;
+  uint16_t* t_lcol = nullptr;
+  void* t_llw = nullptr;
+  void* t_lmw = nullptr;
+  int64_t t_entries = 0, t_slots = 0;
+  void* psi2 = nullptr;
   // work
   void* psi = nullptr;
   void* ya = nullptr;
@@ -92,8 +107,32 @@ struct Engine {
   } ckpt;
   uint64_t dn_version = 0;
 
+  // threads per tile workgroup: the requested count, raised so that no thread
+  // owns more than two compute slots of a tile (the fused kernels' register budget)
+  int tblock() const {
+    const int need = ((max_compute + 1) / 2 + 63) / 64 * 64;
+    return std::min(1024, std::max(tile_block, need));
+  }
+
   size_t real_size() const { return dtype == DEC_BPM_C64 ? 4 : 8; }
   size_t cplx_size() const { return 2 * real_size(); }
+
+  template <typename T>
+  TileOps<T> tiles() const {
+    TileOps<T> t;
+    t.n_tiles = n_tiles;
+    t.TS = tile_size;
+    t.max_slots = max_slots;
+    t.max_compute = max_compute;
+    t.hdr = t_hdr;
+    t.ent_base = t_ent;
+    t.ext = t_ext;
+    t.lsl = t_lsl;
+    t.lcol = t_lcol;
+    t.llw = static_cast<const T*>(t_llw);
+    t.lmw = static_cast<const T*>(t_lmw);
+    return t;
+  }
 
   template <typename T>
   DevOps<T> ops() const {
@@ -153,6 +192,8 @@ struct Engine {
 
 // Default launch shape from the environment (used before any autotuning).
 static void env_defaults(Engine& E) {
+  if (const char* s = std::getenv("DEC_BPM_TILE")) E.tile_size = std::max(64, std::min(4096, std::atoi(s)));
+  if (const char* s = std::getenv("DEC_BPM_FUSED")) E.fused = std::atoi(s) ? 1 : 0;
   if (const char* s = std::getenv("DEC_BPM_BLOCK")) E.block = std::max(64, std::min(1024, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_STEPS_PER_GRAPH")) E.spg = std::max(1, std::atoi(s));
   if (const char* s = std::getenv("DEC_BPM_XCD_REMAP")) E.xcd = std::atoi(s) ? 1 : 0;
@@ -162,6 +203,124 @@ template <typename T>
 static void upload(Engine& E, void*& dst, const std::vector<T>& src) {
   dst = E.dalloc(src.size() * sizeof(T));
   HIP_OK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// Tiles of the fused path: contiguous ranges of tile_size device rows plus
+// three halo rings found by breadth-first search on the adjacency; the
+// operator rows of rings 0..2 are stored again with slot-local columns.
+template <typename T>
+static bool build_tiles_ts(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
+                           const std::vector<double>& alw, const std::vector<double>& amw, bool dec, int TS) {
+  const int64_t n = E.n_rows;
+  const int64_t nt = (n + TS - 1) / TS;
+  std::vector<int32_t> hdr(nt * 8, 0), ext, lsl;
+  std::vector<int64_t> ebase(nt);
+  std::vector<uint16_t> lcol;
+  std::vector<T> llw, lmw;
+  std::vector<int32_t> slot_of(n, -1);
+  int32_t max_slots = 0, max_compute = 0;
+  std::vector<int32_t> slots, ring;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t r0 = t * TS, r1 = std::min(n, r0 + TS);
+    slots.clear();
+    for (int64_t r = r0; r < r1; ++r) {
+      slot_of[r] = int32_t(r - r0);
+      slots.push_back(int32_t(r));
+    }
+    int cnt[4] = {int(r1 - r0), 0, 0, 0};
+    size_t start = 0, end = slots.size();
+    for (int k = 1; k <= 3; ++k) {
+      ring.clear();
+      for (size_t i = start; i < end; ++i)
+        for (int64_t e = arp[slots[i]]; e < arp[slots[i] + 1]; ++e)
+          if (slot_of[acol[e]] == -1) {
+            slot_of[acol[e]] = -2;
+            ring.push_back(acol[e]);
+          }
+      std::sort(ring.begin(), ring.end());
+      for (int32_t q : ring) {
+        slot_of[q] = int32_t(slots.size());
+        slots.push_back(q);
+      }
+      cnt[k] = int(ring.size());
+      start = end;
+      end = slots.size();
+    }
+    if (slots.size() >= 65535) fail(DEC_BPM_EINVAL, "tile too large for 16-bit slot indices");
+    int32_t* h = &hdr[t * 8];
+    h[0] = cnt[0];
+    h[1] = cnt[1];
+    h[2] = cnt[2];
+    h[3] = cnt[3];
+    h[4] = int32_t(ext.size());
+    h[5] = int32_t(lsl.size());
+    ext.insert(ext.end(), slots.begin() + cnt[0], slots.end());
+    const int c2 = cnt[0] + cnt[1] + cnt[2];
+    max_compute = std::max(max_compute, c2);
+    ebase[t] = int64_t(lcol.size());
+    for (int sl = 0; sl * 64 < c2; ++sl) {
+      int W = 0;
+      for (int i = sl * 64; i < std::min(c2, sl * 64 + 64); ++i)
+        W = std::max<int>(W, int(arp[slots[i] + 1] - arp[slots[i]]));
+      const int64_t rel = int64_t(lcol.size()) - ebase[t];
+      lsl.push_back(int32_t((rel << 8) | W));
+      const size_t b = lcol.size();
+      lcol.resize(b + size_t(W) * 64, 0);
+      llw.resize(b + size_t(W) * 64, T(0));
+      lmw.resize(b + size_t(W) * 64, T(0));
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = sl * 64 + lane;
+        for (int k = 0; k < W; ++k) lcol[b + size_t(k) * 64 + lane] = uint16_t(i < c2 ? i : 0);  // padding: self
+        if (i >= c2) continue;
+        int k = 0;
+        for (int64_t e = arp[slots[i]]; e < arp[slots[i] + 1]; ++e, ++k) {
+          const int32_t q = slot_of[acol[e]];
+          if (q < 0) fail(DEC_BPM_EINVAL, "internal: halo ring incomplete");
+          lcol[b + size_t(k) * 64 + lane] = uint16_t(q);
+          llw[b + size_t(k) * 64 + lane] = T(alw[e]);
+          lmw[b + size_t(k) * 64 + lane] = T(amw[e]);
+        }
+      }
+    }
+    if (int64_t(lcol.size()) - ebase[t] >= (int64_t(1) << 23)) fail(DEC_BPM_EINVAL, "tile operator too large");
+    max_slots = std::max<int32_t>(max_slots, int32_t(slots.size()));
+    for (int32_t r : slots) slot_of[r] = -1;
+  }
+  max_slots = (max_slots + 3) / 4 * 4;
+  const size_t shmem = size_t(max_slots) * (7 * sizeof(T));
+  if (shmem > 64 * 1024) return false;      // a tile does not fit one workgroup's LDS
+  if (max_compute > 2 * 1024) return false;  // a thread keeps at most two slots' rows in registers
+  void* p;
+  upload(E, p, hdr);
+  E.t_hdr = static_cast<int32_t*>(p);
+  upload(E, p, ebase);
+  E.t_ent = static_cast<int64_t*>(p);
+  if (ext.empty()) ext.push_back(0);
+  upload(E, p, ext);
+  E.t_ext = static_cast<int32_t*>(p);
+  upload(E, p, lsl);
+  E.t_lsl = static_cast<int32_t*>(p);
+  upload(E, p, lcol);
+  E.t_lcol = static_cast<uint16_t*>(p);
+  upload(E, E.t_llw, llw);
+  if (dec) upload(E, E.t_lmw, lmw);
+  E.n_tiles = int32_t(nt);
+  E.max_slots = max_slots;
+  E.max_compute = max_compute;
+  E.t_entries = int64_t(lcol.size());
+  E.t_slots = int64_t(ext.size()) + n;
+  E.tile_size = TS;
+  E.has_tiles = true;
+  return true;
+}
+
+// Largest tile size (from the requested one, halving) whose biggest tile with
+// its halo rings fits 64 KB of LDS; no tiles (unfused path only) if none does.
+template <typename T>
+static void build_tiles(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
+                        const std::vector<double>& alw, const std::vector<double>& amw, bool dec) {
+  for (int ts = E.tile_size; ts >= 64; ts /= 2)
+    if (build_tiles_ts<T>(E, arp, acol, alw, amw, dec, ts)) return;
 }
 
 // Build the device engine from one or more assembled meshes (concatenated).
@@ -205,6 +364,13 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   std::vector<double> h0(n), h0c(n);
   std::vector<int32_t> perm(n);
   bool any_dec = false;
+  // device-order adjacency (kept on the host to build the tiles)
+  std::vector<int64_t> arp(n + 1, 0);
+  std::vector<int32_t> acol;
+  std::vector<double> alw, amw;
+  acol.reserve(E.nnz_off);
+  alw.reserve(E.nnz_off);
+  amw.reserve(E.nnz_off);
   for (int64_t r = 0; r < n; ++r) {
     const int m = row_mesh[r];
     const Assembled& a = *meshes[m];
@@ -226,6 +392,12 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
       nb.emplace_back(int32_t(off + a.iperm[a.col[e]]), e);
     }
     std::sort(nb.begin(), nb.end());
+    for (auto& e : nb) {
+      acol.push_back(e.first);
+      alw.push_back(-a.k[e.second] / hp);
+      amw.push_back(lumped[m] ? 0.0 : a.qdq[e.second] / hp);
+    }
+    arp[r + 1] = int64_t(acol.size());
     const int64_t s = r >> 6, lane = r & 63;
     for (int k = 0; k < sl_w[s]; ++k) {
       const int64_t slot = sl_off[s] + int64_t(k) * 64 + lane;
@@ -268,8 +440,10 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   E.h0c = static_cast<double*>(p);
   upload(E, p, perm);
   E.perm = static_cast<int32_t*>(p);
+  if (E.F == 1 && E.beta4 == 0.0) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
   const size_t nv = size_t(n) * E.F;
   E.psi = E.dalloc(nv * 2 * sizeof(T));
+  if (E.has_tiles) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
   E.ya = E.dalloc(nv * 2 * sizeof(T));
   E.yb = E.dalloc(nv * 2 * sizeof(T));
   E.t = E.beta4 != 0.0 ? E.dalloc(nv * 2 * sizeof(T)) : nullptr;
@@ -325,13 +499,40 @@ static void z_step(const Engine& E, const DevOps<T>& d, double dz, double gamma,
 }
 
 template <typename T>
-static hipGraphExec_t get_graph(Engine& E, double dz, double gamma) {
+static bool use_fused(const Engine& E) {
+  return E.has_tiles && E.fused;
+}
+
+// One fused middle z step: state cur (psi after NL) and y1 in ya -> next state in nxt, its y1 in ya.
+template <typename T>
+static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl, void* cur, void* nxt, double dz,
+                      double gamma, hipStream_t st) {
+  launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, cur, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), st);
+  launch_fused<T>(d, tl, FUSED_S4_NL_S1, E.yb, cur, nxt, E.ya, nullptr, dz, dz, gamma, E.tblock(), st);
+}
+
+// Steps captured per graph: the fused path alternates two state buffers, so
+// its graphs hold an even number of steps and start and end on psi2.
+static int graph_steps(const Engine& E, bool fused) { return fused ? std::max(2, E.spg / 2 * 2) : E.spg; }
+
+template <typename T>
+static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, bool fused) {
+  const int tb = fused ? E.tblock() : 0;
   for (auto& g : E.graphs)
-    if (g.dz == dz && g.gamma == gamma && g.spg == E.spg && g.block == E.block && g.xcd == E.xcd) return g.exec;
+    if (g.dz == dz && g.gamma == gamma && g.spg == E.spg && g.block == E.block && g.xcd == E.xcd &&
+        g.fused == int(fused) && g.tile_block == tb)
+      return g.exec;
   const DevOps<T> d = E.ops<T>();
+  const TileOps<T> tl = E.tiles<T>();
   hipGraph_t graph;
   HIP_OK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < E.spg; ++k) z_step<T>(E, d, dz, gamma, dz, E.cap);
+  const int steps = graph_steps(E, fused);
+  for (int k = 0; k < steps; ++k) {
+    if (fused)
+      fused_mid<T>(E, d, tl, k % 2 ? E.psi : E.psi2, k % 2 ? E.psi2 : E.psi, dz, gamma, E.cap);
+    else
+      z_step<T>(E, d, dz, gamma, dz, E.cap);
+  }
   hipError_t le = hipGetLastError();
   HIP_OK(hipStreamEndCapture(E.cap, &graph));
   if (le != hipSuccess) fail(DEC_BPM_EHIP, std::string("launch during capture: ") + hipGetErrorString(le));
@@ -342,7 +543,7 @@ static hipGraphExec_t get_graph(Engine& E, double dz, double gamma) {
     (void)hipGraphDestroy(E.graphs.front().graph);
     E.graphs.erase(E.graphs.begin());
   }
-  E.graphs.push_back(GraphEntry{dz, gamma, E.spg, E.block, E.xcd, exec, graph});
+  E.graphs.push_back(GraphEntry{dz, gamma, E.spg, E.block, E.xcd, int(fused), tb, exec, graph});
   return exec;
 }
 
@@ -369,16 +570,27 @@ static void check_prop_args(const Engine& E, const void* field, double dz, int64
   if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
 }
 
-// Middle steps (merged NL(dz)) through graph replays, then the remainder eagerly.
+// Middle steps (merged NL(dz)) through graph replays, then the remainder
+// eagerly.  Fused path: enters and leaves with the state in psi2 when count is
+// even, in psi when odd; returns the buffer holding the state.
 template <typename T>
-static void run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st) {
+static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st) {
   const DevOps<T> d = E.ops<T>();
+  const bool fused = use_fused<T>(E);
+  const int gs = graph_steps(E, fused);
   int64_t done = 0;
-  if (E.spg > 1 && count >= E.spg) {
-    hipGraphExec_t ex = get_graph<T>(E, dz, gamma);
-    for (; done + E.spg <= count; done += E.spg) HIP_OK(hipGraphLaunch(ex, st));
+  if (E.spg > 1 && count >= gs) {
+    hipGraphExec_t ex = get_graph<T>(E, dz, gamma, fused);
+    for (; done + gs <= count; done += gs) HIP_OK(hipGraphLaunch(ex, st));
   }
-  for (; done < count; ++done) z_step<T>(E, d, dz, gamma, dz, st);
+  if (!fused) {
+    for (; done < count; ++done) z_step<T>(E, d, dz, gamma, dz, st);
+    return E.psi;
+  }
+  const TileOps<T> tl = E.tiles<T>();
+  for (; done < count; ++done)
+    fused_mid<T>(E, d, tl, done % 2 ? E.psi : E.psi2, done % 2 ? E.psi2 : E.psi, dz, gamma, st);
+  return count % 2 ? E.psi : E.psi2;
 }
 
 template <typename T>
@@ -387,11 +599,22 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
   const DevOps<T> d = E.ops<T>();
   const int B = E.block;
   launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
-  launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
-  launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
-  run_middle<T>(E, n - 1, dz, gamma, st);
-  z_step<T>(E, d, dz, gamma, 0.5 * dz, st);
-  launch_perm_out<T>(d, E.perm, E.psi, field, 0, E.flag, B, st);
+  if (use_fused<T>(E)) {
+    const TileOps<T> tl = E.tiles<T>();
+    // NL(dz/2) + stage 1: state -> psi2, y1 -> ya
+    launch_fused<T>(d, tl, FUSED_NL_S1, nullptr, E.psi, E.psi2, E.ya, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
+    void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
+    void* nxt = cur == E.psi ? E.psi2 : E.psi;
+    launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, cur, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), st);
+    launch_fused<T>(d, tl, FUSED_S4_NL, E.yb, cur, nxt, nullptr, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
+    launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
+  } else {
+    launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
+    launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
+    run_middle<T>(E, n - 1, dz, gamma, st);
+    z_step<T>(E, d, dz, gamma, 0.5 * dz, st);
+    launch_perm_out<T>(d, E.perm, E.psi, field, 0, E.flag, B, st);
+  }
   check_launch();
 }
 
@@ -443,6 +666,27 @@ static void forward_ckpt_t(Engine& E, void* field, double dz, int64_t n, double 
   const int B = E.block;
   const size_t vb = (size_t(E.n_rows) * E.cplx_size() + 255) / 256 * 256;
   launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
+  if (n > 0 && use_fused<T>(E)) {
+    const TileOps<T> tl = E.tiles<T>();
+    const int TB = E.tblock();
+    launch_copy<T>(E.n_rows, E.psi, ws + L.x0, B, st);
+    launch_fused<T>(d, tl, FUSED_NL_S1, nullptr, E.psi, E.psi2, E.ya, nullptr, dz, 0.5 * dz, gamma, TB, st);
+    launch_copy<T>(E.n_rows, E.psi2, ws + L.ck, B, st);
+    void* cur = E.psi2;
+    void* nxt = E.psi;
+    for (int64_t k = 1; k <= n; ++k) {
+      launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, cur, nullptr, E.yb, nullptr, dz, dz, gamma, TB, st);
+      if (k < n)
+        launch_fused<T>(d, tl, FUSED_S4_NL_S1, E.yb, cur, nxt, E.ya, nullptr, dz, dz, gamma, TB, st);
+      else
+        launch_fused<T>(d, tl, FUSED_S4_NL, E.yb, cur, nxt, nullptr, nullptr, dz, 0.5 * dz, gamma, TB, st);
+      std::swap(cur, nxt);
+      if (k % L.S == 0 && k / L.S < L.K) launch_copy<T>(E.n_rows, cur, ws + L.ck + size_t(k / L.S) * vb, B, st);
+    }
+    launch_perm_out<T>(d, E.perm, cur, field, 0, E.flag, B, st);
+    check_launch();
+    return;
+  }
   if (n > 0) {
     launch_copy<T>(E.n_rows, E.psi, ws + L.x0, B, st);
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
@@ -517,10 +761,68 @@ static void adjoint_t(Engine& E, const void* grad_out, double dz, int64_t n, dou
   check_launch();
 }
 
+// Adjoint on the fused tile kernels: each segment is recomputed with two
+// recording tile launches per step (stages 2+3 keeping y2; stage 4 + Kerr +
+// next stage 1 keeping the pre-Kerr state), then swept back with two adjoint
+// tile launches per step.
+template <typename T>
+static bool adjoint_fused_ok(const Engine& E) {
+  return use_fused<T>(E) && size_t(E.max_slots) * 4 * 2 * sizeof(T) <= 64 * 1024;
+}
+
+template <typename T>
+static void adjoint_fused_t(Engine& E, const void* grad_out, double dz, int64_t n, double gamma, int64_t every,
+                            char* ws, void* grad0, double* grad_dn, hipStream_t st) {
+  const WsLayout L = ws_layout(E, n, every);
+  const DevOps<T> d = E.ops<T>();
+  const TileOps<T> tl = E.tiles<T>();
+  const int B = E.block, TB = E.tblock();
+  const size_t vb = (size_t(E.n_rows) * E.cplx_size() + 255) / 256 * 256;
+  void* lam = ws + L.lam;
+  void* acc = ws + L.acc;
+  void* ua = ws + L.ua;
+  void* sm = ws + L.sm;
+  double* gdn = reinterpret_cast<double*>(ws + L.gdn);
+  launch_perm_in<T>(d, E.perm, grad_out, lam, 1, B, st);
+  launch_zero_f64(E.n_rows, gdn, B, st);
+  auto Y = [&](int64_t j, int k) -> void* { return ws + L.sy + size_t(3 * (j - 1) + k) * vb; };
+  auto Bv = [&](int64_t j) -> void* { return ws + L.sb + size_t(j - 1) * vb; };
+  for (int64_t seg = L.K - 1; seg >= 0 && n > 0; --seg) {
+    const int64_t n0 = seg * L.S, n1 = std::min(n, (seg + 1) * L.S), m = n1 - n0;
+    char* ck = ws + L.ck + size_t(seg) * vb;
+    auto A = [&](int64_t j) -> void* { return j == 0 ? static_cast<void*>(ck) : ws + L.sa + size_t(j) * vb; };
+    launch_stage<T>(d, A(0), nullptr, A(0), Y(1, 0), dz / 4, nullptr, 0.0, B, st);
+    for (int64_t j = 1; j <= m; ++j) {
+      const double tau = (n0 + j < n) ? dz : 0.5 * dz;
+      launch_fused<T>(d, tl, FUSED_S2_S3, Y(j, 0), A(j - 1), nullptr, Y(j, 2), Y(j, 1), dz, dz, gamma, TB, st);
+      if (j < m)
+        launch_fused<T>(d, tl, FUSED_S4_NL_S1, Y(j, 2), A(j - 1), A(j), Y(j + 1, 0), Bv(j), dz, tau, gamma, TB, st);
+      else
+        launch_fused<T>(d, tl, FUSED_S4_NL, Y(j, 2), A(j - 1), A(j), nullptr, Bv(j), dz, tau, gamma, TB, st);
+    }
+    for (int64_t j = m; j >= 1; --j) {
+      const double tau = (n0 + j < n) ? dz : 0.5 * dz;
+      launch_fused_adj<T>(d, tl, 1, lam, A(j), Bv(j), Y(j, 2), Y(j, 1), Y(j, 0), ua, acc, gdn, dz, tau, gamma, TB,
+                          st);
+      launch_fused_adj<T>(d, tl, 2, ua, A(j - 1), nullptr, nullptr, nullptr, nullptr, lam, acc, gdn, dz, tau, gamma,
+                          TB, st);
+    }
+  }
+  if (n > 0) {
+    // first half step NL(dz/2) of the run: x0 -> a_0 (checkpoint 0)
+    launch_adj_prep<T>(d, ws + L.x0, ws + L.ck, lam, sm, 0.5 * dz, gamma, B, st);
+    launch_adj_kerr<T>(d, ws + L.x0, lam, sm, lam, 0.5 * dz, gamma, B, st);
+  }
+  launch_perm_out<T>(d, E.perm, lam, grad0, 1, nullptr, B, st);
+  if (grad_dn) launch_gdn_out(E.n_rows, E.perm, gdn, grad_dn, B, st);
+  check_launch();
+}
+
 // ---- kernel timing with HIP events (graph-captured back-to-back launches) ----
 template <typename T>
 static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double* ms, double* bytes, hipStream_t st) {
   const DevOps<T> d = E.ops<T>();
+  const TileOps<T> tl = E.tiles<T>();
   const int B = E.block;
   const double sr = sizeof(T), sc = 2 * sizeof(T);
   const double nF = double(E.n_rows) * E.F, nr = double(E.n_rows);
@@ -529,20 +831,36 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   by[DEC_BPM_K_KERR] = mat + nr * 2 * sr + nF * (sr + 2 * sc);
   by[DEC_BPM_K_STAGE] = mat + nr * sr + nF * 3 * sc;
   by[DEC_BPM_K_LAP] = mat + nF * 2 * sc;
+  // fused kernels, counted once per owned row (halo recompute is overhead, not algorithmic):
+  // A reads y3, psi, v, w, M_pp and both operators; writes psi'' and y1.  B reads y1, psi, v, L; writes y3.
+  by[DEC_BPM_K_TILE_A] = double(E.nnz_off) * (4.0 + 2 * sr) + nr * 3 * sr + nr * 4 * sc;
+  by[DEC_BPM_K_TILE_B] = mat + nr * sr + nr * 3 * sc;
   launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
   launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
+  launch_fill<T>(d, E.yb, 0.2, -0.1, B, st);
+  if (E.psi2) launch_fill<T>(d, E.psi2, 0.3, 0.1, B, st);
   launch_prep_s<T>(d, E.psi, E.s, dz, B, st);
   HIP_OK(hipStreamSynchronize(st));
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
   for (int kind = 0; kind < DEC_BPM_NUM_KERNELS; ++kind) {
+    const bool tile_kind = kind == DEC_BPM_K_TILE_A || kind == DEC_BPM_K_TILE_B;
+    if (tile_kind && !E.has_tiles) {
+      if (ms) ms[kind] = 0.0;
+      if (bytes) bytes[kind] = 0.0;
+      continue;
+    }
     hipGraph_t g;
     HIP_OK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
     for (int r = 0; r < reps; ++r) {
       if (kind == DEC_BPM_K_KERR) launch_kerr<T>(d, E.psi, E.psi, E.s, dz, gamma, B, E.cap);
       if (kind == DEC_BPM_K_STAGE) launch_stage<T>(d, E.ya, nullptr, E.psi, E.yb, dz / 3, nullptr, 0.0, B, E.cap);
       if (kind == DEC_BPM_K_LAP) launch_lap<T>(d, E.ya, E.yb, B, E.cap);
+      if (kind == DEC_BPM_K_TILE_A)
+        launch_fused<T>(d, tl, FUSED_S4_NL_S1, E.yb, E.psi, E.psi2, E.ya, nullptr, dz, dz, gamma, E.tblock(), E.cap);
+      if (kind == DEC_BPM_K_TILE_B)
+        launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, E.psi, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), E.cap);
     }
     HIP_OK(hipStreamEndCapture(E.cap, &g));
     hipGraphExec_t ex;
@@ -567,7 +885,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
 static std::string tune_key(const Engine& E) {
   std::ostringstream o;
   o << "n" << E.n_rows << "_e" << E.n_entries << "_F" << E.F << "_d" << E.dtype << "_b4" << (E.beta4 != 0.0) << "_nl"
-    << (E.mw ? 0 : 1);
+    << (E.mw ? 0 : 1) << "_ts" << (E.has_tiles ? E.tile_size : 0);
   return o.str();
 }
 
@@ -580,13 +898,16 @@ static bool tune_cache_lookup(Engine& E) {
   while (std::getline(f, line)) {
     size_t p = line.find(key);
     if (p == std::string::npos) continue;
-    int b = 0, s = 0, x = 1;
-    if (std::sscanf(line.c_str() + p + key.size(), ": {\"block\": %d, \"steps_per_graph\": %d, \"xcd\": %d}", &b, &s,
-                    &x) >= 2 &&
-        b >= 64 && s >= 1) {
+    int b = 0, s = 0, x = 1, fu = 0, tb = 256;
+    if (std::sscanf(line.c_str() + p + key.size(),
+                    ": {\"block\": %d, \"steps_per_graph\": %d, \"xcd\": %d, \"fused\": %d, \"tile_block\": %d}",
+                    &b, &s, &x, &fu, &tb) == 5 &&
+        b >= 64 && s >= 1 && tb >= 64) {
       E.block = b;
       E.spg = s;
       E.xcd = x;
+      E.fused = E.has_tiles ? fu : 0;
+      E.tile_block = tb;
       return true;
     }
   }
@@ -612,50 +933,60 @@ static void tune_cache_store(const Engine& E) {
     f << x << ",\n";
   }
   f << "  \"" << tune_key(E) << "\": {\"block\": " << E.block << ", \"steps_per_graph\": " << E.spg
-    << ", \"xcd\": " << E.xcd << "}\n}\n";
+    << ", \"xcd\": " << E.xcd << ", \"fused\": " << E.fused << ", \"tile_block\": " << E.tile_block << "}\n}\n";
 }
 
 template <typename T>
 static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
   if (tune_cache_lookup(E)) return;
   const DevOps<T> d0 = E.ops<T>();
-  const int blocks[] = {64, 128, 256, 512, 1024};
-  const int spgs[] = {1, 8, 32, 128};
-  const int xcds[] = {0, 1};
+  struct Cand {
+    int fused, block, tile_block, spg, xcd;
+  };
+  std::vector<Cand> cands;
+  for (int x : {0, 1})
+    for (int s : {1, 8, 32, 128}) {
+      for (int b : {64, 128, 256, 512, 1024}) cands.push_back({0, b, E.tile_block, s, x});
+      if (E.has_tiles)
+        for (int tb : {128, 256, 512, 1024}) cands.push_back({1, E.block, tb, s, x});
+    }
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
   double best = 1e300;
-  int bb = E.block, bs = E.spg, bx = E.xcd;
+  Cand bc{E.fused, E.block, E.tile_block, E.spg, E.xcd};
   const int64_t steps = 128;
-  for (int x : xcds)
-    for (int b : blocks)
-      for (int s : spgs) {
-        E.block = b;
-        E.spg = s;
-        E.xcd = x;
-        launch_fill<T>(d0, E.psi, 0.3, 0.1, 256, st);
-        launch_prep_s<T>(d0, E.psi, E.s, dz, 256, st);
-        run_middle<T>(E, s, dz, gamma, st);  // warm-up (and graph instantiation)
-        HIP_OK(hipEventRecord(e0, st));
-        run_middle<T>(E, steps, dz, gamma, st);
-        HIP_OK(hipEventRecord(e1, st));
-        HIP_OK(hipEventSynchronize(e1));
-        float t = 0;
-        HIP_OK(hipEventElapsedTime(&t, e0, e1));
-        if (t < best) {
-          best = t;
-          bb = b;
-          bs = s;
-          bx = x;
-        }
-      }
+  for (const Cand& c : cands) {
+    E.fused = c.fused;
+    E.block = c.block;
+    E.tile_block = c.tile_block;
+    E.spg = c.spg;
+    E.xcd = c.xcd;
+    launch_fill<T>(d0, E.psi, 0.3, 0.1, 256, st);
+    if (E.psi2) launch_fill<T>(d0, E.psi2, 0.3, 0.1, 256, st);
+    launch_fill<T>(d0, E.ya, 0.3, 0.1, 256, st);
+    launch_fill<T>(d0, E.yb, 0.3, 0.1, 256, st);
+    launch_prep_s<T>(d0, E.psi, E.s, dz, 256, st);
+    run_middle<T>(E, graph_steps(E, use_fused<T>(E)), dz, gamma, st);  // warm-up (and graph instantiation)
+    HIP_OK(hipEventRecord(e0, st));
+    run_middle<T>(E, steps, dz, gamma, st);
+    HIP_OK(hipEventRecord(e1, st));
+    HIP_OK(hipEventSynchronize(e1));
+    float t = 0;
+    HIP_OK(hipEventElapsedTime(&t, e0, e1));
+    if (t < best) {
+      best = t;
+      bc = c;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   E.drop_graphs();
-  E.block = bb;
-  E.spg = bs;
-  E.xcd = bx;
+  E.fused = bc.fused;
+  E.block = bc.block;
+  E.tile_block = bc.tile_block;
+  E.spg = bc.spg;
+  E.xcd = bc.xcd;
   tune_cache_store(E);
 }
 
@@ -1043,10 +1374,18 @@ int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_step
       E.ckpt.every != L.S || E.ckpt.dn_version != E.dn_version)
     fail(DEC_BPM_EWORKSPACE, "workspace does not hold the checkpoints of a matching forward call");
   char* ws = static_cast<char*>(workspace);
-  if (E.dtype == DEC_BPM_C64)
-    decbpm::adjoint_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, as_stream(stream));
-  else
-    decbpm::adjoint_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, as_stream(stream));
+  hipStream_t st = as_stream(stream);
+  if (E.dtype == DEC_BPM_C64) {
+    if (decbpm::adjoint_fused_ok<float>(E))
+      decbpm::adjoint_fused_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
+    else
+      decbpm::adjoint_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
+  } else {
+    if (decbpm::adjoint_fused_ok<double>(E))
+      decbpm::adjoint_fused_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
+    else
+      decbpm::adjoint_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
+  }
   ABI_CATCH
 }
 
@@ -1134,16 +1473,24 @@ int dec_bpm_get_tuning(dec_bpm_t h, dec_bpm_tuning* t) {
   if (!t) fail(DEC_BPM_EINVAL, "NULL tuning");
   t->block_size = h->E.block;
   t->steps_per_graph = h->E.spg;
+  t->fused = h->E.has_tiles ? h->E.fused : 0;
+  t->tile_block = h->E.has_tiles ? h->E.tblock() : h->E.tile_block;
+  t->xcd_remap = h->E.xcd;
   ABI_CATCH
 }
 
 int dec_bpm_set_tuning(dec_bpm_t h, const dec_bpm_tuning* t) {
   ABI_TRY
   need(h);
-  if (!t || t->block_size < 64 || t->block_size > 1024 || t->block_size % 64 || t->steps_per_graph < 1)
+  if (!t || t->block_size < 64 || t->block_size > 1024 || t->block_size % 64 || t->steps_per_graph < 1 ||
+      t->tile_block < 64 || t->tile_block > 1024 || t->tile_block % 64 || (t->fused != 0 && t->fused != 1) ||
+      (t->xcd_remap != 0 && t->xcd_remap != 1))
     fail(DEC_BPM_EINVAL, "bad tuning");
   h->E.block = t->block_size;
   h->E.spg = t->steps_per_graph;
+  h->E.fused = t->fused;
+  h->E.tile_block = t->tile_block;
+  h->E.xcd = t->xcd_remap;
   ABI_CATCH
 }
 

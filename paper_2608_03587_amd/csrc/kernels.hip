@@ -494,6 +494,567 @@ __global__ void k_zero_f64(int64_t n, double* x) {
   x[r] = 0.0;
 }
 
+// ---- batched kernels: VF adjacent fields of one row per thread ----
+// With many fields per row (field-minor layout) a thread owns VF consecutive
+// fields, so every gather of a neighbour is one 32-byte vector load and the
+// row's operator entries are fetched once per VF fields.
+template <typename T, int VF>
+struct alignas(sizeof(typename CT<T>::C) * VF) CVec {
+  typename CT<T>::C v[VF];
+};
+template <typename T, int VF>
+struct alignas(sizeof(T) * VF) RVec {
+  T v[VF];
+};
+
+template <typename T, int VF>
+__device__ inline void split_w(int64_t idx, const DevOps<T>& d, int64_t& row, int64_t& e0) {
+  const int64_t per = d.F / VF;  // threads per row
+  row = idx / per;
+  e0 = row * d.F + (idx - row * per) * VF;  // first element of this thread
+}
+
+template <typename T, int VF, int KMAX, bool B4, bool WS>
+__global__ void __launch_bounds__(1024) k_stage_w(DevOps<T> d, const typename CT<T>::C* __restrict__ x,
+                                                  const typename CT<T>::C* __restrict__ t,
+                                                  const typename CT<T>::C* psi, typename CT<T>::C* y, T coef,
+                                                  T* __restrict__ s_out, T tau_s) {
+  using V = CVec<T, VF>;
+  const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  int64_t row, e0;
+  split_w<T, VF>(idx, d, row, e0);
+  if (row >= d.n_rows) return;
+  const int64_t fo = e0 - row * d.F;  // field offset inside the row
+  const auto* __restrict__ g = reinterpret_cast<const V*>(B4 ? t : x);
+  const V gr = g[e0 / VF];
+  const V xr = B4 ? reinterpret_cast<const V*>(x)[e0 / VF] : gr;
+  const V p = reinterpret_cast<const V*>(psi)[e0 / VF];
+  const T vr = d.v[row];
+  T ar[VF], ai[VF];
+#pragma unroll
+  for (int f = 0; f < VF; ++f) ar[f] = ai[f] = T(0);
+  for_neighbours<KMAX>(d, d.lw, row, [&](int32_t q, T c) {
+    const V gq = g[(int64_t(q) * d.F + fo) / VF];
+#pragma unroll
+    for (int f = 0; f < VF; ++f) {
+      ar[f] += c * (gr.v[f].x - gq.v[f].x);
+      ai[f] += c * (gr.v[f].y - gq.v[f].y);
+    }
+  });
+  V out;
+  RVec<T, VF> so;
+  const T ph = WS ? phi_w(d.w[row], tau_s) : T(0);
+#pragma unroll
+  for (int f = 0; f < VF; ++f) {
+    T hr, hi;
+    if (B4) {
+      hr = d.p1 * gr.v[f].x + d.beta4 * ar[f] - vr * xr.v[f].x;
+      hi = d.p1 * gr.v[f].y + d.beta4 * ai[f] - vr * xr.v[f].y;
+    } else {
+      hr = d.p1 * ar[f] - vr * xr.v[f].x;
+      hi = d.p1 * ai[f] - vr * xr.v[f].y;
+    }
+    out.v[f].x = p.v[f].x + coef * hi;
+    out.v[f].y = p.v[f].y - coef * hr;
+    so.v[f] = (out.v[f].x * out.v[f].x + out.v[f].y * out.v[f].y) * ph;
+  }
+  reinterpret_cast<V*>(y)[e0 / VF] = out;
+  if (WS) reinterpret_cast<RVec<T, VF>*>(s_out)[e0 / VF] = so;
+}
+
+template <typename T, int VF, int KMAX>
+__global__ void __launch_bounds__(1024) k_lap_w(DevOps<T> d, const typename CT<T>::C* __restrict__ x,
+                                                typename CT<T>::C* __restrict__ t) {
+  using V = CVec<T, VF>;
+  const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  int64_t row, e0;
+  split_w<T, VF>(idx, d, row, e0);
+  if (row >= d.n_rows) return;
+  const int64_t fo = e0 - row * d.F;
+  const auto* __restrict__ g = reinterpret_cast<const V*>(x);
+  const V xr = g[e0 / VF];
+  V out;
+#pragma unroll
+  for (int f = 0; f < VF; ++f) out.v[f].x = out.v[f].y = T(0);
+  for_neighbours<KMAX>(d, d.lw, row, [&](int32_t q, T c) {
+    const V xq = g[(int64_t(q) * d.F + fo) / VF];
+#pragma unroll
+    for (int f = 0; f < VF; ++f) {
+      out.v[f].x += c * (xr.v[f].x - xq.v[f].x);
+      out.v[f].y += c * (xr.v[f].y - xq.v[f].y);
+    }
+  });
+  reinterpret_cast<V*>(t)[e0 / VF] = out;
+}
+
+template <typename T, int VF>
+__global__ void __launch_bounds__(1024) k_prep_w(DevOps<T> d, const typename CT<T>::C* __restrict__ psi,
+                                                 T* __restrict__ s, T tau) {
+  using V = CVec<T, VF>;
+  const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  int64_t row, e0;
+  split_w<T, VF>(idx, d, row, e0);
+  if (row >= d.n_rows) return;
+  const V p = reinterpret_cast<const V*>(psi)[e0 / VF];
+  const T ph = phi_w(d.w[row], tau);
+  RVec<T, VF> o;
+#pragma unroll
+  for (int f = 0; f < VF; ++f) o.v[f] = (p.v[f].x * p.v[f].x + p.v[f].y * p.v[f].y) * ph;
+  reinterpret_cast<RVec<T, VF>*>(s)[e0 / VF] = o;
+}
+
+template <typename T, int VF, int KMAX, bool DEC>
+__global__ void __launch_bounds__(1024) k_kerr_w(DevOps<T> d, const typename CT<T>::C* psi_in,
+                                                 typename CT<T>::C* psi_out, const T* __restrict__ s, T tau,
+                                                 T gamma) {
+  using V = CVec<T, VF>;
+  using R = RVec<T, VF>;
+  const int64_t idx = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  int64_t row, e0;
+  split_w<T, VF>(idx, d, row, e0);
+  if (row >= d.n_rows) return;
+  const int64_t fo = e0 - row * d.F;
+  const auto* __restrict__ sv = reinterpret_cast<const R*>(s);
+  const V p = reinterpret_cast<const V*>(psi_in)[e0 / VF];
+  const R own = sv[e0 / VF];
+  const T md = d.mdiag[row];
+  T th[VF];
+#pragma unroll
+  for (int f = 0; f < VF; ++f) th[f] = md * own.v[f];
+  if (DEC)
+    for_neighbours<KMAX>(d, d.mw, row, [&](int32_t q, T m) {
+      const R sq = sv[(int64_t(q) * d.F + fo) / VF];
+#pragma unroll
+      for (int f = 0; f < VF; ++f) th[f] += m * sq.v[f];
+    });
+  const T damp = d_exp(-d.w[row] * tau);
+  V out;
+#pragma unroll
+  for (int f = 0; f < VF; ++f) {
+    T sn, cs;
+    d_sincos(gamma * th[f], &sn, &cs);
+    out.v[f].x = damp * (p.v[f].x * cs - p.v[f].y * sn);
+    out.v[f].y = damp * (p.v[f].x * sn + p.v[f].y * cs);
+  }
+  reinterpret_cast<V*>(psi_out)[e0 / VF] = out;
+}
+
+// ---- fused z-step kernels on LDS tiles ----
+// One workgroup per tile.  The tile's rows and halo rings are staged in LDS;
+// each stage of the kind is computed on the rings it needs, separated by
+// workgroup barriers only.  Thread j of the workgroup owns slots j, j + B, ...
+// (at most J of them) in every phase, and loads their operator rows (indices,
+// L and M weights) and per-row scalars into registers once, while the field
+// values are being staged, so the phases after the first barrier touch only
+// LDS and registers.
+template <typename T, int KMAX, bool DEC, int KIND, int J>
+__global__ void __launch_bounds__(1024) k_fused(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ in_x,
+                                                const typename CT<T>::C* __restrict__ in_psi,
+                                                typename CT<T>::C* __restrict__ out_psi,
+                                                typename CT<T>::C* __restrict__ out_y,
+                                                typename CT<T>::C* __restrict__ out_rec, T h, T tau, T gamma) {
+  using C = typename CT<T>::C;
+  static_assert(KMAX > 0, "fused kernels need a bounded row width");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;  // whole workgroup leaves together
+  const int32_t* hd = tl.hdr + 8 * tile;
+  const int c0 = hd[0], c1 = c0 + hd[1], c2 = c1 + hd[2], c3 = c2 + hd[3];
+  const int32_t* __restrict__ ext = tl.ext + hd[4];
+  const int32_t* __restrict__ lsl = tl.lsl + hd[5];
+  const int64_t ebase = tl.ent_base[tile];
+  const int64_t row0 = tile * int64_t(tl.TS);
+  const int MS = tl.max_slots;
+  const int B = blockDim.x;
+  C* X = reinterpret_cast<C*>(smem);
+  C* P = X + MS;
+  C* Y = P + MS;
+  T* S = reinterpret_cast<T*>(Y + MS);
+  // ring extents (a triangle-averaged Kerr step gathers one ring, a lumped one none)
+  int nX = 0, nP = 0, nA = 0;
+  if (KIND == FUSED_S4_NL_S1) {
+    nA = DEC ? c2 : c1;  // rows of stage 4
+    nX = DEC ? c3 : c2;
+    nP = nA;
+  } else if (KIND == FUSED_S2_S3) {
+    nA = c1;
+    nX = c2;
+    nP = c1;
+  } else if (KIND == FUSED_NL_S1) {
+    nA = c1;
+    nP = DEC ? c2 : c1;
+  } else {  // FUSED_S4_NL
+    nA = DEC ? c1 : c0;
+    nX = DEC ? c2 : c1;
+    nP = nA;
+  }
+  const int nLoad = nX > nP ? nX : nP;
+  // stage the field values of every slot
+  for (int i = threadIdx.x; i < nLoad; i += B) {
+    const int32_t r = i < c0 ? int32_t(row0 + i) : ext[i - c0];
+    if (i < nX) X[i] = in_x[r];
+    if (i < nP) {
+      const C p = in_psi[r];
+      P[i] = p;
+      if (KIND == FUSED_NL_S1) S[i] = (p.x * p.x + p.y * p.y) * phi_w(d.w[r], tau);
+    }
+  }
+  // registers: the operator rows of this thread's compute slots (all phases use prefixes of [0, nA))
+  int q[J][KMAX];
+  T cl[J][KMAX];
+  T cm[J][DEC ? KMAX : 1];
+  int wd[J];
+  int32_t rr[J];
+  T vv[J], ww[J], md[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    wd[j] = 0;
+    rr[j] = 0;
+    vv[j] = ww[j] = md[j] = T(0);
+    if (i < nA) {
+      const int32_t r = i < c0 ? int32_t(row0 + i) : ext[i - c0];
+      rr[j] = r;
+      vv[j] = d.v[r];
+      ww[j] = d.w[r];
+      md[j] = d.mdiag[r];
+      const int32_t info = lsl[i >> 6];
+      wd[j] = info & 0xff;
+      const int64_t base = ebase + (info >> 8) + (i & 63);
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < wd[j]) {
+          q[j][k] = tl.lcol[base + 64 * k];
+          cl[j][k] = tl.llw[base + 64 * k];
+          if (DEC) cm[j][k] = tl.lmw[base + 64 * k];
+        } else {
+          q[j][k] = i;
+          cl[j][k] = T(0);
+          if (DEC) cm[j][k] = T(0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        q[j][k] = 0;
+        cl[j][k] = T(0);
+        if (DEC) cm[j][k] = T(0);
+      }
+    }
+  }
+  __syncthreads();
+
+  // base + coef * (-i) (p1 L v - V v) for register slot j (slot index i), v gathered from V_
+  auto stage = [&](const C* V_, const C* base_, int j, int i, T coef) {
+    const C vr = V_[i];
+    T ar = T(0), ai = T(0);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < wd[j]) {
+        const C vq = V_[q[j][k]];
+        ar += cl[j][k] * (vr.x - vq.x);
+        ai += cl[j][k] * (vr.y - vq.y);
+      }
+    const T hr = d.p1 * ar - vv[j] * vr.x;
+    const T hi = d.p1 * ai - vv[j] * vr.y;
+    const C b = base_[i];
+    C o;
+    o.x = b.x + coef * hi;
+    o.y = b.y - coef * hr;
+    return o;
+  };
+  // exact Kerr/absorber flow of register slot j of Src, reading |psi|^2 phi from S
+  auto kerr = [&](const C* Src, int j, int i) {
+    T th = md[j] * S[i];
+    if (DEC) {
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < wd[j]) th += cm[j][k] * S[q[j][k]];
+    }
+    const T damp = d_exp(-ww[j] * tau);
+    T sn, cs;
+    d_sincos(gamma * th, &sn, &cs);
+    const C p = Src[i];
+    C o;
+    o.x = damp * (p.x * cs - p.y * sn);
+    o.y = damp * (p.x * sn + p.y * cs);
+    return o;
+  };
+
+  if (KIND == FUSED_S4_NL_S1 || KIND == FUSED_S4_NL) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {  // stage 4: psi_new = psi + h A y3
+      const int i = threadIdx.x + j * B;
+      if (i < nA) {
+        const C o = stage(X, P, j, i, h);
+        Y[i] = o;
+        S[i] = (o.x * o.x + o.y * o.y) * phi_w(ww[j], tau);
+        if (out_rec && i < c0) out_rec[rr[j]] = o;  // state before the Kerr substep (adjoint recompute)
+      }
+    }
+    __syncthreads();
+    const int nNL = KIND == FUSED_S4_NL ? c0 : c1;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < nNL) {
+        const C o = kerr(Y, j, i);
+        if (KIND == FUSED_S4_NL_S1) X[i] = o;
+        if (i < c0) out_psi[rr[j]] = o;
+      }
+    }
+    if (KIND == FUSED_S4_NL_S1) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int i = threadIdx.x + j * B;
+        if (i < c0) out_y[rr[j]] = stage(X, X, j, i, T(0.25) * h);
+      }
+    }
+  } else if (KIND == FUSED_NL_S1) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < c1) {
+        const C o = kerr(P, j, i);
+        X[i] = o;
+        if (i < c0) out_psi[rr[j]] = o;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < c0) out_y[rr[j]] = stage(X, X, j, i, T(0.25) * h);
+    }
+  } else {  // FUSED_S2_S3
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < c1) {
+        const C o = stage(X, P, j, i, h / T(3));
+        Y[i] = o;
+        if (out_rec && i < c0) out_rec[rr[j]] = o;  // y2 (adjoint recompute)
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < c0) out_y[rr[j]] = stage(Y, P, j, i, T(0.5) * h);
+    }
+  }
+}
+
+// ---- fused adjoint kernels on LDS tiles (lambda = H0^{-1} g variables) ----
+// AD1: Kerr/absorber adjoint (rings 0..2), chain links 1 and 2 of the reverse
+//      RK4 (rings 0..1, ring 0):  lam_b = conj(E) lam + 2 phi b (M mu),
+//      u1 = -h A lam_b,  u2 = -(h/2) A u1;  writes u2, acc = lam_b + u1 + u2 and
+//      adds the link-1..3 terms of dJ/d(dn) (forward vectors y3, y2, y1).
+// AD2: links 3 and 4: u3 = -(h/3) A u2 (rings 0..1), u4 = -(h/4) A u3;
+//      lam_new = acc + u3 + u4; adds the link-4 term (forward state a).
+template <typename T, int KMAX, bool DEC, int KIND, int J>
+__global__ void __launch_bounds__(1024) k_fused_adj(DevOps<T> d, TileOps<T> tl,
+                                                    const typename CT<T>::C* __restrict__ vin,
+                                                    const typename CT<T>::C* __restrict__ fa,
+                                                    const typename CT<T>::C* __restrict__ fb,
+                                                    const typename CT<T>::C* __restrict__ y3,
+                                                    const typename CT<T>::C* __restrict__ y2,
+                                                    const typename CT<T>::C* __restrict__ y1,
+                                                    typename CT<T>::C* __restrict__ out_u,
+                                                    typename CT<T>::C* __restrict__ acc,
+                                                    double* __restrict__ gdn, T h, T tau, T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int32_t* hd = tl.hdr + 8 * tile;
+  const int c0 = hd[0], c1 = c0 + hd[1], c2 = c1 + hd[2], c3 = c2 + hd[3];
+  const int32_t* __restrict__ ext = tl.ext + hd[4];
+  const int32_t* __restrict__ lsl = tl.lsl + hd[5];
+  const int64_t ebase = tl.ent_base[tile];
+  const int64_t row0 = tile * int64_t(tl.TS);
+  const int MS = tl.max_slots;
+  const int B = blockDim.x;
+  C* Lm = reinterpret_cast<C*>(smem);  // AD1: lam -> lam_b; AD2: u2
+  C* U = Lm + MS;                      // AD1: u1; AD2: u3
+  C* Bs = U + MS;                      // AD1: b (state before the Kerr substep)
+  C* SM = Bs + MS;                     // AD1: (s, mu) per slot
+  const int nNL = c2;                  // AD1: Kerr adjoint rows
+  const int nLoad = KIND == 1 ? (DEC ? c3 : c2) : c2;
+  for (int i = threadIdx.x; i < nLoad; i += B) {
+    const int32_t r = i < c0 ? int32_t(row0 + i) : ext[i - c0];
+    const C l = vin[r];
+    if (KIND == 1) {
+      const C bb = fb[r];
+      const C aa = fa[r];
+      C sm;
+      sm.x = (bb.x * bb.x + bb.y * bb.y) * phi_w(d.w[r], tau);
+      sm.y = -gamma * (l.x * aa.y - l.y * aa.x);  // gamma Re(i conj(lam) a)
+      SM[i] = sm;
+      if (i < nNL) {
+        Bs[i] = bb;
+        Lm[i] = l;
+      }
+    } else {
+      Lm[i] = l;
+    }
+  }
+  int q[J][KMAX];
+  T cl[J][KMAX];
+  T cm[J][DEC ? KMAX : 1];
+  int wd[J];
+  int32_t rr[J];
+  T vv[J], ww[J], md[J];
+  C fy3[J], fy2[J], fy1[J], fac[J];
+  double h0[J], gd[J];
+  const int nRows = c2;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    wd[j] = 0;
+    rr[j] = 0;
+    vv[j] = ww[j] = md[j] = T(0);
+    h0[j] = gd[j] = 0.0;
+    if (i < nRows) {
+      const int32_t r = i < c0 ? int32_t(row0 + i) : ext[i - c0];
+      rr[j] = r;
+      vv[j] = d.v[r];
+      ww[j] = d.w[r];
+      md[j] = d.mdiag[r];
+      const int32_t info = lsl[i >> 6];
+      wd[j] = info & 0xff;
+      const int64_t base = ebase + (info >> 8) + (i & 63);
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < wd[j]) {
+          q[j][k] = tl.lcol[base + 64 * k];
+          cl[j][k] = tl.llw[base + 64 * k];
+          if (DEC) cm[j][k] = tl.lmw[base + 64 * k];
+        } else {
+          q[j][k] = i;
+          cl[j][k] = T(0);
+          if (DEC) cm[j][k] = T(0);
+        }
+      }
+      if (i < c0) {  // owned rows: forward vectors, accumulators
+        h0[j] = d.h0[r];
+        gd[j] = gdn[r];
+        if (KIND == 1) {
+          fy3[j] = y3[r];
+          fy2[j] = y2[r];
+          fy1[j] = y1[r];
+        } else {
+          fac[j] = acc[r];
+          fy1[j] = fa[r];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        q[j][k] = 0;
+        cl[j][k] = T(0);
+        if (DEC) cm[j][k] = T(0);
+      }
+    }
+  }
+  __syncthreads();
+
+  // coef * (-i) (p1 L v - V v) at register slot j, v gathered from V_
+  auto link = [&](const C* V_, int j, int i, T coef) {
+    const C vr = V_[i];
+    T ar = T(0), ai = T(0);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < wd[j]) {
+        const C vq = V_[q[j][k]];
+        ar += cl[j][k] * (vr.x - vq.x);
+        ai += cl[j][k] * (vr.y - vq.y);
+      }
+    const T hr = d.p1 * ar - vv[j] * vr.x;
+    const T hi = d.p1 * ai - vv[j] * vr.y;
+    C o;
+    o.x = coef * hi;
+    o.y = -coef * hr;
+    return o;
+  };
+  // Re(i conj(u) y) = -(u.x y.y - u.y y.x)
+  auto rdn = [](const C& u, const C& y) { return -(double(u.x) * y.y - double(u.y) * y.x); };
+
+  if (KIND == 1) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {  // Kerr/absorber adjoint
+      const int i = threadIdx.x + j * B;
+      if (i < nNL) {
+        const C own = SM[i];
+        T th = md[j] * own.x, mm = md[j] * own.y;
+        if (DEC) {
+#pragma unroll
+          for (int k = 0; k < KMAX; ++k)
+            if (k < wd[j]) {
+              const C v = SM[q[j][k]];
+              th += cm[j][k] * v.x;
+              mm += cm[j][k] * v.y;
+            }
+        }
+        const T damp = d_exp(-ww[j] * tau);
+        T sn, cs;
+        d_sincos(gamma * th, &sn, &cs);
+        const C l = Lm[i];
+        const C p = Bs[i];
+        const T two_phi_mm = T(2) * phi_w(ww[j], tau) * mm;
+        C o;
+        o.x = damp * (cs * l.x + sn * l.y) + two_phi_mm * p.x;
+        o.y = damp * (cs * l.y - sn * l.x) + two_phi_mm * p.y;
+        Lm[i] = o;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {  // link 1
+      const int i = threadIdx.x + j * B;
+      if (i < c1) U[i] = link(Lm, j, i, -h);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {  // link 2, accumulators
+      const int i = threadIdx.x + j * B;
+      if (i < c0) {
+        const C lb = Lm[i];
+        const C u1 = U[i];
+        const C u2 = link(U, j, i, T(-0.5) * h);
+        out_u[rr[j]] = u2;
+        C a;
+        a.x = lb.x + u1.x + u2.x;
+        a.y = lb.y + u1.y + u2.y;
+        acc[rr[j]] = a;
+        gdn[rr[j]] = gd[j] + h0[j] * (double(h) * rdn(lb, fy3[j]) + 0.5 * double(h) * rdn(u1, fy2[j]) +
+                                      double(h) / 3.0 * rdn(u2, fy1[j]));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {  // link 3
+      const int i = threadIdx.x + j * B;
+      if (i < c1) U[i] = link(Lm, j, i, -h / T(3));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {  // link 4, new adjoint state
+      const int i = threadIdx.x + j * B;
+      if (i < c0) {
+        const C u3 = U[i];
+        const C u4 = link(U, j, i, T(-0.25) * h);
+        C l;
+        l.x = fac[j].x + u3.x + u4.x;
+        l.y = fac[j].y + u3.y + u4.y;
+        out_u[rr[j]] = l;
+        gdn[rr[j]] = gd[j] + h0[j] * 0.25 * double(h) * rdn(u3, fy1[j]);
+      }
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -533,9 +1094,39 @@ inline int kmax_of(int wmax) { return wmax <= 8 ? 8 : (wmax <= 12 ? 12 : 0); }
     default: { constexpr int FB = 0; BODY; } break;               \
   }
 
+// Fields per thread of the batched kernels: 32 bytes of complex values.
+template <typename T>
+inline int vf_of(const DevOps<T>& d) {
+  constexpr int VF = int(32 / sizeof(typename CT<T>::C));
+  return (d.F > 1 && d.F % VF == 0) ? VF : 1;
+}
+
+#define DECBPM_DISPATCH_W(d, BODY)                                   \
+  switch (kmax_of((d).wmax)) {                                       \
+    case 8: { constexpr int KM = 8; constexpr int VF = int(32 / sizeof(typename CT<T>::C)); BODY; } break;   \
+    case 12: { constexpr int KM = 12; constexpr int VF = int(32 / sizeof(typename CT<T>::C)); BODY; } break; \
+    default: { constexpr int KM = 0; constexpr int VF = int(32 / sizeof(typename CT<T>::C)); BODY; } break;  \
+  }
+
 template <typename T>
 void launch_stage(const DevOps<T>& d, const void* x, const void* t, const void* psi, void* y, double coef,
                   void* s_out, double tau_s, int block, hipStream_t st) {
+  if (vf_of(d) > 1) {
+    const unsigned gw = grid_for(d.n_rows * d.F / vf_of(d), block, d.xcd_remap);
+    T* sw = reinterpret_cast<T*>(s_out);
+    const int mode = (t != nullptr) * 2 + (s_out != nullptr);
+#define DECBPM_STAGE_W(B4, WS)                                                                                \
+  hipLaunchKernelGGL((k_stage_w<T, VF, KM, B4, WS>), dim3(gw), dim3(block), 0, st, d, DECBPM_C(T, x),          \
+                     DECBPM_C(T, t), DECBPM_C(T, psi), DECBPM_M(T, y), T(coef), sw, T(tau_s))
+    DECBPM_DISPATCH_W(d, {
+      if (mode == 0) DECBPM_STAGE_W(false, false);
+      else if (mode == 1) DECBPM_STAGE_W(false, true);
+      else if (mode == 2) DECBPM_STAGE_W(true, false);
+      else DECBPM_STAGE_W(true, true);
+    })
+#undef DECBPM_STAGE_W
+    return;
+  }
   const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
   T* s = reinterpret_cast<T*>(s_out);
 #define DECBPM_STAGE(B4, WS)                                                                                 \
@@ -553,6 +1144,12 @@ void launch_stage(const DevOps<T>& d, const void* x, const void* t, const void* 
 
 template <typename T>
 void launch_lap(const DevOps<T>& d, const void* x, void* t, int block, hipStream_t st) {
+  if (vf_of(d) > 1) {
+    const unsigned gw = grid_for(d.n_rows * d.F / vf_of(d), block, d.xcd_remap);
+    DECBPM_DISPATCH_W(d, hipLaunchKernelGGL((k_lap_w<T, VF, KM>), dim3(gw), dim3(block), 0, st, d, DECBPM_C(T, x),
+                                            DECBPM_M(T, t)))
+    return;
+  }
   const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
   DECBPM_DISPATCH_FB_K(d, hipLaunchKernelGGL((k_lap<T, FB, KM>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, x),
                                              DECBPM_M(T, t)))
@@ -560,6 +1157,13 @@ void launch_lap(const DevOps<T>& d, const void* x, void* t, int block, hipStream
 
 template <typename T>
 void launch_prep_s(const DevOps<T>& d, const void* psi, void* s, double tau, int block, hipStream_t st) {
+  if (vf_of(d) > 1) {
+    constexpr int VF = int(32 / sizeof(typename CT<T>::C));
+    const unsigned gw = grid_for(d.n_rows * d.F / VF, block, d.xcd_remap);
+    hipLaunchKernelGGL((k_prep_w<T, VF>), dim3(gw), dim3(block), 0, st, d, DECBPM_C(T, psi), reinterpret_cast<T*>(s),
+                       T(tau));
+    return;
+  }
   const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
   DECBPM_DISPATCH_FB(d, hipLaunchKernelGGL((k_prep_s<T, FB>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, psi),
                                            reinterpret_cast<T*>(s), T(tau)))
@@ -568,8 +1172,20 @@ void launch_prep_s(const DevOps<T>& d, const void* psi, void* s, double tau, int
 template <typename T>
 void launch_kerr(const DevOps<T>& d, const void* psi_in, void* psi_out, const void* s, double tau, double gamma,
                  int block, hipStream_t st) {
-  const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
   const T* sp = reinterpret_cast<const T*>(s);
+  if (vf_of(d) > 1) {
+    const unsigned gw = grid_for(d.n_rows * d.F / vf_of(d), block, d.xcd_remap);
+    if (d.mw) {
+      DECBPM_DISPATCH_W(d, hipLaunchKernelGGL((k_kerr_w<T, VF, KM, true>), dim3(gw), dim3(block), 0, st, d,
+                                              DECBPM_C(T, psi_in), DECBPM_M(T, psi_out), sp, T(tau), T(gamma)))
+    } else {
+      constexpr int VF = int(32 / sizeof(typename CT<T>::C));
+      hipLaunchKernelGGL((k_kerr_w<T, VF, 0, false>), dim3(gw), dim3(block), 0, st, d, DECBPM_C(T, psi_in),
+                         DECBPM_M(T, psi_out), sp, T(tau), T(gamma));
+    }
+    return;
+  }
+  const unsigned g = grid_for(d.n_rows * d.F, block, d.xcd_remap);
   if (d.mw) {
     DECBPM_DISPATCH_FB_K(d, hipLaunchKernelGGL((k_kerr<T, FB, KM, true>), dim3(g), dim3(block), 0, st, d,
                                                DECBPM_C(T, psi_in), DECBPM_M(T, psi_out), sp, T(tau), T(gamma)))
@@ -577,6 +1193,64 @@ void launch_kerr(const DevOps<T>& d, const void* psi_in, void* psi_out, const vo
     DECBPM_DISPATCH_FB(d, hipLaunchKernelGGL((k_kerr<T, FB, 0, false>), dim3(g), dim3(block), 0, st, d,
                                              DECBPM_C(T, psi_in), DECBPM_M(T, psi_out), sp, T(tau), T(gamma)))
   }
+}
+
+template <typename T>
+void launch_fused(const DevOps<T>& d, const TileOps<T>& tl, int kind, const void* in_x, const void* in_psi,
+                  void* out_psi, void* out_y, void* out_rec, double h, double tau, double gamma, int block,
+                  hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
+  const int J = (tl.max_compute + block - 1) / block;  // slots per thread (1 or 2)
+#define DECBPM_FUSED(KM, DEC, KIND, JJ)                                                                          \
+  hipLaunchKernelGGL((k_fused<T, KM, DEC, KIND, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_x), \
+                     DECBPM_C(T, in_psi), DECBPM_M(T, out_psi), DECBPM_M(T, out_y), DECBPM_M(T, out_rec), T(h),  \
+                     T(tau), T(gamma))
+#define DECBPM_FUSED_J(KM, DEC, KIND) \
+  if (J <= 1) DECBPM_FUSED(KM, DEC, KIND, 1); else DECBPM_FUSED(KM, DEC, KIND, 2);
+#define DECBPM_FUSED_K(KM, DEC)                                  \
+  switch (kind) {                                                \
+    case FUSED_S4_NL_S1: DECBPM_FUSED_J(KM, DEC, 0); break;      \
+    case FUSED_S2_S3: DECBPM_FUSED_J(KM, DEC, 1); break;         \
+    case FUSED_NL_S1: DECBPM_FUSED_J(KM, DEC, 2); break;         \
+    default: DECBPM_FUSED_J(KM, DEC, 3); break;                  \
+  }
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_FUSED_K(8, true) } else { DECBPM_FUSED_K(8, false) }
+  } else {
+    if (dec) { DECBPM_FUSED_K(12, true) } else { DECBPM_FUSED_K(12, false) }
+  }
+#undef DECBPM_FUSED_K
+#undef DECBPM_FUSED_J
+#undef DECBPM_FUSED
+}
+
+template <typename T>
+void launch_fused_adj(const DevOps<T>& d, const TileOps<T>& tl, int kind, const void* vin, const void* fa,
+                      const void* fb, const void* y3, const void* y2, const void* y1, void* out_u, void* acc,
+                      double* gdn, double h, double tau, double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * 4 * sizeof(typename CT<T>::C);
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_FADJ(KM, DEC, KIND, JJ)                                                                            \
+  hipLaunchKernelGGL((k_fused_adj<T, KM, DEC, KIND, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, vin), \
+                     DECBPM_C(T, fa), DECBPM_C(T, fb), DECBPM_C(T, y3), DECBPM_C(T, y2), DECBPM_C(T, y1),          \
+                     DECBPM_M(T, out_u), DECBPM_M(T, acc), gdn, T(h), T(tau), T(gamma))
+#define DECBPM_FADJ_J(KM, DEC, KIND) \
+  if (J <= 1) DECBPM_FADJ(KM, DEC, KIND, 1); else DECBPM_FADJ(KM, DEC, KIND, 2);
+#define DECBPM_FADJ_K(KM, DEC)                    \
+  if (kind == 1) { DECBPM_FADJ_J(KM, DEC, 1) }    \
+  else { DECBPM_FADJ_J(KM, DEC, 2) }
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_FADJ_K(8, true) } else { DECBPM_FADJ_K(8, false) }
+  } else {
+    if (dec) { DECBPM_FADJ_K(12, true) } else { DECBPM_FADJ_K(12, false) }
+  }
+#undef DECBPM_FADJ_K
+#undef DECBPM_FADJ_J
+#undef DECBPM_FADJ
 }
 
 template <typename T>
@@ -706,7 +1380,12 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                    int, hipStream_t);                                                            \
   template void launch_hcombine<T>(const DevOps<T>&, const void*, const void*, const void*, void*, int,           \
                                    hipStream_t);                                                                 \
-  template void launch_set_v<T>(int64_t, const T*, const double*, const int32_t*, T*, int, hipStream_t);
+  template void launch_set_v<T>(int64_t, const T*, const double*, const int32_t*, T*, int, hipStream_t);          \
+  template void launch_fused<T>(const DevOps<T>&, const TileOps<T>&, int, const void*, const void*, void*, void*,  \
+                                void*, double, double, double, int, hipStream_t);                                \
+  template void launch_fused_adj<T>(const DevOps<T>&, const TileOps<T>&, int, const void*, const void*,          \
+                                    const void*, const void*, const void*, const void*, void*, void*, double*,   \
+                                    double, double, double, int, hipStream_t);
 
 DECBPM_INSTANTIATE(float)
 DECBPM_INSTANTIATE(double)

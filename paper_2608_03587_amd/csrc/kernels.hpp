@@ -38,6 +38,31 @@ struct DevOps {
   int32_t xcd_remap;   // 1: map consecutive row blocks onto one XCD
 };
 
+// Tiles for the fused kernels (one field per row, no beta4 term).  Tile t
+// owns the contiguous device rows [t*TS, t*TS + nT) and carries its halo
+// rings H1, H2, H3 (rows adjacent to the previous rings).  Inside a tile every
+// row is a "slot": slots [0, nT) are the owned rows in order, then H1, H2, H3
+// (global rows listed in ext).  The operator rows of slots in T, H1 and H2 are
+// stored again with 16-bit slot-local columns, sliced by 64 slots like the
+// global operator (lsl holds (offset << 8) | width per slice, offsets
+// relative to ent_base[t]).
+template <typename T>
+struct TileOps {
+  int32_t n_tiles;
+  int32_t TS;
+  int32_t max_slots;        // largest slot count of a tile (rings 0..3), LDS sizing
+  int32_t max_compute;      // largest count of slots with operator rows (rings 0..2)
+  const int32_t* hdr;       // [n_tiles * 8]: nT, nH1, nH2, nH3, ext_base, lsl_base, 0, 0
+  const int64_t* ent_base;  // [n_tiles]
+  const int32_t* ext;       // halo rows (device order)
+  const int32_t* lsl;
+  const uint16_t* lcol;
+  const T* llw;
+  const T* lmw;             // nullptr for the lumped nonlinearity
+};
+
+enum FusedKind { FUSED_S4_NL_S1 = 0, FUSED_S2_S3 = 1, FUSED_NL_S1 = 2, FUSED_S4_NL = 3 };
+
 template <typename T>
 struct Cplx;
 template <>
@@ -116,6 +141,30 @@ void launch_adj_prep(const DevOps<T>& d, const void* psi_in, const void* psi_out
 template <typename T>
 void launch_adj_kerr(const DevOps<T>& d, const void* psi_in, const void* lam_out, const void* sm, void* lam_in,
                      double tau, double gamma, int block, hipStream_t st);
+// Fused z-step kernels on tiles (see TileOps):
+//   FUSED_S4_NL_S1: psi_new = psi + h A y3 (rings <= 2), psi'' = NL_tau(psi_new) (rings <= 1),
+//                   y1 = psi'' + h/4 A psi'' (owned rows); writes psi'' -> out_psi, y1 -> out_y
+//   FUSED_S2_S3:    y2 = psi + h/3 A y1 (rings <= 1), y3 = psi + h/2 A y2; writes y3 -> out_y
+//   FUSED_NL_S1:    first step: psi'' = NL_tau(psi), y1 = psi'' + h/4 A psi''
+//   FUSED_S4_NL:    last step: psi_new = psi + h A y3, psi'' = NL_tau(psi_new)
+// in_x is y3 (S4 kinds), y1 (S2_S3) or unused; in_psi is the state psi.
+// out_rec (may be null) receives, for owned rows, y2 (FUSED_S2_S3) or the
+// state before the Kerr substep (S4 kinds): the adjoint's segment recompute.
+template <typename T>
+void launch_fused(const DevOps<T>& d, const TileOps<T>& tl, int kind, const void* in_x, const void* in_psi,
+                  void* out_psi, void* out_y, void* out_rec, double h, double tau, double gamma, int block,
+                  hipStream_t st);
+// Fused adjoint of one z step on tiles (lambda = H0^{-1} g variables):
+//   kind 1: vin = lambda after the step, fa = a_n (state after the Kerr substep),
+//           fb = b_n (state before it), y3, y2, y1 = the step's stage vectors;
+//           writes out_u = u2, acc = lam_b + u1 + u2, gdn += link 1-3 terms.
+//   kind 2: vin = u2, fa = a_{n-1} (the step's input state), acc as written by kind 1;
+//           writes out_u = lambda before the step, gdn += link 4 term.
+template <typename T>
+void launch_fused_adj(const DevOps<T>& d, const TileOps<T>& tl, int kind, const void* vin, const void* fa,
+                      const void* fb, const void* y3, const void* y2, const void* y1, void* out_u, void* acc,
+                      double* gdn, double h, double tau, double gamma, int block, hipStream_t st);
+
 // out[perm[r]] = gdn[r]
 void launch_gdn_out(int64_t n, const int32_t* perm, const double* gdn, double* out, int block, hipStream_t st);
 void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st);

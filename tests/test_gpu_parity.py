@@ -263,11 +263,15 @@ def test_batched_equals_plain(dtype):
     packed = batch.pack([dev(x.u0, dtype) for x in ws])
     batch.propagate(packed, ws[0].dz, ws[0].n_steps, 1.0)
     outs = batch.unpack(packed)
+    tol = 1e-12 if dtype == "c128" else 1e-5  # same per-row formulas; only FMA contraction may differ
     for m, x, o in zip(meshes, ws, outs):
         for f in range(4):
-            single = dev(x.u0[f], dtype)
-            m.propagate(single, x.dz, x.n_steps, 1.0)
-            assert torch.equal(o[f].contiguous(), single), "batched and plain differ"
+            for fused in (0, 1):
+                m.tuning = {"fused": fused}
+                single = dev(x.u0[f], dtype)
+                m.propagate(single, x.dz, x.n_steps, 1.0)
+                err = rel(host(o[f].contiguous()), host(single))
+                assert err < tol, (fused, err)
     # and one field against the oracle
     ops = oracle_ops(ws[1])
     ref = S.propagate(ws[1].u0[2], ops, ws[1].dz, ws[1].n_steps, 1.0)
@@ -341,3 +345,68 @@ def test_autotune_keeps_results():
     assert rel(host(a), host(b)) < 1e-6  # block size / graphs do not change the arithmetic
     times = m.time_kernels(w.dz, 1.0, reps=20)
     assert all(v["ms"] > 0 for v in times.values())
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_fused_tile_path_matches_unfused_and_oracle(dtype, nl):
+    """The two-kernel LDS-tiled step (stages 2+3; stage 4 + Kerr + next stage 1)
+    against the five-kernel step and the oracle, for odd and even step counts."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    say("fused", dtype, nl, w.mesh.n_vert)
+    ops = oracle_ops(w, nl)
+    m = lib_mesh(w, dtype, nl)
+    assert m.tuning["fused"] == 1
+    u = dev(w.u0, dtype)
+    for n in (1, 2, 3, 37, 64):
+        outs = {}
+        for fused, spg in ((1, 1), (1, 16), (0, 16)):
+            m.tuning = {"fused": fused, "steps_per_graph": spg}
+            f = u.clone()
+            m.propagate(f, w.dz, n, w.gamma)
+            outs[(fused, spg)] = host(f)
+        assert np.array_equal(outs[(1, 1)], outs[(1, 16)]), n  # graph replay == eager
+        tol = 1e-13 if dtype == "c128" else 1e-5
+        assert rel(outs[(1, 16)], outs[(0, 16)]) < tol, (n, rel(outs[(1, 16)], outs[(0, 16)]))
+        ref = S.propagate(w.u0, ops, w.dz, n, w.gamma)
+        assert rel(outs[(1, 16)], ref) < GATE[dtype], n
+        if n == 37:
+            keep = outs[(1, 16)]
+    for tb in (128, 512, 1024):  # threads per tile do not change the arithmetic
+        m.tuning = {"fused": 1, "tile_block": tb, "steps_per_graph": 16}
+        f = u.clone()
+        m.propagate(f, w.dz, 37, w.gamma)
+        assert np.array_equal(host(f), keep), tb
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_fused_adjoint_matches_unfused_and_oracle(dtype, nl):
+    """The tile-fused checkpointed forward and adjoint against the five-kernel
+    path and the FP64 oracle gradients (field and index perturbation)."""
+    w = W.adjoint_mmf(n_vert=20000, n_steps=10)
+    n, every = 23, 5
+    say("fused adjoint", dtype, nl, w.mesh.n_vert, n)
+    dn = w.extra["dn"]
+    ops = oracle_ops(w, nl, dn=dn)
+    J, g_ref, gdn_ref = OA.gradients(w.u0, w.extra["target"], ops, w.dz, n, w.gamma)
+    m = lib_mesh(w, dtype, nl)
+    m.set_index_perturbation(torch.from_numpy(dn).to(DEV))
+    tgt = dev(w.extra["target"], dtype)
+    res = {}
+    for fused in (1, 0):
+        m.tuning = {"fused": fused}
+        u = dev(w.u0, dtype)
+        wsp = torch.empty(m.workspace_size(n, every), dtype=torch.uint8, device=DEV)
+        m.forward_checkpointed(u, w.dz, n, w.gamma, wsp, every)
+        c = m.overlap(tgt, u)
+        gout = (2 * c * torch.from_numpy(ops.H0).to(DEV) * tgt.to(torch.complex128)).to(u.dtype)
+        g0, gdn = m.adjoint(gout, w.dz, n, w.gamma, wsp, every)
+        res[fused] = (host(g0), gdn.cpu().numpy())
+    tol = 1e-9 if dtype == "c128" else 1e-4
+    for fused in (1, 0):
+        assert rel(res[fused][0], g_ref) < tol, (fused, rel(res[fused][0], g_ref))
+        assert rel(res[fused][1], gdn_ref) < tol, (fused, rel(res[fused][1], gdn_ref))
+    agree = 1e-12 if dtype == "c128" else 1e-5
+    assert rel(res[1][0], res[0][0]) < agree
+    assert rel(res[1][1], res[0][1]) < agree

@@ -157,7 +157,8 @@ def test_host_only_handle_runs_every_check_then_reports_no_device():
     t = B.Tuning()
     assert lib.dec_bpm_get_tuning(m.handle, ctypes.byref(t)) == B.OK
     assert t.block_size in (64, 128, 256, 512, 1024)
-    bad = B.Tuning(100, 1)
+    assert t.fused == 0  # host-only handles have no tiles
+    bad = B.Tuning(100, 1, 0, 256, 1)
     assert lib.dec_bpm_set_tuning(m.handle, ctypes.byref(bad)) == B.EINVAL
 
 
