@@ -241,6 +241,10 @@ int dec_bpm_autotune(dec_bpm_t h, double dz, double gamma, void* stream);
 int dec_bpm_batch_autotune(dec_bpm_batch_t b, double dz, double gamma, void* stream);
 int dec_bpm_get_tuning(dec_bpm_t h, dec_bpm_tuning* t);
 int dec_bpm_set_tuning(dec_bpm_t h, const dec_bpm_tuning* t);
+/* Batched engines: `fused` selects the LDS-tiled batched kernels (one halo
+ * ring, all fields of a tile staged in LDS) over the row-parallel ones. */
+int dec_bpm_batch_get_tuning(dec_bpm_batch_t b, dec_bpm_tuning* t);
+int dec_bpm_batch_set_tuning(dec_bpm_batch_t b, const dec_bpm_tuning* t);
 
 /*
  * Per-kernel timing with HIP events on `stream`: each kernel class is

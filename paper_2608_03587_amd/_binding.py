@@ -82,6 +82,8 @@ _SIGNATURES = [
     ("dec_bpm_batch_autotune", c_int, [c_vp, c_dbl, c_dbl, c_vp]),
     ("dec_bpm_get_tuning", c_int, [c_vp, P(Tuning)]),
     ("dec_bpm_set_tuning", c_int, [c_vp, P(Tuning)]),
+    ("dec_bpm_batch_get_tuning", c_int, [c_vp, P(Tuning)]),
+    ("dec_bpm_batch_set_tuning", c_int, [c_vp, P(Tuning)]),
     ("dec_bpm_time_kernels", c_int, [c_vp, c_dbl, c_dbl, c_i32, P(c_dbl), P(c_dbl), c_vp]),
     ("dec_bpm_batch_time_kernels", c_int, [c_vp, c_dbl, c_dbl, c_i32, P(c_dbl), P(c_dbl), c_vp]),
 ]

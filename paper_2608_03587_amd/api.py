@@ -275,6 +275,20 @@ class Batch:
 
     def autotune(self, dz, gamma=1.0, stream=None):
         B.check(B.lib().dec_bpm_batch_autotune(self._h, float(dz), float(gamma), _stream(stream)))
+        return self.tuning
+
+    @property
+    def tuning(self):
+        t = B.Tuning()
+        B.check(B.lib().dec_bpm_batch_get_tuning(self._h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in B.Tuning._fields_}
+
+    @tuning.setter
+    def tuning(self, value):
+        cur = self.tuning
+        cur.update(value)
+        t = B.Tuning(*[int(cur[f]) for f, _ in B.Tuning._fields_])
+        B.check(B.lib().dec_bpm_batch_set_tuning(self._h, ctypes.byref(t)))
 
 
 class DecBpmFunction(torch.autograd.Function):

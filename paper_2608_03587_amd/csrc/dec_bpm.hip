@@ -35,6 +35,36 @@ thread_local std::string g_last_error;
 // the imaginary axis up to 2 sqrt(2); keep a margin below it.
 constexpr double kStabilityLimit = 2.5;
 
+// Device copy of a tile set.
+struct DevTiles {
+  int32_t n_tiles = 0, TS = 0, max_slots = 0, max_compute = 0;
+  int32_t* hdr = nullptr;
+  int64_t* ent = nullptr;
+  int32_t* ext = nullptr;
+  int32_t* lsl = nullptr;
+  uint16_t* lcol = nullptr;
+  void* llw = nullptr;
+  void* lmw = nullptr;
+  int64_t entries = 0, slots = 0;
+
+  template <typename T>
+  TileOps<T> ops() const {
+    TileOps<T> t;
+    t.n_tiles = n_tiles;
+    t.TS = TS;
+    t.max_slots = max_slots;
+    t.max_compute = max_compute;
+    t.hdr = hdr;
+    t.ent_base = ent;
+    t.ext = ext;
+    t.lsl = lsl;
+    t.lcol = lcol;
+    t.llw = static_cast<const T*>(llw);
+    t.lmw = static_cast<const T*>(lmw);
+    return t;
+  }
+};
+
 struct GraphEntry {
   double dz, gamma;
   int spg, block, xcd, fused, tile_block;
@@ -66,20 +96,13 @@ struct Engine {
   double* h0 = nullptr;
   double* h0c = nullptr;  // caller order
   int32_t* perm = nullptr;
-  // tiles of the fused path (F = 1, beta4 = 0)
+  // tiles of the fused path (F = 1, beta4 = 0) and of the batched path (F > 1)
   bool has_tiles = false;
+  bool has_btiles = false;
   int fused = 1;      // use the fused kernels when tiles exist
   int tile_size = 512;
   int tile_block = 256;
-  int32_t n_tiles = 0, max_slots = 0, max_compute = 0;
-  int32_t* t_hdr = nullptr;
-  int64_t* t_ent = nullptr;
-  int32_t* t_ext = nullptr;
-  int32_t* t_lsl = nullptr;
-  uint16_t* t_lcol = nullptr;
-  void* t_llw = nullptr;
-  void* t_lmw = nullptr;
-  int64_t t_entries = 0, t_slots = 0;
+  DevTiles tl, bt;
   void* psi2 = nullptr;
   // work
   void* psi = nullptr;
@@ -110,7 +133,7 @@ struct Engine {
   // threads per tile workgroup: the requested count, raised so that no thread
   // owns more than two compute slots of a tile (the fused kernels' register budget)
   int tblock() const {
-    const int need = ((max_compute + 1) / 2 + 63) / 64 * 64;
+    const int need = ((tl.max_compute + 1) / 2 + 63) / 64 * 64;
     return std::min(1024, std::max(tile_block, need));
   }
 
@@ -119,19 +142,7 @@ struct Engine {
 
   template <typename T>
   TileOps<T> tiles() const {
-    TileOps<T> t;
-    t.n_tiles = n_tiles;
-    t.TS = tile_size;
-    t.max_slots = max_slots;
-    t.max_compute = max_compute;
-    t.hdr = t_hdr;
-    t.ent_base = t_ent;
-    t.ext = t_ext;
-    t.lsl = t_lsl;
-    t.lcol = t_lcol;
-    t.llw = static_cast<const T*>(t_llw);
-    t.lmw = static_cast<const T*>(t_lmw);
-    return t;
+    return tl.template ops<T>();
   }
 
   template <typename T>
@@ -205,22 +216,31 @@ static void upload(Engine& E, void*& dst, const std::vector<T>& src) {
   HIP_OK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
-// Tiles of the fused path: contiguous ranges of tile_size device rows plus
-// three halo rings found by breadth-first search on the adjacency; the
-// operator rows of rings 0..2 are stored again with slot-local columns.
-template <typename T>
-static bool build_tiles_ts(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
-                           const std::vector<double>& alw, const std::vector<double>& amw, bool dec, int TS) {
-  const int64_t n = E.n_rows;
-  const int64_t nt = (n + TS - 1) / TS;
-  std::vector<int32_t> hdr(nt * 8, 0), ext, lsl;
-  std::vector<int64_t> ebase(nt);
+// Tiles: contiguous ranges of TS device rows plus `rings` halo rings found by
+// breadth-first search on the adjacency; the operator rows of rings
+// 0..ell_rings-1 are stored again with slot-local 16-bit columns, sliced by
+// 64 slots.
+struct HostTiles {
+  int64_t nt = 0;
+  int TS = 0;
+  std::vector<int32_t> hdr, ext, lsl;
+  std::vector<int64_t> ebase;
   std::vector<uint16_t> lcol;
-  std::vector<T> llw, lmw;
-  std::vector<int32_t> slot_of(n, -1);
+  std::vector<double> llw, lmw;
   int32_t max_slots = 0, max_compute = 0;
+};
+
+static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
+                       const std::vector<double>& alw, const std::vector<double>& amw, int TS, int rings,
+                       int ell_rings, HostTiles& H) {
+  H = HostTiles();
+  H.TS = TS;
+  H.nt = (n + TS - 1) / TS;
+  H.hdr.assign(H.nt * 8, 0);
+  H.ebase.resize(H.nt);
+  std::vector<int32_t> slot_of(n, -1);
   std::vector<int32_t> slots, ring;
-  for (int64_t t = 0; t < nt; ++t) {
+  for (int64_t t = 0; t < H.nt; ++t) {
     const int64_t r0 = t * TS, r1 = std::min(n, r0 + TS);
     slots.clear();
     for (int64_t r = r0; r < r1; ++r) {
@@ -229,7 +249,7 @@ static bool build_tiles_ts(Engine& E, const std::vector<int64_t>& arp, const std
     }
     int cnt[4] = {int(r1 - r0), 0, 0, 0};
     size_t start = 0, end = slots.size();
-    for (int k = 1; k <= 3; ++k) {
+    for (int k = 1; k <= rings; ++k) {
       ring.clear();
       for (size_t i = start; i < end; ++i)
         for (int64_t e = arp[slots[i]]; e < arp[slots[i] + 1]; ++e)
@@ -246,81 +266,113 @@ static bool build_tiles_ts(Engine& E, const std::vector<int64_t>& arp, const std
       start = end;
       end = slots.size();
     }
-    if (slots.size() >= 65535) fail(DEC_BPM_EINVAL, "tile too large for 16-bit slot indices");
-    int32_t* h = &hdr[t * 8];
-    h[0] = cnt[0];
-    h[1] = cnt[1];
-    h[2] = cnt[2];
-    h[3] = cnt[3];
-    h[4] = int32_t(ext.size());
-    h[5] = int32_t(lsl.size());
-    ext.insert(ext.end(), slots.begin() + cnt[0], slots.end());
-    const int c2 = cnt[0] + cnt[1] + cnt[2];
-    max_compute = std::max(max_compute, c2);
-    ebase[t] = int64_t(lcol.size());
-    for (int sl = 0; sl * 64 < c2; ++sl) {
+    if (slots.size() >= 65535) {
+      for (int32_t r : slots) slot_of[r] = -1;
+      return false;
+    }
+    int32_t* h = &H.hdr[t * 8];
+    for (int k = 0; k < 4; ++k) h[k] = cnt[k];
+    h[4] = int32_t(H.ext.size());
+    h[5] = int32_t(H.lsl.size());
+    H.ext.insert(H.ext.end(), slots.begin() + cnt[0], slots.end());
+    int ce = 0;
+    for (int k = 0; k < ell_rings; ++k) ce += cnt[k];
+    H.max_compute = std::max(H.max_compute, ce);
+    H.ebase[t] = int64_t(H.lcol.size());
+    for (int sl = 0; sl * 64 < ce; ++sl) {
       int W = 0;
-      for (int i = sl * 64; i < std::min(c2, sl * 64 + 64); ++i)
+      for (int i = sl * 64; i < std::min(ce, sl * 64 + 64); ++i)
         W = std::max<int>(W, int(arp[slots[i] + 1] - arp[slots[i]]));
-      const int64_t rel = int64_t(lcol.size()) - ebase[t];
-      lsl.push_back(int32_t((rel << 8) | W));
-      const size_t b = lcol.size();
-      lcol.resize(b + size_t(W) * 64, 0);
-      llw.resize(b + size_t(W) * 64, T(0));
-      lmw.resize(b + size_t(W) * 64, T(0));
+      const int64_t rel = int64_t(H.lcol.size()) - H.ebase[t];
+      H.lsl.push_back(int32_t((rel << 8) | W));
+      const size_t b = H.lcol.size();
+      H.lcol.resize(b + size_t(W) * 64, 0);
+      H.llw.resize(b + size_t(W) * 64, 0.0);
+      H.lmw.resize(b + size_t(W) * 64, 0.0);
       for (int lane = 0; lane < 64; ++lane) {
         const int i = sl * 64 + lane;
-        for (int k = 0; k < W; ++k) lcol[b + size_t(k) * 64 + lane] = uint16_t(i < c2 ? i : 0);  // padding: self
-        if (i >= c2) continue;
+        for (int k = 0; k < W; ++k) H.lcol[b + size_t(k) * 64 + lane] = uint16_t(i < ce ? i : 0);  // padding: self
+        if (i >= ce) continue;
         int k = 0;
         for (int64_t e = arp[slots[i]]; e < arp[slots[i] + 1]; ++e, ++k) {
           const int32_t q = slot_of[acol[e]];
           if (q < 0) fail(DEC_BPM_EINVAL, "internal: halo ring incomplete");
-          lcol[b + size_t(k) * 64 + lane] = uint16_t(q);
-          llw[b + size_t(k) * 64 + lane] = T(alw[e]);
-          lmw[b + size_t(k) * 64 + lane] = T(amw[e]);
+          H.lcol[b + size_t(k) * 64 + lane] = uint16_t(q);
+          H.llw[b + size_t(k) * 64 + lane] = alw[e];
+          H.lmw[b + size_t(k) * 64 + lane] = amw[e];
         }
       }
     }
-    if (int64_t(lcol.size()) - ebase[t] >= (int64_t(1) << 23)) fail(DEC_BPM_EINVAL, "tile operator too large");
-    max_slots = std::max<int32_t>(max_slots, int32_t(slots.size()));
+    if (int64_t(H.lcol.size()) - H.ebase[t] >= (int64_t(1) << 23)) fail(DEC_BPM_EINVAL, "tile operator too large");
+    H.max_slots = std::max<int32_t>(H.max_slots, int32_t(slots.size()));
     for (int32_t r : slots) slot_of[r] = -1;
   }
-  max_slots = (max_slots + 3) / 4 * 4;
-  const size_t shmem = size_t(max_slots) * (7 * sizeof(T));
-  if (shmem > 64 * 1024) return false;      // a tile does not fit one workgroup's LDS
-  if (max_compute > 2 * 1024) return false;  // a thread keeps at most two slots' rows in registers
-  void* p;
-  upload(E, p, hdr);
-  E.t_hdr = static_cast<int32_t*>(p);
-  upload(E, p, ebase);
-  E.t_ent = static_cast<int64_t*>(p);
-  if (ext.empty()) ext.push_back(0);
-  upload(E, p, ext);
-  E.t_ext = static_cast<int32_t*>(p);
-  upload(E, p, lsl);
-  E.t_lsl = static_cast<int32_t*>(p);
-  upload(E, p, lcol);
-  E.t_lcol = static_cast<uint16_t*>(p);
-  upload(E, E.t_llw, llw);
-  if (dec) upload(E, E.t_lmw, lmw);
-  E.n_tiles = int32_t(nt);
-  E.max_slots = max_slots;
-  E.max_compute = max_compute;
-  E.t_entries = int64_t(lcol.size());
-  E.t_slots = int64_t(ext.size()) + n;
-  E.tile_size = TS;
-  E.has_tiles = true;
+  H.max_slots = (H.max_slots + 3) / 4 * 4;
+  if (H.ext.empty()) H.ext.push_back(0);
   return true;
 }
 
-// Largest tile size (from the requested one, halving) whose biggest tile with
-// its halo rings fits 64 KB of LDS; no tiles (unfused path only) if none does.
+template <typename T>
+static void upload_tiles(Engine& E, const HostTiles& H, bool dec, int64_t n, DevTiles& D) {
+  void* p;
+  upload(E, p, H.hdr);
+  D.hdr = static_cast<int32_t*>(p);
+  upload(E, p, H.ebase);
+  D.ent = static_cast<int64_t*>(p);
+  upload(E, p, H.ext);
+  D.ext = static_cast<int32_t*>(p);
+  upload(E, p, H.lsl);
+  D.lsl = static_cast<int32_t*>(p);
+  upload(E, p, H.lcol);
+  D.lcol = static_cast<uint16_t*>(p);
+  std::vector<T> w(H.llw.begin(), H.llw.end());
+  upload(E, D.llw, w);
+  if (dec) {
+    std::vector<T> m(H.lmw.begin(), H.lmw.end());
+    upload(E, D.lmw, m);
+  }
+  D.n_tiles = int32_t(H.nt);
+  D.TS = H.TS;
+  D.max_slots = H.max_slots;
+  D.max_compute = H.max_compute;
+  D.entries = int64_t(H.lcol.size());
+  D.slots = int64_t(H.ext.size()) + n;
+}
+
+// Plain fused path: the largest tile size (from the requested one, halving)
+// whose biggest tile with three halo rings fits 64 KB of LDS and whose
+// compute slots fit two per thread of a 1024-thread workgroup.
 template <typename T>
 static void build_tiles(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
                         const std::vector<double>& alw, const std::vector<double>& amw, bool dec) {
-  for (int ts = E.tile_size; ts >= 64; ts /= 2)
-    if (build_tiles_ts<T>(E, arp, acol, alw, amw, dec, ts)) return;
+  HostTiles H;
+  for (int ts = E.tile_size; ts >= 64; ts /= 2) {
+    if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, 3, 3, H)) continue;
+    if (size_t(H.max_slots) * 7 * sizeof(T) > 64 * 1024 || H.max_compute > 2 * 1024) continue;
+    upload_tiles<T>(E, H, dec, E.n_rows, E.tl);
+    E.tile_size = ts;
+    E.has_tiles = true;
+    return;
+  }
+}
+
+// Batched path: tiles of one halo ring whose field values (all F fields of
+// every slot) are staged in LDS by one workgroup; rows per tile so that a
+// workgroup has at most 1024 threads of 32 bytes of fields each.
+template <typename T>
+static void build_batch_tiles(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
+                              const std::vector<double>& alw, const std::vector<double>& amw, bool dec) {
+  const int VF = int(32 / (2 * sizeof(T)));
+  if (E.F < VF || E.F % VF || E.wmax > 12) return;
+  const int tpr = E.F / VF;  // threads per row
+  HostTiles H;
+  for (int ts = std::max(1, 1024 / tpr); ts >= 8; ts /= 2) {
+    if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, 1, 1, H)) continue;
+    if (size_t(H.max_slots) * E.F * 2 * sizeof(T) > 64 * 1024) continue;
+    upload_tiles<T>(E, H, dec, E.n_rows, E.bt);
+    E.has_btiles = true;
+    return;
+  }
 }
 
 // Build the device engine from one or more assembled meshes (concatenated).
@@ -441,6 +493,7 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   upload(E, p, perm);
   E.perm = static_cast<int32_t*>(p);
   if (E.F == 1 && E.beta4 == 0.0) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
   const size_t nv = size_t(n) * E.F;
   E.psi = E.dalloc(nv * 2 * sizeof(T));
   if (E.has_tiles) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
@@ -473,10 +526,40 @@ static void check_launch() {
 // ---- one z step on the engine's device-order state psi (F fields per row) ----
 // LIN(dz) as a Horner evaluation of the RK4 polynomial (identical to the four
 // classical stages for a linear autonomous system), then NL(tau_next).
+// Batched engines with tiles run the LDS-tiled kernels (same arithmetic).
+template <typename T>
+static bool use_btiles(const Engine& E) {
+  return E.has_btiles && E.fused;
+}
+
+template <typename T>
+static void do_stage(const Engine& E, const DevOps<T>& d, const void* x, const void* t, const void* psi, void* y,
+                     double coef, void* s_out, double tau_s, hipStream_t st) {
+  if (use_btiles<T>(E))
+    launch_bstage<T>(d, E.bt.template ops<T>(), x, t, psi, y, coef, s_out, tau_s, st);
+  else
+    launch_stage<T>(d, x, t, psi, y, coef, s_out, tau_s, E.block, st);
+}
+
+template <typename T>
+static void do_lap(const Engine& E, const DevOps<T>& d, const void* x, void* t, hipStream_t st) {
+  if (use_btiles<T>(E))
+    launch_blap<T>(d, E.bt.template ops<T>(), x, t, st);
+  else
+    launch_lap<T>(d, x, t, E.block, st);
+}
+
+// The Kerr step stays row-parallel: its gathered vector (|psi|^2 phi, real)
+// is half the size of a field and the tiled variant measured slower.
+template <typename T>
+static void do_kerr(const Engine& E, const DevOps<T>& d, const void* in, void* out, const void* s, double tau,
+                    double gamma, hipStream_t st) {
+  launch_kerr<T>(d, in, out, s, tau, gamma, E.block, st);
+}
+
 template <typename T>
 static void lin_step(const Engine& E, const DevOps<T>& d, const void* in, void* out, void* y1, void* y2, void* y3,
                      double dz, void* s_out, double tau_s, hipStream_t st) {
-  const int B = E.block;
   const void* t = nullptr;
   // y1 = psi + dz/4 A psi;  y2 = psi + dz/3 A y1;  y3 = psi + dz/2 A y2;  out = psi + dz A y3
   const void* xs[4] = {in, y1, y2, y3};
@@ -484,10 +567,10 @@ static void lin_step(const Engine& E, const DevOps<T>& d, const void* in, void* 
   const double cs[4] = {dz / 4, dz / 3, dz / 2, dz};
   for (int k = 0; k < 4; ++k) {
     if (E.beta4 != 0.0) {
-      launch_lap<T>(d, xs[k], E.t, B, st);
+      do_lap<T>(E, d, xs[k], E.t, st);
       t = E.t;
     }
-    launch_stage<T>(d, xs[k], t, in, ys[k], cs[k], k == 3 ? s_out : nullptr, tau_s, B, st);
+    do_stage<T>(E, d, xs[k], t, in, ys[k], cs[k], k == 3 ? s_out : nullptr, tau_s, st);
   }
 }
 
@@ -495,7 +578,7 @@ template <typename T>
 static void z_step(const Engine& E, const DevOps<T>& d, double dz, double gamma, double tau_next, hipStream_t st) {
   // buffers: y1 -> ya, y2 -> yb, y3 -> ya (y1 is dead once y2 exists), result in place on psi
   lin_step<T>(E, d, E.psi, E.psi, E.ya, E.yb, E.ya, dz, E.s, tau_next, st);
-  launch_kerr<T>(d, E.psi, E.psi, E.s, tau_next, gamma, E.block, st);
+  do_kerr<T>(E, d, E.psi, E.psi, E.s, tau_next, gamma, st);
 }
 
 template <typename T>
@@ -610,7 +693,7 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
   } else {
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
-    launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
+    do_kerr<T>(E, d, E.psi, E.psi, E.s, 0.5 * dz, gamma, st);
     run_middle<T>(E, n - 1, dz, gamma, st);
     z_step<T>(E, d, dz, gamma, 0.5 * dz, st);
     launch_perm_out<T>(d, E.perm, E.psi, field, 0, E.flag, B, st);
@@ -767,7 +850,7 @@ static void adjoint_t(Engine& E, const void* grad_out, double dz, int64_t n, dou
 // tile launches per step.
 template <typename T>
 static bool adjoint_fused_ok(const Engine& E) {
-  return use_fused<T>(E) && size_t(E.max_slots) * 4 * 2 * sizeof(T) <= 64 * 1024;
+  return use_fused<T>(E) && size_t(E.tl.max_slots) * 4 * 2 * sizeof(T) <= 64 * 1024;
 }
 
 template <typename T>
@@ -854,9 +937,9 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
     hipGraph_t g;
     HIP_OK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
     for (int r = 0; r < reps; ++r) {
-      if (kind == DEC_BPM_K_KERR) launch_kerr<T>(d, E.psi, E.psi, E.s, dz, gamma, B, E.cap);
-      if (kind == DEC_BPM_K_STAGE) launch_stage<T>(d, E.ya, nullptr, E.psi, E.yb, dz / 3, nullptr, 0.0, B, E.cap);
-      if (kind == DEC_BPM_K_LAP) launch_lap<T>(d, E.ya, E.yb, B, E.cap);
+      if (kind == DEC_BPM_K_KERR) do_kerr<T>(E, d, E.psi, E.psi, E.s, dz, gamma, E.cap);
+      if (kind == DEC_BPM_K_STAGE) do_stage<T>(E, d, E.ya, nullptr, E.psi, E.yb, dz / 3, nullptr, 0.0, E.cap);
+      if (kind == DEC_BPM_K_LAP) do_lap<T>(E, d, E.ya, E.yb, E.cap);
       if (kind == DEC_BPM_K_TILE_A)
         launch_fused<T>(d, tl, FUSED_S4_NL_S1, E.yb, E.psi, E.psi2, E.ya, nullptr, dz, dz, gamma, E.tblock(), E.cap);
       if (kind == DEC_BPM_K_TILE_B)
@@ -906,7 +989,7 @@ static bool tune_cache_lookup(Engine& E) {
       E.block = b;
       E.spg = s;
       E.xcd = x;
-      E.fused = E.has_tiles ? fu : 0;
+      E.fused = (E.has_tiles || E.has_btiles) ? fu : 0;
       E.tile_block = tb;
       return true;
     }
@@ -949,6 +1032,7 @@ static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
       for (int b : {64, 128, 256, 512, 1024}) cands.push_back({0, b, E.tile_block, s, x});
       if (E.has_tiles)
         for (int tb : {128, 256, 512, 1024}) cands.push_back({1, E.block, tb, s, x});
+      if (E.has_btiles) cands.push_back({1, E.block, E.tile_block, s, x});
     }
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
@@ -1467,30 +1551,52 @@ int dec_bpm_batch_autotune(dec_bpm_batch_t b, double dz, double gamma, void* str
   ABI_CATCH
 }
 
+static void get_tuning(const Engine& E, dec_bpm_tuning* t) {
+  t->block_size = E.block;
+  t->steps_per_graph = E.spg;
+  t->fused = (E.has_tiles || E.has_btiles) ? E.fused : 0;
+  t->tile_block = E.has_tiles ? E.tblock() : E.tile_block;
+  t->xcd_remap = E.xcd;
+}
+
+static void set_tuning(Engine& E, const dec_bpm_tuning* t) {
+  if (!t || t->block_size < 64 || t->block_size > 1024 || t->block_size % 64 || t->steps_per_graph < 1 ||
+      t->tile_block < 64 || t->tile_block > 1024 || t->tile_block % 64 || (t->fused != 0 && t->fused != 1) ||
+      (t->xcd_remap != 0 && t->xcd_remap != 1))
+    fail(DEC_BPM_EINVAL, "bad tuning");
+  E.block = t->block_size;
+  E.spg = t->steps_per_graph;
+  E.fused = t->fused;
+  E.tile_block = t->tile_block;
+  E.xcd = t->xcd_remap;
+}
+
+int dec_bpm_batch_get_tuning(dec_bpm_batch_t b, dec_bpm_tuning* t) {
+  ABI_TRY
+  if (!b || !t) fail(DEC_BPM_EINVAL, "NULL argument");
+  get_tuning(b->E, t);
+  ABI_CATCH
+}
+
+int dec_bpm_batch_set_tuning(dec_bpm_batch_t b, const dec_bpm_tuning* t) {
+  ABI_TRY
+  if (!b) fail(DEC_BPM_EINVAL, "batch is NULL");
+  set_tuning(b->E, t);
+  ABI_CATCH
+}
+
 int dec_bpm_get_tuning(dec_bpm_t h, dec_bpm_tuning* t) {
   ABI_TRY
   need(h);
   if (!t) fail(DEC_BPM_EINVAL, "NULL tuning");
-  t->block_size = h->E.block;
-  t->steps_per_graph = h->E.spg;
-  t->fused = h->E.has_tiles ? h->E.fused : 0;
-  t->tile_block = h->E.has_tiles ? h->E.tblock() : h->E.tile_block;
-  t->xcd_remap = h->E.xcd;
+  get_tuning(h->E, t);
   ABI_CATCH
 }
 
 int dec_bpm_set_tuning(dec_bpm_t h, const dec_bpm_tuning* t) {
   ABI_TRY
   need(h);
-  if (!t || t->block_size < 64 || t->block_size > 1024 || t->block_size % 64 || t->steps_per_graph < 1 ||
-      t->tile_block < 64 || t->tile_block > 1024 || t->tile_block % 64 || (t->fused != 0 && t->fused != 1) ||
-      (t->xcd_remap != 0 && t->xcd_remap != 1))
-    fail(DEC_BPM_EINVAL, "bad tuning");
-  h->E.block = t->block_size;
-  h->E.spg = t->steps_per_graph;
-  h->E.fused = t->fused;
-  h->E.tile_block = t->tile_block;
-  h->E.xcd = t->xcd_remap;
+  set_tuning(h->E, t);
   ABI_CATCH
 }
 

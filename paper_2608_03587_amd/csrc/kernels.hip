@@ -9,6 +9,8 @@
 // writes every vector once.  No matrix cores: there is no dense contraction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace decbpm {
@@ -639,6 +641,224 @@ __global__ void __launch_bounds__(1024) k_kerr_w(DevOps<T> d, const typename CT<
   reinterpret_cast<V*>(psi_out)[e0 / VF] = out;
 }
 
+// ---- batched kernels on LDS tiles (one halo ring, all fields of every slot) ----
+// A workgroup stages the gathered vector for its tile's rows and their
+// one-ring halo in LDS (32 bytes of fields per thread), then every neighbour
+// gather of its rows reads LDS instead of L2.
+template <typename T, int VF, int KMAX, bool B4, bool WS>
+__global__ void __launch_bounds__(1024) k_bstage(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ x,
+                                                 const typename CT<T>::C* __restrict__ t,
+                                                 const typename CT<T>::C* psi, typename CT<T>::C* y, T coef,
+                                                 T* __restrict__ s_out, T tau_s) {
+  static_assert(KMAX > 0, "tiled batched kernels need a bounded row width");
+  using V = CVec<T, VF>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int32_t* hd = tl.hdr + 8 * tile;
+  const int c0 = hd[0], c1 = c0 + hd[1];
+  const int32_t* __restrict__ ext = tl.ext + hd[4];
+  const int32_t* __restrict__ lsl = tl.lsl + hd[5];
+  const int64_t ebase = tl.ent_base[tile];
+  const int64_t row0 = tile * int64_t(tl.TS);
+  const int tpr = d.F / VF;
+  V* X = reinterpret_cast<V*>(smem);
+  const auto* __restrict__ g = reinterpret_cast<const V*>(B4 ? t : x);
+  // this thread's element (one per thread: the workgroup covers the tile's rows x fields)
+  const int e = threadIdx.x;
+  const bool mine = e < c0 * tpr;
+  const int slot = e / tpr, fv = e - slot * tpr;
+  const int64_t r = row0 + slot;
+  V p, xr;
+  T vr = T(0), ph = T(0);
+  int W = 0;
+  int qq[KMAX];
+  T cc[KMAX];
+  if (mine) {
+    p = reinterpret_cast<const V*>(psi)[r * tpr + fv];
+    if (B4) xr = reinterpret_cast<const V*>(x)[r * tpr + fv];
+    vr = d.v[r];
+    if (WS) ph = phi_w(d.w[r], tau_s);
+    const int32_t info = lsl[slot >> 6];
+    W = info & 0xff;
+    const int64_t base = ebase + (info >> 8) + (slot & 63);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      qq[k] = k < W ? int(tl.lcol[base + 64 * k]) : 0;
+      cc[k] = k < W ? tl.llw[base + 64 * k] : T(0);
+    }
+  }
+  for (int i = threadIdx.x; i < c1 * tpr; i += blockDim.x) {
+    const int sl = i / tpr, f = i - sl * tpr;
+    const int64_t rr = sl < c0 ? row0 + sl : int64_t(ext[sl - c0]);
+    X[i] = g[rr * tpr + f];
+  }
+  __syncthreads();
+  if (!mine) return;
+  const V gr = X[e];
+  if (!B4) xr = gr;
+  T ar[VF], ai[VF];
+#pragma unroll
+  for (int f = 0; f < VF; ++f) ar[f] = ai[f] = T(0);
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+    if (k < W) {
+      const V gq = X[qq[k] * tpr + fv];
+#pragma unroll
+      for (int f = 0; f < VF; ++f) {
+        ar[f] += cc[k] * (gr.v[f].x - gq.v[f].x);
+        ai[f] += cc[k] * (gr.v[f].y - gq.v[f].y);
+      }
+    }
+  V out;
+  RVec<T, VF> so;
+#pragma unroll
+  for (int f = 0; f < VF; ++f) {
+    T hr, hi;
+    if (B4) {
+      hr = d.p1 * gr.v[f].x + d.beta4 * ar[f] - vr * xr.v[f].x;
+      hi = d.p1 * gr.v[f].y + d.beta4 * ai[f] - vr * xr.v[f].y;
+    } else {
+      hr = d.p1 * ar[f] - vr * xr.v[f].x;
+      hi = d.p1 * ai[f] - vr * xr.v[f].y;
+    }
+    out.v[f].x = p.v[f].x + coef * hi;
+    out.v[f].y = p.v[f].y - coef * hr;
+    so.v[f] = (out.v[f].x * out.v[f].x + out.v[f].y * out.v[f].y) * ph;
+  }
+  reinterpret_cast<V*>(y)[r * tpr + fv] = out;
+  if (WS) reinterpret_cast<RVec<T, VF>*>(s_out)[r * tpr + fv] = so;
+}
+
+template <typename T, int VF, int KMAX>
+__global__ void __launch_bounds__(1024) k_blap(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ x,
+                                               typename CT<T>::C* __restrict__ t) {
+  static_assert(KMAX > 0, "tiled batched kernels need a bounded row width");
+  using V = CVec<T, VF>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int32_t* hd = tl.hdr + 8 * tile;
+  const int c0 = hd[0], c1 = c0 + hd[1];
+  const int32_t* __restrict__ ext = tl.ext + hd[4];
+  const int32_t* __restrict__ lsl = tl.lsl + hd[5];
+  const int64_t ebase = tl.ent_base[tile];
+  const int64_t row0 = tile * int64_t(tl.TS);
+  const int tpr = d.F / VF;
+  V* X = reinterpret_cast<V*>(smem);
+  const auto* __restrict__ g = reinterpret_cast<const V*>(x);
+  const int e = threadIdx.x;
+  const bool mine = e < c0 * tpr;
+  const int slot = e / tpr, fv = e - slot * tpr;
+  const int64_t r = row0 + slot;
+  int W = 0;
+  int qq[KMAX];
+  T cc[KMAX];
+  if (mine) {
+    const int32_t info = lsl[slot >> 6];
+    W = info & 0xff;
+    const int64_t base = ebase + (info >> 8) + (slot & 63);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      qq[k] = k < W ? int(tl.lcol[base + 64 * k]) : 0;
+      cc[k] = k < W ? tl.llw[base + 64 * k] : T(0);
+    }
+  }
+  for (int i = threadIdx.x; i < c1 * tpr; i += blockDim.x) {
+    const int sl = i / tpr, f = i - sl * tpr;
+    const int64_t rr = sl < c0 ? row0 + sl : int64_t(ext[sl - c0]);
+    X[i] = g[rr * tpr + f];
+  }
+  __syncthreads();
+  if (!mine) return;
+  const V xr = X[e];
+  V out;
+#pragma unroll
+  for (int f = 0; f < VF; ++f) out.v[f].x = out.v[f].y = T(0);
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+    if (k < W) {
+      const V xq = X[qq[k] * tpr + fv];
+#pragma unroll
+      for (int f = 0; f < VF; ++f) {
+        out.v[f].x += cc[k] * (xr.v[f].x - xq.v[f].x);
+        out.v[f].y += cc[k] * (xr.v[f].y - xq.v[f].y);
+      }
+    }
+  reinterpret_cast<V*>(t)[r * tpr + fv] = out;
+}
+
+template <typename T, int VF, int KMAX>
+__global__ void __launch_bounds__(1024) k_bkerr(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* psi_in,
+                                                typename CT<T>::C* psi_out, const T* __restrict__ s, T tau, T gamma) {
+  using V = CVec<T, VF>;
+  using R = RVec<T, VF>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int32_t* hd = tl.hdr + 8 * tile;
+  const int c0 = hd[0], c1 = c0 + hd[1];
+  const int32_t* __restrict__ ext = tl.ext + hd[4];
+  const int32_t* __restrict__ lsl = tl.lsl + hd[5];
+  const int64_t ebase = tl.ent_base[tile];
+  const int64_t row0 = tile * int64_t(tl.TS);
+  const int tpr = d.F / VF;
+  R* S = reinterpret_cast<R*>(smem);
+  const auto* __restrict__ sv = reinterpret_cast<const R*>(s);
+  for (int e = threadIdx.x; e < c1 * tpr; e += blockDim.x) {
+    const int slot = e / tpr, fv = e - slot * tpr;
+    const int64_t r = slot < c0 ? row0 + slot : int64_t(ext[slot - c0]);
+    S[e] = sv[r * tpr + fv];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < c0 * tpr; e += blockDim.x) {
+    const int slot = e / tpr, fv = e - slot * tpr;
+    const int64_t r = row0 + slot;
+    const V p = reinterpret_cast<const V*>(psi_in)[r * tpr + fv];
+    const R own = S[e];
+    const T md = d.mdiag[r];
+    T th[VF];
+#pragma unroll
+    for (int f = 0; f < VF; ++f) th[f] = md * own.v[f];
+    const int32_t info = lsl[slot >> 6];
+    const int W = info & 0xff;
+    const int64_t base = ebase + (info >> 8) + (slot & 63);
+    if constexpr (KMAX > 0) {
+      int qq[KMAX];
+      T mm[KMAX];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        qq[k] = k < W ? int(tl.lcol[base + 64 * k]) : 0;
+        mm[k] = k < W ? tl.lmw[base + 64 * k] : T(0);
+      }
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < W) {
+          const R sq = S[qq[k] * tpr + fv];
+#pragma unroll
+          for (int f = 0; f < VF; ++f) th[f] += mm[k] * sq.v[f];
+        }
+    } else {
+      for (int k = 0; k < W; ++k) {
+        const R sq = S[int(tl.lcol[base + 64 * k]) * tpr + fv];
+        const T m = tl.lmw[base + 64 * k];
+#pragma unroll
+        for (int f = 0; f < VF; ++f) th[f] += m * sq.v[f];
+      }
+    }
+    const T damp = d_exp(-d.w[r] * tau);
+    V out;
+#pragma unroll
+    for (int f = 0; f < VF; ++f) {
+      T sn, cs;
+      d_sincos(gamma * th[f], &sn, &cs);
+      out.v[f].x = damp * (p.v[f].x * cs - p.v[f].y * sn);
+      out.v[f].y = damp * (p.v[f].x * sn + p.v[f].y * cs);
+    }
+    reinterpret_cast<V*>(psi_out)[r * tpr + fv] = out;
+  }
+}
+
 // ---- fused z-step kernels on LDS tiles ----
 // One workgroup per tile.  The tile's rows and halo rings are staged in LDS;
 // each stage of the kind is computed on the rings it needs, separated by
@@ -1254,6 +1474,61 @@ void launch_fused_adj(const DevOps<T>& d, const TileOps<T>& tl, int kind, const 
 }
 
 template <typename T>
+void launch_bstage(const DevOps<T>& d, const TileOps<T>& tl, const void* x, const void* t, const void* psi, void* y,
+                   double coef, void* s_out, double tau_s, hipStream_t st) {
+  constexpr int VF = int(32 / sizeof(typename CT<T>::C));
+  const int tpr = d.F / VF;
+  const int block = std::min(1024, std::max(64, (tl.TS * tpr + 63) / 64 * 64));
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * d.F * sizeof(typename CT<T>::C);
+  T* sw = reinterpret_cast<T*>(s_out);
+  const int mode = (t != nullptr) * 2 + (s_out != nullptr);
+#define DECBPM_BSTAGE(B4, WS)                                                                                      \
+  hipLaunchKernelGGL((k_bstage<T, VF, KM, B4, WS>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, x),         \
+                     DECBPM_C(T, t), DECBPM_C(T, psi), DECBPM_M(T, y), T(coef), sw, T(tau_s))
+  if (kmax_of(d.wmax) == 8) {
+    constexpr int KM = 8;
+    if (mode == 0) DECBPM_BSTAGE(false, false);
+    else if (mode == 1) DECBPM_BSTAGE(false, true);
+    else if (mode == 2) DECBPM_BSTAGE(true, false);
+    else DECBPM_BSTAGE(true, true);
+  } else {
+    constexpr int KM = 12;
+    if (mode == 0) DECBPM_BSTAGE(false, false);
+    else if (mode == 1) DECBPM_BSTAGE(false, true);
+    else if (mode == 2) DECBPM_BSTAGE(true, false);
+    else DECBPM_BSTAGE(true, true);
+  }
+#undef DECBPM_BSTAGE
+}
+
+template <typename T>
+void launch_blap(const DevOps<T>& d, const TileOps<T>& tl, const void* x, void* t, hipStream_t st) {
+  constexpr int VF = int(32 / sizeof(typename CT<T>::C));
+  const int tpr = d.F / VF;
+  const int block = std::min(1024, std::max(64, (tl.TS * tpr + 63) / 64 * 64));
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * d.F * sizeof(typename CT<T>::C);
+  if (kmax_of(d.wmax) == 8)
+    hipLaunchKernelGGL((k_blap<T, VF, 8>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, x), DECBPM_M(T, t));
+  else
+    hipLaunchKernelGGL((k_blap<T, VF, 12>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, x), DECBPM_M(T, t));
+}
+
+template <typename T>
+void launch_bkerr(const DevOps<T>& d, const TileOps<T>& tl, const void* psi_in, void* psi_out, const void* s,
+                  double tau, double gamma, hipStream_t st) {
+  constexpr int VF = int(32 / sizeof(typename CT<T>::C));
+  const int tpr = d.F / VF;
+  const int block = std::min(1024, std::max(64, (tl.TS * tpr + 63) / 64 * 64));
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * d.F * sizeof(T);
+  const T* sp = reinterpret_cast<const T*>(s);
+  DECBPM_DISPATCH_K(d, hipLaunchKernelGGL((k_bkerr<T, VF, KM>), dim3(g), dim3(block), shmem, st, d, tl,
+                                          DECBPM_C(T, psi_in), DECBPM_M(T, psi_out), sp, T(tau), T(gamma)))
+}
+
+template <typename T>
 void launch_perm_in(const DevOps<T>& d, const int32_t* perm, const void* src, void* dst, int scale_inv_h0, int block,
                     hipStream_t st) {
   const unsigned g = grid_for(d.n_rows * d.F, block, 0);
@@ -1381,6 +1656,11 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   template void launch_hcombine<T>(const DevOps<T>&, const void*, const void*, const void*, void*, int,           \
                                    hipStream_t);                                                                 \
   template void launch_set_v<T>(int64_t, const T*, const double*, const int32_t*, T*, int, hipStream_t);          \
+  template void launch_bstage<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*, void*, \
+                                 double, void*, double, hipStream_t);                                            \
+  template void launch_blap<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, hipStream_t);           \
+  template void launch_bkerr<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, const void*, double,     \
+                                double, hipStream_t);                                                            \
   template void launch_fused<T>(const DevOps<T>&, const TileOps<T>&, int, const void*, const void*, void*, void*,  \
                                 void*, double, double, double, int, hipStream_t);                                \
   template void launch_fused_adj<T>(const DevOps<T>&, const TileOps<T>&, int, const void*, const void*,          \

@@ -148,6 +148,17 @@ void launch_adj_kerr(const DevOps<T>& d, const void* psi_in, const void* lam_out
 //   FUSED_NL_S1:    first step: psi'' = NL_tau(psi), y1 = psi'' + h/4 A psi''
 //   FUSED_S4_NL:    last step: psi_new = psi + h A y3, psi'' = NL_tau(psi_new)
 // in_x is y3 (S4 kinds), y1 (S2_S3) or unused; in_psi is the state psi.
+// Batched (F > 1) stage / Laplacian / Kerr kernels on one-ring tiles whose
+// fields are staged in LDS (same arithmetic as launch_stage/lap/kerr).
+template <typename T>
+void launch_bstage(const DevOps<T>& d, const TileOps<T>& tl, const void* x, const void* t, const void* psi, void* y,
+                   double coef, void* s_out, double tau_s, hipStream_t st);
+template <typename T>
+void launch_blap(const DevOps<T>& d, const TileOps<T>& tl, const void* x, void* t, hipStream_t st);
+template <typename T>
+void launch_bkerr(const DevOps<T>& d, const TileOps<T>& tl, const void* psi_in, void* psi_out, const void* s,
+                  double tau, double gamma, hipStream_t st);
+
 // out_rec (may be null) receives, for owned rows, y2 (FUSED_S2_S3) or the
 // state before the Kerr substep (S4 kinds): the adjoint's segment recompute.
 template <typename T>

@@ -260,9 +260,17 @@ def test_batched_equals_plain(dtype):
     say("batched", dtype, [x.mesh.n_vert for x in ws])
     meshes = [lib_mesh(x, dtype) for x in ws]
     batch = api.Batch(meshes, 4)
-    packed = batch.pack([dev(x.u0, dtype) for x in ws])
-    batch.propagate(packed, ws[0].dz, ws[0].n_steps, 1.0)
-    outs = batch.unpack(packed)
+    packed0 = batch.pack([dev(x.u0, dtype) for x in ws])
+    # LDS-tiled batched kernels vs row-parallel ones: identical per-row formulas
+    runs = {}
+    for fused in (0, 1):
+        batch.tuning = {"fused": fused}
+        pk = packed0.clone()
+        batch.propagate(pk, ws[0].dz, ws[0].n_steps, 1.0)
+        runs[fused] = pk
+    assert batch.tuning["fused"] == 1
+    assert rel(host(runs[1]), host(runs[0])) < (1e-13 if dtype == "c128" else 1e-6)
+    outs = batch.unpack(runs[1])
     tol = 1e-12 if dtype == "c128" else 1e-5  # same per-row formulas; only FMA contraction may differ
     for m, x, o in zip(meshes, ws, outs):
         for f in range(4):
