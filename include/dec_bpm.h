@@ -225,15 +225,18 @@ int dec_bpm_batch_propagate(dec_bpm_batch_t b, void* packed_fields, double dz, i
  * block size; fused LDS-tiled path: threads per tile; both: z steps per
  * hipGraph and the XCD-aware block mapping) on the handle's own work buffers
  * with HIP events and keeps the fastest; the result is cached in the JSON file
- * named by DEC_BPM_TUNE_CACHE if that variable is set.  Synchronises.  The
- * fused path (two kernels per z step: stages 2+3, and stage 4 + Kerr/absorber
- * + next stage 1, each on a tile of rows with its halo rings in LDS) exists
- * for one-field handles without the beta4 term.
+ * named by DEC_BPM_TUNE_CACHE if that variable is set.  Synchronises.  Two
+ * fused paths exist for one-field handles without the beta4 term: fused = 1
+ * runs two kernels per z step (stages 2+3, and stage 4 + Kerr/absorber + next
+ * stage 1, each on a tile of rows with three halo rings in LDS); fused = 2
+ * runs the whole z step (four stages + Kerr/absorber) as one kernel on tiles
+ * with five halo rings (four for the lumped nonlinearity).  A handle that has
+ * no tiles for the requested mode runs the unfused kernels.
  */
 typedef struct {
   int32_t block_size;       /* threads per workgroup of the unfused kernels      */
   int32_t steps_per_graph;  /* z steps per captured hipGraph (1 = no graph)      */
-  int32_t fused;            /* 1: fused tile kernels (if available)              */
+  int32_t fused;            /* 0: unfused, 1: two tile kernels, 2: one per step  */
   int32_t tile_block;       /* threads per workgroup of the fused kernels        */
   int32_t xcd_remap;        /* 1: consecutive row blocks on one XCD               */
 } dec_bpm_tuning;
@@ -259,7 +262,8 @@ enum {
   DEC_BPM_K_LAP = 2,      /* bare L application (first half of a beta4 stage)    */
   DEC_BPM_K_TILE_A = 3,   /* fused tile kernel: stage 4 + Kerr/absorber + stage 1 */
   DEC_BPM_K_TILE_B = 4,   /* fused tile kernel: stages 2 + 3                      */
-  DEC_BPM_NUM_KERNELS = 5
+  DEC_BPM_K_STEP = 5,     /* one-kernel z step: four stages + Kerr/absorber       */
+  DEC_BPM_NUM_KERNELS = 6
 };
 int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
                          void* stream);

@@ -102,7 +102,8 @@ struct Engine {
   int fused = 1;      // use the fused kernels when tiles exist
   int tile_size = 512;
   int tile_block = 256;
-  DevTiles tl, bt;
+  DevTiles tl, bt, stp;  // two-kernel tiles (3 rings), batched tiles, one-kernel-step tiles (5 rings)
+  bool has_step = false;
   void* psi2 = nullptr;
   // work
   void* psi = nullptr;
@@ -129,6 +130,11 @@ struct Engine {
     uint64_t dn_version = 0;
   } ckpt;
   uint64_t dn_version = 0;
+
+  int sblock() const {
+    const int need = ((stp.max_compute + 1) / 2 + 63) / 64 * 64;
+    return std::min(1024, std::max(tile_block, need));
+  }
 
   // threads per tile workgroup: the requested count, raised so that no thread
   // owns more than two compute slots of a tile (the fused kernels' register budget)
@@ -204,7 +210,7 @@ struct Engine {
 // Default launch shape from the environment (used before any autotuning).
 static void env_defaults(Engine& E) {
   if (const char* s = std::getenv("DEC_BPM_TILE")) E.tile_size = std::max(64, std::min(4096, std::atoi(s)));
-  if (const char* s = std::getenv("DEC_BPM_FUSED")) E.fused = std::atoi(s) ? 1 : 0;
+  if (const char* s = std::getenv("DEC_BPM_FUSED")) E.fused = std::max(0, std::min(2, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_BLOCK")) E.block = std::max(64, std::min(1024, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_STEPS_PER_GRAPH")) E.spg = std::max(1, std::atoi(s));
   if (const char* s = std::getenv("DEC_BPM_XCD_REMAP")) E.xcd = std::atoi(s) ? 1 : 0;
@@ -233,6 +239,7 @@ struct HostTiles {
 static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
                        const std::vector<double>& alw, const std::vector<double>& amw, int TS, int rings,
                        int ell_rings, HostTiles& H) {
+  if (rings > 5 || ell_rings > rings + 1) fail(DEC_BPM_EINVAL, "internal: unsupported ring count");
   H = HostTiles();
   H.TS = TS;
   H.nt = (n + TS - 1) / TS;
@@ -247,7 +254,7 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
       slot_of[r] = int32_t(r - r0);
       slots.push_back(int32_t(r));
     }
-    int cnt[4] = {int(r1 - r0), 0, 0, 0};
+    int cnt[6] = {int(r1 - r0), 0, 0, 0, 0, 0};
     size_t start = 0, end = slots.size();
     for (int k = 1; k <= rings; ++k) {
       ring.clear();
@@ -271,9 +278,15 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
       return false;
     }
     int32_t* h = &H.hdr[t * 8];
-    for (int k = 0; k < 4; ++k) h[k] = cnt[k];
-    h[4] = int32_t(H.ext.size());
-    h[5] = int32_t(H.lsl.size());
+    if (rings <= 3) {  // counts of rings 0..3, ext base, slice-table base
+      for (int k = 0; k < 4; ++k) h[k] = cnt[k];
+      h[4] = int32_t(H.ext.size());
+      h[5] = int32_t(H.lsl.size());
+    } else {  // counts of rings 0..5, ext base, slice-table base
+      for (int k = 0; k < 6; ++k) h[k] = cnt[k];
+      h[6] = int32_t(H.ext.size());
+      h[7] = int32_t(H.lsl.size());
+    }
     H.ext.insert(H.ext.end(), slots.begin() + cnt[0], slots.end());
     int ce = 0;
     for (int k = 0; k < ell_rings; ++k) ce += cnt[k];
@@ -352,6 +365,23 @@ static void build_tiles(Engine& E, const std::vector<int64_t>& arp, const std::v
     upload_tiles<T>(E, H, dec, E.n_rows, E.tl);
     E.tile_size = ts;
     E.has_tiles = true;
+    return;
+  }
+}
+
+// One-kernel-per-step path: tiles with five halo rings (four for the lumped
+// Kerr term) whose state, stage vectors and |psi|^2 phi fit 64 KB of LDS.
+template <typename T>
+static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
+                             const std::vector<double>& alw, const std::vector<double>& amw, bool dec) {
+  if (E.wmax > 12) return;
+  const int rings = dec ? 5 : 4;
+  HostTiles H;
+  for (int ts = E.tile_size; ts >= 64; ts /= 2) {
+    if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H)) continue;
+    if (size_t(H.max_slots) * 7 * sizeof(T) > 64 * 1024 || H.max_compute > 2 * 1024) continue;
+    upload_tiles<T>(E, H, dec, E.n_rows, E.stp);
+    E.has_step = true;
     return;
   }
 }
@@ -492,11 +522,14 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   E.h0c = static_cast<double*>(p);
   upload(E, p, perm);
   E.perm = static_cast<int32_t*>(p);
-  if (E.F == 1 && E.beta4 == 0.0) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  if (E.F == 1 && E.beta4 == 0.0) {
+    build_tiles<T>(E, arp, acol, alw, amw, any_dec);
+    build_step_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  }
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
   const size_t nv = size_t(n) * E.F;
   E.psi = E.dalloc(nv * 2 * sizeof(T));
-  if (E.has_tiles) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
+  if (E.has_tiles || E.has_step) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
   E.ya = E.dalloc(nv * 2 * sizeof(T));
   E.yb = E.dalloc(nv * 2 * sizeof(T));
   E.t = E.beta4 != 0.0 ? E.dalloc(nv * 2 * sizeof(T)) : nullptr;
@@ -581,9 +614,15 @@ static void z_step(const Engine& E, const DevOps<T>& d, double dz, double gamma,
   do_kerr<T>(E, d, E.psi, E.psi, E.s, tau_next, gamma, st);
 }
 
+// fused: 0 = five kernels per step, 1 = two tile kernels per step, 2 = one tile kernel per step
 template <typename T>
 static bool use_fused(const Engine& E) {
-  return E.has_tiles && E.fused;
+  return E.has_tiles && E.fused == 1;
+}
+
+template <typename T>
+static bool use_step(const Engine& E) {
+  return E.has_step && E.fused == 2;
 }
 
 // One fused middle z step: state cur (psi after NL) and y1 in ya -> next state in nxt, its y1 in ya.
@@ -594,28 +633,51 @@ static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl,
   launch_fused<T>(d, tl, FUSED_S4_NL_S1, E.yb, cur, nxt, E.ya, nullptr, dz, dz, gamma, E.tblock(), st);
 }
 
-// Steps captured per graph: the fused path alternates two state buffers, so
-// its graphs hold an even number of steps and start and end on psi2.
-static int graph_steps(const Engine& E, bool fused) { return fused ? std::max(2, E.spg / 2 * 2) : E.spg; }
+// Launch mode of the middle steps: 0 = five kernels, 1 = two tile kernels,
+// 2 = one tile kernel per step.
+template <typename T>
+static int mode_of(const Engine& E) {
+  return use_step<T>(E) ? 2 : (use_fused<T>(E) ? 1 : 0);
+}
+
+// State buffer holding the state before middle step k (modes 1 and 2
+// alternate two buffers; mode 1 starts on psi2, mode 2 on psi).
+static void* state_before(const Engine& E, int mode, int64_t k) {
+  if (mode == 0) return E.psi;
+  const bool odd = k % 2;
+  if (mode == 1) return odd ? E.psi : E.psi2;
+  return odd ? E.psi2 : E.psi;
+}
 
 template <typename T>
-static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, bool fused) {
-  const int tb = fused ? E.tblock() : 0;
+static void middle_step(const Engine& E, const DevOps<T>& d, int mode, int64_t k, double dz, double gamma,
+                        hipStream_t st) {
+  if (mode == 0) {
+    z_step<T>(E, d, dz, gamma, dz, st);
+  } else if (mode == 1) {
+    fused_mid<T>(E, d, E.tiles<T>(), state_before(E, 1, k), state_before(E, 1, k + 1), dz, gamma, st);
+  } else {
+    launch_step<T>(d, E.stp.template ops<T>(), state_before(E, 2, k), state_before(E, 2, k + 1), dz, dz, gamma,
+                   E.sblock(), st);
+  }
+}
+
+// Steps captured per graph: the tile paths alternate two state buffers, so
+// their graphs hold an even number of steps and end where they start.
+static int graph_steps(const Engine& E, int mode) { return mode ? std::max(2, E.spg / 2 * 2) : E.spg; }
+
+template <typename T>
+static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, int mode) {
+  const int tb = mode == 1 ? E.tblock() : (mode == 2 ? E.sblock() : 0);
   for (auto& g : E.graphs)
     if (g.dz == dz && g.gamma == gamma && g.spg == E.spg && g.block == E.block && g.xcd == E.xcd &&
-        g.fused == int(fused) && g.tile_block == tb)
+        g.fused == mode && g.tile_block == tb)
       return g.exec;
   const DevOps<T> d = E.ops<T>();
-  const TileOps<T> tl = E.tiles<T>();
   hipGraph_t graph;
   HIP_OK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
-  const int steps = graph_steps(E, fused);
-  for (int k = 0; k < steps; ++k) {
-    if (fused)
-      fused_mid<T>(E, d, tl, k % 2 ? E.psi : E.psi2, k % 2 ? E.psi2 : E.psi, dz, gamma, E.cap);
-    else
-      z_step<T>(E, d, dz, gamma, dz, E.cap);
-  }
+  const int steps = graph_steps(E, mode);
+  for (int k = 0; k < steps; ++k) middle_step<T>(E, d, mode, k, dz, gamma, E.cap);
   hipError_t le = hipGetLastError();
   HIP_OK(hipStreamEndCapture(E.cap, &graph));
   if (le != hipSuccess) fail(DEC_BPM_EHIP, std::string("launch during capture: ") + hipGetErrorString(le));
@@ -626,7 +688,7 @@ static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, bool fused) 
     (void)hipGraphDestroy(E.graphs.front().graph);
     E.graphs.erase(E.graphs.begin());
   }
-  E.graphs.push_back(GraphEntry{dz, gamma, E.spg, E.block, E.xcd, int(fused), tb, exec, graph});
+  E.graphs.push_back(GraphEntry{dz, gamma, E.spg, E.block, E.xcd, mode, tb, exec, graph});
   return exec;
 }
 
@@ -654,26 +716,19 @@ static void check_prop_args(const Engine& E, const void* field, double dz, int64
 }
 
 // Middle steps (merged NL(dz)) through graph replays, then the remainder
-// eagerly.  Fused path: enters and leaves with the state in psi2 when count is
-// even, in psi when odd; returns the buffer holding the state.
+// eagerly; returns the buffer holding the state.
 template <typename T>
 static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st) {
   const DevOps<T> d = E.ops<T>();
-  const bool fused = use_fused<T>(E);
-  const int gs = graph_steps(E, fused);
+  const int mode = mode_of<T>(E);
+  const int gs = graph_steps(E, mode);
   int64_t done = 0;
   if (E.spg > 1 && count >= gs) {
-    hipGraphExec_t ex = get_graph<T>(E, dz, gamma, fused);
+    hipGraphExec_t ex = get_graph<T>(E, dz, gamma, mode);
     for (; done + gs <= count; done += gs) HIP_OK(hipGraphLaunch(ex, st));
   }
-  if (!fused) {
-    for (; done < count; ++done) z_step<T>(E, d, dz, gamma, dz, st);
-    return E.psi;
-  }
-  const TileOps<T> tl = E.tiles<T>();
-  for (; done < count; ++done)
-    fused_mid<T>(E, d, tl, done % 2 ? E.psi : E.psi2, done % 2 ? E.psi2 : E.psi, dz, gamma, st);
-  return count % 2 ? E.psi : E.psi2;
+  for (; done < count; ++done) middle_step<T>(E, d, mode, done, dz, gamma, st);
+  return state_before(E, mode, count);
 }
 
 template <typename T>
@@ -681,8 +736,9 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
   if (n == 0) return;
   const DevOps<T> d = E.ops<T>();
   const int B = E.block;
+  const int mode = mode_of<T>(E);
   launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
-  if (use_fused<T>(E)) {
+  if (mode == 1) {
     const TileOps<T> tl = E.tiles<T>();
     // NL(dz/2) + stage 1: state -> psi2, y1 -> ya
     launch_fused<T>(d, tl, FUSED_NL_S1, nullptr, E.psi, E.psi2, E.ya, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
@@ -690,6 +746,14 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     void* nxt = cur == E.psi ? E.psi2 : E.psi;
     launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, cur, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), st);
     launch_fused<T>(d, tl, FUSED_S4_NL, E.yb, cur, nxt, nullptr, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
+    launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
+  } else if (mode == 2) {
+    // NL(dz/2) in place, n-1 merged steps, then LIN(dz) + NL(dz/2)
+    launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
+    launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
+    void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
+    void* nxt = cur == E.psi ? E.psi2 : E.psi;
+    launch_step<T>(d, E.stp.template ops<T>(), cur, nxt, dz, 0.5 * dz, gamma, E.sblock(), st);
     launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
   } else {
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
@@ -749,7 +813,7 @@ static void forward_ckpt_t(Engine& E, void* field, double dz, int64_t n, double 
   const int B = E.block;
   const size_t vb = (size_t(E.n_rows) * E.cplx_size() + 255) / 256 * 256;
   launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
-  if (n > 0 && use_fused<T>(E)) {
+  if (n > 0 && E.has_tiles && E.fused != 0) {
     const TileOps<T> tl = E.tiles<T>();
     const int TB = E.tblock();
     launch_copy<T>(E.n_rows, E.psi, ws + L.x0, B, st);
@@ -850,7 +914,7 @@ static void adjoint_t(Engine& E, const void* grad_out, double dz, int64_t n, dou
 // tile launches per step.
 template <typename T>
 static bool adjoint_fused_ok(const Engine& E) {
-  return use_fused<T>(E) && size_t(E.tl.max_slots) * 4 * 2 * sizeof(T) <= 64 * 1024;
+  return E.has_tiles && E.fused != 0 && size_t(E.tl.max_slots) * 4 * 2 * sizeof(T) <= 64 * 1024;
 }
 
 template <typename T>
@@ -910,14 +974,17 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   const double sr = sizeof(T), sc = 2 * sizeof(T);
   const double nF = double(E.n_rows) * E.F, nr = double(E.n_rows);
   const double mat = double(E.nnz_off) * (4.0 + sr);
+  const double mat_lm = double(E.nnz_off) * (4.0 + (E.mw ? 2 : 1) * sr);  // L and M share the pattern
   double by[DEC_BPM_NUM_KERNELS];
-  by[DEC_BPM_K_KERR] = mat + nr * 2 * sr + nF * (sr + 2 * sc);
+  by[DEC_BPM_K_KERR] = (E.mw ? mat : 0.0) + nr * 2 * sr + nF * (sr + 2 * sc);
   by[DEC_BPM_K_STAGE] = mat + nr * sr + nF * 3 * sc;
   by[DEC_BPM_K_LAP] = mat + nF * 2 * sc;
   // fused kernels, counted once per owned row (halo recompute is overhead, not algorithmic):
   // A reads y3, psi, v, w, M_pp and both operators; writes psi'' and y1.  B reads y1, psi, v, L; writes y3.
-  by[DEC_BPM_K_TILE_A] = double(E.nnz_off) * (4.0 + 2 * sr) + nr * 3 * sr + nr * 4 * sc;
+  // The one-kernel step reads psi, v, w, M_pp and both operators and writes psi.
+  by[DEC_BPM_K_TILE_A] = mat_lm + nr * 3 * sr + nr * 4 * sc;
   by[DEC_BPM_K_TILE_B] = mat + nr * sr + nr * 3 * sc;
+  by[DEC_BPM_K_STEP] = mat_lm + nr * 3 * sr + nr * 2 * sc;
   launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
   launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
   launch_fill<T>(d, E.yb, 0.2, -0.1, B, st);
@@ -929,7 +996,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   HIP_OK(hipEventCreate(&e1));
   for (int kind = 0; kind < DEC_BPM_NUM_KERNELS; ++kind) {
     const bool tile_kind = kind == DEC_BPM_K_TILE_A || kind == DEC_BPM_K_TILE_B;
-    if (tile_kind && !E.has_tiles) {
+    if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step)) {
       if (ms) ms[kind] = 0.0;
       if (bytes) bytes[kind] = 0.0;
       continue;
@@ -944,6 +1011,9 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
         launch_fused<T>(d, tl, FUSED_S4_NL_S1, E.yb, E.psi, E.psi2, E.ya, nullptr, dz, dz, gamma, E.tblock(), E.cap);
       if (kind == DEC_BPM_K_TILE_B)
         launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, E.psi, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), E.cap);
+      if (kind == DEC_BPM_K_STEP)
+        launch_step<T>(d, E.stp.template ops<T>(), r % 2 ? E.psi2 : E.psi, r % 2 ? E.psi : E.psi2, dz, dz, gamma,
+                       E.sblock(), E.cap);
     }
     HIP_OK(hipStreamEndCapture(E.cap, &g));
     hipGraphExec_t ex;
@@ -989,7 +1059,7 @@ static bool tune_cache_lookup(Engine& E) {
       E.block = b;
       E.spg = s;
       E.xcd = x;
-      E.fused = (E.has_tiles || E.has_btiles) ? fu : 0;
+      E.fused = (E.has_tiles || E.has_btiles || E.has_step) ? fu : 0;
       E.tile_block = tb;
       return true;
     }
@@ -1032,6 +1102,8 @@ static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
       for (int b : {64, 128, 256, 512, 1024}) cands.push_back({0, b, E.tile_block, s, x});
       if (E.has_tiles)
         for (int tb : {128, 256, 512, 1024}) cands.push_back({1, E.block, tb, s, x});
+      if (E.has_step)
+        for (int tb : {256, 512, 1024}) cands.push_back({2, E.block, tb, s, x});
       if (E.has_btiles) cands.push_back({1, E.block, E.tile_block, s, x});
     }
   hipEvent_t e0, e1;
@@ -1051,7 +1123,7 @@ static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
     launch_fill<T>(d0, E.ya, 0.3, 0.1, 256, st);
     launch_fill<T>(d0, E.yb, 0.3, 0.1, 256, st);
     launch_prep_s<T>(d0, E.psi, E.s, dz, 256, st);
-    run_middle<T>(E, graph_steps(E, use_fused<T>(E)), dz, gamma, st);  // warm-up (and graph instantiation)
+    run_middle<T>(E, graph_steps(E, mode_of<T>(E)), dz, gamma, st);  // warm-up (and graph instantiation)
     HIP_OK(hipEventRecord(e0, st));
     run_middle<T>(E, steps, dz, gamma, st);
     HIP_OK(hipEventRecord(e1, st));
@@ -1554,14 +1626,14 @@ int dec_bpm_batch_autotune(dec_bpm_batch_t b, double dz, double gamma, void* str
 static void get_tuning(const Engine& E, dec_bpm_tuning* t) {
   t->block_size = E.block;
   t->steps_per_graph = E.spg;
-  t->fused = (E.has_tiles || E.has_btiles) ? E.fused : 0;
+  t->fused = (E.has_tiles || E.has_btiles || E.has_step) ? E.fused : 0;
   t->tile_block = E.has_tiles ? E.tblock() : E.tile_block;
   t->xcd_remap = E.xcd;
 }
 
 static void set_tuning(Engine& E, const dec_bpm_tuning* t) {
   if (!t || t->block_size < 64 || t->block_size > 1024 || t->block_size % 64 || t->steps_per_graph < 1 ||
-      t->tile_block < 64 || t->tile_block > 1024 || t->tile_block % 64 || (t->fused != 0 && t->fused != 1) ||
+      t->tile_block < 64 || t->tile_block > 1024 || t->tile_block % 64 || (t->fused < 0 || t->fused > 2) ||
       (t->xcd_remap != 0 && t->xcd_remap != 1))
     fail(DEC_BPM_EINVAL, "bad tuning");
   E.block = t->block_size;

@@ -970,7 +970,7 @@ __global__ void __launch_bounds__(1024) k_fused(DevOps<T> d, TileOps<T> tl, cons
     T ar = T(0), ai = T(0);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
-      if (k < wd[j]) {
+      {  // padded slots: self column, zero weight
         const C vq = V_[q[j][k]];
         ar += cl[j][k] * (vr.x - vq.x);
         ai += cl[j][k] * (vr.y - vq.y);
@@ -989,7 +989,7 @@ __global__ void __launch_bounds__(1024) k_fused(DevOps<T> d, TileOps<T> tl, cons
     if (DEC) {
 #pragma unroll
       for (int k = 0; k < KMAX; ++k)
-        if (k < wd[j]) th += cm[j][k] * S[q[j][k]];
+        th += cm[j][k] * S[q[j][k]];
     }
     const T damp = d_exp(-ww[j] * tau);
     T sn, cs;
@@ -1062,6 +1062,152 @@ __global__ void __launch_bounds__(1024) k_fused(DevOps<T> d, TileOps<T> tl, cons
     for (int j = 0; j < J; ++j) {
       const int i = threadIdx.x + j * B;
       if (i < c0) out_y[rr[j]] = stage(Y, P, j, i, T(0.5) * h);
+    }
+  }
+}
+
+// ---- one kernel per z step on LDS tiles with five halo rings ----
+// The whole merged Strang step, LIN(h) then NL(tau): the four Horner stages
+// of RK4 and the Kerr/absorber flow, on a tile whose halo is wide enough for
+// every stage (stage k on rings 0..4-k; the triangle-averaged Kerr step of
+// ring 0 needs stage 4 on ring 1).  Input: the state after the previous
+// Kerr substep; output: the state after this one (owned rows).
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__(1024) k_step(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ in_psi,
+                                               typename CT<T>::C* __restrict__ out_psi, T h, T tau, T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int32_t* hd = tl.hdr + 8 * tile;
+  int cr[6];  // cr[k] = slots in rings 0..k
+  cr[0] = hd[0];
+#pragma unroll
+  for (int k = 1; k < 6; ++k) cr[k] = cr[k - 1] + hd[k];
+  const int32_t* __restrict__ ext = tl.ext + hd[6];
+  const int32_t* __restrict__ lsl = tl.lsl + hd[7];
+  const int64_t ebase = tl.ent_base[tile];
+  const int64_t row0 = tile * int64_t(tl.TS);
+  const int MS = tl.max_slots;
+  const int B = blockDim.x;
+  C* P = reinterpret_cast<C*>(smem);
+  C* X = P + MS;
+  C* Y = X + MS;
+  T* S = reinterpret_cast<T*>(Y + MS);
+  const int o = DEC ? 1 : 0;  // extra ring for the triangle-averaged Kerr gather
+  const int nLoad = cr[4 + o], n1 = cr[3 + o], n2 = cr[2 + o], n3 = cr[1 + o], n4 = cr[o], nNL = cr[0];
+  for (int i = threadIdx.x; i < nLoad; i += B) {
+    const int32_t r = i < cr[0] ? int32_t(row0 + i) : ext[i - cr[0]];
+    P[i] = in_psi[r];
+  }
+  int q[J][KMAX];
+  T cl[J][KMAX];
+  T cm[J][DEC ? KMAX : 1];
+  int wd[J];
+  int32_t rr[J];
+  T vv[J], ww[J], md[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    wd[j] = 0;
+    rr[j] = 0;
+    vv[j] = ww[j] = md[j] = T(0);
+    if (i < n1) {
+      const int32_t r = i < cr[0] ? int32_t(row0 + i) : ext[i - cr[0]];
+      rr[j] = r;
+      vv[j] = d.v[r];
+      ww[j] = d.w[r];
+      md[j] = d.mdiag[r];
+      const int32_t info = lsl[i >> 6];
+      wd[j] = info & 0xff;
+      const int64_t base = ebase + (info >> 8) + (i & 63);
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < wd[j]) {
+          q[j][k] = tl.lcol[base + 64 * k];
+          cl[j][k] = tl.llw[base + 64 * k];
+          if (DEC) cm[j][k] = tl.lmw[base + 64 * k];
+        } else {
+          q[j][k] = i;
+          cl[j][k] = T(0);
+          if (DEC) cm[j][k] = T(0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        q[j][k] = 0;
+        cl[j][k] = T(0);
+        if (DEC) cm[j][k] = T(0);
+      }
+    }
+  }
+  __syncthreads();
+  // P + coef * (-i) (p1 L v - V v) at register slot j, v gathered from V_
+  auto stage = [&](const C* V_, int j, int i, T coef) {
+    const C vr = V_[i];
+    T ar = T(0), ai = T(0);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      {  // padded slots: self column, zero weight
+        const C vq = V_[q[j][k]];
+        ar += cl[j][k] * (vr.x - vq.x);
+        ai += cl[j][k] * (vr.y - vq.y);
+      }
+    const T hr = d.p1 * ar - vv[j] * vr.x;
+    const T hi = d.p1 * ai - vv[j] * vr.y;
+    const C b = P[i];
+    C r;
+    r.x = b.x + coef * hi;
+    r.y = b.y - coef * hr;
+    return r;
+  };
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    if (i < n1) Y[i] = stage(P, j, i, T(0.25) * h);  // y1
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    if (i < n2) X[i] = stage(Y, j, i, h / T(3));  // y2
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    if (i < n3) Y[i] = stage(X, j, i, T(0.5) * h);  // y3
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    if (i < n4) {  // state before the Kerr substep
+      const C b = stage(Y, j, i, h);
+      X[i] = b;
+      S[i] = (b.x * b.x + b.y * b.y) * phi_w(ww[j], tau);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    if (i < nNL) {
+      T th = md[j] * S[i];
+      if (DEC) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          th += cm[j][k] * S[q[j][k]];
+      }
+      const T damp = d_exp(-ww[j] * tau);
+      T sn, cs;
+      d_sincos(gamma * th, &sn, &cs);
+      const C b = X[i];
+      C r;
+      r.x = damp * (b.x * cs - b.y * sn);
+      r.y = damp * (b.x * sn + b.y * cs);
+      out_psi[rr[j]] = r;
     }
   }
 }
@@ -1186,7 +1332,7 @@ __global__ void __launch_bounds__(1024) k_fused_adj(DevOps<T> d, TileOps<T> tl,
     T ar = T(0), ai = T(0);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
-      if (k < wd[j]) {
+      {  // padded slots: self column, zero weight
         const C vq = V_[q[j][k]];
         ar += cl[j][k] * (vr.x - vq.x);
         ai += cl[j][k] * (vr.y - vq.y);
@@ -1211,7 +1357,7 @@ __global__ void __launch_bounds__(1024) k_fused_adj(DevOps<T> d, TileOps<T> tl,
         if (DEC) {
 #pragma unroll
           for (int k = 0; k < KMAX; ++k)
-            if (k < wd[j]) {
+            {  // padded slots: self column, zero weight
               const C v = SM[q[j][k]];
               th += cm[j][k] * v.x;
               mm += cm[j][k] * v.y;
@@ -1529,6 +1675,27 @@ void launch_bkerr(const DevOps<T>& d, const TileOps<T>& tl, const void* psi_in, 
 }
 
 template <typename T>
+void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h, double tau,
+                 double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_STEP(KM, DEC, JJ)                                                                               \
+  hipLaunchKernelGGL((k_step<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi),     \
+                     DECBPM_M(T, out_psi), T(h), T(tau), T(gamma))
+#define DECBPM_STEP_J(KM, DEC) \
+  if (J <= 1) DECBPM_STEP(KM, DEC, 1); else DECBPM_STEP(KM, DEC, 2);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_STEP_J(8, true) } else { DECBPM_STEP_J(8, false) }
+  } else {
+    if (dec) { DECBPM_STEP_J(12, true) } else { DECBPM_STEP_J(12, false) }
+  }
+#undef DECBPM_STEP_J
+#undef DECBPM_STEP
+}
+
+template <typename T>
 void launch_perm_in(const DevOps<T>& d, const int32_t* perm, const void* src, void* dst, int scale_inv_h0, int block,
                     hipStream_t st) {
   const unsigned g = grid_for(d.n_rows * d.F, block, 0);
@@ -1656,6 +1823,8 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   template void launch_hcombine<T>(const DevOps<T>&, const void*, const void*, const void*, void*, int,           \
                                    hipStream_t);                                                                 \
   template void launch_set_v<T>(int64_t, const T*, const double*, const int32_t*, T*, int, hipStream_t);          \
+  template void launch_step<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double,   \
+                               int, hipStream_t);                                                                \
   template void launch_bstage<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*, void*, \
                                  double, void*, double, hipStream_t);                                            \
   template void launch_blap<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, hipStream_t);           \

@@ -159,6 +159,13 @@ template <typename T>
 void launch_bkerr(const DevOps<T>& d, const TileOps<T>& tl, const void* psi_in, void* psi_out, const void* s,
                   double tau, double gamma, hipStream_t st);
 
+// One kernel per merged Strang step on tiles with five halo rings (hdr holds
+// the six ring counts in [0..5], the ext and slice-table bases in [6], [7]):
+// out_psi = NL_tau(LIN_h(in_psi)) on the owned rows.
+template <typename T>
+void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h, double tau,
+                 double gamma, int block, hipStream_t st);
+
 // out_rec (may be null) receives, for owned rows, y2 (FUSED_S2_S3) or the
 // state before the Kerr substep (S4 kinds): the adjoint's segment recompute.
 template <typename T>

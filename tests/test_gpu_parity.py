@@ -389,6 +389,41 @@ def test_fused_tile_path_matches_unfused_and_oracle(dtype, nl):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_one_kernel_step_matches_unfused_and_oracle(dtype, nl):
+    """The one-kernel z step (four stages + Kerr/absorber on a tile with five
+    halo rings in LDS) against the five-kernel step and the oracle."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    say("step kernel", dtype, nl, w.mesh.n_vert)
+    ops = oracle_ops(w, nl)
+    m = lib_mesh(w, dtype, nl)
+    m.tuning = {"fused": 2}
+    assert m.tuning["fused"] == 2
+    u = dev(w.u0, dtype)
+    for n in (1, 2, 3, 37, 64):
+        outs = {}
+        for fused, spg in ((2, 1), (2, 16), (0, 16)):
+            m.tuning = {"fused": fused, "steps_per_graph": spg}
+            f = u.clone()
+            m.propagate(f, w.dz, n, w.gamma)
+            outs[(fused, spg)] = host(f)
+        assert np.array_equal(outs[(2, 1)], outs[(2, 16)]), n  # graph replay == eager
+        tol = 1e-13 if dtype == "c128" else 1e-5
+        assert rel(outs[(2, 16)], outs[(0, 16)]) < tol, (n, rel(outs[(2, 16)], outs[(0, 16)]))
+        ref = S.propagate(w.u0, ops, w.dz, n, w.gamma)
+        assert rel(outs[(2, 16)], ref) < GATE[dtype], n
+        if n == 37:
+            keep = outs[(2, 16)]
+    for tb in (256, 512, 1024):  # threads per tile do not change the arithmetic
+        m.tuning = {"fused": 2, "tile_block": tb, "steps_per_graph": 16}
+        f = u.clone()
+        m.propagate(f, w.dz, 37, w.gamma)
+        assert np.array_equal(host(f), keep), tb
+    times = m.time_kernels(w.dz, w.gamma, reps=20)
+    assert times["step"]["ms"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
 def test_fused_adjoint_matches_unfused_and_oracle(dtype, nl):
     """The tile-fused checkpointed forward and adjoint against the five-kernel
     path and the FP64 oracle gradients (field and index perturbation)."""
