@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the DEC beam-propagation hot path on one MI355X.
 
-A "step" is one z step of the whole hot path (merged Strang step: Kerr +
-absorber substep, four fused RK4 stage kernels of the DEC Laplacian) over the
+A "step" is one z step of the whole hot path (merged Strang step: the four RK4
+stages of the DEC linear operator and the Kerr + absorber substep) over the
 step-index workload: graded disk of radius 40 with ~250k vertices, core of
 radius 5 with index contrast 1, absorber ring r > 35 (quadratic up to 0.5),
 tilted elliptic Gaussian launch (waists 2 and 4, 30 degrees, amplitude 1.2),
@@ -11,9 +11,11 @@ dz = 5e-4, gamma = 1, complex64.  The metric is vertex z-steps per second
 kernels run on, inputs already resident in HBM.
 
 Also reported on the same JSON line:
-  roofline      the RK4 stage kernel (4 of 5 launches per step): algorithmic
-                bytes per launch / mean launch time (HIP events over
-                graph-captured back-to-back launches) against 8 TB/s
+  roofline      the dominant kernel of the tuned launch mode (for the one-kernel
+                step: the step kernel itself): algorithmic bytes per launch /
+                mean launch time (HIP events over graph-captured back-to-back
+                launches on the library's stream) against 8 TB/s; traffic from
+                the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary
   cpu_baseline  the FP64 CPU oracle on the same mesh and launch, a bounded
                 prefix of steps, single thread
   parity        GPU vs oracle after the same prefix (relative L2)
@@ -48,6 +50,48 @@ def cpu_model():
     return platform.processor()
 
 
+COPY_BYTES = 256 << 20
+
+# kernel class timed for the roofline of each launch mode: the kernel that
+# takes most of a z step (mode 0: four RK4 stage launches of five; mode 1: the
+# larger of the two tile kernels; mode 2: the only kernel; mode 3: the
+# persistent launch, per z step)
+_DOMINANT = {0: ("stage", "k_stage (RK4 stage: L gather + stage update)", 4),
+             1: ("tile_a", "k_fused (stage 4 + Kerr/absorber + next stage 1 on 3-ring LDS tiles)", 1),
+             2: ("step", "k_step (whole z step: 4 RK4 stages + Kerr/absorber on 5-ring LDS tiles)", 1),
+             3: ("persist", "k_persist (persistent cooperative z stepping, per step)", 1)}
+
+
+def dominant_kernel_roofline(mode, kt):
+    cls, name, per_step = _DOMINANT[int(mode)]
+    k = kt[cls]
+    achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "kernel_class": cls, "achieved": achieved, "peak": 8000.0,
+            "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None, "bytes_per_launch": k["bytes"],
+            "launch_us": k["ms"] * 1e3, "launches_per_step": per_step,
+            "kernels_us": {c: v["ms"] * 1e3 for c, v in kt.items() if v["ms"] > 0}}
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of the kernel class from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"k_{cls}_step_index_250k_pmc.md")
+    src = os.path.join(ROOT, "paper_2608_03587_amd", "csrc", "kernels.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None, None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)\s+kernels_hip_sha256_16:\s*([0-9a-f]+)", text)
+    if not m:
+        return None, None
+    if m.group(2) != digest:
+        return None, f"{os.path.basename(path)} (stale: kernel sources changed since the counters were taken)"
+    return float(m.group(1)), os.path.basename(path)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +102,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="only the timed propagation (for rocprofv3)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="with --profile: also run a 256 MiB device copy (traffic counter calibration)")
     ap.add_argument("--tuning", default="", help="fixed launch shape as JSON (skips autotuning), e.g. the "
                                                  "config.tuning of a previous run")
     args = ap.parse_args()
@@ -111,19 +157,20 @@ def main():
     value = N * args.steps / (ms * 1e-3)
     log(f"[bench] {args.dtype}: {args.steps} steps in {ms:.2f} ms -> {value:.4e} vertex z-steps/s")
     if args.profile:
-        print(json.dumps({"metric": "vertex z-steps/s", "value": value, "profile_only": True}))
+        if args.calibrate_copy:  # a plain copy of known size, for scaling the traffic counters
+            src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"metric": "vertex z-steps/s", "value": value, "profile_only": True,
+                          "tuning": m.tuning}))
         return
 
     kt = m.time_kernels(w.dz, w.gamma, reps=200)
-    st = kt["stage"]
-    achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
-    log(f"[bench] kernel means (ms): " + ", ".join(f"{k} {v['ms'] * 1e3:.2f}us" for k, v in kt.items()))
-    roofline = {"bound": "hbm", "kernel": "k_stage (RK4 stage: L gather + stage update)",
-                "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
-                "traffic": None, "bytes_per_launch": st["bytes"], "launch_us": st["ms"] * 1e3,
-                "kernels_us": {k: v["ms"] * 1e3 for k, v in kt.items()},
-                "working_set_MB": None}
-
+    log(f"[bench] kernel means: " + ", ".join(f"{k} {v['ms'] * 1e3:.2f}us" for k, v in kt.items()))
+    roofline = dominant_kernel_roofline(m.tuning["fused"], kt)
+    roofline["traffic"], roofline["traffic_source"] = measured_traffic(roofline["kernel_class"])
     out = {
         "metric": "vertex z-steps/s",
         "value": value,
@@ -181,9 +228,11 @@ def main():
         try:
             m2 = make(other)
             ms2, _ = timed_propagate(m2, other, args.steps, args.warmup)
-            kt2 = m2.time_kernels(w.dz, w.gamma, reps=200)["stage"]
+            kt2 = m2.time_kernels(w.dz, w.gamma, reps=200)
+            r2 = dominant_kernel_roofline(m2.tuning["fused"], kt2)
             extras[other] = {"value": N * args.steps / (ms2 * 1e-3), "ms_per_step": ms2 / args.steps,
-                             "stage_GBps": kt2["bytes"] / (kt2["ms"] * 1e-3) / 1e9, "tuning": m2.tuning}
+                             "roofline": {k: r2[k] for k in ("kernel", "achieved", "frac", "launch_us")},
+                             "tuning": m2.tuning}
             log(f"[bench] {other}: {extras[other]['value']:.4e} vertex z-steps/s")
             del m2
         except Exception as e:  # noqa: BLE001
@@ -249,12 +298,35 @@ def bench_batched(api, W, torch, dev, tdt):
         m.propagate(g, dz, n_steps, 1.0)
         same &= bool(torch.equal(ref, g))
         max_rel_unfused = max(max_rel_unfused, float(torch.linalg.norm(ref - g) / torch.linalg.norm(ref)))
+    # conditioning of the workload (the launches are supercritical for some fields): the same field
+    # of the largest mesh in complex64 and complex128 after the full length, and batched vs plain
+    # after a short prefix, where rounding differences have not yet been amplified
+    big = max(range(len(ws)), key=lambda i: ws[i].mesh.n_vert)
+    x = ws[big]
+    m128 = api.Mesh(x.mesh.xy, x.mesh.tri, x.index_tri, x.absorber, dtype="c128")
+    f128 = torch.from_numpy(x.u0[0]).to(dev, tdt["c128"])
+    m128.propagate(f128, dz, n_steps, 1.0)
+    f64 = torch.from_numpy(x.u0[0]).to(dev, tdt["c64"])
+    meshes[big].propagate(f64, dz, n_steps, 1.0)
+    c64_vs_c128 = float(torch.linalg.norm(f64.to(torch.complex128) - f128) / torch.linalg.norm(f128))
+    del m128
+    short = 100
+    p = packed0.clone()
+    batch.propagate(p, dz, short, 1.0)
+    prefix_rel = 0.0
+    for m, x, o in zip(meshes, ws, batch.unpack(p)):
+        f = torch.from_numpy(x.u0[0]).to(dev, tdt["c64"])
+        m.propagate(f, dz, short, 1.0)
+        r = o[0].contiguous()
+        prefix_rel = max(prefix_rel, float(torch.linalg.norm(r - f) / torch.linalg.norm(r)))
     kt = batch.time_kernels(dz, 1.0, reps=20)["stage"]
     res = {"vertex_field_steps_per_s": vf * n_steps / (t_b * 1e-3), "ms": t_b,
            "plain_ms_extrapolated": t_plain, "speedup_vs_plain": t_plain / t_b,
            "stage_GBps": kt["bytes"] / (kt["ms"] * 1e-3) / 1e9, "stage_frac_hbm": kt["bytes"] / (kt["ms"] * 1e-3) / 8e12,
            "batched_equals_unfused_plain_bitwise": same, "max_rel_vs_unfused_plain": max_rel_unfused,
-           "max_rel_vs_tuned_plain": max_rel, "fields": F * len(ws), "vertex_fields": vf, "steps": n_steps,
+           "max_rel_vs_tuned_plain": max_rel, f"max_rel_vs_tuned_plain_after_{short}_steps": prefix_rel,
+           "largest_mesh_field0_c64_vs_c128_full_length": c64_vs_c128,
+           "fields": F * len(ws), "vertex_fields": vf, "steps": n_steps,
            "note": "plain = 8 fields (one per mesh) timed at full length x 32"}
     log(f"[bench] batched: {res['vertex_field_steps_per_s']:.3e} vertex-field z-steps/s, "
         f"{res['speedup_vs_plain']:.1f}x plain, bitwise equal {same}")

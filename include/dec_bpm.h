@@ -230,13 +230,21 @@ int dec_bpm_batch_propagate(dec_bpm_batch_t b, void* packed_fields, double dz, i
  * runs two kernels per z step (stages 2+3, and stage 4 + Kerr/absorber + next
  * stage 1, each on a tile of rows with three halo rings in LDS); fused = 2
  * runs the whole z step (four stages + Kerr/absorber) as one kernel on tiles
- * with five halo rings (four for the lumped nonlinearity).  A handle that has
- * no tiles for the requested mode runs the unfused kernels.
+ * with five halo rings (four for the lumped nonlinearity); fused = 3 runs all
+ * middle steps of a propagate in one persistent cooperative launch on those
+ * tiles, every tile resident with its operator rows in registers, tiles
+ * synchronising with their neighbour tiles only (available when all tiles fit
+ * on the device at once; otherwise fused = 3 runs as fused = 2).  A handle
+ * that has no tiles for the requested mode runs the unfused kernels.  A
+ * persistent neighbour wait that exceeds its bound (DEC_BPM_SPIN_LIMIT polls,
+ * default 2^20) leaves the launch early and makes the next
+ * dec_bpm_check_finite report DEC_BPM_ENONFINITE.
  */
 typedef struct {
   int32_t block_size;       /* threads per workgroup of the unfused kernels      */
   int32_t steps_per_graph;  /* z steps per captured hipGraph (1 = no graph)      */
-  int32_t fused;            /* 0: unfused, 1: two tile kernels, 2: one per step  */
+  int32_t fused;            /* 0 unfused, 1 two tile kernels, 2 one kernel per    */
+                            /* step, 3 persistent launch                          */
   int32_t tile_block;       /* threads per workgroup of the fused kernels        */
   int32_t xcd_remap;        /* 1: consecutive row blocks on one XCD               */
 } dec_bpm_tuning;
@@ -263,7 +271,8 @@ enum {
   DEC_BPM_K_TILE_A = 3,   /* fused tile kernel: stage 4 + Kerr/absorber + stage 1 */
   DEC_BPM_K_TILE_B = 4,   /* fused tile kernel: stages 2 + 3                      */
   DEC_BPM_K_STEP = 5,     /* one-kernel z step: four stages + Kerr/absorber       */
-  DEC_BPM_NUM_KERNELS = 6
+  DEC_BPM_K_PERSIST = 6,  /* persistent launch: time and bytes per z step         */
+  DEC_BPM_NUM_KERNELS = 7
 };
 int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
                          void* stream);

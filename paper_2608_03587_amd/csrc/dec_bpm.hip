@@ -99,11 +99,19 @@ struct Engine {
   // tiles of the fused path (F = 1, beta4 = 0) and of the batched path (F > 1)
   bool has_tiles = false;
   bool has_btiles = false;
-  int fused = 1;      // use the fused kernels when tiles exist
+  int fused = -1;     // launch mode (-1: chosen after the tiles are built)
   int tile_size = 512;
   int tile_block = 256;
   DevTiles tl, bt, stp;  // two-kernel tiles (3 rings), batched tiles, one-kernel-step tiles (5 rings)
   bool has_step = false;
+  int step_tile = 1024;  // rows per tile of the one-kernel step (largest that fits)
+  // persistent stepping on the step tiles: neighbour-tile lists, flags, wait bound
+  bool has_persist = false;
+  int32_t* nb_ptr = nullptr;
+  int32_t* nb_list = nullptr;
+  int32_t* pflags = nullptr;
+  int spin_limit = 1 << 20;
+  int persist_cap_block = -1, persist_cap = 0;  // resident workgroups at that block size
   void* psi2 = nullptr;
   // work
   void* psi = nullptr;
@@ -210,7 +218,9 @@ struct Engine {
 // Default launch shape from the environment (used before any autotuning).
 static void env_defaults(Engine& E) {
   if (const char* s = std::getenv("DEC_BPM_TILE")) E.tile_size = std::max(64, std::min(4096, std::atoi(s)));
-  if (const char* s = std::getenv("DEC_BPM_FUSED")) E.fused = std::max(0, std::min(2, std::atoi(s)));
+  if (const char* s = std::getenv("DEC_BPM_STEP_TILE")) E.step_tile = std::max(64, std::min(4096, std::atoi(s)));
+  if (const char* s = std::getenv("DEC_BPM_SPIN_LIMIT")) E.spin_limit = std::max(0, std::atoi(s));
+  if (const char* s = std::getenv("DEC_BPM_FUSED")) E.fused = std::max(0, std::min(3, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_BLOCK")) E.block = std::max(64, std::min(1024, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_STEPS_PER_GRAPH")) E.spg = std::max(1, std::atoi(s));
   if (const char* s = std::getenv("DEC_BPM_XCD_REMAP")) E.xcd = std::atoi(s) ? 1 : 0;
@@ -377,13 +387,42 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
   if (E.wmax > 12) return;
   const int rings = dec ? 5 : 4;
   HostTiles H;
-  for (int ts = E.tile_size; ts >= 64; ts /= 2) {
+  for (int ts = E.step_tile; ts >= 64; ts /= 2) {
     if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H)) continue;
     if (size_t(H.max_slots) * 7 * sizeof(T) > 64 * 1024 || H.max_compute > 2 * 1024) continue;
     upload_tiles<T>(E, H, dec, E.n_rows, E.stp);
     E.has_step = true;
-    return;
+    E.step_tile = ts;
+    break;
   }
+  if (!E.has_step) return;
+  // tiles owning the halo rows of each tile (the persistent kernel's wait set)
+  std::vector<int32_t> ptr(H.nt + 1, 0), list, seen(H.nt, -1);
+  bool fits = true;
+  for (int64_t t = 0; t < H.nt; ++t) {
+    const int32_t* h = &H.hdr[t * 8];
+    int32_t halo = 0;
+    for (int k = 1; k < 6; ++k) halo += h[k];
+    int cnt = 0;
+    for (int32_t i = 0; i < halo; ++i) {
+      const int32_t u = int32_t(H.ext[h[6] + i] / H.TS);
+      if (u == t || seen[u] == int32_t(t)) continue;
+      seen[u] = int32_t(t);
+      list.push_back(u);
+      ++cnt;
+    }
+    if (cnt > 64) fits = false;
+    ptr[t + 1] = int32_t(list.size());
+  }
+  if (!fits) return;
+  if (list.empty()) list.push_back(0);
+  void* p;
+  upload(E, p, ptr);
+  E.nb_ptr = static_cast<int32_t*>(p);
+  upload(E, p, list);
+  E.nb_list = static_cast<int32_t*>(p);
+  E.pflags = static_cast<int32_t*>(E.dalloc(size_t(H.nt) * sizeof(int32_t)));
+  E.has_persist = true;
 }
 
 // Batched path: tiles of one halo ring whose field values (all F fields of
@@ -549,6 +588,7 @@ static void build_engine(Engine& E, const std::vector<const Assembled*>& meshes,
     build_engine_t<float>(E, meshes, lumped);
   else
     build_engine_t<double>(E, meshes, lumped);
+  if (E.fused < 0) E.fused = E.has_step ? 2 : ((E.has_tiles || E.has_btiles) ? 1 : 0);
 }
 
 static void check_launch() {
@@ -625,6 +665,24 @@ static bool use_step(const Engine& E) {
   return E.has_step && E.fused == 2;
 }
 
+// Persistent stepping needs every step tile resident at once.
+template <typename T>
+static bool persist_fits(Engine& E) {
+  if (!E.has_persist) return false;
+  const int b = E.sblock();
+  if (E.persist_cap_block != b) {
+    E.persist_cap = persist_capacity<T>(E.ops<T>(), E.stp.template ops<T>(), b);
+    E.persist_cap_block = b;
+  }
+  const int64_t grid = E.xcd ? (int64_t(E.stp.n_tiles) + 7) / 8 * 8 : E.stp.n_tiles;  // as launched
+  return E.persist_cap >= grid;
+}
+
+template <typename T>
+static bool use_persist(Engine& E) {
+  return E.fused == 3 && persist_fits<T>(E);
+}
+
 // One fused middle z step: state cur (psi after NL) and y1 in ya -> next state in nxt, its y1 in ya.
 template <typename T>
 static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl, void* cur, void* nxt, double dz,
@@ -634,9 +692,12 @@ static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl,
 }
 
 // Launch mode of the middle steps: 0 = five kernels, 1 = two tile kernels,
-// 2 = one tile kernel per step.
+// 2 = one tile kernel per step, 3 = one persistent launch for all of them
+// (modes whose tiles are missing fall back to the five kernels).
 template <typename T>
-static int mode_of(const Engine& E) {
+static int mode_of(Engine& E) {
+  if (use_persist<T>(E)) return 3;
+  if (E.fused == 3 && E.has_step) return 2;
   return use_step<T>(E) ? 2 : (use_fused<T>(E) ? 1 : 0);
 }
 
@@ -646,7 +707,7 @@ static void* state_before(const Engine& E, int mode, int64_t k) {
   if (mode == 0) return E.psi;
   const bool odd = k % 2;
   if (mode == 1) return odd ? E.psi : E.psi2;
-  return odd ? E.psi2 : E.psi;
+  return odd ? E.psi2 : E.psi;  // modes 2 and 3
 }
 
 template <typename T>
@@ -721,6 +782,18 @@ template <typename T>
 static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st) {
   const DevOps<T> d = E.ops<T>();
   const int mode = mode_of<T>(E);
+  if (mode == 3) {
+    const int64_t chunk = int64_t(1) << 30;  // steps per launch (the parity of each chunk start is even)
+    for (int64_t done = 0; done < count; done += chunk) {
+      const int32_t k = int32_t(std::min(chunk, count - done));
+      void* b0 = state_before(E, 3, done);
+      void* b1 = b0 == E.psi ? E.psi2 : E.psi;
+      hipError_t e = launch_persist<T>(d, E.stp.template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, E.pflags, E.flag, k,
+                                       E.spin_limit, dz, gamma, E.sblock(), st);
+      if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+    }
+    return state_before(E, 3, count);
+  }
   const int gs = graph_steps(E, mode);
   int64_t done = 0;
   if (E.spg > 1 && count >= gs) {
@@ -747,7 +820,7 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, cur, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), st);
     launch_fused<T>(d, tl, FUSED_S4_NL, E.yb, cur, nxt, nullptr, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
     launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
-  } else if (mode == 2) {
+  } else if (mode >= 2) {
     // NL(dz/2) in place, n-1 merged steps, then LIN(dz) + NL(dz/2)
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
     launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
@@ -985,6 +1058,9 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   by[DEC_BPM_K_TILE_A] = mat_lm + nr * 3 * sr + nr * 4 * sc;
   by[DEC_BPM_K_TILE_B] = mat + nr * sr + nr * 3 * sc;
   by[DEC_BPM_K_STEP] = mat_lm + nr * 3 * sr + nr * 2 * sc;
+  // persistent stepping, per z step: the same algorithmic bytes as the one-kernel step (the
+  // implementation keeps the operator rows on chip, the algorithm still needs them every step)
+  by[DEC_BPM_K_PERSIST] = by[DEC_BPM_K_STEP];
   launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
   launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
   launch_fill<T>(d, E.yb, 0.2, -0.1, B, st);
@@ -996,9 +1072,25 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   HIP_OK(hipEventCreate(&e1));
   for (int kind = 0; kind < DEC_BPM_NUM_KERNELS; ++kind) {
     const bool tile_kind = kind == DEC_BPM_K_TILE_A || kind == DEC_BPM_K_TILE_B;
-    if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step)) {
+    if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step) ||
+        (kind == DEC_BPM_K_PERSIST && !(E.has_persist && persist_fits<T>(E)))) {
       if (ms) ms[kind] = 0.0;
       if (bytes) bytes[kind] = 0.0;
+      continue;
+    }
+    if (kind == DEC_BPM_K_PERSIST) {  // one launch of `reps` steps, time per step
+      const TileOps<T> sp = E.stp.template ops<T>();
+      HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, 2, E.spin_limit, dz, gamma,
+                               E.sblock(), st));  // warm-up
+      HIP_OK(hipEventRecord(e0, st));
+      HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, reps, E.spin_limit, dz,
+                               gamma, E.sblock(), st));
+      HIP_OK(hipEventRecord(e1, st));
+      HIP_OK(hipEventSynchronize(e1));
+      float t = 0;
+      HIP_OK(hipEventElapsedTime(&t, e0, e1));
+      if (ms) ms[kind] = double(t) / reps;
+      if (bytes) bytes[kind] = by[kind];
       continue;
     }
     hipGraph_t g;
@@ -1038,7 +1130,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
 static std::string tune_key(const Engine& E) {
   std::ostringstream o;
   o << "n" << E.n_rows << "_e" << E.n_entries << "_F" << E.F << "_d" << E.dtype << "_b4" << (E.beta4 != 0.0) << "_nl"
-    << (E.mw ? 0 : 1) << "_ts" << (E.has_tiles ? E.tile_size : 0);
+    << (E.mw ? 0 : 1) << "_ts" << (E.has_tiles ? E.tile_size : 0) << "_st" << (E.has_step ? E.step_tile : 0);
   return o.str();
 }
 
@@ -1104,6 +1196,8 @@ static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
         for (int tb : {128, 256, 512, 1024}) cands.push_back({1, E.block, tb, s, x});
       if (E.has_step)
         for (int tb : {256, 512, 1024}) cands.push_back({2, E.block, tb, s, x});
+      if (E.has_persist && s == 32)  // one launch runs every step: steps per graph do not apply
+        for (int tb : {256, 512, 1024}) cands.push_back({3, E.block, tb, s, x});
       if (E.has_btiles) cands.push_back({1, E.block, E.tile_block, s, x});
     }
   hipEvent_t e0, e1;
@@ -1118,6 +1212,7 @@ static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
     E.tile_block = c.tile_block;
     E.spg = c.spg;
     E.xcd = c.xcd;
+    if (c.fused == 3 && !persist_fits<T>(E)) continue;
     launch_fill<T>(d0, E.psi, 0.3, 0.1, 256, st);
     if (E.psi2) launch_fill<T>(d0, E.psi2, 0.3, 0.1, 256, st);
     launch_fill<T>(d0, E.ya, 0.3, 0.1, 256, st);
@@ -1431,7 +1526,8 @@ int dec_bpm_check_finite(dec_bpm_t h, void* stream) {
   if (f) {
     HIP_OK(hipMemsetAsync(E.flag, 0, sizeof(int), st));
     HIP_OK(hipStreamSynchronize(st));
-    fail(DEC_BPM_ENONFINITE, "a propagated field contains NaN or Inf");
+    fail(DEC_BPM_ENONFINITE, (f & 2) ? "a persistent launch timed out waiting for a neighbour tile (its output is invalid)"
+                                      : "a propagated field contains NaN or Inf");
   }
   ABI_CATCH
 }
@@ -1633,7 +1729,7 @@ static void get_tuning(const Engine& E, dec_bpm_tuning* t) {
 
 static void set_tuning(Engine& E, const dec_bpm_tuning* t) {
   if (!t || t->block_size < 64 || t->block_size > 1024 || t->block_size % 64 || t->steps_per_graph < 1 ||
-      t->tile_block < 64 || t->tile_block > 1024 || t->tile_block % 64 || (t->fused < 0 || t->fused > 2) ||
+      t->tile_block < 64 || t->tile_block > 1024 || t->tile_block % 64 || (t->fused < 0 || t->fused > 3) ||
       (t->xcd_remap != 0 && t->xcd_remap != 1))
     fail(DEC_BPM_EINVAL, "bad tuning");
   E.block = t->block_size;

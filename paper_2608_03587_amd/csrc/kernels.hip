@@ -1072,88 +1072,88 @@ __global__ void __launch_bounds__(1024) k_fused(DevOps<T> d, TileOps<T> tl, cons
 // every stage (stage k on rings 0..4-k; the triangle-averaged Kerr step of
 // ring 0 needs stage 4 on ring 1).  Input: the state after the previous
 // Kerr substep; output: the state after this one (owned rows).
+// One tile of the one-kernel z step: the operator rows of its compute slots
+// in registers (J slots per thread), the LIN(h) stages in Horner form on the
+// LDS-staged state, then the Kerr/absorber flow over tau on the owned rows.
+// Rings: the state is staged on rings 0..4+o (o = 1 for the triangle-averaged
+// Kerr gather, 0 for the lumped one), each stage shrinks the valid region by
+// one ring.  Padded ELL entries point at their own slot with weight zero, so
+// the neighbour loops run to KMAX unconditionally.
 template <typename T, int KMAX, bool DEC, int J>
-__global__ void __launch_bounds__(1024) k_step(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ in_psi,
-                                               typename CT<T>::C* __restrict__ out_psi, T h, T tau, T gamma) {
+struct StepTile {
   using C = typename CT<T>::C;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int64_t tile = logical_block(d.xcd_remap);
-  if (tile >= tl.n_tiles) return;
-  const int32_t* hd = tl.hdr + 8 * tile;
-  int cr[6];  // cr[k] = slots in rings 0..k
-  cr[0] = hd[0];
-#pragma unroll
-  for (int k = 1; k < 6; ++k) cr[k] = cr[k - 1] + hd[k];
-  const int32_t* __restrict__ ext = tl.ext + hd[6];
-  const int32_t* __restrict__ lsl = tl.lsl + hd[7];
-  const int64_t ebase = tl.ent_base[tile];
-  const int64_t row0 = tile * int64_t(tl.TS);
-  const int MS = tl.max_slots;
-  const int B = blockDim.x;
-  C* P = reinterpret_cast<C*>(smem);
-  C* X = P + MS;
-  C* Y = X + MS;
-  T* S = reinterpret_cast<T*>(Y + MS);
-  const int o = DEC ? 1 : 0;  // extra ring for the triangle-averaged Kerr gather
-  const int nLoad = cr[4 + o], n1 = cr[3 + o], n2 = cr[2 + o], n3 = cr[1 + o], n4 = cr[o], nNL = cr[0];
-  for (int i = threadIdx.x; i < nLoad; i += B) {
-    const int32_t r = i < cr[0] ? int32_t(row0 + i) : ext[i - cr[0]];
-    P[i] = in_psi[r];
-  }
+  int nLoad, n1, n2, n3, n4, nNL, c0;
+  int64_t row0;
+  const int32_t* ext;
   int q[J][KMAX];
   T cl[J][KMAX];
   T cm[J][DEC ? KMAX : 1];
-  int wd[J];
   int32_t rr[J];
   T vv[J], ww[J], md[J];
+
+  __device__ int32_t slot_row(int i) const { return i < c0 ? int32_t(row0 + i) : ext[i - c0]; }
+
+  __device__ void init(const DevOps<T>& d, const TileOps<T>& tl, int64_t tile) {
+    const int32_t* hd = tl.hdr + 8 * tile;
+    int cr[6];  // cr[k] = slots in rings 0..k
+    cr[0] = hd[0];
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int i = threadIdx.x + j * B;
-    wd[j] = 0;
-    rr[j] = 0;
-    vv[j] = ww[j] = md[j] = T(0);
-    if (i < n1) {
-      const int32_t r = i < cr[0] ? int32_t(row0 + i) : ext[i - cr[0]];
-      rr[j] = r;
-      vv[j] = d.v[r];
-      ww[j] = d.w[r];
-      md[j] = d.mdiag[r];
-      const int32_t info = lsl[i >> 6];
-      wd[j] = info & 0xff;
-      const int64_t base = ebase + (info >> 8) + (i & 63);
+    for (int k = 1; k < 6; ++k) cr[k] = cr[k - 1] + hd[k];
+    ext = tl.ext + hd[6];
+    const int32_t* __restrict__ lsl = tl.lsl + hd[7];
+    const int64_t ebase = tl.ent_base[tile];
+    row0 = tile * int64_t(tl.TS);
+    c0 = cr[0];
+    const int o = DEC ? 1 : 0;
+    nLoad = cr[4 + o];
+    n1 = cr[3 + o];
+    n2 = cr[2 + o];
+    n3 = cr[1 + o];
+    n4 = cr[o];
+    nNL = cr[0];
+    const int B = blockDim.x;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      rr[j] = 0;
+      vv[j] = ww[j] = md[j] = T(0);
+      int wd = 0;
+      int64_t base = 0;
+      if (i < n1) {
+        const int32_t r = slot_row(i);
+        rr[j] = r;
+        vv[j] = d.v[r];
+        ww[j] = d.w[r];
+        md[j] = d.mdiag[r];
+        const int32_t info = lsl[i >> 6];
+        wd = info & 0xff;
+        base = ebase + (info >> 8) + (i & 63);
+      }
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) {
-        if (k < wd[j]) {
+        if (k < wd) {
           q[j][k] = tl.lcol[base + 64 * k];
           cl[j][k] = tl.llw[base + 64 * k];
           if (DEC) cm[j][k] = tl.lmw[base + 64 * k];
         } else {
-          q[j][k] = i;
+          q[j][k] = i < n1 ? i : 0;
           cl[j][k] = T(0);
           if (DEC) cm[j][k] = T(0);
         }
       }
-    } else {
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        q[j][k] = 0;
-        cl[j][k] = T(0);
-        if (DEC) cm[j][k] = T(0);
-      }
     }
   }
-  __syncthreads();
+
   // P + coef * (-i) (p1 L v - V v) at register slot j, v gathered from V_
-  auto stage = [&](const C* V_, int j, int i, T coef) {
+  __device__ C stage(const DevOps<T>& d, const C* P, const C* V_, int j, int i, T coef) const {
     const C vr = V_[i];
     T ar = T(0), ai = T(0);
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-      {  // padded slots: self column, zero weight
-        const C vq = V_[q[j][k]];
-        ar += cl[j][k] * (vr.x - vq.x);
-        ai += cl[j][k] * (vr.y - vq.y);
-      }
+    for (int k = 0; k < KMAX; ++k) {
+      const C vq = V_[q[j][k]];
+      ar += cl[j][k] * (vr.x - vq.x);
+      ai += cl[j][k] * (vr.y - vq.y);
+    }
     const T hr = d.p1 * ar - vv[j] * vr.x;
     const T hi = d.p1 * ai - vv[j] * vr.y;
     const C b = P[i];
@@ -1161,55 +1161,212 @@ __global__ void __launch_bounds__(1024) k_step(DevOps<T> d, TileOps<T> tl, const
     r.x = b.x + coef * hi;
     r.y = b.y - coef * hr;
     return r;
-  };
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int i = threadIdx.x + j * B;
-    if (i < n1) Y[i] = stage(P, j, i, T(0.25) * h);  // y1
   }
-  __syncthreads();
+
+  // LIN(h) then NL(tau) of the state staged in P (slots < nLoad); X, Y, S are
+  // LDS scratch of the same slot count.  Calls out(r, value) for every owned
+  // row r.  Every thread of the workgroup must call it (it holds barriers).
+  template <typename Out>
+  __device__ void step(const DevOps<T>& d, const C* P, C* X, C* Y, T* S, T h, T tau, T gamma, Out out) const {
+    const int B = blockDim.x;
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int i = threadIdx.x + j * B;
-    if (i < n2) X[i] = stage(Y, j, i, h / T(3));  // y2
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int i = threadIdx.x + j * B;
-    if (i < n3) Y[i] = stage(X, j, i, T(0.5) * h);  // y3
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int i = threadIdx.x + j * B;
-    if (i < n4) {  // state before the Kerr substep
-      const C b = stage(Y, j, i, h);
-      X[i] = b;
-      S[i] = (b.x * b.x + b.y * b.y) * phi_w(ww[j], tau);
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n1) Y[i] = stage(d, P, P, j, i, T(0.25) * h);  // y1
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int i = threadIdx.x + j * B;
-    if (i < nNL) {
-      T th = md[j] * S[i];
-      if (DEC) {
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n2) X[i] = stage(d, P, Y, j, i, h / T(3));  // y2
+    }
+    __syncthreads();
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          th += cm[j][k] * S[q[j][k]];
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n3) Y[i] = stage(d, P, X, j, i, T(0.5) * h);  // y3
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n4) {  // state before the Kerr substep
+        const C b = stage(d, P, Y, j, i, h);
+        X[i] = b;
+        S[i] = (b.x * b.x + b.y * b.y) * phi_w(ww[j], tau);
       }
-      const T damp = d_exp(-ww[j] * tau);
-      T sn, cs;
-      d_sincos(gamma * th, &sn, &cs);
-      const C b = X[i];
-      C r;
-      r.x = damp * (b.x * cs - b.y * sn);
-      r.y = damp * (b.x * sn + b.y * cs);
-      out_psi[rr[j]] = r;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < nNL) {
+        T th = md[j] * S[i];
+        if (DEC) {
+#pragma unroll
+          for (int k = 0; k < KMAX; ++k) th += cm[j][k] * S[q[j][k]];
+        }
+        const T damp = d_exp(-ww[j] * tau);
+        T sn, cs;
+        d_sincos(gamma * th, &sn, &cs);
+        const C b = X[i];
+        C r;
+        r.x = damp * (b.x * cs - b.y * sn);
+        r.y = damp * (b.x * sn + b.y * cs);
+        out(rr[j], r);
+      }
     }
   }
+};
+
+// One whole z step, LIN(h) then NL(tau), per tile of rows (five halo rings).
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__(1024) k_step(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ in_psi,
+                                               typename CT<T>::C* __restrict__ out_psi, T h, T tau, T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  C* P = reinterpret_cast<C*>(smem);
+  C* X = P + MS;
+  C* Y = X + MS;
+  T* S = reinterpret_cast<T*>(Y + MS);
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P[i] = in_psi[st.slot_row(i)];
+  __syncthreads();
+  st.step(d, P, X, Y, S, h, tau, gamma, [&](int32_t r, const C& v) { out_psi[r] = v; });
+}
+
+// ---- persistent z stepping on resident tiles ----
+// Device-coherent (agent scope) element access for state exchanged between
+// workgroups of one persistent launch, which may run on different XCDs.
+__device__ inline float2 coherent_load(const float2* p) {
+  const uint64_t u =
+      __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<float2*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  float2 r;
+  __builtin_memcpy(&r, &u, sizeof(r));
+  return r;
+}
+__device__ inline double2 coherent_load(const double2* p) {
+  uint64_t* q = reinterpret_cast<uint64_t*>(const_cast<double2*>(p));
+  const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double2 r;
+  __builtin_memcpy(&r.x, &a, 8);
+  __builtin_memcpy(&r.y, &b, 8);
+  return r;
+}
+__device__ inline void coherent_store(float2* p, const float2& v) {
+  uint64_t u;
+  __builtin_memcpy(&u, &v, sizeof(u));
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void coherent_store(double2* p, const double2& v) {
+  uint64_t a, b;
+  __builtin_memcpy(&a, &v.x, 8);
+  __builtin_memcpy(&b, &v.y, 8);
+  uint64_t* q = reinterpret_cast<uint64_t*>(p);
+  __hip_atomic_store(q, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until this wave's stores have been acknowledged (vmcnt = 0; the
+// export and LDS counters are left at their maxima).  With every exchanged
+// element written and read by agent-scope accesses, this orders the state
+// stores before the flag store without a cache write-back or invalidate.
+__device__ inline void wait_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// n_steps merged z steps in one launch, one workgroup per tile, all resident
+// (cooperative launch).  The operator rows stay in registers for the whole
+// launch; per step only the state crosses memory.  The state alternates
+// between buf0 (even steps) and buf1; after writing step s+1 a tile publishes
+// flags[tile] = s+1, and before reading step s it waits for every tile that
+// owns one of its halo rows to have published s.  The halo relation is
+// symmetric, so that wait also guarantees the neighbours have finished reading
+// the buffer this tile is about to overwrite.  Exchanged elements and flags are
+// agent-scope atomic accesses (coherent across XCDs); each wave waits for its
+// state stores to be acknowledged before the workgroup barrier that precedes
+// the flag store, and the state loads follow the barrier that ends the flag
+// wait, so no L2 write-back or invalidate is needed.  Each wait is bounded: after
+// spin_limit polls the tile sets bit 1 of *status and leaves, and its
+// neighbours then time out in turn, so every workgroup exits.
+template <typename T, int KMAX, bool DEC, int J, int LS>
+__global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, const int32_t* __restrict__ nb_ptr,
+                                                  const int32_t* __restrict__ nb_list, typename CT<T>::C* buf0,
+                                                  typename CT<T>::C* buf1, int32_t* flags, int32_t* status,
+                                                  int32_t n_steps, int32_t spin_limit, T h, T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t nb_s[64];
+  __shared__ int32_t abort_s;
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  const int B = blockDim.x;
+  C* P = reinterpret_cast<C*>(smem);
+  C* X = P + MS;
+  C* Y = X + MS;
+  T* S = reinterpret_cast<T*>(Y + MS);
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  int32_t pr[LS];  // rows of this thread's state slots
+#pragma unroll
+  for (int l = 0; l < LS; ++l) {
+    const int i = threadIdx.x + l * B;
+    pr[l] = i < st.nLoad ? st.slot_row(i) : -1;
+  }
+  const int32_t nb0 = nb_ptr[tile];
+  const int n_nb = nb_ptr[tile + 1] - nb0;
+  if (threadIdx.x < n_nb) nb_s[threadIdx.x] = nb_list[nb0 + threadIdx.x];
+  __syncthreads();
+  for (int32_t s = 0; s < n_steps; ++s) {
+    const C* src = (s & 1) ? buf1 : buf0;
+    C* dst = (s & 1) ? buf0 : buf1;
+    if (s > 0) {
+      if (threadIdx.x < 64) {  // one wave polls all neighbour flags at once
+        const int32_t u = int(threadIdx.x) < n_nb ? nb_s[threadIdx.x] : -1;
+        bool ok = true;
+        for (int32_t spins = 0;; ++spins) {
+          const bool ready = u < 0 || __hip_atomic_load(flags + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= s;
+          if (__all(ready)) break;
+          if (spins >= spin_limit) {
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (threadIdx.x == 0) {
+          abort_s = ok ? 0 : 1;
+          if (!ok) __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      __syncthreads();
+      if (abort_s) return;
+    }
+    C pv[LS];  // issue every load before the first use
+#pragma unroll
+    for (int l = 0; l < LS; ++l)
+      if (pr[l] >= 0) pv[l] = coherent_load(src + pr[l]);
+#pragma unroll
+    for (int l = 0; l < LS; ++l)
+      if (pr[l] >= 0) P[threadIdx.x + l * B] = pv[l];
+    __syncthreads();
+    st.step(d, P, X, Y, S, h, h, gamma, [&](int32_t r, const C& v) { coherent_store(dst + r, v); });
+    wait_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flags + tile, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void k_zero_i32(int64_t n, int32_t* __restrict__ x) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
 }
 
 // ---- fused adjoint kernels on LDS tiles (lambda = H0^{-1} g variables) ----
@@ -1695,6 +1852,57 @@ void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, v
 #undef DECBPM_STEP
 }
 
+// Kernel instance of the persistent step for a tile set and block size.
+template <typename T>
+static const void* persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block) {
+  const int J = (tl.max_compute + block - 1) / block;
+  const bool dec = tl.lmw != nullptr;
+#define DECBPM_PK(KM, DEC, JJ) reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3>)
+#define DECBPM_PK_J(KM, DEC) return J <= 1 ? DECBPM_PK(KM, DEC, 1) : DECBPM_PK(KM, DEC, 2);
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_PK_J(8, true) } else { DECBPM_PK_J(8, false) }
+  } else {
+    if (dec) { DECBPM_PK_J(12, true) } else { DECBPM_PK_J(12, false) }
+  }
+#undef DECBPM_PK_J
+#undef DECBPM_PK
+}
+
+template <typename T>
+size_t persist_lds(const TileOps<T>& tl) {
+  return size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
+}
+
+template <typename T>
+int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block) {
+  if (tl.max_slots > 3 * block || tl.max_compute > 2 * block) return 0;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel<T>(d, tl, block), block,
+                                                   persist_lds<T>(tl)) != hipSuccess)
+    return 0;
+  return cus * per_cu;
+}
+
+template <typename T>
+hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_t* nb_ptr, const int32_t* nb_list,
+                          void* buf0, void* buf1, int32_t* flags, int32_t* status, int32_t n_steps,
+                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st) {
+  using C = typename CT<T>::C;
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(tl.n_tiles, 256, 0)), dim3(256), 0, st, int64_t(tl.n_tiles), flags);
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  DevOps<T> dd = d;
+  TileOps<T> tt = tl;
+  C* b0 = static_cast<C*>(buf0);
+  C* b1 = static_cast<C*>(buf1);
+  T th = T(h), tg = T(gamma);
+  void* args[] = {&dd, &tt, const_cast<int32_t**>(&nb_ptr), const_cast<int32_t**>(&nb_list), &b0, &b1, &flags, &status,
+                  &n_steps, &spin_limit, &th, &tg};
+  return hipLaunchCooperativeKernel(persist_kernel<T>(d, tl, block), dim3(g), dim3(block), args,
+                                    unsigned(persist_lds<T>(tl)), st);
+}
+
 template <typename T>
 void launch_perm_in(const DevOps<T>& d, const int32_t* perm, const void* src, void* dst, int scale_inv_h0, int block,
                     hipStream_t st) {
@@ -1825,6 +2033,10 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   template void launch_set_v<T>(int64_t, const T*, const double*, const int32_t*, T*, int, hipStream_t);          \
   template void launch_step<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double,   \
                                int, hipStream_t);                                                                \
+  template int persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int);                                     \
+  template hipError_t launch_persist<T>(const DevOps<T>&, const TileOps<T>&, const int32_t*, const int32_t*, void*, \
+                                        void*, int32_t*, int32_t*, int32_t, int32_t, double, double, int,        \
+                                        hipStream_t);                                                            \
   template void launch_bstage<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*, void*, \
                                  double, void*, double, hipStream_t);                                            \
   template void launch_blap<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, hipStream_t);           \

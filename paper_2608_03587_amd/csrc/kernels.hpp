@@ -50,9 +50,10 @@ template <typename T>
 struct TileOps {
   int32_t n_tiles;
   int32_t TS;
-  int32_t max_slots;        // largest slot count of a tile (rings 0..3), LDS sizing
-  int32_t max_compute;      // largest count of slots with operator rows (rings 0..2)
-  const int32_t* hdr;       // [n_tiles * 8]: nT, nH1, nH2, nH3, ext_base, lsl_base, 0, 0
+  int32_t max_slots;        // largest slot count of a tile (all rings), LDS sizing
+  int32_t max_compute;      // largest count of slots with operator rows
+  const int32_t* hdr;       // [n_tiles * 8]: ring counts, ext base, slice-table base (three rings:
+                            // nT, nH1, nH2, nH3, ext, lsl, 0, 0; five: nT, nH1..nH5, ext, lsl)
   const int64_t* ent_base;  // [n_tiles]
   const int32_t* ext;       // halo rows (device order)
   const int32_t* lsl;
@@ -165,6 +166,20 @@ void launch_bkerr(const DevOps<T>& d, const TileOps<T>& tl, const void* psi_in, 
 template <typename T>
 void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h, double tau,
                  double gamma, int block, hipStream_t st);
+
+// Persistent z stepping (n_steps merged steps in one cooperative launch, one
+// resident workgroup per tile of the five-ring step tiles).  nb_ptr/nb_list:
+// per tile, the other tiles owning its halo rows.  flags: n_tiles ints of
+// scratch (cleared by the launch).  status: bit 1 is set if a neighbour wait
+// timed out.  Returns the launch status (the launch fails if the tiles cannot
+// all be resident).  persist_capacity: resident workgroups the device holds
+// for this kernel at `block` threads (0 if the tiles do not fit the kernel).
+template <typename T>
+int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block);
+template <typename T>
+hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_t* nb_ptr, const int32_t* nb_list,
+                          void* buf0, void* buf1, int32_t* flags, int32_t* status, int32_t n_steps,
+                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st);
 
 // out_rec (may be null) receives, for owned rows, y2 (FUSED_S2_S3) or the
 // state before the Kerr substep (S4 kinds): the adjoint's segment recompute.

@@ -11,6 +11,7 @@ import pytest
 import torch
 
 from oracle import adjoint as OA, dec, diagnostics as D, stepper as S
+from paper_2608_03587_amd import _binding as B
 from paper_2608_03587_amd import api
 from paper_2608_03587_amd.inputs import fields as F
 from paper_2608_03587_amd.inputs import meshes as M
@@ -274,7 +275,7 @@ def test_batched_equals_plain(dtype):
     tol = 1e-12 if dtype == "c128" else 1e-5  # same per-row formulas; only FMA contraction may differ
     for m, x, o in zip(meshes, ws, outs):
         for f in range(4):
-            for fused in (0, 1):
+            for fused in (0, 1, 2, 3):
                 m.tuning = {"fused": fused}
                 single = dev(x.u0[f], dtype)
                 m.propagate(single, x.dz, x.n_steps, 1.0)
@@ -364,6 +365,8 @@ def test_fused_tile_path_matches_unfused_and_oracle(dtype, nl):
     say("fused", dtype, nl, w.mesh.n_vert)
     ops = oracle_ops(w, nl)
     m = lib_mesh(w, dtype, nl)
+    assert m.tuning["fused"] == 2  # default: the one-kernel step
+    m.tuning = {"fused": 1}
     assert m.tuning["fused"] == 1
     u = dev(w.u0, dtype)
     for n in (1, 2, 3, 37, 64):
@@ -420,6 +423,77 @@ def test_one_kernel_step_matches_unfused_and_oracle(dtype, nl):
         assert np.array_equal(host(f), keep), tb
     times = m.time_kernels(w.dz, w.gamma, reps=20)
     assert times["step"]["ms"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_persistent_launch_matches_step_kernel_and_oracle(dtype, nl):
+    """All middle steps in one persistent cooperative launch (operator rows in
+    registers, neighbour-tile flags instead of kernel boundaries) against the
+    one-kernel step (same arithmetic: bitwise) and the oracle."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    say("persistent", dtype, nl, w.mesh.n_vert)
+    ops = oracle_ops(w, nl)
+    m = lib_mesh(w, dtype, nl)
+    m.tuning = {"fused": 3, "steps_per_graph": 16}
+    assert m.tuning["fused"] == 3
+    assert m.time_kernels(w.dz, w.gamma, reps=20)["persist"]["ms"] > 0  # the tiles fit: the path is in use
+    u = dev(w.u0, dtype)
+    for n in (1, 2, 3, 37, 64, 200):
+        outs = {}
+        for fused in (3, 2):
+            m.tuning = {"fused": fused}
+            f = u.clone()
+            m.propagate(f, w.dz, n, w.gamma)
+            outs[fused] = host(f)
+        m.check_finite()
+        assert np.array_equal(outs[3], outs[2]), (n, rel(outs[3], outs[2]))
+        if n <= 64:
+            ref = S.propagate(w.u0, ops, w.dz, n, w.gamma)
+            assert rel(outs[3], ref) < GATE[dtype], n
+    for tb in (512, 1024):
+        m.tuning = {"fused": 3, "tile_block": tb}
+        f = u.clone()
+        m.propagate(f, w.dz, 37, w.gamma)
+        m.check_finite()
+        m.tuning = {"fused": 2}
+        g = u.clone()
+        m.propagate(g, w.dz, 37, w.gamma)
+        assert np.array_equal(host(f), host(g)), tb
+
+
+def test_persistent_wait_bound_ends_the_launch(monkeypatch):
+    """With a wait bound of zero polls a tile that finds a neighbour behind
+    leaves the launch; the launch still ends and the next finiteness check
+    reports it (or, if no wait was ever needed, the result is exact)."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    monkeypatch.setenv("DEC_BPM_SPIN_LIMIT", "0")
+    m = lib_mesh(w, "c64", "dec")
+    monkeypatch.delenv("DEC_BPM_SPIN_LIMIT")
+    m.tuning = {"fused": 3}
+    u = dev(w.u0, "c64")
+    f = u.clone()
+    m.propagate(f, w.dz, 300, w.gamma)
+    torch.cuda.synchronize()
+    try:
+        m.check_finite()
+        timed_out = False
+    except api.DecBpmError as e:
+        assert e.code == B.ENONFINITE and "timed out" in str(e), str(e)
+        timed_out = True
+    say("wait bound 0: timed out" if timed_out else "wait bound 0: no wait needed")
+    m.check_finite()  # the report clears the flag
+    ok = lib_mesh(w, "c64", "dec")
+    ok.tuning = {"fused": 3}
+    g = u.clone()
+    ok.propagate(g, w.dz, 300, w.gamma)
+    ok.check_finite()
+    ok.tuning = {"fused": 2}
+    h = u.clone()
+    ok.propagate(h, w.dz, 300, w.gamma)
+    assert np.array_equal(host(g), host(h))
+    if not timed_out:
+        assert np.array_equal(host(f), host(h))
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
