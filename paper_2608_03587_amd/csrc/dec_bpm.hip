@@ -46,10 +46,13 @@ struct DevTiles {
   void* llw = nullptr;
   void* lmw = nullptr;
   int64_t entries = 0, slots = 0;
+  int32_t ext_stride = 0, lsl_stride = 0;
 
   template <typename T>
   TileOps<T> ops() const {
     TileOps<T> t;
+    t.ext_stride = ext_stride;
+    t.lsl_stride = lsl_stride;
     t.n_tiles = n_tiles;
     t.TS = TS;
     t.max_slots = max_slots;
@@ -105,6 +108,7 @@ struct Engine {
   DevTiles tl, bt, stp;  // two-kernel tiles (3 rings), batched tiles, one-kernel-step tiles (5 rings)
   bool has_step = false;
   int step_tile = 1024;  // rows per tile of the one-kernel step (largest that fits)
+  bool sort_ring0 = true;  // step tiles: order the owned rows by degree too
   // persistent stepping on the step tiles: neighbour-tile lists, flags, wait bound
   bool has_persist = false;
   int32_t* nb_ptr = nullptr;
@@ -220,6 +224,7 @@ static void env_defaults(Engine& E) {
   if (const char* s = std::getenv("DEC_BPM_TILE")) E.tile_size = std::max(64, std::min(4096, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_STEP_TILE")) E.step_tile = std::max(64, std::min(4096, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_SPIN_LIMIT")) E.spin_limit = std::max(0, std::atoi(s));
+  if (const char* s = std::getenv("DEC_BPM_SORT_RING0")) E.sort_ring0 = std::atoi(s) != 0;
   if (const char* s = std::getenv("DEC_BPM_FUSED")) E.fused = std::max(0, std::min(3, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_BLOCK")) E.block = std::max(64, std::min(1024, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_STEPS_PER_GRAPH")) E.spg = std::max(1, std::atoi(s));
@@ -244,11 +249,21 @@ struct HostTiles {
   std::vector<uint16_t> lcol;
   std::vector<double> llw, lmw;
   int32_t max_slots = 0, max_compute = 0;
+  int32_t ext_stride = 0, lsl_stride = 0;  // step layout: fixed per-tile strides
 };
 
+// Tiles of TS consecutive rows with `rings` halo rings (breadth-first over the
+// mesh graph) and the operator rows of the slots in rings 0..ell_rings-1 in
+// tile-local sliced ELL (16-bit slot columns).
+// Classic layout: ring 0 slot i is row t*TS + i, the halo rows of all tiles
+// are concatenated (header holds the offsets), rings sorted by row.
+// Step layout: every ring, ring 0 included, is sorted by decreasing degree
+// (then row) so the 64-slot slices have nearly uniform width; the halo list
+// holds every slot and it and the slice table sit at fixed per-tile strides,
+// so a tile finds them without reading its header first.
 static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
                        const std::vector<double>& alw, const std::vector<double>& amw, int TS, int rings,
-                       int ell_rings, HostTiles& H) {
+                       int ell_rings, HostTiles& H, bool step_layout = false, bool sort_ring0 = true) {
   if (rings > 5 || ell_rings > rings + 1) fail(DEC_BPM_EINVAL, "internal: unsupported ring count");
   H = HostTiles();
   H.TS = TS;
@@ -257,6 +272,12 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
   H.ebase.resize(H.nt);
   std::vector<int32_t> slot_of(n, -1);
   std::vector<int32_t> slots, ring;
+  std::vector<std::vector<int32_t>> ext_t, lsl_t;
+  if (step_layout) {
+    ext_t.resize(H.nt);
+    lsl_t.resize(H.nt);
+  }
+  auto deg = [&](int32_t r) { return arp[r + 1] - arp[r]; };
   for (int64_t t = 0; t < H.nt; ++t) {
     const int64_t r0 = t * TS, r1 = std::min(n, r0 + TS);
     slots.clear();
@@ -287,27 +308,40 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
       for (int32_t r : slots) slot_of[r] = -1;
       return false;
     }
+    if (step_layout) {
+      size_t b = 0;
+      for (int k = 0; k <= rings; ++k) {
+        if (k > 0 || sort_ring0)
+          std::stable_sort(slots.begin() + b, slots.begin() + b + cnt[k],
+                           [&](int32_t x, int32_t y) { return deg(x) > deg(y); });
+        b += cnt[k];
+      }
+      for (size_t i = 0; i < slots.size(); ++i) slot_of[slots[i]] = int32_t(i);
+    }
     int32_t* h = &H.hdr[t * 8];
-    if (rings <= 3) {  // counts of rings 0..3, ext base, slice-table base
+    if (step_layout) {  // counts of rings 0..5 (offsets come from the strides)
+      for (int k = 0; k < 6; ++k) h[k] = cnt[k];
+      ext_t[t] = slots;
+    } else if (rings <= 3) {  // counts of rings 0..3, ext base, slice-table base
       for (int k = 0; k < 4; ++k) h[k] = cnt[k];
       h[4] = int32_t(H.ext.size());
       h[5] = int32_t(H.lsl.size());
+      H.ext.insert(H.ext.end(), slots.begin() + cnt[0], slots.end());
     } else {  // counts of rings 0..5, ext base, slice-table base
       for (int k = 0; k < 6; ++k) h[k] = cnt[k];
       h[6] = int32_t(H.ext.size());
       h[7] = int32_t(H.lsl.size());
+      H.ext.insert(H.ext.end(), slots.begin() + cnt[0], slots.end());
     }
-    H.ext.insert(H.ext.end(), slots.begin() + cnt[0], slots.end());
     int ce = 0;
     for (int k = 0; k < ell_rings; ++k) ce += cnt[k];
     H.max_compute = std::max(H.max_compute, ce);
     H.ebase[t] = int64_t(H.lcol.size());
     for (int sl = 0; sl * 64 < ce; ++sl) {
       int W = 0;
-      for (int i = sl * 64; i < std::min(ce, sl * 64 + 64); ++i)
-        W = std::max<int>(W, int(arp[slots[i] + 1] - arp[slots[i]]));
+      for (int i = sl * 64; i < std::min(ce, sl * 64 + 64); ++i) W = std::max<int>(W, int(deg(slots[i])));
       const int64_t rel = int64_t(H.lcol.size()) - H.ebase[t];
-      H.lsl.push_back(int32_t((rel << 8) | W));
+      (step_layout ? lsl_t[t] : H.lsl).push_back(int32_t((rel << 8) | W));
       const size_t b = H.lcol.size();
       H.lcol.resize(b + size_t(W) * 64, 0);
       H.llw.resize(b + size_t(W) * 64, 0.0);
@@ -331,7 +365,22 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
     for (int32_t r : slots) slot_of[r] = -1;
   }
   H.max_slots = (H.max_slots + 3) / 4 * 4;
+  if (step_layout) {
+    for (int64_t t = 0; t < H.nt; ++t) {
+      H.ext_stride = std::max<int32_t>(H.ext_stride, int32_t(ext_t[t].size()));
+      H.lsl_stride = std::max<int32_t>(H.lsl_stride, int32_t(lsl_t[t].size()));
+    }
+    H.ext_stride = (H.ext_stride + 63) / 64 * 64;
+    H.lsl_stride = std::max<int32_t>(1, (H.lsl_stride + 15) / 16 * 16);
+    H.ext.assign(size_t(H.nt) * H.ext_stride, 0);
+    H.lsl.assign(size_t(H.nt) * H.lsl_stride, 0);
+    for (int64_t t = 0; t < H.nt; ++t) {
+      std::copy(ext_t[t].begin(), ext_t[t].end(), H.ext.begin() + t * H.ext_stride);
+      std::copy(lsl_t[t].begin(), lsl_t[t].end(), H.lsl.begin() + t * H.lsl_stride);
+    }
+  }
   if (H.ext.empty()) H.ext.push_back(0);
+  if (H.lsl.empty()) H.lsl.push_back(0);
   return true;
 }
 
@@ -360,6 +409,8 @@ static void upload_tiles(Engine& E, const HostTiles& H, bool dec, int64_t n, Dev
   D.max_compute = H.max_compute;
   D.entries = int64_t(H.lcol.size());
   D.slots = int64_t(H.ext.size()) + n;
+  D.ext_stride = H.ext_stride;
+  D.lsl_stride = H.lsl_stride;
 }
 
 // Plain fused path: the largest tile size (from the requested one, halving)
@@ -388,7 +439,7 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
   const int rings = dec ? 5 : 4;
   HostTiles H;
   for (int ts = E.step_tile; ts >= 64; ts /= 2) {
-    if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H)) continue;
+    if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H, true, E.sort_ring0)) continue;
     if (size_t(H.max_slots) * 7 * sizeof(T) > 64 * 1024 || H.max_compute > 2 * 1024) continue;
     upload_tiles<T>(E, H, dec, E.n_rows, E.stp);
     E.has_step = true;
@@ -405,7 +456,7 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
     for (int k = 1; k < 6; ++k) halo += h[k];
     int cnt = 0;
     for (int32_t i = 0; i < halo; ++i) {
-      const int32_t u = int32_t(H.ext[h[6] + i] / H.TS);
+      const int32_t u = int32_t(H.ext[t * H.ext_stride + h[0] + i] / H.TS);
       if (u == t || seen[u] == int32_t(t)) continue;
       seen[u] = int32_t(t);
       list.push_back(u);

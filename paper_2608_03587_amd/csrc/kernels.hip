@@ -1077,33 +1077,33 @@ __global__ void __launch_bounds__(1024) k_fused(DevOps<T> d, TileOps<T> tl, cons
 // LDS-staged state, then the Kerr/absorber flow over tau on the owned rows.
 // Rings: the state is staged on rings 0..4+o (o = 1 for the triangle-averaged
 // Kerr gather, 0 for the lumped one), each stage shrinks the valid region by
-// one ring.  Padded ELL entries point at their own slot with weight zero, so
-// the neighbour loops run to KMAX unconditionally.
+// one ring.  Tiles use the step layout: every slot listed at a fixed per-tile
+// stride, rings sorted by degree so that the width of a 64-slot slice (one
+// wavefront) is nearly every row's degree; the neighbour loops run to that
+// wave-uniform width, padded entries pointing at their own slot with weight 0.
 template <typename T, int KMAX, bool DEC, int J>
 struct StepTile {
   using C = typename CT<T>::C;
-  int nLoad, n1, n2, n3, n4, nNL, c0;
-  int64_t row0;
+  int nLoad, n1, n2, n3, n4, nNL;
   const int32_t* ext;
   int q[J][KMAX];
   T cl[J][KMAX];
   T cm[J][DEC ? KMAX : 1];
+  int wd[J];  // slice width (wave-uniform)
   int32_t rr[J];
   T vv[J], ww[J], md[J];
 
-  __device__ int32_t slot_row(int i) const { return i < c0 ? int32_t(row0 + i) : ext[i - c0]; }
+  __device__ int32_t slot_row(int i) const { return ext[i]; }
 
   __device__ void init(const DevOps<T>& d, const TileOps<T>& tl, int64_t tile) {
     const int32_t* hd = tl.hdr + 8 * tile;
+    ext = tl.ext + tile * int64_t(tl.ext_stride);
+    const int32_t* __restrict__ lsl = tl.lsl + tile * int64_t(tl.lsl_stride);
+    const int64_t ebase = tl.ent_base[tile];
     int cr[6];  // cr[k] = slots in rings 0..k
     cr[0] = hd[0];
 #pragma unroll
     for (int k = 1; k < 6; ++k) cr[k] = cr[k - 1] + hd[k];
-    ext = tl.ext + hd[6];
-    const int32_t* __restrict__ lsl = tl.lsl + hd[7];
-    const int64_t ebase = tl.ent_base[tile];
-    row0 = tile * int64_t(tl.TS);
-    c0 = cr[0];
     const int o = DEC ? 1 : 0;
     nLoad = cr[4 + o];
     n1 = cr[3 + o];
@@ -1117,21 +1117,23 @@ struct StepTile {
       const int i = threadIdx.x + j * B;
       rr[j] = 0;
       vv[j] = ww[j] = md[j] = T(0);
-      int wd = 0;
+      int w = 0;
       int64_t base = 0;
       if (i < n1) {
-        const int32_t r = slot_row(i);
+        const int32_t r = ext[i];
         rr[j] = r;
         vv[j] = d.v[r];
         ww[j] = d.w[r];
         md[j] = d.mdiag[r];
         const int32_t info = lsl[i >> 6];
-        wd = info & 0xff;
+        w = info & 0xff;
         base = ebase + (info >> 8) + (i & 63);
       }
+      // lanes past n1 in a wave whose slice starts below n1 read the same slice word
+      wd[j] = __builtin_amdgcn_readfirstlane(w);
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) {
-        if (k < wd) {
+        if (k < w) {
           q[j][k] = tl.lcol[base + 64 * k];
           cl[j][k] = tl.llw[base + 64 * k];
           if (DEC) cm[j][k] = tl.lmw[base + 64 * k];
@@ -1144,56 +1146,106 @@ struct StepTile {
     }
   }
 
-  // P + coef * (-i) (p1 L v - V v) at register slot j, v gathered from V_
-  __device__ C stage(const DevOps<T>& d, const C* P, const C* V_, int j, int i, T coef) const {
-    const C vr = V_[i];
-    T ar = T(0), ai = T(0);
+  // sum_k c_k (vr - V_[q_k]) over the first N entries of register slot j
+  template <int N>
+  __device__ void lsum_n(const C* V_, int j, const C& vr, T& ar, T& ai) const {
+    C vq[N];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      const C vq = V_[q[j][k]];
-      ar += cl[j][k] * (vr.x - vq.x);
-      ai += cl[j][k] * (vr.y - vq.y);
+    for (int k = 0; k < N; ++k) vq[k] = V_[q[j][k]];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      ar += cl[j][k] * (vr.x - vq[k].x);
+      ai += cl[j][k] * (vr.y - vq[k].y);
     }
+  }
+  template <int N>
+  __device__ void lsum_w(int W, const C* V_, int j, const C& vr, T& ar, T& ai) const {
+    if constexpr (N > 0) {
+      if (W == N) {
+        lsum_n<N>(V_, j, vr, ar, ai);
+        return;
+      }
+      lsum_w<N - 1>(W, V_, j, vr, ar, ai);
+    }
+  }
+  // th + sum_k m_k S[q_k] over the first N entries of register slot j
+  template <int N>
+  __device__ T msum_n(const T* S, int j, T th) const {
+    T sq[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) sq[k] = S[q[j][k]];
+#pragma unroll
+    for (int k = 0; k < N; ++k) th += cm[j][k] * sq[k];
+    return th;
+  }
+  template <int N>
+  __device__ T msum_w(int W, const T* S, int j, T th) const {
+    if constexpr (N > 0) {
+      if (W == N) return msum_n<N>(S, j, th);
+      return msum_w<N - 1>(W, S, j, th);
+    } else {
+      return th;
+    }
+  }
+
+  // base + coef * (-i) (p1 L v - V v) at register slot j: the slot's own value
+  // vr and base come from registers, only the neighbours are gathered from V_
+  __device__ C stage(const DevOps<T>& d, const C* V_, const C& vr, const C& base, int j, T coef) const {
+    T ar = T(0), ai = T(0);
+    lsum_w<KMAX>(wd[j], V_, j, vr, ar, ai);
     const T hr = d.p1 * ar - vv[j] * vr.x;
     const T hi = d.p1 * ai - vv[j] * vr.y;
-    const C b = P[i];
     C r;
-    r.x = b.x + coef * hi;
-    r.y = b.y - coef * hr;
+    r.x = base.x + coef * hi;
+    r.y = base.y - coef * hr;
     return r;
   }
 
   // LIN(h) then NL(tau) of the state staged in P (slots < nLoad); X, Y, S are
   // LDS scratch of the same slot count.  Calls out(r, value) for every owned
   // row r.  Every thread of the workgroup must call it (it holds barriers).
+  // A thread keeps the values of its own slots (the state, the latest stage,
+  // |b|^2 phi) in registers; LDS serves the neighbour gathers only.
   template <typename Out>
   __device__ void step(const DevOps<T>& d, const C* P, C* X, C* Y, T* S, T h, T tau, T gamma, Out out) const {
     const int B = blockDim.x;
+    C p[J], cur[J];
+    T so[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int i = threadIdx.x + j * B;
-      if (i < n1) Y[i] = stage(d, P, P, j, i, T(0.25) * h);  // y1
+      if (i < n1) {
+        p[j] = P[i];
+        cur[j] = stage(d, P, p[j], p[j], j, T(0.25) * h);  // y1
+        Y[i] = cur[j];
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int i = threadIdx.x + j * B;
-      if (i < n2) X[i] = stage(d, P, Y, j, i, h / T(3));  // y2
+      if (i < n2) {
+        cur[j] = stage(d, Y, cur[j], p[j], j, h / T(3));  // y2
+        X[i] = cur[j];
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int i = threadIdx.x + j * B;
-      if (i < n3) Y[i] = stage(d, P, X, j, i, T(0.5) * h);  // y3
+      if (i < n3) {
+        cur[j] = stage(d, X, cur[j], p[j], j, T(0.5) * h);  // y3
+        Y[i] = cur[j];
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int i = threadIdx.x + j * B;
       if (i < n4) {  // state before the Kerr substep
-        const C b = stage(d, P, Y, j, i, h);
-        X[i] = b;
-        S[i] = (b.x * b.x + b.y * b.y) * phi_w(ww[j], tau);
+        cur[j] = stage(d, Y, cur[j], p[j], j, h);
+        so[j] = (cur[j].x * cur[j].x + cur[j].y * cur[j].y) * phi_w(ww[j], tau);
+        S[i] = so[j];
       }
     }
     __syncthreads();
@@ -1201,15 +1253,12 @@ struct StepTile {
     for (int j = 0; j < J; ++j) {
       const int i = threadIdx.x + j * B;
       if (i < nNL) {
-        T th = md[j] * S[i];
-        if (DEC) {
-#pragma unroll
-          for (int k = 0; k < KMAX; ++k) th += cm[j][k] * S[q[j][k]];
-        }
+        T th = md[j] * so[j];
+        if (DEC) th = msum_w<KMAX>(wd[j], S, j, th);
         const T damp = d_exp(-ww[j] * tau);
         T sn, cs;
         d_sincos(gamma * th, &sn, &cs);
-        const C b = X[i];
+        const C b = cur[j];
         C r;
         r.x = damp * (b.x * cs - b.y * sn);
         r.y = damp * (b.x * sn + b.y * cs);

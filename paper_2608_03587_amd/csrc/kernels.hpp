@@ -60,6 +60,8 @@ struct TileOps {
   const uint16_t* lcol;
   const T* llw;
   const T* lmw;             // nullptr for the lumped nonlinearity
+  int32_t ext_stride;       // step layout: per-tile stride of ext (every slot listed) and of lsl;
+  int32_t lsl_stride;       // 0: classic layout (offsets in the header, ring 0 implicit)
 };
 
 enum FusedKind { FUSED_S4_NL_S1 = 0, FUSED_S2_S3 = 1, FUSED_NL_S1 = 2, FUSED_S4_NL = 3 };
