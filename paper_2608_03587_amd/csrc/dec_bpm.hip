@@ -716,6 +716,12 @@ static bool use_step(const Engine& E) {
   return E.has_step && E.fused == 2;
 }
 
+// Checkpointed forward and adjoint on the step tiles (launch modes 2 and 3).
+template <typename T>
+static bool use_step_adjoint(const Engine& E) {
+  return E.has_step && E.fused >= 2 && size_t(E.stp.max_slots) * 3 * 2 * sizeof(T) <= 64 * 1024;
+}
+
 // Persistent stepping needs every step tile resident at once.
 template <typename T>
 static bool persist_fits(Engine& E) {
@@ -937,6 +943,23 @@ static void forward_ckpt_t(Engine& E, void* field, double dz, int64_t n, double 
   const int B = E.block;
   const size_t vb = (size_t(E.n_rows) * E.cplx_size() + 255) / 256 * 256;
   launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
+  if (n > 0 && use_step_adjoint<T>(E)) {  // one-kernel steps
+    const TileOps<T> sp = E.stp.template ops<T>();
+    launch_copy<T>(E.n_rows, E.psi, ws + L.x0, B, st);
+    launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
+    launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
+    launch_copy<T>(E.n_rows, E.psi, ws + L.ck, B, st);
+    void* cur = E.psi;
+    void* nxt = E.psi2;
+    for (int64_t k = 1; k <= n; ++k) {
+      launch_step<T>(d, sp, cur, nxt, dz, k < n ? dz : 0.5 * dz, gamma, E.sblock(), st);
+      std::swap(cur, nxt);
+      if (k % L.S == 0 && k / L.S < L.K) launch_copy<T>(E.n_rows, cur, ws + L.ck + size_t(k / L.S) * vb, B, st);
+    }
+    launch_perm_out<T>(d, E.perm, cur, field, 0, E.flag, B, st);
+    check_launch();
+    return;
+  }
   if (n > 0 && E.has_tiles && E.fused != 0) {
     const TileOps<T> tl = E.tiles<T>();
     const int TB = E.tblock();
@@ -1036,6 +1059,45 @@ static void adjoint_t(Engine& E, const void* grad_out, double dz, int64_t n, dou
 // recording tile launches per step (stages 2+3 keeping y2; stage 4 + Kerr +
 // next stage 1 keeping the pre-Kerr state), then swept back with two adjoint
 // tile launches per step.
+template <typename T>
+static void adjoint_step_t(Engine& E, const void* grad_out, double dz, int64_t n, double gamma, int64_t every,
+                           char* ws, void* grad0, double* grad_dn, hipStream_t st) {
+  const WsLayout L = ws_layout(E, n, every);
+  const DevOps<T> d = E.ops<T>();
+  const TileOps<T> sp = E.stp.template ops<T>();
+  const int B = E.block, SB = E.sblock();
+  const size_t vb = (size_t(E.n_rows) * E.cplx_size() + 255) / 256 * 256;
+  void* lam = ws + L.lam;
+  void* other = ws + L.ua;
+  void* sm = ws + L.sm;
+  double* gdn = reinterpret_cast<double*>(ws + L.gdn);
+  launch_perm_in<T>(d, E.perm, grad_out, lam, 1, B, st);
+  launch_zero_f64(E.n_rows, gdn, B, st);
+  auto Y = [&](int64_t j, int k) -> void* { return ws + L.sy + size_t(3 * (j - 1) + k) * vb; };
+  auto Bv = [&](int64_t j) -> void* { return ws + L.sb + size_t(j - 1) * vb; };
+  for (int64_t seg = L.K - 1; seg >= 0 && n > 0; --seg) {
+    const int64_t n0 = seg * L.S, n1 = std::min(n, (seg + 1) * L.S), m = n1 - n0;
+    char* ck = ws + L.ck + size_t(seg) * vb;
+    auto A = [&](int64_t j) -> void* { return j == 0 ? static_cast<void*>(ck) : ws + L.sa + size_t(j) * vb; };
+    for (int64_t j = 1; j <= m; ++j)  // recompute the segment, recording the stage vectors
+      launch_step_rec<T>(d, sp, A(j - 1), A(j), Y(j, 0), Y(j, 1), Y(j, 2), Bv(j), dz, (n0 + j < n) ? dz : 0.5 * dz,
+                         gamma, SB, st);
+    for (int64_t j = m; j >= 1; --j) {
+      launch_step_adj<T>(d, sp, lam, A(j), Bv(j), Y(j, 2), Y(j, 1), Y(j, 0), A(j - 1), other, gdn, dz,
+                         (n0 + j < n) ? dz : 0.5 * dz, gamma, SB, st);
+      std::swap(lam, other);
+    }
+  }
+  if (n > 0) {
+    // first half step NL(dz/2) of the run: x0 -> a_0 (checkpoint 0)
+    launch_adj_prep<T>(d, ws + L.x0, ws + L.ck, lam, sm, 0.5 * dz, gamma, B, st);
+    launch_adj_kerr<T>(d, ws + L.x0, lam, sm, lam, 0.5 * dz, gamma, B, st);
+  }
+  launch_perm_out<T>(d, E.perm, lam, grad0, 1, nullptr, B, st);
+  if (grad_dn) launch_gdn_out(E.n_rows, E.perm, gdn, grad_dn, B, st);
+  check_launch();
+}
+
 template <typename T>
 static bool adjoint_fused_ok(const Engine& E) {
   return E.has_tiles && E.fused != 0 && size_t(E.tl.max_slots) * 4 * 2 * sizeof(T) <= 64 * 1024;
@@ -1679,12 +1741,16 @@ int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_step
   char* ws = static_cast<char*>(workspace);
   hipStream_t st = as_stream(stream);
   if (E.dtype == DEC_BPM_C64) {
-    if (decbpm::adjoint_fused_ok<float>(E))
+    if (decbpm::use_step_adjoint<float>(E))
+      decbpm::adjoint_step_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
+    else if (decbpm::adjoint_fused_ok<float>(E))
       decbpm::adjoint_fused_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
     else
       decbpm::adjoint_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
   } else {
-    if (decbpm::adjoint_fused_ok<double>(E))
+    if (decbpm::use_step_adjoint<double>(E))
+      decbpm::adjoint_step_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
+    else if (decbpm::adjoint_fused_ok<double>(E))
       decbpm::adjoint_fused_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
     else
       decbpm::adjoint_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);

@@ -1188,6 +1188,41 @@ struct StepTile {
     }
   }
 
+  // (th, mm) + sum_k m_k (SM[q_k].x, SM[q_k].y) over the first N entries of register slot j
+  template <int N>
+  __device__ void msum2_n(const C* SM, int j, T& th, T& mm) const {
+    C sq[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) sq[k] = SM[q[j][k]];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      th += cm[j][k] * sq[k].x;
+      mm += cm[j][k] * sq[k].y;
+    }
+  }
+  template <int N>
+  __device__ void msum2_w(int W, const C* SM, int j, T& th, T& mm) const {
+    if constexpr (N > 0) {
+      if (W == N) {
+        msum2_n<N>(SM, j, th, mm);
+        return;
+      }
+      msum2_w<N - 1>(W, SM, j, th, mm);
+    }
+  }
+
+  // coef * (-i) (p1 L v - V v) at register slot j (own value vr, neighbours from V_)
+  __device__ C link(const DevOps<T>& d, const C* V_, const C& vr, int j, T coef) const {
+    T ar = T(0), ai = T(0);
+    lsum_w<KMAX>(wd[j], V_, j, vr, ar, ai);
+    const T hr = d.p1 * ar - vv[j] * vr.x;
+    const T hi = d.p1 * ai - vv[j] * vr.y;
+    C o;
+    o.x = coef * hi;
+    o.y = -coef * hr;
+    return o;
+  }
+
   // base + coef * (-i) (p1 L v - V v) at register slot j: the slot's own value
   // vr and base come from registers, only the neighbours are gathered from V_
   __device__ C stage(const DevOps<T>& d, const C* V_, const C& vr, const C& base, int j, T coef) const {
@@ -1203,11 +1238,14 @@ struct StepTile {
 
   // LIN(h) then NL(tau) of the state staged in P (slots < nLoad); X, Y, S are
   // LDS scratch of the same slot count.  Calls out(r, value) for every owned
-  // row r.  Every thread of the workgroup must call it (it holds barriers).
-  // A thread keeps the values of its own slots (the state, the latest stage,
-  // |b|^2 phi) in registers; LDS serves the neighbour gathers only.
-  template <typename Out>
-  __device__ void step(const DevOps<T>& d, const C* P, C* X, C* Y, T* S, T h, T tau, T gamma, Out out) const {
+  // row r, and rec(k, r, value) with the stage vectors y1, y2, y3 (k = 0..2)
+  // and the state before the Kerr substep (k = 3) of every owned row.  Every
+  // thread of the workgroup must call it (it holds barriers).  A thread keeps
+  // the values of its own slots (the state, the latest stage, |b|^2 phi) in
+  // registers; LDS serves the neighbour gathers only.
+  template <typename Out, typename Rec>
+  __device__ void step(const DevOps<T>& d, const C* P, C* X, C* Y, T* S, T h, T tau, T gamma, Out out,
+                       Rec rec) const {
     const int B = blockDim.x;
     C p[J], cur[J];
     T so[J];
@@ -1218,6 +1256,7 @@ struct StepTile {
         p[j] = P[i];
         cur[j] = stage(d, P, p[j], p[j], j, T(0.25) * h);  // y1
         Y[i] = cur[j];
+        if (i < nNL) rec(0, rr[j], cur[j]);
       }
     }
     __syncthreads();
@@ -1227,6 +1266,7 @@ struct StepTile {
       if (i < n2) {
         cur[j] = stage(d, Y, cur[j], p[j], j, h / T(3));  // y2
         X[i] = cur[j];
+        if (i < nNL) rec(1, rr[j], cur[j]);
       }
     }
     __syncthreads();
@@ -1236,6 +1276,7 @@ struct StepTile {
       if (i < n3) {
         cur[j] = stage(d, X, cur[j], p[j], j, T(0.5) * h);  // y3
         Y[i] = cur[j];
+        if (i < nNL) rec(2, rr[j], cur[j]);
       }
     }
     __syncthreads();
@@ -1246,6 +1287,7 @@ struct StepTile {
         cur[j] = stage(d, Y, cur[j], p[j], j, h);
         so[j] = (cur[j].x * cur[j].x + cur[j].y * cur[j].y) * phi_w(ww[j], tau);
         S[i] = so[j];
+        if (i < nNL) rec(3, rr[j], cur[j]);
       }
     }
     __syncthreads();
@@ -1254,7 +1296,7 @@ struct StepTile {
       const int i = threadIdx.x + j * B;
       if (i < nNL) {
         T th = md[j] * so[j];
-        if (DEC) th = msum_w<KMAX>(wd[j], S, j, th);
+        if constexpr (DEC) th = msum_w<KMAX>(wd[j], S, j, th);
         const T damp = d_exp(-ww[j] * tau);
         T sn, cs;
         d_sincos(gamma * th, &sn, &cs);
@@ -1285,7 +1327,212 @@ __global__ void __launch_bounds__(1024) k_step(DevOps<T> d, TileOps<T> tl, const
   st.init(d, tl, tile);
   for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P[i] = in_psi[st.slot_row(i)];
   __syncthreads();
-  st.step(d, P, X, Y, S, h, tau, gamma, [&](int32_t r, const C& v) { out_psi[r] = v; });
+  st.step(d, P, X, Y, S, h, tau, gamma, [&](int32_t r, const C& v) { out_psi[r] = v; },
+          [](int, int32_t, const C&) {});
+}
+
+// The one-kernel step that also records, for the adjoint's forward recompute,
+// the stage vectors y1, y2, y3 and the state before the Kerr substep.
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__(1024) k_step_rec(DevOps<T> d, TileOps<T> tl,
+                                                   const typename CT<T>::C* __restrict__ in_psi,
+                                                   typename CT<T>::C* __restrict__ out_psi,
+                                                   typename CT<T>::C* __restrict__ o_y1,
+                                                   typename CT<T>::C* __restrict__ o_y2,
+                                                   typename CT<T>::C* __restrict__ o_y3,
+                                                   typename CT<T>::C* __restrict__ o_b, T h, T tau, T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  C* P = reinterpret_cast<C*>(smem);
+  C* X = P + MS;
+  C* Y = X + MS;
+  T* S = reinterpret_cast<T*>(Y + MS);
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P[i] = in_psi[st.slot_row(i)];
+  __syncthreads();
+  st.step(d, P, X, Y, S, h, tau, gamma, [&](int32_t r, const C& v) { out_psi[r] = v; },
+          [&](int k, int32_t r, const C& v) {
+            C* o = k == 0 ? o_y1 : (k == 1 ? o_y2 : (k == 2 ? o_y3 : o_b));
+            o[r] = v;
+          });
+}
+
+// One reverse z step of the adjoint in the lambda = H0^{-1} g variables on the
+// step tiles (the transpose of the one-kernel step): the Kerr/absorber adjoint
+// lam_b = conj(E) lam' + 2 phi b (M mu), mu = gamma Re(i conj(lam') a), then the
+// four links of the reverse Horner chain u1 = -h A lam_b, u2 = -(h/2) A u1,
+// u3 = -(h/3) A u2, u4 = -(h/4) A u3; lam = lam_b + u1 + u2 + u3 + u4, and the
+// index-perturbation gradient grows by
+// H0 Re(i [h conj(lam_b) y3 + h/2 conj(u1) y2 + h/3 conj(u2) y1 + h/4 conj(u3) a0]).
+// Inputs: lam' (adjoint of the state a after the step), a, the state b before
+// the Kerr substep, the step's y1..y3 and its input state a0.  lam_out must not
+// alias lam_in (other tiles read lam_in's halo).
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__(1024) k_step_adj(DevOps<T> d, TileOps<T> tl,
+                                                   const typename CT<T>::C* __restrict__ lam_in,
+                                                   const typename CT<T>::C* __restrict__ fa,
+                                                   const typename CT<T>::C* __restrict__ fb,
+                                                   const typename CT<T>::C* __restrict__ y3,
+                                                   const typename CT<T>::C* __restrict__ y2,
+                                                   const typename CT<T>::C* __restrict__ y1,
+                                                   const typename CT<T>::C* __restrict__ fa0,
+                                                   typename CT<T>::C* __restrict__ lam_out,
+                                                   double* __restrict__ gdn, T h, T tau, T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  const int B = blockDim.x;
+  C* LB = reinterpret_cast<C*>(smem);  // lam' -> lam_b -> u2
+  C* U = LB + MS;                      // b -> u1 -> u3
+  C* SM = U + MS;                      // (|b|^2 phi, mu) per slot
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  const int32_t* hd = tl.hdr + 8 * tile;
+  int cr[5];
+  cr[0] = hd[0];
+#pragma unroll
+  for (int k = 1; k < 5; ++k) cr[k] = cr[k - 1] + hd[k];
+  // Kerr adjoint rows: rings 0..4 (triangle-averaged: gathered in a phase of
+  // its own; lumped: pointwise, done while staging)
+  for (int i = threadIdx.x; i < st.nLoad; i += B) {
+    const int32_t r = st.slot_row(i);
+    const C l = lam_in[r];
+    const C aa = fa[r];
+    const C bb = fb[r];
+    const T w = d.w[r];
+    C sm;
+    sm.x = (bb.x * bb.x + bb.y * bb.y) * phi_w(w, tau);
+    sm.y = -gamma * (l.x * aa.y - l.y * aa.x);  // gamma Re(i conj(lam) a)
+    SM[i] = sm;
+    if (DEC) {
+      LB[i] = l;
+      U[i] = bb;
+    } else {
+      const T md = d.mdiag[r];
+      const T th = md * sm.x, mm = md * sm.y;
+      const T damp = d_exp(-w * tau);
+      T sn, cs;
+      d_sincos(gamma * th, &sn, &cs);
+      const T two_phi_mm = T(2) * phi_w(w, tau) * mm;
+      C o;
+      o.x = damp * (cs * l.x + sn * l.y) + two_phi_mm * bb.x;
+      o.y = damp * (cs * l.y - sn * l.x) + two_phi_mm * bb.y;
+      LB[i] = o;
+    }
+  }
+  // owned rows: forward vectors and the gradient accumulator
+  C fy3[J], fy2[J], fy1[J], fa0r[J];
+  double h0[J], g0[J], gd[J];  // H0, gradient so far, this step's sum of Re(i conj(u) y) terms
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    h0[j] = g0[j] = gd[j] = 0.0;
+    if (i < cr[0]) {
+      const int32_t r = st.rr[j];
+      fy3[j] = y3[r];
+      fy2[j] = y2[r];
+      fy1[j] = y1[r];
+      fa0r[j] = fa0[r];
+      h0[j] = d.h0[r];
+      g0[j] = gdn[r];
+    }
+  }
+  __syncthreads();
+  // Re(i conj(u) y) = -(u.x y.y - u.y y.x)
+  auto rdn = [](const C& u, const C& y) { return -(double(u.x) * y.y - double(u.y) * y.x); };
+  C cur[J], acc[J];
+  if constexpr (DEC) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {  // Kerr/absorber adjoint, rings 0..4
+      const int i = threadIdx.x + j * B;
+      if (i < cr[4]) {
+        const C own = SM[i];
+        T th = st.md[j] * own.x, mm = st.md[j] * own.y;
+        st.template msum2_w<KMAX>(st.wd[j], SM, j, th, mm);
+        const T damp = d_exp(-st.ww[j] * tau);
+        T sn, cs;
+        d_sincos(gamma * th, &sn, &cs);
+        const C l = LB[i];
+        const C p = U[i];
+        const T two_phi_mm = T(2) * phi_w(st.ww[j], tau) * mm;
+        C o;
+        o.x = damp * (cs * l.x + sn * l.y) + two_phi_mm * p.x;
+        o.y = damp * (cs * l.y - sn * l.x) + two_phi_mm * p.y;
+        cur[j] = o;
+        LB[i] = o;  // only this thread reads LB[i] and U[i] in this phase
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < cr[3]) cur[j] = LB[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {  // link 1, rings 0..3
+    const int i = threadIdx.x + j * B;
+    if (i < cr[3]) {
+      const C u1 = st.link(d, LB, cur[j], j, -h);
+      U[i] = u1;
+      if (i < cr[0]) {
+        gd[j] += double(h) * rdn(cur[j], fy3[j]) + 0.5 * double(h) * rdn(u1, fy2[j]);
+        acc[j].x = cur[j].x + u1.x;
+        acc[j].y = cur[j].y + u1.y;
+      }
+      cur[j] = u1;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {  // link 2, rings 0..2
+    const int i = threadIdx.x + j * B;
+    if (i < cr[2]) {
+      const C u2 = st.link(d, U, cur[j], j, T(-0.5) * h);
+      LB[i] = u2;
+      if (i < cr[0]) {
+        gd[j] += double(h) / 3.0 * rdn(u2, fy1[j]);
+        acc[j].x += u2.x;
+        acc[j].y += u2.y;
+      }
+      cur[j] = u2;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {  // link 3, rings 0..1
+    const int i = threadIdx.x + j * B;
+    if (i < cr[1]) {
+      const C u3 = st.link(d, LB, cur[j], j, -h / T(3));
+      U[i] = u3;
+      if (i < cr[0]) {
+        gd[j] += 0.25 * double(h) * rdn(u3, fa0r[j]);
+        acc[j].x += u3.x;
+        acc[j].y += u3.y;
+      }
+      cur[j] = u3;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {  // link 4, owned rows
+    const int i = threadIdx.x + j * B;
+    if (i < cr[0]) {
+      const C u4 = st.link(d, U, cur[j], j, T(-0.25) * h);
+      C l;
+      l.x = acc[j].x + u4.x;
+      l.y = acc[j].y + u4.y;
+      lam_out[st.rr[j]] = l;
+      gdn[st.rr[j]] = g0[j] + h0[j] * gd[j];
+    }
+  }
 }
 
 // ---- persistent z stepping on resident tiles ----
@@ -1406,7 +1653,8 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
     for (int l = 0; l < LS; ++l)
       if (pr[l] >= 0) P[threadIdx.x + l * B] = pv[l];
     __syncthreads();
-    st.step(d, P, X, Y, S, h, h, gamma, [&](int32_t r, const C& v) { coherent_store(dst + r, v); });
+    st.step(d, P, X, Y, S, h, h, gamma, [&](int32_t r, const C& v) { coherent_store(dst + r, v); },
+            [](int, int32_t, const C&) {});
     wait_stores();
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(flags + tile, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1901,6 +2149,51 @@ void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, v
 #undef DECBPM_STEP
 }
 
+template <typename T>
+void launch_step_rec(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, void* y1, void* y2,
+                     void* y3, void* b, double h, double tau, double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_STEPR(KM, DEC, JJ)                                                                              \
+  hipLaunchKernelGGL((k_step_rec<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi), \
+                     DECBPM_M(T, out_psi), DECBPM_M(T, y1), DECBPM_M(T, y2), DECBPM_M(T, y3), DECBPM_M(T, b),   \
+                     T(h), T(tau), T(gamma))
+#define DECBPM_STEPR_J(KM, DEC) \
+  if (J <= 1) DECBPM_STEPR(KM, DEC, 1); else DECBPM_STEPR(KM, DEC, 2);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_STEPR_J(8, true) } else { DECBPM_STEPR_J(8, false) }
+  } else {
+    if (dec) { DECBPM_STEPR_J(12, true) } else { DECBPM_STEPR_J(12, false) }
+  }
+#undef DECBPM_STEPR_J
+#undef DECBPM_STEPR
+}
+
+template <typename T>
+void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_in, const void* fa, const void* fb,
+                     const void* y3, const void* y2, const void* y1, const void* fa0, void* lam_out, double* gdn,
+                     double h, double tau, double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * 3 * sizeof(typename CT<T>::C);
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_STEPA(KM, DEC, JJ)                                                                              \
+  hipLaunchKernelGGL((k_step_adj<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, lam_in), \
+                     DECBPM_C(T, fa), DECBPM_C(T, fb), DECBPM_C(T, y3), DECBPM_C(T, y2), DECBPM_C(T, y1),       \
+                     DECBPM_C(T, fa0), DECBPM_M(T, lam_out), gdn, T(h), T(tau), T(gamma))
+#define DECBPM_STEPA_J(KM, DEC) \
+  if (J <= 1) DECBPM_STEPA(KM, DEC, 1); else DECBPM_STEPA(KM, DEC, 2);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_STEPA_J(8, true) } else { DECBPM_STEPA_J(8, false) }
+  } else {
+    if (dec) { DECBPM_STEPA_J(12, true) } else { DECBPM_STEPA_J(12, false) }
+  }
+#undef DECBPM_STEPA_J
+#undef DECBPM_STEPA
+}
+
 // Kernel instance of the persistent step for a tile set and block size.
 template <typename T>
 static const void* persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block) {
@@ -2083,6 +2376,11 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   template void launch_step<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double,   \
                                int, hipStream_t);                                                                \
   template int persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int);                                     \
+  template void launch_step_rec<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, void*, void*, void*,    \
+                                   void*, double, double, double, int, hipStream_t);                             \
+  template void launch_step_adj<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*,     \
+                                   const void*, const void*, const void*, const void*, void*, double*, double,   \
+                                   double, double, int, hipStream_t);                                            \
   template hipError_t launch_persist<T>(const DevOps<T>&, const TileOps<T>&, const int32_t*, const int32_t*, void*, \
                                         void*, int32_t*, int32_t*, int32_t, int32_t, double, double, int,        \
                                         hipStream_t);                                                            \

@@ -169,6 +169,18 @@ template <typename T>
 void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h, double tau,
                  double gamma, int block, hipStream_t st);
 
+// The one-kernel step that also writes the owned rows' stage vectors y1..y3
+// and the state before the Kerr substep (the adjoint's forward recompute).
+template <typename T>
+void launch_step_rec(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, void* y1, void* y2,
+                     void* y3, void* b, double h, double tau, double gamma, int block, hipStream_t st);
+// One reverse z step of the adjoint on the step tiles (lam_out must not alias
+// lam_in; gdn accumulates in place).
+template <typename T>
+void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_in, const void* fa, const void* fb,
+                     const void* y3, const void* y2, const void* y1, const void* fa0, void* lam_out, double* gdn,
+                     double h, double tau, double gamma, int block, hipStream_t st);
+
 // Persistent z stepping (n_steps merged steps in one cooperative launch, one
 // resident workgroup per tile of the five-ring step tiles).  nb_ptr/nb_list:
 // per tile, the other tiles owning its halo rows.  flags: n_tiles ints of
