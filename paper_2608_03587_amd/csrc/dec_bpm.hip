@@ -143,9 +143,15 @@ struct Engine {
   } ckpt;
   uint64_t dn_version = 0;
 
+  // threads per workgroup of the step-tile kernels: the requested count if it
+  // covers every compute slot once (one slot per thread), else at least half of
+  // them (two slots per thread) and at most the two-slot kernels' bound (640
+  // threads in complex128, 1024 in complex64)
   int sblock() const {
-    const int need = ((stp.max_compute + 1) / 2 + 63) / 64 * 64;
-    return std::min(1024, std::max(tile_block, need));
+    const int mc = stp.max_compute;
+    const int b = std::max(tile_block, ((mc + 1) / 2 + 63) / 64 * 64);
+    if (b >= mc) return std::min(1024, b);
+    return std::min(dtype == DEC_BPM_C128 ? 640 : 1024, b);
   }
 
   // threads per tile workgroup: the requested count, raised so that no thread
@@ -440,7 +446,9 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
   HostTiles H;
   for (int ts = E.step_tile; ts >= 64; ts /= 2) {
     if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H, true, E.sort_ring0)) continue;
-    if (size_t(H.max_slots) * 7 * sizeof(T) > 64 * 1024 || H.max_compute > 2 * 1024) continue;
+    // 64 KiB of LDS per workgroup, less 1 KiB for the persistent kernel's static arrays
+    if (size_t(H.max_slots) * 7 * sizeof(T) > 63 * 1024 || H.max_compute > 2 * (sizeof(T) == 8 ? 640 : 1024))
+      continue;
     upload_tiles<T>(E, H, dec, E.n_rows, E.stp);
     E.has_step = true;
     E.step_tile = ts;

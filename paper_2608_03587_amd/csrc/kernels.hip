@@ -1072,6 +1072,17 @@ __global__ void __launch_bounds__(1024) k_fused(DevOps<T> d, TileOps<T> tl, cons
 // every stage (stage k on rings 0..4-k; the triangle-averaged Kerr step of
 // ring 0 needs stage 4 on ring 1).  Input: the state after the previous
 // Kerr substep; output: the state after this one (owned rows).
+// Threads per workgroup the step-tile kernels are compiled for.  With two
+// compute slots per thread the complex128 kernels hold twice the operator
+// registers of the complex64 ones, so their workgroups are capped at 640
+// threads (up to 170 VGPRs per lane instead of 128; no spills).  The
+// persistent kernel keeps the 1024 bound: there, keeping every tile resident
+// (more waves per CU) matters more than the spills.
+template <typename T, int J>
+struct StepBound {
+  static constexpr int value = (sizeof(T) == 8 && J >= 2) ? 640 : 1024;
+};
+
 // One tile of the one-kernel z step: the operator rows of its compute slots
 // in registers (J slots per thread), the LIN(h) stages in Horner form on the
 // LDS-staged state, then the Kerr/absorber flow over tau on the owned rows.
@@ -1086,7 +1097,7 @@ struct StepTile {
   using C = typename CT<T>::C;
   int nLoad, n1, n2, n3, n4, nNL;
   const int32_t* ext;
-  int q[J][KMAX];
+  int q[J][KMAX];  // neighbour slots
   T cl[J][KMAX];
   T cm[J][DEC ? KMAX : 1];
   int wd[J];  // slice width (wave-uniform)
@@ -1094,6 +1105,7 @@ struct StepTile {
   T vv[J], ww[J], md[J];
 
   __device__ int32_t slot_row(int i) const { return ext[i]; }
+  __device__ int nb(int j, int k) const { return q[j][k]; }
 
   __device__ void init(const DevOps<T>& d, const TileOps<T>& tl, int64_t tile) {
     const int32_t* hd = tl.hdr + 8 * tile;
@@ -1146,12 +1158,22 @@ struct StepTile {
     }
   }
 
+  // Tells the compiler the neighbour slots may change here, so that a loop
+  // over z steps recomputes their LDS addresses in each phase instead of
+  // keeping one address per (neighbour, phase buffer) live across the loop.
+  __device__ void opaque_neighbours() {
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) asm volatile("" : "+v"(q[j][k]));
+  }
+
   // sum_k c_k (vr - V_[q_k]) over the first N entries of register slot j
   template <int N>
   __device__ void lsum_n(const C* V_, int j, const C& vr, T& ar, T& ai) const {
     C vq[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) vq[k] = V_[q[j][k]];
+    for (int k = 0; k < N; ++k) vq[k] = V_[nb(j, k)];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       ar += cl[j][k] * (vr.x - vq[k].x);
@@ -1173,7 +1195,7 @@ struct StepTile {
   __device__ T msum_n(const T* S, int j, T th) const {
     T sq[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) sq[k] = S[q[j][k]];
+    for (int k = 0; k < N; ++k) sq[k] = S[nb(j, k)];
 #pragma unroll
     for (int k = 0; k < N; ++k) th += cm[j][k] * sq[k];
     return th;
@@ -1193,7 +1215,7 @@ struct StepTile {
   __device__ void msum2_n(const C* SM, int j, T& th, T& mm) const {
     C sq[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) sq[k] = SM[q[j][k]];
+    for (int k = 0; k < N; ++k) sq[k] = SM[nb(j, k)];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       th += cm[j][k] * sq[k].x;
@@ -1312,7 +1334,7 @@ struct StepTile {
 
 // One whole z step, LIN(h) then NL(tau), per tile of rows (five halo rings).
 template <typename T, int KMAX, bool DEC, int J>
-__global__ void __launch_bounds__(1024) k_step(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ in_psi,
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_step(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ in_psi,
                                                typename CT<T>::C* __restrict__ out_psi, T h, T tau, T gamma) {
   using C = typename CT<T>::C;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1334,7 +1356,7 @@ __global__ void __launch_bounds__(1024) k_step(DevOps<T> d, TileOps<T> tl, const
 // The one-kernel step that also records, for the adjoint's forward recompute,
 // the stage vectors y1, y2, y3 and the state before the Kerr substep.
 template <typename T, int KMAX, bool DEC, int J>
-__global__ void __launch_bounds__(1024) k_step_rec(DevOps<T> d, TileOps<T> tl,
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_rec(DevOps<T> d, TileOps<T> tl,
                                                    const typename CT<T>::C* __restrict__ in_psi,
                                                    typename CT<T>::C* __restrict__ out_psi,
                                                    typename CT<T>::C* __restrict__ o_y1,
@@ -1372,7 +1394,7 @@ __global__ void __launch_bounds__(1024) k_step_rec(DevOps<T> d, TileOps<T> tl,
 // the Kerr substep, the step's y1..y3 and its input state a0.  lam_out must not
 // alias lam_in (other tiles read lam_in's halo).
 template <typename T, int KMAX, bool DEC, int J>
-__global__ void __launch_bounds__(1024) k_step_adj(DevOps<T> d, TileOps<T> tl,
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T> d, TileOps<T> tl,
                                                    const typename CT<T>::C* __restrict__ lam_in,
                                                    const typename CT<T>::C* __restrict__ fa,
                                                    const typename CT<T>::C* __restrict__ fb,
@@ -1622,6 +1644,7 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
   if (threadIdx.x < n_nb) nb_s[threadIdx.x] = nb_list[nb0 + threadIdx.x];
   __syncthreads();
   for (int32_t s = 0; s < n_steps; ++s) {
+    st.opaque_neighbours();
     const C* src = (s & 1) ? buf1 : buf0;
     C* dst = (s & 1) ? buf0 : buf1;
     if (s > 0) {
