@@ -20,7 +20,8 @@ Also reported on the same JSON line:
                 prefix of steps, single thread
   parity        GPU vs oracle after the same prefix (relative L2)
   extras        complex128 throughput; batched photonic-crystal-fibre mode vs
-                per-instance plain launches; checkpointed adjoint vs forward
+                per-instance plain launches; checkpointed adjoint vs forward;
+                the 1M-vertex vortex launch with the beta4 L^2 term
 """
 from __future__ import annotations
 
@@ -59,7 +60,8 @@ COPY_BYTES = 256 << 20
 _DOMINANT = {0: ("stage", "k_stage (RK4 stage: L gather + stage update)", 4),
              1: ("tile_a", "k_fused (stage 4 + Kerr/absorber + next stage 1 on 3-ring LDS tiles)", 1),
              2: ("step", "k_step (whole z step: 4 RK4 stages + Kerr/absorber on 5-ring LDS tiles)", 1),
-             3: ("persist", "k_persist (persistent cooperative z stepping, per step)", 1)}
+             3: ("persist", "k_persist (persistent cooperative z stepping on resident 5-ring LDS tiles, "
+                            "operator rows in registers; time and algorithmic bytes per z step)", 1)}
 
 
 def dominant_kernel_roofline(mode, kt):
@@ -245,6 +247,10 @@ def main():
             extras["adjoint"] = bench_adjoint(api, W, torch, dev, tdt)
         except Exception as e:  # noqa: BLE001
             extras["adjoint"] = {"error": repr(e)}
+        try:
+            extras["vortex_beta4"] = bench_vortex(api, W, torch, dev, tdt)
+        except Exception as e:  # noqa: BLE001
+            extras["vortex_beta4"] = {"error": repr(e)}
         out["extras"] = extras
     print(json.dumps(out))
 
@@ -371,6 +377,35 @@ def bench_adjoint(api, W, torch, dev, tdt):
            "vertices": w.mesh.n_vert, "steps": n, "objective": abs(c) ** 2,
            "grad_finite": bool(torch.isfinite(torch.view_as_real(g0)).all() and torch.isfinite(gdn).all())}
     log(f"[bench] adjoint: {t_a / t_f:.2f}x forward (checkpointed fwd + adjoint {res['total_over_forward']:.2f}x)")
+    return res
+
+
+def bench_vortex(api, W, torch, dev, tdt):
+    """Vortex launch with the beta4 L^2 term: uniform disk of radius 60 with ~1M vertices, complex64,
+    a 1000-step stretch of the 10,000-step run (the beta4 term runs on the five-kernel path)."""
+    t0 = time.time()
+    w = W.vortex_beta4()
+    N = w.mesh.n_vert
+    log(f"[bench] vortex_beta4 mesh: {N} vertices ({time.time() - t0:.1f} s)")
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype="c64", p1=w.p1, beta4=w.beta4)
+    m.autotune(w.dz, w.gamma)
+    f = torch.from_numpy(w.u0).to(dev, tdt["c64"])
+    m.propagate(f, w.dz, 50, w.gamma)
+    f = torch.from_numpy(w.u0).to(dev, tdt["c64"])
+    steps = 1000
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    m.propagate(f, w.dz, steps, w.gamma)
+    e1.record()
+    torch.cuda.synchronize()
+    m.check_finite()
+    ms = e0.elapsed_time(e1)
+    kt = m.time_kernels(w.dz, w.gamma, reps=50)
+    res = {"value": N * steps / (ms * 1e-3), "unit": "vertex z-steps/s", "ms_per_step": ms / steps, "steps": steps,
+           "vertices": N, "rho_dz": m.spectral_radius() * w.dz, "tuning": m.tuning,
+           "kernels_us": {c: v["ms"] * 1e3 for c, v in kt.items() if v["ms"] > 0}}
+    log(f"[bench] vortex_beta4: {res['value']:.3e} vertex z-steps/s ({res['ms_per_step'] * 1e3:.1f} us per step)")
     return res
 
 
