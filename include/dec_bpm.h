@@ -230,7 +230,8 @@ int dec_bpm_batch_propagate(dec_bpm_batch_t b, void* packed_fields, double dz, i
  * runs two kernels per z step (stages 2+3, and stage 4 + Kerr/absorber + next
  * stage 1, each on a tile of rows with three halo rings in LDS); fused = 2
  * runs the whole z step (four stages + Kerr/absorber) as one kernel on tiles
- * with five halo rings (four for the lumped nonlinearity); fused = 3 runs all
+ * with five halo rings (four for the lumped nonlinearity; with the beta4 term
+ * two rings per stage, nine or eight); fused = 3 runs all
  * middle steps of a propagate in one persistent cooperative launch on those
  * tiles, every tile resident with its operator rows in registers, tiles
  * synchronising with their neighbour tiles only (available when all tiles fit

@@ -46,13 +46,14 @@ struct DevTiles {
   void* llw = nullptr;
   void* lmw = nullptr;
   int64_t entries = 0, slots = 0;
-  int32_t ext_stride = 0, lsl_stride = 0;
+  int32_t ext_stride = 0, lsl_stride = 0, hdr_stride = 8;
 
   template <typename T>
   TileOps<T> ops() const {
     TileOps<T> t;
     t.ext_stride = ext_stride;
     t.lsl_stride = lsl_stride;
+    t.hdr_stride = hdr_stride;
     t.n_tiles = n_tiles;
     t.TS = TS;
     t.max_slots = max_slots;
@@ -107,6 +108,7 @@ struct Engine {
   int tile_block = 256;
   DevTiles tl, bt, stp;  // two-kernel tiles (3 rings), batched tiles, one-kernel-step tiles (5 rings)
   bool has_step = false;
+  bool has_step4 = false;  // the step tiles hold the beta4 layout (eight or nine rings)
   int step_tile = 1024;  // rows per tile of the one-kernel step (largest that fits)
   bool sort_ring0 = true;  // step tiles: order the owned rows by degree too
   // persistent stepping on the step tiles: neighbour-tile lists, flags, wait bound
@@ -256,6 +258,7 @@ struct HostTiles {
   std::vector<double> llw, lmw;
   int32_t max_slots = 0, max_compute = 0;
   int32_t ext_stride = 0, lsl_stride = 0;  // step layout: fixed per-tile strides
+  int32_t hdr_stride = 8;
 };
 
 // Tiles of TS consecutive rows with `rings` halo rings (breadth-first over the
@@ -270,11 +273,12 @@ struct HostTiles {
 static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
                        const std::vector<double>& alw, const std::vector<double>& amw, int TS, int rings,
                        int ell_rings, HostTiles& H, bool step_layout = false, bool sort_ring0 = true) {
-  if (rings > 5 || ell_rings > rings + 1) fail(DEC_BPM_EINVAL, "internal: unsupported ring count");
+  if (rings > (step_layout ? 9 : 5) || ell_rings > rings + 1) fail(DEC_BPM_EINVAL, "internal: unsupported ring count");
   H = HostTiles();
   H.TS = TS;
   H.nt = (n + TS - 1) / TS;
-  H.hdr.assign(H.nt * 8, 0);
+  H.hdr_stride = step_layout ? 16 : 8;
+  H.hdr.assign(H.nt * H.hdr_stride, 0);
   H.ebase.resize(H.nt);
   std::vector<int32_t> slot_of(n, -1);
   std::vector<int32_t> slots, ring;
@@ -291,7 +295,7 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
       slot_of[r] = int32_t(r - r0);
       slots.push_back(int32_t(r));
     }
-    int cnt[6] = {int(r1 - r0), 0, 0, 0, 0, 0};
+    int cnt[10] = {int(r1 - r0), 0, 0, 0, 0, 0, 0, 0, 0, 0};
     size_t start = 0, end = slots.size();
     for (int k = 1; k <= rings; ++k) {
       ring.clear();
@@ -324,9 +328,11 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
       }
       for (size_t i = 0; i < slots.size(); ++i) slot_of[slots[i]] = int32_t(i);
     }
-    int32_t* h = &H.hdr[t * 8];
-    if (step_layout) {  // counts of rings 0..5 (offsets come from the strides)
-      for (int k = 0; k < 6; ++k) h[k] = cnt[k];
+    int32_t* h = &H.hdr[t * H.hdr_stride];
+    if (step_layout) {  // cumulative counts of rings 0..k, ring count (offsets come from the strides)
+      int c = 0;
+      for (int k = 0; k < 10; ++k) h[k] = (c += cnt[k]);
+      h[15] = rings;
       ext_t[t] = slots;
     } else if (rings <= 3) {  // counts of rings 0..3, ext base, slice-table base
       for (int k = 0; k < 4; ++k) h[k] = cnt[k];
@@ -417,6 +423,7 @@ static void upload_tiles(Engine& E, const HostTiles& H, bool dec, int64_t n, Dev
   D.slots = int64_t(H.ext.size()) + n;
   D.ext_stride = H.ext_stride;
   D.lsl_stride = H.lsl_stride;
+  D.hdr_stride = H.hdr_stride;
 }
 
 // Plain fused path: the largest tile size (from the requested one, halving)
@@ -442,26 +449,35 @@ template <typename T>
 static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
                              const std::vector<double>& alw, const std::vector<double>& amw, bool dec) {
   if (E.wmax > 12) return;
-  const int rings = dec ? 5 : 4;
+  // without beta4: five rings (four for the lumped Kerr term), 7 reals of LDS
+  // per slot; with beta4: two rings per stage, nine (eight), 9 reals per slot
+  const bool b4 = E.beta4 != 0.0;
+  const int rings = (b4 ? 8 : 4) + (dec ? 1 : 0);
+  const size_t lds_reals = b4 ? 9 : 7;
+  // LDS per workgroup: 63 KiB (the persistent kernel's static arrays take the
+  // rest of 64 KiB, and two workgroups share a CU's 160 KiB).  The beta4 step
+  // (never persistent) may use up to 100 KiB and, in complex64, three compute
+  // slots per thread, so that its nine-ring tiles keep 1024 owned rows.
+  const size_t lds_max = b4 ? 100 * 1024 : 63 * 1024;
+  const int max_compute = sizeof(T) == 8 ? 2 * 640 : (b4 ? 3 : 2) * 1024;
   HostTiles H;
+  bool built = false;
   for (int ts = E.step_tile; ts >= 64; ts /= 2) {
     if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H, true, E.sort_ring0)) continue;
-    // 64 KiB of LDS per workgroup, less 1 KiB for the persistent kernel's static arrays
-    if (size_t(H.max_slots) * 7 * sizeof(T) > 63 * 1024 || H.max_compute > 2 * (sizeof(T) == 8 ? 640 : 1024))
-      continue;
+    if (size_t(H.max_slots) * lds_reals * sizeof(T) > lds_max || H.max_compute > max_compute) continue;
     upload_tiles<T>(E, H, dec, E.n_rows, E.stp);
-    E.has_step = true;
+    (b4 ? E.has_step4 : E.has_step) = true;
     E.step_tile = ts;
+    built = true;
     break;
   }
-  if (!E.has_step) return;
+  if (!built || b4) return;
   // tiles owning the halo rows of each tile (the persistent kernel's wait set)
   std::vector<int32_t> ptr(H.nt + 1, 0), list, seen(H.nt, -1);
   bool fits = true;
   for (int64_t t = 0; t < H.nt; ++t) {
-    const int32_t* h = &H.hdr[t * 8];
-    int32_t halo = 0;
-    for (int k = 1; k < 6; ++k) halo += h[k];
+    const int32_t* h = &H.hdr[t * H.hdr_stride];
+    const int32_t halo = h[h[15]] - h[0];
     int cnt = 0;
     for (int32_t i = 0; i < halo; ++i) {
       const int32_t u = int32_t(H.ext[t * H.ext_stride + h[0] + i] / H.TS);
@@ -620,14 +636,12 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   E.h0c = static_cast<double*>(p);
   upload(E, p, perm);
   E.perm = static_cast<int32_t*>(p);
-  if (E.F == 1 && E.beta4 == 0.0) {
-    build_tiles<T>(E, arp, acol, alw, amw, any_dec);
-    build_step_tiles<T>(E, arp, acol, alw, amw, any_dec);
-  }
+  if (E.F == 1 && E.beta4 == 0.0) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  if (E.F == 1) build_step_tiles<T>(E, arp, acol, alw, amw, any_dec);
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
   const size_t nv = size_t(n) * E.F;
   E.psi = E.dalloc(nv * 2 * sizeof(T));
-  if (E.has_tiles || E.has_step) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
+  if (E.has_tiles || E.has_step || E.has_step4) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
   E.ya = E.dalloc(nv * 2 * sizeof(T));
   E.yb = E.dalloc(nv * 2 * sizeof(T));
   E.t = E.beta4 != 0.0 ? E.dalloc(nv * 2 * sizeof(T)) : nullptr;
@@ -647,7 +661,7 @@ static void build_engine(Engine& E, const std::vector<const Assembled*>& meshes,
     build_engine_t<float>(E, meshes, lumped);
   else
     build_engine_t<double>(E, meshes, lumped);
-  if (E.fused < 0) E.fused = E.has_step ? 2 : ((E.has_tiles || E.has_btiles) ? 1 : 0);
+  if (E.fused < 0) E.fused = (E.has_step || E.has_step4) ? 2 : ((E.has_tiles || E.has_btiles) ? 1 : 0);
 }
 
 static void check_launch() {
@@ -756,11 +770,13 @@ static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl,
   launch_fused<T>(d, tl, FUSED_S4_NL_S1, E.yb, cur, nxt, E.ya, nullptr, dz, dz, gamma, E.tblock(), st);
 }
 
-// Launch mode of the middle steps: 0 = five kernels, 1 = two tile kernels,
-// 2 = one tile kernel per step, 3 = one persistent launch for all of them
-// (modes whose tiles are missing fall back to the five kernels).
+// Launch mode of the middle steps: 0 = five kernels (nine with beta4), 1 = two
+// tile kernels, 2 = one tile kernel per step, 3 = one persistent launch for all
+// of them, 4 = one tile kernel per step with the beta4 term (modes whose tiles
+// are missing fall back to the row kernels).
 template <typename T>
 static int mode_of(Engine& E) {
+  if (E.has_step4) return E.fused >= 2 ? 4 : 0;  // beta4: its one-kernel step or the five kernels
   if (use_persist<T>(E)) return 3;
   if (E.fused == 3 && E.has_step) return 2;
   return use_step<T>(E) ? 2 : (use_fused<T>(E) ? 1 : 0);
@@ -772,7 +788,7 @@ static void* state_before(const Engine& E, int mode, int64_t k) {
   if (mode == 0) return E.psi;
   const bool odd = k % 2;
   if (mode == 1) return odd ? E.psi : E.psi2;
-  return odd ? E.psi2 : E.psi;  // modes 2 and 3
+  return odd ? E.psi2 : E.psi;  // modes 2, 3 and 4
 }
 
 template <typename T>
@@ -782,9 +798,12 @@ static void middle_step(const Engine& E, const DevOps<T>& d, int mode, int64_t k
     z_step<T>(E, d, dz, gamma, dz, st);
   } else if (mode == 1) {
     fused_mid<T>(E, d, E.tiles<T>(), state_before(E, 1, k), state_before(E, 1, k + 1), dz, gamma, st);
-  } else {
+  } else if (mode == 2) {
     launch_step<T>(d, E.stp.template ops<T>(), state_before(E, 2, k), state_before(E, 2, k + 1), dz, dz, gamma,
                    E.sblock(), st);
+  } else {
+    launch_step_b4<T>(d, E.stp.template ops<T>(), state_before(E, 4, k), state_before(E, 4, k + 1), dz, dz, gamma,
+                      E.sblock(), st);
   }
 }
 
@@ -794,7 +813,7 @@ static int graph_steps(const Engine& E, int mode) { return mode ? std::max(2, E.
 
 template <typename T>
 static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, int mode) {
-  const int tb = mode == 1 ? E.tblock() : (mode == 2 ? E.sblock() : 0);
+  const int tb = mode == 1 ? E.tblock() : (mode >= 2 ? E.sblock() : 0);
   for (auto& g : E.graphs)
     if (g.dz == dz && g.gamma == gamma && g.spg == E.spg && g.block == E.block && g.xcd == E.xcd &&
         g.fused == mode && g.tile_block == tb)
@@ -891,7 +910,10 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
     void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
     void* nxt = cur == E.psi ? E.psi2 : E.psi;
-    launch_step<T>(d, E.stp.template ops<T>(), cur, nxt, dz, 0.5 * dz, gamma, E.sblock(), st);
+    if (mode == 4)
+      launch_step_b4<T>(d, E.stp.template ops<T>(), cur, nxt, dz, 0.5 * dz, gamma, E.sblock(), st);
+    else
+      launch_step<T>(d, E.stp.template ops<T>(), cur, nxt, dz, 0.5 * dz, gamma, E.sblock(), st);
     launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
   } else {
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
@@ -1193,7 +1215,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   HIP_OK(hipEventCreate(&e1));
   for (int kind = 0; kind < DEC_BPM_NUM_KERNELS; ++kind) {
     const bool tile_kind = kind == DEC_BPM_K_TILE_A || kind == DEC_BPM_K_TILE_B;
-    if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step) ||
+    if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step && !E.has_step4) ||
         (kind == DEC_BPM_K_PERSIST && !(E.has_persist && persist_fits<T>(E)))) {
       if (ms) ms[kind] = 0.0;
       if (bytes) bytes[kind] = 0.0;
@@ -1224,7 +1246,10 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
         launch_fused<T>(d, tl, FUSED_S4_NL_S1, E.yb, E.psi, E.psi2, E.ya, nullptr, dz, dz, gamma, E.tblock(), E.cap);
       if (kind == DEC_BPM_K_TILE_B)
         launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, E.psi, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), E.cap);
-      if (kind == DEC_BPM_K_STEP)
+      if (kind == DEC_BPM_K_STEP && E.has_step4)
+        launch_step_b4<T>(d, E.stp.template ops<T>(), r % 2 ? E.psi2 : E.psi, r % 2 ? E.psi : E.psi2, dz, dz,
+                          gamma, E.sblock(), E.cap);
+      else if (kind == DEC_BPM_K_STEP)
         launch_step<T>(d, E.stp.template ops<T>(), r % 2 ? E.psi2 : E.psi, r % 2 ? E.psi : E.psi2, dz, dz, gamma,
                        E.sblock(), E.cap);
     }
@@ -1251,7 +1276,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
 static std::string tune_key(const Engine& E) {
   std::ostringstream o;
   o << "n" << E.n_rows << "_e" << E.n_entries << "_F" << E.F << "_d" << E.dtype << "_b4" << (E.beta4 != 0.0) << "_nl"
-    << (E.mw ? 0 : 1) << "_ts" << (E.has_tiles ? E.tile_size : 0) << "_st" << (E.has_step ? E.step_tile : 0);
+    << (E.mw ? 0 : 1) << "_ts" << (E.has_tiles ? E.tile_size : 0) << "_st" << ((E.has_step || E.has_step4) ? E.step_tile : 0);
   return o.str();
 }
 
@@ -1272,7 +1297,7 @@ static bool tune_cache_lookup(Engine& E) {
       E.block = b;
       E.spg = s;
       E.xcd = x;
-      E.fused = (E.has_tiles || E.has_btiles || E.has_step) ? fu : 0;
+      E.fused = (E.has_tiles || E.has_btiles || E.has_step || E.has_step4) ? fu : 0;
       E.tile_block = tb;
       return true;
     }
@@ -1315,7 +1340,7 @@ static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
       for (int b : {64, 128, 256, 512, 1024}) cands.push_back({0, b, E.tile_block, s, x});
       if (E.has_tiles)
         for (int tb : {128, 256, 512, 1024}) cands.push_back({1, E.block, tb, s, x});
-      if (E.has_step)
+      if (E.has_step || E.has_step4)
         for (int tb : {256, 512, 1024}) cands.push_back({2, E.block, tb, s, x});
       if (E.has_persist && s == 32)  // one launch runs every step: steps per graph do not apply
         for (int tb : {256, 512, 1024}) cands.push_back({3, E.block, tb, s, x});
@@ -1847,7 +1872,7 @@ int dec_bpm_batch_autotune(dec_bpm_batch_t b, double dz, double gamma, void* str
 static void get_tuning(const Engine& E, dec_bpm_tuning* t) {
   t->block_size = E.block;
   t->steps_per_graph = E.spg;
-  t->fused = (E.has_tiles || E.has_btiles || E.has_step) ? E.fused : 0;
+  t->fused = (E.has_tiles || E.has_btiles || E.has_step || E.has_step4) ? E.fused : 0;
   t->tile_block = E.has_tiles ? E.tblock() : E.tile_block;
   t->xcd_remap = E.xcd;
 }

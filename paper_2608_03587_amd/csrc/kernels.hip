@@ -1106,6 +1106,7 @@ template <typename T, int KMAX, bool DEC, int J>
 struct StepTile {
   using C = typename CT<T>::C;
   int nLoad, n1, n2, n3, n4, nNL;
+  const int32_t* hd;
   const int32_t* ext;
   int q[J][KMAX];  // neighbour slots
   T cl[J][KMAX];
@@ -1118,21 +1119,17 @@ struct StepTile {
   __device__ int nb(int j, int k) const { return q[j][k]; }
 
   __device__ void init(const DevOps<T>& d, const TileOps<T>& tl, int64_t tile) {
-    const int32_t* hd = tl.hdr + 8 * tile;
+    hd = tl.hdr + int64_t(tl.hdr_stride) * tile;  // hd[k]: slots in rings 0..k; hd[15]: rings
     ext = tl.ext + tile * int64_t(tl.ext_stride);
     const int32_t* __restrict__ lsl = tl.lsl + tile * int64_t(tl.lsl_stride);
     const int64_t ebase = tl.ent_base[tile];
-    int cr[6];  // cr[k] = slots in rings 0..k
-    cr[0] = hd[0];
-#pragma unroll
-    for (int k = 1; k < 6; ++k) cr[k] = cr[k - 1] + hd[k];
-    const int o = DEC ? 1 : 0;
-    nLoad = cr[4 + o];
-    n1 = cr[3 + o];
-    n2 = cr[2 + o];
-    n3 = cr[1 + o];
-    n4 = cr[o];
-    nNL = cr[0];
+    const int R = hd[15];
+    nLoad = hd[R];
+    n1 = hd[R - 1];  // slots with operator rows
+    n2 = hd[R - 2];
+    n3 = hd[R - 3];
+    n4 = hd[R - 4];
+    nNL = hd[0];
     const int B = blockDim.x;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -1342,6 +1339,82 @@ struct StepTile {
       }
     }
   }
+
+  // The same z step with the beta4 L^2 term: H v = p1 L v + beta4 L(L v) - V v.
+  // Each stage takes two gather phases (t = L v into T, then L t), so the
+  // state is staged on 8 halo rings (9 with the triangle-averaged Kerr
+  // gather) and each stage shrinks the valid region by two rings.
+  template <typename V, typename Out>
+  __device__ void step_b4(const DevOps<T>& d, const V& P, const V& X, const V& Y, const V& Tb, T* S, T h, T tau,
+                          T gamma, Out out) const {
+    const int B = blockDim.x;
+    const int R = hd[15];
+    C p[J], cur[J], tl[J];
+    T so[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n1) {
+        p[j] = P.get(i);
+        cur[j] = p[j];
+      }
+    }
+    const T coefs[4] = {T(0.25) * h, h / T(3), T(0.5) * h, h};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const V& Vin = k == 0 ? P : ((k & 1) ? Y : X);  // y1 -> Y, y2 -> X, y3 -> Y
+      const V& Vout = (k & 1) ? X : Y;
+      const int na = hd[R - 1 - 2 * k], nb_ = hd[R - 2 - 2 * k];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {  // t = L v
+        const int i = threadIdx.x + j * B;
+        if (i < na) {
+          T ar = T(0), ai = T(0);
+          lsum_w<KMAX>(wd[j], Vin, j, cur[j], ar, ai);
+          tl[j].x = ar;
+          tl[j].y = ai;
+          Tb.put(i, tl[j]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < J; ++j) {  // y = p + coef (-i) (p1 t + beta4 L t - V v)
+        const int i = threadIdx.x + j * B;
+        if (i < nb_) {
+          T ar = T(0), ai = T(0);
+          lsum_w<KMAX>(wd[j], Tb, j, tl[j], ar, ai);
+          const T hr = d.p1 * tl[j].x + d.beta4 * ar - vv[j] * cur[j].x;
+          const T hi = d.p1 * tl[j].y + d.beta4 * ai - vv[j] * cur[j].y;
+          C y;
+          y.x = p[j].x + coefs[k] * hi;
+          y.y = p[j].y - coefs[k] * hr;
+          cur[j] = y;
+          if (k < 3) Vout.put(i, y);
+          else {
+            so[j] = (y.x * y.x + y.y * y.y) * phi_w(ww[j], tau);
+            S[i] = so[j];
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < nNL) {
+        T th = md[j] * so[j];
+        if constexpr (DEC) th = msum_w<KMAX>(wd[j], S, j, th);
+        const T damp = d_exp(-ww[j] * tau);
+        T sn, cs;
+        d_sincos(gamma * th, &sn, &cs);
+        const C b = cur[j];
+        C r;
+        r.x = damp * (b.x * cs - b.y * sn);
+        r.y = damp * (b.x * sn + b.y * cs);
+        out(i, rr[j], r);
+      }
+    }
+  }
 };
 
 // One whole z step, LIN(h) then NL(tau), per tile of rows (five halo rings).
@@ -1362,6 +1435,27 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step(DevOps<T> d, 
   __syncthreads();
   st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out_psi[r] = v; },
           [](int, int32_t, const C&) {});
+}
+
+// One whole z step with the beta4 L^2 term per tile (8 or 9 halo rings).
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_b4(DevOps<T> d, TileOps<T> tl,
+                                                                     const typename CT<T>::C* __restrict__ in_psi,
+                                                                     typename CT<T>::C* __restrict__ out_psi, T h,
+                                                                     T tau, T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  C* base = reinterpret_cast<C*>(smem);
+  const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS}, Tb{base + 3 * MS};
+  T* S = reinterpret_cast<T*>(base + 4 * MS);
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P.put(i, in_psi[st.slot_row(i)]);
+  __syncthreads();
+  st.step_b4(d, P, X, Y, Tb, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out_psi[r] = v; });
 }
 
 // The one-kernel step that also records, for the adjoint's forward recompute,
@@ -1425,11 +1519,9 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
   C* SM = U + MS;                      // (|b|^2 phi, mu) per slot
   StepTile<T, KMAX, DEC, J> st;
   st.init(d, tl, tile);
-  const int32_t* hd = tl.hdr + 8 * tile;
-  int cr[5];
-  cr[0] = hd[0];
+  int cr[5];  // slots in rings 0..k
 #pragma unroll
-  for (int k = 1; k < 5; ++k) cr[k] = cr[k - 1] + hd[k];
+  for (int k = 0; k < 5; ++k) cr[k] = st.hd[k];
   // Kerr adjoint rows: rings 0..4 (triangle-averaged: gathered in a phase of
   // its own; lumped: pointwise, done while staging)
   for (int i = threadIdx.x; i < st.nLoad; i += B) {
@@ -2190,6 +2282,27 @@ void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, v
 }
 
 template <typename T>
+void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
+                    double tau, double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * (4 * sizeof(typename CT<T>::C) + sizeof(T));
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_STEP4(KM, DEC, JJ)                                                                              \
+  hipLaunchKernelGGL((k_step_b4<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi),  \
+                     DECBPM_M(T, out_psi), T(h), T(tau), T(gamma))
+#define DECBPM_STEP4_J(KM, DEC) \
+  if (J <= 1) DECBPM_STEP4(KM, DEC, 1); else if (J == 2) DECBPM_STEP4(KM, DEC, 2); else DECBPM_STEP4(KM, DEC, 3);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_STEP4_J(8, true) } else { DECBPM_STEP4_J(8, false) }
+  } else {
+    if (dec) { DECBPM_STEP4_J(12, true) } else { DECBPM_STEP4_J(12, false) }
+  }
+#undef DECBPM_STEP4_J
+#undef DECBPM_STEP4
+}
+
+template <typename T>
 void launch_step_rec(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, void* y1, void* y2,
                      void* y3, void* b, double h, double tau, double gamma, int block, hipStream_t st) {
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
@@ -2416,6 +2529,8 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   template void launch_step<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double,   \
                                int, hipStream_t);                                                                \
   template int persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int);                                     \
+  template void launch_step_b4<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double, \
+                                  int, hipStream_t);                                                             \
   template void launch_step_rec<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, void*, void*, void*,    \
                                    void*, double, double, double, int, hipStream_t);                             \
   template void launch_step_adj<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*,     \

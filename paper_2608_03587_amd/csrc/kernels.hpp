@@ -52,8 +52,9 @@ struct TileOps {
   int32_t TS;
   int32_t max_slots;        // largest slot count of a tile (all rings), LDS sizing
   int32_t max_compute;      // largest count of slots with operator rows
-  const int32_t* hdr;       // [n_tiles * 8]: ring counts, ext base, slice-table base (three rings:
-                            // nT, nH1, nH2, nH3, ext, lsl, 0, 0; five: nT, nH1..nH5, ext, lsl)
+  const int32_t* hdr;       // [n_tiles * hdr_stride].  Classic layout (stride 8): ring counts nT,
+                            // nH1..nH3, ext base, slice-table base.  Step layout (stride 16):
+                            // cumulative slot counts of rings 0..k for k = 0..9, [15] = ring count
   const int64_t* ent_base;  // [n_tiles]
   const int32_t* ext;       // halo rows (device order)
   const int32_t* lsl;
@@ -62,6 +63,7 @@ struct TileOps {
   const T* lmw;             // nullptr for the lumped nonlinearity
   int32_t ext_stride;       // step layout: per-tile stride of ext (every slot listed) and of lsl;
   int32_t lsl_stride;       // 0: classic layout (offsets in the header, ring 0 implicit)
+  int32_t hdr_stride;       // ints per tile header (8 classic, 16 step layout)
 };
 
 enum FusedKind { FUSED_S4_NL_S1 = 0, FUSED_S2_S3 = 1, FUSED_NL_S1 = 2, FUSED_S4_NL = 3 };
@@ -168,6 +170,11 @@ void launch_bkerr(const DevOps<T>& d, const TileOps<T>& tl, const void* psi_in, 
 template <typename T>
 void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h, double tau,
                  double gamma, int block, hipStream_t st);
+// One whole z step with the beta4 L^2 term (two gathers per stage) on tiles of
+// 8 halo rings (9 with the triangle-averaged Kerr term).
+template <typename T>
+void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
+                    double tau, double gamma, int block, hipStream_t st);
 
 // The one-kernel step that also writes the owned rows' stage vectors y1..y3
 // and the state before the Kerr substep (the adjoint's forward recompute).

@@ -166,6 +166,39 @@ def test_vortex_beta4_replica_end_to_end(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_beta4_one_kernel_step_matches_row_kernels_and_oracle(dtype, nl):
+    """The beta4 one-kernel step (two gathers per stage on tiles of eight or
+    nine halo rings) against the nine-kernel row path and the oracle."""
+    w = case("vortex", n_vert=20000, n_steps=10)
+    say("beta4 step", dtype, nl, w.mesh.n_vert)
+    ops = oracle_ops(w, nl)
+    m = lib_mesh(w, dtype, nl)
+    assert m.tuning["fused"] == 2  # the beta4 step tiles exist
+    u = dev(w.u0, dtype)
+    for n in (1, 2, 3, 37):
+        outs = {}
+        for fused, spg in ((2, 1), (2, 16), (0, 16)):
+            m.tuning = {"fused": fused, "steps_per_graph": spg}
+            f = u.clone()
+            m.propagate(f, w.dz, n, w.gamma)
+            outs[(fused, spg)] = host(f)
+        assert np.array_equal(outs[(2, 1)], outs[(2, 16)]), n  # graph replay == eager
+        tol = 1e-13 if dtype == "c128" else 1e-5
+        assert rel(outs[(2, 16)], outs[(0, 16)]) < tol, (n, rel(outs[(2, 16)], outs[(0, 16)]))
+        ref = S.propagate(w.u0, ops, w.dz, n, w.gamma)
+        assert rel(outs[(2, 16)], ref) < GATE[dtype], n
+        if n == 37:
+            keep = outs[(2, 16)]
+    for tb in (256, 1024):  # one or two slots per thread: separate instantiations, rounding may differ
+        m.tuning = {"fused": 2, "tile_block": tb, "steps_per_graph": 16}
+        f = u.clone()
+        m.propagate(f, w.dz, 37, w.gamma)
+        assert rel(host(f), keep) < KERNEL_TOL[dtype], tb
+    assert m.time_kernels(w.dz, w.gamma, reps=10)["step"]["ms"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_step_index_full_size_prefix(dtype):
     """The full 250k-vertex step-index workload, 20 steps, in the bench's launch configuration."""
     w = case("step_index")
