@@ -225,20 +225,21 @@ int dec_bpm_batch_propagate(dec_bpm_batch_t b, void* packed_fields, double dz, i
  * block size; fused LDS-tiled path: threads per tile; both: z steps per
  * hipGraph and the XCD-aware block mapping) on the handle's own work buffers
  * with HIP events and keeps the fastest; the result is cached in the JSON file
- * named by DEC_BPM_TUNE_CACHE if that variable is set.  Synchronises.  Two
- * fused paths exist for one-field handles without the beta4 term: fused = 1
- * runs two kernels per z step (stages 2+3, and stage 4 + Kerr/absorber + next
+ * named by DEC_BPM_TUNE_CACHE if that variable is set.  Synchronises.
+ * Fused paths of one-field handles: fused = 1 (without the beta4 term) runs
+ * two kernels per z step (stages 2+3, and stage 4 + Kerr/absorber + next
  * stage 1, each on a tile of rows with three halo rings in LDS); fused = 2
  * runs the whole z step (four stages + Kerr/absorber) as one kernel on tiles
  * with five halo rings (four for the lumped nonlinearity; with the beta4 term
- * two rings per stage, nine or eight); fused = 3 runs all
- * middle steps of a propagate in one persistent cooperative launch on those
- * tiles, every tile resident with its operator rows in registers, tiles
+ * two rings per stage: nine, or eight); fused = 3 (without the beta4 term)
+ * runs all middle steps of a propagate in one persistent cooperative launch on
+ * those tiles, every tile resident with its operator rows in registers, tiles
  * synchronising with their neighbour tiles only (available when all tiles fit
- * on the device at once; otherwise fused = 3 runs as fused = 2).  A handle
- * that has no tiles for the requested mode runs the unfused kernels.  A
- * persistent neighbour wait that exceeds its bound (DEC_BPM_SPIN_LIMIT polls,
- * default 2^20) leaves the launch early and makes the next
+ * on the device at once; otherwise, and with the beta4 term, fused = 3 runs
+ * as fused = 2).  A handle that has no tiles for the requested mode runs the
+ * unfused kernels.  A persistent neighbour wait that exceeds its bound
+ * (DEC_BPM_SPIN_LIMIT polls, default 2^20) leaves the launch early and makes
+ * the next
  * dec_bpm_check_finite report DEC_BPM_ENONFINITE.
  */
 typedef struct {
