@@ -214,9 +214,14 @@ def test_step_index_full_size_prefix(dtype):
     assert err < GATE[dtype]
 
 
-def test_edge_cases_and_launch_paths():
+@pytest.mark.parametrize("fused", [0, 1, 2, 3])
+def test_edge_cases_and_launch_paths(fused):
+    """Zero, one, two and odd step counts, graph replay vs eager, block sizes
+    and chunked calls, in every launch mode (4k-vertex mesh: four step tiles)."""
     w = case("plain_small")
     m = lib_mesh(w, "c128")
+    m.tuning = {"fused": fused}
+    say("edge cases, mode", fused)
     ops = oracle_ops(w)
     u = dev(w.u0, "c128")
     f = u.clone()
@@ -227,7 +232,7 @@ def test_edge_cases_and_launch_paths():
         m.propagate(f, w.dz, n, 1.0)
         assert rel(host(f), S.propagate(w.u0, ops, w.dz, n, 1.0)) < 1e-12, n
     # graph and eager launches produce identical bits
-    m.tuning = {"block_size": 256, "steps_per_graph": 1}
+    m.tuning = {"block_size": 256, "steps_per_graph": 1, "fused": fused}
     a = u.clone()
     m.propagate(a, w.dz, 70, 1.0)
     m.tuning = {"block_size": 256, "steps_per_graph": 16}
@@ -249,6 +254,20 @@ def test_edge_cases_and_launch_paths():
     m.propagate(e, w.dz, 35, 1.0)
     m.propagate(e, w.dz, 35, 1.0)
     assert rel(host(e), host(b)) < 1e-13
+
+
+@pytest.mark.parametrize("fused", [2, 3])
+def test_single_tile_mesh(fused):
+    """A mesh of one step tile: no halo rows, no neighbour tiles to wait for."""
+    w = W.plain_small(n_vert=700, n_steps=10)
+    m = lib_mesh(w, "c128")
+    m.tuning = {"fused": fused}
+    ops = oracle_ops(w)
+    for n in (1, 2, 5, 40):
+        f = dev(w.u0, "c128")
+        m.propagate(f, w.dz, n, 1.0)
+        m.check_finite()
+        assert rel(host(f), S.propagate(w.u0, ops, w.dz, n, 1.0)) < 1e-12, n
 
 
 def test_nonfinite_is_flagged():
