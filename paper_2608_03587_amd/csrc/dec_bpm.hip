@@ -454,11 +454,12 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
   const bool b4 = E.beta4 != 0.0;
   const int rings = (b4 ? 8 : 4) + (dec ? 1 : 0);
   const size_t lds_reals = b4 ? 9 : 7;
-  // LDS per workgroup: 63 KiB (the persistent kernel's static arrays take the
-  // rest of 64 KiB, and two workgroups share a CU's 160 KiB).  The beta4 step
-  // (never persistent) may use up to 100 KiB and, in complex64, three compute
-  // slots per thread, so that its nine-ring tiles keep 1024 owned rows.
-  const size_t lds_max = b4 ? 100 * 1024 : 63 * 1024;
+  // LDS per workgroup: 63 KiB in complex64 (two workgroups then share a CU's
+  // 160 KiB).  Complex128 and the beta4 step may use up to 100 KiB, so that
+  // their tiles keep 512 owned rows (the halo work of 256-row tiles doubles
+  // it); the beta4 step also takes three compute slots per thread in
+  // complex64.
+  const size_t lds_max = (b4 || sizeof(T) == 8) ? 100 * 1024 : 63 * 1024;
   const int max_compute = sizeof(T) == 8 ? 2 * 640 : (b4 ? 3 : 2) * 1024;
   HostTiles H;
   bool built = false;
