@@ -450,16 +450,20 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
                              const std::vector<double>& alw, const std::vector<double>& amw, bool dec) {
   if (E.wmax > 12) return;
   // without beta4: five rings (four for the lumped Kerr term), 7 reals of LDS
-  // per slot; with beta4: two rings per stage, nine (eight), 9 reals per slot
+  // per slot; with beta4: two rings per stage, nine (eight), 9 reals per slot;
+  // batched handles: VF fields per slot (32 bytes of each state vector), no beta4
   const bool b4 = E.beta4 != 0.0;
+  const bool batched = E.F > 1;
+  const int VF = int(32 / (2 * sizeof(T)));  // fields per slot of the batched step kernel
+  if (batched && (b4 || E.F % VF != 0)) return;
   const int rings = (b4 ? 8 : 4) + (dec ? 1 : 0);
-  const size_t lds_reals = b4 ? 9 : 7;
+  const size_t lds_reals = batched ? size_t(7 * VF) : (b4 ? 9 : 7);
   // LDS per workgroup: 63 KiB in complex64 (two workgroups then share a CU's
   // 160 KiB).  Complex128 and the beta4 step may use up to 100 KiB, so that
   // their tiles keep 512 owned rows (the halo work of 256-row tiles doubles
   // it); the beta4 step also takes three compute slots per thread in
   // complex64.
-  const size_t lds_max = (b4 || sizeof(T) == 8) ? 100 * 1024 : 63 * 1024;
+  const size_t lds_max = batched ? 150 * 1024 : ((b4 || sizeof(T) == 8) ? 100 * 1024 : 63 * 1024);
   const int max_compute = sizeof(T) == 8 ? 2 * 640 : (b4 ? 3 : 2) * 1024;
   HostTiles H;
   bool built = false;
@@ -472,7 +476,7 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
     built = true;
     break;
   }
-  if (!built || b4) return;
+  if (!built || b4 || batched) return;  // the persistent kernel takes one-field handles only
   // tiles owning the halo rows of each tile (the persistent kernel's wait set)
   std::vector<int32_t> ptr(H.nt + 1, 0), list, seen(H.nt, -1);
   bool fits = true;
@@ -638,7 +642,7 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   upload(E, p, perm);
   E.perm = static_cast<int32_t*>(p);
   if (E.F == 1 && E.beta4 == 0.0) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
-  if (E.F == 1) build_step_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  build_step_tiles<T>(E, arp, acol, alw, amw, any_dec);
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
   const size_t nv = size_t(n) * E.F;
   E.psi = E.dalloc(nv * 2 * sizeof(T));
@@ -1201,7 +1205,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   // The one-kernel step reads psi, v, w, M_pp and both operators and writes psi.
   by[DEC_BPM_K_TILE_A] = mat_lm + nr * 3 * sr + nr * 4 * sc;
   by[DEC_BPM_K_TILE_B] = mat + nr * sr + nr * 3 * sc;
-  by[DEC_BPM_K_STEP] = mat_lm + nr * 3 * sr + nr * 2 * sc;
+  by[DEC_BPM_K_STEP] = mat_lm + nr * 3 * sr + nF * 2 * sc;
   // persistent stepping, per z step: the same algorithmic bytes as the one-kernel step (the
   // implementation keeps the operator rows on chip, the algorithm still needs them every step)
   by[DEC_BPM_K_PERSIST] = by[DEC_BPM_K_STEP];

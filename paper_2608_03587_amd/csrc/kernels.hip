@@ -1415,6 +1415,138 @@ struct StepTile {
       }
     }
   }
+
+  // ---- VF fields per slot (batched handles: the fields of a row are contiguous) ----
+  // sum_k c_k (vr - V_[q_k]) over the first N entries of register slot j, per field
+  template <int N, int VF>
+  __device__ void lsumv_n(const CVec<T, VF>* V_, int j, const CVec<T, VF>& vr, T* ar, T* ai) const {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const CVec<T, VF> vq = V_[nb(j, k)];
+#pragma unroll
+      for (int f = 0; f < VF; ++f) {
+        ar[f] += cl[j][k] * (vr.v[f].x - vq.v[f].x);
+        ai[f] += cl[j][k] * (vr.v[f].y - vq.v[f].y);
+      }
+    }
+  }
+  template <int N, int VF>
+  __device__ void lsumv_w(int W, const CVec<T, VF>* V_, int j, const CVec<T, VF>& vr, T* ar, T* ai) const {
+    if constexpr (N > 0) {
+      if (W == N) {
+        lsumv_n<N>(V_, j, vr, ar, ai);
+        return;
+      }
+      lsumv_w<N - 1>(W, V_, j, vr, ar, ai);
+    }
+  }
+  template <int N, int VF>
+  __device__ void msumv_n(const RVec<T, VF>* S, int j, T* th) const {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const RVec<T, VF> sq = S[nb(j, k)];
+#pragma unroll
+      for (int f = 0; f < VF; ++f) th[f] += cm[j][k] * sq.v[f];
+    }
+  }
+  template <int N, int VF>
+  __device__ void msumv_w(int W, const RVec<T, VF>* S, int j, T* th) const {
+    if constexpr (N > 0) {
+      if (W == N) {
+        msumv_n<N>(S, j, th);
+        return;
+      }
+      msumv_w<N - 1>(W, S, j, th);
+    }
+  }
+  template <int VF>
+  __device__ CVec<T, VF> stagev(const DevOps<T>& d, const CVec<T, VF>* V_, const CVec<T, VF>& vr,
+                                const CVec<T, VF>& base, int j, T coef) const {
+    T ar[VF], ai[VF];
+#pragma unroll
+    for (int f = 0; f < VF; ++f) ar[f] = ai[f] = T(0);
+    lsumv_w<KMAX>(wd[j], V_, j, vr, ar, ai);
+    CVec<T, VF> r;
+#pragma unroll
+    for (int f = 0; f < VF; ++f) {
+      const T hr = d.p1 * ar[f] - vv[j] * vr.v[f].x;
+      const T hi = d.p1 * ai[f] - vv[j] * vr.v[f].y;
+      r.v[f].x = base.v[f].x + coef * hi;
+      r.v[f].y = base.v[f].y - coef * hr;
+    }
+    return r;
+  }
+
+  // The z step of step() for VF fields per slot (same per-field arithmetic).
+  template <int VF, typename Out>
+  __device__ void step_vec(const DevOps<T>& d, const CVec<T, VF>* P, CVec<T, VF>* X, CVec<T, VF>* Y,
+                           RVec<T, VF>* S, T h, T tau, T gamma, Out out) const {
+    const int B = blockDim.x;
+    CVec<T, VF> p[J], cur[J];
+    RVec<T, VF> so[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n1) {
+        p[j] = P[i];
+        cur[j] = stagev<VF>(d, P, p[j], p[j], j, T(0.25) * h);  // y1
+        Y[i] = cur[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n2) {
+        cur[j] = stagev<VF>(d, Y, cur[j], p[j], j, h / T(3));  // y2
+        X[i] = cur[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n3) {
+        cur[j] = stagev<VF>(d, X, cur[j], p[j], j, T(0.5) * h);  // y3
+        Y[i] = cur[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n4) {  // state before the Kerr substep
+        cur[j] = stagev<VF>(d, Y, cur[j], p[j], j, h);
+        const T ph = phi_w(ww[j], tau);
+#pragma unroll
+        for (int f = 0; f < VF; ++f)
+          so[j].v[f] = (cur[j].v[f].x * cur[j].v[f].x + cur[j].v[f].y * cur[j].v[f].y) * ph;
+        S[i] = so[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < nNL) {
+        T th[VF];
+#pragma unroll
+        for (int f = 0; f < VF; ++f) th[f] = md[j] * so[j].v[f];
+        if constexpr (DEC) msumv_w<KMAX>(wd[j], S, j, th);
+        const T damp = d_exp(-ww[j] * tau);
+        CVec<T, VF> r;
+#pragma unroll
+        for (int f = 0; f < VF; ++f) {
+          T sn, cs;
+          d_sincos(gamma * th[f], &sn, &cs);
+          const C b = cur[j].v[f];
+          r.v[f].x = damp * (b.x * cs - b.y * sn);
+          r.v[f].y = damp * (b.x * sn + b.y * cs);
+        }
+        out(i, rr[j], r);
+      }
+    }
+  }
 };
 
 // One whole z step, LIN(h) then NL(tau), per tile of rows (five halo rings).
@@ -1435,6 +1567,32 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step(DevOps<T> d, 
   __syncthreads();
   st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out_psi[r] = v; },
           [](int, int32_t, const C&) {});
+}
+
+// One whole z step for a batched handle: workgroup b handles step tile
+// b / G and the b % G-th group of VF fields (G = F / VF) of every row of it, so
+// the G workgroups of a tile run back to back on one XCD and share its
+// operator rows in L2.
+template <typename T, int KMAX, bool DEC, int J, int VF>
+__global__ void __launch_bounds__(1024) k_bstep(DevOps<T> d, TileOps<T> tl, const CVec<T, VF>* __restrict__ in_psi,
+                                                CVec<T, VF>* __restrict__ out_psi, T h, T tau, T gamma) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int G = d.F / VF;
+  const int64_t b = logical_block(d.xcd_remap);
+  const int64_t tile = b / G;
+  const int grp = int(b - tile * G);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  CVec<T, VF>* P = reinterpret_cast<CVec<T, VF>*>(smem);
+  CVec<T, VF>* X = P + MS;
+  CVec<T, VF>* Y = X + MS;
+  RVec<T, VF>* S = reinterpret_cast<RVec<T, VF>*>(Y + MS);
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P[i] = in_psi[int64_t(st.slot_row(i)) * G + grp];
+  __syncthreads();
+  st.template step_vec<VF>(d, P, X, Y, S, h, tau, gamma,
+                           [&](int, int32_t r, const CVec<T, VF>& v) { out_psi[int64_t(r) * G + grp] = v; });
 }
 
 // One whole z step with the beta4 L^2 term per tile (8 or 9 halo rings).
@@ -2261,8 +2419,36 @@ void launch_bkerr(const DevOps<T>& d, const TileOps<T>& tl, const void* psi_in, 
 }
 
 template <typename T>
+void launch_bstep(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h, double tau,
+                  double gamma, int block, hipStream_t st) {
+  constexpr int VF = int(32 / sizeof(typename CT<T>::C));  // 32 bytes of each state vector per slot
+  const int G = d.F / VF;
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * G * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * (3 * sizeof(CVec<T, VF>) + sizeof(RVec<T, VF>));
+  const int J = (tl.max_compute + block - 1) / block;
+  using V = CVec<T, VF>;
+#define DECBPM_BSTEP(KM, DEC, JJ)                                                                                   \
+  hipLaunchKernelGGL((k_bstep<T, KM, DEC, JJ, VF>), dim3(g), dim3(block), shmem, st, d, tl,                         \
+                     reinterpret_cast<const V*>(in_psi), reinterpret_cast<V*>(out_psi), T(h), T(tau), T(gamma))
+#define DECBPM_BSTEP_J(KM, DEC) \
+  if (J <= 1) DECBPM_BSTEP(KM, DEC, 1); else DECBPM_BSTEP(KM, DEC, 2);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_BSTEP_J(8, true) } else { DECBPM_BSTEP_J(8, false) }
+  } else {
+    if (dec) { DECBPM_BSTEP_J(12, true) } else { DECBPM_BSTEP_J(12, false) }
+  }
+#undef DECBPM_BSTEP_J
+#undef DECBPM_BSTEP
+}
+
+template <typename T>
 void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h, double tau,
                  double gamma, int block, hipStream_t st) {
+  if (d.F > 1) {  // batched handle: VF fields per slot
+    launch_bstep<T>(d, tl, in_psi, out_psi, h, tau, gamma, block, st);
+    return;
+  }
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
   const size_t shmem = size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
   const int J = (tl.max_compute + block - 1) / block;

@@ -314,15 +314,19 @@ def test_batched_equals_plain(dtype):
     meshes = [lib_mesh(x, dtype) for x in ws]
     batch = api.Batch(meshes, 4)
     packed0 = batch.pack([dev(x.u0, dtype) for x in ws])
-    # LDS-tiled batched kernels vs row-parallel ones: identical per-row formulas
+    # LDS-tiled batched stage kernels and the batched one-kernel step vs the
+    # row-parallel kernels: identical per-row formulas
     runs = {}
-    for fused in (0, 1):
+    for fused in (0, 1, 2):
         batch.tuning = {"fused": fused}
+        assert batch.tuning["fused"] == fused
         pk = packed0.clone()
         batch.propagate(pk, ws[0].dz, ws[0].n_steps, 1.0)
         runs[fused] = pk
-    assert batch.tuning["fused"] == 1
-    assert rel(host(runs[1]), host(runs[0])) < (1e-13 if dtype == "c128" else 1e-6)
+    for fused in (1, 2):
+        assert rel(host(runs[fused]), host(runs[0])) < (1e-13 if dtype == "c128" else 1e-6), fused
+    times = batch.time_kernels(ws[0].dz, 1.0, reps=5)
+    assert times["step"]["ms"] > 0  # the batched step tiles exist
     outs = batch.unpack(runs[1])
     tol = 1e-12 if dtype == "c128" else 1e-5  # same per-row formulas; only FMA contraction may differ
     for m, x, o in zip(meshes, ws, outs):
