@@ -13,6 +13,8 @@ What it computes, in the paper's order and notation:
                  operators of the semi-discrete ODE (Eqs. 10-14).
 * ``stepper``    z-marching: exact Kerr/absorber flow, classical RK4 for the
                  linear part, Strang composition (half steps are never merged).
+* ``unsplit``    z-marching of the whole right-hand side (Kerr term inside
+                 every stage) with classical RK4 at a fixed step.
 * ``diagnostics`` power, Hamiltonian, overlap, the paper's intensity error
                  (Eq. 15) and the plain relative L2 error.
 * ``adjoint``    the exact reverse of ``stepper.propagate`` for the overlap objective,
@@ -25,4 +27,5 @@ against a closed form, invariant, hand-computed value or brute-force result.
 """
 from .dec import Operators, assemble  # noqa: F401
 from .stepper import propagate, strang_step, nl_flow, lin_rk4  # noqa: F401
+from .unsplit import rhs, rk4_step, propagate_rk4  # noqa: F401
 from .diagnostics import power, hamiltonian, overlap, e_rel, rel_l2  # noqa: F401
