@@ -166,6 +166,17 @@ int dec_bpm_linear_step(dec_bpm_t h, void* field, double dz, void* stream);
  */
 int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream);
 
+/*
+ * The paper's unsplit scheme (Eq. 10 integrated as one ODE, "DEC beam
+ * propagation"): n_steps classical RK4 steps of
+ *   dPsi/dz = -i H_lin Psi + i gamma (M |Psi|^2) Psi - w Psi,
+ * the Kerr term and the absorber evaluated inside every stage, at the fixed
+ * step dz, in place on `field` (caller order).  Runs on the one-field step
+ * tiles (one kernel per step); EINVAL for handles without them (the beta4
+ * term, rows of more than 12 neighbours).  Other errors as dec_bpm_propagate.
+ */
+int dec_bpm_propagate_unsplit(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream);
+
 /* Synchronise `stream` and return ENONFINITE if the last propagate produced a
  * non-finite value (the flag is cleared), else OK. */
 int dec_bpm_check_finite(dec_bpm_t h, void* stream);
@@ -274,7 +285,8 @@ enum {
   DEC_BPM_K_TILE_B = 4,   /* fused tile kernel: stages 2 + 3                      */
   DEC_BPM_K_STEP = 5,     /* one-kernel z step: four stages + Kerr/absorber       */
   DEC_BPM_K_PERSIST = 6,  /* persistent launch: time and bytes per z step         */
-  DEC_BPM_NUM_KERNELS = 7
+  DEC_BPM_K_UNSPLIT = 7,  /* one unsplit RK4 step (dec_bpm_propagate_unsplit)     */
+  DEC_BPM_NUM_KERNELS = 8
 };
 int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
                          void* stream);

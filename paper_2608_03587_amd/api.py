@@ -137,6 +137,13 @@ class Mesh:
                                           _stream(stream)))
         return field
 
+    def propagate_unsplit(self, field: torch.Tensor, dz: float, n_steps: int, gamma: float = 1.0, stream=None):
+        """March ``n_steps`` classical RK4 steps of the whole right-hand side (Kerr term inside
+        every stage) in place on ``field`` (asynchronous)."""
+        B.check(B.lib().dec_bpm_propagate_unsplit(self._h, self._field(field), float(dz), int(n_steps),
+                                                  float(gamma), _stream(stream)))
+        return field
+
     def check_finite(self, stream=None):
         B.check(B.lib().dec_bpm_check_finite(self._h, _stream(stream)))
 
@@ -224,7 +231,7 @@ def _time_kernels(fn, h, dz, gamma, reps, stream):
     by = (ctypes.c_double * B.NUM_KERNELS)()
     B.check(fn(h, float(dz), float(gamma), int(reps), ms, by, _stream(stream)))
     names = {B.K_KERR: "kerr", B.K_STAGE: "stage", B.K_LAP: "lap", B.K_TILE_A: "tile_a", B.K_TILE_B: "tile_b",
-             B.K_STEP: "step", B.K_PERSIST: "persist"}
+             B.K_STEP: "step", B.K_PERSIST: "persist", B.K_UNSPLIT: "unsplit"}
     return {names[k]: {"ms": ms[k], "bytes": by[k]} for k in range(B.NUM_KERNELS)}
 
 

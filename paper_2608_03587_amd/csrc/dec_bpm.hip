@@ -778,7 +778,8 @@ static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl,
 // Launch mode of the middle steps: 0 = five kernels (nine with beta4), 1 = two
 // tile kernels, 2 = one tile kernel per step, 3 = one persistent launch for all
 // of them, 4 = one tile kernel per step with the beta4 term (modes whose tiles
-// are missing fall back to the row kernels).
+// are missing fall back to the row kernels).  Mode 5, one unsplit RK4 step per
+// tile kernel, is only requested explicitly (dec_bpm_propagate_unsplit).
 template <typename T>
 static int mode_of(Engine& E) {
   if (E.has_step4) return E.fused >= 2 ? 4 : 0;  // beta4: its one-kernel step or the five kernels
@@ -793,7 +794,7 @@ static void* state_before(const Engine& E, int mode, int64_t k) {
   if (mode == 0) return E.psi;
   const bool odd = k % 2;
   if (mode == 1) return odd ? E.psi : E.psi2;
-  return odd ? E.psi2 : E.psi;  // modes 2, 3 and 4
+  return odd ? E.psi2 : E.psi;  // modes 2 to 5
 }
 
 template <typename T>
@@ -806,8 +807,11 @@ static void middle_step(const Engine& E, const DevOps<T>& d, int mode, int64_t k
   } else if (mode == 2) {
     launch_step<T>(d, E.stp.template ops<T>(), state_before(E, 2, k), state_before(E, 2, k + 1), dz, dz, gamma,
                    E.sblock(), st);
-  } else {
+  } else if (mode == 4) {
     launch_step_b4<T>(d, E.stp.template ops<T>(), state_before(E, 4, k), state_before(E, 4, k + 1), dz, dz, gamma,
+                      E.sblock(), st);
+  } else {  // 5: unsplit RK4
+    launch_unsplit<T>(d, E.stp.template ops<T>(), state_before(E, 5, k), state_before(E, 5, k + 1), dz, gamma,
                       E.sblock(), st);
   }
 }
@@ -868,9 +872,9 @@ static void check_prop_args(const Engine& E, const void* field, double dz, int64
 // Middle steps (merged NL(dz)) through graph replays, then the remainder
 // eagerly; returns the buffer holding the state.
 template <typename T>
-static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st) {
+static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st, int mode = -1) {
   const DevOps<T> d = E.ops<T>();
-  const int mode = mode_of<T>(E);
+  if (mode < 0) mode = mode_of<T>(E);
   if (mode == 3) {
     const int64_t chunk = int64_t(1) << 30;  // steps per launch (the parity of each chunk start is even)
     for (int64_t done = 0; done < count; done += chunk) {
@@ -935,6 +939,17 @@ static void propagate(Engine& E, void* field, double dz, int64_t n, double gamma
     propagate_t<float>(E, field, dz, n, gamma, st);
   else
     propagate_t<double>(E, field, dz, n, gamma, st);
+}
+
+// n unsplit RK4 steps (no half steps to merge: every step is self-contained).
+template <typename T>
+static void propagate_unsplit_t(Engine& E, void* field, double dz, int64_t n, double gamma, hipStream_t st) {
+  if (n == 0) return;
+  const DevOps<T> d = E.ops<T>();
+  launch_perm_in<T>(d, E.perm, field, E.psi, 0, E.block, st);
+  void* cur = run_middle<T>(E, n, dz, gamma, st, 5);
+  launch_perm_out<T>(d, E.perm, cur, field, 0, E.flag, E.block, st);
+  check_launch();
 }
 
 // ---- checkpointed forward and adjoint ----
@@ -1209,6 +1224,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   // persistent stepping, per z step: the same algorithmic bytes as the one-kernel step (the
   // implementation keeps the operator rows on chip, the algorithm still needs them every step)
   by[DEC_BPM_K_PERSIST] = by[DEC_BPM_K_STEP];
+  by[DEC_BPM_K_UNSPLIT] = by[DEC_BPM_K_STEP];  // one unsplit RK4 step: the same data
   launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
   launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
   launch_fill<T>(d, E.yb, 0.2, -0.1, B, st);
@@ -1221,6 +1237,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   for (int kind = 0; kind < DEC_BPM_NUM_KERNELS; ++kind) {
     const bool tile_kind = kind == DEC_BPM_K_TILE_A || kind == DEC_BPM_K_TILE_B;
     if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step && !E.has_step4) ||
+        (kind == DEC_BPM_K_UNSPLIT && (!E.has_step || E.F != 1)) ||
         (kind == DEC_BPM_K_PERSIST && !(E.has_persist && persist_fits<T>(E)))) {
       if (ms) ms[kind] = 0.0;
       if (bytes) bytes[kind] = 0.0;
@@ -1257,6 +1274,9 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       else if (kind == DEC_BPM_K_STEP)
         launch_step<T>(d, E.stp.template ops<T>(), r % 2 ? E.psi2 : E.psi, r % 2 ? E.psi : E.psi2, dz, dz, gamma,
                        E.sblock(), E.cap);
+      if (kind == DEC_BPM_K_UNSPLIT)
+        launch_unsplit<T>(d, E.stp.template ops<T>(), r % 2 ? E.psi2 : E.psi, r % 2 ? E.psi : E.psi2, dz, gamma,
+                          E.sblock(), E.cap);
     }
     HIP_OK(hipStreamEndCapture(E.cap, &g));
     hipGraphExec_t ex;
@@ -1662,6 +1682,21 @@ int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, doub
   need(h);
   decbpm::check_prop_args(h->E, field, dz, n_steps, gamma);
   decbpm::propagate(h->E, field, dz, n_steps, gamma, as_stream(stream));
+  ABI_CATCH
+}
+
+int dec_bpm_propagate_unsplit(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream) {
+  ABI_TRY
+  need(h);
+  decbpm::check_prop_args(h->E, field, dz, n_steps, gamma);
+  if (!h->E.has_step || h->E.F != 1)
+    fail(DEC_BPM_EINVAL,
+         "the unsplit integrator runs on the one-field step tiles: not available with the beta4 term or with rows of "
+         "more than 12 neighbours");
+  if (h->E.dtype == DEC_BPM_C64)
+    decbpm::propagate_unsplit_t<float>(h->E, field, dz, n_steps, gamma, as_stream(stream));
+  else
+    decbpm::propagate_unsplit_t<double>(h->E, field, dz, n_steps, gamma, as_stream(stream));
   ABI_CATCH
 }
 

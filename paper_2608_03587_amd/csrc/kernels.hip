@@ -1547,6 +1547,75 @@ struct StepTile {
       }
     }
   }
+
+  // One step of classical RK4 on the whole right-hand side
+  //   F(v) = -i (p1 L v - V v) + i gamma (M |v|^2) v - w v
+  // (the Kerr term inside every stage).  Stage k evaluates F on rings
+  // 0..4-k, gathering its input v from A and |v|^2 from SA (rings 0..5-k), and
+  // writes the next stage's input and its |.|^2 to B and SB; the buffers then
+  // swap.  The state is staged in A and SA (rings 0..4); own values stay in
+  // registers.  Calls out(slot, r, value) for every owned row.
+  template <typename Out>
+  __device__ void step_unsplit(const DevOps<T>& d, C* A, C* Bv, T* SA, T* SB, T h, T gamma, Out out) const {
+    const int B = blockDim.x;
+    C p[J], cur[J], acc[J];
+    T so[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < hd[3]) {
+        p[j] = A[i];
+        cur[j] = p[j];
+        so[j] = SA[i];
+        acc[j].x = acc[j].y = T(0);
+      }
+    }
+    const T cnext[3] = {T(0.5) * h, T(0.5) * h, h};
+    const T wsum[4] = {T(1), T(2), T(2), T(1)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      C* Vin = (k & 1) ? Bv : A;
+      C* Vout = (k & 1) ? A : Bv;
+      T* Sin = (k & 1) ? SB : SA;
+      T* Sout = (k & 1) ? SA : SB;
+      const int nk = hd[3 - k];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int i = threadIdx.x + j * B;
+        if (i < nk) {
+          T ar = T(0), ai = T(0);
+          lsum_w<KMAX>(wd[j], CplxAoS<T>{Vin}, j, cur[j], ar, ai);
+          T th = md[j] * so[j];
+          if constexpr (DEC) th = msum_w<KMAX>(wd[j], Sin, j, th);
+          const T hr = d.p1 * ar - vv[j] * cur[j].x;
+          const T hi = d.p1 * ai - vv[j] * cur[j].y;
+          C f;  // -i (hr + i hi) + i gamma th v - w v
+          f.x = hi - gamma * th * cur[j].y - ww[j] * cur[j].x;
+          f.y = -hr + gamma * th * cur[j].x - ww[j] * cur[j].y;
+          acc[j].x += wsum[k] * f.x;
+          acc[j].y += wsum[k] * f.y;
+          if (k < 3) {
+            cur[j].x = p[j].x + cnext[k] * f.x;
+            cur[j].y = p[j].y + cnext[k] * f.y;
+            so[j] = cur[j].x * cur[j].x + cur[j].y * cur[j].y;
+            Vout[i] = cur[j];
+            Sout[i] = so[j];
+          }
+        }
+      }
+      if (k < 3) __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < hd[0]) {
+        C r;
+        r.x = p[j].x + (h / T(6)) * acc[j].x;
+        r.y = p[j].y + (h / T(6)) * acc[j].y;
+        out(i, rr[j], r);
+      }
+    }
+  }
 };
 
 // One whole z step, LIN(h) then NL(tau), per tile of rows (five halo rings).
@@ -1593,6 +1662,32 @@ __global__ void __launch_bounds__(1024) k_bstep(DevOps<T> d, TileOps<T> tl, cons
   __syncthreads();
   st.template step_vec<VF>(d, P, X, Y, S, h, tau, gamma,
                            [&](int, int32_t r, const CVec<T, VF>& v) { out_psi[int64_t(r) * G + grp] = v; });
+}
+
+// One unsplit classical RK4 step per tile (the Kerr term inside every stage).
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_rk4u(DevOps<T> d, TileOps<T> tl,
+                                                                  const typename CT<T>::C* __restrict__ in_psi,
+                                                                  typename CT<T>::C* __restrict__ out_psi, T h,
+                                                                  T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  C* A = reinterpret_cast<C*>(smem);
+  C* Bv = A + MS;
+  T* SA = reinterpret_cast<T*>(Bv + MS);
+  T* SB = SA + MS;
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  for (int i = threadIdx.x; i < st.hd[4]; i += blockDim.x) {
+    const C v = in_psi[st.slot_row(i)];
+    A[i] = v;
+    SA[i] = v.x * v.x + v.y * v.y;
+  }
+  __syncthreads();
+  st.step_unsplit(d, A, Bv, SA, SB, h, gamma, [&](int, int32_t r, const C& v) { out_psi[r] = v; });
 }
 
 // One whole z step with the beta4 L^2 term per tile (8 or 9 halo rings).
@@ -2468,6 +2563,27 @@ void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, v
 }
 
 template <typename T>
+void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
+                    double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * 2 * (sizeof(typename CT<T>::C) + sizeof(T));
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_RK4U(KM, DEC, JJ)                                                                               \
+  hipLaunchKernelGGL((k_rk4u<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi),     \
+                     DECBPM_M(T, out_psi), T(h), T(gamma))
+#define DECBPM_RK4U_J(KM, DEC) \
+  if (J <= 1) DECBPM_RK4U(KM, DEC, 1); else DECBPM_RK4U(KM, DEC, 2);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_RK4U_J(8, true) } else { DECBPM_RK4U_J(8, false) }
+  } else {
+    if (dec) { DECBPM_RK4U_J(12, true) } else { DECBPM_RK4U_J(12, false) }
+  }
+#undef DECBPM_RK4U_J
+#undef DECBPM_RK4U
+}
+
+template <typename T>
 void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
                     double tau, double gamma, int block, hipStream_t st) {
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
@@ -2717,6 +2833,8 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   template int persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int);                                     \
   template void launch_step_b4<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double, \
                                   int, hipStream_t);                                                             \
+  template void launch_unsplit<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, int,    \
+                                  hipStream_t);                                                                  \
   template void launch_step_rec<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, void*, void*, void*,    \
                                    void*, double, double, double, int, hipStream_t);                             \
   template void launch_step_adj<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*,     \

@@ -175,6 +175,12 @@ void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, v
 template <typename T>
 void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
                     double tau, double gamma, int block, hipStream_t st);
+// One step of classical RK4 on the whole right-hand side (the Kerr term and
+// the absorber inside every stage) on the five-ring step tiles (four rings are
+// used: one per stage).
+template <typename T>
+void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
+                    double gamma, int block, hipStream_t st);
 
 // The one-kernel step that also writes the owned rows' stage vectors y1..y3
 // and the state before the Kerr substep (the adjoint's forward recompute).

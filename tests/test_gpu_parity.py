@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import adjoint as OA, dec, diagnostics as D, stepper as S
+from oracle import adjoint as OA, dec, diagnostics as D, stepper as S, unsplit as US
 from paper_2608_03587_amd import _binding as B
 from paper_2608_03587_amd import api
 from paper_2608_03587_amd.inputs import fields as F
@@ -196,6 +196,38 @@ def test_beta4_one_kernel_step_matches_row_kernels_and_oracle(dtype, nl):
         m.propagate(f, w.dz, 37, w.gamma)
         assert rel(host(f), keep) < KERNEL_TOL[dtype], tb
     assert m.time_kernels(w.dz, w.gamma, reps=10)["step"]["ms"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_unsplit_rk4_matches_oracle(dtype, nl):
+    """Classical RK4 on the whole right-hand side (Kerr and absorber inside every
+    stage), one tile kernel per step, against the oracle's unsplit scheme."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    say("unsplit", dtype, nl, w.mesh.n_vert)
+    ops = oracle_ops(w, nl)
+    m = lib_mesh(w, dtype, nl)
+    u = dev(w.u0, dtype)
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    for n in (1, 2, 3, 37):
+        outs = {}
+        for spg in (1, 16):
+            m.tuning = {"steps_per_graph": spg}
+            f = u.clone()
+            m.propagate_unsplit(f, w.dz, n, w.gamma)
+            outs[spg] = host(f)
+        m.check_finite()
+        assert np.array_equal(outs[1], outs[16]), n  # graph replay == eager
+        ref = US.propagate_rk4(w.u0, ops, w.dz, n, w.gamma)
+        err = rel(outs[16], ref)
+        assert err < tol, (n, err)
+    assert m.time_kernels(w.dz, w.gamma, reps=10)["unsplit"]["ms"] > 0
+    # a handle without one-field step tiles (the beta4 term) refuses, before any device work
+    wb = case("vortex", n_vert=20000, n_steps=10)
+    mb = lib_mesh(wb, dtype)
+    with pytest.raises(api.DecBpmError) as e:
+        mb.propagate_unsplit(dev(wb.u0, dtype), wb.dz, 3, wb.gamma)
+    assert e.value.code == B.EINVAL
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])

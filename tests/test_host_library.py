@@ -148,6 +148,8 @@ def test_host_only_handle_runs_every_check_then_reports_no_device():
     assert lib.dec_bpm_propagate(m.handle, ctypes.c_void_p((1 << 20) + 4), 1e-3, 1, 1.0, None) == B.EINVAL
     assert lib.dec_bpm_propagate(m.handle, fake, 1e-3, 10, float("nan"), None) == B.EINVAL
     assert lib.dec_bpm_propagate(m.handle, fake, 1e-3, 10, 1.0, None) == B.ENODEVICE
+    assert lib.dec_bpm_propagate_unsplit(m.handle, fake, 3.0 / rho, 10, 1.0, None) == B.EUNSTABLE
+    assert lib.dec_bpm_propagate_unsplit(m.handle, fake, 1e-3, 10, 1.0, None) == B.ENODEVICE
     assert lib.dec_bpm_apply(m.handle, 0, fake, fake, None) == B.EINVAL  # x == y
     assert lib.dec_bpm_diagnostics(m.handle, fake, 1.0, None, None, None) == B.ENODEVICE
     size = ctypes.c_size_t()
