@@ -12,15 +12,16 @@ side is
 
 ``H_lin = p1 L + beta4 L^2 - diag(v)``, ``M`` the nonlinear averaging matrix
 (Eq. 14, or the lumped diagonal) and ``w >= 0`` the absorber.  This module
-takes the classical fourth-order Runge-Kutta method on F at a fixed step: the
-Kerr term is evaluated inside every stage (the paper's own scheme is adaptive;
-the fixed step is what the workloads specify).
+takes the classical fourth-order Runge-Kutta method on F at a fixed step (the
+Kerr term evaluated inside every stage; the fixed step is what the workloads
+specify) and the paper's own choice, the adaptive embedded Dormand-Prince 5(4)
+pair.
 """
 from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["rhs", "rk4_step", "propagate_rk4"]
+__all__ = ["rhs", "rk4_step", "propagate_rk4", "dp54_step", "error_norm", "propagate_dp54"]
 
 
 def rhs(psi: np.ndarray, ops, gamma: float) -> np.ndarray:
@@ -44,3 +45,77 @@ def propagate_rk4(psi0, ops, dz: float, n_steps: int, gamma: float) -> np.ndarra
     for _ in range(n_steps):
         psi = rk4_step(psi, dz, gamma, ops)
     return psi
+
+
+# ---- adaptive Dormand-Prince 5(4) ----
+# The paper's integrator is an adaptive embedded Runge-Kutta pair of orders
+# 5 and 4 (Dormand and Prince; it is the pair behind SciPy's RK45, which the
+# paper names).  Coefficients of the published tableau:
+DP_C = (0.0, 1 / 5, 3 / 10, 4 / 5, 8 / 9, 1.0, 1.0)
+DP_A = (
+    (),
+    (1 / 5,),
+    (3 / 40, 9 / 40),
+    (44 / 45, -56 / 15, 32 / 9),
+    (19372 / 6561, -25360 / 2187, 64448 / 6561, -212 / 729),
+    (9017 / 3168, -355 / 33, 46732 / 5247, 49 / 176, -5103 / 18656),
+    (35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84),
+)
+DP_B5 = (35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84, 0.0)
+DP_B4 = (5179 / 57600, 0.0, 7571 / 16695, 393 / 640, -92097 / 339200, 187 / 2100, 1 / 40)
+
+
+def dp54_step(psi: np.ndarray, h: float, gamma: float, ops):
+    """One Dormand-Prince step: the fifth-order solution and the difference
+    between the fifth- and fourth-order solutions (the local error estimate)."""
+    k = []
+    for s in range(7):
+        y = psi + h * sum(a * kj for a, kj in zip(DP_A[s], k)) if s else psi
+        k.append(rhs(y, ops, gamma))
+    y5 = psi + h * sum(b * kj for b, kj in zip(DP_B5, k))
+    err = h * sum((b5 - b4) * kj for b5, b4, kj in zip(DP_B5, DP_B4, k))
+    return y5, err
+
+
+def error_norm(err: np.ndarray, y0: np.ndarray, y1: np.ndarray, rtol: float, atol: float) -> float:
+    """Root-mean-square over vertices of |err_p| / (atol + rtol max(|y0_p|, |y1_p|))."""
+    sc = atol + rtol * np.maximum(np.abs(y0), np.abs(y1))
+    return float(np.sqrt(np.mean((np.abs(err) / sc) ** 2)))
+
+
+def propagate_dp54(psi0, ops, z_end: float, h0: float, gamma: float, rtol: float = 1e-9, atol: float = 1e-11,
+                   max_attempts: int = 100000, facmax: float = 10.0):
+    """Adaptive Dormand-Prince 5(4) from z = 0 to z_end, first trial step h0
+    (tolerances default to the paper's rtol = 1e-9, atol = 1e-11).
+
+    Step-size control (the standard rule of Hairer, Norsett and Wanner,
+    Solving ODEs I, section II.4): a step is accepted when the error norm is
+    below 1; the next trial step is h * min(facmax, max(0.2, 0.9 err^{-1/5})),
+    where facmax drops to 1 for the step that follows a rejection, and a trial
+    step is clipped so that the last step ends at z_end.  Returns the state
+    and a dict of counters (accepted, rejected, last accepted h, final z)."""
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    z, h = 0.0, float(h0)
+    acc = rej = 0
+    last_h = 0.0
+    prev_rejected = False
+    for _ in range(max_attempts):
+        if z >= z_end:
+            break
+        h = min(h, z_end - z)
+        y5, e = dp54_step(psi, h, gamma, ops)
+        err = error_norm(e, psi, y5, rtol, atol)
+        if err < 1.0:
+            psi, z = y5, z + h
+            acc += 1
+            last_h = h
+            fac = facmax if not prev_rejected else 1.0
+            prev_rejected = False
+        else:
+            rej += 1
+            fac = 1.0
+            prev_rejected = True
+        h = h * min(fac, max(0.2, 0.9 * (err if err > 0 else 1e-300) ** -0.2))
+    else:
+        raise RuntimeError("adaptive integration did not reach z_end")
+    return psi, {"accepted": acc, "rejected": rej, "last_h": last_h, "z": z}

@@ -95,3 +95,76 @@ def test_split_and_unsplit_schemes_converge_to_the_same_solution():
          for n in (20, 40, 80)]
     orders = [math.log(d[k] / d[k + 1], 2) for k in range(2)]
     assert min(orders) > 1.8, (d, orders)
+
+
+def test_dormand_prince_tableau_is_consistent():
+    """Row sums of A equal c, both weight vectors sum to 1, and the last stage is the
+    fifth-order solution (first same as last)."""
+    for s in range(1, 7):
+        assert abs(sum(U.DP_A[s]) - U.DP_C[s]) < 1e-15
+    assert abs(sum(U.DP_B5) - 1) < 1e-15 and abs(sum(U.DP_B4) - 1) < 1e-15
+    assert all(abs(a - b) < 1e-16 for a, b in zip(U.DP_A[6], U.DP_B5[:6]))
+
+
+def test_dormand_prince_fixed_steps_are_fifth_order_and_the_estimate_fourth():
+    ops, u0 = _gaussian_case()
+    z, gamma = 0.4, 1.0
+
+    def run(n):
+        psi = u0.copy()
+        for _ in range(n):
+            psi, _ = U.dp54_step(psi, z / n, gamma, ops)
+        return psi
+
+    ref = run(320)
+    errs = [D.rel_l2(run(n), ref) for n in (20, 40, 80)]
+    orders = [math.log(errs[k] / errs[k + 1], 2) for k in range(2)]
+    assert min(orders) > 4.6, (errs, orders)
+    # the local error estimate scales like h^5 (the embedded fourth-order solution)
+    est = [np.linalg.norm(U.dp54_step(u0, h, gamma, ops)[1]) for h in (0.02, 0.01)]
+    assert 4.5 < math.log(est[0] / est[1], 2) < 5.5, est
+
+
+def test_adaptive_dormand_prince_matches_scipy_rk45():
+    """SciPy's RK45 (the paper's integrator) is the same pair with the same error norm and
+    step-size rule: both take the same number of steps, reach the ODE solution (DOP853 at
+    1e-13) with the same error, and the error shrinks with the tolerance."""
+    from scipy.integrate import solve_ivp
+
+    mesh = M.random_delaunay_mesh(40, 6)
+    rng = np.random.default_rng(6)
+    ops = dec.assemble(mesh.xy * 12.0, mesh.tri, index_tri=rng.uniform(0, 1, mesh.n_tri),
+                       absorber=rng.uniform(0, 0.5, mesh.n_vert))
+    gamma, z = 0.7, 2.0
+    psi0 = rng.normal(size=ops.n) + 1j * rng.normal(size=ops.n)
+    sol = solve_ivp(lambda _, y: U.rhs(y, ops, gamma), (0, z), psi0.astype(np.complex128),
+                    method="DOP853", rtol=1e-13, atol=1e-15)
+    ref = sol.y[:, -1]
+    errs = []
+    for rtol in (1e-7, 1e-10):
+        out, stats = U.propagate_dp54(psi0, ops, z, 1e-3, gamma, rtol=rtol, atol=rtol * 1e-2)
+        assert stats["accepted"] > 0 and abs(stats["z"] - z) < 1e-13
+        s45 = solve_ivp(lambda _, y: U.rhs(y, ops, gamma), (0, z), psi0.astype(np.complex128),
+                        method="RK45", rtol=rtol, atol=rtol * 1e-2)
+        e_ours, e_scipy = D.rel_l2(out, ref), D.rel_l2(s45.y[:, -1], ref)
+        # same pair, same norm, same controller: the step sequences and errors coincide
+        assert abs(stats["accepted"] - (len(s45.t) - 1)) <= 2, (stats, len(s45.t))
+        assert e_ours < 1e3 * rtol and abs(e_ours - e_scipy) < 0.1 * e_scipy, (rtol, e_ours, e_scipy)
+        errs.append(e_ours)
+    assert errs[1] < 1e-2 * errs[0]
+
+
+@pytest.mark.parametrize("nl", ["dec", "lumped"])
+def test_adaptive_plane_wave_reaches_the_exact_solution(nl):
+    """Plane wave with uniform potential: the adaptive run reproduces a e^{i (V0 + gamma |a|^2) z}
+    within the requested tolerance, and a tighter tolerance takes more steps."""
+    mesh = M.disk_mesh(3.0, 0.5, 1)
+    V0, a, gamma, z = 0.7, 0.9 - 0.3j, 1.3, 3.0
+    ops = dec.assemble(mesh.xy, mesh.tri, index_tri=np.full(mesh.n_tri, V0), nl=nl)
+    exact = a * np.exp(1j * (V0 + gamma * abs(a) ** 2) * z)
+    steps = []
+    for rtol in (1e-6, 1e-9):
+        out, stats = U.propagate_dp54(np.full(ops.n, a), ops, z, 0.1, gamma, rtol=rtol, atol=rtol * 1e-2)
+        assert np.abs(out - exact).max() < 50 * rtol * abs(a), (rtol, np.abs(out - exact).max())
+        steps.append(stats["accepted"])
+    assert steps[1] > steps[0]
