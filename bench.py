@@ -19,7 +19,8 @@ Also reported on the same JSON line:
   cpu_baseline  the FP64 CPU oracle on the same mesh and launch, a bounded
                 prefix of steps, single thread
   parity        GPU vs oracle after the same prefix (relative L2)
-  extras        complex128 throughput; batched photonic-crystal-fibre mode vs
+  extras        complex128 throughput; the unsplit RK4 and adaptive Dormand-Prince
+                5(4) integrators; batched photonic-crystal-fibre mode vs
                 per-instance plain launches; checkpointed adjoint vs forward;
                 the 1M-vertex vortex launch with the beta4 L^2 term
 """
@@ -240,6 +241,14 @@ def main():
         except Exception as e:  # noqa: BLE001
             extras[other] = {"error": repr(e)}
         try:
+            extras["unsplit_rk4"] = bench_unsplit(api, w, torch, dev, tdt, args.steps, not args.no_cpu)
+        except Exception as e:  # noqa: BLE001
+            extras["unsplit_rk4"] = {"error": repr(e)}
+        try:
+            extras["adaptive_dp54"] = bench_adaptive(api, w, torch, dev, tdt, not args.no_cpu)
+        except Exception as e:  # noqa: BLE001
+            extras["adaptive_dp54"] = {"error": repr(e)}
+        try:
             extras["conditioning"] = bench_conditioning(api, w, torch, dev, tdt, args.steps)
         except Exception as e:  # noqa: BLE001
             extras["conditioning"] = {"error": repr(e)}
@@ -382,6 +391,93 @@ def bench_adjoint(api, W, torch, dev, tdt):
            "grad_finite": bool(torch.isfinite(torch.view_as_real(g0)).all() and torch.isfinite(gdn).all())}
     log(f"[bench] adjoint: {t_a / t_f:.2f}x forward (checkpointed fwd + adjoint {res['total_over_forward']:.2f}x)")
     return res
+
+
+def bench_unsplit(api, w, torch, dev, tdt, steps, with_oracle):
+    """The paper's unsplit scheme (classical RK4 on the whole right-hand side, Kerr term inside
+    every stage) on the same step-index workload, complex64: throughput, parity with the oracle's
+    unsplit RK4 on a 40-step prefix, and its distance to the split scheme at full length."""
+    import numpy as np
+
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype="c64", p1=w.p1, beta4=w.beta4)
+    m.autotune(w.dz, w.gamma)
+    u0 = torch.from_numpy(w.u0).to(dev, tdt["c64"])
+    f = u0.clone()
+    m.propagate_unsplit(f, w.dz, 50, w.gamma)
+    f = u0.clone()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    m.propagate_unsplit(f, w.dz, steps, w.gamma)
+    e1.record()
+    torch.cuda.synchronize()
+    m.check_finite()
+    ms = e0.elapsed_time(e1)
+    g = u0.clone()
+    m.propagate(g, w.dz, steps, w.gamma)
+    split_dist = float(torch.linalg.norm(g - f) / torch.linalg.norm(f))
+    kt = m.time_kernels(w.dz, w.gamma, reps=100)["unsplit"]
+    res = {"value": w.mesh.n_vert * steps / (ms * 1e-3), "unit": "vertex z-steps/s", "ms_per_step": ms / steps,
+           "steps": steps, "kernel_us": kt["ms"] * 1e3, "kernel_GBps": kt["bytes"] / (kt["ms"] * 1e-3) / 1e9,
+           "rel_l2_vs_split_scheme_full_length": split_dist, "tuning": m.tuning}
+    if with_oracle:
+        from oracle import dec, unsplit
+
+        ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, beta4=w.beta4)
+        n = 40
+        ref = unsplit.propagate_rk4(w.u0, ops, w.dz, n, w.gamma)
+        h = u0.clone()
+        m.propagate_unsplit(h, w.dz, n, w.gamma)
+        got = h.cpu().numpy().astype(np.complex128)
+        res["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), "steps": n}
+    log(f"[bench] unsplit RK4: {res['value']:.4e} vertex z-steps/s ({res['ms_per_step'] * 1e3:.2f} us per step), "
+        f"parity {res.get('parity', {}).get('rel_l2_vs_oracle')}")
+    return res
+
+
+def bench_adaptive(api, w, torch, dev, tdt, with_oracle):
+    """The paper's own integrator, adaptive Dormand-Prince 5(4) on the whole right-hand side, on
+    the same step-index workload: complex128 at the paper's tolerances (rtol 1e-9, atol 1e-11)
+    and complex64 at rtol 1e-6, atol 1e-8, over 400 configured z steps (z_end = 0.2); accepted
+    steps per second, the trial kernel's time, and the oracle's adaptive run on a 4-step prefix."""
+    import numpy as np
+
+    z_end = 400 * w.dz
+    out = {"z_end": z_end, "h0": w.dz}
+    for dt, rtol, atol in (("c128", 1e-9, 1e-11), ("c64", 1e-6, 1e-8)):
+        m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=dt, p1=w.p1, beta4=w.beta4)
+        u0 = torch.from_numpy(w.u0).to(dev, tdt[dt])
+        f = u0.clone()
+        m.propagate_adaptive(f, 4 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)  # builds the tiles
+        f = u0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = m.propagate_adaptive(f, z_end, w.dz, w.gamma, rtol=rtol, atol=atol)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        m.check_finite()
+        kt = m.time_kernels(w.dz, w.gamma, reps=50)["dp5"]
+        attempts = st["accepted"] + st["rejected"]
+        r = {"rtol": rtol, "atol": atol, **st, "seconds": sec,
+             "value": w.mesh.n_vert * st["accepted"] / sec, "unit": "vertex z-steps/s (accepted steps)",
+             "us_per_attempt": sec / attempts * 1e6, "trial_kernel_us": kt["ms"] * 1e3,
+             "trial_kernel_GBps": kt["bytes"] / (kt["ms"] * 1e-3) / 1e9}
+        if with_oracle:
+            from oracle import dec, unsplit
+
+            ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, beta4=w.beta4)
+            ref, rs = unsplit.propagate_dp54(w.u0, ops, 4 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
+            g = u0.clone()
+            sg = m.propagate_adaptive(g, 4 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
+            got = g.cpu().numpy().astype(np.complex128)
+            r["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                           "z_end": 4 * w.dz, "gpu_steps": [sg["accepted"], sg["rejected"]],
+                           "oracle_steps": [rs["accepted"], rs["rejected"]]}
+        out[dt] = r
+        log(f"[bench] adaptive DP5(4) {dt}: {st['accepted']} accepted / {st['rejected']} rejected in {sec:.3f} s, "
+            f"{r['us_per_attempt']:.1f} us per attempt, trial kernel {r['trial_kernel_us']:.1f} us, "
+            f"parity {r.get('parity', {}).get('rel_l2_vs_oracle')}")
+    return out
 
 
 def bench_conditioning(api, w, torch, dev, tdt, steps):

@@ -177,6 +177,31 @@ int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, doub
  */
 int dec_bpm_propagate_unsplit(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream);
 
+/*
+ * The paper's integrator proper (section 3, the adaptive embedded Runge-Kutta
+ * pair it runs through SciPy's RK45): Dormand-Prince 5(4) on the same
+ * right-hand side as dec_bpm_propagate_unsplit, from z = 0 to z_end, first
+ * trial step h0 (clipped to z_end), in place on `field` (caller order).
+ * Error norm: the root mean square over vertices of
+ * |e_p| / (atol + rtol max(|psi_p|, |psi'_p|)), e the embedded estimate; a
+ * trial is accepted when it is below 1, and the next trial step is the last
+ * one times min(10, max(0.2, 0.9 norm^(-1/5))), the growth capped at 1 right
+ * after a rejection.  Trials, norms and decisions run on the device; the call
+ * returns when the run has ended (it synchronises `stream`).
+ * rtol >= 0 and atol > 0 (the paper's values are 1e-9 and 1e-11; complex64
+ * handles need rtol of about 1e-6 or more, since rounding then dominates the
+ * estimate).  max_attempts bounds accepted plus rejected trials.
+ * n_accepted, n_rejected, last_h (the last accepted step) and z_reached may
+ * be NULL.  Errors: EINVAL (arguments, or a handle without one-field step
+ * tiles: the beta4 term, rows of more than 12 neighbours), EUNSTABLE (the
+ * attempts ran out, or the step fell below 10 ulp of z, before z_end),
+ * ENONFINITE (a non-finite error norm); in these cases `field` holds the last
+ * accepted state and the counters are filled.  EHIP, ENODEVICE.
+ */
+int dec_bpm_propagate_adaptive(dec_bpm_t h, void* field, double z_end, double h0, double gamma, double rtol,
+                               double atol, int64_t max_attempts, int64_t* n_accepted, int64_t* n_rejected,
+                               double* last_h, double* z_reached, void* stream);
+
 /* Synchronise `stream` and return ENONFINITE if the last propagate produced a
  * non-finite value (the flag is cleared), else OK. */
 int dec_bpm_check_finite(dec_bpm_t h, void* stream);
@@ -286,7 +311,8 @@ enum {
   DEC_BPM_K_STEP = 5,     /* one-kernel z step: four stages + Kerr/absorber       */
   DEC_BPM_K_PERSIST = 6,  /* persistent launch: time and bytes per z step         */
   DEC_BPM_K_UNSPLIT = 7,  /* one unsplit RK4 step (dec_bpm_propagate_unsplit)     */
-  DEC_BPM_NUM_KERNELS = 8
+  DEC_BPM_K_DP5 = 8,      /* one adaptive Dormand-Prince trial (seven stages)     */
+  DEC_BPM_NUM_KERNELS = 9
 };
 int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
                          void* stream);

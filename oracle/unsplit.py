@@ -92,7 +92,8 @@ def propagate_dp54(psi0, ops, z_end: float, h0: float, gamma: float, rtol: float
     Solving ODEs I, section II.4): a step is accepted when the error norm is
     below 1; the next trial step is h * min(facmax, max(0.2, 0.9 err^{-1/5})),
     where facmax drops to 1 for the step that follows a rejection, and a trial
-    step is clipped so that the last step ends at z_end.  Returns the state
+    step is clipped so that the last step ends exactly at z_end (a trial below
+    10 ulp of z is an error).  Returns the state
     and a dict of counters (accepted, rejected, last accepted h, final z)."""
     psi = np.array(psi0, dtype=np.complex128, copy=True)
     z, h = 0.0, float(h0)
@@ -102,11 +103,14 @@ def propagate_dp54(psi0, ops, z_end: float, h0: float, gamma: float, rtol: float
     for _ in range(max_attempts):
         if z >= z_end:
             break
-        h = min(h, z_end - z)
+        z_new = min(z + h, z_end)
+        h = z_new - z
+        if h < 10 * (np.nextafter(z, np.inf) - z):
+            raise RuntimeError("step size fell below 10 ulp of z")
         y5, e = dp54_step(psi, h, gamma, ops)
         err = error_norm(e, psi, y5, rtol, atol)
         if err < 1.0:
-            psi, z = y5, z + h
+            psi, z = y5, z_new
             acc += 1
             last_h = h
             fac = facmax if not prev_rejected else 1.0

@@ -144,6 +144,26 @@ class Mesh:
                                                   float(gamma), _stream(stream)))
         return field
 
+    def propagate_adaptive(self, field: torch.Tensor, z_end: float, h0: float, gamma: float = 1.0,
+                           rtol: float = 1e-9, atol: float = 1e-11, max_attempts: int = 1 << 40, stream=None):
+        """Adaptive Dormand-Prince 5(4) on the whole right-hand side from z = 0 to ``z_end``
+        (first trial step ``h0``), in place on ``field``.  Synchronises the stream and returns
+        the counters ``{"accepted", "rejected", "last_h", "z"}``; on a failed run the
+        raised error carries them as ``.stats``."""
+        acc, rej = ctypes.c_int64(0), ctypes.c_int64(0)
+        lh, zr = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        code = B.lib().dec_bpm_propagate_adaptive(self._h, self._field(field), float(z_end), float(h0), float(gamma),
+                                                  float(rtol), float(atol), int(max_attempts), ctypes.byref(acc),
+                                                  ctypes.byref(rej), ctypes.byref(lh), ctypes.byref(zr),
+                                                  _stream(stream))
+        stats = {"accepted": acc.value, "rejected": rej.value, "last_h": lh.value, "z": zr.value}
+        try:
+            B.check(code)
+        except DecBpmError as e:
+            e.stats = stats
+            raise
+        return stats
+
     def check_finite(self, stream=None):
         B.check(B.lib().dec_bpm_check_finite(self._h, _stream(stream)))
 
@@ -231,7 +251,7 @@ def _time_kernels(fn, h, dz, gamma, reps, stream):
     by = (ctypes.c_double * B.NUM_KERNELS)()
     B.check(fn(h, float(dz), float(gamma), int(reps), ms, by, _stream(stream)))
     names = {B.K_KERR: "kerr", B.K_STAGE: "stage", B.K_LAP: "lap", B.K_TILE_A: "tile_a", B.K_TILE_B: "tile_b",
-             B.K_STEP: "step", B.K_PERSIST: "persist", B.K_UNSPLIT: "unsplit"}
+             B.K_STEP: "step", B.K_PERSIST: "persist", B.K_UNSPLIT: "unsplit", B.K_DP5: "dp5"}
     return {names[k]: {"ms": ms[k], "bytes": by[k]} for k in range(B.NUM_KERNELS)}
 
 

@@ -71,9 +71,10 @@ struct DevTiles {
 
 struct GraphEntry {
   double dz, gamma;
-  int spg, block, xcd, fused, tile_block;
+  int spg, block, xcd, fused, tile_block;  // fused < 0: -(trials) of an adaptive chunk
   hipGraphExec_t exec;
   hipGraph_t graph;
+  double rtol = 0.0, atol = 0.0;
 };
 
 struct Engine {
@@ -119,6 +120,22 @@ struct Engine {
   int spin_limit = 1 << 20;
   int persist_cap_block = -1, persist_cap = 0;  // resident workgroups at that block size
   void* psi2 = nullptr;
+  // adaptive Dormand-Prince runs: seven-ring tiles built at the first call from
+  // the device-order adjacency kept on the host, the controller state and the
+  // per-tile error partials
+  struct {
+    std::vector<int64_t> arp;
+    std::vector<int32_t> col;
+    std::vector<double> lw, mw;
+    bool dec = false;
+  } adj;
+  bool dp5_tried = false, has_dp5 = false;
+  int dp5_tile = 1024;        // largest rows per tile tried
+  bool dp5_one_slot = false;  // one compute slot per thread (smaller tiles)
+  DevTiles dp5;
+  Dp5Ctl* dp5ctl = nullptr;
+  double* dp5part = nullptr;
+  uint32_t* dp5arr = nullptr;
   // work
   void* psi = nullptr;
   void* ya = nullptr;
@@ -233,6 +250,8 @@ static void env_defaults(Engine& E) {
   if (const char* s = std::getenv("DEC_BPM_STEP_TILE")) E.step_tile = std::max(64, std::min(4096, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_SPIN_LIMIT")) E.spin_limit = std::max(0, std::atoi(s));
   if (const char* s = std::getenv("DEC_BPM_SORT_RING0")) E.sort_ring0 = std::atoi(s) != 0;
+  if (const char* s = std::getenv("DEC_BPM_DP5_TILE")) E.dp5_tile = std::max(64, std::min(1024, std::atoi(s)));
+  if (const char* s = std::getenv("DEC_BPM_DP5_ONE_SLOT")) E.dp5_one_slot = std::atoi(s) != 0;
   if (const char* s = std::getenv("DEC_BPM_FUSED")) E.fused = std::max(0, std::min(3, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_BLOCK")) E.block = std::max(64, std::min(1024, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_STEPS_PER_GRAPH")) E.spg = std::max(1, std::atoi(s));
@@ -644,6 +663,13 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   if (E.F == 1 && E.beta4 == 0.0) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
   build_step_tiles<T>(E, arp, acol, alw, amw, any_dec);
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  if (E.has_step && E.F == 1) {  // kept for the adaptive integrator's tiles
+    E.adj.arp = std::move(arp);
+    E.adj.col = std::move(acol);
+    E.adj.lw = std::move(alw);
+    E.adj.mw = std::move(amw);
+    E.adj.dec = any_dec;
+  }
   const size_t nv = size_t(n) * E.F;
   E.psi = E.dalloc(nv * 2 * sizeof(T));
   if (E.has_tiles || E.has_step || E.has_step4) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
@@ -837,7 +863,7 @@ static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, int mode) {
   if (le != hipSuccess) fail(DEC_BPM_EHIP, std::string("launch during capture: ") + hipGetErrorString(le));
   hipGraphExec_t exec;
   HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  if (E.graphs.size() >= 8) {
+  if (E.graphs.size() >= 16) {
     (void)hipGraphExecDestroy(E.graphs.front().exec);
     (void)hipGraphDestroy(E.graphs.front().graph);
     E.graphs.erase(E.graphs.begin());
@@ -950,6 +976,127 @@ static void propagate_unsplit_t(Engine& E, void* field, double dz, int64_t n, do
   void* cur = run_middle<T>(E, n, dz, gamma, st, 5);
   launch_perm_out<T>(d, E.perm, cur, field, 0, E.flag, E.block, st);
   check_launch();
+}
+
+// Tiles of the adaptive pair: seven halo rings (one per stage), the stage
+// input and its |.|^2 double-buffered in LDS (6 reals per slot; 63 KiB in
+// complex64, 100 KiB in complex128), one compute slot per thread of a
+// 1024-thread workgroup in complex128, up to two in complex64.
+template <typename T>
+static bool ensure_dp5_tiles(Engine& E) {
+  if (E.dp5_tried) return E.has_dp5;
+  E.dp5_tried = true;
+  if (!E.has_step || E.F != 1 || E.adj.arp.empty()) return false;
+  const size_t lds_max = sizeof(T) == 8 ? 100 * 1024 : 63 * 1024;
+  const int max_compute = (sizeof(T) == 8 || E.dp5_one_slot) ? 1024 : 2048;
+  HostTiles H;
+  for (int ts = E.dp5_tile; ts >= 64; ts /= 2) {
+    if (!make_tiles(E.n_rows, E.adj.arp, E.adj.col, E.adj.lw, E.adj.mw, ts, 7, 7, H, true, E.sort_ring0)) continue;
+    if (size_t(H.max_slots) * 6 * sizeof(T) > lds_max || H.max_compute > max_compute) continue;
+    upload_tiles<T>(E, H, E.adj.dec, E.n_rows, E.dp5);
+    E.has_dp5 = true;
+    break;
+  }
+  if (!E.has_dp5) return false;
+  E.dp5ctl = static_cast<Dp5Ctl*>(E.dalloc(sizeof(Dp5Ctl)));
+  E.dp5part = static_cast<double*>(E.dalloc(size_t(E.dp5.n_tiles) * sizeof(double)));
+  E.dp5arr = static_cast<uint32_t*>(E.dalloc(256));
+  return true;
+}
+
+// threads per workgroup of the adaptive trial kernel: one per compute slot
+// up to 1024, else two slots per thread (complex64 tiles only)
+static int dp5_block(const Engine& E) {
+  const int mc = E.dp5.max_compute;
+  const int one = (mc + 63) / 64 * 64;
+  if (one <= 1024) return std::max(64, one);
+  return ((mc + 1) / 2 + 63) / 64 * 64;
+}
+
+struct AdaptiveResult {
+  int64_t accepted = 0, rejected = 0;
+  double last_h = 0.0, z = 0.0;
+  int status = 0;
+};
+
+// A graph of K back-to-back trials (each ends with its own accept/reject
+// decision on the device), cached with the handle's other graphs.
+template <typename T>
+static hipGraphExec_t dp5_graph(Engine& E, int K, double gamma, double rtol, double atol) {
+  const int blk = dp5_block(E);
+  for (auto& g : E.graphs)
+    if (g.fused == -K && g.gamma == gamma && g.rtol == rtol && g.atol == atol && g.block == blk && g.xcd == E.xcd)
+      return g.exec;
+  const DevOps<T> d = E.ops<T>();
+  const TileOps<T> tl = E.dp5.template ops<T>();
+  const double inv_n = 1.0 / double(E.n_rows);
+  hipGraph_t graph;
+  HIP_OK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < K; ++k)
+    launch_dp5<T>(d, tl, E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5arr, gamma, rtol, atol, inv_n, blk, E.cap);
+  hipError_t le = hipGetLastError();
+  HIP_OK(hipStreamEndCapture(E.cap, &graph));
+  if (le != hipSuccess) fail(DEC_BPM_EHIP, std::string("launch during capture: ") + hipGetErrorString(le));
+  hipGraphExec_t exec;
+  HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  if (E.graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(E.graphs.front().exec);
+    (void)hipGraphDestroy(E.graphs.front().graph);
+    E.graphs.erase(E.graphs.begin());
+  }
+  GraphEntry g{0.0, gamma, 0, blk, E.xcd, -K, 0, exec, graph};
+  g.rtol = rtol;
+  g.atol = atol;
+  E.graphs.push_back(g);
+  return exec;
+}
+
+// Adaptive Dormand-Prince 5(4) from z = 0 to z_end.  Trials and decisions run
+// on the device; the host enqueues them in graph-captured chunks of 8 to 512
+// trials (powers of two) sized from the remaining distance at the current
+// step (trials after the end return at once) and reads the controller state
+// between chunks.
+template <typename T>
+static AdaptiveResult propagate_adaptive_t(Engine& E, void* field, double z_end, double h0, double gamma, double rtol,
+                                           double atol, int64_t max_attempts, hipStream_t st) {
+  const DevOps<T> d = E.ops<T>();
+  const TileOps<T> tl = E.dp5.template ops<T>();
+  const int blk = dp5_block(E);
+  const double inv_n = 1.0 / double(E.n_rows);
+  launch_perm_in<T>(d, E.perm, field, E.psi, 0, E.block, st);
+  launch_dp5_init(E.dp5ctl, E.dp5arr, z_end, h0, max_attempts, 10.0, st);
+  Dp5Ctl c{};
+  c.h_abs = h0;
+  int64_t launched = 0;
+  for (;;) {
+    // trials still expected at the current step size; the first chunk is short,
+    // since h0 may be far from the step the controller settles on
+    const double want = launched == 0 ? 8.0 : std::min((z_end - c.z) / std::max(c.h_abs, 1e-300) + 1.0, 1e9);
+    const int64_t left = max_attempts - launched;
+    int K = 8;
+    while (K < 512 && 2 * K <= want) K *= 2;
+    if (K > left) {  // the last few attempts: plain launches
+      for (int64_t k = 0; k < left; ++k)
+        launch_dp5<T>(d, tl, E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5arr, gamma, rtol, atol, inv_n, blk, st);
+      check_launch();
+      launched += left;
+    } else {
+      HIP_OK(hipGraphLaunch(dp5_graph<T>(E, K, gamma, rtol, atol), st));
+      launched += K;
+    }
+    HIP_OK(hipMemcpyAsync(&c, E.dp5ctl, sizeof(Dp5Ctl), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (c.done || launched >= max_attempts) break;
+  }
+  launch_perm_out<T>(d, E.perm, c.cur ? E.psi2 : E.psi, field, 0, E.flag, E.block, st);
+  check_launch();
+  AdaptiveResult r;
+  r.accepted = c.accepted;
+  r.rejected = c.rejected;
+  r.last_h = c.last_h;
+  r.z = c.z;
+  r.status = c.done ? c.status : 1;
+  return r;
 }
 
 // ---- checkpointed forward and adjoint ----
@@ -1225,6 +1372,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   // implementation keeps the operator rows on chip, the algorithm still needs them every step)
   by[DEC_BPM_K_PERSIST] = by[DEC_BPM_K_STEP];
   by[DEC_BPM_K_UNSPLIT] = by[DEC_BPM_K_STEP];  // one unsplit RK4 step: the same data
+  by[DEC_BPM_K_DP5] = by[DEC_BPM_K_STEP];      // one adaptive trial: the same data
   launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
   launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
   launch_fill<T>(d, E.yb, 0.2, -0.1, B, st);
@@ -1238,6 +1386,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
     const bool tile_kind = kind == DEC_BPM_K_TILE_A || kind == DEC_BPM_K_TILE_B;
     if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step && !E.has_step4) ||
         (kind == DEC_BPM_K_UNSPLIT && (!E.has_step || E.F != 1)) ||
+        (kind == DEC_BPM_K_DP5 && !(E.has_step && E.F == 1 && ensure_dp5_tiles<T>(E))) ||
         (kind == DEC_BPM_K_PERSIST && !(E.has_persist && persist_fits<T>(E)))) {
       if (ms) ms[kind] = 0.0;
       if (bytes) bytes[kind] = 0.0;
@@ -1258,6 +1407,10 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       if (bytes) bytes[kind] = by[kind];
       continue;
     }
+    if (kind == DEC_BPM_K_DP5) {  // trials of step dz (growth factor capped at 1, no end in sight)
+      launch_dp5_init(E.dp5ctl, E.dp5arr, 1e300, dz, int64_t(1) << 62, 1.0, st);
+      HIP_OK(hipStreamSynchronize(st));
+    }
     hipGraph_t g;
     HIP_OK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
     for (int r = 0; r < reps; ++r) {
@@ -1277,6 +1430,9 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       if (kind == DEC_BPM_K_UNSPLIT)
         launch_unsplit<T>(d, E.stp.template ops<T>(), r % 2 ? E.psi2 : E.psi, r % 2 ? E.psi : E.psi2, dz, gamma,
                           E.sblock(), E.cap);
+      if (kind == DEC_BPM_K_DP5)
+        launch_dp5<T>(d, E.dp5.template ops<T>(), E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5arr, gamma, 1e-6, 1e-8,
+                      1.0 / double(E.n_rows), dp5_block(E), E.cap);
     }
     HIP_OK(hipStreamEndCapture(E.cap, &g));
     hipGraphExec_t ex;
@@ -1697,6 +1853,46 @@ int dec_bpm_propagate_unsplit(dec_bpm_t h, void* field, double dz, int64_t n_ste
     decbpm::propagate_unsplit_t<float>(h->E, field, dz, n_steps, gamma, as_stream(stream));
   else
     decbpm::propagate_unsplit_t<double>(h->E, field, dz, n_steps, gamma, as_stream(stream));
+  ABI_CATCH
+}
+
+int dec_bpm_propagate_adaptive(dec_bpm_t h, void* field, double z_end, double h0, double gamma, double rtol,
+                               double atol, int64_t max_attempts, int64_t* n_accepted, int64_t* n_rejected,
+                               double* last_h, double* z_reached, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (n_accepted) *n_accepted = 0;
+  if (n_rejected) *n_rejected = 0;
+  if (last_h) *last_h = 0.0;
+  if (z_reached) *z_reached = 0.0;
+  if (!field) fail(DEC_BPM_EINVAL, "field is NULL");
+  if (!(z_end >= 0.0) || !std::isfinite(z_end)) fail(DEC_BPM_EINVAL, "z_end must be finite and >= 0");
+  if (!(h0 > 0.0) || !std::isfinite(h0)) fail(DEC_BPM_EINVAL, "h0 must be finite and > 0");
+  if (!(rtol >= 0.0) || !(atol > 0.0) || !std::isfinite(rtol) || !std::isfinite(atol))
+    fail(DEC_BPM_EINVAL, "need rtol >= 0 and atol > 0");
+  if (!std::isfinite(gamma)) fail(DEC_BPM_EINVAL, "gamma must be finite");
+  if (max_attempts < 1) fail(DEC_BPM_EINVAL, "max_attempts must be >= 1");
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  if (!E.has_step || E.F != 1)
+    fail(DEC_BPM_EINVAL,
+         "the adaptive integrator runs on one-field step tiles: not available with the beta4 term or with rows of "
+         "more than 12 neighbours");
+  if (z_end == 0.0) return DEC_BPM_OK;
+  const bool ok = E.dtype == DEC_BPM_C64 ? decbpm::ensure_dp5_tiles<float>(E) : decbpm::ensure_dp5_tiles<double>(E);
+  if (!ok) fail(DEC_BPM_EINVAL, "no seven-ring tiling of this mesh fits the adaptive kernel's LDS budget");
+  hipStream_t st = as_stream(stream);
+  const decbpm::AdaptiveResult r =
+      E.dtype == DEC_BPM_C64
+          ? decbpm::propagate_adaptive_t<float>(E, field, z_end, h0, gamma, rtol, atol, max_attempts, st)
+          : decbpm::propagate_adaptive_t<double>(E, field, z_end, h0, gamma, rtol, atol, max_attempts, st);
+  if (n_accepted) *n_accepted = r.accepted;
+  if (n_rejected) *n_rejected = r.rejected;
+  if (last_h) *last_h = r.last_h;
+  if (z_reached) *z_reached = r.z;
+  if (r.status == 1) fail(DEC_BPM_EUNSTABLE, "adaptive run: max_attempts trials did not reach z_end");
+  if (r.status == 2) fail(DEC_BPM_ENONFINITE, "adaptive run: non-finite error norm");
+  if (r.status == 3) fail(DEC_BPM_EUNSTABLE, "adaptive run: step size fell below 10 ulp of z");
   ABI_CATCH
 }
 

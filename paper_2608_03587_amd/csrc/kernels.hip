@@ -1616,6 +1616,107 @@ struct StepTile {
       }
     }
   }
+
+  // One trial step of the Dormand-Prince 5(4) pair on the whole right-hand
+  // side F of step_unsplit.  Stage s (0..6) evaluates k_s = F(y_s) on rings
+  // 0..6-s, gathering y_s from A/SA or B/SB (rings 0..7-s), and forms the next
+  // stage input y_{s+1} = psi + h sum_j a_{s+1,j} k_j on the same rows.  The
+  // seventh stage input is the fifth-order solution y5 (first same as last),
+  // so k_6 = F(y5) completes the embedded estimate e = h sum_j (b_j - b*_j) k_j.
+  // Calls out(slot, r, y5) for every owned row and returns this thread's sum
+  // over its owned rows of (|e| / (atol + rtol max(|psi|, |y5|)))^2.
+  template <typename Out>
+  __device__ double step_dp5(const DevOps<T>& d, C* A, C* Bv, T* SA, T* SB, T h, T gamma, T rtol, T atol,
+                             Out out) const {
+    // Dormand and Prince (1980): stage coefficients a (row s+1 builds y_{s+1}),
+    // fifth-order weights (= row 7) and the differences to the fourth-order ones
+    constexpr double a[7][6] = {
+        {0, 0, 0, 0, 0, 0},
+        {1.0 / 5, 0, 0, 0, 0, 0},
+        {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+        {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+        {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+        {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+        {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84},
+    };
+    constexpr double eb[7] = {35.0 / 384 - 5179.0 / 57600,      0.0, 500.0 / 1113 - 7571.0 / 16695,
+                              125.0 / 192 - 393.0 / 640,        -2187.0 / 6784 + 92097.0 / 339200,
+                              11.0 / 84 - 187.0 / 2100,         -1.0 / 40};
+    const int B = blockDim.x;
+    C p[J], cur[J], k[J][7];
+    T so[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < hd[6]) {
+        p[j] = A[i];
+        cur[j] = p[j];
+        so[j] = SA[i];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+      C* Vin = (s & 1) ? Bv : A;
+      C* Vout = (s & 1) ? A : Bv;
+      T* Sin = (s & 1) ? SB : SA;
+      T* Sout = (s & 1) ? SA : SB;
+      const int ns = hd[6 - s];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int i = threadIdx.x + j * B;
+        if (i < ns) {
+          T ar = T(0), ai = T(0);
+          lsum_w<KMAX>(wd[j], CplxAoS<T>{Vin}, j, cur[j], ar, ai);
+          T th = md[j] * so[j];
+          if constexpr (DEC) th = msum_w<KMAX>(wd[j], Sin, j, th);
+          const T hr = d.p1 * ar - vv[j] * cur[j].x;
+          const T hi = d.p1 * ai - vv[j] * cur[j].y;
+          k[j][s].x = hi - gamma * th * cur[j].y - ww[j] * cur[j].x;
+          k[j][s].y = -hr + gamma * th * cur[j].x - ww[j] * cur[j].y;
+          if (s < 6) {
+            T yx = T(0), yy = T(0);
+#pragma unroll
+            for (int q2 = 0; q2 <= s; ++q2) {
+              if (a[s + 1][q2] != 0.0) {
+                yx += T(a[s + 1][q2]) * k[j][q2].x;
+                yy += T(a[s + 1][q2]) * k[j][q2].y;
+              }
+            }
+            cur[j].x = p[j].x + h * yx;
+            cur[j].y = p[j].y + h * yy;
+            so[j] = cur[j].x * cur[j].x + cur[j].y * cur[j].y;
+            Vout[i] = cur[j];
+            Sout[i] = so[j];
+          }
+        }
+      }
+      if (s < 6) __syncthreads();
+    }
+    double q = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < hd[0]) {
+        T ex = T(0), ey = T(0);
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+          if (eb[s] != 0.0) {
+            ex += T(eb[s]) * k[j][s].x;
+            ey += T(eb[s]) * k[j][s].y;
+          }
+        }
+        ex *= h;
+        ey *= h;
+        const T m0 = sqrt(p[j].x * p[j].x + p[j].y * p[j].y);
+        const T m1 = sqrt(so[j]);
+        const T sc = atol + rtol * (m0 > m1 ? m0 : m1);
+        const T rx = ex / sc, ry = ey / sc;
+        q += double(rx * rx + ry * ry);
+        out(i, rr[j], cur[j]);
+      }
+    }
+    return q;
+  }
 };
 
 // One whole z step, LIN(h) then NL(tau), per tile of rows (five halo rings).
@@ -1688,6 +1789,194 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_rk4u(DevOps<T> d, 
   }
   __syncthreads();
   st.step_unsplit(d, A, Bv, SA, SB, h, gamma, [&](int, int32_t r, const C& v) { out_psi[r] = v; });
+}
+
+// ---- device-coherent access between workgroups of one launch ----
+// Device-coherent (agent scope) element access for state exchanged between
+// workgroups of one persistent launch, which may run on different XCDs.
+__device__ inline float2 coherent_load(const float2* p) {
+  const uint64_t u =
+      __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<float2*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  float2 r;
+  __builtin_memcpy(&r, &u, sizeof(r));
+  return r;
+}
+__device__ inline double2 coherent_load(const double2* p) {
+  uint64_t* q = reinterpret_cast<uint64_t*>(const_cast<double2*>(p));
+  const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double2 r;
+  __builtin_memcpy(&r.x, &a, 8);
+  __builtin_memcpy(&r.y, &b, 8);
+  return r;
+}
+__device__ inline void coherent_store(float2* p, const float2& v) {
+  uint64_t u;
+  __builtin_memcpy(&u, &v, sizeof(u));
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void coherent_store(double2* p, const double2& v) {
+  uint64_t a, b;
+  __builtin_memcpy(&a, &v.x, 8);
+  __builtin_memcpy(&b, &v.y, 8);
+  uint64_t* q = reinterpret_cast<uint64_t*>(p);
+  __hip_atomic_store(q, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until this wave's stores have been acknowledged (vmcnt = 0; the
+// export and LDS counters are left at their maxima).  With every exchanged
+// element written and read by agent-scope accesses, this orders the state
+// stores before the flag store without a cache write-back or invalidate.
+__device__ inline void wait_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ inline double coherent_load(const double* p) {
+  const uint64_t u =
+      __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double r;
+  __builtin_memcpy(&r, &u, 8);
+  return r;
+}
+__device__ inline void coherent_store(double* p, double v) {
+  uint64_t u;
+  __builtin_memcpy(&u, &v, 8);
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Accept/reject rule of the standard embedded-pair controller (Hairer,
+// Norsett and Wanner, Solving ODEs I, section II.4): accept when the error
+// norm is below 1, scale the step by min(facmax, max(0.2, 0.9 err^(-1/5)))
+// with facmax = 1 right after a rejection, clip the next trial to z_end.
+__device__ inline void dp5_decide(Dp5Ctl* ctl, double sumsq, double inv_n) {
+  Dp5Ctl c = *ctl;
+  const double err = sqrt(sumsq * inv_n);
+  c.err = err;
+  if (!isfinite(err)) {
+    c.status = 2;
+    c.done = 1;
+    c.rejected += 1;
+    *ctl = c;
+    return;
+  }
+  double fac;
+  if (err < 1.0) {
+    c.z = c.z_trial;
+    c.cur ^= 1;
+    c.accepted += 1;
+    c.last_h = c.h_step;
+    fac = err == 0.0 ? c.facmax : fmin(c.facmax, 0.9 * pow(err, -0.2));
+    if (c.prev_rejected) fac = fmin(1.0, fac);
+    c.prev_rejected = 0;
+  } else {
+    fac = fmax(0.2, 0.9 * pow(err, -0.2));
+    c.rejected += 1;
+    c.prev_rejected = 1;
+  }
+  c.h_abs = c.h_step * fac;
+  if (c.z >= c.z_end) {
+    c.done = 1;
+  } else if (c.accepted + c.rejected >= c.max_attempts) {
+    c.done = 1;
+    c.status = 1;
+  } else {
+    const double zt = c.z + c.h_abs;
+    c.z_trial = zt < c.z_end ? zt : c.z_end;
+    c.h_step = c.z_trial - c.z;
+    if (c.h_step < 10.0 * (nextafter(c.z, INFINITY) - c.z)) {
+      c.done = 1;
+      c.status = 3;
+    }
+  }
+  *ctl = c;
+}
+
+// One Dormand-Prince 5(4) trial per tile of the seven-ring tiles.  The
+// controller state says which buffer holds the state (x[cur]) and the trial
+// step; the candidate goes to x[1 - cur].  Each tile publishes its share of
+// the squared error norm (agent-scope store, acknowledged before it counts
+// itself in); the workgroup that arrives last sums the shares in tile order,
+// runs the controller and resets the arrival count for the next trial.
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__(1024) k_dp5(DevOps<T> d, TileOps<T> tl, typename CT<T>::C* x0,
+                                              typename CT<T>::C* x1, Dp5Ctl* ctl, double* __restrict__ partial,
+                                              uint32_t* __restrict__ arrivals, T gamma, T rtol, T atol,
+                                              double inv_n) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16];
+  __shared__ int last;
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles || ctl->done) return;
+  const int cur = ctl->cur;
+  const T h = T(ctl->h_step);
+  const C* in_psi = cur ? x1 : x0;
+  C* out_psi = cur ? x0 : x1;
+  const int MS = tl.max_slots;
+  C* A = reinterpret_cast<C*>(smem);
+  C* Bv = A + MS;
+  T* SA = reinterpret_cast<T*>(Bv + MS);
+  T* SB = SA + MS;
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  for (int i = threadIdx.x; i < st.hd[7]; i += blockDim.x) {
+    const C v = in_psi[st.slot_row(i)];
+    A[i] = v;
+    SA[i] = v.x * v.x + v.y * v.y;
+  }
+  __syncthreads();
+  double q = st.step_dp5(d, A, Bv, SA, SB, h, gamma, rtol, atol, [&](int, int32_t r, const C& v) { out_psi[r] = v; });
+  const int nw = int(blockDim.x + 63) / 64;
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_down(q, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    coherent_store(partial + tile, t);
+    wait_stores();
+    last = __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+           uint32_t(tl.n_tiles - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  double t = 0.0;
+  for (int k = threadIdx.x; k < tl.n_tiles; k += blockDim.x) t += coherent_load(partial + k);
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+  __syncthreads();  // red[] reuse
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < nw; ++w) sum += red[w];
+    __hip_atomic_store(arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    dp5_decide(ctl, sum, inv_n);
+  }
+}
+
+__global__ void k_dp5_init(Dp5Ctl* ctl, uint32_t* arrivals, double z_end, double h0, int64_t max_attempts,
+                           double facmax) {
+  if (threadIdx.x != 0) return;
+  Dp5Ctl c;
+  c.z = 0.0;
+  c.z_end = z_end;
+  c.h_abs = h0;
+  c.z_trial = h0 < z_end ? h0 : z_end;
+  c.h_step = c.z_trial;
+  c.last_h = 0.0;
+  c.err = 0.0;
+  c.facmax = facmax;
+  c.accepted = c.rejected = 0;
+  c.max_attempts = max_attempts;
+  c.cur = 0;
+  c.prev_rejected = 0;
+  c.done = z_end <= 0.0 || max_attempts <= 0;
+  c.status = (z_end > 0.0 && max_attempts <= 0) ? 1 : 0;
+  *ctl = c;
+  *arrivals = 0u;
 }
 
 // One whole z step with the beta4 L^2 term per tile (8 or 9 halo rings).
@@ -1913,48 +2202,6 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
 }
 
 // ---- persistent z stepping on resident tiles ----
-// Device-coherent (agent scope) element access for state exchanged between
-// workgroups of one persistent launch, which may run on different XCDs.
-__device__ inline float2 coherent_load(const float2* p) {
-  const uint64_t u =
-      __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<float2*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  float2 r;
-  __builtin_memcpy(&r, &u, sizeof(r));
-  return r;
-}
-__device__ inline double2 coherent_load(const double2* p) {
-  uint64_t* q = reinterpret_cast<uint64_t*>(const_cast<double2*>(p));
-  const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  double2 r;
-  __builtin_memcpy(&r.x, &a, 8);
-  __builtin_memcpy(&r.y, &b, 8);
-  return r;
-}
-__device__ inline void coherent_store(float2* p, const float2& v) {
-  uint64_t u;
-  __builtin_memcpy(&u, &v, sizeof(u));
-  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void coherent_store(double2* p, const double2& v) {
-  uint64_t a, b;
-  __builtin_memcpy(&a, &v.x, 8);
-  __builtin_memcpy(&b, &v.y, 8);
-  uint64_t* q = reinterpret_cast<uint64_t*>(p);
-  __hip_atomic_store(q, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(q + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Wait until this wave's stores have been acknowledged (vmcnt = 0; the
-// export and LDS counters are left at their maxima).  With every exchanged
-// element written and read by agent-scope accesses, this orders the state
-// stores before the flag store without a cache write-back or invalidate.
-__device__ inline void wait_stores() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0x0F70);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
 // n_steps merged z steps in one launch, one workgroup per tile, all resident
 // (cooperative launch).  The operator rows stay in registers for the whole
 // launch; per step only the state crosses memory.  The state alternates
@@ -2562,6 +2809,38 @@ void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, v
 #undef DECBPM_STEP
 }
 
+void launch_dp5_init(Dp5Ctl* ctl, uint32_t* arrivals, double z_end, double h0, int64_t max_attempts, double facmax,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_dp5_init, dim3(1), dim3(64), 0, st, ctl, arrivals, z_end, h0, max_attempts, facmax);
+}
+
+template <typename T>
+void launch_dp5(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp5Ctl* ctl, double* partial,
+                uint32_t* arrivals, double gamma, double rtol, double atol, double inv_n, int block, hipStream_t st) {
+  using C = typename CT<T>::C;
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * 2 * (sizeof(C) + sizeof(T));
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_DP5(KM, DEC, JJ)                                                                                   \
+  hipLaunchKernelGGL((k_dp5<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, static_cast<C*>(x0),         \
+                     static_cast<C*>(x1), ctl, partial, arrivals, T(gamma), T(rtol), T(atol), inv_n)
+  // complex128 tiles keep every compute slot on its own thread (J = 1): two
+  // slots of rows with 12 neighbours need more than the 128 registers of a
+  // 1024-thread workgroup, and halving the workgroup costs more than the spills
+#define DECBPM_DP5_J(KM, DEC)                          \
+  if constexpr (sizeof(T) == 8) DECBPM_DP5(KM, DEC, 1); \
+  else if (J <= 1) DECBPM_DP5(KM, DEC, 1);              \
+  else DECBPM_DP5(KM, DEC, 2);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_DP5_J(8, true) } else { DECBPM_DP5_J(8, false) }
+  } else {
+    if (dec) { DECBPM_DP5_J(12, true) } else { DECBPM_DP5_J(12, false) }
+  }
+#undef DECBPM_DP5_J
+#undef DECBPM_DP5
+}
+
 template <typename T>
 void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
                     double gamma, int block, hipStream_t st) {
@@ -2835,6 +3114,8 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                   int, hipStream_t);                                                             \
   template void launch_unsplit<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, int,    \
                                   hipStream_t);                                                                  \
+  template void launch_dp5<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, Dp5Ctl*, double*, uint32_t*,     \
+                              double, double, double, double, int, hipStream_t);                                 \
   template void launch_step_rec<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, void*, void*, void*,    \
                                    void*, double, double, double, int, hipStream_t);                             \
   template void launch_step_adj<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*,     \

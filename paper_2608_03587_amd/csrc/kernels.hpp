@@ -182,6 +182,35 @@ template <typename T>
 void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
                     double gamma, int block, hipStream_t st);
 
+// Device-resident state of an adaptive Dormand-Prince 5(4) run.  A trial
+// kernel reads the state from x[cur], writes the fifth-order candidate to
+// x[1 - cur], and its last-finishing workgroup accepts (cur flips, z advances)
+// or rejects and sets the next trial step.  Once done is set, trials return
+// at once.
+struct Dp5Ctl {
+  double z, z_end;    // accepted position, end of the run
+  double h_abs;       // step size before clipping to z_end
+  double h_step;      // the trial step of the next attempt (clipped)
+  double z_trial;     // z + h_step
+  double last_h;      // last accepted step
+  double err;         // error norm of the last attempt
+  double facmax;      // largest growth factor after an accepted step
+  int64_t accepted, rejected, max_attempts;
+  int32_t cur, prev_rejected, done;
+  int32_t status;  // 0 running or reached z_end, 1 attempts exhausted, 2 non-finite error, 3 step underflow
+};
+
+// Sets up an adaptive run: z = 0, first trial step min(h0, z_end), cur = 0,
+// arrival count 0; done at once when z_end == 0.
+void launch_dp5_init(Dp5Ctl* ctl, uint32_t* arrivals, double z_end, double h0, int64_t max_attempts, double facmax,
+                     hipStream_t st);
+// One trial step of the pair and its accept/reject decision on the seven-ring
+// tiles of tl (one ring per stage).  partial: n_tiles doubles of scratch;
+// inv_n: 1 / vertex count (the norm is a mean over vertices).
+template <typename T>
+void launch_dp5(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp5Ctl* ctl, double* partial,
+                uint32_t* arrivals, double gamma, double rtol, double atol, double inv_n, int block, hipStream_t st);
+
 // The one-kernel step that also writes the owned rows' stage vectors y1..y3
 // and the state before the Kerr substep (the adjoint's forward recompute).
 template <typename T>

@@ -231,6 +231,83 @@ def test_unsplit_rk4_matches_oracle(dtype, nl):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adaptive_dp54_matches_oracle(dtype):
+    """Adaptive Dormand-Prince 5(4) with the trials, error norms and accept/reject
+    decisions on the device, against the oracle's adaptive run: in complex128 the
+    same step sequence (counts, last step) and the state within the gate; in
+    complex64 (looser tolerances) the state within the complex64 gate."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    ops = oracle_ops(w)
+    m = lib_mesh(w, dtype)
+    u = dev(w.u0, dtype)
+    rtol, atol = (1e-9, 1e-11) if dtype == "c128" else (1e-5, 1e-7)
+    # (z_end, h0): accuracy-limited steps with a rejection, a first trial clipped to z_end,
+    # and a large first trial that is rejected several times
+    for z_end, h0 in ((20 * w.dz, w.dz), (0.3 * w.dz, w.dz), (8 * w.dz, 40 * w.dz)):
+        say("adaptive", dtype, w.mesh.n_vert, z_end, h0)
+        f = u.clone()
+        st = m.propagate_adaptive(f, z_end, h0, w.gamma, rtol=rtol, atol=atol)
+        m.check_finite()
+        ref, rs = US.propagate_dp54(w.u0, ops, z_end, h0, w.gamma, rtol=rtol, atol=atol)
+        say("  gpu", st, "oracle", rs)
+        assert st["z"] == z_end
+        if dtype == "c128":
+            assert (st["accepted"], st["rejected"]) == (rs["accepted"], rs["rejected"])
+            # the error norm is a difference of stage sums (cancellation), so its low bits
+            # depend on summation order; each step size inherits that at the 1e-8 level
+            assert abs(st["last_h"] - rs["last_h"]) <= 1e-6 * rs["last_h"]
+        else:
+            assert abs(st["accepted"] - rs["accepted"]) <= 1 + rs["accepted"] // 10
+        err = rel(host(f), ref)
+        say("  rel err", err)
+        assert err < GATE[dtype], (z_end, h0, err)
+    # a second handle call after a different run gives the same result (controller reset)
+    f1 = u.clone()
+    m.propagate_adaptive(f1, 2 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
+    f2 = u.clone()
+    m.propagate_adaptive(f2, 2 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
+    assert torch.equal(f1, f2)
+    # z_end = 0: nothing happens
+    f = u.clone()
+    st = m.propagate_adaptive(f, 0.0, w.dz, w.gamma)
+    assert torch.equal(f, u) and st["accepted"] == 0
+    # too few attempts: EUNSTABLE, the counters say how far it got and the field is the
+    # last accepted state (finite)
+    f = u.clone()
+    with pytest.raises(api.DecBpmError) as e:
+        m.propagate_adaptive(f, 50 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol, max_attempts=3)
+    assert e.value.code == B.EUNSTABLE
+    assert e.value.stats["accepted"] + e.value.stats["rejected"] == 3 and e.value.stats["z"] < 50 * w.dz
+    assert torch.isfinite(torch.view_as_real(f)).all()
+    # bad arguments
+    for kw in ({"rtol": -1.0}, {"atol": 0.0}):
+        with pytest.raises(api.DecBpmError) as e:
+            m.propagate_adaptive(u.clone(), w.dz, w.dz, w.gamma, **kw)
+        assert e.value.code == B.EINVAL
+    assert m.time_kernels(w.dz, w.gamma, reps=10)["dp5"]["ms"] > 0
+
+
+def test_adaptive_dp54_small_meshes_and_refusals():
+    """Few tiles (a 4k-vertex mesh) and the lumped Kerr term, complex128; a beta4
+    handle refuses before any device work."""
+    w = case("plain_small")
+    for nl in ("dec", "lumped"):
+        ops = oracle_ops(w, nl)
+        m = lib_mesh(w, "c128", nl)
+        say("adaptive small", nl, w.mesh.n_vert)
+        f = dev(w.u0, "c128")
+        st = m.propagate_adaptive(f, 200 * w.dz, w.dz, w.gamma, rtol=1e-10, atol=1e-12)
+        ref, rs = US.propagate_dp54(w.u0, ops, 200 * w.dz, w.dz, w.gamma, rtol=1e-10, atol=1e-12)
+        assert (st["accepted"], st["rejected"]) == (rs["accepted"], rs["rejected"]), (st, rs)
+        assert rel(host(f), ref) < GATE["c128"]
+    wb = case("vortex", n_vert=20000, n_steps=10)
+    mb = lib_mesh(wb, "c128")
+    with pytest.raises(api.DecBpmError) as e:
+        mb.propagate_adaptive(dev(wb.u0, "c128"), wb.dz, wb.dz, wb.gamma)
+    assert e.value.code == B.EINVAL
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_step_index_full_size_prefix(dtype):
     """The full 250k-vertex step-index workload, 20 steps, in the bench's launch configuration."""
     w = case("step_index")

@@ -150,6 +150,17 @@ def test_host_only_handle_runs_every_check_then_reports_no_device():
     assert lib.dec_bpm_propagate(m.handle, fake, 1e-3, 10, 1.0, None) == B.ENODEVICE
     assert lib.dec_bpm_propagate_unsplit(m.handle, fake, 3.0 / rho, 10, 1.0, None) == B.EUNSTABLE
     assert lib.dec_bpm_propagate_unsplit(m.handle, fake, 1e-3, 10, 1.0, None) == B.ENODEVICE
+    acc, rej = ctypes.c_int64(7), ctypes.c_int64(7)
+    lh, zr = ctypes.c_double(7.0), ctypes.c_double(7.0)
+    ad = lib.dec_bpm_propagate_adaptive
+    for args in ((-1.0, 1e-3, 1e-9, 1e-11, 100), (1.0, 0.0, 1e-9, 1e-11, 100), (1.0, 1e-3, -1.0, 1e-11, 100),
+                 (1.0, 1e-3, 1e-9, 0.0, 100), (1.0, 1e-3, 1e-9, 1e-11, 0), (float("inf"), 1e-3, 1e-9, 1e-11, 100)):
+        z_end, h0, rtol, atol, mx = args
+        assert ad(m.handle, fake, z_end, h0, 1.0, rtol, atol, mx, None, None, None, None, None) == B.EINVAL, args
+    assert ad(m.handle, None, 1.0, 1e-3, 1.0, 1e-9, 1e-11, 100, None, None, None, None, None) == B.EINVAL
+    assert ad(m.handle, fake, 1.0, 1e-3, 1.0, 1e-9, 1e-11, 100, ctypes.byref(acc), ctypes.byref(rej),
+              ctypes.byref(lh), ctypes.byref(zr), None) == B.ENODEVICE
+    assert (acc.value, rej.value, lh.value, zr.value) == (0, 0, 0.0, 0.0)  # counters cleared on every call
     assert lib.dec_bpm_apply(m.handle, 0, fake, fake, None) == B.EINVAL  # x == y
     assert lib.dec_bpm_diagnostics(m.handle, fake, 1.0, None, None, None) == B.ENODEVICE
     size = ctypes.c_size_t()
