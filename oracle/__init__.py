@@ -14,7 +14,10 @@ What it computes, in the paper's order and notation:
 * ``stepper``    z-marching: exact Kerr/absorber flow, classical RK4 for the
                  linear part, Strang composition (half steps are never merged).
 * ``unsplit``    z-marching of the whole right-hand side (Kerr term inside
-                 every stage) with classical RK4 at a fixed step.
+                 every stage): classical RK4 at a fixed step and the adaptive
+                 Dormand-Prince 5(4) pair with its step-size controller.
+* ``soliton``    nonlinear eigenmodes (soliton launches) by imaginary-z
+                 propagation with power renormalisation.
 * ``diagnostics`` power, Hamiltonian, overlap, the paper's intensity error
                  (Eq. 15) and the plain relative L2 error.
 * ``adjoint``    the exact reverse of ``stepper.propagate`` for the overlap objective,
@@ -27,5 +30,6 @@ against a closed form, invariant, hand-computed value or brute-force result.
 """
 from .dec import Operators, assemble  # noqa: F401
 from .stepper import propagate, strang_step, nl_flow, lin_rk4  # noqa: F401
-from .unsplit import rhs, rk4_step, propagate_rk4  # noqa: F401
+from .unsplit import rhs, rk4_step, propagate_rk4, propagate_dp54  # noqa: F401
+from .soliton import find_mode  # noqa: F401
 from .diagnostics import power, hamiltonian, overlap, e_rel, rel_l2  # noqa: F401
