@@ -202,6 +202,30 @@ int dec_bpm_propagate_adaptive(dec_bpm_t h, void* field, double z_end, double h0
                                double atol, int64_t max_attempts, int64_t* n_accepted, int64_t* n_rejected,
                                double* last_h, double* z_reached, void* stream);
 
+/*
+ * Nonlinear eigenmode for a soliton launch (the stationary solutions
+ * Psi(z) = phi e^{-i mu z} the paper launches in its soliton benchmark, whose
+ * own solver is not given): mu phi = H_lin phi - gamma (M |phi|^2) phi at the
+ * prescribed power P = sum_p H0_p |phi_p|^2 (the absorber plays no part).
+ * Gradient flow with discrete normalisation: from phi_0 = field scaled to
+ * power P, each iteration takes y = R4(-dtau A_k) phi_k (one classical RK4
+ * step of dx/dtau = -A_k x, A_k = H_lin - gamma diag(M |phi_k|^2) frozen at
+ * phi_k) and rescales y to power P.  Iteration k first evaluates
+ * mu_k = Re<phi_k, A_k phi_k>_H0 / P and r_k = ||A_k phi_k - mu_{k-1} phi_k||_H0
+ * / ||phi_k||_H0 (mu_{-1} = 0) and stops with phi_k when k > 0, tol > 0 and
+ * r_k <= tol |mu_k|.  tol == 0 runs exactly max_iter iterations and returns
+ * phi_{max_iter} (mu, r of the last tested iterate).  Converges to the mode
+ * of lowest mu reachable from the start.  field (caller order) is the start
+ * on entry and the mode on return; mu, residual, iterations (the k of the
+ * result) may be NULL.  Synchronises `stream`.  One-field step tiles only
+ * (EINVAL with the beta4 term or rows of more than 12 neighbours);
+ * EUNSTABLE if dtau * rho(H_lin) exceeds the RK4 margin or if tol > 0 and
+ * max_iter iterations did not converge (field then holds the last iterate),
+ * ENONFINITE for a start without power or a non-finite iterate.
+ */
+int dec_bpm_find_mode(dec_bpm_t h, void* field, double power, double dtau, double gamma, double tol,
+                      int64_t max_iter, double* mu, double* residual, int64_t* iterations, void* stream);
+
 /* Synchronise `stream` and return ENONFINITE if the last propagate produced a
  * non-finite value (the flag is cleared), else OK. */
 int dec_bpm_check_finite(dec_bpm_t h, void* stream);
@@ -312,7 +336,8 @@ enum {
   DEC_BPM_K_PERSIST = 6,  /* persistent launch: time and bytes per z step         */
   DEC_BPM_K_UNSPLIT = 7,  /* one unsplit RK4 step (dec_bpm_propagate_unsplit)     */
   DEC_BPM_K_DP5 = 8,      /* one adaptive Dormand-Prince trial (seven stages)     */
-  DEC_BPM_NUM_KERNELS = 9
+  DEC_BPM_K_MODE = 9,     /* one nonlinear mode iteration (dec_bpm_find_mode)     */
+  DEC_BPM_NUM_KERNELS = 10
 };
 int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
                          void* stream);

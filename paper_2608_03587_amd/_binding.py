@@ -20,7 +20,7 @@ OK, EINVAL, EMESH, EUNSTABLE, ENOMEM, EHIP, ENONFINITE, EWORKSPACE, ENODEVICE = 
 C64, C128 = 1, 2
 NL_DEC, NL_LUMPED = 0, 1
 OP_L, OP_L2, OP_H = 0, 1, 2
-K_KERR, K_STAGE, K_LAP, K_TILE_A, K_TILE_B, K_STEP, K_PERSIST, K_UNSPLIT, K_DP5, NUM_KERNELS = range(10)
+K_KERR, K_STAGE, K_LAP, K_TILE_A, K_TILE_B, K_STEP, K_PERSIST, K_UNSPLIT, K_DP5, K_MODE, NUM_KERNELS = range(11)
 
 ERROR_NAMES = {EINVAL: "EINVAL", EMESH: "EMESH", EUNSTABLE: "EUNSTABLE", ENOMEM: "ENOMEM", EHIP: "EHIP",
                ENONFINITE: "ENONFINITE", EWORKSPACE: "EWORKSPACE", ENODEVICE: "ENODEVICE"}
@@ -69,6 +69,8 @@ _SIGNATURES = [
     ("dec_bpm_linear_step", c_int, [c_vp, c_vp, c_dbl, c_vp]),
     ("dec_bpm_propagate", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_vp]),
     ("dec_bpm_propagate_unsplit", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_vp]),
+    ("dec_bpm_find_mode", c_int, [c_vp, c_vp, c_dbl, c_dbl, c_dbl, c_dbl, c_i64, ctypes.POINTER(c_dbl),
+                                  ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64), c_vp]),
     ("dec_bpm_propagate_adaptive", c_int, [c_vp, c_vp, c_dbl, c_dbl, c_dbl, c_dbl, c_dbl, c_i64,
                                            ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
                                            ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), c_vp]),

@@ -164,6 +164,24 @@ class Mesh:
             raise
         return stats
 
+    def find_mode(self, field: torch.Tensor, power: float, dtau: float, gamma: float = 1.0, tol: float = 1e-10,
+                  max_iter: int = 1 << 40, stream=None):
+        """Nonlinear eigenmode of the given power by imaginary-z RK4 with renormalisation,
+        started from ``field`` and returned in it.  Synchronises the stream and returns
+        ``{"mu", "residual", "iterations"}``; on a failed run the raised error carries them
+        as ``.stats``."""
+        mu, res, it = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_int64(0)
+        code = B.lib().dec_bpm_find_mode(self._h, self._field(field), float(power), float(dtau), float(gamma),
+                                         float(tol), int(max_iter), ctypes.byref(mu), ctypes.byref(res),
+                                         ctypes.byref(it), _stream(stream))
+        stats = {"mu": mu.value, "residual": res.value, "iterations": it.value}
+        try:
+            B.check(code)
+        except DecBpmError as e:
+            e.stats = stats
+            raise
+        return stats
+
     def check_finite(self, stream=None):
         B.check(B.lib().dec_bpm_check_finite(self._h, _stream(stream)))
 
@@ -251,7 +269,7 @@ def _time_kernels(fn, h, dz, gamma, reps, stream):
     by = (ctypes.c_double * B.NUM_KERNELS)()
     B.check(fn(h, float(dz), float(gamma), int(reps), ms, by, _stream(stream)))
     names = {B.K_KERR: "kerr", B.K_STAGE: "stage", B.K_LAP: "lap", B.K_TILE_A: "tile_a", B.K_TILE_B: "tile_b",
-             B.K_STEP: "step", B.K_PERSIST: "persist", B.K_UNSPLIT: "unsplit", B.K_DP5: "dp5"}
+             B.K_STEP: "step", B.K_PERSIST: "persist", B.K_UNSPLIT: "unsplit", B.K_DP5: "dp5", B.K_MODE: "mode"}
     return {names[k]: {"ms": ms[k], "bytes": by[k]} for k in range(B.NUM_KERNELS)}
 
 

@@ -136,6 +136,10 @@ struct Engine {
   Dp5Ctl* dp5ctl = nullptr;
   double* dp5part = nullptr;
   uint32_t* dp5arr = nullptr;
+  // nonlinear mode iteration on the step tiles
+  ModeCtl* modectl = nullptr;
+  double* modepart = nullptr;
+  uint32_t* modearr = nullptr;
   // work
   void* psi = nullptr;
   void* ya = nullptr;
@@ -1099,6 +1103,89 @@ static AdaptiveResult propagate_adaptive_t(Engine& E, void* field, double z_end,
   return r;
 }
 
+struct ModeResult {
+  double mu = 0.0, res = 0.0;
+  int64_t iter = 0;
+  int status = 0;
+};
+
+// A graph of K back-to-back mode iterations, cached with the other graphs
+// (key: fused = -(1 << 20) - K).
+template <typename T>
+static hipGraphExec_t mode_graph(Engine& E, int K, double dtau, double gamma) {
+  const int blk = E.sblock();
+  const int key = -(1 << 20) - K;
+  for (auto& g : E.graphs)
+    if (g.fused == key && g.dz == dtau && g.gamma == gamma && g.block == blk && g.xcd == E.xcd) return g.exec;
+  const DevOps<T> d = E.ops<T>();
+  const TileOps<T> tl = E.stp.template ops<T>();
+  hipGraph_t graph;
+  HIP_OK(hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < K; ++k)
+    launch_mode<T>(d, tl, E.psi, E.psi2, E.modectl, E.modepart, E.modearr, dtau, gamma, blk, E.cap);
+  hipError_t le = hipGetLastError();
+  HIP_OK(hipStreamEndCapture(E.cap, &graph));
+  if (le != hipSuccess) fail(DEC_BPM_EHIP, std::string("launch during capture: ") + hipGetErrorString(le));
+  hipGraphExec_t exec;
+  HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  if (E.graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(E.graphs.front().exec);
+    (void)hipGraphDestroy(E.graphs.front().graph);
+    E.graphs.erase(E.graphs.begin());
+  }
+  E.graphs.push_back(GraphEntry{dtau, gamma, 0, blk, E.xcd, key, 0, exec, graph});
+  return exec;
+}
+
+// Nonlinear mode iteration from the caller's field (the start) to the
+// returned mode, in place.  Iterations and stopping tests run on the device
+// in graph-captured chunks of 8, 16, ..., 512; the host reads the state
+// between chunks and finally scales the current iterate to the power P.
+template <typename T>
+static ModeResult find_mode_t(Engine& E, void* field, double power, double dtau, double gamma, double tol,
+                              int64_t max_iter, hipStream_t st) {
+  if (!E.modectl) {
+    E.modectl = static_cast<ModeCtl*>(E.dalloc(sizeof(ModeCtl)));
+    E.modepart = static_cast<double*>(E.dalloc(size_t(E.stp.n_tiles) * 4 * sizeof(double)));
+    E.modearr = static_cast<uint32_t*>(E.dalloc(256));
+  }
+  const DevOps<T> d = E.ops<T>();
+  const TileOps<T> tl = E.stp.template ops<T>();
+  const int blk = E.sblock();
+  launch_perm_in<T>(d, E.perm, field, E.psi, 0, E.block, st);
+  launch_diag<T>(d, E.psi, 0.0, E.partials, E.n_red_blocks, E.red_out, st);
+  launch_mode_init(E.modectl, E.modearr, E.red_out, power, tol, max_iter, st);
+  ModeCtl c{};
+  int64_t launched = 0;
+  int K = 8;
+  for (;;) {
+    const int64_t left = max_iter - launched;
+    if (K > left) {
+      for (int64_t k = 0; k < left; ++k)
+        launch_mode<T>(d, tl, E.psi, E.psi2, E.modectl, E.modepart, E.modearr, dtau, gamma, blk, st);
+      check_launch();
+      launched += left;
+    } else {
+      HIP_OK(hipGraphLaunch(mode_graph<T>(E, K, dtau, gamma), st));
+      launched += K;
+      K = std::min(K * 2, 512);
+    }
+    HIP_OK(hipMemcpyAsync(&c, E.modectl, sizeof(ModeCtl), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (c.done || launched >= max_iter) break;
+  }
+  void* x = c.cur ? E.psi2 : E.psi;
+  launch_scale<T>(E.n_rows, x, c.s, E.block, st);
+  launch_perm_out<T>(d, E.perm, x, field, 0, E.flag, E.block, st);
+  check_launch();
+  ModeResult r;
+  r.mu = c.mu;
+  r.res = c.res;
+  r.iter = c.iter;
+  r.status = c.done ? c.status : 1;
+  return r;
+}
+
 // ---- checkpointed forward and adjoint ----
 struct WsLayout {
   int64_t K = 0, S = 0;
@@ -1373,6 +1460,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   by[DEC_BPM_K_PERSIST] = by[DEC_BPM_K_STEP];
   by[DEC_BPM_K_UNSPLIT] = by[DEC_BPM_K_STEP];  // one unsplit RK4 step: the same data
   by[DEC_BPM_K_DP5] = by[DEC_BPM_K_STEP];      // one adaptive trial: the same data
+  by[DEC_BPM_K_MODE] = by[DEC_BPM_K_STEP];     // one mode iteration: the same data
   launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
   launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
   launch_fill<T>(d, E.yb, 0.2, -0.1, B, st);
@@ -1387,6 +1475,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
     if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step && !E.has_step4) ||
         (kind == DEC_BPM_K_UNSPLIT && (!E.has_step || E.F != 1)) ||
         (kind == DEC_BPM_K_DP5 && !(E.has_step && E.F == 1 && ensure_dp5_tiles<T>(E))) ||
+        (kind == DEC_BPM_K_MODE && !(E.has_step && E.F == 1)) ||
         (kind == DEC_BPM_K_PERSIST && !(E.has_persist && persist_fits<T>(E)))) {
       if (ms) ms[kind] = 0.0;
       if (bytes) bytes[kind] = 0.0;
@@ -1406,6 +1495,16 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       if (ms) ms[kind] = double(t) / reps;
       if (bytes) bytes[kind] = by[kind];
       continue;
+    }
+    if (kind == DEC_BPM_K_MODE) {  // iterations of step dz at power 1, no stopping test
+      if (!E.modectl) {
+        E.modectl = static_cast<ModeCtl*>(E.dalloc(sizeof(ModeCtl)));
+        E.modepart = static_cast<double*>(E.dalloc(size_t(E.stp.n_tiles) * 4 * sizeof(double)));
+        E.modearr = static_cast<uint32_t*>(E.dalloc(256));
+      }
+      launch_diag<T>(d, E.psi, 0.0, E.partials, E.n_red_blocks, E.red_out, st);
+      launch_mode_init(E.modectl, E.modearr, E.red_out, 1.0, 0.0, int64_t(1) << 62, st);
+      HIP_OK(hipStreamSynchronize(st));
     }
     if (kind == DEC_BPM_K_DP5) {  // trials of step dz (growth factor capped at 1, no end in sight)
       launch_dp5_init(E.dp5ctl, E.dp5arr, 1e300, dz, int64_t(1) << 62, 1.0, st);
@@ -1430,6 +1529,9 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       if (kind == DEC_BPM_K_UNSPLIT)
         launch_unsplit<T>(d, E.stp.template ops<T>(), r % 2 ? E.psi2 : E.psi, r % 2 ? E.psi : E.psi2, dz, gamma,
                           E.sblock(), E.cap);
+      if (kind == DEC_BPM_K_MODE)
+        launch_mode<T>(d, E.stp.template ops<T>(), E.psi, E.psi2, E.modectl, E.modepart, E.modearr, dz, gamma,
+                       E.sblock(), E.cap);
       if (kind == DEC_BPM_K_DP5)
         launch_dp5<T>(d, E.dp5.template ops<T>(), E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5arr, gamma, 1e-6, 1e-8,
                       1.0 / double(E.n_rows), dp5_block(E), E.cap);
@@ -1893,6 +1995,38 @@ int dec_bpm_propagate_adaptive(dec_bpm_t h, void* field, double z_end, double h0
   if (r.status == 1) fail(DEC_BPM_EUNSTABLE, "adaptive run: max_attempts trials did not reach z_end");
   if (r.status == 2) fail(DEC_BPM_ENONFINITE, "adaptive run: non-finite error norm");
   if (r.status == 3) fail(DEC_BPM_EUNSTABLE, "adaptive run: step size fell below 10 ulp of z");
+  ABI_CATCH
+}
+
+int dec_bpm_find_mode(dec_bpm_t h, void* field, double power, double dtau, double gamma, double tol,
+                      int64_t max_iter, double* mu, double* residual, int64_t* iterations, void* stream) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  if (mu) *mu = 0.0;
+  if (residual) *residual = 0.0;
+  if (iterations) *iterations = 0;
+  if (!field) fail(DEC_BPM_EINVAL, "field is NULL");
+  if (!(power > 0.0) || !std::isfinite(power)) fail(DEC_BPM_EINVAL, "power must be finite and > 0");
+  if (!(dtau > 0.0) || !std::isfinite(dtau)) fail(DEC_BPM_EINVAL, "dtau must be finite and > 0");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) fail(DEC_BPM_EINVAL, "tol must be finite and >= 0");
+  if (!std::isfinite(gamma)) fail(DEC_BPM_EINVAL, "gamma must be finite");
+  if (max_iter < 1) fail(DEC_BPM_EINVAL, "max_iter must be >= 1");
+  decbpm::check_stability(E, dtau);
+  if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
+  if (!E.has_step || E.F != 1)
+    fail(DEC_BPM_EINVAL,
+         "the mode solver runs on one-field step tiles: not available with the beta4 term or with rows of more "
+         "than 12 neighbours");
+  hipStream_t st = as_stream(stream);
+  const decbpm::ModeResult r =
+      E.dtype == DEC_BPM_C64 ? decbpm::find_mode_t<float>(E, field, power, dtau, gamma, tol, max_iter, st)
+                             : decbpm::find_mode_t<double>(E, field, power, dtau, gamma, tol, max_iter, st);
+  if (mu) *mu = r.mu;
+  if (residual) *residual = r.res;
+  if (iterations) *iterations = r.iter;
+  if (r.status == 1) fail(DEC_BPM_EUNSTABLE, "mode solver: no convergence within max_iter iterations");
+  if (r.status == 2) fail(DEC_BPM_ENONFINITE, "mode solver: zero or non-finite power or quotient");
   ABI_CATCH
 }
 

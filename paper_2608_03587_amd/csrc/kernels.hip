@@ -1717,6 +1717,72 @@ struct StepTile {
     }
     return q;
   }
+
+  // One step of the nonlinear mode iteration: y = R4(-h A) phi with
+  // A = H_lin - gamma diag(M |phi|^2), the nonlinearity frozen at phi, in
+  // Horner form.  The innermost product g = A phi is taken on rings 0..3 with
+  // the |phi|^2 gather (SA); theta stays in registers for the three outer
+  // products (rings 0..2, 0..1, 0), which gather from the other buffer.  Adds
+  // over the owned rows, H0-weighted: acc[0] += Re(conj(phi) g),
+  // acc[1] += |g - mu_prev phi|^2, acc[2] += |phi|^2, acc[3] += |y|^2, and
+  // calls out(slot, r, y).
+  template <typename Out>
+  __device__ void step_mode(const DevOps<T>& d, C* A, C* Bv, const T* SA, T h, T gamma, T mu_prev, double (&acc)[4],
+                            Out out) const {
+    const int B = blockDim.x;
+    C p[J], cur[J];
+    T th[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < hd[3]) {
+        p[j] = A[i];
+        cur[j] = p[j];
+        th[j] = md[j] * SA[i];
+      }
+    }
+    const T cf[4] = {h / T(4), h / T(3), h / T(2), h};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      C* Vin = (k & 1) ? Bv : A;
+      C* Vout = (k & 1) ? A : Bv;
+      const int nk = hd[3 - k];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int i = threadIdx.x + j * B;
+        if (i < nk) {
+          T ar = T(0), ai = T(0);
+          lsum_w<KMAX>(wd[j], CplxAoS<T>{Vin}, j, cur[j], ar, ai);
+          if (k == 0) {
+            if constexpr (DEC) th[j] = msum_w<KMAX>(wd[j], SA, j, th[j]);
+            th[j] *= gamma;
+          }
+          C g;  // A cur = p1 L cur - v cur - gamma theta cur
+          g.x = d.p1 * ar - (vv[j] + th[j]) * cur[j].x;
+          g.y = d.p1 * ai - (vv[j] + th[j]) * cur[j].y;
+          if (k == 0 && i < hd[0]) {
+            const double w0 = d.h0[rr[j]];
+            acc[0] += w0 * (double(p[j].x) * g.x + double(p[j].y) * g.y);
+            const double ex = double(g.x) - double(mu_prev) * p[j].x, ey = double(g.y) - double(mu_prev) * p[j].y;
+            acc[1] += w0 * (ex * ex + ey * ey);
+            acc[2] += w0 * (double(p[j].x) * p[j].x + double(p[j].y) * p[j].y);
+          }
+          cur[j].x = p[j].x - cf[k] * g.x;
+          cur[j].y = p[j].y - cf[k] * g.y;
+          if (k < 3) Vout[i] = cur[j];
+        }
+      }
+      if (k < 3) __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < hd[0]) {
+        acc[3] += d.h0[rr[j]] * (double(cur[j].x) * cur[j].x + double(cur[j].y) * cur[j].y);
+        out(i, rr[j], cur[j]);
+      }
+    }
+  }
 };
 
 // One whole z step, LIN(h) then NL(tau), per tile of rows (five halo rings).
@@ -1977,6 +2043,153 @@ __global__ void k_dp5_init(Dp5Ctl* ctl, uint32_t* arrivals, double z_end, double
   c.status = (z_end > 0.0 && max_attempts <= 0) ? 1 : 0;
   *ctl = c;
   *arrivals = 0u;
+}
+
+// Gradient-flow mode iteration on the step tiles: x[cur] * s is the current
+// iterate phi_k (power P); the kernel writes y = R4(-h A_k) phi_k to
+// x[1 - cur] and four H0-weighted partial sums per tile; the workgroup that
+// arrives last sums them in tile order and updates the state: the Rayleigh
+// quotient mu_k, the residual with the previous quotient, the stopping test
+// (k > 0, tol > 0, r <= tol |mu|: phi_k is the result), else s = sqrt(P /
+// P(y)), cur flips and k advances.
+__device__ inline void mode_decide(ModeCtl* ctl, const double (&S)[4]) {
+  ModeCtl c = *ctl;
+  const double mu = S[0] / S[2];
+  const double r = sqrt(S[1] / S[2]);
+  c.mu = mu;
+  c.res = r;
+  if (c.iter > 0 && c.tol > 0.0 && r <= c.tol * fabs(mu)) {
+    c.done = 1;
+    c.status = 0;
+    *ctl = c;
+    return;
+  }
+  if (!(S[3] > 0.0) || !isfinite(S[3]) || !isfinite(mu)) {
+    c.done = 1;
+    c.status = 2;
+    *ctl = c;
+    return;
+  }
+  c.s = sqrt(c.power / S[3]);
+  c.cur ^= 1;
+  c.mu_prev = mu;
+  c.iter += 1;
+  if (c.iter >= c.max_iter) {
+    c.done = 1;
+    c.status = c.tol > 0.0 ? 1 : 0;
+  }
+  *ctl = c;
+}
+
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_mode(DevOps<T> d, TileOps<T> tl, typename CT<T>::C* x0,
+                                                                  typename CT<T>::C* x1, ModeCtl* ctl,
+                                                                  double* __restrict__ partial,
+                                                                  uint32_t* __restrict__ arrivals, T h, T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16][4];
+  __shared__ int last;
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles || ctl->done) return;
+  const int cur = ctl->cur;
+  const T sc = T(ctl->s);
+  const T mu_prev = T(ctl->mu_prev);
+  const C* in_psi = cur ? x1 : x0;
+  C* out_psi = cur ? x0 : x1;
+  const int MS = tl.max_slots;
+  C* A = reinterpret_cast<C*>(smem);
+  C* Bv = A + MS;
+  T* SA = reinterpret_cast<T*>(Bv + MS);
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  for (int i = threadIdx.x; i < st.hd[4]; i += blockDim.x) {
+    C v = in_psi[st.slot_row(i)];
+    v.x *= sc;
+    v.y *= sc;
+    A[i] = v;
+    SA[i] = v.x * v.x + v.y * v.y;
+  }
+  __syncthreads();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  st.step_mode(d, A, Bv, SA, h, gamma, mu_prev, acc, [&](int, int32_t r, const C& v) { out_psi[r] = v; });
+  const int nw = int(blockDim.x + 63) / 64;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_down(acc[c], off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = acc[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w][threadIdx.x];
+    coherent_store(partial + 4 * tile + threadIdx.x, t);
+    wait_stores();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+           uint32_t(tl.n_tiles - 1);
+  __syncthreads();
+  if (!last) return;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < tl.n_tiles; k += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) t[c] += coherent_load(partial + 4 * k + c);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    for (int off = 32; off > 0; off >>= 1) t[c] += __shfl_down(t[c], off, 64);
+  }
+  __syncthreads();  // red[] reuse
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[threadIdx.x >> 6][c] = t[c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < nw; ++w)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) S[c] += red[w][c];
+    __hip_atomic_store(arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mode_decide(ctl, S);
+  }
+}
+
+// Starts a mode iteration from x[0] with power p0 = pw[0] (a power reduction
+// of x[0]): s = sqrt(P / p0); a start with no power or a non-finite one ends
+// at once with status 2.
+__global__ void k_mode_init(ModeCtl* ctl, uint32_t* arrivals, const double* pw, double power, double tol,
+                            int64_t max_iter) {
+  if (threadIdx.x != 0) return;
+  ModeCtl c;
+  const double p0 = pw[0];
+  c.s = sqrt(power / p0);
+  c.power = power;
+  c.mu_prev = 0.0;
+  c.mu = c.res = 0.0;
+  c.tol = tol;
+  c.iter = 0;
+  c.max_iter = max_iter;
+  c.cur = 0;
+  c.done = 0;
+  c.status = 0;
+  c.pad = 0;
+  if (!(p0 > 0.0) || !isfinite(c.s)) {
+    c.done = 1;
+    c.status = 2;
+  }
+  *ctl = c;
+  *arrivals = 0u;
+}
+
+// x[:] *= s (device order, F = 1)
+template <typename T>
+__global__ void k_scale(typename CT<T>::C* x, int64_t n, T s) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    x[i].x *= s;
+    x[i].y *= s;
+  }
 }
 
 // One whole z step with the beta4 L^2 term per tile (8 or 9 halo rings).
@@ -2841,6 +3054,39 @@ void launch_dp5(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp
 #undef DECBPM_DP5
 }
 
+void launch_mode_init(ModeCtl* ctl, uint32_t* arrivals, const double* pw, double power, double tol, int64_t max_iter,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_mode_init, dim3(1), dim3(64), 0, st, ctl, arrivals, pw, power, tol, max_iter);
+}
+
+template <typename T>
+void launch_scale(int64_t n, void* x, double s, int block, hipStream_t st) {
+  const unsigned g = unsigned((n + block - 1) / block);
+  if (g) hipLaunchKernelGGL((k_scale<T>), dim3(g), dim3(block), 0, st, static_cast<typename CT<T>::C*>(x), n, T(s));
+}
+
+template <typename T>
+void launch_mode(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, ModeCtl* ctl, double* partial,
+                 uint32_t* arrivals, double h, double gamma, int block, hipStream_t st) {
+  using C = typename CT<T>::C;
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * (2 * sizeof(C) + sizeof(T));
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_MODE(KM, DEC, JJ)                                                                                  \
+  hipLaunchKernelGGL((k_mode<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, static_cast<C*>(x0),        \
+                     static_cast<C*>(x1), ctl, partial, arrivals, T(h), T(gamma))
+#define DECBPM_MODE_J(KM, DEC) \
+  if (J <= 1) DECBPM_MODE(KM, DEC, 1); else DECBPM_MODE(KM, DEC, 2);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_MODE_J(8, true) } else { DECBPM_MODE_J(8, false) }
+  } else {
+    if (dec) { DECBPM_MODE_J(12, true) } else { DECBPM_MODE_J(12, false) }
+  }
+#undef DECBPM_MODE_J
+#undef DECBPM_MODE
+}
+
 template <typename T>
 void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
                     double gamma, int block, hipStream_t st) {
@@ -3116,6 +3362,9 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                   hipStream_t);                                                                  \
   template void launch_dp5<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, Dp5Ctl*, double*, uint32_t*,     \
                               double, double, double, double, int, hipStream_t);                                 \
+  template void launch_mode<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, ModeCtl*, double*, uint32_t*,   \
+                               double, double, int, hipStream_t);                                                \
+  template void launch_scale<T>(int64_t, void*, double, int, hipStream_t);                                        \
   template void launch_step_rec<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, void*, void*, void*,    \
                                    void*, double, double, double, int, hipStream_t);                             \
   template void launch_step_adj<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*,     \

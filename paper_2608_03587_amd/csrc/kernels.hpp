@@ -211,6 +211,33 @@ template <typename T>
 void launch_dp5(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp5Ctl* ctl, double* partial,
                 uint32_t* arrivals, double gamma, double rtol, double atol, double inv_n, int block, hipStream_t st);
 
+// Device-resident state of a nonlinear mode iteration (imaginary-z RK4 with
+// the nonlinearity frozen per step, renormalised to the power P): the current
+// iterate is s * x[cur].  Once done is set, iterations return at once.
+struct ModeCtl {
+  double s;        // scale of x[cur] giving the current iterate
+  double power;    // prescribed power P = sum_p H0_p |phi_p|^2
+  double mu_prev;  // Rayleigh quotient of the previous iterate (0 before the first)
+  double mu, res;  // quotient and residual of the last tested iterate
+  double tol;      // stop when r <= tol |mu| (k > 0); 0: run max_iter steps
+  int64_t iter, max_iter;  // index k of the current iterate
+  int32_t cur, done;
+  int32_t status;  // 0 converged (or max_iter reached with tol == 0), 1 not converged, 2 non-finite
+  int32_t pad;
+};
+
+// Starts the iteration from x[0]; pw[0] holds the power of x[0].
+void launch_mode_init(ModeCtl* ctl, uint32_t* arrivals, const double* pw, double power, double tol, int64_t max_iter,
+                      hipStream_t st);
+// One iteration and its stopping test on the step tiles (rings 0..4 staged);
+// partial: 4 * n_tiles doubles of scratch.
+template <typename T>
+void launch_mode(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, ModeCtl* ctl, double* partial,
+                 uint32_t* arrivals, double h, double gamma, int block, hipStream_t st);
+// x[0..n) *= s (complex, device order)
+template <typename T>
+void launch_scale(int64_t n, void* x, double s, int block, hipStream_t st);
+
 // The one-kernel step that also writes the owned rows' stage vectors y1..y3
 // and the state before the Kerr substep (the adjoint's forward recompute).
 template <typename T>

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import adjoint as OA, dec, diagnostics as D, stepper as S, unsplit as US
+from oracle import adjoint as OA, dec, diagnostics as D, soliton as SO, stepper as S, unsplit as US
 from paper_2608_03587_amd import _binding as B
 from paper_2608_03587_amd import api
 from paper_2608_03587_amd.inputs import fields as F
@@ -304,6 +304,76 @@ def test_adaptive_dp54_small_meshes_and_refusals():
     mb = lib_mesh(wb, "c128")
     with pytest.raises(api.DecBpmError) as e:
         mb.propagate_adaptive(dev(wb.u0, "c128"), wb.dz, wb.dz, wb.gamma)
+    assert e.value.code == B.EINVAL
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_mode_iterations_match_oracle(dtype):
+    """Nonlinear mode iteration (imaginary-z RK4 with frozen nonlinearity, renormalised to
+    the power) on the 89k-vertex step-index mesh: a fixed number of iterations (tol = 0)
+    against the oracle's iterate, Rayleigh quotient and residual."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    ops = oracle_ops(w)
+    m = lib_mesh(w, dtype)
+    dtau = 2.0 / m.spectral_radius()
+    for n in (1, 2, 31):
+        say("mode iterations", dtype, w.mesh.n_vert, n)
+        f = dev(w.u0, dtype)
+        st = m.find_mode(f, 4.0, dtau, w.gamma, tol=0.0, max_iter=n)
+        m.check_finite()
+        ref, info = SO.find_mode(w.u0, ops, 4.0, dtau, w.gamma, tol=0.0, max_iter=n)
+        assert st["iterations"] == info["iterations"] == n
+        err = rel(host(f), ref)
+        say("  rel err", err, "mu", st["mu"], info["mu"], "res", st["residual"], info["residual"])
+        assert err < GATE[dtype], (n, err)
+        tq = 1e-12 if dtype == "c128" else 1e-5
+        assert abs(st["mu"] - info["mu"]) <= tq * abs(info["mu"])
+        assert abs(st["residual"] - info["residual"]) <= (1e-9 if dtype == "c128" else 1e-3) * info["residual"]
+    assert m.time_kernels(w.dz, w.gamma, reps=10)["mode"]["ms"] > 0
+
+
+def test_mode_solver_converges_like_the_oracle():
+    """A guided mode on a 4k-vertex disk (four step tiles), complex128, to tol 1e-10: the
+    same iteration count as the oracle, the same mode and quotient, and the mode is
+    stationary under the library's own z-marching."""
+    mesh = M.disk_mesh(10.0, 0.301, 11)
+    r = np.hypot(*mesh.xy[mesh.tri].mean(axis=1).T)
+    V = np.where(r < 3.0, 1.0, 0.0)
+    ops = dec.assemble(mesh.xy, mesh.tri, V)
+    m = api.Mesh(mesh.xy, mesh.tri, V, None, dtype="c128")
+    start = np.exp(-np.sum(mesh.xy**2, axis=1) / 4.0) + 0j
+    dtau = 2.0 / m.spectral_radius()
+    say("mode solver", mesh.n_vert, dtau)
+    f = dev(start, "c128")
+    st = m.find_mode(f, 3.0, dtau, 1.0, tol=1e-10)
+    ref, info = SO.find_mode(start, ops, 3.0, dtau, 1.0, tol=1e-10)
+    say("  gpu", st, "oracle", info)
+    assert st["iterations"] == info["iterations"]
+    assert abs(st["mu"] - info["mu"]) <= 1e-12 * abs(info["mu"])
+    phi = host(f)
+    assert rel(phi, ref) < GATE["c128"]
+    assert abs(D.power(phi, ops) - 3.0) < 1e-12
+    g = f.clone()
+    z, n = 0.5, 500
+    m.propagate(g, z / n, n, 1.0)
+    assert rel(host(g), phi * np.exp(-1j * st["mu"] * z)) < 1e-4
+    # failures: no convergence in too few iterations (the field holds the last iterate),
+    # a start without power, a step beyond the RK4 margin, a beta4 handle
+    f = dev(start, "c128")
+    with pytest.raises(api.DecBpmError) as e:
+        m.find_mode(f, 3.0, dtau, 1.0, tol=1e-10, max_iter=5)
+    assert e.value.code == B.EUNSTABLE and e.value.stats["iterations"] == 5
+    assert abs(D.power(host(f), ops) - 3.0) < 1e-12
+    with pytest.raises(api.DecBpmError) as e:
+        m.find_mode(torch.zeros_like(f), 3.0, dtau, 1.0)
+    assert e.value.code == B.ENONFINITE
+    with pytest.raises(api.DecBpmError) as e:
+        m.find_mode(f, 3.0, 3.0 / m.spectral_radius(), 1.0)
+    assert e.value.code == B.EUNSTABLE
+    wb = case("vortex", n_vert=20000, n_steps=10)
+    mb = lib_mesh(wb, "c128")
+    with pytest.raises(api.DecBpmError) as e:
+        mb.find_mode(dev(wb.u0, "c128"), 1.0, wb.dz, 1.0)
     assert e.value.code == B.EINVAL
 
 

@@ -161,6 +161,13 @@ def test_host_only_handle_runs_every_check_then_reports_no_device():
     assert ad(m.handle, fake, 1.0, 1e-3, 1.0, 1e-9, 1e-11, 100, ctypes.byref(acc), ctypes.byref(rej),
               ctypes.byref(lh), ctypes.byref(zr), None) == B.ENODEVICE
     assert (acc.value, rej.value, lh.value, zr.value) == (0, 0, 0.0, 0.0)  # counters cleared on every call
+    fm = lib.dec_bpm_find_mode
+    for args in ((0.0, 1e-3, 1e-10, 10), (1.0, 0.0, 1e-10, 10), (1.0, 1e-3, -1.0, 10), (1.0, 1e-3, 1e-10, 0),
+                 (float("nan"), 1e-3, 1e-10, 10)):
+        power, dtau, tol, mx = args
+        assert fm(m.handle, fake, power, dtau, 1.0, tol, mx, None, None, None, None) == B.EINVAL, args
+    assert fm(m.handle, fake, 1.0, 3.0 / rho, 1.0, 1e-10, 10, None, None, None, None) == B.EUNSTABLE
+    assert fm(m.handle, fake, 1.0, 1e-3, 1.0, 1e-10, 10, None, None, None, None) == B.ENODEVICE
     assert lib.dec_bpm_apply(m.handle, 0, fake, fake, None) == B.EINVAL  # x == y
     assert lib.dec_bpm_diagnostics(m.handle, fake, 1.0, None, None, None) == B.ENODEVICE
     size = ctypes.c_size_t()
