@@ -184,6 +184,67 @@ def whitney_hodge1(xy: np.ndarray, tri: np.ndarray, edges: np.ndarray, xi: float
     return sp.csr_matrix((local.ravel(), (rows, cols)), shape=(n_e, n_e))
 
 
+def pml_stretch(r: np.ndarray, r0: float, r1: float, sigma_max: float, m: float = 2.0):
+    """Radial complex coordinate stretching of a perfectly matched layer beyond r0.
+
+    r~(r) = r + i S(r), S(r) = integral_{r0}^{r} sigma, with the profile
+    sigma(r) = sigma_max ((r - r0)/(r1 - r0))^m for r > r0 (0 inside).
+    Returns the stretch factors s_r = dr~/dr = 1 + i sigma and s_t = r~/r."""
+    r = np.asarray(r, dtype=np.float64)
+    u = np.clip((r - r0) / (r1 - r0), 0.0, None)
+    inside = r > r0
+    sigma = np.where(inside, sigma_max * u**m, 0.0)
+    S = np.where(inside, sigma_max * (r1 - r0) * u ** (m + 1) / (m + 1), 0.0)
+    s_r = 1.0 + 1j * sigma
+    s_t = 1.0 + 1j * np.divide(S, r, out=np.zeros_like(r), where=r > 0)
+    return s_r, s_t
+
+
+def pml_hodge_stars(xy, tri, edges, pml):
+    """Complex-stretched Hodge stars of a radial PML (the paper proposes stretching
+    the Hodge stars; the construction is ours).  In the stretched coordinates the
+    Laplacian is (1/(s_r s_t)) div(Lambda grad), Lambda = (s_t/s_r) rr^T + (s_r/s_t) tt^T
+    (r, t the radial and azimuthal unit vectors).  Per triangle, with the stretch
+    evaluated at its centroid: H0 picks up the area factor s_r s_t and H1 is the
+    Galerkin star of the Whitney proxies with the tensor Lambda (three-point rule,
+    exact for a constant tensor).  Returns (H0 complex diagonal, H1 complex CSR)."""
+    r0, r1, sigma_max = pml[:3]
+    m = pml[3] if len(pml) > 3 else 2.0
+    c = xy[tri].mean(axis=1)
+    rc = np.hypot(c[:, 0], c[:, 1])
+    s_r, s_t = pml_stretch(rc, r0, r1, sigma_max, m)
+    rhat = np.where(rc[:, None] > 0, c / np.where(rc > 0, rc, 1.0)[:, None], np.array([1.0, 0.0]))
+    that = np.stack([-rhat[:, 1], rhat[:, 0]], axis=1)
+    Lam = (s_t / s_r)[:, None, None] * np.einsum("ti,tj->tij", rhat, rhat) + \
+        (s_r / s_t)[:, None, None] * np.einsum("ti,tj->tij", that, that)
+    area = triangle_areas(xy, tri)
+    n = xy.shape[0]
+    H0 = np.zeros(n, dtype=np.complex128)
+    for k in range(3):
+        np.add.at(H0, tri[:, k], area * s_r * s_t / 3.0)
+    grads = barycentric_gradients(xy, tri)
+    n_t = tri.shape[0]
+    qp = np.array([[0.5, 0.5, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5]])
+    slots = np.array([[0, 1], [1, 2], [0, 2]])
+    t_idx = np.arange(n_t)
+    W = np.zeros((n_t, 3, 3, 2))
+    edge_id = np.zeros((n_t, 3), dtype=np.int64)
+    for e, (a, b) in enumerate(slots):
+        edge_id[:, e] = _edge_ids(edges, tri[:, a], tri[:, b])
+        a_first = edges[edge_id[:, e], 0] == tri[:, a]
+        i = np.where(a_first, a, b)
+        j = np.where(a_first, b, a)
+        gi = grads[t_idx, i]
+        gj = grads[t_idx, j]
+        for q in range(3):
+            W[:, e, q] = qp[q][i][:, None] * gj - qp[q][j][:, None] * gi
+    local = (area / 3.0)[:, None, None] * np.einsum("taqi,tij,tbqj->tab", W, Lam, W)
+    rows = np.repeat(edge_id, 3, axis=1).ravel()
+    cols = np.tile(edge_id, (1, 3)).ravel()
+    n_e = edges.shape[0]
+    return H0, sp.csr_matrix((local.ravel(), (rows, cols)), shape=(n_e, n_e))
+
+
 def stiffness(D0: sp.csr_matrix, H1: sp.csr_matrix) -> sp.csr_matrix:
     """K = D0^T H1 D0 (the bracket of Eq. 11 without the potential)."""
     return (D0.T @ H1 @ D0).tocsr()
@@ -241,7 +302,7 @@ class Operators:
         return out
 
     def dense_H(self):
-        H = self.p1 * self.L.toarray() - np.diag(self.v)
+        H = self.p1 * self.L.toarray() - np.diag(self.v).astype(self.L.dtype)
         if self.beta4 != 0.0:
             Ld = self.L.toarray()
             H = H + self.beta4 * Ld @ Ld
@@ -249,8 +310,12 @@ class Operators:
 
 
 def assemble(xy, tri, index_tri=None, absorber=None, chi_tri=None, p1=0.5, beta4=0.0, nl="dec",
-             dn=None) -> Operators:
-    """Assemble every operator of the semi-discrete ODE (Eqs. 10-14)."""
+             dn=None, pml=None) -> Operators:
+    """Assemble every operator of the semi-discrete ODE (Eqs. 10-14).
+
+    ``pml = (r0, r1, sigma_max[, m])`` replaces H0 and H1 inside L by the
+    complex-stretched stars of ``pml_hodge_stars`` (L becomes complex; the
+    potential, the nonlinear matrix and the power keep the real H0)."""
     xy = np.asarray(xy, dtype=np.float64)
     tri = orient_ccw(xy, np.asarray(tri))
     n = xy.shape[0]
@@ -261,7 +326,11 @@ def assemble(xy, tri, index_tri=None, absorber=None, chi_tri=None, p1=0.5, beta4
     H0 = hodge0(xy, tri)
     H1 = whitney_hodge1(xy, tri, edges)
     K = stiffness(D0, H1)
-    L = (sp.diags(1.0 / H0) @ K).tocsr()
+    if pml is None:
+        L = (sp.diags(1.0 / H0) @ K).tocsr()
+    else:
+        H0p, H1p = pml_hodge_stars(xy, tri, edges, pml)
+        L = (sp.diags(1.0 / H0p) @ stiffness(D0, H1p)).tocsr()
     V_tri = np.zeros(tri.shape[0]) if index_tri is None else np.asarray(index_tri, dtype=np.float64)
     v = hodge0_pulse(xy, tri, V_tri) / H0
     if dn is not None:
