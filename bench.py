@@ -20,7 +20,8 @@ Also reported on the same JSON line:
                 prefix of steps, single thread
   parity        GPU vs oracle after the same prefix (relative L2)
   extras        complex128 throughput; the unsplit RK4 and adaptive Dormand-Prince
-                5(4) integrators; batched photonic-crystal-fibre mode vs
+                5(4) integrators; the perfectly matched layer; batched
+                photonic-crystal-fibre mode vs
                 per-instance plain launches; checkpointed adjoint vs forward;
                 the 1M-vertex vortex launch with the beta4 L^2 term
 """
@@ -248,6 +249,10 @@ def main():
             extras["adaptive_dp54"] = bench_adaptive(api, w, torch, dev, tdt, not args.no_cpu)
         except Exception as e:  # noqa: BLE001
             extras["adaptive_dp54"] = {"error": repr(e)}
+        try:
+            extras["pml"] = bench_pml(api, w, torch, dev, tdt, min(args.steps, 2000))
+        except Exception as e:  # noqa: BLE001
+            extras["pml"] = {"error": repr(e)}
         try:
             extras["conditioning"] = bench_conditioning(api, w, torch, dev, tdt, args.steps)
         except Exception as e:  # noqa: BLE001
@@ -477,6 +482,33 @@ def bench_adaptive(api, w, torch, dev, tdt, with_oracle):
         log(f"[bench] adaptive DP5(4) {dt}: {st['accepted']} accepted / {st['rejected']} rejected in {sec:.3f} s, "
             f"{r['us_per_attempt']:.1f} us per attempt, trial kernel {r['trial_kernel_us']:.1f} us, "
             f"parity {r.get('parity', {}).get('rel_l2_vs_oracle')}")
+    return out
+
+
+def bench_pml(api, w, torch, dev, tdt, steps):
+    """The step-index launch with a perfectly matched layer on 35 < r < 40 (sigma_max 1) in
+    place of the absorber, complex64, one-kernel step with complex L weights, against the
+    same step with the absorber."""
+    out = {}
+    for name, pml, ab in (("pml", (35.0, 40.0, 1.0), None), ("absorber", None, w.absorber)):
+        m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, ab, dtype="c64", p1=w.p1, pml=pml)
+        m.tuning = {"fused": 2}
+        u0 = torch.from_numpy(w.u0).to(dev, tdt["c64"])
+        f = u0.clone()
+        m.propagate(f, w.dz, 50, w.gamma)
+        f = u0.clone()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        m.propagate(f, w.dz, steps, w.gamma)
+        e1.record()
+        torch.cuda.synchronize()
+        m.check_finite()
+        ms = e0.elapsed_time(e1)
+        out[name] = {"value": w.mesh.n_vert * steps / (ms * 1e-3), "ms_per_step": ms / steps, "tuning": m.tuning}
+        del m
+    log(f"[bench] PML: {out['pml']['ms_per_step'] * 1e3:.2f} us per step vs absorber "
+        f"{out['absorber']['ms_per_step'] * 1e3:.2f} us (one-kernel step)")
     return out
 
 

@@ -81,6 +81,22 @@ typedef struct {
                              for dec_bpm_export_operators and argument checks        */
   int32_t block_size;     /* threads per workgroup, 0 = library default / autotuned   */
   int32_t steps_per_graph;/* z steps captured per hipGraph, 0 = default; 1 disables   */
+  /* Perfectly matched layer in place of (or beside) the absorber, by radial
+   * complex stretching of the Hodge stars (the paper's proposal for long
+   * distances; the construction is this library's): r~ = r + i S(r),
+   * S' = sigma(r) = pml_sigma ((r - pml_r0)/(pml_r1 - pml_r0))^2 for r > pml_r0,
+   * centre at the origin.  L becomes H0~^{-1} D0^T H1~ D0 with the dual areas
+   * times s_r s_t and the Galerkin H1 with the tensor (s_t/s_r) rr^T +
+   * (s_r/s_t) tt^T (s_r = 1 + i sigma, s_t = r~/r, taken at each triangle's
+   * centroid); v, M and the power keep the real H0.  pml_sigma = 0: none.
+   * Needs 0 < pml_r0 < pml_r1, no beta4 term and rows of at most 12
+   * neighbours; the handle then runs dec_bpm_propagate on the one-kernel step
+   * (fused = 2) and kerr_step/diagnostics (Hamiltonian NaN); every entry point
+   * that applies a real L (apply, linear_step, unsplit, adaptive, find_mode,
+   * checkpointed forward and adjoint, batches) returns EINVAL.  The stability
+   * check uses the unstretched operator's spectral radius, which bounds the
+   * stretched one's. */
+  double pml_r0, pml_r1, pml_sigma;
 } dec_bpm_options;
 
 /* Fill *opt with the defaults above. */
@@ -135,6 +151,15 @@ int dec_bpm_spectral_radius(dec_bpm_t h, double* rho);
  */
 int dec_bpm_export_operators(dec_bpm_t h, double* h0, double* v, double* w, int64_t* nnz,
                              int64_t* row_ptr, int32_t* col, double* kval, double* mval);
+
+/*
+ * With a PML (dec_bpm_options.pml_sigma > 0): the complex-stretched operators
+ * on the pattern of dec_bpm_export_operators, caller order, interleaved
+ * (re, im): h0p[2n] the stretched dual areas, kp[2 nnz] the stretched
+ * K~ = D0^T H1~ D0.  Either may be NULL.  EINVAL on a handle without a PML.
+ * Works on host-only handles.
+ */
+int dec_bpm_export_pml(dec_bpm_t h, double* h0p, double* kp);
 
 /*
  * Set the per-vertex index perturbation dn (added to v after averaging,

@@ -38,6 +38,9 @@ class Options(ctypes.Structure):
         ("host_only", c_i32),
         ("block_size", c_i32),
         ("steps_per_graph", c_i32),
+        ("pml_r0", c_dbl),
+        ("pml_r1", c_dbl),
+        ("pml_sigma", c_dbl),
     ]
 
 
@@ -69,6 +72,7 @@ _SIGNATURES = [
     ("dec_bpm_linear_step", c_int, [c_vp, c_vp, c_dbl, c_vp]),
     ("dec_bpm_propagate", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_vp]),
     ("dec_bpm_propagate_unsplit", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_vp]),
+    ("dec_bpm_export_pml", c_int, [c_vp, P(c_dbl), P(c_dbl)]),
     ("dec_bpm_find_mode", c_int, [c_vp, c_vp, c_dbl, c_dbl, c_dbl, c_dbl, c_i64, ctypes.POINTER(c_dbl),
                                   ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64), c_vp]),
     ("dec_bpm_propagate_adaptive", c_int, [c_vp, c_vp, c_dbl, c_dbl, c_dbl, c_dbl, c_dbl, c_i64,

@@ -44,7 +44,7 @@ class Mesh:
     """
 
     def __init__(self, xy, tri, index_tri=None, absorber=None, chi_tri=None, dtype="c64", p1=0.5, beta4=0.0,
-                 nonlinearity="dec", reorder=True, host_only=False, block_size=0, steps_per_graph=0):
+                 nonlinearity="dec", reorder=True, host_only=False, block_size=0, steps_per_graph=0, pml=None):
         L = B.lib()
         self.dtype_name = dtype
         code, self.torch_dtype = _DT[dtype]
@@ -62,6 +62,8 @@ class Mesh:
         opt.host_only = int(bool(host_only))
         opt.block_size = int(block_size)
         opt.steps_per_graph = int(steps_per_graph)
+        if pml is not None:  # (r0, r1, sigma_max): radial perfectly matched layer
+            opt.pml_r0, opt.pml_r1, opt.pml_sigma = (float(v) for v in pml)
         keep = []
         if chi_tri is not None:
             chi = np.ascontiguousarray(chi_tri, dtype=np.float64)
@@ -121,6 +123,14 @@ class Mesh:
                                            _ptr(col, ctypes.c_int32), _ptr(k, ctypes.c_double),
                                            _ptr(m, ctypes.c_double)))
         return dict(h0=h0, v=v, w=w, row_ptr=rp, col=col, K=k, QtDQ=m)
+
+    def export_pml(self):
+        """Complex-stretched dual areas and K (pattern of ``export_operators``) of a PML handle."""
+        ops = self.export_operators()
+        h0p = np.empty(2 * self.n_vert)
+        kp = np.empty(2 * ops["col"].size)
+        B.check(B.lib().dec_bpm_export_pml(self._h, _ptr(h0p, ctypes.c_double), _ptr(kp, ctypes.c_double)))
+        return dict(ops, h0p=h0p[0::2] + 1j * h0p[1::2], Kp=kp[0::2] + 1j * kp[1::2])
 
     # ---- device calls ----
     def _field(self, x: torch.Tensor, name="field", n=None):

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <numeric>
 
 #include "../../include/dec_bpm.h"
@@ -60,6 +61,10 @@ Assembled assemble(const AssemblyInput& in) {
   if (!(in.p1 >= 0.0) || !(in.beta4 >= 0.0) || !std::isfinite(in.p1) || !std::isfinite(in.beta4))
     fail(DEC_BPM_EINVAL, "p1 and beta4 must be finite and >= 0");
   if (in.nonlinearity != 0 && in.nonlinearity != 1) fail(DEC_BPM_EINVAL, "unknown nonlinearity mode");
+  if (!(in.pml_sigma >= 0.0) || !std::isfinite(in.pml_sigma) ||
+      (in.pml_sigma > 0.0 && !(in.pml_r0 > 0.0 && in.pml_r1 > in.pml_r0 && std::isfinite(in.pml_r1))))
+    fail(DEC_BPM_EINVAL, "PML: need pml_sigma >= 0 and, when it is > 0, 0 < pml_r0 < pml_r1");
+  if (in.pml_sigma > 0.0 && in.beta4 != 0.0) fail(DEC_BPM_EINVAL, "PML: not available with the beta4 term");
   const int64_t n = in.n, nt = in.n_tri;
   Assembled a;
   a.n = n;
@@ -225,6 +230,71 @@ Assembled assemble(const AssemblyInput& in) {
     std::copy(c2.begin(), c2.end(), a.col.begin() + b);
     std::copy(k2.begin(), k2.end(), a.k.begin() + b);
     std::copy(q2.begin(), q2.end(), a.qdq.begin() + b);
+  }
+
+  // Perfectly matched layer: radial complex stretching r~ = r + i S(r),
+  // S' = sigma.  With s_r = 1 + i sigma and s_t = r~ / r, the stretched
+  // Laplacian is div(Lambda grad) / (s_r s_t), Lambda = (s_t/s_r) r r^T +
+  // (s_r/s_t) t t^T.  Per triangle (stretch taken at the centroid) the P1
+  // stiffness |t| grad(lambda_a)^T Lambda grad(lambda_b) is D0^T H1 D0 with the
+  // stretched Galerkin H1, and the dual areas pick up s_r s_t.
+  if (in.pml_sigma > 0.0) {
+    using cd = std::complex<double>;
+    const double r0 = in.pml_r0, r1 = in.pml_r1, sm = in.pml_sigma;
+    std::vector<cd> kp(nnz, cd(0.0)), h0p(n, cd(0.0));
+    auto slot = [&](int32_t p, int32_t q) {
+      const int32_t* b = a.col.data() + a.rp[p];
+      const int32_t* e = a.col.data() + a.rp[p + 1];
+      return a.rp[p] + (std::lower_bound(b, e, q) - b);
+    };
+    for (int64_t t = 0; t < nt; ++t) {
+      const int32_t* v = &a.tri[3 * t];
+      double P[3][2];
+      for (int k = 0; k < 3; ++k) {
+        P[k][0] = in.xy[2 * v[k]];
+        P[k][1] = in.xy[2 * v[k] + 1];
+      }
+      const double cx = (P[0][0] + P[1][0] + P[2][0]) / 3.0, cy = (P[0][1] + P[1][1] + P[2][1]) / 3.0;
+      const double rc = std::hypot(cx, cy);
+      cd s_r(1.0, 0.0), s_t(1.0, 0.0);
+      if (rc > r0) {
+        const double u = (rc - r0) / (r1 - r0);
+        s_r = cd(1.0, sm * u * u);
+        s_t = cd(1.0, sm * (r1 - r0) * u * u * u / 3.0 / rc);
+      }
+      const double ex = rc > 0 ? cx / rc : 1.0, ey = rc > 0 ? cy / rc : 0.0;
+      const cd ar = s_t / s_r, at = s_r / s_t;  // radial and azimuthal weights
+      const cd L00 = ar * ex * ex + at * ey * ey, L11 = ar * ey * ey + at * ex * ex, L01 = (ar - at) * ex * ey;
+      const double A2 = (P[1][0] - P[0][0]) * (P[2][1] - P[0][1]) - (P[2][0] - P[0][0]) * (P[1][1] - P[0][1]);
+      double g[3][2];
+      for (int k = 0; k < 3; ++k) {
+        const double* pb = P[(k + 1) % 3];
+        const double* pc = P[(k + 2) % 3];
+        g[k][0] = (pb[1] - pc[1]) / A2;
+        g[k][1] = (pc[0] - pb[0]) / A2;
+      }
+      for (int k = 0; k < 3; ++k) h0p[v[k]] += area[t] / 3.0 * s_r * s_t;
+      for (int k = 0; k < 3; ++k)
+        for (int l = k + 1; l < 3; ++l) {
+          const cd kk = area[t] * (g[k][0] * (L00 * g[l][0] + L01 * g[l][1]) + g[k][1] * (L01 * g[l][0] + L11 * g[l][1]));
+          kp[slot(v[k], v[l])] += kk;
+          kp[slot(v[l], v[k])] += kk;
+          kp[slot(v[k], v[k])] -= kk;  // rows sum to zero (K 1 = 0)
+          kp[slot(v[l], v[l])] -= kk;
+        }
+    }
+    a.kp_re.resize(nnz);
+    a.kp_im.resize(nnz);
+    for (int64_t e = 0; e < nnz; ++e) {
+      a.kp_re[e] = kp[e].real();
+      a.kp_im[e] = kp[e].imag();
+    }
+    a.h0p_re.resize(n);
+    a.h0p_im.resize(n);
+    for (int64_t p = 0; p < n; ++p) {
+      a.h0p_re[p] = h0p[p].real();
+      a.h0p_im[p] = h0p[p].imag();
+    }
   }
 
   // device vertex order: Hilbert curve over the bounding square

@@ -28,6 +28,9 @@ struct AssemblyInput {
   double beta4 = 0.0;
   int nonlinearity = 0;  // 0 = triangle-averaged (Eq. 14), 1 = lumped
   bool reorder = true;
+  // radial perfectly matched layer: sigma(r) = pml_sigma ((r - pml_r0)/(pml_r1 - pml_r0))^2
+  // beyond pml_r0 (centre at the origin); pml_sigma == 0: none
+  double pml_r0 = 0.0, pml_r1 = 0.0, pml_sigma = 0.0;
 };
 
 // Operators in the caller's vertex order (FP64), plus the device vertex order.
@@ -42,6 +45,9 @@ struct Assembled {
   std::vector<int64_t> rp;
   std::vector<int32_t> col;
   std::vector<double> k, qdq;
+  // with a PML: the complex-stretched K (same CSR pattern) and dual areas;
+  // empty otherwise
+  std::vector<double> kp_re, kp_im, h0p_re, h0p_im;
   // device order: perm[i] = caller index of device row i; iperm = inverse
   std::vector<int32_t> perm, iperm;
   double rho = 0.0;  // spectral-radius estimate of H_lin

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -45,6 +46,7 @@ struct DevTiles {
   uint16_t* lcol = nullptr;
   void* llw = nullptr;
   void* lmw = nullptr;
+  void* llwi = nullptr;  // imaginary part of the L weights (PML handles), else null
   int64_t entries = 0, slots = 0;
   int32_t ext_stride = 0, lsl_stride = 0, hdr_stride = 8;
 
@@ -65,6 +67,7 @@ struct DevTiles {
     t.lcol = lcol;
     t.llw = static_cast<const T*>(llw);
     t.lmw = static_cast<const T*>(lmw);
+    t.llwi = static_cast<const T*>(llwi);
     return t;
   }
 };
@@ -110,6 +113,7 @@ struct Engine {
   DevTiles tl, bt, stp;  // two-kernel tiles (3 rings), batched tiles, one-kernel-step tiles (5 rings)
   bool has_step = false;
   bool has_step4 = false;  // the step tiles hold the beta4 layout (eight or nine rings)
+  bool pml = false;        // complex-stretched L (perfectly matched layer): one-kernel step only
   int step_tile = 1024;  // rows per tile of the one-kernel step (largest that fits)
   bool sort_ring0 = true;  // step tiles: order the owned rows by degree too
   // persistent stepping on the step tiles: neighbour-tile lists, flags, wait bound
@@ -278,7 +282,7 @@ struct HostTiles {
   std::vector<int32_t> hdr, ext, lsl;
   std::vector<int64_t> ebase;
   std::vector<uint16_t> lcol;
-  std::vector<double> llw, lmw;
+  std::vector<double> llw, lmw, llwi;
   int32_t max_slots = 0, max_compute = 0;
   int32_t ext_stride = 0, lsl_stride = 0;  // step layout: fixed per-tile strides
   int32_t hdr_stride = 8;
@@ -295,7 +299,8 @@ struct HostTiles {
 // so a tile finds them without reading its header first.
 static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
                        const std::vector<double>& alw, const std::vector<double>& amw, int TS, int rings,
-                       int ell_rings, HostTiles& H, bool step_layout = false, bool sort_ring0 = true) {
+                       int ell_rings, HostTiles& H, bool step_layout = false, bool sort_ring0 = true,
+                       const std::vector<double>* alwi = nullptr) {
   if (rings > (step_layout ? 9 : 5) || ell_rings > rings + 1) fail(DEC_BPM_EINVAL, "internal: unsupported ring count");
   H = HostTiles();
   H.TS = TS;
@@ -381,6 +386,7 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
       H.lcol.resize(b + size_t(W) * 64, 0);
       H.llw.resize(b + size_t(W) * 64, 0.0);
       H.lmw.resize(b + size_t(W) * 64, 0.0);
+      if (alwi) H.llwi.resize(b + size_t(W) * 64, 0.0);
       for (int lane = 0; lane < 64; ++lane) {
         const int i = sl * 64 + lane;
         for (int k = 0; k < W; ++k) H.lcol[b + size_t(k) * 64 + lane] = uint16_t(i < ce ? i : 0);  // padding: self
@@ -392,6 +398,7 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
           H.lcol[b + size_t(k) * 64 + lane] = uint16_t(q);
           H.llw[b + size_t(k) * 64 + lane] = alw[e];
           H.lmw[b + size_t(k) * 64 + lane] = amw[e];
+          if (alwi) H.llwi[b + size_t(k) * 64 + lane] = (*alwi)[e];
         }
       }
     }
@@ -434,6 +441,10 @@ static void upload_tiles(Engine& E, const HostTiles& H, bool dec, int64_t n, Dev
   D.lcol = static_cast<uint16_t*>(p);
   std::vector<T> w(H.llw.begin(), H.llw.end());
   upload(E, D.llw, w);
+  if (!H.llwi.empty()) {
+    std::vector<T> wi(H.llwi.begin(), H.llwi.end());
+    upload(E, D.llwi, wi);
+  }
   if (dec) {
     std::vector<T> m(H.lmw.begin(), H.lmw.end());
     upload(E, D.lmw, m);
@@ -470,7 +481,8 @@ static void build_tiles(Engine& E, const std::vector<int64_t>& arp, const std::v
 // Kerr term) whose state, stage vectors and |psi|^2 phi fit 64 KB of LDS.
 template <typename T>
 static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
-                             const std::vector<double>& alw, const std::vector<double>& amw, bool dec) {
+                             const std::vector<double>& alw, const std::vector<double>& amw, bool dec,
+                             const std::vector<double>* alwi = nullptr) {
   if (E.wmax > 12) return;
   // without beta4: five rings (four for the lumped Kerr term), 7 reals of LDS
   // per slot; with beta4: two rings per stage, nine (eight), 9 reals per slot;
@@ -491,7 +503,7 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
   HostTiles H;
   bool built = false;
   for (int ts = E.step_tile; ts >= 64; ts /= 2) {
-    if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H, true, E.sort_ring0)) continue;
+    if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H, true, E.sort_ring0, alwi)) continue;
     if (size_t(H.max_slots) * lds_reals * sizeof(T) > lds_max || H.max_compute > max_compute) continue;
     upload_tiles<T>(E, H, dec, E.n_rows, E.stp);
     (b4 ? E.has_step4 : E.has_step) = true;
@@ -499,7 +511,7 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
     built = true;
     break;
   }
-  if (!built || b4 || batched) return;  // the persistent kernel takes one-field handles only
+  if (!built || b4 || batched || alwi) return;  // the persistent kernel: real one-field operators only
   // tiles owning the halo rows of each tile (the persistent kernel's wait set)
   std::vector<int32_t> ptr(H.nt + 1, 0), list, seen(H.nt, -1);
   bool fits = true;
@@ -591,7 +603,10 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   // device-order adjacency (kept on the host to build the tiles)
   std::vector<int64_t> arp(n + 1, 0);
   std::vector<int32_t> acol;
-  std::vector<double> alw, amw;
+  std::vector<double> alw, amw, alwi;
+  // a perfectly matched layer makes L complex: c_pq = -K~_pq / H0~_p
+  const bool pml = meshes.size() == 1 && !meshes[0]->kp_re.empty();
+  E.pml = pml;
   acol.reserve(E.nnz_off);
   alw.reserve(E.nnz_off);
   amw.reserve(E.nnz_off);
@@ -618,7 +633,14 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
     std::sort(nb.begin(), nb.end());
     for (auto& e : nb) {
       acol.push_back(e.first);
-      alw.push_back(-a.k[e.second] / hp);
+      if (pml) {
+        const std::complex<double> c =
+            -std::complex<double>(a.kp_re[e.second], a.kp_im[e.second]) / std::complex<double>(a.h0p_re[p], a.h0p_im[p]);
+        alw.push_back(c.real());
+        alwi.push_back(c.imag());
+      } else {
+        alw.push_back(-a.k[e.second] / hp);
+      }
       amw.push_back(lumped[m] ? 0.0 : a.qdq[e.second] / hp);
     }
     arp[r + 1] = int64_t(acol.size());
@@ -627,7 +649,7 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
       const int64_t slot = sl_off[s] + int64_t(k) * 64 + lane;
       if (k < int(nb.size())) {
         col[slot] = nb[k].first;
-        lw[slot] = T(-a.k[nb[k].second] / hp);
+        lw[slot] = T(pml ? alw[arp[r] + k] : -a.k[nb[k].second] / hp);  // PML: real part (diagnostics only)
         mw[slot] = lumped[m] ? T(0) : T(a.qdq[nb[k].second] / hp);
       } else {
         col[slot] = int32_t(r);  // padding: self, zero weights
@@ -664,10 +686,12 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   E.h0c = static_cast<double*>(p);
   upload(E, p, perm);
   E.perm = static_cast<int32_t*>(p);
-  if (E.F == 1 && E.beta4 == 0.0) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
-  build_step_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  if (E.F == 1 && E.beta4 == 0.0 && !pml) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  build_step_tiles<T>(E, arp, acol, alw, amw, any_dec, pml ? &alwi : nullptr);
+  if (pml && !E.has_step)
+    fail(DEC_BPM_EINVAL, "PML: the mesh needs the one-kernel step tiles (rows of at most 12 neighbours)");
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
-  if (E.has_step && E.F == 1) {  // kept for the adaptive integrator's tiles
+  if (E.has_step && E.F == 1 && !pml) {  // kept for the adaptive integrator's tiles
     E.adj.arp = std::move(arp);
     E.adj.col = std::move(acol);
     E.adj.lw = std::move(alw);
@@ -697,6 +721,7 @@ static void build_engine(Engine& E, const std::vector<const Assembled*>& meshes,
   else
     build_engine_t<double>(E, meshes, lumped);
   if (E.fused < 0) E.fused = (E.has_step || E.has_step4) ? 2 : ((E.has_tiles || E.has_btiles) ? 1 : 0);
+  if (E.pml) E.fused = 2;
 }
 
 static void check_launch() {
@@ -812,6 +837,7 @@ static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl,
 // tile kernel, is only requested explicitly (dec_bpm_propagate_unsplit).
 template <typename T>
 static int mode_of(Engine& E) {
+  if (E.pml) return 2;                            // complex L: the one-kernel step only
   if (E.has_step4) return E.fused >= 2 ? 4 : 0;  // beta4: its one-kernel step or the five kernels
   if (use_persist<T>(E)) return 3;
   if (E.fused == 3 && E.has_step) return 2;
@@ -874,6 +900,11 @@ static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, int mode) {
   }
   E.graphs.push_back(GraphEntry{dz, gamma, E.spg, E.block, E.xcd, mode, tb, exec, graph});
   return exec;
+}
+
+// Entry points whose kernels take a real L refuse handles with a PML.
+static void no_pml(const Engine& E, const char* what) {
+  if (E.pml) fail(DEC_BPM_EINVAL, std::string(what) + ": not available on a handle with a PML (complex L)");
 }
 
 static void check_stability(const Engine& E, double dz) {
@@ -1620,7 +1651,8 @@ static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
   std::vector<Cand> cands;
   for (int x : {0, 1})
     for (int s : {1, 8, 32, 128}) {
-      for (int b : {64, 128, 256, 512, 1024}) cands.push_back({0, b, E.tile_block, s, x});
+      if (!E.pml)
+        for (int b : {64, 128, 256, 512, 1024}) cands.push_back({0, b, E.tile_block, s, x});
       if (E.has_tiles)
         for (int tb : {128, 256, 512, 1024}) cands.push_back({1, E.block, tb, s, x});
       if (E.has_step || E.has_step4)
@@ -1766,6 +1798,9 @@ int dec_bpm_create(const double* xy, int64_t n_vert, const int32_t* tri, int64_t
   in.beta4 = o.beta4;
   in.nonlinearity = o.nonlinearity;
   in.reorder = o.reorder != 0;
+  in.pml_r0 = o.pml_r0;
+  in.pml_r1 = o.pml_r1;
+  in.pml_sigma = o.pml_sigma;
   std::unique_ptr<dec_bpm_s> h(new dec_bpm_s());
   h->A = decbpm::assemble(in);
   o.chi_tri = nullptr;  // not kept
@@ -1777,6 +1812,7 @@ int dec_bpm_create(const double* xy, int64_t n_vert, const int32_t* tri, int64_t
   E.beta4 = o.beta4;
   E.nl = o.nonlinearity;
   E.rho = h->A.rho;
+  E.pml = !h->A.kp_re.empty();
   if (!o.host_only) {
     decbpm::build_engine(E, {&h->A}, {o.nonlinearity == DEC_BPM_NL_LUMPED ? 1 : 0});
     if (o.block_size) E.block = o.block_size;
@@ -1824,6 +1860,24 @@ int dec_bpm_export_operators(dec_bpm_t h, double* h0, double* v, double* w, int6
   ABI_CATCH
 }
 
+int dec_bpm_export_pml(dec_bpm_t h, double* h0p, double* kp) {
+  ABI_TRY
+  need(h);
+  const decbpm::Assembled& A = h->A;
+  if (A.kp_re.empty()) fail(DEC_BPM_EINVAL, "the handle has no PML");
+  if (h0p)
+    for (int64_t p = 0; p < A.n; ++p) {
+      h0p[2 * p] = A.h0p_re[p];
+      h0p[2 * p + 1] = A.h0p_im[p];
+    }
+  if (kp)
+    for (size_t e = 0; e < A.kp_re.size(); ++e) {
+      kp[2 * e] = A.kp_re[e];
+      kp[2 * e + 1] = A.kp_im[e];
+    }
+  ABI_CATCH
+}
+
 int dec_bpm_set_index_perturbation(dec_bpm_t h, const double* dn_dev, void* stream) {
   ABI_TRY
   need(h);
@@ -1856,6 +1910,7 @@ int dec_bpm_set_index_perturbation(dec_bpm_t h, const double* dn_dev, void* stre
 int dec_bpm_apply(dec_bpm_t h, int op, const void* x, void* y, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_pml(h->E, "dec_bpm_apply");
   Engine& E = h->E;
   if (!x || !y || x == y) fail(DEC_BPM_EINVAL, "x and y must be distinct non-NULL device vectors");
   if (op < DEC_BPM_OP_L || op > DEC_BPM_OP_H) fail(DEC_BPM_EINVAL, "unknown operator");
@@ -1917,6 +1972,7 @@ int dec_bpm_kerr_step(dec_bpm_t h, void* field, double tau, double gamma, void* 
 int dec_bpm_linear_step(dec_bpm_t h, void* field, double dz, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_pml(h->E, "dec_bpm_linear_step");
   Engine& E = h->E;
   decbpm::check_prop_args(E, field, dz, 1, 0.0);
   hipStream_t st = as_stream(stream);
@@ -1946,6 +2002,7 @@ int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, doub
 int dec_bpm_propagate_unsplit(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_pml(h->E, "dec_bpm_propagate_unsplit");
   decbpm::check_prop_args(h->E, field, dz, n_steps, gamma);
   if (!h->E.has_step || h->E.F != 1)
     fail(DEC_BPM_EINVAL,
@@ -1963,6 +2020,7 @@ int dec_bpm_propagate_adaptive(dec_bpm_t h, void* field, double z_end, double h0
                                double* last_h, double* z_reached, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_pml(h->E, "dec_bpm_propagate_adaptive");
   Engine& E = h->E;
   if (n_accepted) *n_accepted = 0;
   if (n_rejected) *n_rejected = 0;
@@ -2002,6 +2060,7 @@ int dec_bpm_find_mode(dec_bpm_t h, void* field, double power, double dtau, doubl
                       int64_t max_iter, double* mu, double* residual, int64_t* iterations, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_pml(h->E, "dec_bpm_find_mode");
   Engine& E = h->E;
   if (mu) *mu = 0.0;
   if (residual) *residual = 0.0;
@@ -2071,7 +2130,8 @@ int dec_bpm_diagnostics(dec_bpm_t h, const void* field, double gamma, double* po
   HIP_OK(hipMemcpyAsync(out, E.red_out, sizeof out, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   if (power) *power = out[0];
-  if (hamiltonian) *hamiltonian = out[1];
+  // with a PML the Hamiltonian is not defined (complex L): NaN
+  if (hamiltonian) *hamiltonian = E.pml ? std::nan("") : out[1];
   ABI_CATCH
 }
 
@@ -2107,6 +2167,7 @@ int dec_bpm_forward_checkpointed(dec_bpm_t h, void* field, double dz, int64_t n_
                                  void* workspace, size_t ws_bytes, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_pml(h->E, "dec_bpm_forward_checkpointed");
   Engine& E = h->E;
   decbpm::check_prop_args(E, field, dz, n_steps, gamma);
   if (every < 0) fail(DEC_BPM_EINVAL, "every must be >= 0");
@@ -2132,6 +2193,7 @@ int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_step
                     void* workspace, size_t ws_bytes, void* grad_field0, double* grad_dn, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_pml(h->E, "dec_bpm_adjoint");
   Engine& E = h->E;
   decbpm::check_prop_args(E, grad_field0, dz, n_steps, gamma);
   if (!grad_out) fail(DEC_BPM_EINVAL, "grad_out is NULL");
@@ -2175,6 +2237,7 @@ int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, int32_t fiel
   for (int32_t m = 0; m < n_meshes; ++m) {
     const dec_bpm_s* h = meshes[m];
     if (!h) fail(DEC_BPM_EINVAL, "NULL mesh handle");
+    if (!h->A.kp_re.empty()) fail(DEC_BPM_EINVAL, "batches do not take meshes with a PML");
     if (h->opt.dtype != m0->opt.dtype || h->opt.p1 != m0->opt.p1 || h->opt.beta4 != m0->opt.beta4 ||
         h->opt.nonlinearity != m0->opt.nonlinearity)
       fail(DEC_BPM_EINVAL, "all meshes of a batch must share dtype, p1, beta4 and nonlinearity");
@@ -2252,6 +2315,7 @@ static void set_tuning(Engine& E, const dec_bpm_tuning* t) {
       t->tile_block < 64 || t->tile_block > 1024 || t->tile_block % 64 || (t->fused < 0 || t->fused > 3) ||
       (t->xcd_remap != 0 && t->xcd_remap != 1))
     fail(DEC_BPM_EINVAL, "bad tuning");
+  if (E.pml && t->fused != 2) fail(DEC_BPM_EINVAL, "a PML handle runs the one-kernel step only (fused = 2)");
   E.block = t->block_size;
   E.spg = t->steps_per_graph;
   E.fused = t->fused;

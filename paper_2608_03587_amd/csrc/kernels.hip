@@ -1102,7 +1102,9 @@ struct StepBound {
 // stride, rings sorted by degree so that the width of a 64-slot slice (one
 // wavefront) is nearly every row's degree; the neighbour loops run to that
 // wave-uniform width, padded entries pointing at their own slot with weight 0.
-template <typename T, int KMAX, bool DEC, int J>
+// CL: the L weights are complex (a perfectly matched layer stretches the
+// Hodge stars); their imaginary parts ride in a second register array.
+template <typename T, int KMAX, bool DEC, int J, bool CL = false>
 struct StepTile {
   using C = typename CT<T>::C;
   int nLoad, n1, n2, n3, n4, nNL;
@@ -1110,6 +1112,7 @@ struct StepTile {
   const int32_t* ext;
   int q[J][KMAX];  // neighbour slots
   T cl[J][KMAX];
+  T cli[J][CL ? KMAX : 1];
   T cm[J][DEC ? KMAX : 1];
   int wd[J];  // slice width (wave-uniform)
   int32_t rr[J];
@@ -1156,10 +1159,12 @@ struct StepTile {
           q[j][k] = tl.lcol[base + 64 * k];
           cl[j][k] = tl.llw[base + 64 * k];
           if (DEC) cm[j][k] = tl.lmw[base + 64 * k];
+          if constexpr (CL) cli[j][k] = tl.llwi[base + 64 * k];
         } else {
           q[j][k] = i < n1 ? i : 0;
           cl[j][k] = T(0);
           if (DEC) cm[j][k] = T(0);
+          if constexpr (CL) cli[j][k] = T(0);
         }
       }
     }
@@ -1183,8 +1188,14 @@ struct StepTile {
     for (int k = 0; k < N; ++k) vq[k] = V_.get(nb(j, k));
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      ar += cl[j][k] * (vr.x - vq[k].x);
-      ai += cl[j][k] * (vr.y - vq[k].y);
+      const T dx = vr.x - vq[k].x, dy = vr.y - vq[k].y;
+      if constexpr (CL) {  // (cl + i cli) (dx + i dy)
+        ar += cl[j][k] * dx - cli[j][k] * dy;
+        ai += cl[j][k] * dy + cli[j][k] * dx;
+      } else {
+        ar += cl[j][k] * dx;
+        ai += cl[j][k] * dy;
+      }
     }
   }
   template <int N, typename V>
@@ -1786,7 +1797,7 @@ struct StepTile {
 };
 
 // One whole z step, LIN(h) then NL(tau), per tile of rows (five halo rings).
-template <typename T, int KMAX, bool DEC, int J>
+template <typename T, int KMAX, bool DEC, int J, bool CL = false>
 __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ in_psi,
                                                typename CT<T>::C* __restrict__ out_psi, T h, T tau, T gamma) {
   using C = typename CT<T>::C;
@@ -1797,7 +1808,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step(DevOps<T> d, 
   C* base = reinterpret_cast<C*>(smem);
   const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS};
   T* S = reinterpret_cast<T*>(base + 3 * MS);
-  StepTile<T, KMAX, DEC, J> st;
+  StepTile<T, KMAX, DEC, J, CL> st;
   st.init(d, tl, tile);
   for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P.put(i, in_psi[st.slot_row(i)]);
   __syncthreads();
@@ -3007,11 +3018,16 @@ void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, v
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
   const size_t shmem = size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
   const int J = (tl.max_compute + block - 1) / block;
-#define DECBPM_STEP(KM, DEC, JJ)                                                                               \
-  hipLaunchKernelGGL((k_step<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi),     \
+#define DECBPM_STEP(KM, DEC, JJ, CLX)                                                                          \
+  hipLaunchKernelGGL((k_step<T, KM, DEC, JJ, CLX>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi), \
                      DECBPM_M(T, out_psi), T(h), T(tau), T(gamma))
-#define DECBPM_STEP_J(KM, DEC) \
-  if (J <= 1) DECBPM_STEP(KM, DEC, 1); else DECBPM_STEP(KM, DEC, 2);
+  // complex L weights (perfectly matched layer): their own instantiation
+#define DECBPM_STEP_J(KM, DEC)                                                   \
+  if (tl.llwi) {                                                                 \
+    if (J <= 1) DECBPM_STEP(KM, DEC, 1, true); else DECBPM_STEP(KM, DEC, 2, true); \
+  } else {                                                                       \
+    if (J <= 1) DECBPM_STEP(KM, DEC, 1, false); else DECBPM_STEP(KM, DEC, 2, false); \
+  }
   const bool dec = tl.lmw != nullptr;
   if (kmax_of(d.wmax) == 8) {
     if (dec) { DECBPM_STEP_J(8, true) } else { DECBPM_STEP_J(8, false) }

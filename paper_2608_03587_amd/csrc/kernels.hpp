@@ -61,6 +61,7 @@ struct TileOps {
   const uint16_t* lcol;
   const T* llw;
   const T* lmw;             // nullptr for the lumped nonlinearity
+  const T* llwi;            // imaginary part of the L weights (complex-stretched L), else nullptr
   int32_t ext_stride;       // step layout: per-tile stride of ext (every slot listed) and of lsl;
   int32_t lsl_stride;       // 0: classic layout (offsets in the header, ring 0 implicit)
   int32_t hdr_stride;       // ints per tile header (8 classic, 16 step layout)

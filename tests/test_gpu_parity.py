@@ -378,6 +378,70 @@ def test_mode_solver_converges_like_the_oracle():
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_pml_step_matches_oracle(dtype):
+    """A perfectly matched layer (complex-stretched Hodge stars) in place of the absorber on
+    the 89k-vertex step-index mesh: the one-kernel step with complex L weights against the
+    oracle's split scheme on the stretched operators, for step counts that mix graph
+    replays and eager steps; the handle refuses other launch modes and real-L entry points."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    pml = (35.0, 40.0, 1.0)
+    ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, None, pml=pml)
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, None, dtype=dtype, pml=pml)
+    assert m.tuning["fused"] == 2
+    u = dev(w.u0, dtype)
+    for n in (1, 2, 33):
+        say("pml", dtype, w.mesh.n_vert, n)
+        f = u.clone()
+        m.propagate(f, w.dz, n, w.gamma)
+        m.check_finite()
+        ref = S.propagate(w.u0, ops, w.dz, n, w.gamma)
+        err = rel(host(f), ref)
+        say("  rel err", err)
+        assert err < (1e-12 if dtype == "c128" else 1e-5), (n, err)
+    t = dict(m.tuning)
+    t["fused"] = 1
+    with pytest.raises(api.DecBpmError) as e:
+        m.tuning = t
+    assert e.value.code == B.EINVAL
+    with pytest.raises(api.DecBpmError) as e:
+        m.apply("L", u.clone())
+    assert e.value.code == B.EINVAL
+    P, E = m.diagnostics(u.clone(), w.gamma)
+    assert P > 0 and math.isnan(E)
+    assert m.time_kernels(w.dz, w.gamma, reps=10)["step"]["ms"] > 0
+
+
+def test_pml_absorbs_on_the_gpu():
+    """The outgoing-beam case of the oracle's absorption pin, run by the library (complex128):
+    equal to the oracle with the layer, and, inside r < 4.5, equal to the open-domain field
+    (the oracle on a disk of twice the radius) up to the meshes' mismatch, where a
+    reflecting boundary is far off."""
+    from scipy.interpolate import LinearNDInterpolator
+
+    mesh = M.disk_mesh(8.0, 0.25, 7)
+    launch = np.exp(-(mesh.xy[:, 0] ** 2 + mesh.xy[:, 1] ** 2)) * np.exp(3j * mesh.xy[:, 0])
+    pml = (5.0, 8.0, 1.0)
+    inner = np.hypot(mesh.xy[:, 0], mesh.xy[:, 1]) < 4.5
+    n, dz = 200, 0.02
+    out = {}
+    for name, kw in (("pml", {"pml": pml}), ("reflecting", {})):
+        m = api.Mesh(mesh.xy, mesh.tri, None, None, dtype="c128", p1=0.5, **kw)
+        f = dev(launch, "c128")
+        m.propagate(f, dz, n, 0.0)
+        out[name] = host(f)
+    ref = S.propagate(launch, dec.assemble(mesh.xy, mesh.tri, pml=pml), dz, n, 0.0)
+    assert rel(out["pml"], ref) < 1e-11
+    u0n = np.linalg.norm(launch[inner])
+    big = M.disk_mesh(16.0, 0.25, 7)
+    lb = np.exp(-(big.xy[:, 0] ** 2 + big.xy[:, 1] ** 2)) * np.exp(3j * big.xy[:, 0])
+    open_ref = S.propagate(lb, dec.assemble(big.xy, big.tri), dz, n, 0.0)
+    open_ref = LinearNDInterpolator(big.xy, open_ref)(mesh.xy[inner])
+    err = {k: np.linalg.norm(v[inner] - open_ref) / u0n for k, v in out.items()}
+    say("  interior error vs the open domain", err)
+    assert err["pml"] < 0.03 and err["reflecting"] > 0.3, err
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_step_index_full_size_prefix(dtype):
     """The full 250k-vertex step-index workload, 20 steps, in the bench's launch configuration."""
     w = case("step_index")

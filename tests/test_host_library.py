@@ -190,3 +190,36 @@ def test_workspace_size_grows_like_sqrt_n_checkpoints():
     s10000 = m.workspace_size(10000)  # 100 + 100
     assert 20 * vec < s100 < 80 * vec
     assert s10000 < 12 * s100
+
+
+def test_pml_host_assembly_matches_the_oracle():
+    """The library's stretched stiffness (P1 form |t| grad^T Lambda grad, accumulated per
+    triangle) and dual areas against the oracle's Whitney-Galerkin stretched stars; the
+    entry points that apply a real L refuse a PML handle; bad layer options are refused."""
+    import scipy.sparse as sp
+
+    mesh = M.disk_mesh(6.0, 0.4, 9)
+    pml = (4.0, 6.0, 1.5)
+    m = api.Mesh(mesh.xy, mesh.tri, dtype="c128", host_only=True, pml=pml)
+    ex = m.export_pml()
+    ops = dec.assemble(mesh.xy, mesh.tri, pml=pml)
+    H0p, H1p = dec.pml_hodge_stars(ops.xy, ops.tri, ops.edges, pml)
+    Kp = (ops.D0.T @ H1p @ ops.D0).tocsr()
+    n = mesh.n_vert
+    K_lib = sp.csr_matrix((ex["Kp"], ex["col"], ex["row_ptr"]), shape=(n, n))
+    assert abs(K_lib - Kp).max() < 1e-13 * abs(Kp).max()
+    assert np.abs(ex["h0p"] - H0p).max() < 1e-13 * np.abs(H0p).max()
+    # the real operators are exported unchanged
+    assert np.abs(ex["h0"] - ops.H0).max() < 1e-13 * ops.H0.max()
+    lib = B.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.dec_bpm_propagate_unsplit(m.handle, fake, 1e-3, 1, 1.0, None) == B.EINVAL
+    assert lib.dec_bpm_linear_step(m.handle, fake, 1e-3, None) == B.EINVAL
+    assert lib.dec_bpm_propagate(m.handle, fake, 1e-3, 1, 1.0, None) == B.ENODEVICE
+    plain = api.Mesh(mesh.xy, mesh.tri, dtype="c128", host_only=True)
+    assert lib.dec_bpm_export_pml(plain.handle, None, None) == B.EINVAL
+    for bad in ((0.0, 6.0, 1.0), (5.0, 4.0, 1.0), (4.0, 6.0, -1.0)):
+        with pytest.raises(api.DecBpmError):
+            api.Mesh(mesh.xy, mesh.tri, dtype="c128", host_only=True, pml=bad)
+    with pytest.raises(api.DecBpmError):
+        api.Mesh(mesh.xy, mesh.tri, dtype="c128", host_only=True, pml=pml, beta4=1e-3)
