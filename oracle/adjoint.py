@@ -99,8 +99,12 @@ def gradients(psi0, target, ops, dz, n_steps, gamma):
     """Return ``(J, g_psi0, g_dn)`` for ``J = |<t, psi(z_L)>_H0|^2``.
 
     ``g_dn`` is the gradient with respect to a per-vertex perturbation added to
-    the vertex potential ``v`` (``ops`` already holds the current ``v``)."""
+    the vertex potential ``v`` (``ops`` already holds the current ``v``).
+    Written for the Kerr response and H_lin = p1 L + beta4 L^2 - diag(v)."""
     from .stepper import lin_rk4, nl_flow
+
+    if ops.nl_kind != "kerr" or ops.p3 != 0.0 or ops.p4 != 0.0 or np.iscomplexobj(ops.L.data):
+        raise NotImplementedError("the adjoint covers the Kerr response, terms up to L^2 and a real L")
 
     h = dz
     states = []  # (x0, x1, x2) per step: step input, after NL(h/2), after LIN

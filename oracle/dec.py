@@ -276,6 +276,10 @@ class Operators:
     p1: float
     beta4: float
     nl: str
+    p3: float = 0.0  # coefficients of L^3 and L^4 (the general sum over n of p_n L^n)
+    p4: float = 0.0
+    nl_kind: str = "kerr"  # N(I): "kerr" I, "saturable" I/(1 + I/I_s), "cubic_quintic" I - s I^2
+    nl_param: float = 0.0  # I_s or s
 
     @property
     def n(self) -> int:
@@ -285,12 +289,23 @@ class Operators:
         return self.L @ x
 
     def apply_H(self, x):
-        """H_lin x = p1 L x + beta4 L(L x) - v x."""
+        """H_lin x = p1 L x + beta4 L^2 x + p3 L^3 x + p4 L^4 x - v x (powers applied in turn)."""
         Lx = self.L @ x
         out = self.p1 * Lx - self.v * x
-        if self.beta4 != 0.0:
-            out = out + self.beta4 * (self.L @ Lx)
+        t = Lx
+        for c in (self.beta4, self.p3, self.p4):
+            t = self.L @ t
+            if c != 0.0:
+                out = out + c * t
         return out
+
+    def N(self, I):
+        """Kerr response N(I) of the intensity I = |psi|^2 (Eq. 1's nonlinear term)."""
+        if self.nl_kind == "kerr":
+            return I
+        if self.nl_kind == "saturable":
+            return I / (1.0 + I / self.nl_param)
+        return I - self.nl_param * I * I
 
     def apply_HT(self, x):
         """Transpose of H_lin (needed by the adjoint): p1 L^T x + beta4 L^T L^T x - v x."""
@@ -302,16 +317,23 @@ class Operators:
         return out
 
     def dense_H(self):
-        H = self.p1 * self.L.toarray() - np.diag(self.v).astype(self.L.dtype)
-        if self.beta4 != 0.0:
-            Ld = self.L.toarray()
-            H = H + self.beta4 * Ld @ Ld
+        Ld = self.L.toarray()
+        H = self.p1 * Ld - np.diag(self.v).astype(self.L.dtype)
+        P = Ld
+        for c in (self.beta4, self.p3, self.p4):
+            P = P @ Ld
+            if c != 0.0:
+                H = H + c * P
         return H
 
 
 def assemble(xy, tri, index_tri=None, absorber=None, chi_tri=None, p1=0.5, beta4=0.0, nl="dec",
-             dn=None, pml=None) -> Operators:
+             dn=None, pml=None, p3=0.0, p4=0.0, nl_kind="kerr", nl_param=0.0) -> Operators:
     """Assemble every operator of the semi-discrete ODE (Eqs. 10-14).
+
+    Eq. 1 in full: ``p3``, ``p4`` add p3 L^3 + p4 L^4 to H_lin (beta4 is p2), and
+    ``nl_kind`` replaces the Kerr response N(I) = I by the saturable
+    I/(1 + I/I_s) or the cubic-quintic I - s I^2 (``nl_param`` = I_s or s).
 
     ``pml = (r0, r1, sigma_max[, m])`` replaces H0 and H1 inside L by the
     complex-stretched stars of ``pml_hodge_stars`` (L becomes complex; the
@@ -345,4 +367,7 @@ def assemble(xy, tri, index_tri=None, absorber=None, chi_tri=None, p1=0.5, beta4
         M = sp.diags(hodge0_pulse(xy, tri, chi) / H0).tocsr()
     else:
         raise ValueError(f"unknown nonlinearity {nl!r}")
-    return Operators(xy, tri, edges, D0, D1, area, H0, H1, K, L, v, w, chi, Q, QtDQ, M, float(p1), float(beta4), nl)
+    if nl_kind not in ("kerr", "saturable", "cubic_quintic"):
+        raise ValueError(f"unknown Kerr response {nl_kind!r}")
+    return Operators(xy, tri, edges, D0, D1, area, H0, H1, K, L, v, w, chi, Q, QtDQ, M, float(p1), float(beta4), nl,
+                     float(p3), float(p4), nl_kind, float(nl_param))

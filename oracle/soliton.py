@@ -6,13 +6,13 @@ A stationary solution ``Psi(z) = phi exp(-i mu z)`` of the semi-discrete
 equation without absorber (Eq. 10 with the operators of Eqs. 11-14, sign
 reading of ``oracle.dec``) solves the nonlinear eigenproblem
 
-    mu phi = G(phi),   G(phi) = H_lin phi - gamma (M |phi|^2) * phi.
+    mu phi = G(phi),   G(phi) = H_lin phi - gamma (M N(|phi|^2)) * phi.
 
 The paper launches such modes (its soliton shape-preservation benchmark) but
 its eigen-solver sits in a supplementary note that is not available; this
 module uses the gradient flow with discrete normalisation of Bao and Du
 (SIAM J. Sci. Comput. 25, 2004): march the imaginary-z equation
-``dphi/dtau = -A_k phi``, ``A_k = H_lin - gamma diag(M |phi_k|^2)`` (the
+``dphi/dtau = -A_k phi``, ``A_k = H_lin - gamma diag(M N(|phi_k|^2))`` (the
 nonlinearity frozen at the start of the step, as in their discretisations),
 one classical RK4 step of length ``dtau``, then rescale to the prescribed
 power ``P = sum_p H0_p |phi_p|^2``.  A fixed point is an eigenvector of
@@ -41,13 +41,13 @@ __all__ = ["G", "itp_rk4_step", "find_mode"]
 
 
 def G(phi: np.ndarray, ops, gamma: float) -> np.ndarray:
-    """H_lin phi - gamma (M |phi|^2) phi (the absorber plays no part)."""
-    return ops.apply_H(phi) - gamma * (ops.M @ (np.abs(phi) ** 2)) * phi
+    """H_lin phi - gamma (M N(|phi|^2)) phi (the absorber plays no part)."""
+    return ops.apply_H(phi) - gamma * (ops.M @ ops.N(np.abs(phi) ** 2)) * phi
 
 
 def itp_rk4_step(phi: np.ndarray, dtau: float, gamma: float, ops) -> np.ndarray:
-    """One classical RK4 step of dx/dtau = -A x, A = H_lin - gamma diag(M |phi|^2) frozen at phi."""
-    theta = ops.M @ (np.abs(phi) ** 2)
+    """One classical RK4 step of dx/dtau = -A x, A = H_lin - gamma diag(M N(|phi|^2)) frozen at phi."""
+    theta = ops.M @ ops.N(np.abs(phi) ** 2)
     f = lambda x: -(ops.apply_H(x) - gamma * theta * x)  # noqa: E731
     k1 = f(phi)
     k2 = f(phi + 0.5 * dtau * k1)

@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["phi", "nl_flow", "lin_rk4", "strang_step", "propagate"]
+__all__ = ["phi", "nl_integral", "nl_flow", "lin_rk4", "strang_step", "propagate"]
 
 
 def phi(w: np.ndarray, tau: float) -> np.ndarray:
@@ -37,9 +37,33 @@ def phi(w: np.ndarray, tau: float) -> np.ndarray:
     return out
 
 
+def nl_integral(I: np.ndarray, w: np.ndarray, tau: float, ops) -> np.ndarray:
+    """Integral over [0, tau] of N(I e^{-2 w z}): what the phase Theta = M (.) of the
+    exact flow accumulates when |psi|^2 decays as I e^{-2 w z}.
+
+    kerr: I phi(w, tau); cubic-quintic: I phi(w, tau) - s I^2 phi(2w, tau);
+    saturable (I_s): with a = I/I_s and e = e^{-2 w tau},
+    (I_s / (2w)) log((1 + a) / (1 + a e)), which tends to tau I / (1 + a) as w -> 0;
+    evaluated as (I_s / (2w)) log1p(a (1 - e) / (1 + a e)) with 1 - e = -expm1(-2 w tau),
+    which keeps full precision for small a and small w tau."""
+    w = np.asarray(w, dtype=np.float64)
+    if ops.nl_kind == "kerr":
+        return I * phi(w, tau)
+    if ops.nl_kind == "cubic_quintic":
+        return I * phi(w, tau) - ops.nl_param * I * I * phi(2.0 * w, tau)
+    Is = ops.nl_param
+    a = I / Is
+    out = tau * I / (1.0 + a)
+    nz = w > 0
+    one_minus_e = -np.expm1(-2.0 * w[nz] * tau)
+    e = 1.0 - one_minus_e
+    out[nz] = Is / (2.0 * w[nz]) * np.log1p(a[nz] * one_minus_e / (1.0 + a[nz] * e))
+    return out
+
+
 def nl_flow(psi: np.ndarray, tau: float, gamma: float, ops) -> np.ndarray:
     """Exact flow of the Kerr phase and absorber damping over ``tau``."""
-    theta = ops.M @ (np.abs(psi) ** 2 * phi(ops.w, tau))
+    theta = ops.M @ nl_integral(np.abs(psi) ** 2, ops.w, tau, ops)
     return psi * np.exp(-ops.w * tau) * np.exp(1j * gamma * theta)
 
 

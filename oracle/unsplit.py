@@ -8,9 +8,10 @@ than splitting it into a linear propagator and a Kerr step.  Written as
 ``dPsi/dz = F(Psi)``, with the sign reading of ``oracle.dec``, the right-hand
 side is
 
-    F(Psi) = -i H_lin Psi + i gamma (M |Psi|^2) * Psi - w * Psi,
+    F(Psi) = -i H_lin Psi + i gamma (M N(|Psi|^2)) * Psi - w * Psi,
 
-``H_lin = p1 L + beta4 L^2 - diag(v)``, ``M`` the nonlinear averaging matrix
+``H_lin = sum_n p_n L^n - diag(v)``, ``N`` the Kerr response (``N(I) = I``
+unless another is chosen), ``M`` the nonlinear averaging matrix
 (Eq. 14, or the lumped diagonal) and ``w >= 0`` the absorber.  This module
 takes the classical fourth-order Runge-Kutta method on F at a fixed step (the
 Kerr term evaluated inside every stage; the fixed step is what the workloads
@@ -25,8 +26,8 @@ __all__ = ["rhs", "rk4_step", "propagate_rk4", "dp54_step", "error_norm", "propa
 
 
 def rhs(psi: np.ndarray, ops, gamma: float) -> np.ndarray:
-    """F(Psi) = -i H_lin Psi + i gamma (M |Psi|^2) Psi - w Psi."""
-    theta = ops.M @ (np.abs(psi) ** 2)
+    """F(Psi) = -i H_lin Psi + i gamma (M N(|Psi|^2)) Psi - w Psi."""
+    theta = ops.M @ ops.N(np.abs(psi) ** 2)
     return -1j * ops.apply_H(psi) + 1j * gamma * theta * psi - ops.w * psi
 
 
