@@ -68,6 +68,7 @@ enum {
 
 typedef enum { DEC_BPM_C64 = 1, DEC_BPM_C128 = 2 } dec_bpm_dtype;
 typedef enum { DEC_BPM_NL_DEC = 0, DEC_BPM_NL_LUMPED = 1 } dec_bpm_nl;
+typedef enum { DEC_BPM_N_KERR = 0, DEC_BPM_N_SATURABLE = 1, DEC_BPM_N_CUBIC_QUINTIC = 2 } dec_bpm_response;
 
 typedef struct {
   uint32_t struct_size;   /* sizeof(dec_bpm_options); set by dec_bpm_default_options */
@@ -97,6 +98,19 @@ typedef struct {
    * check uses the unstretched operator's spectral radius, which bounds the
    * stretched one's. */
   double pml_r0, pml_r1, pml_sigma;
+  /* Eq. 1 in full: H_lin = p1 L + beta4 L^2 + p3 L^3 + p4 L^4 - diag(v), and
+   * the Kerr response N(I) in place of I = |psi|^2 (DEC_BPM_N_KERR, default;
+   * DEC_BPM_N_SATURABLE: I / (1 + I / nl_param), nl_param = I_s > 0;
+   * DEC_BPM_N_CUBIC_QUINTIC: I - nl_param I^2, nl_param >= 0).  The Kerr
+   * substep stays the exact flow: Theta = M (integral over the substep of
+   * N(|psi|^2 e^{-2 w z}), in closed form).  p3 or p4 non-zero, or a non-Kerr
+   * response, runs the five-kernel path (fused = 0; the L powers by Horner
+   * in extra gather launches); the checkpointed forward and adjoint, the tile
+   * paths, apply(H), batches, unsplit, adaptive and find_mode return EINVAL,
+   * and diagnostics report a NaN Hamiltonian. */
+  double p3, p4;
+  int32_t nl_kind;
+  double nl_param;
 } dec_bpm_options;
 
 /* Fill *opt with the defaults above. */

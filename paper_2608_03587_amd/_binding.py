@@ -41,6 +41,10 @@ class Options(ctypes.Structure):
         ("pml_r0", c_dbl),
         ("pml_r1", c_dbl),
         ("pml_sigma", c_dbl),
+        ("p3", c_dbl),
+        ("p4", c_dbl),
+        ("nl_kind", c_i32),
+        ("nl_param", c_dbl),
     ]
 
 

@@ -44,7 +44,8 @@ class Mesh:
     """
 
     def __init__(self, xy, tri, index_tri=None, absorber=None, chi_tri=None, dtype="c64", p1=0.5, beta4=0.0,
-                 nonlinearity="dec", reorder=True, host_only=False, block_size=0, steps_per_graph=0, pml=None):
+                 nonlinearity="dec", reorder=True, host_only=False, block_size=0, steps_per_graph=0, pml=None,
+                 p3=0.0, p4=0.0, response="kerr", response_param=0.0):
         L = B.lib()
         self.dtype_name = dtype
         code, self.torch_dtype = _DT[dtype]
@@ -64,6 +65,9 @@ class Mesh:
         opt.steps_per_graph = int(steps_per_graph)
         if pml is not None:  # (r0, r1, sigma_max): radial perfectly matched layer
             opt.pml_r0, opt.pml_r1, opt.pml_sigma = (float(v) for v in pml)
+        opt.p3, opt.p4 = float(p3), float(p4)
+        opt.nl_kind = {"kerr": 0, "saturable": 1, "cubic_quintic": 2}[response]
+        opt.nl_param = float(response_param)
         keep = []
         if chi_tri is not None:
             chi = np.ascontiguousarray(chi_tri, dtype=np.float64)

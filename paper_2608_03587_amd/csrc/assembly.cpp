@@ -60,6 +60,7 @@ Assembled assemble(const AssemblyInput& in) {
   if (in.n >= (int64_t(1) << 31) - 1) fail(DEC_BPM_EINVAL, "too many vertices for 32-bit indices");
   if (!(in.p1 >= 0.0) || !(in.beta4 >= 0.0) || !std::isfinite(in.p1) || !std::isfinite(in.beta4))
     fail(DEC_BPM_EINVAL, "p1 and beta4 must be finite and >= 0");
+  if (!std::isfinite(in.p3) || !std::isfinite(in.p4)) fail(DEC_BPM_EINVAL, "p3 and p4 must be finite");
   if (in.nonlinearity != 0 && in.nonlinearity != 1) fail(DEC_BPM_EINVAL, "unknown nonlinearity mode");
   if (!(in.pml_sigma >= 0.0) || !std::isfinite(in.pml_sigma) ||
       (in.pml_sigma > 0.0 && !(in.pml_r0 > 0.0 && in.pml_r1 > in.pml_r0 && std::isfinite(in.pml_r1))))
@@ -314,7 +315,7 @@ Assembled assemble(const AssemblyInput& in) {
   a.iperm.resize(n);
   for (int64_t i = 0; i < n; ++i) a.iperm[a.perm[i]] = int32_t(i);
 
-  a.rho = spectral_radius(a, in.p1, in.beta4, a.v);
+  a.rho = spectral_radius(a, in.p1, in.beta4, a.v, in.p3, in.p4);
   return a;
 }
 
@@ -335,14 +336,15 @@ int sturm_count(const std::vector<double>& al, const std::vector<double>& be, do
 
 }  // namespace
 
-double spectral_radius(const Assembled& a, double p1, double beta4, const std::vector<double>& v) {
+double spectral_radius(const Assembled& a, double p1, double beta4, const std::vector<double>& v, double p3,
+                       double p4) {
   const int64_t n = a.n;
   std::vector<double> s(n), is(n);
   for (int64_t p = 0; p < n; ++p) {
     s[p] = std::sqrt(a.h0[p]);
     is[p] = 1.0 / s[p];
   }
-  // B = H0^{-1/2} K H0^{-1/2};  S = p1 B + beta4 B^2 - diag(v)   (symmetric)
+  // B = H0^{-1/2} K H0^{-1/2};  S = p1 B + beta4 B^2 + p3 B^3 + p4 B^4 - diag(v)   (symmetric)
   auto applyB = [&](const std::vector<double>& x, std::vector<double>& y) {
     for (int64_t p = 0; p < n; ++p) {
       double acc = 0.0;
@@ -351,10 +353,19 @@ double spectral_radius(const Assembled& a, double p1, double beta4, const std::v
     }
   };
   std::vector<double> t1(n), t2(n);
+  const double c[4] = {p1, beta4, p3, p4};
+  const int deg = p4 != 0.0 ? 4 : (p3 != 0.0 ? 3 : (beta4 != 0.0 ? 2 : 1));
   auto applyS = [&](const std::vector<double>& x, std::vector<double>& y) {
+    for (int64_t p = 0; p < n; ++p) y[p] = -v[p] * x[p];
     applyB(x, t1);
-    if (beta4 != 0.0) applyB(t1, t2);
-    for (int64_t p = 0; p < n; ++p) y[p] = p1 * t1[p] + (beta4 != 0.0 ? beta4 * t2[p] : 0.0) - v[p] * x[p];
+    for (int k = 0; k < deg; ++k) {
+      if (k) {
+        applyB(t1, t2);
+        t1.swap(t2);
+      }
+      if (c[k] != 0.0)
+        for (int64_t p = 0; p < n; ++p) y[p] += c[k] * t1[p];
+    }
   };
   const int kmax = int(std::min<int64_t>(n, 120));
   std::vector<double> q(n), qprev(n, 0.0), z(n), al, be;

@@ -26,6 +26,7 @@ struct AssemblyInput {
   const double* chi_tri = nullptr;    // [t] or null
   double p1 = 0.5;
   double beta4 = 0.0;
+  double p3 = 0.0, p4 = 0.0;  // coefficients of L^3 and L^4
   int nonlinearity = 0;  // 0 = triangle-averaged (Eq. 14), 1 = lumped
   bool reorder = true;
   // radial perfectly matched layer: sigma(r) = pml_sigma ((r - pml_r0)/(pml_r1 - pml_r0))^2
@@ -55,9 +56,10 @@ struct Assembled {
 
 Assembled assemble(const AssemblyInput& in);
 
-// Spectral radius of p1 L + beta4 L^2 - diag(v) by Lanczos on the H0-symmetrised
-// operator (FP64), returned with a small safety factor.
-double spectral_radius(const Assembled& a, double p1, double beta4, const std::vector<double>& v);
+// Spectral radius of p1 L + beta4 L^2 + p3 L^3 + p4 L^4 - diag(v) by Lanczos on
+// the H0-symmetrised operator (FP64), returned with a small safety factor.
+double spectral_radius(const Assembled& a, double p1, double beta4, const std::vector<double>& v, double p3 = 0.0,
+                       double p4 = 0.0);
 
 // Hilbert-curve index of (x, y) in [0, 2^order)^2.
 uint64_t hilbert_index(uint32_t x, uint32_t y, int order);

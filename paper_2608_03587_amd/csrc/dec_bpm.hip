@@ -85,6 +85,9 @@ struct Engine {
   int64_t n_rows = 0;  // device rows
   int32_t F = 1;
   double p1 = 0.5, beta4 = 0.0;
+  double p3 = 0.0, p4 = 0.0;  // coefficients of L^3, L^4
+  int nk = DEC_BPM_N_KERR;    // Kerr response
+  double npar = 0.0;
   int nl = DEC_BPM_NL_DEC;
   double rho = 0.0;
   double dn_max = 0.0;
@@ -149,6 +152,7 @@ struct Engine {
   void* ya = nullptr;
   void* yb = nullptr;
   void* t = nullptr;
+  void* u = nullptr;  // second Horner buffer of the L^3, L^4 terms
   void* s = nullptr;
   double* partials = nullptr;
   double* red_out = nullptr;
@@ -188,6 +192,9 @@ struct Engine {
     return std::min(1024, std::max(tile_block, need));
   }
 
+  // terms beyond the kernels' fused forms (L^3, L^4, a non-Kerr response): five-kernel path only
+  bool general() const { return p3 != 0.0 || p4 != 0.0 || nk != DEC_BPM_N_KERR; }
+
   size_t real_size() const { return dtype == DEC_BPM_C64 ? 4 : 8; }
   size_t cplx_size() const { return 2 * real_size(); }
 
@@ -216,6 +223,8 @@ struct Engine {
     d.p1 = T(p1);
     d.beta4 = T(beta4);
     d.xcd_remap = xcd;
+    d.nk = nk;
+    d.npar = T(npar);
     return d;
   }
 
@@ -686,8 +695,8 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   E.h0c = static_cast<double*>(p);
   upload(E, p, perm);
   E.perm = static_cast<int32_t*>(p);
-  if (E.F == 1 && E.beta4 == 0.0 && !pml) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
-  build_step_tiles<T>(E, arp, acol, alw, amw, any_dec, pml ? &alwi : nullptr);
+  if (E.F == 1 && E.beta4 == 0.0 && !pml && !E.general()) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  if (!E.general()) build_step_tiles<T>(E, arp, acol, alw, amw, any_dec, pml ? &alwi : nullptr);
   if (pml && !E.has_step)
     fail(DEC_BPM_EINVAL, "PML: the mesh needs the one-kernel step tiles (rows of at most 12 neighbours)");
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
@@ -703,7 +712,8 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   if (E.has_tiles || E.has_step || E.has_step4) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
   E.ya = E.dalloc(nv * 2 * sizeof(T));
   E.yb = E.dalloc(nv * 2 * sizeof(T));
-  E.t = E.beta4 != 0.0 ? E.dalloc(nv * 2 * sizeof(T)) : nullptr;
+  E.t = (E.beta4 != 0.0 || E.general()) ? E.dalloc(nv * 2 * sizeof(T)) : nullptr;
+  E.u = (E.p3 != 0.0 || E.p4 != 0.0) ? E.dalloc(nv * 2 * sizeof(T)) : nullptr;
   E.s = E.dalloc(nv * sizeof(T));
   E.n_red_blocks = int((n + 255) / 256);
   E.partials = static_cast<double*>(E.dalloc(2 * size_t(std::max(E.n_red_blocks, 1)) * sizeof(double)));
@@ -722,6 +732,7 @@ static void build_engine(Engine& E, const std::vector<const Assembled*>& meshes,
     build_engine_t<double>(E, meshes, lumped);
   if (E.fused < 0) E.fused = (E.has_step || E.has_step4) ? 2 : ((E.has_tiles || E.has_btiles) ? 1 : 0);
   if (E.pml) E.fused = 2;
+  if (E.general()) E.fused = 0;
 }
 
 static void check_launch() {
@@ -771,6 +782,25 @@ static void lin_step(const Engine& E, const DevOps<T>& d, const void* in, void* 
   const void* xs[4] = {in, y1, y2, y3};
   void* ys[4] = {y1, y2, y3, out};
   const double cs[4] = {dz / 4, dz / 3, dz / 2, dz};
+  if (E.p3 != 0.0 || E.p4 != 0.0) {
+    // sum_n p_n L^n x = L U with U = p1 x + L(p2 x + L(p3 x + p4 L x)) by Horner;
+    // the beta4 stage with p1 -> 0, beta4 -> 1 and t = U applies the last L
+    DevOps<T> dg = d;
+    dg.p1 = T(0);
+    dg.beta4 = T(1);
+    for (int k = 0; k < 4; ++k) {
+      const void* x = xs[k];
+      if (E.p4 != 0.0) {
+        launch_lapc<T>(d, x, x, E.p4, E.p3, E.t, E.block, st);    // p3 x + p4 L x
+        launch_lapc<T>(d, E.t, x, 1.0, E.beta4, E.u, E.block, st);  // p2 x + L(.)
+      } else {
+        launch_lapc<T>(d, x, x, E.p3, E.beta4, E.u, E.block, st);   // p2 x + p3 L x
+      }
+      launch_lapc<T>(d, E.u, x, 1.0, E.p1, E.t, E.block, st);      // U = p1 x + L(.)
+      do_stage<T>(E, dg, x, E.t, in, ys[k], cs[k], k == 3 ? s_out : nullptr, tau_s, st);
+    }
+    return;
+  }
   for (int k = 0; k < 4; ++k) {
     if (E.beta4 != 0.0) {
       do_lap<T>(E, d, xs[k], E.t, st);
@@ -838,6 +868,7 @@ static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl,
 template <typename T>
 static int mode_of(Engine& E) {
   if (E.pml) return 2;                            // complex L: the one-kernel step only
+  if (E.general()) return 0;                      // L^3, L^4 or a non-Kerr response: five kernels
   if (E.has_step4) return E.fused >= 2 ? 4 : 0;  // beta4: its one-kernel step or the five kernels
   if (use_persist<T>(E)) return 3;
   if (E.fused == 3 && E.has_step) return 2;
@@ -902,9 +933,14 @@ static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, int mode) {
   return exec;
 }
 
-// Entry points whose kernels take a real L refuse handles with a PML.
+// Entry points whose kernels take a real L refuse handles with a PML; those
+// written for the Kerr response and terms up to L^2 refuse the general ones.
 static void no_pml(const Engine& E, const char* what) {
   if (E.pml) fail(DEC_BPM_EINVAL, std::string(what) + ": not available on a handle with a PML (complex L)");
+}
+static void no_general(const Engine& E, const char* what) {
+  if (E.general())
+    fail(DEC_BPM_EINVAL, std::string(what) + ": not available with L^3, L^4 or a non-Kerr response");
 }
 
 static void check_stability(const Engine& E, double dz) {
@@ -1801,6 +1837,15 @@ int dec_bpm_create(const double* xy, int64_t n_vert, const int32_t* tri, int64_t
   in.pml_r0 = o.pml_r0;
   in.pml_r1 = o.pml_r1;
   in.pml_sigma = o.pml_sigma;
+  in.p3 = o.p3;
+  in.p4 = o.p4;
+  if (o.nl_kind < DEC_BPM_N_KERR || o.nl_kind > DEC_BPM_N_CUBIC_QUINTIC) fail(DEC_BPM_EINVAL, "unknown nl_kind");
+  if (o.nl_kind == DEC_BPM_N_SATURABLE && !(o.nl_param > 0.0 && std::isfinite(o.nl_param)))
+    fail(DEC_BPM_EINVAL, "the saturable response needs nl_param = I_s > 0");
+  if (o.nl_kind == DEC_BPM_N_CUBIC_QUINTIC && !(o.nl_param >= 0.0 && std::isfinite(o.nl_param)))
+    fail(DEC_BPM_EINVAL, "the cubic-quintic response needs nl_param >= 0");
+  if ((o.p3 != 0.0 || o.p4 != 0.0 || o.nl_kind != DEC_BPM_N_KERR) && o.pml_sigma > 0.0)
+    fail(DEC_BPM_EINVAL, "a PML does not combine with L^3, L^4 or a non-Kerr response");
   std::unique_ptr<dec_bpm_s> h(new dec_bpm_s());
   h->A = decbpm::assemble(in);
   o.chi_tri = nullptr;  // not kept
@@ -1811,6 +1856,10 @@ int dec_bpm_create(const double* xy, int64_t n_vert, const int32_t* tri, int64_t
   E.p1 = o.p1;
   E.beta4 = o.beta4;
   E.nl = o.nonlinearity;
+  E.p3 = o.p3;
+  E.p4 = o.p4;
+  E.nk = o.nl_kind;
+  E.npar = o.nl_param;
   E.rho = h->A.rho;
   E.pml = !h->A.kp_re.empty();
   if (!o.host_only) {
@@ -1914,6 +1963,8 @@ int dec_bpm_apply(dec_bpm_t h, int op, const void* x, void* y, void* stream) {
   Engine& E = h->E;
   if (!x || !y || x == y) fail(DEC_BPM_EINVAL, "x and y must be distinct non-NULL device vectors");
   if (op < DEC_BPM_OP_L || op > DEC_BPM_OP_H) fail(DEC_BPM_EINVAL, "unknown operator");
+  if (op == DEC_BPM_OP_H && (E.p3 != 0.0 || E.p4 != 0.0))
+    fail(DEC_BPM_EINVAL, "dec_bpm_apply(H): not available with L^3 or L^4 terms");
   if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
   hipStream_t st = as_stream(stream);
   auto run = [&](auto tag) {
@@ -2002,6 +2053,7 @@ int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, doub
 int dec_bpm_propagate_unsplit(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_general(h->E, "dec_bpm_propagate_unsplit");
   decbpm::no_pml(h->E, "dec_bpm_propagate_unsplit");
   decbpm::check_prop_args(h->E, field, dz, n_steps, gamma);
   if (!h->E.has_step || h->E.F != 1)
@@ -2020,6 +2072,7 @@ int dec_bpm_propagate_adaptive(dec_bpm_t h, void* field, double z_end, double h0
                                double* last_h, double* z_reached, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_general(h->E, "dec_bpm_propagate_adaptive");
   decbpm::no_pml(h->E, "dec_bpm_propagate_adaptive");
   Engine& E = h->E;
   if (n_accepted) *n_accepted = 0;
@@ -2060,6 +2113,7 @@ int dec_bpm_find_mode(dec_bpm_t h, void* field, double power, double dtau, doubl
                       int64_t max_iter, double* mu, double* residual, int64_t* iterations, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_general(h->E, "dec_bpm_find_mode");
   decbpm::no_pml(h->E, "dec_bpm_find_mode");
   Engine& E = h->E;
   if (mu) *mu = 0.0;
@@ -2131,7 +2185,7 @@ int dec_bpm_diagnostics(dec_bpm_t h, const void* field, double gamma, double* po
   HIP_OK(hipStreamSynchronize(st));
   if (power) *power = out[0];
   // with a PML the Hamiltonian is not defined (complex L): NaN
-  if (hamiltonian) *hamiltonian = E.pml ? std::nan("") : out[1];
+  if (hamiltonian) *hamiltonian = (E.pml || E.general()) ? std::nan("") : out[1];
   ABI_CATCH
 }
 
@@ -2167,6 +2221,7 @@ int dec_bpm_forward_checkpointed(dec_bpm_t h, void* field, double dz, int64_t n_
                                  void* workspace, size_t ws_bytes, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_general(h->E, "dec_bpm_forward_checkpointed");
   decbpm::no_pml(h->E, "dec_bpm_forward_checkpointed");
   Engine& E = h->E;
   decbpm::check_prop_args(E, field, dz, n_steps, gamma);
@@ -2193,6 +2248,7 @@ int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_step
                     void* workspace, size_t ws_bytes, void* grad_field0, double* grad_dn, void* stream) {
   ABI_TRY
   need(h);
+  decbpm::no_general(h->E, "dec_bpm_adjoint");
   decbpm::no_pml(h->E, "dec_bpm_adjoint");
   Engine& E = h->E;
   decbpm::check_prop_args(E, grad_field0, dz, n_steps, gamma);
@@ -2238,6 +2294,7 @@ int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, int32_t fiel
     const dec_bpm_s* h = meshes[m];
     if (!h) fail(DEC_BPM_EINVAL, "NULL mesh handle");
     if (!h->A.kp_re.empty()) fail(DEC_BPM_EINVAL, "batches do not take meshes with a PML");
+    if (h->E.general()) fail(DEC_BPM_EINVAL, "batches do not take L^3, L^4 or non-Kerr responses");
     if (h->opt.dtype != m0->opt.dtype || h->opt.p1 != m0->opt.p1 || h->opt.beta4 != m0->opt.beta4 ||
         h->opt.nonlinearity != m0->opt.nonlinearity)
       fail(DEC_BPM_EINVAL, "all meshes of a batch must share dtype, p1, beta4 and nonlinearity");
@@ -2316,6 +2373,8 @@ static void set_tuning(Engine& E, const dec_bpm_tuning* t) {
       (t->xcd_remap != 0 && t->xcd_remap != 1))
     fail(DEC_BPM_EINVAL, "bad tuning");
   if (E.pml && t->fused != 2) fail(DEC_BPM_EINVAL, "a PML handle runs the one-kernel step only (fused = 2)");
+  if (E.general() && t->fused != 0)
+    fail(DEC_BPM_EINVAL, "L^3, L^4 or a non-Kerr response run the five-kernel path only (fused = 0)");
   E.block = t->block_size;
   E.spg = t->steps_per_graph;
   E.fused = t->fused;

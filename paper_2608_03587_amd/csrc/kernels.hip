@@ -22,6 +22,8 @@ __device__ inline float d_exp(float x) { return expf(x); }
 __device__ inline double d_exp(double x) { return exp(x); }
 __device__ inline float d_expm1(float x) { return expm1f(x); }
 __device__ inline double d_expm1(double x) { return expm1(x); }
+__device__ inline float d_log1p(float x) { return log1pf(x); }
+__device__ inline double d_log1p(double x) { return log1p(x); }
 __device__ inline void d_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ inline void d_sincos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ inline bool d_finite(float x) { return isfinite(x); }
@@ -31,6 +33,23 @@ __device__ inline bool d_finite(double x) { return isfinite(x); }
 template <typename T>
 __device__ inline T phi_w(T w, T tau) {
   return w > T(0) ? -d_expm1(T(-2) * w * tau) / (T(2) * w) : tau;
+}
+
+// Integral over [0, tau] of N(I e^{-2 w z}): the intensity a row contributes to
+// the Kerr phase of an exact substep of length tau (the response N of d.nk;
+// |psi|^2 decays as I e^{-2 w z} along the substep).  Kerr: I phi(w, tau);
+// cubic-quintic: I phi(w, tau) - s I^2 phi(2w, tau); saturable (I_s):
+// (I_s/(2w)) log((1 + a)/(1 + a e)), a = I/I_s, e = e^{-2 w tau}, taken as
+// log1p(a (1 - e)/(1 + a e)) with 1 - e = -expm1(-2 w tau) (full precision
+// for small a and small w tau), and tau I/(1 + a) at w = 0.
+template <typename T>
+__device__ inline T nl_int(const DevOps<T>& d, T I, T w, T tau) {
+  if (d.nk == 0) return I * phi_w(w, tau);
+  if (d.nk == 2) return I * phi_w(w, tau) - d.npar * I * I * phi_w(T(2) * w, tau);
+  const T a = I / d.npar;
+  if (w <= T(0)) return tau * I / (T(1) + a);
+  const T ome = -d_expm1(T(-2) * w * tau);
+  return d.npar / (T(2) * w) * d_log1p(a * ome / (T(1) + a * (T(1) - ome)));
 }
 
 template <typename T>
@@ -148,7 +167,7 @@ __global__ void __launch_bounds__(1024) k_stage(DevOps<T> d, const typename CT<T
   out.x = p.x + coef * hi;  // -i (hr + i hi) = hi - i hr
   out.y = p.y - coef * hr;
   y[idx] = out;
-  if (WS) s_out[idx] = (out.x * out.x + out.y * out.y) * phi_w(d.w[row], tau_s);
+  if (WS) s_out[idx] = nl_int(d, out.x * out.x + out.y * out.y, d.w[row], tau_s);
 }
 
 // t = L x
@@ -175,6 +194,28 @@ __global__ void __launch_bounds__(1024) k_lap(DevOps<T> d, const typename CT<T>:
   t[idx] = out;
 }
 
+// y = a L z + b x (F = 1)
+template <typename T, int KMAX>
+__global__ void __launch_bounds__(1024) k_lapc(DevOps<T> d, const typename CT<T>::C* __restrict__ z,
+                                               const typename CT<T>::C* __restrict__ x, T a, T b,
+                                               typename CT<T>::C* __restrict__ y) {
+  using C = typename CT<T>::C;
+  const int64_t row = logical_block(d.xcd_remap) * blockDim.x + threadIdx.x;
+  if (row >= d.n_rows) return;
+  const C zr = z[row];
+  const C xr = x[row];
+  T ar = T(0), ai = T(0);
+  for_neighbours<KMAX>(d, d.lw, row, [&](int32_t q, T c) {
+    const C zq = z[q];
+    ar += c * (zr.x - zq.x);
+    ai += c * (zr.y - zq.y);
+  });
+  C out;
+  out.x = a * ar + b * xr.x;
+  out.y = a * ai + b * xr.y;
+  y[row] = out;
+}
+
 template <typename T, int FB>
 __global__ void __launch_bounds__(1024) k_prep_s(DevOps<T> d, const typename CT<T>::C* __restrict__ psi,
                                                  T* __restrict__ s, T tau) {
@@ -184,7 +225,7 @@ __global__ void __launch_bounds__(1024) k_prep_s(DevOps<T> d, const typename CT<
   split<FB>(idx, d, row, f);
   if (row >= d.n_rows) return;
   const auto p = psi[idx];
-  s[idx] = (p.x * p.x + p.y * p.y) * phi_w(d.w[row], tau);
+  s[idx] = nl_int(d, p.x * p.x + p.y * p.y, d.w[row], tau);
 }
 
 // Exact Kerr/absorber flow over tau:
@@ -2832,6 +2873,14 @@ void launch_lap(const DevOps<T>& d, const void* x, void* t, int block, hipStream
 }
 
 template <typename T>
+void launch_lapc(const DevOps<T>& d, const void* z, const void* x, double a, double b, void* y, int block,
+                 hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows, block, d.xcd_remap);
+  DECBPM_DISPATCH_K(d, hipLaunchKernelGGL((k_lapc<T, KM>), dim3(g), dim3(block), 0, st, d, DECBPM_C(T, z),
+                                          DECBPM_C(T, x), T(a), T(b), DECBPM_M(T, y)))
+}
+
+template <typename T>
 void launch_prep_s(const DevOps<T>& d, const void* psi, void* s, double tau, int block, hipStream_t st) {
   if (vf_of(d) > 1) {
     constexpr int VF = int(32 / sizeof(typename CT<T>::C));
@@ -3376,6 +3425,8 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                   int, hipStream_t);                                                             \
   template void launch_unsplit<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, int,    \
                                   hipStream_t);                                                                  \
+  template void launch_lapc<T>(const DevOps<T>&, const void*, const void*, double, double, void*, int,         \
+                               hipStream_t);                                                                     \
   template void launch_dp5<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, Dp5Ctl*, double*, uint32_t*,     \
                               double, double, double, double, int, hipStream_t);                                 \
   template void launch_mode<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, ModeCtl*, double*, uint32_t*,   \

@@ -36,6 +36,8 @@ struct DevOps {
   const double* h0;    // dual areas (device order)
   T p1, beta4;
   int32_t xcd_remap;   // 1: map consecutive row blocks onto one XCD
+  int32_t nk;          // Kerr response: 0 N(I) = I, 1 saturable I/(1 + I/npar), 2 cubic-quintic I - npar I^2
+  T npar;
 };
 
 // Tiles for the fused kernels (one field per row, no beta4 term).  Tile t
@@ -92,6 +94,10 @@ void launch_stage(const DevOps<T>& d, const void* x, const void* t, const void* 
 // t = L x
 template <typename T>
 void launch_lap(const DevOps<T>& d, const void* x, void* t, int block, hipStream_t st);
+// y = a L z + b x  (one Horner step of a sum of powers of L; F = 1)
+template <typename T>
+void launch_lapc(const DevOps<T>& d, const void* z, const void* x, double a, double b, void* y, int block,
+                 hipStream_t st);
 // s = |psi|^2 phi(w, tau)
 template <typename T>
 void launch_prep_s(const DevOps<T>& d, const void* psi, void* s, double tau, int block, hipStream_t st);

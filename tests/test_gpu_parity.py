@@ -442,6 +442,48 @@ def test_pml_absorbs_on_the_gpu():
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("response,param,p3,p4", [("kerr", 0.0, -4e-3, 1e-3), ("saturable", 0.8, 0.0, 0.0),
+                                                   ("cubic_quintic", 0.25, 2e-3, 0.0)])
+def test_general_operator_sum_and_responses_match_oracle(dtype, response, param, p3, p4):
+    """Eq. 1 in full on the five-kernel path: terms up to p4 L^4 (Horner gathers) and the
+    saturable and cubic-quintic Kerr responses (closed-form flow integrals), against the
+    oracle's split scheme on the step-index replica (89k vertices, with absorber), plus
+    the Kerr substep and the linear step alone."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    kw = dict(p3=p3, p4=p4, nl_kind=response, nl_param=param)
+    ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, beta4=2e-3, **kw)
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=dtype, p1=w.p1, beta4=2e-3, p3=p3, p4=p4,
+                 response=response, response_param=param)
+    assert m.tuning["fused"] == 0
+    dz = 0.9 * 2.5 / m.spectral_radius()
+    u0 = 1.5 * w.u0
+    u = dev(u0, dtype)
+    tol = 1e-12 if dtype == "c128" else 2e-5
+    say("general", dtype, response, p3, p4, "dz", dz)
+    f = u.clone()
+    m.kerr_step(f, 0.37, w.gamma)
+    assert rel(host(f), S.nl_flow(u0, 0.37, w.gamma, ops)) < tol
+    f = u.clone()
+    m.linear_step(f, dz)
+    assert rel(host(f), S.lin_rk4(u0, dz, ops)) < tol
+    for n in (1, 7):
+        f = u.clone()
+        m.propagate(f, dz, n, w.gamma)
+        m.check_finite()
+        err = rel(host(f), S.propagate(u0, ops, dz, n, w.gamma))
+        say("  steps", n, "rel err", err)
+        assert err < tol, (n, err)
+    P, E = m.diagnostics(u.clone(), w.gamma)
+    assert P > 0 and math.isnan(E)
+    with pytest.raises(api.DecBpmError) as e:
+        m.tuning = {"fused": 2}
+    assert e.value.code == B.EINVAL
+    with pytest.raises(api.DecBpmError) as e:
+        m.propagate_unsplit(u.clone(), dz, 1, w.gamma)
+    assert e.value.code == B.EINVAL
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_step_index_full_size_prefix(dtype):
     """The full 250k-vertex step-index workload, 20 steps, in the bench's launch configuration."""
     w = case("step_index")

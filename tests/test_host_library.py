@@ -223,3 +223,26 @@ def test_pml_host_assembly_matches_the_oracle():
             api.Mesh(mesh.xy, mesh.tri, dtype="c128", host_only=True, pml=bad)
     with pytest.raises(api.DecBpmError):
         api.Mesh(mesh.xy, mesh.tri, dtype="c128", host_only=True, pml=pml, beta4=1e-3)
+
+
+def test_general_operator_sum_and_responses_on_the_host():
+    """L^3 and L^4 enter the stability bound (Lanczos of the symmetrised sum against the
+    oracle's dense spectrum); bad response options are refused; entry points written for
+    the Kerr response and terms up to L^2 refuse the general handles."""
+    mesh = M.disk_mesh(4.0, 0.35, 3)
+    p3, p4 = -2e-3, 4e-4
+    m = api.Mesh(mesh.xy, mesh.tri, dtype="c128", host_only=True, p3=p3, p4=p4)
+    ops = dec.assemble(mesh.xy, mesh.tri, p3=p3, p4=p4)
+    rho = np.abs(np.linalg.eigvals(ops.dense_H())).max()
+    assert rho <= m.spectral_radius() <= 1.02 * rho
+    lib = B.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.dec_bpm_propagate_unsplit(m.handle, fake, 1e-4, 1, 1.0, None) == B.EINVAL
+    assert lib.dec_bpm_propagate(m.handle, fake, 1e-4, 1, 1.0, None) == B.ENODEVICE
+    assert lib.dec_bpm_apply(m.handle, B.OP_H, fake, ctypes.c_void_p(1 << 21), None) == B.EINVAL
+    s = api.Mesh(mesh.xy, mesh.tri, dtype="c64", host_only=True, response="saturable", response_param=2.0)
+    assert lib.dec_bpm_find_mode(s.handle, fake, 1.0, 1e-3, 1.0, 1e-8, 10, None, None, None, None) == B.EINVAL
+    for kw in ({"response": "saturable", "response_param": 0.0}, {"response": "cubic_quintic", "response_param": -1.0},
+               {"p3": float("inf")}, {"response": "saturable", "response_param": 1.0, "pml": (3.0, 4.0, 1.0)}):
+        with pytest.raises(api.DecBpmError):
+            api.Mesh(mesh.xy, mesh.tri, dtype="c64", host_only=True, **kw)
