@@ -20,7 +20,8 @@ Also reported on the same JSON line:
                 prefix of steps, single thread
   parity        GPU vs oracle after the same prefix (relative L2)
   extras        complex128 throughput; the unsplit RK4 and adaptive Dormand-Prince
-                5(4) integrators; the perfectly matched layer; batched
+                5(4) integrators; the perfectly matched layer; Eq. 1's general
+                operator sum and Kerr responses; batched
                 photonic-crystal-fibre mode vs
                 per-instance plain launches; checkpointed adjoint vs forward;
                 the 1M-vertex vortex launch with the beta4 L^2 term
@@ -272,6 +273,10 @@ def main():
             extras["pml"] = bench_pml(api, w, torch, dev, tdt, min(args.steps, 2000))
         except Exception as e:  # noqa: BLE001
             extras["pml"] = {"error": repr(e)}
+        try:
+            extras["general"] = bench_general(api, w, torch, dev, tdt, min(args.steps, 1000))
+        except Exception as e:  # noqa: BLE001
+            extras["general"] = {"error": repr(e)}
         try:
             extras["conditioning"] = bench_conditioning(api, w, torch, dev, tdt, args.steps)
         except Exception as e:  # noqa: BLE001
@@ -528,6 +533,37 @@ def bench_pml(api, w, torch, dev, tdt, steps):
         del m
     log(f"[bench] PML: {out['pml']['ms_per_step'] * 1e3:.2f} us per step vs absorber "
         f"{out['absorber']['ms_per_step'] * 1e3:.2f} us (one-kernel step)")
+    return out
+
+
+def bench_general(api, w, torch, dev, tdt, steps):
+    """Eq. 1 in full on the step-index mesh (complex64, five-kernel path): terms up to
+    p4 L^4 (p2..p4 = 1e-9, -1e-12, 1e-16, small enough to keep the configured dz stable)
+    with the Kerr response, and the saturable response (I_s = 1) alone, against the same
+    five-kernel path with the plain operator."""
+    out = {}
+    cases = (("plain", {}), ("L4_sum", {"beta4": 1e-9, "p3": -1e-12, "p4": 1e-16}),
+             ("saturable", {"response": "saturable", "response_param": 1.0}))
+    for name, kw in cases:
+        m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype="c64", p1=w.p1, **kw)
+        m.tuning = {"fused": 0}
+        u0 = torch.from_numpy(w.u0).to(dev, tdt["c64"])
+        f = u0.clone()
+        m.propagate(f, w.dz, 20, w.gamma)
+        f = u0.clone()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        m.propagate(f, w.dz, steps, w.gamma)
+        e1.record()
+        torch.cuda.synchronize()
+        m.check_finite()
+        ms = e0.elapsed_time(e1)
+        out[name] = {"value": w.mesh.n_vert * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                     "rho_dz": m.spectral_radius() * w.dz}
+        del m
+    log("[bench] five-kernel path, us per step: " +
+        ", ".join(f"{k} {v['ms_per_step'] * 1e3:.2f}" for k, v in out.items()))
     return out
 
 
