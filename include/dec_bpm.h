@@ -372,7 +372,7 @@ enum {
   DEC_BPM_K_TILE_A = 3,   /* fused tile kernel: stage 4 + Kerr/absorber + stage 1 */
   DEC_BPM_K_TILE_B = 4,   /* fused tile kernel: stages 2 + 3                      */
   DEC_BPM_K_STEP = 5,     /* one-kernel z step: four stages + Kerr/absorber       */
-  DEC_BPM_K_PERSIST = 6,  /* persistent launch: time and bytes per z step         */
+  DEC_BPM_K_PERSIST = 6,  /* persistent launch of max(reps, 2000) steps: per step */
   DEC_BPM_K_UNSPLIT = 7,  /* one unsplit RK4 step (dec_bpm_propagate_unsplit)     */
   DEC_BPM_K_DP5 = 8,      /* one adaptive Dormand-Prince trial (seven stages)     */
   DEC_BPM_K_MODE = 9,     /* one nonlinear mode iteration (dec_bpm_find_mode)     */

@@ -1548,18 +1548,19 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       if (bytes) bytes[kind] = 0.0;
       continue;
     }
-    if (kind == DEC_BPM_K_PERSIST) {  // one launch of `reps` steps, time per step
+    if (kind == DEC_BPM_K_PERSIST) {  // one launch of at least 2000 steps, time per step
       const TileOps<T> sp = E.stp.template ops<T>();
+      const int steps = std::max(reps, 2000);  // the launch's fixed cost spread thin, as in a long propagate
       HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, 2, E.spin_limit, dz, gamma,
                                E.sblock(), st));  // warm-up
       HIP_OK(hipEventRecord(e0, st));
-      HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, reps, E.spin_limit, dz,
+      HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, steps, E.spin_limit, dz,
                                gamma, E.sblock(), st));
       HIP_OK(hipEventRecord(e1, st));
       HIP_OK(hipEventSynchronize(e1));
       float t = 0;
       HIP_OK(hipEventElapsedTime(&t, e0, e1));
-      if (ms) ms[kind] = double(t) / reps;
+      if (ms) ms[kind] = double(t) / steps;
       if (bytes) bytes[kind] = by[kind];
       continue;
     }
