@@ -20,7 +20,8 @@ Also reported on the same JSON line:
                 prefix of steps, single thread
   parity        GPU vs oracle after the same prefix (relative L2)
   extras        complex128 throughput; the unsplit RK4 and adaptive Dormand-Prince
-                5(4) integrators; the perfectly matched layer; Eq. 1's general
+                5(4) integrators; the soliton-launch mode solver; the perfectly
+                matched layer; Eq. 1's general
                 operator sum and Kerr responses; batched
                 photonic-crystal-fibre mode vs
                 per-instance plain launches; checkpointed adjoint vs forward;
@@ -273,6 +274,10 @@ def main():
             extras["pml"] = bench_pml(api, w, torch, dev, tdt, min(args.steps, 2000))
         except Exception as e:  # noqa: BLE001
             extras["pml"] = {"error": repr(e)}
+        try:
+            extras["mode_solver"] = bench_mode(api, w, torch, dev, tdt)
+        except Exception as e:  # noqa: BLE001
+            extras["mode_solver"] = {"error": repr(e)}
         try:
             extras["general"] = bench_general(api, w, torch, dev, tdt, min(args.steps, 1000))
         except Exception as e:  # noqa: BLE001
@@ -564,6 +569,35 @@ def bench_general(api, w, torch, dev, tdt, steps):
         del m
     log("[bench] five-kernel path, us per step: " +
         ", ".join(f"{k} {v['ms_per_step'] * 1e3:.2f}" for k, v in out.items()))
+    return out
+
+
+def bench_mode(api, w, torch, dev, tdt):
+    """The soliton-launch mode solver on the step-index mesh (power 4, dtau = 2/rho): time per
+    iteration over 2000 fixed iterations, and a complex128 solve to r <= 1e-6 |mu|."""
+    out = {}
+    for dt in ("c64", "c128"):
+        m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=dt, p1=w.p1, beta4=w.beta4)
+        m.autotune(w.dz, w.gamma)
+        u0 = torch.from_numpy(w.u0).to(dev, tdt[dt])
+        dtau = 2.0 / m.spectral_radius()
+        f = u0.clone()
+        m.find_mode(f, 4.0, dtau, w.gamma, tol=0.0, max_iter=20)
+        f = u0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.find_mode(f, 4.0, dtau, w.gamma, tol=0.0, max_iter=2000)
+        sec = time.perf_counter() - t0
+        r = {"us_per_iteration": sec / 2000 * 1e6, "kernel_us": m.time_kernels(w.dz, w.gamma, reps=50)["mode"]["ms"] * 1e3}
+        if dt == "c128":
+            f = u0.clone()
+            t0 = time.perf_counter()
+            st = m.find_mode(f, 4.0, dtau, w.gamma, tol=1e-6, max_iter=400000)
+            r["solve"] = {**st, "seconds": time.perf_counter() - t0, "tol": 1e-6}
+        out[dt] = r
+        del m
+    log(f"[bench] mode solver: {out['c64']['us_per_iteration']:.1f} us per iteration (c64), "
+        f"{out['c128']['us_per_iteration']:.1f} (c128); c128 solve {out['c128']['solve']}")
     return out
 
 

@@ -124,6 +124,11 @@ struct Engine {
   int32_t* nb_ptr = nullptr;
   int32_t* nb_list = nullptr;
   int32_t* pflags = nullptr;
+  // complex128: the step tiles are cut for the one-kernel step's 100 KiB of LDS
+  // (512 owned rows), too many to be resident at once; the persistent kernel
+  // then gets tiles of its own (1024 owned rows, up to 150 KiB of LDS)
+  DevTiles pst;
+  bool pst_own = false;
   int spin_limit = 1 << 20;
   int persist_cap_block = -1, persist_cap = 0;  // resident workgroups at that block size
   void* psi2 = nullptr;
@@ -183,6 +188,15 @@ struct Engine {
     const int b = std::max(tile_block, ((mc + 1) / 2 + 63) / 64 * 64);
     if (b >= mc) return std::min(1024, b);
     return std::min(dtype == DEC_BPM_C128 ? 640 : 1024, b);
+  }
+
+  const DevTiles& ptiles() const { return pst_own ? pst : stp; }
+  // threads per workgroup of the persistent kernel: as the step kernels on the
+  // step tiles; on its own tiles at most two slots per thread of 1024
+  int pblock() const {
+    if (!pst_own) return sblock();
+    const int mc = pst.max_compute;
+    return std::min(1024, std::max(tile_block, ((mc + 1) / 2 + 63) / 64 * 64));
   }
 
   // threads per tile workgroup: the requested count, raised so that no thread
@@ -521,6 +535,17 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
     break;
   }
   if (!built || b4 || batched || alwi) return;  // the persistent kernel: real one-field operators only
+  if (sizeof(T) == 8) {
+    HostTiles H2;
+    for (int ts = 1024; ts > E.step_tile; ts /= 2) {  // larger than the step tiles: fewer to keep resident
+      if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H2, true, E.sort_ring0)) continue;
+      if (size_t(H2.max_slots) * 7 * sizeof(T) > 150 * 1024 || H2.max_compute > 2048) continue;
+      upload_tiles<T>(E, H2, dec, E.n_rows, E.pst);
+      E.pst_own = true;
+      H = std::move(H2);
+      break;
+    }
+  }
   // tiles owning the halo rows of each tile (the persistent kernel's wait set)
   std::vector<int32_t> ptr(H.nt + 1, 0), list, seen(H.nt, -1);
   bool fits = true;
@@ -838,12 +863,12 @@ static bool use_step_adjoint(const Engine& E) {
 template <typename T>
 static bool persist_fits(Engine& E) {
   if (!E.has_persist) return false;
-  const int b = E.sblock();
+  const int b = E.pblock();
   if (E.persist_cap_block != b) {
-    E.persist_cap = persist_capacity<T>(E.ops<T>(), E.stp.template ops<T>(), b);
+    E.persist_cap = persist_capacity<T>(E.ops<T>(), E.ptiles().template ops<T>(), b);
     E.persist_cap_block = b;
   }
-  const int64_t grid = E.xcd ? (int64_t(E.stp.n_tiles) + 7) / 8 * 8 : E.stp.n_tiles;  // as launched
+  const int64_t grid = E.xcd ? (int64_t(E.ptiles().n_tiles) + 7) / 8 * 8 : E.ptiles().n_tiles;  // as launched
   return E.persist_cap >= grid;
 }
 
@@ -978,8 +1003,8 @@ static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipSt
       const int32_t k = int32_t(std::min(chunk, count - done));
       void* b0 = state_before(E, 3, done);
       void* b1 = b0 == E.psi ? E.psi2 : E.psi;
-      hipError_t e = launch_persist<T>(d, E.stp.template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, E.pflags, E.flag, k,
-                                       E.spin_limit, dz, gamma, E.sblock(), st);
+      hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, E.pflags, E.flag,
+                                       k, E.spin_limit, dz, gamma, E.pblock(), st);
       if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     }
     return state_before(E, 3, count);
@@ -1549,13 +1574,13 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       continue;
     }
     if (kind == DEC_BPM_K_PERSIST) {  // one launch of at least 2000 steps, time per step
-      const TileOps<T> sp = E.stp.template ops<T>();
+      const TileOps<T> sp = E.ptiles().template ops<T>();
       const int steps = std::max(reps, 2000);  // the launch's fixed cost spread thin, as in a long propagate
       HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, 2, E.spin_limit, dz, gamma,
-                               E.sblock(), st));  // warm-up
+                               E.pblock(), st));  // warm-up
       HIP_OK(hipEventRecord(e0, st));
       HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, steps, E.spin_limit, dz,
-                               gamma, E.sblock(), st));
+                               gamma, E.pblock(), st));
       HIP_OK(hipEventRecord(e1, st));
       HIP_OK(hipEventSynchronize(e1));
       float t = 0;

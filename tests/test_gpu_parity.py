@@ -483,6 +483,31 @@ def test_general_operator_sum_and_responses_match_oracle(dtype, response, param,
     assert e.value.code == B.EINVAL
 
 
+def test_full_size_pml_and_mode_iterations():
+    """The full 249k-vertex step-index mesh in the bench's configurations of the layer
+    (one-kernel step with complex weights, 5 steps) and of the mode solver (10 iterations),
+    complex64, against the oracle."""
+    w = case("step_index")
+    say("full size pml / mode", w.mesh.n_vert)
+    pml = (35.0, 40.0, 1.0)
+    ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, None, pml=pml)
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, None, dtype="c64", pml=pml)
+    f = dev(w.u0, "c64")
+    m.propagate(f, w.dz, 5, w.gamma)
+    err = rel(host(f), S.propagate(w.u0, ops, w.dz, 5, w.gamma))
+    say("  pml rel err", err)
+    assert err < 1e-5
+    ops = oracle_ops(w)
+    m = lib_mesh(w, "c64")
+    dtau = 2.0 / m.spectral_radius()
+    f = dev(w.u0, "c64")
+    st = m.find_mode(f, 4.0, dtau, w.gamma, tol=0.0, max_iter=10)
+    ref, info = SO.find_mode(w.u0, ops, 4.0, dtau, w.gamma, tol=0.0, max_iter=10)
+    err = rel(host(f), ref)
+    say("  mode rel err", err, st["mu"], info["mu"])
+    assert err < 1e-5 and abs(st["mu"] - info["mu"]) < 1e-5 * abs(info["mu"])
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_step_index_full_size_prefix(dtype):
     """The full 250k-vertex step-index workload, 20 steps, in the bench's launch configuration."""
