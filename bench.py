@@ -68,6 +68,22 @@ _DOMINANT = {0: ("stage", "k_stage (RK4 stage: L gather + stage update)", 4),
                             "operator rows in registers; time and algorithmic bytes per z step)", 1)}
 
 
+def oracle_timed(fn):
+    """Run an oracle call single-threaded; return (result, seconds)."""
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        out = fn()
+        return out, time.perf_counter() - t0
+
+
+def kernel_roofline(k):
+    """HBM roofline of one timed kernel class: algorithmic bytes per launch / launch time."""
+    gbps = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
+    return {"kernel_us": k["ms"] * 1e3, "GBps": gbps, "frac": gbps / 8000.0}
+
+
 def dominant_kernel_roofline(mode, kt):
     cls, name, per_step = _DOMINANT[int(mode)]
     k = kt[cls]
@@ -271,15 +287,15 @@ def main():
         except Exception as e:  # noqa: BLE001
             extras["adaptive_dp54"] = {"error": repr(e)}
         try:
-            extras["pml"] = bench_pml(api, w, torch, dev, tdt, min(args.steps, 2000))
+            extras["pml"] = bench_pml(api, w, torch, dev, tdt, min(args.steps, 2000), not args.no_cpu)
         except Exception as e:  # noqa: BLE001
             extras["pml"] = {"error": repr(e)}
         try:
-            extras["mode_solver"] = bench_mode(api, w, torch, dev, tdt)
+            extras["mode_solver"] = bench_mode(api, w, torch, dev, tdt, not args.no_cpu)
         except Exception as e:  # noqa: BLE001
             extras["mode_solver"] = {"error": repr(e)}
         try:
-            extras["general"] = bench_general(api, w, torch, dev, tdt, min(args.steps, 1000))
+            extras["general"] = bench_general(api, w, torch, dev, tdt, min(args.steps, 1000), not args.no_cpu)
         except Exception as e:  # noqa: BLE001
             extras["general"] = {"error": repr(e)}
         try:
@@ -453,13 +469,15 @@ def bench_unsplit(api, w, torch, dev, tdt, steps, with_oracle):
     kt = m.time_kernels(w.dz, w.gamma, reps=100)["unsplit"]
     res = {"value": w.mesh.n_vert * steps / (ms * 1e-3), "unit": "vertex z-steps/s", "ms_per_step": ms / steps,
            "steps": steps, "kernel_us": kt["ms"] * 1e3, "kernel_GBps": kt["bytes"] / (kt["ms"] * 1e-3) / 1e9,
+           "roofline": kernel_roofline(kt),
            "rel_l2_vs_split_scheme_full_length": split_dist, "tuning": m.tuning}
     if with_oracle:
         from oracle import dec, unsplit
 
         ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, beta4=w.beta4)
         n = 40
-        ref = unsplit.propagate_rk4(w.u0, ops, w.dz, n, w.gamma)
+        ref, sec = oracle_timed(lambda: unsplit.propagate_rk4(w.u0, ops, w.dz, n, w.gamma))
+        res["oracle"] = {"us_per_step": sec / n * 1e6, "cores": 1}
         h = u0.clone()
         m.propagate_unsplit(h, w.dz, n, w.gamma)
         got = h.cpu().numpy().astype(np.complex128)
@@ -495,12 +513,15 @@ def bench_adaptive(api, w, torch, dev, tdt, with_oracle):
         r = {"rtol": rtol, "atol": atol, **st, "seconds": sec,
              "value": w.mesh.n_vert * st["accepted"] / sec, "unit": "vertex z-steps/s (accepted steps)",
              "us_per_attempt": sec / attempts * 1e6, "trial_kernel_us": kt["ms"] * 1e3,
+             "roofline": kernel_roofline(kt),
              "trial_kernel_GBps": kt["bytes"] / (kt["ms"] * 1e-3) / 1e9}
         if with_oracle:
             from oracle import dec, unsplit
 
             ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, beta4=w.beta4)
-            ref, rs = unsplit.propagate_dp54(w.u0, ops, 4 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
+            (ref, rs), sec_o = oracle_timed(
+                lambda: unsplit.propagate_dp54(w.u0, ops, 4 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol))
+            r["oracle"] = {"us_per_attempt": sec_o / (rs["accepted"] + rs["rejected"]) * 1e6, "cores": 1}
             g = u0.clone()
             sg = m.propagate_adaptive(g, 4 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
             got = g.cpu().numpy().astype(np.complex128)
@@ -514,10 +535,13 @@ def bench_adaptive(api, w, torch, dev, tdt, with_oracle):
     return out
 
 
-def bench_pml(api, w, torch, dev, tdt, steps):
+def bench_pml(api, w, torch, dev, tdt, steps, with_oracle):
     """The step-index launch with a perfectly matched layer on 35 < r < 40 (sigma_max 1) in
     place of the absorber, complex64, one-kernel step with complex L weights, against the
-    same step with the absorber."""
+    same step with the absorber; parity with the oracle's split scheme on the stretched
+    operators after 5 steps, the oracle timed beside it."""
+    import numpy as np
+
     out = {}
     for name, pml, ab in (("pml", (35.0, 40.0, 1.0), None), ("absorber", None, w.absorber)):
         m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, ab, dtype="c64", p1=w.p1, pml=pml)
@@ -534,14 +558,31 @@ def bench_pml(api, w, torch, dev, tdt, steps):
         torch.cuda.synchronize()
         m.check_finite()
         ms = e0.elapsed_time(e1)
-        out[name] = {"value": w.mesh.n_vert * steps / (ms * 1e-3), "ms_per_step": ms / steps, "tuning": m.tuning}
+        # the step kernel's algorithmic bytes plus the imaginary L weights of the layer
+        kt = m.time_kernels(w.dz, w.gamma, reps=50)["step"]
+        if pml is not None:
+            kt = dict(kt, bytes=kt["bytes"] + 6 * w.mesh.n_vert * 4)
+        out[name] = {"value": w.mesh.n_vert * steps / (ms * 1e-3), "ms_per_step": ms / steps, "tuning": m.tuning,
+                     "roofline": kernel_roofline(kt)}
+        if with_oracle and pml is not None:
+            from oracle import dec, stepper
+
+            ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, None, p1=w.p1, pml=pml)
+            ref, sec = oracle_timed(lambda: stepper.propagate(w.u0, ops, w.dz, 5, w.gamma))
+            g = u0.clone()
+            m.propagate(g, w.dz, 5, w.gamma)
+            got = g.cpu().numpy().astype(np.complex128)
+            out[name]["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                                   "steps": 5}
+            out[name]["oracle"] = {"us_per_step": sec / 5 * 1e6, "cores": 1}
         del m
     log(f"[bench] PML: {out['pml']['ms_per_step'] * 1e3:.2f} us per step vs absorber "
-        f"{out['absorber']['ms_per_step'] * 1e3:.2f} us (one-kernel step)")
+        f"{out['absorber']['ms_per_step'] * 1e3:.2f} us (one-kernel step), parity "
+        f"{out['pml'].get('parity', {}).get('rel_l2_vs_oracle')}")
     return out
 
 
-def bench_general(api, w, torch, dev, tdt, steps):
+def bench_general(api, w, torch, dev, tdt, steps, with_oracle):
     """Eq. 1 in full on the step-index mesh (complex64, five-kernel path): terms up to
     p4 L^4 (p2..p4 = 1e-9, -1e-12, 1e-16, small enough to keep the configured dz stable)
     with the Kerr response, and the saturable response (I_s = 1) alone, against the same
@@ -566,13 +607,28 @@ def bench_general(api, w, torch, dev, tdt, steps):
         ms = e0.elapsed_time(e1)
         out[name] = {"value": w.mesh.n_vert * steps / (ms * 1e-3), "ms_per_step": ms / steps,
                      "rho_dz": m.spectral_radius() * w.dz}
+        if with_oracle and name != "plain":
+            import numpy as np
+
+            from oracle import dec, stepper
+
+            okw = {"beta4": kw.get("beta4", 0.0), "p3": kw.get("p3", 0.0), "p4": kw.get("p4", 0.0),
+                   "nl_kind": kw.get("response", "kerr"), "nl_param": kw.get("response_param", 0.0)}
+            ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, **okw)
+            ref, sec = oracle_timed(lambda: stepper.propagate(w.u0, ops, w.dz, 5, w.gamma))
+            g = u0.clone()
+            m.propagate(g, w.dz, 5, w.gamma)
+            got = g.cpu().numpy().astype(np.complex128)
+            out[name]["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                                   "steps": 5}
+            out[name]["oracle"] = {"us_per_step": sec / 5 * 1e6, "cores": 1}
         del m
     log("[bench] five-kernel path, us per step: " +
         ", ".join(f"{k} {v['ms_per_step'] * 1e3:.2f}" for k, v in out.items()))
     return out
 
 
-def bench_mode(api, w, torch, dev, tdt):
+def bench_mode(api, w, torch, dev, tdt, with_oracle):
     """The soliton-launch mode solver on the step-index mesh (power 4, dtau = 2/rho): time per
     iteration over 2000 fixed iterations, and a complex128 solve to r <= 1e-6 |mu|."""
     out = {}
@@ -588,7 +644,22 @@ def bench_mode(api, w, torch, dev, tdt):
         t0 = time.perf_counter()
         m.find_mode(f, 4.0, dtau, w.gamma, tol=0.0, max_iter=2000)
         sec = time.perf_counter() - t0
-        r = {"us_per_iteration": sec / 2000 * 1e6, "kernel_us": m.time_kernels(w.dz, w.gamma, reps=50)["mode"]["ms"] * 1e3}
+        kt = m.time_kernels(w.dz, w.gamma, reps=50)["mode"]
+        r = {"us_per_iteration": sec / 2000 * 1e6, "kernel_us": kt["ms"] * 1e3, "roofline": kernel_roofline(kt)}
+        if with_oracle and dt == "c64":
+            import numpy as np
+
+            from oracle import dec, soliton
+
+            ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, beta4=w.beta4)
+            (ref, info), sec_o = oracle_timed(lambda: soliton.find_mode(w.u0, ops, 4.0, dtau, w.gamma, tol=0.0,
+                                                                        max_iter=10))
+            g = u0.clone()
+            m.find_mode(g, 4.0, dtau, w.gamma, tol=0.0, max_iter=10)
+            got = g.cpu().numpy().astype(np.complex128)
+            r["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                           "iterations": 10, "mu_oracle": info["mu"]}
+            r["oracle"] = {"us_per_iteration": sec_o / 10 * 1e6, "cores": 1}
         if dt == "c128":
             f = u0.clone()
             t0 = time.perf_counter()
