@@ -258,8 +258,12 @@ def main():
         m.propagate(g, w.dz, n_cpu, w.gamma)
         got = g.cpu().numpy().astype(np.complex128)
         err = float(np.linalg.norm(got - psi) / np.linalg.norm(psi))
+        from oracle import diagnostics
+
+        err_h0 = float(np.sqrt(np.sum(ops.H0 * np.abs(got - psi) ** 2) / np.sum(ops.H0 * np.abs(psi) ** 2)))
         out["parity"] = {"rel_l2_vs_oracle": err, "steps": n_cpu, "gate": 1e-4 if args.dtype == "c64" else 1e-10,
-                         "pass": err < (1e-4 if args.dtype == "c64" else 1e-10)}
+                         "pass": err < (1e-4 if args.dtype == "c64" else 1e-10),
+                         "rel_l2_h0_weighted": err_h0, "e_rel_eq15": diagnostics.e_rel(got, psi)}
         log(f"[bench] parity after {n_cpu} steps: rel L2 {err:.3e}")
 
     # ---- extras ----
