@@ -63,9 +63,13 @@ def build(verbose: bool = False) -> str:
     jobs = []
     objs = []
     for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        jobs.append([hipcc, *HIPCC_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        # the kernels compile as two objects in parallel: complex64 (with the
+        # precision-independent launchers) and complex128
+        parts = [("_f", ["-DDECBPM_PART=1"]), ("_d", ["-DDECBPM_PART=2"])] if src == "kernels.hip" else [("", [])]
+        for suffix, defs in parts:
+            obj = os.path.join(BUILD, src.replace(".hip", suffix + ".o"))
+            jobs.append([hipcc, *HIPCC_FLAGS, *defs, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
+            objs.append(obj)
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
         jobs.append(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", *inc, "-c", os.path.join(CSRC, src), "-o", obj])

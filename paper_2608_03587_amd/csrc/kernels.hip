@@ -13,6 +13,13 @@
 
 #include "kernels.hpp"
 
+// The build compiles this file twice in parallel: DECBPM_PART 1 emits the
+// complex64 instantiations and the precision-independent launchers, 2 the
+// complex128 ones (3, the default, emits everything in one object).
+#ifndef DECBPM_PART
+#define DECBPM_PART 3
+#endif
+
 namespace decbpm {
 
 namespace {
@@ -3087,10 +3094,12 @@ void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, v
 #undef DECBPM_STEP
 }
 
+#if DECBPM_PART & 1
 void launch_dp5_init(Dp5Ctl* ctl, uint32_t* arrivals, double z_end, double h0, int64_t max_attempts, double facmax,
                      hipStream_t st) {
   hipLaunchKernelGGL(k_dp5_init, dim3(1), dim3(64), 0, st, ctl, arrivals, z_end, h0, max_attempts, facmax);
 }
+#endif
 
 template <typename T>
 void launch_dp5(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp5Ctl* ctl, double* partial,
@@ -3119,10 +3128,12 @@ void launch_dp5(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp
 #undef DECBPM_DP5
 }
 
+#if DECBPM_PART & 1
 void launch_mode_init(ModeCtl* ctl, uint32_t* arrivals, const double* pw, double power, double tol, int64_t max_iter,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_mode_init, dim3(1), dim3(64), 0, st, ctl, arrivals, pw, power, tol, max_iter);
 }
+#endif
 
 template <typename T>
 void launch_scale(int64_t n, void* x, double s, int block, hipStream_t st) {
@@ -3387,13 +3398,17 @@ void launch_set_v(int64_t n, const T* v0, const double* dn, const int32_t* perm,
   hipLaunchKernelGGL((k_set_v<T>), dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, v0, dn, perm, v);
 }
 
+#if DECBPM_PART & 1
 void launch_gdn_out(int64_t n, const int32_t* perm, const double* gdn, double* out, int block, hipStream_t st) {
   hipLaunchKernelGGL(k_gdn_out, dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, perm, gdn, out);
 }
+#endif
 
+#if DECBPM_PART & 1
 void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, x);
 }
+#endif
 
 #define DECBPM_INSTANTIATE(T)                                                                                     \
   template void launch_stage<T>(const DevOps<T>&, const void*, const void*, const void*, void*, double, void*,     \
@@ -3451,7 +3466,11 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                     const void*, const void*, const void*, const void*, void*, void*, double*,   \
                                     double, double, double, int, hipStream_t);
 
+#if DECBPM_PART & 1
 DECBPM_INSTANTIATE(float)
+#endif
+#if DECBPM_PART & 2
 DECBPM_INSTANTIATE(double)
+#endif
 
 }  // namespace decbpm
