@@ -508,6 +508,42 @@ def test_full_size_pml_and_mode_iterations():
     assert err < 1e-5 and abs(st["mu"] - info["mu"]) < 1e-5 * abs(info["mu"])
 
 
+def test_vortex_beta4_full_size_prefix():
+    """The full 1M-vertex vortex launch with the beta4 L^2 term in the bench's launch
+    configuration (autotuned: the beta4 one-kernel step), complex64, 3 steps vs the oracle."""
+    w = case("vortex")
+    say("vortex full size", w.mesh.n_vert)
+    m = lib_mesh(w, "c64")
+    m.autotune(w.dz, w.gamma)
+    f = dev(w.u0, "c64")
+    m.propagate(f, w.dz, 3, w.gamma)
+    ref = S.propagate(w.u0, oracle_ops(w), w.dz, 3, w.gamma)
+    err = rel(host(f), ref)
+    say("  rel err", err, m.tuning)
+    assert err < 1e-5
+
+
+def test_batched_full_size_prefix():
+    """The full batched workload (8 PCF meshes of 19k-198k vertices x 32 fields) in the bench's
+    launch configuration (autotuned), complex64, 3 steps: sampled fields of the smallest and
+    largest mesh against the oracle."""
+    ws = W.batched_pcf()
+    F = ws[0].u0.shape[0]
+    say("batched full size", [x.mesh.n_vert for x in ws], F)
+    meshes = [lib_mesh(x, "c64") for x in ws]
+    batch = api.Batch(meshes, F)
+    packed = batch.pack([dev(x.u0, "c64") for x in ws])
+    batch.autotune(ws[0].dz, 1.0)
+    batch.propagate(packed, ws[0].dz, 3, 1.0)
+    outs = batch.unpack(packed)
+    for k, f in ((0, 0), (len(ws) - 1, F - 1)):
+        x = ws[k]
+        ref = S.propagate(x.u0[f], oracle_ops(x), x.dz, 3, 1.0)
+        err = rel(host(outs[k][f].contiguous()), ref)
+        say("  mesh", k, "field", f, "rel err", err, batch.tuning)
+        assert err < 1e-5
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_step_index_full_size_prefix(dtype):
     """The full 250k-vertex step-index workload, 20 steps, in the bench's launch configuration."""
