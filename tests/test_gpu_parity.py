@@ -743,6 +743,48 @@ def test_autograd_function_and_finite_differences():
         assert abs(float(fd_n - an_n)) < 1e-6 * abs(float(fd_n))
 
 
+def test_adjoint_full_size_directional_derivatives():
+    """The full 498k-vertex multimode-fibre adjoint workload in the bench's launch configuration
+    (autotuned), 40 steps with 7-step checkpoints: the adjoint's field and index gradients
+    against central differences of the library's own forward (complex128), and the complex64
+    gradients against the complex128 ones to 1e-4 (the workload's finite-difference bar)."""
+    w = case("adjoint")
+    n = 40
+    say("adjoint full size", w.mesh.n_vert, n)
+    grads = {}
+    for dtype in ("c128", "c64"):
+        m = lib_mesh(w, dtype)
+        m.autotune(w.dz, w.gamma)
+        tgt = dev(w.extra["target"], dtype)
+        h0 = torch.from_numpy(m.export_operators()["h0"]).to(DEV)
+
+        def J(u0, dn):
+            u = api.propagate_with_grad(m, u0, dn, w.dz, n, w.gamma, every=7)
+            c = (h0 * tgt.conj() * u).sum()
+            return (c.conj() * c).real
+
+        u0 = dev(w.u0, dtype).requires_grad_(True)
+        dn = torch.from_numpy(w.extra["dn"]).to(DEV).requires_grad_(True)
+        J(u0, dn).backward()
+        grads[dtype] = (u0.grad.detach().to(torch.complex128), dn.grad.detach())
+        if dtype == "c128":
+            rng = np.random.default_rng(4)
+            with torch.no_grad():
+                d = dev(rng.normal(size=m.n_vert) + 1j * rng.normal(size=m.n_vert), dtype)
+                e = torch.from_numpy(rng.normal(size=m.n_vert)).to(DEV)
+                fd_u = (J(u0 + 1e-6 * d, dn) - J(u0 - 1e-6 * d, dn)) / 2e-6
+                an_u = (u0.grad.conj() * d).real.sum()
+                fd_n = (J(u0, dn + 1e-4 * e) - J(u0, dn - 1e-4 * e)) / 2e-4
+                an_n = (dn.grad * e).sum()
+            say("  fd", float(fd_u), float(an_u), float(fd_n), float(an_n))
+            assert abs(float(fd_u - an_u)) < 1e-6 * abs(float(fd_u))
+            assert abs(float(fd_n - an_n)) < 1e-5 * abs(float(fd_n))
+    gu = rel(grads["c64"][0].cpu().numpy(), grads["c128"][0].cpu().numpy())
+    gn = rel(grads["c64"][1].cpu().numpy(), grads["c128"][1].cpu().numpy())
+    say("  c64 vs c128 gradients", gu, gn)
+    assert gu < 1e-4 and gn < 1e-4
+
+
 def test_autotune_keeps_results():
     w = case("plain_small")
     m = lib_mesh(w, "c64")
