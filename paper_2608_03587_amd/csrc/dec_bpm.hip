@@ -131,6 +131,7 @@ struct Engine {
   bool pst_own = false;
   int spin_limit = 1 << 20;
   int persist_cap_block = -1, persist_cap = 0;  // resident workgroups at that block size
+  int persist_cap_block_u = -1, persist_cap_u = 0;  // the same for the unsplit RK4 body
   void* psi2 = nullptr;
   // adaptive Dormand-Prince runs: seven-ring tiles built at the first call from
   // the device-order adjacency kept on the host, the controller state and the
@@ -859,17 +860,20 @@ static bool use_step_adjoint(const Engine& E) {
   return E.has_step && E.fused >= 2 && size_t(E.stp.max_slots) * 3 * 2 * sizeof(T) <= 64 * 1024;
 }
 
-// Persistent stepping needs every step tile resident at once.
+// Persistent stepping needs every step tile resident at once (body 0: the
+// split step, 1: the unsplit RK4 step).
 template <typename T>
-static bool persist_fits(Engine& E) {
+static bool persist_fits(Engine& E, int body = 0) {
   if (!E.has_persist) return false;
   const int b = E.pblock();
-  if (E.persist_cap_block != b) {
-    E.persist_cap = persist_capacity<T>(E.ops<T>(), E.ptiles().template ops<T>(), b);
-    E.persist_cap_block = b;
+  int& cap_block = body ? E.persist_cap_block_u : E.persist_cap_block;
+  int& cap = body ? E.persist_cap_u : E.persist_cap;
+  if (cap_block != b) {
+    cap = persist_capacity<T>(E.ops<T>(), E.ptiles().template ops<T>(), b, body);
+    cap_block = b;
   }
   const int64_t grid = E.xcd ? (int64_t(E.ptiles().n_tiles) + 7) / 8 * 8 : E.ptiles().n_tiles;  // as launched
-  return E.persist_cap >= grid;
+  return cap >= grid;
 }
 
 template <typename T>
@@ -997,6 +1001,20 @@ template <typename T>
 static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st, int mode = -1) {
   const DevOps<T> d = E.ops<T>();
   if (mode < 0) mode = mode_of<T>(E);
+  // unsplit RK4 on the resident tiles; not on complex128's own persistent tiles, where the
+  // unsplit body's register spills make it slower than one tile kernel per step
+  if (mode == 5 && E.fused == 3 && !E.pst_own && persist_fits<T>(E, 1)) {
+    const int64_t chunk = int64_t(1) << 30;
+    for (int64_t done = 0; done < count; done += chunk) {
+      const int32_t k = int32_t(std::min(chunk, count - done));
+      void* b0 = state_before(E, 5, done);
+      void* b1 = b0 == E.psi ? E.psi2 : E.psi;
+      hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, E.pflags, E.flag,
+                                       k, E.spin_limit, dz, gamma, E.pblock(), st, 1);
+      if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+    }
+    return state_before(E, 5, count);
+  }
   if (mode == 3) {
     const int64_t chunk = int64_t(1) << 30;  // steps per launch (the parity of each chunk start is even)
     for (int64_t done = 0; done < count; done += chunk) {

@@ -2488,7 +2488,10 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
 // wait, so no L2 write-back or invalidate is needed.  Each wait is bounded: after
 // spin_limit polls the tile sets bit 1 of *status and leaves, and its
 // neighbours then time out in turn, so every workgroup exits.
-template <typename T, int KMAX, bool DEC, int J, int LS>
+// BODY 0: the merged split step; BODY 1: one unsplit classical RK4 step of the
+// whole right-hand side (the stage inputs and their |.|^2 double-buffered in
+// the same LDS; the owned state and its |.|^2 written back after the step).
+template <typename T, int KMAX, bool DEC, int J, int LS, int BODY>
 __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, const int32_t* __restrict__ nb_ptr,
                                                   const int32_t* __restrict__ nb_list, typename CT<T>::C* buf0,
                                                   typename CT<T>::C* buf1, int32_t* flags, int32_t* status,
@@ -2504,6 +2507,10 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
   C* base = reinterpret_cast<C*>(smem);
   const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS};
   T* S = reinterpret_cast<T*>(base + 3 * MS);
+  C* UA = base;  // BODY 1: stage buffers A, B and their |.|^2
+  C* UB = base + MS;
+  T* USA = reinterpret_cast<T*>(base + 2 * MS);
+  T* USB = USA + MS;
   StepTile<T, KMAX, DEC, J> st;
   st.init(d, tl, tile);
   int32_t pr[LS];  // rows of this thread's state slots
@@ -2551,14 +2558,30 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
       if (pr[l] >= 0 && int(threadIdx.x) + l * B >= first) pv[l] = coherent_load(src + pr[l]);
 #pragma unroll
     for (int l = 0; l < LS; ++l)
-      if (pr[l] >= 0 && int(threadIdx.x) + l * B >= first) P.put(threadIdx.x + l * B, pv[l]);
+      if (pr[l] >= 0 && int(threadIdx.x) + l * B >= first) {
+        if constexpr (BODY == 0) {
+          P.put(threadIdx.x + l * B, pv[l]);
+        } else {
+          UA[threadIdx.x + l * B] = pv[l];
+          USA[threadIdx.x + l * B] = pv[l].x * pv[l].x + pv[l].y * pv[l].y;
+        }
+      }
     __syncthreads();
-    st.step(d, P, X, Y, S, h, h, gamma,
-            [&](int i, int32_t r, const C& v) {
-              coherent_store(dst + r, v);
-              P.put(i, v);  // the next step's owned state
-            },
-            [](int, int32_t, const C&) {});
+    if constexpr (BODY == 0) {
+      st.step(d, P, X, Y, S, h, h, gamma,
+              [&](int i, int32_t r, const C& v) {
+                coherent_store(dst + r, v);
+                P.put(i, v);  // the next step's owned state
+              },
+              [](int, int32_t, const C&) {});
+    } else {
+      // the last stage reads B only, so the owned state can go back into A
+      st.step_unsplit(d, UA, UB, USA, USB, h, gamma, [&](int i, int32_t r, const C& v) {
+        coherent_store(dst + r, v);
+        UA[i] = v;
+        USA[i] = v.x * v.x + v.y * v.y;
+      });
+    }
     wait_stores();
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(flags + tile, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -3252,10 +3275,12 @@ void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_i
 
 // Kernel instance of the persistent step for a tile set and block size.
 template <typename T>
-static const void* persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block) {
+static const void* persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block, int body) {
   const int J = (tl.max_compute + block - 1) / block;
   const bool dec = tl.lmw != nullptr;
-#define DECBPM_PK(KM, DEC, JJ) reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3>)
+#define DECBPM_PK(KM, DEC, JJ)                                                    \
+  (body ? reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 1>)          \
+        : reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0>))
 #define DECBPM_PK_J(KM, DEC) return J <= 1 ? DECBPM_PK(KM, DEC, 1) : DECBPM_PK(KM, DEC, 2);
   if (kmax_of(d.wmax) == 8) {
     if (dec) { DECBPM_PK_J(8, true) } else { DECBPM_PK_J(8, false) }
@@ -3272,12 +3297,12 @@ size_t persist_lds(const TileOps<T>& tl) {
 }
 
 template <typename T>
-int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block) {
+int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block, int body) {
   if (tl.max_slots > 3 * block || tl.max_compute > 2 * block) return 0;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel<T>(d, tl, block), block,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel<T>(d, tl, block, body), block,
                                                    persist_lds<T>(tl)) != hipSuccess)
     return 0;
   return cus * per_cu;
@@ -3286,7 +3311,7 @@ int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block) {
 template <typename T>
 hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_t* nb_ptr, const int32_t* nb_list,
                           void* buf0, void* buf1, int32_t* flags, int32_t* status, int32_t n_steps,
-                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st) {
+                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st, int body) {
   using C = typename CT<T>::C;
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(tl.n_tiles, 256, 0)), dim3(256), 0, st, int64_t(tl.n_tiles), flags);
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
@@ -3297,7 +3322,7 @@ hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_
   T th = T(h), tg = T(gamma);
   void* args[] = {&dd, &tt, const_cast<int32_t**>(&nb_ptr), const_cast<int32_t**>(&nb_list), &b0, &b1, &flags, &status,
                   &n_steps, &spin_limit, &th, &tg};
-  return hipLaunchCooperativeKernel(persist_kernel<T>(d, tl, block), dim3(g), dim3(block), args,
+  return hipLaunchCooperativeKernel(persist_kernel<T>(d, tl, block, body), dim3(g), dim3(block), args,
                                     unsigned(persist_lds<T>(tl)), st);
 }
 
@@ -3435,7 +3460,7 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   template void launch_set_v<T>(int64_t, const T*, const double*, const int32_t*, T*, int, hipStream_t);          \
   template void launch_step<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double,   \
                                int, hipStream_t);                                                                \
-  template int persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int);                                     \
+  template int persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int, int);                                \
   template void launch_step_b4<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double, \
                                   int, hipStream_t);                                                             \
   template void launch_unsplit<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, int,    \
@@ -3454,7 +3479,7 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                    double, double, int, hipStream_t);                                            \
   template hipError_t launch_persist<T>(const DevOps<T>&, const TileOps<T>&, const int32_t*, const int32_t*, void*, \
                                         void*, int32_t*, int32_t*, int32_t, int32_t, double, double, int,        \
-                                        hipStream_t);                                                            \
+                                        hipStream_t, int);                                                       \
   template void launch_bstage<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*, void*, \
                                  double, void*, double, hipStream_t);                                            \
   template void launch_blap<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, hipStream_t);           \

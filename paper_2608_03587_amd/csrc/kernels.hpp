@@ -264,12 +264,14 @@ void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_i
 // timed out.  Returns the launch status (the launch fails if the tiles cannot
 // all be resident).  persist_capacity: resident workgroups the device holds
 // for this kernel at `block` threads (0 if the tiles do not fit the kernel).
+// body: 0 the merged split step (LIN(h) then NL(h)), 1 one unsplit RK4 step
+// of the whole right-hand side.
 template <typename T>
-int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block);
+int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block, int body = 0);
 template <typename T>
 hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_t* nb_ptr, const int32_t* nb_list,
                           void* buf0, void* buf1, int32_t* flags, int32_t* status, int32_t n_steps,
-                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st);
+                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st, int body = 0);
 
 // out_rec (may be null) receives, for owned rows, y2 (FUSED_S2_S3) or the
 // state before the Kerr substep (S4 kinds): the adjoint's segment recompute.
