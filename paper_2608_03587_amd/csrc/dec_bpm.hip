@@ -132,6 +132,7 @@ struct Engine {
   int spin_limit = 1 << 20;
   int persist_cap_block = -1, persist_cap = 0;  // resident workgroups at that block size
   int persist_cap_block_u = -1, persist_cap_u = 0;  // the same for the unsplit RK4 body
+  int mode_cap_block = -1, mode_cap = 0;            // and for the persistent mode iteration
   void* psi2 = nullptr;
   // adaptive Dormand-Prince runs: seven-ring tiles built at the first call from
   // the device-order adjacency kept on the host, the controller state and the
@@ -1256,7 +1257,7 @@ static ModeResult find_mode_t(Engine& E, void* field, double power, double dtau,
                               int64_t max_iter, hipStream_t st) {
   if (!E.modectl) {
     E.modectl = static_cast<ModeCtl*>(E.dalloc(sizeof(ModeCtl)));
-    E.modepart = static_cast<double*>(E.dalloc(size_t(E.stp.n_tiles) * 4 * sizeof(double)));
+    E.modepart = static_cast<double*>(E.dalloc(size_t(E.stp.n_tiles) * 8 * sizeof(double)));
     E.modearr = static_cast<uint32_t*>(E.dalloc(256));
   }
   const DevOps<T> d = E.ops<T>();
@@ -1268,7 +1269,24 @@ static ModeResult find_mode_t(Engine& E, void* field, double power, double dtau,
   ModeCtl c{};
   int64_t launched = 0;
   int K = 8;
-  for (;;) {
+  // every step tile resident: the whole iteration in one cooperative launch (complex64 tiles)
+  if (E.fused == 3 && E.has_persist && !E.pst_own) {
+    if (E.mode_cap_block != blk) {
+      E.mode_cap = mode_persist_capacity<T>(d, tl, blk);
+      E.mode_cap_block = blk;
+    }
+    const int64_t grid = E.xcd ? (int64_t(tl.n_tiles) + 7) / 8 * 8 : tl.n_tiles;
+    if (E.mode_cap >= grid) {
+      const hipError_t e = launch_mode_persist<T>(d, tl, E.psi, E.psi2, E.modectl, E.modepart, E.pflags, E.flag,
+                                                  E.spin_limit, dtau, gamma, blk, st);
+      if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+      HIP_OK(hipMemcpyAsync(&c, E.modectl, sizeof(ModeCtl), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      if (!c.done) fail(DEC_BPM_EHIP, "mode solver: a tile's wait for the others timed out");
+      launched = max_iter;
+    }
+  }
+  for (; launched < max_iter;) {
     const int64_t left = max_iter - launched;
     if (K > left) {
       for (int64_t k = 0; k < left; ++k)
@@ -1610,7 +1628,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
     if (kind == DEC_BPM_K_MODE) {  // iterations of step dz at power 1, no stopping test
       if (!E.modectl) {
         E.modectl = static_cast<ModeCtl*>(E.dalloc(sizeof(ModeCtl)));
-        E.modepart = static_cast<double*>(E.dalloc(size_t(E.stp.n_tiles) * 4 * sizeof(double)));
+        E.modepart = static_cast<double*>(E.dalloc(size_t(E.stp.n_tiles) * 8 * sizeof(double)));
         E.modearr = static_cast<uint32_t*>(E.dalloc(256));
       }
       launch_diag<T>(d, E.psi, 0.0, E.partials, E.n_red_blocks, E.red_out, st);

@@ -2214,6 +2214,114 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_mode(DevOps<T> d, 
   }
 }
 
+// The mode iteration with every step tile resident (cooperative launch): the
+// iterations of k_mode back to back, each ended by a grid-wide exchange
+// instead of a kernel boundary.  A tile publishes its four sums and its new
+// rows (agent-scope stores, acknowledged), then its iteration counter; it
+// waits for every tile's counter (bounded: status bit 2 and exit), sums all
+// tiles' shares in tile order and takes the stopping decision itself, so
+// every tile reaches the same one; tile 0 keeps the controller state in
+// memory.  The global wait also orders the buffer reuse: x[1 - cur] is only
+// written after every tile has read it as the previous iteration's input,
+// and the shares alternate between two halves of `partial` (8 * n_tiles
+// doubles), so a tile still summing iteration k's shares is never overwritten.
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__(1024) k_mode_persist(DevOps<T> d, TileOps<T> tl, typename CT<T>::C* x0,
+                                                       typename CT<T>::C* x1, ModeCtl* ctl,
+                                                       double* __restrict__ partial, int32_t* flags, int32_t* status,
+                                                       int32_t spin_limit, T h, T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16][4];
+  __shared__ ModeCtl cs;
+  __shared__ int32_t abort_s;
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  const int nw = int(blockDim.x + 63) / 64;
+  C* A = reinterpret_cast<C*>(smem);
+  C* Bv = A + MS;
+  T* SA = reinterpret_cast<T*>(Bv + MS);
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  if (threadIdx.x == 0) cs = *ctl;
+  __syncthreads();
+  for (int32_t it = 0; !cs.done; ++it) {
+    st.opaque_neighbours();
+    const C* in_psi = cs.cur ? x1 : x0;
+    C* out_psi = cs.cur ? x0 : x1;
+    const T sc = T(cs.s);
+    const T mu_prev = T(cs.mu_prev);
+    for (int i = threadIdx.x; i < st.hd[4]; i += blockDim.x) {
+      C v = coherent_load(in_psi + st.slot_row(i));
+      v.x *= sc;
+      v.y *= sc;
+      A[i] = v;
+      SA[i] = v.x * v.x + v.y * v.y;
+    }
+    __syncthreads();
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    st.step_mode(d, A, Bv, SA, h, gamma, mu_prev, acc,
+                 [&](int, int32_t r, const C& v) { coherent_store(out_psi + r, v); });
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_down(acc[c], off, 64);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = acc[c];
+    }
+    __syncthreads();
+    double* half = partial + int64_t(it & 1) * 4 * tl.n_tiles;
+    if (threadIdx.x < 4) {
+      double t = 0.0;
+      for (int w = 0; w < nw; ++w) t += red[w][threadIdx.x];
+      coherent_store(half + 4 * tile + threadIdx.x, t);
+    }
+    wait_stores();  // every wave: its rows and shares acknowledged
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flags + tile, it + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 64) {  // wait for every tile's iteration it
+      bool ok = true;
+      for (int32_t spins = 0;; ++spins) {
+        bool all = true;
+        for (int k = threadIdx.x; k < tl.n_tiles; k += 64)
+          all = all && __hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= it + 1;
+        if (__all(all)) break;
+        if (spins >= spin_limit) {
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (threadIdx.x == 0) {
+        abort_s = ok ? 0 : 1;
+        if (!ok) __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __syncthreads();
+    if (abort_s) return;
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < tl.n_tiles; k += blockDim.x)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[c] += coherent_load(half + 4 * k + c);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      for (int off = 32; off > 0; off >>= 1) t[c] += __shfl_down(t[c], off, 64);
+    __syncthreads();  // red[] reuse
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[threadIdx.x >> 6][c] = t[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double S[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int w = 0; w < nw; ++w)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) S[c] += red[w][c];
+      mode_decide(&cs, S);
+      if (tile == 0) *ctl = cs;
+    }
+    __syncthreads();
+  }
+}
+
 // Starts a mode iteration from x[0] with power p0 = pw[0] (a power reduction
 // of x[0]): s = sqrt(P / p0); a start with no power or a non-finite one ends
 // at once with status 2.
@@ -3187,6 +3295,52 @@ void launch_mode(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, M
 }
 
 template <typename T>
+static const void* mode_persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block) {
+  const int J = (tl.max_compute + block - 1) / block;
+  const bool dec = tl.lmw != nullptr;
+#define DECBPM_MP(KM, DEC, JJ) reinterpret_cast<const void*>(&k_mode_persist<T, KM, DEC, JJ>)
+#define DECBPM_MP_J(KM, DEC) return J <= 1 ? DECBPM_MP(KM, DEC, 1) : DECBPM_MP(KM, DEC, 2);
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_MP_J(8, true) } else { DECBPM_MP_J(8, false) }
+  } else {
+    if (dec) { DECBPM_MP_J(12, true) } else { DECBPM_MP_J(12, false) }
+  }
+#undef DECBPM_MP_J
+#undef DECBPM_MP
+}
+
+template <typename T>
+int mode_persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block) {
+  if (tl.max_compute > 2 * block) return 0;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const size_t lds = size_t(tl.max_slots) * (2 * sizeof(typename CT<T>::C) + sizeof(T));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mode_persist_kernel<T>(d, tl, block), block, lds) !=
+      hipSuccess)
+    return 0;
+  return cus * per_cu;
+}
+
+template <typename T>
+hipError_t launch_mode_persist(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, ModeCtl* ctl,
+                               double* partial, int32_t* flags, int32_t* status, int32_t spin_limit, double h,
+                               double gamma, int block, hipStream_t st) {
+  using C = typename CT<T>::C;
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(tl.n_tiles, 256, 0)), dim3(256), 0, st, int64_t(tl.n_tiles), flags);
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  DevOps<T> dd = d;
+  TileOps<T> tt = tl;
+  C* b0 = static_cast<C*>(x0);
+  C* b1 = static_cast<C*>(x1);
+  T th = T(h), tg = T(gamma);
+  void* args[] = {&dd, &tt, &b0, &b1, &ctl, &partial, &flags, &status, &spin_limit, &th, &tg};
+  const size_t lds = size_t(tl.max_slots) * (2 * sizeof(C) + sizeof(T));
+  return hipLaunchCooperativeKernel(mode_persist_kernel<T>(d, tl, block), dim3(g), dim3(block), args, unsigned(lds),
+                                    st);
+}
+
+template <typename T>
 void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
                     double gamma, int block, hipStream_t st) {
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
@@ -3472,6 +3626,9 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   template void launch_mode<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, ModeCtl*, double*, uint32_t*,   \
                                double, double, int, hipStream_t);                                                \
   template void launch_scale<T>(int64_t, void*, double, int, hipStream_t);                                        \
+  template int mode_persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int);                                \
+  template hipError_t launch_mode_persist<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, ModeCtl*, double*, \
+                                             int32_t*, int32_t*, int32_t, double, double, int, hipStream_t);      \
   template void launch_step_rec<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, void*, void*, void*,    \
                                    void*, double, double, double, int, hipStream_t);                             \
   template void launch_step_adj<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*,     \

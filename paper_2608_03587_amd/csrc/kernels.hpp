@@ -241,6 +241,16 @@ void launch_mode_init(ModeCtl* ctl, uint32_t* arrivals, const double* pw, double
 template <typename T>
 void launch_mode(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, ModeCtl* ctl, double* partial,
                  uint32_t* arrivals, double h, double gamma, int block, hipStream_t st);
+// The mode iteration to its end (stopping test, max_iter or a wait timeout:
+// status bit 2) in one cooperative launch with every step tile resident;
+// flags: n_tiles ints of scratch (cleared by the launch).
+// mode_persist_capacity: resident workgroups at `block` threads.
+template <typename T>
+int mode_persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block);
+template <typename T>
+hipError_t launch_mode_persist(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, ModeCtl* ctl,
+                               double* partial, int32_t* flags, int32_t* status, int32_t spin_limit, double h,
+                               double gamma, int block, hipStream_t st);
 // x[0..n) *= s (complex, device order)
 template <typename T>
 void launch_scale(int64_t n, void* x, double s, int block, hipStream_t st);

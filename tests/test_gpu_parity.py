@@ -369,6 +369,18 @@ def test_mode_solver_converges_like_the_oracle():
     z, n = 0.5, 500
     m.propagate(g, z / n, n, 1.0)
     assert rel(host(g), phi * np.exp(-1j * st["mu"] * z)) < 1e-4
+    # the whole solve in one persistent launch (every tile resident; a grid-wide exchange per
+    # iteration instead of a kernel boundary): the same iterations and mode
+    for dtype in ("c128", "c64"):
+        mp = api.Mesh(mesh.xy, mesh.tri, V, None, dtype=dtype)
+        runs = {}
+        for fused in (2, 3):
+            mp.tuning = {"fused": fused}
+            fp = dev(start, dtype)
+            runs[fused] = (mp.find_mode(fp, 3.0, dtau, 1.0, tol=1e-10 if dtype == "c128" else 1e-4), host(fp))
+        say("  persistent mode solver", dtype, runs[2][0], runs[3][0])
+        assert runs[2][0]["iterations"] == runs[3][0]["iterations"]
+        assert rel(runs[3][1], runs[2][1]) < (1e-13 if dtype == "c128" else 1e-6)
     # failures: no convergence in too few iterations (the field holds the last iterate),
     # a start without power, a step beyond the RK4 margin, a beta4 handle
     f = dev(start, "c128")
