@@ -150,6 +150,8 @@ struct Engine {
   Dp5Ctl* dp5ctl = nullptr;
   double* dp5part = nullptr;
   uint32_t* dp5arr = nullptr;
+  int32_t* dp5flags = nullptr;
+  int dp5_cap_block = -1, dp5_cap = 0;  // resident workgroups of the persistent adaptive kernel
   // nonlinear mode iteration on the step tiles
   ModeCtl* modectl = nullptr;
   double* modepart = nullptr;
@@ -1114,8 +1116,9 @@ static bool ensure_dp5_tiles(Engine& E) {
   }
   if (!E.has_dp5) return false;
   E.dp5ctl = static_cast<Dp5Ctl*>(E.dalloc(sizeof(Dp5Ctl)));
-  E.dp5part = static_cast<double*>(E.dalloc(size_t(E.dp5.n_tiles) * sizeof(double)));
+  E.dp5part = static_cast<double*>(E.dalloc(size_t(E.dp5.n_tiles) * 2 * sizeof(double)));
   E.dp5arr = static_cast<uint32_t*>(E.dalloc(256));
+  E.dp5flags = static_cast<int32_t*>(E.dalloc(size_t(E.dp5.n_tiles) * sizeof(int32_t)));
   return true;
 }
 
@@ -1183,7 +1186,24 @@ static AdaptiveResult propagate_adaptive_t(Engine& E, void* field, double z_end,
   Dp5Ctl c{};
   c.h_abs = h0;
   int64_t launched = 0;
-  for (;;) {
+  // every seven-ring tile resident: the whole run in one cooperative launch
+  if (E.fused == 3) {
+    if (E.dp5_cap_block != blk) {
+      E.dp5_cap = dp5_persist_capacity<T>(d, tl, blk);
+      E.dp5_cap_block = blk;
+    }
+    const int64_t grid = E.xcd ? (int64_t(tl.n_tiles) + 7) / 8 * 8 : tl.n_tiles;
+    if (E.dp5_cap >= grid) {
+      const hipError_t e = launch_dp5_persist<T>(d, tl, E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5flags, E.flag,
+                                                 E.spin_limit, gamma, rtol, atol, inv_n, blk, st);
+      if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+      HIP_OK(hipMemcpyAsync(&c, E.dp5ctl, sizeof(Dp5Ctl), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      if (!c.done) fail(DEC_BPM_EHIP, "adaptive run: a tile's wait for the others timed out");
+      launched = max_attempts;
+    }
+  }
+  for (; launched < max_attempts;) {
     // trials still expected at the current step size; the first chunk is short,
     // since h0 may be far from the step the controller settles on
     const double want = launched == 0 ? 8.0 : std::min((z_end - c.z) / std::max(c.h_abs, 1e-300) + 1.0, 1e9);

@@ -2082,6 +2082,97 @@ __global__ void __launch_bounds__(1024) k_dp5(DevOps<T> d, TileOps<T> tl, typena
   }
 }
 
+// The adaptive run with every seven-ring tile resident (cooperative launch):
+// the trials of k_dp5 back to back, each ended by a grid-wide exchange of the
+// tiles' error shares (agent-scope stores, acknowledged, then an iteration
+// counter); every tile sums all shares in tile order and runs the controller
+// itself, so all take the same decision; tile 0 keeps the state in memory.
+// The global wait orders the buffer reuse (a trial writes x[1 - cur], which no
+// tile still reads) and the shares alternate between two halves of `partial`
+// (2 * n_tiles doubles).
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__(1024) k_dp5_persist(DevOps<T> d, TileOps<T> tl, typename CT<T>::C* x0,
+                                                      typename CT<T>::C* x1, Dp5Ctl* ctl, double* __restrict__ partial,
+                                                      int32_t* flags, int32_t* status, int32_t spin_limit, T gamma,
+                                                      T rtol, T atol, double inv_n) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16];
+  __shared__ Dp5Ctl cs;
+  __shared__ int32_t abort_s;
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  const int nw = int(blockDim.x + 63) / 64;
+  C* A = reinterpret_cast<C*>(smem);
+  C* Bv = A + MS;
+  T* SA = reinterpret_cast<T*>(Bv + MS);
+  T* SB = SA + MS;
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  if (threadIdx.x == 0) cs = *ctl;
+  __syncthreads();
+  for (int32_t it = 0; !cs.done; ++it) {
+    st.opaque_neighbours();
+    const C* in_psi = cs.cur ? x1 : x0;
+    C* out_psi = cs.cur ? x0 : x1;
+    const T h = T(cs.h_step);
+    for (int i = threadIdx.x; i < st.hd[7]; i += blockDim.x) {
+      const C v = coherent_load(in_psi + st.slot_row(i));
+      A[i] = v;
+      SA[i] = v.x * v.x + v.y * v.y;
+    }
+    __syncthreads();
+    double q = st.step_dp5(d, A, Bv, SA, SB, h, gamma, rtol, atol,
+                           [&](int, int32_t r, const C& v) { coherent_store(out_psi + r, v); });
+    for (int off = 32; off > 0; off >>= 1) q += __shfl_down(q, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    double* half = partial + int64_t(it & 1) * tl.n_tiles;
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < nw; ++w) t += red[w];
+      coherent_store(half + tile, t);
+    }
+    wait_stores();  // every wave: its rows and the share acknowledged
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flags + tile, it + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 64) {  // wait for every tile's trial it
+      bool ok = true;
+      for (int32_t spins = 0;; ++spins) {
+        bool all = true;
+        for (int k = threadIdx.x; k < tl.n_tiles; k += 64)
+          all = all && __hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= it + 1;
+        if (__all(all)) break;
+        if (spins >= spin_limit) {
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (threadIdx.x == 0) {
+        abort_s = ok ? 0 : 1;
+        if (!ok) __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __syncthreads();
+    if (abort_s) return;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < tl.n_tiles; k += blockDim.x) t += coherent_load(half + k);
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+    __syncthreads();  // red[] reuse
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < nw; ++w) sum += red[w];
+      dp5_decide(&cs, sum, inv_n);
+      if (tile == 0) *ctl = cs;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_dp5_init(Dp5Ctl* ctl, uint32_t* arrivals, double z_end, double h0, int64_t max_attempts,
                            double facmax) {
   if (threadIdx.x != 0) return;
@@ -3295,6 +3386,52 @@ void launch_mode(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, M
 }
 
 template <typename T>
+static const void* dp5_persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block) {
+  const int J = (tl.max_compute + block - 1) / block;
+  const bool dec = tl.lmw != nullptr;
+#define DECBPM_DP(KM, DEC, JJ) reinterpret_cast<const void*>(&k_dp5_persist<T, KM, DEC, JJ>)
+#define DECBPM_DP_J(KM, DEC) return J <= 1 ? DECBPM_DP(KM, DEC, 1) : DECBPM_DP(KM, DEC, 2);
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_DP_J(8, true) } else { DECBPM_DP_J(8, false) }
+  } else {
+    if (dec) { DECBPM_DP_J(12, true) } else { DECBPM_DP_J(12, false) }
+  }
+#undef DECBPM_DP_J
+#undef DECBPM_DP
+}
+
+template <typename T>
+int dp5_persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block) {
+  if (tl.max_compute > 2 * block) return 0;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const size_t lds = size_t(tl.max_slots) * 2 * (sizeof(typename CT<T>::C) + sizeof(T));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dp5_persist_kernel<T>(d, tl, block), block, lds) !=
+      hipSuccess)
+    return 0;
+  return cus * per_cu;
+}
+
+template <typename T>
+hipError_t launch_dp5_persist(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp5Ctl* ctl,
+                              double* partial, int32_t* flags, int32_t* status, int32_t spin_limit, double gamma,
+                              double rtol, double atol, double inv_n, int block, hipStream_t st) {
+  using C = typename CT<T>::C;
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(tl.n_tiles, 256, 0)), dim3(256), 0, st, int64_t(tl.n_tiles), flags);
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  DevOps<T> dd = d;
+  TileOps<T> tt = tl;
+  C* b0 = static_cast<C*>(x0);
+  C* b1 = static_cast<C*>(x1);
+  T tg = T(gamma), tr = T(rtol), ta = T(atol);
+  void* args[] = {&dd, &tt, &b0, &b1, &ctl, &partial, &flags, &status, &spin_limit, &tg, &tr, &ta, &inv_n};
+  const size_t lds = size_t(tl.max_slots) * 2 * (sizeof(C) + sizeof(T));
+  return hipLaunchCooperativeKernel(dp5_persist_kernel<T>(d, tl, block), dim3(g), dim3(block), args, unsigned(lds),
+                                    st);
+}
+
+template <typename T>
 static const void* mode_persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block) {
   const int J = (tl.max_compute + block - 1) / block;
   const bool dec = tl.lmw != nullptr;
@@ -3627,6 +3764,10 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                double, double, int, hipStream_t);                                                \
   template void launch_scale<T>(int64_t, void*, double, int, hipStream_t);                                        \
   template int mode_persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int);                                \
+  template int dp5_persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int);                                 \
+  template hipError_t launch_dp5_persist<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, Dp5Ctl*, double*,  \
+                                            int32_t*, int32_t*, int32_t, double, double, double, double, int,      \
+                                            hipStream_t);                                                         \
   template hipError_t launch_mode_persist<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, ModeCtl*, double*, \
                                              int32_t*, int32_t*, int32_t, double, double, int, hipStream_t);      \
   template void launch_step_rec<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, void*, void*, void*,    \

@@ -241,6 +241,16 @@ void launch_mode_init(ModeCtl* ctl, uint32_t* arrivals, const double* pw, double
 template <typename T>
 void launch_mode(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, ModeCtl* ctl, double* partial,
                  uint32_t* arrivals, double h, double gamma, int block, hipStream_t st);
+// The adaptive run to its end in one cooperative launch with every
+// seven-ring tile resident (a wait timeout sets status bit 2 and leaves the
+// controller state not done); partial: 2 * n_tiles doubles, flags: n_tiles
+// ints of scratch (cleared by the launch).
+template <typename T>
+int dp5_persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block);
+template <typename T>
+hipError_t launch_dp5_persist(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp5Ctl* ctl,
+                              double* partial, int32_t* flags, int32_t* status, int32_t spin_limit, double gamma,
+                              double rtol, double atol, double inv_n, int block, hipStream_t st);
 // The mode iteration to its end (stopping test, max_iter or a wait timeout:
 // status bit 2) in one cooperative launch with every step tile resident;
 // flags: n_tiles ints of scratch (cleared by the launch).

@@ -273,6 +273,17 @@ def test_adaptive_dp54_matches_oracle(dtype):
         err = rel(host(f), ref)
         say("  rel err", err)
         assert err < GATE[dtype], (z_end, h0, err)
+    # the whole run in one persistent launch (every seven-ring tile resident, a grid-wide
+    # exchange per trial instead of a kernel boundary): the same steps and state
+    runs = {}
+    for fused in (2, 3):
+        m.tuning = {"fused": fused}
+        f = u.clone()
+        runs[fused] = (m.propagate_adaptive(f, 20 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol), host(f))
+    say("  persistent adaptive", runs[2][0], runs[3][0])
+    assert (runs[2][0]["accepted"], runs[2][0]["rejected"]) == (runs[3][0]["accepted"], runs[3][0]["rejected"])
+    assert rel(runs[3][1], runs[2][1]) < (1e-13 if dtype == "c128" else 1e-6)
+    m.tuning = {"fused": 2}
     # a second handle call after a different run gives the same result (controller reset)
     f1 = u.clone()
     m.propagate_adaptive(f1, 2 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
