@@ -235,7 +235,10 @@ int dec_bpm_propagate_unsplit(dec_bpm_t h, void* field, double dz, int64_t n_ste
  * tiles: the beta4 term, rows of more than 12 neighbours), EUNSTABLE (the
  * attempts ran out, or the step fell below 10 ulp of z, before z_end),
  * ENONFINITE (a non-finite error norm); in these cases `field` holds the last
- * accepted state and the counters are filled.  EHIP, ENODEVICE.
+ * accepted state and the counters are filled.  EHIP, ENODEVICE.  When the
+ * handle's launch mode is the persistent one and every trial tile fits on the
+ * device at once, the whole run is one cooperative launch; a tile whose wait
+ * for the others exceeds the spin limit then ends the run with EHIP.
  */
 int dec_bpm_propagate_adaptive(dec_bpm_t h, void* field, double z_end, double h0, double gamma, double rtol,
                                double atol, int64_t max_attempts, int64_t* n_accepted, int64_t* n_rejected,
