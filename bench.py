@@ -91,7 +91,9 @@ def dominant_kernel_roofline(mode, kt):
     return {"bound": "hbm", "kernel": name, "kernel_class": cls, "achieved": achieved, "peak": 8000.0,
             "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None, "bytes_per_launch": k["bytes"],
             "launch_us": k["ms"] * 1e3, "launches_per_step": per_step,
-            "kernels_us": {c: v["ms"] * 1e3 for c, v in kt.items() if v["ms"] > 0}}
+            "kernels_us": {c: v["ms"] * 1e3 for c, v in kt.items() if v["ms"] > 0},
+            # every kernel class alone: algorithmic bytes per launch / launch time / 8 TB/s
+            "kernels_frac": {c: v["bytes"] / (v["ms"] * 1e-3) / 8e12 for c, v in kt.items() if v["ms"] > 0}}
 
 
 def measured_traffic(cls):
@@ -204,6 +206,8 @@ def main():
     log(f"[bench] five more runs: median {reps_ms[2]:.2f} ms (min {reps_ms[0]:.2f}, max {reps_ms[-1]:.2f})")
     kt = m.time_kernels(w.dz, w.gamma, reps=200)
     log(f"[bench] kernel means: " + ", ".join(f"{k} {v['ms'] * 1e3:.2f}us" for k, v in kt.items()))
+    log(f"[bench] fraction of 8 TB/s: " + ", ".join(f"{k} {v['bytes'] / (v['ms'] * 1e-3) / 8e12:.3f}"
+                                                    for k, v in kt.items() if v['ms'] > 0))
     roofline = dominant_kernel_roofline(m.tuning["fused"], kt)
     roofline["traffic"], roofline["traffic_source"] = measured_traffic(roofline["kernel_class"])
     out = {
