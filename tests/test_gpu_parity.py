@@ -941,6 +941,56 @@ def test_persistent_launch_matches_step_kernel_and_oracle(dtype, nl):
         assert np.array_equal(host(f), host(g)), tb
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_results_do_not_depend_on_the_tiling(dtype, monkeypatch):
+    """Cutting the mesh into tiles of other row counts (not powers of two, so
+    the last tile is ragged; 97 rows gives about 200 tiles with halos spanning
+    many tiles) moves rows within LDS and changes which tiles exchange halos,
+    not the per-row arithmetic.  The split step (one kernel per step and
+    persistent), the unsplit step and the adaptive run (per-trial kernels and
+    persistent; its error norm is summed tile by tile) agree with the default
+    tiling to rounding, and the adaptive run takes the same steps."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    u = dev(w.u0, dtype)
+    rtol, atol = (1e-9, 1e-11) if dtype == "c128" else (1e-5, 1e-7)
+    tol = 1e-13 if dtype == "c128" else 1e-6
+
+    def run(env):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        m = lib_mesh(w, dtype, "dec")
+        for k in env:
+            monkeypatch.delenv(k)
+        out = {}
+        for fused in (2, 3):
+            m.tuning = {"fused": fused}
+            f = u.clone()
+            m.propagate(f, w.dz, 40, w.gamma)
+            out[("split", fused)] = host(f)
+            g = u.clone()
+            m.propagate_unsplit(g, w.dz, 40, w.gamma)
+            out[("unsplit", fused)] = host(g)
+            a = u.clone()
+            st = m.propagate_adaptive(a, 10 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
+            out[("adaptive", fused)] = host(a)
+            out[("steps", fused)] = (st["accepted"], st["rejected"])
+            m.check_finite()
+        return out
+
+    ref = run({})
+    for env in ({"DEC_BPM_STEP_TILE": "333", "DEC_BPM_DP5_TILE": "300"},
+                {"DEC_BPM_STEP_TILE": "97", "DEC_BPM_DP5_TILE": "129"}):
+        say("tiling", dtype, env)
+        got = run(env)
+        for key, r in ref.items():
+            if key[0] == "steps":
+                assert got[key] == r, (env, key)
+                continue
+            say("  ", key, "bitwise" if np.array_equal(got[key], r) else f"rel {rel(got[key], r):.2e}")
+            assert rel(got[key], r) < tol, (env, key)
+
+
 def test_persistent_wait_bound_ends_the_launch(monkeypatch):
     """With a wait bound of zero polls a tile that finds a neighbour behind
     leaves the launch; the launch still ends and the next finiteness check
