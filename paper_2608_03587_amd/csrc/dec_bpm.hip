@@ -521,11 +521,13 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
   const int rings = (b4 ? 8 : 4) + (dec ? 1 : 0);
   const size_t lds_reals = batched ? size_t(7 * VF) : (b4 ? 9 : 7);
   // LDS per workgroup: 63 KiB in complex64 (two workgroups then share a CU's
-  // 160 KiB).  Complex128 and the beta4 step may use up to 100 KiB, so that
-  // their tiles keep 512 owned rows (the halo work of 256-row tiles doubles
-  // it); the beta4 step also takes three compute slots per thread in
-  // complex64.
-  const size_t lds_max = batched ? 150 * 1024 : ((b4 || sizeof(T) == 8) ? 100 * 1024 : 63 * 1024);
+  // 160 KiB).  Complex128 may use up to 100 KiB, so that its tiles keep 512
+  // owned rows (the halo work of 256-row tiles doubles it).  The complex64
+  // beta4 step, one workgroup per CU either way, may use up to 150 KiB, so that
+  // its nine-ring tiles can keep 1024 owned rows (less halo work per owned
+  // row); it also takes three compute slots per thread.
+  const size_t lds_max = batched ? 150 * 1024
+                                 : (b4 ? (sizeof(T) == 8 ? 100 : 150) * 1024 : (sizeof(T) == 8 ? 100 * 1024 : 63 * 1024));
   const int max_compute = sizeof(T) == 8 ? 2 * 640 : (b4 ? 3 : 2) * 1024;
   HostTiles H;
   bool built = false;
