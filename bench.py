@@ -545,16 +545,14 @@ def bench_adaptive(api, w, torch, dev, tdt, with_oracle):
 
 def bench_pml(api, w, torch, dev, tdt, steps, with_oracle):
     """The step-index launch with a perfectly matched layer on 35 < r < 40 (sigma_max 1) in
-    place of the absorber, complex64, one-kernel step with complex L weights, against the
-    same step with the absorber; parity with the oracle's split scheme on the stretched
-    operators after 5 steps, the oracle timed beside it."""
+    place of the absorber, complex64, against the same launch with the absorber: the
+    one-kernel step with complex L weights (fused 2) and the persistent launch (fused 3);
+    parity with the oracle's split scheme on the stretched operators after 5 steps, the
+    oracle timed beside it."""
     import numpy as np
 
-    out = {}
-    for name, pml, ab in (("pml", (35.0, 40.0, 1.0), None), ("absorber", None, w.absorber)):
-        m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, ab, dtype="c64", p1=w.p1, pml=pml)
-        m.tuning = {"fused": 2}
-        u0 = torch.from_numpy(w.u0).to(dev, tdt["c64"])
+    def timed(m, u0, fused, kind, extra_bytes):
+        m.tuning = {"fused": fused}
         f = u0.clone()
         m.propagate(f, w.dz, 50, w.gamma)
         f = u0.clone()
@@ -566,27 +564,38 @@ def bench_pml(api, w, torch, dev, tdt, steps, with_oracle):
         torch.cuda.synchronize()
         m.check_finite()
         ms = e0.elapsed_time(e1)
-        # the step kernel's algorithmic bytes plus the imaginary L weights of the layer
-        kt = m.time_kernels(w.dz, w.gamma, reps=50)["step"]
-        if pml is not None:
-            kt = dict(kt, bytes=kt["bytes"] + 6 * w.mesh.n_vert * 4)
-        out[name] = {"value": w.mesh.n_vert * steps / (ms * 1e-3), "ms_per_step": ms / steps, "tuning": m.tuning,
-                     "roofline": kernel_roofline(kt)}
+        kt = m.time_kernels(w.dz, w.gamma, reps=50)[kind]
+        kt = dict(kt, bytes=kt["bytes"] + extra_bytes)
+        return {"value": w.mesh.n_vert * steps / (ms * 1e-3), "ms_per_step": ms / steps, "tuning": m.tuning,
+                "roofline": kernel_roofline(kt)}
+
+    out = {}
+    for name, pml, ab in (("pml", (35.0, 40.0, 1.0), None), ("absorber", None, w.absorber)):
+        m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, ab, dtype="c64", p1=w.p1, pml=pml)
+        u0 = torch.from_numpy(w.u0).to(dev, tdt["c64"])
+        # the step's algorithmic bytes plus, with the layer, its imaginary L weights
+        extra = 6 * w.mesh.n_vert * 4 if pml is not None else 0
+        out[name] = timed(m, u0, 2, "step", extra)
+        out[name]["persistent"] = timed(m, u0, 3, "persist", extra)
         if with_oracle and pml is not None:
             from oracle import dec, stepper
 
             ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, None, p1=w.p1, pml=pml)
             ref, sec = oracle_timed(lambda: stepper.propagate(w.u0, ops, w.dz, 5, w.gamma))
-            g = u0.clone()
-            m.propagate(g, w.dz, 5, w.gamma)
-            got = g.cpu().numpy().astype(np.complex128)
-            out[name]["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-                                   "steps": 5}
+            for key, fused in (("parity", 2), ("parity_persistent", 3)):
+                m.tuning = {"fused": fused}
+                g = u0.clone()
+                m.propagate(g, w.dz, 5, w.gamma)
+                got = g.cpu().numpy().astype(np.complex128)
+                out[name][key] = {"rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                                  "steps": 5}
             out[name]["oracle"] = {"us_per_step": sec / 5 * 1e6, "cores": 1}
         del m
     log(f"[bench] PML: {out['pml']['ms_per_step'] * 1e3:.2f} us per step vs absorber "
-        f"{out['absorber']['ms_per_step'] * 1e3:.2f} us (one-kernel step), parity "
-        f"{out['pml'].get('parity', {}).get('rel_l2_vs_oracle')}")
+        f"{out['absorber']['ms_per_step'] * 1e3:.2f} us (one-kernel step); persistent "
+        f"{out['pml']['persistent']['ms_per_step'] * 1e3:.2f} vs {out['absorber']['persistent']['ms_per_step'] * 1e3:.2f} us; "
+        f"parity {out['pml'].get('parity', {}).get('rel_l2_vs_oracle')}, "
+        f"{out['pml'].get('parity_persistent', {}).get('rel_l2_vs_oracle')}")
     return out
 
 

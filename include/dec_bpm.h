@@ -92,7 +92,8 @@ typedef struct {
    * centroid); v, M and the power keep the real H0.  pml_sigma = 0: none.
    * Needs 0 < pml_r0 < pml_r1, no beta4 term and rows of at most 12
    * neighbours; the handle then runs dec_bpm_propagate on the one-kernel step
-   * (fused = 2) and kerr_step/diagnostics (Hamiltonian NaN); every entry point
+   * (fused = 2) or, in complex64 when every tile fits at once, the persistent
+   * launch (fused = 3), and kerr_step/diagnostics (Hamiltonian NaN); every entry point
    * that applies a real L (apply, linear_step, unsplit, adaptive, find_mode,
    * checkpointed forward and adjoint, batches) returns EINVAL.  The stability
    * check uses the unstretched operator's spectral radius, which bounds the

@@ -540,7 +540,8 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
     built = true;
     break;
   }
-  if (!built || b4 || batched || alwi) return;  // the persistent kernel: real one-field operators only
+  // the persistent kernel: one-field operators without beta4; complex L (a PML) in complex64 only
+  if (!built || b4 || batched || (alwi && sizeof(T) == 8)) return;
   if (sizeof(T) == 8) {
     HostTiles H2;
     for (int ts = 1024; ts > E.step_tile; ts /= 2) {  // larger than the step tiles: fewer to keep resident
@@ -901,7 +902,7 @@ static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl,
 // tile kernel, is only requested explicitly (dec_bpm_propagate_unsplit).
 template <typename T>
 static int mode_of(Engine& E) {
-  if (E.pml) return 2;                            // complex L: the one-kernel step only
+  if (E.pml) return use_persist<T>(E) ? 3 : 2;   // complex L: the one-kernel step or the persistent launch
   if (E.general()) return 0;                      // L^3, L^4 or a non-Kerr response: five kernels
   if (E.has_step4) return E.fused >= 2 ? 4 : 0;  // beta4: its one-kernel step or the five kernels
   if (use_persist<T>(E)) return 3;
@@ -2456,7 +2457,8 @@ static void set_tuning(Engine& E, const dec_bpm_tuning* t) {
       t->tile_block < 64 || t->tile_block > 1024 || t->tile_block % 64 || (t->fused < 0 || t->fused > 3) ||
       (t->xcd_remap != 0 && t->xcd_remap != 1))
     fail(DEC_BPM_EINVAL, "bad tuning");
-  if (E.pml && t->fused != 2) fail(DEC_BPM_EINVAL, "a PML handle runs the one-kernel step only (fused = 2)");
+  if (E.pml && t->fused != 2 && t->fused != 3)
+    fail(DEC_BPM_EINVAL, "a PML handle runs the one-kernel step or the persistent launch only (fused = 2 or 3)");
   if (E.general() && t->fused != 0)
     fail(DEC_BPM_EINVAL, "L^3, L^4 or a non-Kerr response run the five-kernel path only (fused = 0)");
   E.block = t->block_size;

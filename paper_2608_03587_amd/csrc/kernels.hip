@@ -2690,7 +2690,8 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
 // BODY 0: the merged split step; BODY 1: one unsplit classical RK4 step of the
 // whole right-hand side (the stage inputs and their |.|^2 double-buffered in
 // the same LDS; the owned state and its |.|^2 written back after the step).
-template <typename T, int KMAX, bool DEC, int J, int LS, int BODY>
+// CL: complex L weights (a perfectly matched layer), split-step body only.
+template <typename T, int KMAX, bool DEC, int J, int LS, int BODY, bool CL = false>
 __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, const int32_t* __restrict__ nb_ptr,
                                                   const int32_t* __restrict__ nb_list, typename CT<T>::C* buf0,
                                                   typename CT<T>::C* buf1, int32_t* flags, int32_t* status,
@@ -2710,7 +2711,7 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
   C* UB = base + MS;
   T* USA = reinterpret_cast<T*>(base + 2 * MS);
   T* USB = USA + MS;
-  StepTile<T, KMAX, DEC, J> st;
+  StepTile<T, KMAX, DEC, J, CL> st;
   st.init(d, tl, tile);
   int32_t pr[LS];  // rows of this thread's state slots
 #pragma unroll
@@ -3564,14 +3565,27 @@ void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_i
 #undef DECBPM_STEPA
 }
 
+// Persistent kernel instance for a body; tiles with complex L weights have one
+// for the split-step body in complex64 only (nullptr otherwise).
+template <typename T, int KM, bool DEC, int JJ>
+static const void* persist_instance(int body, bool cl) {
+  if (cl) {
+    if constexpr (sizeof(T) == 4) {
+      if (body == 0) return reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0, true>);
+    }
+    return nullptr;
+  }
+  return body ? reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 1>)
+              : reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0>);
+}
+
 // Kernel instance of the persistent step for a tile set and block size.
 template <typename T>
 static const void* persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block, int body) {
   const int J = (tl.max_compute + block - 1) / block;
   const bool dec = tl.lmw != nullptr;
-#define DECBPM_PK(KM, DEC, JJ)                                                    \
-  (body ? reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 1>)          \
-        : reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0>))
+  const bool cl = tl.llwi != nullptr;
+#define DECBPM_PK(KM, DEC, JJ) persist_instance<T, KM, DEC, JJ>(body, cl)
 #define DECBPM_PK_J(KM, DEC) return J <= 1 ? DECBPM_PK(KM, DEC, 1) : DECBPM_PK(KM, DEC, 2);
   if (kmax_of(d.wmax) == 8) {
     if (dec) { DECBPM_PK_J(8, true) } else { DECBPM_PK_J(8, false) }
@@ -3590,12 +3604,12 @@ size_t persist_lds(const TileOps<T>& tl) {
 template <typename T>
 int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block, int body) {
   if (tl.max_slots > 3 * block || tl.max_compute > 2 * block) return 0;
+  const void* k = persist_kernel<T>(d, tl, block, body);
+  if (!k) return 0;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel<T>(d, tl, block, body), block,
-                                                   persist_lds<T>(tl)) != hipSuccess)
-    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, persist_lds<T>(tl)) != hipSuccess) return 0;
   return cus * per_cu;
 }
 
@@ -3604,6 +3618,8 @@ hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_
                           void* buf0, void* buf1, int32_t* flags, int32_t* status, int32_t n_steps,
                           int32_t spin_limit, double h, double gamma, int block, hipStream_t st, int body) {
   using C = typename CT<T>::C;
+  const void* k = persist_kernel<T>(d, tl, block, body);
+  if (!k) return hipErrorInvalidDeviceFunction;
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(tl.n_tiles, 256, 0)), dim3(256), 0, st, int64_t(tl.n_tiles), flags);
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
   DevOps<T> dd = d;
@@ -3613,8 +3629,7 @@ hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_
   T th = T(h), tg = T(gamma);
   void* args[] = {&dd, &tt, const_cast<int32_t**>(&nb_ptr), const_cast<int32_t**>(&nb_list), &b0, &b1, &flags, &status,
                   &n_steps, &spin_limit, &th, &tg};
-  return hipLaunchCooperativeKernel(persist_kernel<T>(d, tl, block, body), dim3(g), dim3(block), args,
-                                    unsigned(persist_lds<T>(tl)), st);
+  return hipLaunchCooperativeKernel(k, dim3(g), dim3(block), args, unsigned(persist_lds<T>(tl)), st);
 }
 
 template <typename T>

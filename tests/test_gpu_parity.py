@@ -417,7 +417,9 @@ def test_pml_step_matches_oracle(dtype):
     """A perfectly matched layer (complex-stretched Hodge stars) in place of the absorber on
     the 89k-vertex step-index mesh: the one-kernel step with complex L weights against the
     oracle's split scheme on the stretched operators, for step counts that mix graph
-    replays and eager steps; the handle refuses other launch modes and real-L entry points."""
+    replays and eager steps; in complex64 the persistent launch with complex weights gives
+    the one-kernel step's bits; the handle refuses other launch modes and real-L entry
+    points."""
     w = case("step_index", n_vert=20000, n_steps=10)
     pml = (35.0, 40.0, 1.0)
     ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, None, pml=pml)
@@ -433,6 +435,16 @@ def test_pml_step_matches_oracle(dtype):
         err = rel(host(f), ref)
         say("  rel err", err)
         assert err < (1e-12 if dtype == "c128" else 1e-5), (n, err)
+        if dtype == "c64":
+            m.tuning = {"fused": 3}
+            g = u.clone()
+            m.propagate(g, w.dz, n, w.gamma)
+            m.check_finite()
+            m.tuning = {"fused": 2}
+            assert np.array_equal(host(g), host(f)), (n, rel(host(g), host(f)))
+    persist_ms = m.time_kernels(w.dz, w.gamma, reps=10)["persist"]["ms"]
+    say("  persistent launch ms per step", persist_ms)
+    assert (persist_ms > 0) == (dtype == "c64")  # the complex-weight persistent kernel: complex64 only
     t = dict(m.tuning)
     t["fused"] = 1
     with pytest.raises(api.DecBpmError) as e:
@@ -520,8 +532,8 @@ def test_general_operator_sum_and_responses_match_oracle(dtype, response, param,
 
 def test_full_size_pml_and_mode_iterations():
     """The full 249k-vertex step-index mesh in the bench's configurations of the layer
-    (one-kernel step with complex weights, 5 steps) and of the mode solver (10 iterations),
-    complex64, against the oracle."""
+    (one-kernel step with complex weights and the persistent launch, 5 steps) and of the
+    mode solver (10 iterations), complex64, against the oracle."""
     w = case("step_index")
     say("full size pml / mode", w.mesh.n_vert)
     pml = (35.0, 40.0, 1.0)
@@ -532,6 +544,11 @@ def test_full_size_pml_and_mode_iterations():
     err = rel(host(f), S.propagate(w.u0, ops, w.dz, 5, w.gamma))
     say("  pml rel err", err)
     assert err < 1e-5
+    m.tuning = {"fused": 3}  # the persistent launch with complex weights: the same bits
+    g = dev(w.u0, "c64")
+    m.propagate(g, w.dz, 5, w.gamma)
+    m.check_finite()
+    assert np.array_equal(host(g), host(f)), rel(host(g), host(f))
     ops = oracle_ops(w)
     m = lib_mesh(w, "c64")
     dtau = 2.0 / m.spectral_radius()
