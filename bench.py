@@ -552,7 +552,8 @@ def bench_pml(api, w, torch, dev, tdt, steps, with_oracle):
     import numpy as np
 
     def timed(m, u0, fused, kind, extra_bytes):
-        m.tuning = {"fused": fused}
+        # the persistent launch in the shape the autotuner picks for this workload
+        m.tuning = {"fused": 3, "tile_block": 1024, "xcd_remap": 0} if fused == 3 else {"fused": fused}
         f = u0.clone()
         m.propagate(f, w.dz, 50, w.gamma)
         f = u0.clone()
