@@ -96,6 +96,44 @@ def dominant_kernel_roofline(mode, kt):
             "kernels_frac": {c: v["bytes"] / (v["ms"] * 1e-3) / 8e12 for c, v in kt.items() if v["ms"] > 0}}
 
 
+def profile_path(args, api, W, torch, dev, tdt):
+    """One path alone, for rocprofv3: warm-up, then the timed call; prints one JSON line."""
+    w = W.vortex_beta4() if args.profile_path == "vortex_beta4" else W.step_index()
+    pml = (35.0, 40.0, 1.0) if args.profile_path == "pml" else None
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, None if pml else w.absorber, dtype=args.dtype, p1=w.p1,
+                 beta4=w.beta4, pml=pml)
+    if args.tuning:
+        m.tuning = json.loads(args.tuning)
+    else:
+        m.autotune(w.dz, w.gamma)
+    u0 = torch.from_numpy(w.u0).to(dev, tdt)
+    rtol, atol = (1e-9, 1e-11) if args.dtype == "c128" else (1e-6, 1e-8)
+    dtau = 2.0 / m.spectral_radius()
+
+    def run(k):
+        f = u0.clone()
+        if args.profile_path == "adaptive":
+            return m.propagate_adaptive(f, k * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
+        if args.profile_path == "mode":
+            return m.find_mode(f, 4.0, dtau, w.gamma, tol=0.0, max_iter=k)
+        m.propagate(f, w.dz, k, w.gamma)
+        return None
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    info = run(args.steps)
+    s1.record()
+    torch.cuda.synchronize()
+    m.check_finite()
+    units = args.steps
+    if args.profile_path == "adaptive":
+        units = info["accepted"] + info["rejected"]
+    print(json.dumps({"profile_only": True, "path": args.profile_path, "vertices": w.mesh.n_vert,
+                      "units": units, "us_per_unit": s0.elapsed_time(s1) * 1e3 / units, "tuning": m.tuning}))
+
+
 def measured_traffic(cls):
     """HBM bytes per launch of the kernel class from the committed rocprofv3
     counter summary, if it was taken on the current kernel sources (else None)."""
@@ -126,6 +164,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="only the timed propagation (for rocprofv3)")
+    ap.add_argument("--profile-path", default="split", choices=["split", "vortex_beta4", "pml", "adaptive", "mode"],
+                    help="with --profile: which path to run (split: the step-index propagate; vortex_beta4: the "
+                         "1M-vertex beta4 launch; pml: the step-index launch with the layer; adaptive: the "
+                         "Dormand-Prince run over --steps dz; mode: --steps mode-solver iterations)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="with --profile: also run a 256 MiB device copy (traffic counter calibration)")
     ap.add_argument("--tuning", default="", help="fixed launch shape as JSON (skips autotuning), e.g. the "
@@ -147,6 +189,9 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     tdt = {"c64": torch.complex64, "c128": torch.complex128}
+    if args.profile and args.profile_path != "split":
+        profile_path(args, api, W, torch, dev, tdt[args.dtype])
+        return
 
     t0 = time.time()
     w = W.step_index()
