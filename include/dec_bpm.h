@@ -380,7 +380,10 @@ enum {
   DEC_BPM_K_UNSPLIT = 7,  /* one unsplit RK4 step (dec_bpm_propagate_unsplit)     */
   DEC_BPM_K_DP5 = 8,      /* one adaptive Dormand-Prince trial (seven stages)     */
   DEC_BPM_K_MODE = 9,     /* one nonlinear mode iteration (dec_bpm_find_mode)     */
-  DEC_BPM_NUM_KERNELS = 10
+  DEC_BPM_K_DP5_PERSIST = 10, /* one trial inside a persistent adaptive launch of   */
+                              /* max(reps, 200) trials (0: the trial tiles do not   */
+                              /* all fit on the device at once)                     */
+  DEC_BPM_NUM_KERNELS = 11
 };
 int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
                          void* stream);

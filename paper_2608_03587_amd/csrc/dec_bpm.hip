@@ -1134,6 +1134,19 @@ static int dp5_block(const Engine& E) {
   return ((mc + 1) / 2 + 63) / 64 * 64;
 }
 
+// Whether the adaptive trial tiles can all be resident at once (the persistent
+// adaptive launch), at the trial kernels' block size; the capacity is cached.
+template <typename T>
+static bool dp5_persist_fits(Engine& E) {
+  const int blk = dp5_block(E);
+  if (E.dp5_cap_block != blk) {
+    E.dp5_cap = dp5_persist_capacity<T>(E.ops<T>(), E.dp5.template ops<T>(), blk);
+    E.dp5_cap_block = blk;
+  }
+  const int64_t grid = E.xcd ? (int64_t(E.dp5.n_tiles) + 7) / 8 * 8 : E.dp5.n_tiles;
+  return E.dp5_cap >= grid;
+}
+
 struct AdaptiveResult {
   int64_t accepted = 0, rejected = 0;
   double last_h = 0.0, z = 0.0;
@@ -1190,21 +1203,14 @@ static AdaptiveResult propagate_adaptive_t(Engine& E, void* field, double z_end,
   c.h_abs = h0;
   int64_t launched = 0;
   // every seven-ring tile resident: the whole run in one cooperative launch
-  if (E.fused == 3) {
-    if (E.dp5_cap_block != blk) {
-      E.dp5_cap = dp5_persist_capacity<T>(d, tl, blk);
-      E.dp5_cap_block = blk;
-    }
-    const int64_t grid = E.xcd ? (int64_t(tl.n_tiles) + 7) / 8 * 8 : tl.n_tiles;
-    if (E.dp5_cap >= grid) {
-      const hipError_t e = launch_dp5_persist<T>(d, tl, E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5flags, E.flag,
-                                                 E.spin_limit, gamma, rtol, atol, inv_n, blk, st);
-      if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
-      HIP_OK(hipMemcpyAsync(&c, E.dp5ctl, sizeof(Dp5Ctl), hipMemcpyDeviceToHost, st));
-      HIP_OK(hipStreamSynchronize(st));
-      if (!c.done) fail(DEC_BPM_EHIP, "adaptive run: a tile's wait for the others timed out");
-      launched = max_attempts;
-    }
+  if (E.fused == 3 && dp5_persist_fits<T>(E)) {
+    const hipError_t e = launch_dp5_persist<T>(d, tl, E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5flags, E.flag,
+                                               E.spin_limit, gamma, rtol, atol, inv_n, blk, st);
+    if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+    HIP_OK(hipMemcpyAsync(&c, E.dp5ctl, sizeof(Dp5Ctl), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (!c.done) fail(DEC_BPM_EHIP, "adaptive run: a tile's wait for the others timed out");
+    launched = max_attempts;
   }
   for (; launched < max_attempts;) {
     // trials still expected at the current step size; the first chunk is short,
@@ -1612,6 +1618,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   by[DEC_BPM_K_UNSPLIT] = by[DEC_BPM_K_STEP];  // one unsplit RK4 step: the same data
   by[DEC_BPM_K_DP5] = by[DEC_BPM_K_STEP];      // one adaptive trial: the same data
   by[DEC_BPM_K_MODE] = by[DEC_BPM_K_STEP];     // one mode iteration: the same data
+  by[DEC_BPM_K_DP5_PERSIST] = by[DEC_BPM_K_STEP];
   launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
   launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
   launch_fill<T>(d, E.yb, 0.2, -0.1, B, st);
@@ -1627,6 +1634,8 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
         (kind == DEC_BPM_K_UNSPLIT && (!E.has_step || E.F != 1)) ||
         (kind == DEC_BPM_K_DP5 && !(E.has_step && E.F == 1 && ensure_dp5_tiles<T>(E))) ||
         (kind == DEC_BPM_K_MODE && !(E.has_step && E.F == 1)) ||
+        (kind == DEC_BPM_K_DP5_PERSIST &&
+         !(E.has_step && E.F == 1 && ensure_dp5_tiles<T>(E) && dp5_persist_fits<T>(E))) ||
         (kind == DEC_BPM_K_PERSIST && !(E.has_persist && persist_fits<T>(E)))) {
       if (ms) ms[kind] = 0.0;
       if (bytes) bytes[kind] = 0.0;
@@ -1645,6 +1654,25 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       float t = 0;
       HIP_OK(hipEventElapsedTime(&t, e0, e1));
       if (ms) ms[kind] = double(t) / steps;
+      if (bytes) bytes[kind] = by[kind];
+      continue;
+    }
+    if (kind == DEC_BPM_K_DP5_PERSIST) {  // one launch of a fixed trial count, time per trial
+      const TileOps<T> tp = E.dp5.template ops<T>();
+      const int blk = dp5_block(E);
+      const int trials = std::max(reps, 200);
+      for (int pass = 0; pass < 2; ++pass) {  // warm-up, then timed
+        const int n = pass ? trials : 2;
+        launch_dp5_init(E.dp5ctl, E.dp5arr, 1e300, dz, n, 1.0, st);
+        if (pass) HIP_OK(hipEventRecord(e0, st));
+        HIP_OK(launch_dp5_persist<T>(d, tp, E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5flags, E.flag, E.spin_limit,
+                                     gamma, 1e-6, 1e-8, 1.0 / double(E.n_rows), blk, st));
+      }
+      HIP_OK(hipEventRecord(e1, st));
+      HIP_OK(hipEventSynchronize(e1));
+      float t = 0;
+      HIP_OK(hipEventElapsedTime(&t, e0, e1));
+      if (ms) ms[kind] = double(t) / trials;
       if (bytes) bytes[kind] = by[kind];
       continue;
     }

@@ -274,7 +274,14 @@ def test_adaptive_dp54_matches_oracle(dtype):
         say("  rel err", err)
         assert err < GATE[dtype], (z_end, h0, err)
     # the whole run in one persistent launch (every seven-ring tile resident, a grid-wide
-    # exchange per trial instead of a kernel boundary): the same steps and state
+    # exchange per trial instead of a kernel boundary): the same steps and state.  In
+    # complex64 this mesh's trial tiles fit at once (the timing class shows the path is
+    # live); complex128's smaller tiles do not, and its runs stay per trial.
+    m.tuning = {"fused": 3}
+    persist_ms = m.time_kernels(w.dz, w.gamma, reps=20)["dp5_persist"]["ms"]
+    say("  persistent adaptive trial ms", persist_ms)
+    if dtype == "c64":
+        assert persist_ms > 0
     runs = {}
     for fused in (2, 3):
         m.tuning = {"fused": fused}
@@ -283,6 +290,8 @@ def test_adaptive_dp54_matches_oracle(dtype):
     say("  persistent adaptive", runs[2][0], runs[3][0])
     assert (runs[2][0]["accepted"], runs[2][0]["rejected"]) == (runs[3][0]["accepted"], runs[3][0]["rejected"])
     assert rel(runs[3][1], runs[2][1]) < (1e-13 if dtype == "c128" else 1e-6)
+    assert rel(runs[3][1], US.propagate_dp54(w.u0, ops, 20 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)[0]) < \
+        GATE[dtype]
     m.tuning = {"fused": 2}
     # a second handle call after a different run gives the same result (controller reset)
     f1 = u.clone()
