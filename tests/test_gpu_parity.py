@@ -445,12 +445,13 @@ def test_pml_step_matches_oracle(dtype):
         say("  rel err", err)
         assert err < (1e-12 if dtype == "c128" else 1e-5), (n, err)
         if dtype == "c64":
-            m.tuning = {"fused": 3}
-            g = u.clone()
-            m.propagate(g, w.dz, n, w.gamma)
-            m.check_finite()
-            m.tuning = {"fused": 2}
-            assert np.array_equal(host(g), host(f)), (n, rel(host(g), host(f)))
+            for x in (0, 1):
+                m.tuning = {"fused": 3, "tile_block": 1024, "xcd_remap": x}
+                g = u.clone()
+                m.propagate(g, w.dz, n, w.gamma)
+                m.check_finite()
+                assert np.array_equal(host(g), host(f)), (n, x, rel(host(g), host(f)))
+            m.tuning = {"fused": 2, "xcd_remap": 0}
     persist_ms = m.time_kernels(w.dz, w.gamma, reps=10)["persist"]["ms"]
     say("  persistent launch ms per step", persist_ms)
     assert (persist_ms > 0) == (dtype == "c64")  # the complex-weight persistent kernel: complex64 only
@@ -956,15 +957,17 @@ def test_persistent_launch_matches_step_kernel_and_oracle(dtype, nl):
         if n <= 64:
             ref = S.propagate(w.u0, ops, w.dz, n, w.gamma)
             assert rel(outs[3], ref) < GATE[dtype], n
-    for tb in (512, 1024):
-        m.tuning = {"fused": 3, "tile_block": tb}
+    # block sizes, and the XCD-aware block order (grid padded to a multiple of 8 with
+    # workgroups that leave at once)
+    for tb, x in ((512, 0), (1024, 0), (1024, 1)):
+        m.tuning = {"fused": 3, "tile_block": tb, "xcd_remap": x}
         f = u.clone()
         m.propagate(f, w.dz, 37, w.gamma)
         m.check_finite()
-        m.tuning = {"fused": 2}
+        m.tuning = {"fused": 2, "xcd_remap": 0}
         g = u.clone()
         m.propagate(g, w.dz, 37, w.gamma)
-        assert np.array_equal(host(f), host(g)), tb
+        assert np.array_equal(host(f), host(g)), (tb, x)
 
 
 @pytest.mark.gpu
