@@ -383,7 +383,10 @@ enum {
   DEC_BPM_K_DP5_PERSIST = 10, /* one trial inside a persistent adaptive launch of   */
                               /* max(reps, 200) trials (0: the trial tiles do not   */
                               /* all fit on the device at once)                     */
-  DEC_BPM_NUM_KERNELS = 11
+  DEC_BPM_K_MODE_PERSIST = 11, /* one iteration inside a persistent mode-solver     */
+                               /* launch of max(reps, 200) iterations (0: not used  */
+                               /* by this handle)                                   */
+  DEC_BPM_NUM_KERNELS = 12
 };
 int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
                          void* stream);

@@ -1147,6 +1147,27 @@ static bool dp5_persist_fits(Engine& E) {
   return E.dp5_cap >= grid;
 }
 
+// Whether the whole mode iteration can run in one cooperative launch: complex64
+// step tiles (complex128's persistent tiles are its own), all resident at once.
+template <typename T>
+static bool mode_persist_fits(Engine& E) {
+  if (!E.has_persist || E.pst_own) return false;
+  const int blk = E.sblock();
+  if (E.mode_cap_block != blk) {
+    E.mode_cap = mode_persist_capacity<T>(E.ops<T>(), E.stp.template ops<T>(), blk);
+    E.mode_cap_block = blk;
+  }
+  const int64_t grid = E.xcd ? (int64_t(E.stp.n_tiles) + 7) / 8 * 8 : E.stp.n_tiles;
+  return E.mode_cap >= grid;
+}
+
+static void ensure_mode_ctl(Engine& E) {
+  if (E.modectl) return;
+  E.modectl = static_cast<ModeCtl*>(E.dalloc(sizeof(ModeCtl)));
+  E.modepart = static_cast<double*>(E.dalloc(size_t(E.stp.n_tiles) * 8 * sizeof(double)));
+  E.modearr = static_cast<uint32_t*>(E.dalloc(256));
+}
+
 struct AdaptiveResult {
   int64_t accepted = 0, rejected = 0;
   double last_h = 0.0, z = 0.0;
@@ -1284,11 +1305,7 @@ static hipGraphExec_t mode_graph(Engine& E, int K, double dtau, double gamma) {
 template <typename T>
 static ModeResult find_mode_t(Engine& E, void* field, double power, double dtau, double gamma, double tol,
                               int64_t max_iter, hipStream_t st) {
-  if (!E.modectl) {
-    E.modectl = static_cast<ModeCtl*>(E.dalloc(sizeof(ModeCtl)));
-    E.modepart = static_cast<double*>(E.dalloc(size_t(E.stp.n_tiles) * 8 * sizeof(double)));
-    E.modearr = static_cast<uint32_t*>(E.dalloc(256));
-  }
+  ensure_mode_ctl(E);
   const DevOps<T> d = E.ops<T>();
   const TileOps<T> tl = E.stp.template ops<T>();
   const int blk = E.sblock();
@@ -1299,21 +1316,14 @@ static ModeResult find_mode_t(Engine& E, void* field, double power, double dtau,
   int64_t launched = 0;
   int K = 8;
   // every step tile resident: the whole iteration in one cooperative launch (complex64 tiles)
-  if (E.fused == 3 && E.has_persist && !E.pst_own) {
-    if (E.mode_cap_block != blk) {
-      E.mode_cap = mode_persist_capacity<T>(d, tl, blk);
-      E.mode_cap_block = blk;
-    }
-    const int64_t grid = E.xcd ? (int64_t(tl.n_tiles) + 7) / 8 * 8 : tl.n_tiles;
-    if (E.mode_cap >= grid) {
-      const hipError_t e = launch_mode_persist<T>(d, tl, E.psi, E.psi2, E.modectl, E.modepart, E.pflags, E.flag,
-                                                  E.spin_limit, dtau, gamma, blk, st);
-      if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
-      HIP_OK(hipMemcpyAsync(&c, E.modectl, sizeof(ModeCtl), hipMemcpyDeviceToHost, st));
-      HIP_OK(hipStreamSynchronize(st));
-      if (!c.done) fail(DEC_BPM_EHIP, "mode solver: a tile's wait for the others timed out");
-      launched = max_iter;
-    }
+  if (E.fused == 3 && mode_persist_fits<T>(E)) {
+    const hipError_t e = launch_mode_persist<T>(d, tl, E.psi, E.psi2, E.modectl, E.modepart, E.pflags, E.flag,
+                                                E.spin_limit, dtau, gamma, blk, st);
+    if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+    HIP_OK(hipMemcpyAsync(&c, E.modectl, sizeof(ModeCtl), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (!c.done) fail(DEC_BPM_EHIP, "mode solver: a tile's wait for the others timed out");
+    launched = max_iter;
   }
   for (; launched < max_iter;) {
     const int64_t left = max_iter - launched;
@@ -1619,6 +1629,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   by[DEC_BPM_K_DP5] = by[DEC_BPM_K_STEP];      // one adaptive trial: the same data
   by[DEC_BPM_K_MODE] = by[DEC_BPM_K_STEP];     // one mode iteration: the same data
   by[DEC_BPM_K_DP5_PERSIST] = by[DEC_BPM_K_STEP];
+  by[DEC_BPM_K_MODE_PERSIST] = by[DEC_BPM_K_STEP];
   launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
   launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
   launch_fill<T>(d, E.yb, 0.2, -0.1, B, st);
@@ -1634,6 +1645,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
         (kind == DEC_BPM_K_UNSPLIT && (!E.has_step || E.F != 1)) ||
         (kind == DEC_BPM_K_DP5 && !(E.has_step && E.F == 1 && ensure_dp5_tiles<T>(E))) ||
         (kind == DEC_BPM_K_MODE && !(E.has_step && E.F == 1)) ||
+        (kind == DEC_BPM_K_MODE_PERSIST && !(E.has_step && E.F == 1 && mode_persist_fits<T>(E))) ||
         (kind == DEC_BPM_K_DP5_PERSIST &&
          !(E.has_step && E.F == 1 && ensure_dp5_tiles<T>(E) && dp5_persist_fits<T>(E))) ||
         (kind == DEC_BPM_K_PERSIST && !(E.has_persist && persist_fits<T>(E)))) {
@@ -1676,12 +1688,27 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       if (bytes) bytes[kind] = by[kind];
       continue;
     }
-    if (kind == DEC_BPM_K_MODE) {  // iterations of step dz at power 1, no stopping test
-      if (!E.modectl) {
-        E.modectl = static_cast<ModeCtl*>(E.dalloc(sizeof(ModeCtl)));
-        E.modepart = static_cast<double*>(E.dalloc(size_t(E.stp.n_tiles) * 8 * sizeof(double)));
-        E.modearr = static_cast<uint32_t*>(E.dalloc(256));
+    if (kind == DEC_BPM_K_MODE_PERSIST) {  // one launch of a fixed iteration count, time per iteration
+      ensure_mode_ctl(E);
+      const TileOps<T> ts = E.stp.template ops<T>();
+      const int iters = std::max(reps, 200);
+      for (int pass = 0; pass < 2; ++pass) {  // warm-up, then timed
+        launch_diag<T>(d, E.psi, 0.0, E.partials, E.n_red_blocks, E.red_out, st);
+        launch_mode_init(E.modectl, E.modearr, E.red_out, 1.0, 0.0, pass ? iters : 2, st);
+        if (pass) HIP_OK(hipEventRecord(e0, st));
+        HIP_OK(launch_mode_persist<T>(d, ts, E.psi, E.psi2, E.modectl, E.modepart, E.pflags, E.flag, E.spin_limit,
+                                      dz, gamma, E.sblock(), st));
       }
+      HIP_OK(hipEventRecord(e1, st));
+      HIP_OK(hipEventSynchronize(e1));
+      float t = 0;
+      HIP_OK(hipEventElapsedTime(&t, e0, e1));
+      if (ms) ms[kind] = double(t) / iters;
+      if (bytes) bytes[kind] = by[kind];
+      continue;
+    }
+    if (kind == DEC_BPM_K_MODE) {  // iterations of step dz at power 1, no stopping test
+      ensure_mode_ctl(E);
       launch_diag<T>(d, E.psi, 0.0, E.partials, E.n_red_blocks, E.red_out, st);
       launch_mode_init(E.modectl, E.modearr, E.red_out, 1.0, 0.0, int64_t(1) << 62, st);
       HIP_OK(hipStreamSynchronize(st));

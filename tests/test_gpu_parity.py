@@ -283,16 +283,18 @@ def test_adaptive_dp54_matches_oracle(dtype):
     if dtype == "c64":
         assert persist_ms > 0
     runs = {}
-    for fused in (2, 3):
-        m.tuning = {"fused": fused}
+    for fused, x in ((2, 0), (3, 0), (3, 1)):
+        m.tuning = {"fused": fused, "xcd_remap": x}
         f = u.clone()
-        runs[fused] = (m.propagate_adaptive(f, 20 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol), host(f))
-    say("  persistent adaptive", runs[2][0], runs[3][0])
-    assert (runs[2][0]["accepted"], runs[2][0]["rejected"]) == (runs[3][0]["accepted"], runs[3][0]["rejected"])
-    assert rel(runs[3][1], runs[2][1]) < (1e-13 if dtype == "c128" else 1e-6)
-    assert rel(runs[3][1], US.propagate_dp54(w.u0, ops, 20 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)[0]) < \
-        GATE[dtype]
-    m.tuning = {"fused": 2}
+        runs[(fused, x)] = (m.propagate_adaptive(f, 20 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol), host(f))
+    say("  persistent adaptive", runs[(2, 0)][0], runs[(3, 0)][0])
+    ref = US.propagate_dp54(w.u0, ops, 20 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)[0]
+    for key in ((3, 0), (3, 1)):
+        st2, st3 = runs[(2, 0)][0], runs[key][0]
+        assert (st2["accepted"], st2["rejected"]) == (st3["accepted"], st3["rejected"]), key
+        assert rel(runs[key][1], runs[(2, 0)][1]) < (1e-13 if dtype == "c128" else 1e-6), key
+        assert rel(runs[key][1], ref) < GATE[dtype], key
+    m.tuning = {"fused": 2, "xcd_remap": 0}
     # a second handle call after a different run gives the same result (controller reset)
     f1 = u.clone()
     m.propagate_adaptive(f1, 2 * w.dz, w.dz, w.gamma, rtol=rtol, atol=atol)
@@ -391,16 +393,22 @@ def test_mode_solver_converges_like_the_oracle():
     assert rel(host(g), phi * np.exp(-1j * st["mu"] * z)) < 1e-4
     # the whole solve in one persistent launch (every tile resident; a grid-wide exchange per
     # iteration instead of a kernel boundary): the same iterations and mode
+    # (complex64; complex128 keeps one kernel per iteration), also with the XCD-aware block order
     for dtype in ("c128", "c64"):
         mp = api.Mesh(mesh.xy, mesh.tri, V, None, dtype=dtype)
+        mp.tuning = {"fused": 3}
+        persist_ms = mp.time_kernels(dtau, 1.0, reps=20)["mode_persist"]["ms"]
+        say("  persistent mode iteration ms", dtype, persist_ms)
+        assert (persist_ms > 0) == (dtype == "c64")  # the path is live where it should be
         runs = {}
-        for fused in (2, 3):
-            mp.tuning = {"fused": fused}
+        for fused, x in ((2, 0), (3, 0), (3, 1)):
+            mp.tuning = {"fused": fused, "xcd_remap": x}
             fp = dev(start, dtype)
-            runs[fused] = (mp.find_mode(fp, 3.0, dtau, 1.0, tol=1e-10 if dtype == "c128" else 1e-4), host(fp))
-        say("  persistent mode solver", dtype, runs[2][0], runs[3][0])
-        assert runs[2][0]["iterations"] == runs[3][0]["iterations"]
-        assert rel(runs[3][1], runs[2][1]) < (1e-13 if dtype == "c128" else 1e-6)
+            runs[(fused, x)] = (mp.find_mode(fp, 3.0, dtau, 1.0, tol=1e-10 if dtype == "c128" else 1e-4), host(fp))
+        say("  persistent mode solver", dtype, runs[(2, 0)][0], runs[(3, 0)][0])
+        for key in ((3, 0), (3, 1)):
+            assert runs[(2, 0)][0]["iterations"] == runs[key][0]["iterations"], key
+            assert rel(runs[key][1], runs[(2, 0)][1]) < (1e-13 if dtype == "c128" else 1e-6), key
     # failures: no convergence in too few iterations (the field holds the last iterate),
     # a start without power, a step beyond the RK4 margin, a beta4 handle
     f = dev(start, "c128")
