@@ -386,7 +386,9 @@ enum {
   DEC_BPM_K_MODE_PERSIST = 11, /* one iteration inside a persistent mode-solver     */
                                /* launch of max(reps, 200) iterations (0: not used  */
                                /* by this handle)                                   */
-  DEC_BPM_NUM_KERNELS = 12
+  DEC_BPM_K_UNSPLIT_PERSIST = 12, /* one unsplit RK4 step inside a persistent launch */
+                                  /* of max(reps, 2000) steps (0: not used)          */
+  DEC_BPM_NUM_KERNELS = 13
 };
 int dec_bpm_time_kernels(dec_bpm_t h, double dz, double gamma, int32_t reps, double* ms, double* bytes,
                          void* stream);

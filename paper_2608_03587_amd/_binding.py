@@ -21,7 +21,7 @@ C64, C128 = 1, 2
 NL_DEC, NL_LUMPED = 0, 1
 OP_L, OP_L2, OP_H = 0, 1, 2
 K_KERR, K_STAGE, K_LAP, K_TILE_A, K_TILE_B, K_STEP, K_PERSIST, K_UNSPLIT, K_DP5, K_MODE, K_DP5_PERSIST, \
-    K_MODE_PERSIST, NUM_KERNELS = range(13)
+    K_MODE_PERSIST, K_UNSPLIT_PERSIST, NUM_KERNELS = range(14)
 
 ERROR_NAMES = {EINVAL: "EINVAL", EMESH: "EMESH", EUNSTABLE: "EUNSTABLE", ENOMEM: "ENOMEM", EHIP: "EHIP",
                ENONFINITE: "ENONFINITE", EWORKSPACE: "EWORKSPACE", ENODEVICE: "ENODEVICE"}

@@ -284,7 +284,8 @@ def _time_kernels(fn, h, dz, gamma, reps, stream):
     B.check(fn(h, float(dz), float(gamma), int(reps), ms, by, _stream(stream)))
     names = {B.K_KERR: "kerr", B.K_STAGE: "stage", B.K_LAP: "lap", B.K_TILE_A: "tile_a", B.K_TILE_B: "tile_b",
              B.K_STEP: "step", B.K_PERSIST: "persist", B.K_UNSPLIT: "unsplit", B.K_DP5: "dp5", B.K_MODE: "mode",
-             B.K_DP5_PERSIST: "dp5_persist", B.K_MODE_PERSIST: "mode_persist"}
+             B.K_DP5_PERSIST: "dp5_persist", B.K_MODE_PERSIST: "mode_persist",
+             B.K_UNSPLIT_PERSIST: "unsplit_persist"}
     return {names[k]: {"ms": ms[k], "bytes": by[k]} for k in range(B.NUM_KERNELS)}
 
 

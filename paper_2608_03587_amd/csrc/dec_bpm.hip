@@ -1630,6 +1630,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   by[DEC_BPM_K_MODE] = by[DEC_BPM_K_STEP];     // one mode iteration: the same data
   by[DEC_BPM_K_DP5_PERSIST] = by[DEC_BPM_K_STEP];
   by[DEC_BPM_K_MODE_PERSIST] = by[DEC_BPM_K_STEP];
+  by[DEC_BPM_K_UNSPLIT_PERSIST] = by[DEC_BPM_K_STEP];
   launch_fill<T>(d, E.psi, 0.3, 0.1, B, st);
   launch_fill<T>(d, E.ya, 0.2, -0.1, B, st);
   launch_fill<T>(d, E.yb, 0.2, -0.1, B, st);
@@ -1646,6 +1647,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
         (kind == DEC_BPM_K_DP5 && !(E.has_step && E.F == 1 && ensure_dp5_tiles<T>(E))) ||
         (kind == DEC_BPM_K_MODE && !(E.has_step && E.F == 1)) ||
         (kind == DEC_BPM_K_MODE_PERSIST && !(E.has_step && E.F == 1 && mode_persist_fits<T>(E))) ||
+        (kind == DEC_BPM_K_UNSPLIT_PERSIST && !(E.has_persist && !E.pst_own && persist_fits<T>(E, 1))) ||
         (kind == DEC_BPM_K_DP5_PERSIST &&
          !(E.has_step && E.F == 1 && ensure_dp5_tiles<T>(E) && dp5_persist_fits<T>(E))) ||
         (kind == DEC_BPM_K_PERSIST && !(E.has_persist && persist_fits<T>(E)))) {
@@ -1653,14 +1655,15 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       if (bytes) bytes[kind] = 0.0;
       continue;
     }
-    if (kind == DEC_BPM_K_PERSIST) {  // one launch of at least 2000 steps, time per step
+    if (kind == DEC_BPM_K_PERSIST || kind == DEC_BPM_K_UNSPLIT_PERSIST) {  // one launch of >= 2000 steps
       const TileOps<T> sp = E.ptiles().template ops<T>();
       const int steps = std::max(reps, 2000);  // the launch's fixed cost spread thin, as in a long propagate
+      const int body = kind == DEC_BPM_K_UNSPLIT_PERSIST ? 1 : 0;
       HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, 2, E.spin_limit, dz, gamma,
-                               E.pblock(), st));  // warm-up
+                               E.pblock(), st, body));  // warm-up
       HIP_OK(hipEventRecord(e0, st));
       HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, steps, E.spin_limit, dz,
-                               gamma, E.pblock(), st));
+                               gamma, E.pblock(), st, body));
       HIP_OK(hipEventRecord(e1, st));
       HIP_OK(hipEventSynchronize(e1));
       float t = 0;

@@ -225,6 +225,12 @@ def test_unsplit_rk4_matches_oracle(dtype, nl):
     # the persistent launch (every tile resident, one launch for all steps) runs the same
     # per-row arithmetic; it keeps the owned |v|^2 from the previous step where the tile kernel
     # recomputes it on load, so the two may differ by the contraction of that sum (ulps)
+    # (complex64: the step tiles; complex128's persistent tiles are its own, and its unsplit
+    # steps stay one kernel each)
+    m.tuning = {"fused": 3}
+    persist_ms = m.time_kernels(w.dz, w.gamma, reps=10)["unsplit_persist"]["ms"]
+    say("  persistent unsplit step ms", persist_ms)
+    assert (persist_ms > 0) == (dtype == "c64")
     for n in (1, 2, 37):
         outs = {}
         for fused in (2, 3):
