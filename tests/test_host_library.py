@@ -37,6 +37,25 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in lib.dec_bpm_version()
 
 
+def test_binding_constants_match_the_header():
+    """Every DEC_BPM_* enumerator and #define of the header has the value the
+    Python binding uses (error codes, dtypes, responses, timing classes)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    values = {m.group(1): int(m.group(2)) for m in re.finditer(r"\bDEC_BPM_([A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    values.update({m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+DEC_BPM_([A-Z0-9_]+)\s+\(?(-?\d+)\)?",
+                                                                       text)})
+    timing = {k: v for k, v in values.items() if k.startswith("K_") or k == "NUM_KERNELS"}
+    assert len(timing) >= 14
+    for name, v in timing.items():
+        assert getattr(B, name) == v, name
+    checked = len(timing)
+    for name, v in values.items():
+        if hasattr(B, name) and name not in timing:
+            assert getattr(B, name) == v, name
+            checked += 1
+    assert checked >= 20
+
+
 def _csr(ops):
     n = len(ops["h0"])
     return sp.csr_matrix((ops["K"], ops["col"], ops["row_ptr"]), shape=(n, n)), \
