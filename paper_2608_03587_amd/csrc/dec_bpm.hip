@@ -124,6 +124,9 @@ struct Engine {
   int32_t* nb_ptr = nullptr;
   int32_t* nb_list = nullptr;
   int32_t* pflags = nullptr;
+  // flag values of the next persistent launch start above pepoch (flags only
+  // grow); INT32_MAX: the flags hold values of another kind and are cleared first
+  int32_t pepoch = INT32_MAX;
   // complex128: the step tiles are cut for the one-kernel step's 100 KiB of LDS
   // (512 owned rows), too many to be resident at once; the persistent kernel
   // then gets tiles of its own (1024 owned rows, up to 150 KiB of LDS)
@@ -1001,6 +1004,20 @@ static void check_prop_args(const Engine& E, const void* field, double dz, int64
   if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
 }
 
+// Flag base of a persistent launch of n steps (it publishes at most
+// base + n + 1).  The flags are cleared only when the count would pass 2^30
+// or another kernel has used them.
+static PersistIO persist_io(Engine& E, int64_t n, hipStream_t st) {
+  if (E.pepoch > (int32_t(1) << 30) - int32_t(std::min<int64_t>(n, int64_t(1) << 29)) - 2) {
+    launch_zero_i32(E.ptiles().n_tiles, E.pflags, st);
+    E.pepoch = 0;
+  }
+  PersistIO io;
+  io.base = E.pepoch;
+  E.pepoch += int32_t(n) + 2;
+  return io;
+}
+
 // Middle steps (merged NL(dz)) through graph replays, then the remainder
 // eagerly; returns the buffer holding the state.
 template <typename T>
@@ -1016,7 +1033,7 @@ static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipSt
       void* b0 = state_before(E, 5, done);
       void* b1 = b0 == E.psi ? E.psi2 : E.psi;
       hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, E.pflags, E.flag,
-                                       k, E.spin_limit, dz, gamma, E.pblock(), st, 1);
+                                       k, E.spin_limit, dz, gamma, E.pblock(), st, 1, persist_io(E, k, st));
       if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     }
     return state_before(E, 5, count);
@@ -1028,7 +1045,7 @@ static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipSt
       void* b0 = state_before(E, 3, done);
       void* b1 = b0 == E.psi ? E.psi2 : E.psi;
       hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, E.pflags, E.flag,
-                                       k, E.spin_limit, dz, gamma, E.pblock(), st);
+                                       k, E.spin_limit, dz, gamma, E.pblock(), st, 0, persist_io(E, k, st));
       if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     }
     return state_before(E, 3, count);
@@ -1049,7 +1066,9 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
   const DevOps<T> d = E.ops<T>();
   const int B = E.block;
   const int mode = mode_of<T>(E);
-  launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
+  // one-field step tiles read the caller's field and write the result through the permutation
+  const bool io_tiles = mode >= 2 && E.F == 1;
+  if (!io_tiles) launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
   if (mode == 1) {
     const TileOps<T> tl = E.tiles<T>();
     // NL(dz/2) + stage 1: state -> psi2, y1 -> ya
@@ -1059,16 +1078,34 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, cur, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), st);
     launch_fused<T>(d, tl, FUSED_S4_NL, E.yb, cur, nxt, nullptr, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
     launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
-  } else if (mode >= 2) {
-    // NL(dz/2) in place, n-1 merged steps, then LIN(dz) + NL(dz/2)
+  } else if (mode == 3 && io_tiles && n <= (int64_t(1) << 30)) {
+    // the whole propagate in one persistent launch: NL(dz/2) of the caller's
+    // field, n - 1 merged steps, then LIN(dz) + NL(dz/2) into the caller's field
+    PersistIO io = persist_io(E, n, st);
+    io.in = field;
+    io.out = field;
+    io.perm = E.perm;
+    io.tau_first = io.tau_last = 0.5 * dz;
+    const hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, E.psi, E.psi2,
+                                           E.pflags, E.flag, int32_t(n), E.spin_limit, dz, gamma, E.pblock(), st, 0,
+                                           io);
+    if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+  } else if (io_tiles) {
+    // NL(dz/2) of the caller's field into psi (on the step tiles: the same
+    // per-row arithmetic as the persistent launch), n-1 merged steps, then
+    // LIN(dz) + NL(dz/2) straight into the caller's field
+    launch_kerr_tile<T>(d, E.stp.template ops<T>(), field, E.perm, E.psi, 0.5 * dz, gamma, E.sblock(), st);
+    void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
+    if (mode == 4)
+      launch_step_b4<T>(d, E.stp.template ops<T>(), cur, field, dz, 0.5 * dz, gamma, E.sblock(), st, E.perm, E.flag);
+    else
+      launch_step<T>(d, E.stp.template ops<T>(), cur, field, dz, 0.5 * dz, gamma, E.sblock(), st, E.perm, E.flag);
+  } else if (mode >= 2) {  // batched step tiles
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
     launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
     void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
     void* nxt = cur == E.psi ? E.psi2 : E.psi;
-    if (mode == 4)
-      launch_step_b4<T>(d, E.stp.template ops<T>(), cur, nxt, dz, 0.5 * dz, gamma, E.sblock(), st);
-    else
-      launch_step<T>(d, E.stp.template ops<T>(), cur, nxt, dz, 0.5 * dz, gamma, E.sblock(), st);
+    launch_step<T>(d, E.stp.template ops<T>(), cur, nxt, dz, 0.5 * dz, gamma, E.sblock(), st);
     launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
   } else {
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
@@ -1317,6 +1354,7 @@ static ModeResult find_mode_t(Engine& E, void* field, double power, double dtau,
   int K = 8;
   // every step tile resident: the whole iteration in one cooperative launch (complex64 tiles)
   if (E.fused == 3 && mode_persist_fits<T>(E)) {
+    E.pepoch = INT32_MAX;  // the mode launch counts its iterations in the same flags
     const hipError_t e = launch_mode_persist<T>(d, tl, E.psi, E.psi2, E.modectl, E.modepart, E.pflags, E.flag,
                                                 E.spin_limit, dtau, gamma, blk, st);
     if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
@@ -1659,11 +1697,23 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       const TileOps<T> sp = E.ptiles().template ops<T>();
       const int steps = std::max(reps, 2000);  // the launch's fixed cost spread thin, as in a long propagate
       const int body = kind == DEC_BPM_K_UNSPLIT_PERSIST ? 1 : 0;
+      // the split body as a propagate runs it: from a caller-order field (ya) to another (yb)
+      auto io = [&](int n) {
+        PersistIO r = persist_io(E, n, st);
+        if (body == 0) {
+          r.in = E.ya;
+          r.out = E.yb;
+          r.perm = E.perm;
+          r.tau_first = r.tau_last = 0.5 * dz;
+        }
+        return r;
+      };
       HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, 2, E.spin_limit, dz, gamma,
-                               E.pblock(), st, body));  // warm-up
+                               E.pblock(), st, body, io(2)));  // warm-up
+      const PersistIO timed = io(steps);
       HIP_OK(hipEventRecord(e0, st));
       HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, steps, E.spin_limit, dz,
-                               gamma, E.pblock(), st, body));
+                               gamma, E.pblock(), st, body, timed));
       HIP_OK(hipEventRecord(e1, st));
       HIP_OK(hipEventSynchronize(e1));
       float t = 0;
@@ -1699,6 +1749,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
         launch_diag<T>(d, E.psi, 0.0, E.partials, E.n_red_blocks, E.red_out, st);
         launch_mode_init(E.modectl, E.modearr, E.red_out, 1.0, 0.0, pass ? iters : 2, st);
         if (pass) HIP_OK(hipEventRecord(e0, st));
+        E.pepoch = INT32_MAX;  // the mode launch counts its iterations in the same flags
         HIP_OK(launch_mode_persist<T>(d, ts, E.psi, E.psi2, E.modectl, E.modepart, E.pflags, E.flag, E.spin_limit,
                                       dz, gamma, E.sblock(), st));
       }

@@ -1169,7 +1169,9 @@ struct StepTile {
   __device__ int32_t slot_row(int i) const { return ext[i]; }
   __device__ int nb(int j, int k) const { return q[j][k]; }
 
-  __device__ void init(const DevOps<T>& d, const TileOps<T>& tl, int64_t tile) {
+  // kerr_only: load the rows the NL substep alone needs (rings 0..1, the
+  // reach of the M gather), not every compute slot's
+  __device__ void init(const DevOps<T>& d, const TileOps<T>& tl, int64_t tile, bool kerr_only = false) {
     hd = tl.hdr + int64_t(tl.hdr_stride) * tile;  // hd[k]: slots in rings 0..k; hd[15]: rings
     ext = tl.ext + tile * int64_t(tl.ext_stride);
     const int32_t* __restrict__ lsl = tl.lsl + tile * int64_t(tl.lsl_stride);
@@ -1181,6 +1183,7 @@ struct StepTile {
     n3 = hd[R - 3];
     n4 = hd[R - 4];
     nNL = hd[0];
+    const int nRows = kerr_only ? hd[1] : n1;
     const int B = blockDim.x;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -1189,7 +1192,7 @@ struct StepTile {
       vv[j] = ww[j] = md[j] = T(0);
       int w = 0;
       int64_t base = 0;
-      if (i < n1) {
+      if (i < nRows) {
         const int32_t r = ext[i];
         rr[j] = r;
         vv[j] = d.v[r];
@@ -1394,6 +1397,45 @@ struct StepTile {
         C r;
         r.x = damp * (b.x * cs - b.y * sn);
         r.y = damp * (b.x * sn + b.y * cs);
+        out(i, rr[j], r);
+      }
+    }
+  }
+
+  // NL(tau) alone of a field held in the caller's vertex order (row r at
+  // src[perm[r]]), for the owned rows: |psi|^2 phi(w, tau) is staged in S on
+  // rings 0..1 (the reach of the M gather; ring 0 for the lumped form), then
+  // out(slot, r, value) receives each owned row's result.  Every thread of the
+  // workgroup must call it (it holds a barrier).
+  template <typename Out>
+  __device__ void kerr_from(const DevOps<T>& d, const C* __restrict__ src, const int32_t* __restrict__ perm, T* S,
+                            T tau, T gamma, Out out) const {
+    const int B = blockDim.x;
+    const int nS = DEC ? hd[1] : nNL;
+    C p[J];
+    T so[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < nS) {
+        p[j] = src[perm[rr[j]]];
+        so[j] = (p[j].x * p[j].x + p[j].y * p[j].y) * phi_w(ww[j], tau);
+        S[i] = so[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < nNL) {
+        T th = md[j] * so[j];
+        if constexpr (DEC) th = msum_w<KMAX>(wd[j], S, j, th);
+        const T damp = d_exp(-ww[j] * tau);
+        T sn, cs;
+        d_sincos(gamma * th, &sn, &cs);
+        C r;
+        r.x = damp * (p[j].x * cs - p[j].y * sn);
+        r.y = damp * (p[j].x * sn + p[j].y * cs);
         out(i, rr[j], r);
       }
     }
@@ -1845,9 +1887,24 @@ struct StepTile {
 };
 
 // One whole z step, LIN(h) then NL(tau), per tile of rows (five halo rings).
+// Stores a step's result: in device order, or (out_perm given) at the
+// caller's index out_perm[r], flagging a non-finite value in bit 0 of *flag.
+template <typename C>
+__device__ inline void put_result(C* __restrict__ out, const int32_t* __restrict__ out_perm, int* flag, int32_t r,
+                                  const C& v) {
+  if (out_perm) {
+    if (!(d_finite(v.x) && d_finite(v.y))) atomicOr(flag, 1);
+    out[out_perm[r]] = v;
+  } else {
+    out[r] = v;
+  }
+}
+
+// One whole z step: LIN(h) then NL(tau).  out_perm: see put_result.
 template <typename T, int KMAX, bool DEC, int J, bool CL = false>
 __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step(DevOps<T> d, TileOps<T> tl, const typename CT<T>::C* __restrict__ in_psi,
-                                               typename CT<T>::C* __restrict__ out_psi, T h, T tau, T gamma) {
+                                               typename CT<T>::C* __restrict__ out_psi, T h, T tau, T gamma,
+                                               const int32_t* __restrict__ out_perm, int* flag) {
   using C = typename CT<T>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t tile = logical_block(d.xcd_remap);
@@ -1860,8 +1917,27 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step(DevOps<T> d, 
   st.init(d, tl, tile);
   for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P.put(i, in_psi[st.slot_row(i)]);
   __syncthreads();
-  st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out_psi[r] = v; },
+  st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { put_result(out_psi, out_perm, flag, r, v); },
           [](int, int32_t, const C&) {});
+}
+
+// NL(tau) of the caller's field (caller order, row r at src[perm[r]]) into a
+// device-order state buffer, on the step tiles: the first half step of a
+// propagate, with the same per-row arithmetic as the persistent launch's.
+template <typename T, int KMAX, bool DEC, int J, bool CL = false>
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_kerr_tile(DevOps<T> d, TileOps<T> tl,
+                                                                        const typename CT<T>::C* __restrict__ src,
+                                                                        const int32_t* __restrict__ perm,
+                                                                        typename CT<T>::C* __restrict__ dst, T tau,
+                                                                        T gamma) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  T* S = reinterpret_cast<T*>(smem);
+  StepTile<T, KMAX, DEC, J, CL> st;
+  st.init(d, tl, tile, true);
+  st.kerr_from(d, src, perm, S, tau, gamma, [&](int, int32_t r, const C& v) { dst[r] = v; });
 }
 
 // One whole z step for a batched handle: workgroup b handles step tile
@@ -2455,7 +2531,8 @@ template <typename T, int KMAX, bool DEC, int J>
 __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_b4(DevOps<T> d, TileOps<T> tl,
                                                                      const typename CT<T>::C* __restrict__ in_psi,
                                                                      typename CT<T>::C* __restrict__ out_psi, T h,
-                                                                     T tau, T gamma) {
+                                                                     T tau, T gamma,
+                                                                     const int32_t* __restrict__ out_perm, int* flag) {
   using C = typename CT<T>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t tile = logical_block(d.xcd_remap);
@@ -2468,7 +2545,8 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_b4(DevOps<T> 
   st.init(d, tl, tile);
   for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P.put(i, in_psi[st.slot_row(i)]);
   __syncthreads();
-  st.step_b4(d, P, X, Y, Tb, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out_psi[r] = v; });
+  st.step_b4(d, P, X, Y, Tb, S, h, tau, gamma,
+             [&](int, int32_t r, const C& v) { put_result(out_psi, out_perm, flag, r, v); });
 }
 
 // The one-kernel step that also records, for the adjoint's forward recompute,
@@ -2673,29 +2751,49 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
 }
 
 // ---- persistent z stepping on resident tiles ----
-// n_steps merged z steps in one launch, one workgroup per tile, all resident
+// n_steps z steps in one launch, one workgroup per tile, all resident
 // (cooperative launch).  The operator rows stay in registers for the whole
 // launch; per step only the state crosses memory.  The state alternates
-// between buf0 (even steps) and buf1; after writing step s+1 a tile publishes
-// flags[tile] = s+1, and before reading step s it waits for every tile that
-// owns one of its halo rows to have published s.  The halo relation is
-// symmetric, so that wait also guarantees the neighbours have finished reading
-// the buffer this tile is about to overwrite.  Exchanged elements and flags are
-// agent-scope atomic accesses (coherent across XCDs); each wave waits for its
-// state stores to be acknowledged before the workgroup barrier that precedes
-// the flag store, and the state loads follow the barrier that ends the flag
-// wait, so no L2 write-back or invalidate is needed.  Each wait is bounded: after
-// spin_limit polls the tile sets bit 1 of *status and leaves, and its
-// neighbours then time out in turn, so every workgroup exits.
+// between buf0 (before even steps) and buf1.  Flags only grow: a tile
+// publishes flags[tile] = base + k once the state its step k - 1 produced is
+// stored (k = 0 being the starting state when the launch makes it itself), and
+// before reading a state it waits for every tile that owns one of its halo
+// rows to have published it.  The halo relation is symmetric, so that wait
+// also guarantees the neighbours have finished reading the buffer this tile is
+// about to overwrite.  Exchanged elements and flags are agent-scope atomic
+// accesses (coherent across XCDs); each wave waits for its state stores to be
+// acknowledged before the workgroup barrier that precedes the flag store, and
+// the state loads follow the barrier that ends the flag wait, so no L2
+// write-back or invalidate is needed.  Each wait is bounded: after spin_limit
+// polls the tile sets bit 1 of *status and leaves, and its neighbours then
+// time out in turn, so every workgroup exits.
+// With io.in (split-step body) the launch starts from the caller's field: each
+// tile applies NL(tau_first) to its owned rows (reading rings 0..1 through the
+// permutation) and publishes them as the starting state.  With io.out the last
+// step applies NL(tau_last) and writes the caller's field through the
+// permutation.  The caller's field is read only before a tile's first flag and
+// written only after its first wait, which every tile reading those rows has
+// passed, so out may alias in.
 // BODY 0: the merged split step; BODY 1: one unsplit classical RK4 step of the
 // whole right-hand side (the stage inputs and their |.|^2 double-buffered in
 // the same LDS; the owned state and its |.|^2 written back after the step).
 // CL: complex L weights (a perfectly matched layer), split-step body only.
+template <typename T>
+struct PersistArgs {
+  using C = typename CT<T>::C;
+  const C* in;
+  C* out;
+  const int32_t* perm;
+  int32_t base;
+  T tau_first, tau_last;
+};
+
 template <typename T, int KMAX, bool DEC, int J, int LS, int BODY, bool CL = false>
 __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, const int32_t* __restrict__ nb_ptr,
                                                   const int32_t* __restrict__ nb_list, typename CT<T>::C* buf0,
                                                   typename CT<T>::C* buf1, int32_t* flags, int32_t* status,
-                                                  int32_t n_steps, int32_t spin_limit, T h, T gamma) {
+                                                  int32_t n_steps, int32_t spin_limit, T h, T gamma,
+                                                  PersistArgs<T> io) {
   using C = typename CT<T>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t nb_s[64];
@@ -2722,19 +2820,30 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
   const int32_t nb0 = nb_ptr[tile];
   const int n_nb = nb_ptr[tile + 1] - nb0;
   if (threadIdx.x < n_nb) nb_s[threadIdx.x] = nb_list[nb0 + threadIdx.x];
+  const bool pro = BODY == 0 && io.in != nullptr;
+  if (pro) {  // the starting state: NL(tau_first) of the caller's field, owned rows
+    st.kerr_from(d, io.in, io.perm, S, io.tau_first, gamma, [&](int i, int32_t r, const C& v) {
+      coherent_store(buf0 + r, v);
+      P.put(i, v);
+    });
+    wait_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flags + tile, io.base + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   __syncthreads();
   for (int32_t s = 0; s < n_steps; ++s) {
     st.opaque_neighbours();
     const C* src = (s & 1) ? buf1 : buf0;
     C* dst = (s & 1) ? buf0 : buf1;
-    if (s > 0) {
+    const int32_t need = io.base + s + (pro ? 1 : 0);  // flag of the state step s reads
+    if (s > 0 || pro) {
       if (threadIdx.x < 64) {  // one wave polls all neighbour flags at once
         // lanes without a neighbour poll this tile's own flag, which already
-        // holds s (published at the end of the previous step)
+        // holds the value (published at the end of the previous step)
         const int32_t* fl = flags + (int(threadIdx.x) < n_nb ? nb_s[threadIdx.x] : int32_t(tile));
         bool ok = true;
         for (int32_t spins = 0;; ++spins) {
-          if (__all(__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= s)) break;
+          if (__all(__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need)) break;
           if (spins >= spin_limit) {
             ok = false;
             break;
@@ -2750,8 +2859,8 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
       if (abort_s) return;
     }
     // stage the state: the owned slots (ring 0) stay in LDS from the previous
-    // step, so after the first step only the halo is loaded
-    const int first = s == 0 ? 0 : st.nNL;
+    // step (or the prologue), so only the halo is loaded
+    const int first = (s == 0 && !pro) ? 0 : st.nNL;
     C pv[LS];  // issue every load before the first use
 #pragma unroll
     for (int l = 0; l < LS; ++l)
@@ -2767,24 +2876,34 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
         }
       }
     __syncthreads();
+    const bool fin = io.out != nullptr && s == n_steps - 1;  // the result goes to the caller's field
     if constexpr (BODY == 0) {
-      st.step(d, P, X, Y, S, h, h, gamma,
+      st.step(d, P, X, Y, S, h, fin ? io.tau_last : h, gamma,
               [&](int i, int32_t r, const C& v) {
-                coherent_store(dst + r, v);
-                P.put(i, v);  // the next step's owned state
+                if (fin) {
+                  put_result(io.out, io.perm, status, r, v);
+                } else {
+                  coherent_store(dst + r, v);
+                  P.put(i, v);  // the next step's owned state
+                }
               },
               [](int, int32_t, const C&) {});
     } else {
       // the last stage reads B only, so the owned state can go back into A
       st.step_unsplit(d, UA, UB, USA, USB, h, gamma, [&](int i, int32_t r, const C& v) {
-        coherent_store(dst + r, v);
-        UA[i] = v;
-        USA[i] = v.x * v.x + v.y * v.y;
+        if (fin) {
+          put_result(io.out, io.perm, status, r, v);
+        } else {
+          coherent_store(dst + r, v);
+          UA[i] = v;
+          USA[i] = v.x * v.x + v.y * v.y;
+        }
       });
     }
+    if (fin) break;
     wait_stores();
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flags + tile, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(flags + tile, need + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -3289,7 +3408,7 @@ void launch_bstep(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, 
 
 template <typename T>
 void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h, double tau,
-                 double gamma, int block, hipStream_t st) {
+                 double gamma, int block, hipStream_t st, const int32_t* out_perm, int* flag) {
   if (d.F > 1) {  // batched handle: VF fields per slot
     launch_bstep<T>(d, tl, in_psi, out_psi, h, tau, gamma, block, st);
     return;
@@ -3299,7 +3418,7 @@ void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, v
   const int J = (tl.max_compute + block - 1) / block;
 #define DECBPM_STEP(KM, DEC, JJ, CLX)                                                                          \
   hipLaunchKernelGGL((k_step<T, KM, DEC, JJ, CLX>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi), \
-                     DECBPM_M(T, out_psi), T(h), T(tau), T(gamma))
+                     DECBPM_M(T, out_psi), T(h), T(tau), T(gamma), out_perm, flag)
   // complex L weights (perfectly matched layer): their own instantiation
 #define DECBPM_STEP_J(KM, DEC)                                                   \
   if (tl.llwi) {                                                                 \
@@ -3501,13 +3620,13 @@ void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi
 
 template <typename T>
 void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
-                    double tau, double gamma, int block, hipStream_t st) {
+                    double tau, double gamma, int block, hipStream_t st, const int32_t* out_perm, int* flag) {
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
   const size_t shmem = size_t(tl.max_slots) * (4 * sizeof(typename CT<T>::C) + sizeof(T));
   const int J = (tl.max_compute + block - 1) / block;
 #define DECBPM_STEP4(KM, DEC, JJ)                                                                              \
   hipLaunchKernelGGL((k_step_b4<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi),  \
-                     DECBPM_M(T, out_psi), T(h), T(tau), T(gamma))
+                     DECBPM_M(T, out_psi), T(h), T(tau), T(gamma), out_perm, flag)
 #define DECBPM_STEP4_J(KM, DEC) \
   if (J <= 1) DECBPM_STEP4(KM, DEC, 1); else if (J == 2) DECBPM_STEP4(KM, DEC, 2); else DECBPM_STEP4(KM, DEC, 3);
   const bool dec = tl.lmw != nullptr;
@@ -3518,6 +3637,28 @@ void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi
   }
 #undef DECBPM_STEP4_J
 #undef DECBPM_STEP4
+}
+
+template <typename T>
+void launch_kerr_tile(const DevOps<T>& d, const TileOps<T>& tl, const void* src, const int32_t* perm, void* dst,
+                      double tau, double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * sizeof(T);
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_KT(KM, DEC, JJ, CLX)                                                                               \
+  hipLaunchKernelGGL((k_kerr_tile<T, KM, DEC, JJ, CLX>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, src), \
+                     perm, DECBPM_M(T, dst), T(tau), T(gamma))
+  // the operator rows are not used past rings 0..1, so complex L weights need no instance of their own
+#define DECBPM_KT_J(KM, DEC) \
+  if (J <= 1) DECBPM_KT(KM, DEC, 1, false); else if (J == 2) DECBPM_KT(KM, DEC, 2, false); else DECBPM_KT(KM, DEC, 3, false);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_KT_J(8, true) } else { DECBPM_KT_J(8, false) }
+  } else {
+    if (dec) { DECBPM_KT_J(12, true) } else { DECBPM_KT_J(12, false) }
+  }
+#undef DECBPM_KT_J
+#undef DECBPM_KT
 }
 
 template <typename T>
@@ -3616,19 +3757,21 @@ int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block, int bo
 template <typename T>
 hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_t* nb_ptr, const int32_t* nb_list,
                           void* buf0, void* buf1, int32_t* flags, int32_t* status, int32_t n_steps,
-                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st, int body) {
+                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st, int body,
+                          const PersistIO& io) {
   using C = typename CT<T>::C;
   const void* k = persist_kernel<T>(d, tl, block, body);
   if (!k) return hipErrorInvalidDeviceFunction;
-  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(tl.n_tiles, 256, 0)), dim3(256), 0, st, int64_t(tl.n_tiles), flags);
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
   DevOps<T> dd = d;
   TileOps<T> tt = tl;
   C* b0 = static_cast<C*>(buf0);
   C* b1 = static_cast<C*>(buf1);
   T th = T(h), tg = T(gamma);
+  PersistArgs<T> pa{static_cast<const C*>(io.in), static_cast<C*>(io.out), io.perm, io.base, T(io.tau_first),
+                    T(io.tau_last)};
   void* args[] = {&dd, &tt, const_cast<int32_t**>(&nb_ptr), const_cast<int32_t**>(&nb_list), &b0, &b1, &flags, &status,
-                  &n_steps, &spin_limit, &th, &tg};
+                  &n_steps, &spin_limit, &th, &tg, &pa};
   return hipLaunchCooperativeKernel(k, dim3(g), dim3(block), args, unsigned(persist_lds<T>(tl)), st);
 }
 
@@ -3736,6 +3879,10 @@ void launch_gdn_out(int64_t n, const int32_t* perm, const double* gdn, double* o
 #endif
 
 #if DECBPM_PART & 1
+void launch_zero_i32(int64_t n, int32_t* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(n, 256, 0)), dim3(256), 0, st, n, x);
+}
+
 void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, x);
 }
@@ -3765,10 +3912,12 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                    hipStream_t);                                                                 \
   template void launch_set_v<T>(int64_t, const T*, const double*, const int32_t*, T*, int, hipStream_t);          \
   template void launch_step<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double,   \
-                               int, hipStream_t);                                                                \
+                               int, hipStream_t, const int32_t*, int*);                                          \
+  template void launch_kerr_tile<T>(const DevOps<T>&, const TileOps<T>&, const void*, const int32_t*, void*,      \
+                                    double, double, int, hipStream_t);                                           \
   template int persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int, int);                                \
   template void launch_step_b4<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double, \
-                                  int, hipStream_t);                                                             \
+                                  int, hipStream_t, const int32_t*, int*);                                       \
   template void launch_unsplit<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, int,    \
                                   hipStream_t);                                                                  \
   template void launch_lapc<T>(const DevOps<T>&, const void*, const void*, double, double, void*, int,         \
@@ -3792,7 +3941,7 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                    double, double, int, hipStream_t);                                            \
   template hipError_t launch_persist<T>(const DevOps<T>&, const TileOps<T>&, const int32_t*, const int32_t*, void*, \
                                         void*, int32_t*, int32_t*, int32_t, int32_t, double, double, int,        \
-                                        hipStream_t, int);                                                       \
+                                        hipStream_t, int, const PersistIO&);                                     \
   template void launch_bstage<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*, void*, \
                                  double, void*, double, hipStream_t);                                            \
   template void launch_blap<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, hipStream_t);           \

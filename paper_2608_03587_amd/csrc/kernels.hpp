@@ -173,15 +173,24 @@ void launch_bkerr(const DevOps<T>& d, const TileOps<T>& tl, const void* psi_in, 
 
 // One kernel per merged Strang step on tiles with five halo rings (hdr holds
 // the six ring counts in [0..5], the ext and slice-table bases in [6], [7]):
-// out_psi = NL_tau(LIN_h(in_psi)) on the owned rows.
+// out_psi = NL_tau(LIN_h(in_psi)) on the owned rows.  With out_perm the result
+// goes to out_psi[out_perm[r]] (the caller's order) and a non-finite value
+// sets bit 0 of *flag.
 template <typename T>
 void launch_step(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h, double tau,
-                 double gamma, int block, hipStream_t st);
+                 double gamma, int block, hipStream_t st, const int32_t* out_perm = nullptr, int* flag = nullptr);
 // One whole z step with the beta4 L^2 term (two gathers per stage) on tiles of
-// 8 halo rings (9 with the triangle-averaged Kerr term).
+// 8 halo rings (9 with the triangle-averaged Kerr term); out_perm as above.
 template <typename T>
 void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
-                    double tau, double gamma, int block, hipStream_t st);
+                    double tau, double gamma, int block, hipStream_t st, const int32_t* out_perm = nullptr,
+                    int* flag = nullptr);
+// NL(tau) of the caller's field (caller order: row r at src[perm[r]]) into
+// the device-order buffer dst, on the step tiles (any ring count): the first
+// half step of a propagate, with the persistent launch's per-row arithmetic.
+template <typename T>
+void launch_kerr_tile(const DevOps<T>& d, const TileOps<T>& tl, const void* src, const int32_t* perm, void* dst,
+                      double tau, double gamma, int block, hipStream_t st);
 // One step of classical RK4 on the whole right-hand side (the Kerr term and
 // the absorber inside every stage) on the five-ring step tiles (four rings are
 // used: one per stage).
@@ -277,10 +286,28 @@ void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_i
                      const void* y3, const void* y2, const void* y1, const void* fa0, void* lam_out, double* gdn,
                      double h, double tau, double gamma, int block, hipStream_t st);
 
-// Persistent z stepping (n_steps merged steps in one cooperative launch, one
+// Where a persistent launch takes its state from and puts its result.
+// in: the caller's field (caller order, row r at in[perm[r]]); the launch
+//     starts with NL(tau_first) of it (split-step body only).  nullptr: the
+//     state before the first step is already in buf0 (device order).
+// out: the caller's field for the result (caller order); the last step then
+//     uses NL(tau_last) and writes there, setting bit 0 of *status for a
+//     non-finite value.  nullptr: every step is a merged step (NL(h)) and the
+//     result stays in buf0/buf1 (buf0 after an even step count).
+// out may alias in.  base: a value no flag exceeds before the launch; the
+// launch publishes base + 1, base + 2, ... (at most base + n_steps + 1).
+struct PersistIO {
+  const void* in = nullptr;
+  void* out = nullptr;
+  const int32_t* perm = nullptr;
+  int32_t base = 0;
+  double tau_first = 0.0, tau_last = 0.0;
+};
+
+// Persistent z stepping (n_steps steps in one cooperative launch, one
 // resident workgroup per tile of the five-ring step tiles).  nb_ptr/nb_list:
-// per tile, the other tiles owning its halo rows.  flags: n_tiles ints of
-// scratch (cleared by the launch).  status: bit 1 is set if a neighbour wait
+// per tile, the other tiles owning its halo rows.  flags: n_tiles ints that
+// only grow (see PersistIO::base).  status: bit 1 is set if a neighbour wait
 // timed out.  Returns the launch status (the launch fails if the tiles cannot
 // all be resident).  persist_capacity: resident workgroups the device holds
 // for this kernel at `block` threads (0 if the tiles do not fit the kernel).
@@ -291,7 +318,10 @@ int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block, int bo
 template <typename T>
 hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_t* nb_ptr, const int32_t* nb_list,
                           void* buf0, void* buf1, int32_t* flags, int32_t* status, int32_t n_steps,
-                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st, int body = 0);
+                          int32_t spin_limit, double h, double gamma, int block, hipStream_t st, int body,
+                          const PersistIO& io);
+// n ints set to 0
+void launch_zero_i32(int64_t n, int32_t* x, hipStream_t st);
 
 // out_rec (may be null) receives, for owned rows, y2 (FUSED_S2_S3) or the
 // state before the Kerr substep (S4 kinds): the adjoint's segment recompute.
