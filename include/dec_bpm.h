@@ -177,6 +177,17 @@ int dec_bpm_export_operators(dec_bpm_t h, double* h0, double* v, double* w, int6
 int dec_bpm_export_pml(dec_bpm_t h, double* h0p, double* kp);
 
 /*
+ * Diagnostics of the vertex order (not in the paper): the tile of the current
+ * launch mode that owns each vertex.  The library renumbers the vertices
+ * along a Hilbert curve and cuts that order into tiles of *rows_per_tile
+ * consecutive rows; tile[i] is the tile of caller vertex i, or -1 (and
+ * *rows_per_tile = -1) when the launch mode steps without tiles or the
+ * handle is host-only.  tile: host array of n_vert ints, or NULL;
+ * rows_per_tile: host int, or NULL.  Errors: EINVAL.
+ */
+int dec_bpm_vertex_tiles(dec_bpm_t h, int32_t* tile, int32_t* rows_per_tile);
+
+/*
  * Set the per-vertex index perturbation dn (added to v after averaging,
  * unit coupling); dn_dev is a device array of n_vert doubles in caller order,
  * or NULL to reset to 0.  Synchronises (dn is also folded into the stability

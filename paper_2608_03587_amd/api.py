@@ -128,6 +128,13 @@ class Mesh:
                                            _ptr(m, ctypes.c_double)))
         return dict(h0=h0, v=v, w=w, row_ptr=rp, col=col, K=k, QtDQ=m)
 
+    def vertex_tiles(self):
+        """(tile of each caller vertex in the current launch mode, rows per tile); -1 without tiles."""
+        tile = np.empty(self.n_vert, dtype=np.int32)
+        ts = ctypes.c_int32(0)
+        B.check(B.lib().dec_bpm_vertex_tiles(self._h, _ptr(tile, ctypes.c_int32), ctypes.byref(ts)))
+        return tile, ts.value
+
     def export_pml(self):
         """Complex-stretched dual areas and K (pattern of ``export_operators``) of a PML handle."""
         ops = self.export_operators()

@@ -496,6 +496,9 @@ static void upload_tiles(Engine& E, const HostTiles& H, bool dec, int64_t n, Dev
 template <typename T>
 static void build_tiles(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
                         const std::vector<double>& alw, const std::vector<double>& amw, bool dec) {
+  // the tile kernels unroll the neighbour loop to at most 12 entries; wider
+  // rows (degree 13 and 14 pass the 25-degree angle bound) take the row kernels
+  if (E.wmax > 12) return;
   HostTiles H;
   for (int ts = E.tile_size; ts >= 64; ts /= 2) {
     if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, 3, 3, H)) continue;
@@ -2100,6 +2103,23 @@ int dec_bpm_export_operators(dec_bpm_t h, double* h0, double* v, double* w, int6
   if (col) std::copy(A.col.begin(), A.col.end(), col);
   if (kval) std::copy(A.k.begin(), A.k.end(), kval);
   if (mval) std::copy(A.qdq.begin(), A.qdq.end(), mval);
+  ABI_CATCH
+}
+
+int dec_bpm_vertex_tiles(dec_bpm_t h, int32_t* tile, int32_t* rows_per_tile) {
+  ABI_TRY
+  need(h);
+  Engine& E = h->E;
+  int ts = -1;
+  if (E.on_device) {
+    const int mode = E.dtype == DEC_BPM_C64 ? decbpm::mode_of<float>(E) : decbpm::mode_of<double>(E);
+    if (mode == 3) ts = E.ptiles().TS;
+    else if (mode >= 2) ts = E.stp.TS;
+    else if (mode == 1) ts = E.tl.TS;
+  }
+  if (rows_per_tile) *rows_per_tile = ts;
+  if (tile)
+    for (int64_t i = 0; i < h->A.n; ++i) tile[i] = ts > 0 ? h->A.iperm[i] / ts : -1;
   ABI_CATCH
 }
 

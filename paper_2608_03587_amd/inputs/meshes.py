@@ -39,6 +39,7 @@ __all__ = [
     "regular_grid_mesh",
     "hex_patch_mesh",
     "random_delaunay_mesh",
+    "wheel_disk_mesh",
 ]
 
 
@@ -313,3 +314,29 @@ def random_delaunay_mesh(n: int, seed: int, min_angle: float = 0.0) -> Mesh:
     pts = rng.uniform(0.0, 1.0, (n, 2))
     mesh, _ = _finish(pts, {"kind": "random", "n": n}, min_angle)
     return mesh
+
+
+def wheel_disk_mesh(R: float = 10.0, h: float = 0.3, seed: int = 5, spokes: int = 14,
+                    centres=((0.0, 0.0), (3.0, 2.0)), min_angle: float = 25.0) -> Mesh:
+    """Disk of radius ``R`` (as ``disk_mesh``) with a wheel around each centre: the
+    centre vertex, ``spokes`` points on a circle of radius ``h`` and a second
+    ring at ``1.8 h`` (half a spoke out of phase), the lattice cleared within
+    ``2.4 h``.  The centres get degree ``spokes``: 14 is the most a vertex can
+    have while every angle stays at least 25 degrees (360/14 = 25.7)."""
+    spacing = 2.0 * math.pi * h / spokes
+
+    def build(rng):
+        p = _hex_lattice(-R, R, -R, R, h)
+        p = p + rng.uniform(-0.05 * h, 0.05 * h, p.shape)
+        p = p[np.hypot(p[:, 0], p[:, 1]) < R - 0.75 * h]
+        for c in centres:
+            p = p[np.hypot(p[:, 0] - c[0], p[:, 1] - c[1]) > 2.4 * h]
+        parts = [p, _ring(R, round(2.0 * math.pi * R / h), rng)]
+        for c in centres:
+            parts.append(np.array([c], dtype=np.float64))
+            parts.append(_ring(h, spokes, rng, centre=c, phase=0.0))
+            parts.append(_ring(1.8 * h, round(0.55 * 2.0 * math.pi * 1.8 * h / spacing), rng, centre=c,
+                               phase=math.pi / spokes))
+        return _finish(np.concatenate(parts), {"kind": "wheel_disk", "R": R, "h": h, "spokes": spokes}, min_angle)
+
+    return _retry(build, seed, min_angle)
