@@ -188,24 +188,36 @@ int dec_bpm_export_pml(dec_bpm_t h, double* h0p, double* kp);
 int dec_bpm_vertex_tiles(dec_bpm_t h, int32_t* tile, int32_t* rows_per_tile);
 
 /*
- * Set the per-vertex index perturbation dn (added to v after averaging,
- * unit coupling); dn_dev is a device array of n_vert doubles in caller order,
+ * Set the per-vertex index perturbation dn: the design variable of the
+ * structure optimisation the paper motivates (Abstract, Conclusion); it
+ * enters the potential of Eq. 11 as v + dn (added after the triangle-to-vertex
+ * averaging of "Discrete Hodge star", unit coupling; derived, the paper gives
+ * no coupling).  dn_dev is a device array of n_vert doubles in caller order,
  * or NULL to reset to 0.  Synchronises (dn is also folded into the stability
- * bound on the host).
+ * bound on the host).  Errors: EINVAL (misaligned pointer), EUNSTABLE is
+ * reported by the next propagate if dn pushes dz rho(H_lin) past the margin.
  */
 int dec_bpm_set_index_perturbation(dec_bpm_t h, const double* dn_dev, void* stream);
 
 /* Operator application (parity hooks for the hot kernels), caller order:
- *   DEC_BPM_OP_L:  y = L x;   DEC_BPM_OP_L2: y = L (L x);
- *   DEC_BPM_OP_H:  y = H_lin x.
- * x and y are distinct device complex vectors of n_vert entries. */
+ *   DEC_BPM_OP_L:  y = L x          (Eq. 11's stiffness part, Table I Laplacian row);
+ *   DEC_BPM_OP_L2: y = L (L x)      (Table I, cascaded higher-order row);
+ *   DEC_BPM_OP_H:  y = H_lin x      (the linear part of Eq. 10 with Eq. 11).
+ * x and y are distinct device complex vectors of n_vert entries (caller-owned).
+ * Errors: EINVAL (bad op, NULL or aliased vectors), ENODEVICE, EHIP. */
 enum { DEC_BPM_OP_L = 0, DEC_BPM_OP_L2 = 1, DEC_BPM_OP_H = 2 };
 int dec_bpm_apply(dec_bpm_t h, int op, const void* x, void* y, void* stream);
 
-/* One Kerr/absorber substep NL(tau), in place (caller order). */
+/* One Kerr/absorber substep NL(tau), in place (caller order): the exact flow
+ * of the nonlinear term of Eq. 10 with M from Eq. 14 (or the lumped form) and
+ * the absorbing imaginary potential (Conclusion: absorbing boundaries); the
+ * flow itself is derived (|psi_p| decays as e^{-w tau}, so the phase
+ * integrates in closed form).  Errors: EINVAL, ENODEVICE, EHIP. */
 int dec_bpm_kerr_step(dec_bpm_t h, void* field, double tau, double gamma, void* stream);
 
-/* One linear RK4 step LIN(h) of dPsi/dz = -i H_lin Psi, in place. */
+/* One linear RK4 step LIN(h) of dPsi/dz = -i H_lin Psi (Eq. 10 without its
+ * nonlinear term; the explicit RK4 of the Introduction), in place, caller
+ * order.  Errors: EINVAL, EUNSTABLE, ENODEVICE, EHIP. */
 int dec_bpm_linear_step(dec_bpm_t h, void* field, double dz, void* stream);
 
 /*
@@ -281,7 +293,8 @@ int dec_bpm_find_mode(dec_bpm_t h, void* field, double power, double dtau, doubl
                       int64_t max_iter, double* mu, double* residual, int64_t* iterations, void* stream);
 
 /* Synchronise `stream` and return ENONFINITE if the last propagate produced a
- * non-finite value (the flag is cleared), else OK. */
+ * non-finite value, or a persistent launch's neighbour wait timed out (the
+ * flag is cleared), else OK.  Not in the paper: a health check of the run. */
 int dec_bpm_check_finite(dec_bpm_t h, void* stream);
 
 /*
@@ -289,17 +302,28 @@ int dec_bpm_check_finite(dec_bpm_t h, void* stream);
  *   power       = sum_p H0_p |psi_p|^2 (conserved without absorber)
  *   hamiltonian = Psi^H H0 H_lin Psi - (gamma/2) sum_t chi_t |t| (mean_t |psi|^2)^2
  *                 (lumped: - (gamma/2) sum_p H0_p chibar_p |psi_p|^4).
- * Either output pointer may be NULL.
+ * Derived from Eq. 10-14 (not printed in the paper): the power is the
+ * discrete L2 norm built from the Hodge star H0 that the semi-discrete flow
+ * conserves, and the Hamiltonian satisfies i H0 dPsi/dz = dE/d conj(Psi) for
+ * Eq. 10 with Eq. 14.  Either output pointer may be NULL.  Errors: EINVAL,
+ * ENODEVICE, EHIP.
  */
 int dec_bpm_diagnostics(dec_bpm_t h, const void* field, double gamma, double* power, double* hamiltonian,
                         void* stream);
 
-/* H0-weighted inner product c = sum_p H0_p conj(a_p) b_p; synchronises. */
+/* H0-weighted inner product c = sum_p H0_p conj(a_p) b_p (the discrete L2
+ * product of 0-forms through the Hodge star H0, "Discrete Hodge star"; derived:
+ * the overlap objective of the gradient runs), conjugating its first argument,
+ * FP64 accumulation; synchronises.  a, b: device complex vectors, caller order.
+ * Errors: EINVAL, ENODEVICE, EHIP. */
 int dec_bpm_overlap(dec_bpm_t h, const void* a, const void* b, double* re, double* im, void* stream);
 
 /*
  * Checkpointed forward sweep and its adjoint (gradients of a real objective J
- * of the final field).  Gradients follow g = dJ/dRe + i dJ/dIm.
+ * of the final field): the gradient loop of the structure optimisation the
+ * paper motivates (Abstract, Conclusion).  The adjoint is derived here as the
+ * exact reverse of the discrete Strang step built from Eq. 10-14 (the paper
+ * gives no gradient formulation).  Gradients follow g = dJ/dRe + i dJ/dIm.
  * dec_bpm_workspace_size gives the bytes of caller-owned device workspace for
  * a run of n_steps with checkpoints every `every` steps (0 = ceil(sqrt(n))).
  * dec_bpm_forward_checkpointed propagates `field` in place like
@@ -318,24 +342,42 @@ int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_step
                     void* workspace, size_t ws_bytes, void* grad_field0, double* grad_dn, void* stream);
 
 /*
- * Batched propagation of many fields on many meshes in one launch per kernel
- * stage.  All meshes must share dtype, p1, beta4 and nonlinearity mode and
- * carry `fields_per_mesh` fields each.  The packed field layout is
+ * Batched propagation of many launch fields on many meshes at once (the
+ * paper's use case of sweeping fibre cross-sections and launch conditions,
+ * Abstract and Conclusion; each field follows Eq. 10 exactly as
+ * dec_bpm_propagate would advance it alone).  All meshes must share dtype,
+ * p1, beta4 and nonlinearity mode, and none may carry a PML, L^3, L^4 or a
+ * non-Kerr response.  fields_per_mesh[m] (1 to 4096) is the number of fields
+ * on mesh m; counts may differ between meshes.  The packed field layout is
  * field-minor, per mesh in the order given: element (mesh m, caller vertex i,
- * field f) sits at complex offset base_m + i * fields_per_mesh + f, with
- * base_m = fields_per_mesh * (n_0 + ... + n_{m-1}).  The batch holds its own
- * copy of the operators; the mesh handles may be destroyed afterwards.
+ * field f < F_m) sits at complex offset base_m + i * F_m + f, with
+ * base_m = n_0 F_0 + ... + n_{m-1} F_{m-1}.  The batch holds its own copy of
+ * the operators; the mesh handles may be destroyed afterwards; the host array
+ * fields_per_mesh is copied.  Errors: EINVAL (NULL or bad arguments, meshes
+ * that do not match), ENOMEM, EHIP.
  */
-int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, int32_t fields_per_mesh,
+int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, const int32_t* fields_per_mesh,
                          dec_bpm_batch_t* out);
+/* Releases the batch's device memory (NULL is a no-op). */
 void dec_bpm_batch_destroy(dec_bpm_batch_t b);
-/* Total packed complex elements (sum_m n_m * fields_per_mesh). */
+/* Total packed complex elements (sum_m n_m * fields_per_mesh[m]).  Errors: EINVAL. */
 int dec_bpm_batch_size(dec_bpm_batch_t b, int64_t* n_elems);
+/* n_steps Strang steps of length dz of every field, in place in the packed
+ * layout above (caller-owned device memory, dec_bpm_batch_size elements);
+ * the same scheme and arguments as dec_bpm_propagate (Eq. 10-14), each field
+ * on its own mesh.  Errors: EINVAL, EUNSTABLE, EHIP, ENODEVICE (a batch of
+ * host-only meshes).  Non-finite results are flagged on the device and
+ * reported by dec_bpm_batch_check_finite. */
 int dec_bpm_batch_propagate(dec_bpm_batch_t b, void* packed_fields, double dz, int64_t n_steps, double gamma,
                             void* stream);
+/* As dec_bpm_check_finite, for a batch. */
+int dec_bpm_batch_check_finite(dec_bpm_batch_t b, void* stream);
 
 /*
- * Launch tuning.  dec_bpm_autotune times candidate launch shapes (unfused:
+ * Launch tuning (not in the paper: how the same arithmetic is scheduled on the
+ * device; no call here changes a result beyond rounding order, and the
+ * one-kernel and persistent split steps give identical bits).
+ * dec_bpm_autotune times candidate launch shapes (unfused:
  * block size; fused LDS-tiled path: threads per tile; both: z steps per
  * hipGraph and the XCD-aware block mapping) on the handle's own work buffers
  * with HIP events and keeps the fastest; the result is cached in the JSON file
@@ -374,7 +416,8 @@ int dec_bpm_batch_get_tuning(dec_bpm_batch_t b, dec_bpm_tuning* t);
 int dec_bpm_batch_set_tuning(dec_bpm_batch_t b, const dec_bpm_tuning* t);
 
 /*
- * Per-kernel timing with HIP events on `stream`: each kernel class is
+ * Per-kernel timing (measurement support, not in the paper) with HIP events on
+ * `stream`: each kernel class is
  * captured `reps` times back to back in a hipGraph and timed; the mean device
  * time per launch in milliseconds goes to ms[DEC_BPM_NUM_KERNELS] and the
  * algorithmic bytes one launch moves to bytes[DEC_BPM_NUM_KERNELS] (either may

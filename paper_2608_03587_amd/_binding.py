@@ -90,7 +90,8 @@ _SIGNATURES = [
     ("dec_bpm_workspace_size", c_int, [c_vp, c_i64, c_i64, P(c_sz)]),
     ("dec_bpm_forward_checkpointed", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_i64, c_vp, c_sz, c_vp]),
     ("dec_bpm_adjoint", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_i64, c_vp, c_sz, c_vp, c_vp, c_vp]),
-    ("dec_bpm_batch_create", c_int, [P(c_vp), c_i32, c_i32, P(c_vp)]),
+    ("dec_bpm_batch_check_finite", c_int, [c_vp, c_vp]),
+    ("dec_bpm_batch_create", c_int, [P(c_vp), c_i32, P(c_i32), P(c_vp)]),
     ("dec_bpm_batch_destroy", None, [c_vp]),
     ("dec_bpm_batch_size", c_int, [c_vp, P(c_i64)]),
     ("dec_bpm_batch_propagate", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_vp]),

@@ -7,13 +7,26 @@ a machine without a GPU, or with the library unbuilt, raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import math
+import weakref
 
 import numpy as np
 import torch
 
 from . import _binding as B
+
+# Live handles, released before the interpreter shuts down: freeing device memory
+# and graphs from finalisers that run during shutdown can reach a HIP runtime (or
+# a profiler attached to it) that has already been torn down.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_LIVE):
+        obj.close()
 
 __all__ = ["Mesh", "Batch", "DecBpmFunction", "propagate_with_grad", "DecBpmError"]
 
@@ -90,12 +103,17 @@ class Mesh:
         self._destroy = L.dec_bpm_destroy
         self.n_vert = xy.shape[0]
         self.n_tri = tri.shape[0]
+        _LIVE.add(self)
 
-    def __del__(self):
+    def close(self):
+        """Release the handle's device memory now (idempotent); the object is unusable afterwards."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             self._destroy(h)
-            self._h = None
+        self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
 
     @property
     def handle(self):
@@ -297,38 +315,54 @@ def _time_kernels(fn, h, dz, gamma, reps, stream):
 
 
 class Batch:
-    """Many fields on many meshes advanced together (field-minor packing)."""
+    """Many fields on many meshes advanced together.
 
-    def __init__(self, meshes, fields_per_mesh: int):
+    ``fields_per_mesh``: one count for every mesh, or a list with one count per
+    mesh (counts may differ).  Packed layout: per mesh in order, field-minor
+    (``[vertex][field]``) with that mesh's own field count."""
+
+    def __init__(self, meshes, fields_per_mesh):
+        counts = [int(fields_per_mesh)] * len(meshes) if np.isscalar(fields_per_mesh) else \
+            [int(f) for f in fields_per_mesh]
+        if len(counts) != len(meshes):
+            raise ValueError("fields_per_mesh needs one count per mesh")
         arr = (ctypes.c_void_p * len(meshes))(*[m.handle.value for m in meshes])
+        fpm = np.ascontiguousarray(counts, dtype=np.int32)
         h = ctypes.c_void_p()
-        B.check(B.lib().dec_bpm_batch_create(arr, len(meshes), int(fields_per_mesh), ctypes.byref(h)))
+        B.check(B.lib().dec_bpm_batch_create(arr, len(meshes), _ptr(fpm, ctypes.c_int32), ctypes.byref(h)))
         self._h = h
         self._destroy = B.lib().dec_bpm_batch_destroy
+        _LIVE.add(self)
         self.meshes = list(meshes)
-        self.F = int(fields_per_mesh)
+        self.counts = counts
+        self.F = counts[0] if len(set(counts)) == 1 else None  # the common count, if there is one
         self.torch_dtype = meshes[0].torch_dtype
         n = ctypes.c_int64()
         B.check(B.lib().dec_bpm_batch_size(h, ctypes.byref(n)))
         self.n_elems = n.value
-        self.offsets = np.cumsum([0] + [m.n_vert * self.F for m in meshes])
+        self.offsets = np.cumsum([0] + [m.n_vert * f for m, f in zip(meshes, counts)])
 
-    def __del__(self):
+    def close(self):
+        """Release the batch's device memory now (idempotent)."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             self._destroy(h)
-            self._h = None
+        self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
 
     def pack(self, fields_per_mesh_list):
-        """Pack a list (per mesh) of [F, N_m] complex tensors into the field-minor layout."""
+        """Pack a list (per mesh) of [F_m, N_m] complex tensors into the field-minor layout."""
         parts = [f.transpose(0, 1).contiguous().reshape(-1) for f in fields_per_mesh_list]
         return torch.cat(parts)
 
     def unpack(self, packed):
+        """Views [F_m, N_m] of each mesh's fields in a packed tensor."""
         out = []
         for m, mesh in enumerate(self.meshes):
             seg = packed[self.offsets[m]:self.offsets[m + 1]]
-            out.append(seg.reshape(mesh.n_vert, self.F).transpose(0, 1))
+            out.append(seg.reshape(mesh.n_vert, self.counts[m]).transpose(0, 1))
         return out
 
     def propagate(self, packed: torch.Tensor, dz, n_steps, gamma=1.0, stream=None):
@@ -338,6 +372,9 @@ class Batch:
         B.check(B.lib().dec_bpm_batch_propagate(self._h, ctypes.c_void_p(packed.data_ptr()), float(dz), int(n_steps),
                                                 float(gamma), _stream(stream)))
         return packed
+
+    def check_finite(self, stream=None):
+        B.check(B.lib().dec_bpm_batch_check_finite(self._h, _stream(stream)))
 
     def time_kernels(self, dz, gamma=1.0, reps=20, stream=None):
         return _time_kernels(B.lib().dec_bpm_batch_time_kernels, self._h, dz, gamma, reps, stream)

@@ -84,6 +84,12 @@ struct Engine {
   int dtype = DEC_BPM_C64;
   int64_t n_rows = 0;  // device rows
   int32_t F = 1;
+  // batches: fields of each mesh in the caller's layout (the device carries F,
+  // at least the largest, per row), and per device row its first caller
+  // element and its mesh's field count
+  std::vector<int32_t> fpm;
+  int64_t* bcbase = nullptr;
+  int32_t* bfcount = nullptr;
   double p1 = 0.5, beta4 = 0.0;
   double p3 = 0.0, p4 = 0.0;  // coefficients of L^3, L^4
   int nk = DEC_BPM_N_KERR;    // Kerr response
@@ -733,6 +739,20 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   E.h0c = static_cast<double*>(p);
   upload(E, p, perm);
   E.perm = static_cast<int32_t*>(p);
+  if (E.F > 1) {  // caller element of each device row's first field
+    std::vector<int64_t> ebase(meshes.size() + 1, 0), cbase(n);
+    std::vector<int32_t> fcount(n);
+    for (size_t m = 0; m < meshes.size(); ++m) ebase[m + 1] = ebase[m] + meshes[m]->n * E.fpm[m];
+    for (int64_t r = 0; r < n; ++r) {
+      const int m = row_mesh[r];
+      cbase[r] = ebase[m] + (int64_t(perm[r]) - mesh_off[m]) * E.fpm[m];
+      fcount[r] = E.fpm[m];
+    }
+    upload(E, p, cbase);
+    E.bcbase = static_cast<int64_t*>(p);
+    upload(E, p, fcount);
+    E.bfcount = static_cast<int32_t*>(p);
+  }
   if (E.F == 1 && E.beta4 == 0.0 && !pml && !E.general()) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
   if (!E.general()) build_step_tiles<T>(E, arp, acol, alw, amw, any_dec, pml ? &alwi : nullptr);
   if (pml && !E.has_step)
@@ -1063,6 +1083,22 @@ static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipSt
   return state_before(E, mode, count);
 }
 
+// The caller's field into device order (psi), and a device-order state back.
+template <typename T>
+static void field_in(const Engine& E, const DevOps<T>& d, const void* field, void* dst, hipStream_t st) {
+  if (E.bcbase)
+    launch_bperm<T>(d, E.bcbase, E.bfcount, field, dst, false, nullptr, E.block, st);
+  else
+    launch_perm_in<T>(d, E.perm, field, dst, 0, E.block, st);
+}
+template <typename T>
+static void field_out(const Engine& E, const DevOps<T>& d, const void* src, void* field, hipStream_t st) {
+  if (E.bcbase)
+    launch_bperm<T>(d, E.bcbase, E.bfcount, src, field, true, E.flag, E.block, st);
+  else
+    launch_perm_out<T>(d, E.perm, src, field, 0, E.flag, E.block, st);
+}
+
 template <typename T>
 static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gamma, hipStream_t st) {
   if (n == 0) return;
@@ -1071,7 +1107,7 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
   const int mode = mode_of<T>(E);
   // one-field step tiles read the caller's field and write the result through the permutation
   const bool io_tiles = mode >= 2 && E.F == 1;
-  if (!io_tiles) launch_perm_in<T>(d, E.perm, field, E.psi, 0, B, st);
+  if (!io_tiles) field_in<T>(E, d, field, E.psi, st);
   if (mode == 1) {
     const TileOps<T> tl = E.tiles<T>();
     // NL(dz/2) + stage 1: state -> psi2, y1 -> ya
@@ -1080,7 +1116,7 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     void* nxt = cur == E.psi ? E.psi2 : E.psi;
     launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, cur, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), st);
     launch_fused<T>(d, tl, FUSED_S4_NL, E.yb, cur, nxt, nullptr, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
-    launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
+    field_out<T>(E, d, nxt, field, st);
   } else if (mode == 3 && io_tiles && n <= (int64_t(1) << 30)) {
     // the whole propagate in one persistent launch: NL(dz/2) of the caller's
     // field, n - 1 merged steps, then LIN(dz) + NL(dz/2) into the caller's field
@@ -1109,13 +1145,13 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
     void* nxt = cur == E.psi ? E.psi2 : E.psi;
     launch_step<T>(d, E.stp.template ops<T>(), cur, nxt, dz, 0.5 * dz, gamma, E.sblock(), st);
-    launch_perm_out<T>(d, E.perm, nxt, field, 0, E.flag, B, st);
+    field_out<T>(E, d, nxt, field, st);
   } else {
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
     do_kerr<T>(E, d, E.psi, E.psi, E.s, 0.5 * dz, gamma, st);
     run_middle<T>(E, n - 1, dz, gamma, st);
     z_step<T>(E, d, dz, gamma, 0.5 * dz, st);
-    launch_perm_out<T>(d, E.perm, E.psi, field, 0, E.flag, B, st);
+    field_out<T>(E, d, E.psi, field, st);
   }
   check_launch();
 }
@@ -1950,7 +1986,7 @@ struct dec_bpm_s {
 
 struct dec_bpm_batch_s {
   Engine E;
-  std::vector<int64_t> n_per_mesh;
+  int64_t n_elems = 0;  // packed complex elements in the caller's layout
   ~dec_bpm_batch_s() { E.release(); }
 };
 
@@ -2357,10 +2393,7 @@ int dec_bpm_find_mode(dec_bpm_t h, void* field, double power, double dtau, doubl
   ABI_CATCH
 }
 
-int dec_bpm_check_finite(dec_bpm_t h, void* stream) {
-  ABI_TRY
-  need(h);
-  Engine& E = h->E;
+static void check_finite(Engine& E, void* stream) {
   if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
   hipStream_t st = as_stream(stream);
   int f = 0;
@@ -2372,6 +2405,19 @@ int dec_bpm_check_finite(dec_bpm_t h, void* stream) {
     fail(DEC_BPM_ENONFINITE, (f & 2) ? "a persistent launch timed out waiting for a neighbour tile (its output is invalid)"
                                       : "a propagated field contains NaN or Inf");
   }
+}
+
+int dec_bpm_check_finite(dec_bpm_t h, void* stream) {
+  ABI_TRY
+  need(h);
+  check_finite(h->E, stream);
+  ABI_CATCH
+}
+
+int dec_bpm_batch_check_finite(dec_bpm_batch_t b, void* stream) {
+  ABI_TRY
+  if (!b) fail(DEC_BPM_EINVAL, "batch is NULL");
+  check_finite(b->E, stream);
   ABI_CATCH
 }
 
@@ -2493,12 +2539,19 @@ int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_step
   ABI_CATCH
 }
 
-int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, int32_t fields_per_mesh, dec_bpm_batch_t* out) {
+int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, const int32_t* fields_per_mesh,
+                         dec_bpm_batch_t* out) {
   ABI_TRY
   if (!out) fail(DEC_BPM_EINVAL, "out is NULL");
   *out = nullptr;
   if (!meshes || n_meshes < 1) fail(DEC_BPM_EINVAL, "need at least one mesh");
-  if (fields_per_mesh < 1) fail(DEC_BPM_EINVAL, "fields_per_mesh must be >= 1");
+  if (!fields_per_mesh) fail(DEC_BPM_EINVAL, "fields_per_mesh is NULL");
+  int32_t fmax = 0;
+  for (int32_t m = 0; m < n_meshes; ++m) {
+    if (fields_per_mesh[m] < 1 || fields_per_mesh[m] > 4096)
+      fail(DEC_BPM_EINVAL, "every mesh needs between 1 and 4096 fields");
+    fmax = std::max(fmax, fields_per_mesh[m]);
+  }
   std::vector<const decbpm::Assembled*> list;
   std::vector<int> lumped;
   const dec_bpm_s* m0 = meshes[0];
@@ -2510,8 +2563,8 @@ int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, int32_t fiel
     if (!h->A.kp_re.empty()) fail(DEC_BPM_EINVAL, "batches do not take meshes with a PML");
     if (h->E.general()) fail(DEC_BPM_EINVAL, "batches do not take L^3, L^4 or non-Kerr responses");
     if (h->opt.dtype != m0->opt.dtype || h->opt.p1 != m0->opt.p1 || h->opt.beta4 != m0->opt.beta4 ||
-        h->opt.nonlinearity != m0->opt.nonlinearity)
-      fail(DEC_BPM_EINVAL, "all meshes of a batch must share dtype, p1, beta4 and nonlinearity");
+        h->opt.nonlinearity != m0->opt.nonlinearity || h->opt.host_only != m0->opt.host_only)
+      fail(DEC_BPM_EINVAL, "all meshes of a batch must share dtype, p1, beta4, nonlinearity and host_only");
     list.push_back(&h->A);
     lumped.push_back(h->opt.nonlinearity == DEC_BPM_NL_LUMPED ? 1 : 0);
     rho = std::max(rho, h->A.rho);
@@ -2519,13 +2572,20 @@ int dec_bpm_batch_create(const dec_bpm_t* meshes, int32_t n_meshes, int32_t fiel
   std::unique_ptr<dec_bpm_batch_s> b(new dec_bpm_batch_s());
   Engine& E = b->E;
   E.dtype = m0->opt.dtype;
-  E.F = fields_per_mesh;
+  // the device carries the largest field count on every row, rounded up to
+  // whole groups of the batched tile kernels (32 bytes of fields per slot);
+  // one field per mesh stays a one-field engine
+  const int32_t vf = E.dtype == DEC_BPM_C64 ? 4 : 2;
+  E.F = fmax == 1 ? 1 : (fmax + vf - 1) / vf * vf;
+  E.fpm.assign(fields_per_mesh, fields_per_mesh + n_meshes);
   E.p1 = m0->opt.p1;
   E.beta4 = m0->opt.beta4;
   E.nl = m0->opt.nonlinearity;
   E.rho = rho;
-  decbpm::build_engine(E, list, lumped);
-  for (auto* a : list) b->n_per_mesh.push_back(a->n);
+  E.n_rows = 0;
+  for (auto* a : list) E.n_rows += a->n;
+  if (!m0->opt.host_only) decbpm::build_engine(E, list, lumped);  // host-only meshes: a host-only batch
+  for (int32_t m = 0; m < n_meshes; ++m) b->n_elems += list[m]->n * fields_per_mesh[m];
   *out = b.release();
   ABI_CATCH
 }
@@ -2535,7 +2595,7 @@ void dec_bpm_batch_destroy(dec_bpm_batch_t b) { delete b; }
 int dec_bpm_batch_size(dec_bpm_batch_t b, int64_t* n_elems) {
   ABI_TRY
   if (!b || !n_elems) fail(DEC_BPM_EINVAL, "NULL argument");
-  *n_elems = b->E.n_rows * b->E.F;
+  *n_elems = b->n_elems;
   ABI_CATCH
 }
 

@@ -300,6 +300,38 @@ __global__ void k_perm_out(DevOps<T> d, const int32_t* __restrict__ perm, const 
   dst[int64_t(perm[row]) * F + f] = v;
 }
 
+// Batched caller layout <-> device layout.  Device element (row, f) is
+// row * F + f; the caller's is cbase[row] + f for the first fcount[row]
+// fields of the row's mesh, and the device's further fields (padding up to F)
+// are zero on the way in and dropped on the way out.
+template <typename T>
+__global__ void k_bperm_in(int64_t n_rows, int32_t F, const int64_t* __restrict__ cbase,
+                           const int32_t* __restrict__ fcount, const typename CT<T>::C* __restrict__ src,
+                           typename CT<T>::C* __restrict__ dst) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n_rows * F) return;
+  const int64_t row = idx / F;
+  const int32_t f = int32_t(idx - row * F);
+  typename CT<T>::C v;
+  v.x = v.y = T(0);
+  if (f < fcount[row]) v = src[cbase[row] + f];
+  dst[idx] = v;
+}
+
+template <typename T>
+__global__ void k_bperm_out(int64_t n_rows, int32_t F, const int64_t* __restrict__ cbase,
+                            const int32_t* __restrict__ fcount, const typename CT<T>::C* __restrict__ src,
+                            typename CT<T>::C* __restrict__ dst, int* flag) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n_rows * F) return;
+  const int64_t row = idx / F;
+  const int32_t f = int32_t(idx - row * F);
+  if (f >= fcount[row]) return;
+  const auto v = src[idx];
+  if (!(d_finite(v.x) && d_finite(v.y))) atomicOr(flag, 1);
+  dst[cbase[row] + f] = v;
+}
+
 template <typename T>
 __global__ void k_fill(int64_t n, typename CT<T>::C* x, T re, T im) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -3792,6 +3824,18 @@ void launch_perm_out(const DevOps<T>& d, const int32_t* perm, const void* src, v
 }
 
 template <typename T>
+void launch_bperm(const DevOps<T>& d, const int64_t* cbase, const int32_t* fcount, const void* src, void* dst,
+                  bool out, int* flag, int block, hipStream_t st) {
+  const unsigned g = grid_for(d.n_rows * d.F, block, 0);
+  if (out)
+    hipLaunchKernelGGL((k_bperm_out<T>), dim3(g), dim3(block), 0, st, d.n_rows, d.F, cbase, fcount,
+                       DECBPM_C(T, src), DECBPM_M(T, dst), flag);
+  else
+    hipLaunchKernelGGL((k_bperm_in<T>), dim3(g), dim3(block), 0, st, d.n_rows, d.F, cbase, fcount,
+                       DECBPM_C(T, src), DECBPM_M(T, dst));
+}
+
+template <typename T>
 void launch_fill(const DevOps<T>& d, void* x, double re, double im, int block, hipStream_t st) {
   const int64_t n = d.n_rows * d.F;
   hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n, block, 0)), dim3(block), 0, st, n, DECBPM_M(T, x), T(re), T(im));
@@ -3915,6 +3959,8 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                int, hipStream_t, const int32_t*, int*);                                          \
   template void launch_kerr_tile<T>(const DevOps<T>&, const TileOps<T>&, const void*, const int32_t*, void*,      \
                                     double, double, int, hipStream_t);                                           \
+  template void launch_bperm<T>(const DevOps<T>&, const int64_t*, const int32_t*, const void*, void*, bool, int*,  \
+                                int, hipStream_t);                                                               \
   template int persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int, int);                                \
   template void launch_step_b4<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double, \
                                   int, hipStream_t, const int32_t*, int*);                                       \

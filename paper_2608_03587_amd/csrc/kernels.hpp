@@ -185,6 +185,14 @@ template <typename T>
 void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
                     double tau, double gamma, int block, hipStream_t st, const int32_t* out_perm = nullptr,
                     int* flag = nullptr);
+// Batched fields between the caller's layout (per mesh, field-minor, that
+// mesh's own field count) and the device's (row * F + f, F fields per row):
+// device element (row, f) is caller element cbase[row] + f when
+// f < fcount[row]; other device fields are zero in (out = false) and dropped
+// out (out = true, which also sets bit 0 of *flag for a non-finite value).
+template <typename T>
+void launch_bperm(const DevOps<T>& d, const int64_t* cbase, const int32_t* fcount, const void* src, void* dst,
+                  bool out, int* flag, int block, hipStream_t st);
 // NL(tau) of the caller's field (caller order: row r at src[perm[r]]) into
 // the device-order buffer dst, on the step tiles (any ring count): the first
 // half step of a propagate, with the persistent launch's per-row arithmetic.

@@ -750,7 +750,7 @@ def test_batched_equals_plain(dtype):
     times = batch.time_kernels(ws[0].dz, 1.0, reps=5)
     assert times["step"]["ms"] > 0  # the batched step tiles exist
     outs = batch.unpack(runs[1])
-    tol = 1e-12 if dtype == "c128" else 1e-5  # same per-row formulas; only FMA contraction may differ
+    tol = 1e-12 if dtype == "c128" else 1e-6  # same per-row formulas; only FMA contraction may differ
     for m, x, o in zip(meshes, ws, outs):
         for f in range(4):
             for fused in (0, 1, 2, 3):
@@ -763,6 +763,42 @@ def test_batched_equals_plain(dtype):
     ops = oracle_ops(ws[1])
     ref = S.propagate(ws[1].u0[2], ops, ws[1].dz, ws[1].n_steps, 1.0)
     assert rel(host(outs[1][2].contiguous()), ref) < GATE[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batched_uneven_field_counts(dtype):
+    """Meshes carrying different numbers of fields (1, 5 and 3: the device pads every row
+    to the largest count, rounded up to whole field groups): each field equals a plain
+    propagate of it, the padding never reaches the caller's buffer, and one field matches
+    the oracle."""
+    ws = W.batched_pcf(n_meshes=3, fields_per_mesh=5, n_min=3000, n_max=9000, n_steps=40)
+    counts = [1, 5, 3]
+    say("batched uneven", dtype, [x.mesh.n_vert for x in ws], counts)
+    meshes = [lib_mesh(x, dtype) for x in ws]
+    batch = api.Batch(meshes, counts)
+    assert batch.n_elems == sum(x.mesh.n_vert * c for x, c in zip(ws, counts))
+    fields = [dev(x.u0[:c], dtype) for x, c in zip(ws, counts)]
+    guard = 7
+    buf = torch.full((batch.n_elems + 2 * guard,), 3.5 - 1.5j, dtype=fields[0].dtype, device=DEV)
+    buf[guard:guard + batch.n_elems] = batch.pack(fields)
+    packed = buf[guard:guard + batch.n_elems]
+    for fused in (0, 1, 2):
+        batch.tuning = {"fused": fused}
+        pk = packed.clone()
+        batch.propagate(pk, ws[0].dz, ws[0].n_steps, 1.0)
+        outs = batch.unpack(pk)
+        tol = 1e-12 if dtype == "c128" else 1e-6
+        for m, x, o, c in zip(meshes, ws, outs, counts):
+            assert o.shape == (c, x.mesh.n_vert)
+            for f in range(c):
+                single = dev(x.u0[f], dtype)
+                m.propagate(single, x.dz, x.n_steps, 1.0)
+                err = rel(host(o[f].contiguous()), host(single))
+                assert err < tol, (fused, f, err)
+    batch.propagate(packed, ws[0].dz, ws[0].n_steps, 1.0)  # in place inside the guarded buffer
+    assert torch.all(buf[:guard] == 3.5 - 1.5j) and torch.all(buf[guard + batch.n_elems:] == 3.5 - 1.5j)
+    ref = S.propagate(ws[1].u0[4], oracle_ops(ws[1]), ws[1].dz, ws[1].n_steps, 1.0)
+    assert rel(host(batch.unpack(packed)[1][4].contiguous()), ref) < GATE[dtype]
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])

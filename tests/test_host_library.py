@@ -265,3 +265,37 @@ def test_general_operator_sum_and_responses_on_the_host():
                {"p3": float("inf")}, {"response": "saturable", "response_param": 1.0, "pml": (3.0, 4.0, 1.0)}):
         with pytest.raises(api.DecBpmError):
             api.Mesh(mesh.xy, mesh.tri, dtype="c64", host_only=True, **kw)
+
+
+def test_batch_layout_with_uneven_field_counts():
+    """A batch of host-only meshes with different field counts per mesh: the packed size
+    is sum_m n_m F_m and the Python layout (offsets, pack, unpack) follows the header's
+    field-minor, per-mesh layout; bad counts are refused before any device work, and a
+    host-only batch refuses to propagate."""
+    import torch
+
+    ms = [api.Mesh(M.disk_mesh(2.0 + k, 0.5, 3 + k).xy, M.disk_mesh(2.0 + k, 0.5, 3 + k).tri, host_only=True)
+          for k in range(3)]
+    counts = [1, 5, 3]
+    b = api.Batch(ms, counts)
+    assert b.n_elems == sum(m.n_vert * f for m, f in zip(ms, counts))
+    assert list(b.offsets) == list(np.cumsum([0] + [m.n_vert * f for m, f in zip(ms, counts)]))
+    fields = [torch.arange(f * m.n_vert, dtype=torch.float64).reshape(f, m.n_vert).to(torch.complex128) + 1000 * k
+              for k, (m, f) in enumerate(zip(ms, counts))]
+    packed = b.pack(fields)
+    assert packed.numel() == b.n_elems
+    # element (mesh m, vertex i, field f) at base_m + i F_m + f
+    m, i, f = 1, 7, 3
+    assert packed[b.offsets[m] + i * counts[m] + f] == fields[m][f, i]
+    for a, c in zip(b.unpack(packed), fields):
+        assert torch.equal(a, c)
+    assert B.lib().dec_bpm_batch_propagate(b._h, ctypes.c_void_p(16), 1e-3, 1, 1.0, None) == B.ENODEVICE
+    for bad in ([0, 1, 1], [1, -2, 1], [1, 5000, 1]):
+        with pytest.raises(api.DecBpmError) as e:
+            api.Batch(ms, bad)
+        assert e.value.code == B.EINVAL
+    arr = (ctypes.c_void_p * 3)(*[x.handle.value for x in ms])
+    out = ctypes.c_void_p()
+    assert B.lib().dec_bpm_batch_create(arr, 3, None, ctypes.byref(out)) == B.EINVAL
+    b.close()
+    b.close()  # idempotent
