@@ -40,6 +40,7 @@ __all__ = [
     "hex_patch_mesh",
     "random_delaunay_mesh",
     "wheel_disk_mesh",
+    "jittered_lattice_mesh",
 ]
 
 
@@ -340,3 +341,36 @@ def wheel_disk_mesh(R: float = 10.0, h: float = 0.3, seed: int = 5, spokes: int 
         return _finish(np.concatenate(parts), {"kind": "wheel_disk", "R": R, "h": h, "spokes": spokes}, min_angle)
 
     return _retry(build, seed, min_angle)
+
+
+def jittered_lattice_mesh(nx: int, ny: int, jitter: float, seed: int, angle: float = 0.0, shear: float = 0.0,
+                          shuffle: bool = True) -> Mesh:
+    """Delaunay triangulation of an ``nx`` x ``ny`` hexagonal lattice (spacing 1),
+    each point moved by up to ``jitter`` in each coordinate, then sheared by
+    ``shear`` and rotated by ``angle``; with ``shuffle`` the vertex order, the
+    triangle order and each triangle's orientation are randomised (seeded), as
+    an arbitrary mesher's output would be.  For property tests of mesh ingest.
+    Without jitter the lattice's straight rows give Qhull collinear (zero-area)
+    triangles on the hull, which a valid mesh cannot have: use jitter > 0."""
+    rng = np.random.default_rng(seed)
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    x = ii + 0.5 * (jj & 1)
+    y = jj * (math.sqrt(3.0) / 2.0)
+    pts = np.stack([x.ravel(), y.ravel()], axis=1).astype(np.float64)
+    pts = pts + rng.uniform(-jitter, jitter, pts.shape)
+    pts[:, 0] += shear * pts[:, 1]
+    c, s_ = math.cos(angle), math.sin(angle)
+    pts = pts @ np.array([[c, s_], [-s_, c]])
+    tri = _triangulate(pts)
+    if shuffle:
+        order = rng.permutation(len(pts))
+        inv = np.empty_like(order)
+        inv[order] = np.arange(len(pts))
+        pts = pts[order]
+        tri = inv[tri].astype(np.int32)
+        tri = tri[rng.permutation(len(tri))]
+        flip = rng.random(len(tri)) < 0.5
+        tri[flip] = tri[flip][:, [0, 2, 1]]
+    meta = {"kind": "jittered_lattice", "nx": nx, "ny": ny, "jitter": jitter, "seed": seed,
+            "min_angle_deg": min_angle_deg(pts, tri)}
+    return Mesh(np.ascontiguousarray(pts), np.ascontiguousarray(tri, dtype=np.int32), meta)
