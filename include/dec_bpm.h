@@ -230,6 +230,25 @@ int dec_bpm_linear_step(dec_bpm_t h, void* field, double dz, void* stream);
 int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream);
 
 /*
+ * dec_bpm_propagate without any allocation, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc): the
+ * same steps, kernels and result as dec_bpm_propagate, but its two state
+ * buffers and the persistent launch's flags live in a static device array of
+ * 12 MiB that each device holds until the process ends, and every kernel is
+ * launched directly (no graph is instantiated).  No hipMalloc, hipFree or
+ * allocating library routine is called.  Limits: one-field handles with the
+ * step tiles (EINVAL for rows of more than 12 neighbours, L^3, L^4 or a
+ * non-Kerr response), and 2 n_vert complex values of the handle's dtype at
+ * most 12 MiB - 64 KiB (about 786k vertices in complex64, 393k in
+ * complex128; EINVAL beyond, with the sizes in the message).  Every call on a
+ * device shares that device's array, which keeps the last call's contents:
+ * calls that overlap on one device (other streams, other threads, other
+ * handles) race and must be serialised by the caller.  The flags are cleared
+ * by a kernel at each call.  Other errors as dec_bpm_propagate.
+ */
+int dec_bpm_propagate_noalloc(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream);
+
+/*
  * The paper's unsplit scheme (Eq. 10 integrated as one ODE, "DEC beam
  * propagation"): n_steps classical RK4 steps of
  *   dPsi/dz = -i H_lin Psi + i gamma (M |Psi|^2) Psi - w Psi,

@@ -76,6 +76,7 @@ _SIGNATURES = [
     ("dec_bpm_kerr_step", c_int, [c_vp, c_vp, c_dbl, c_dbl, c_vp]),
     ("dec_bpm_linear_step", c_int, [c_vp, c_vp, c_dbl, c_vp]),
     ("dec_bpm_propagate", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_vp]),
+    ("dec_bpm_propagate_noalloc", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_vp]),
     ("dec_bpm_propagate_unsplit", c_int, [c_vp, c_vp, c_dbl, c_i64, c_dbl, c_vp]),
     ("dec_bpm_export_pml", c_int, [c_vp, P(c_dbl), P(c_dbl)]),
     ("dec_bpm_vertex_tiles", c_int, [c_vp, P(c_i32), P(c_i32)]),

@@ -176,6 +176,12 @@ class Mesh:
                                           _stream(stream)))
         return field
 
+    def propagate_noalloc(self, field: torch.Tensor, dz: float, n_steps: int, gamma: float = 1.0, stream=None):
+        """``propagate`` through the library's static scratch: allocates nothing (see the header)."""
+        B.check(B.lib().dec_bpm_propagate_noalloc(self._h, self._field(field), float(dz), int(n_steps), float(gamma),
+                                                  _stream(stream)))
+        return field
+
     def propagate_unsplit(self, field: torch.Tensor, dz: float, n_steps: int, gamma: float = 1.0, stream=None):
         """March ``n_steps`` classical RK4 steps of the whole right-hand side (Kerr term inside
         every stage) in place on ``field`` (asynchronous)."""

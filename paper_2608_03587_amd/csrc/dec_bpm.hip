@@ -14,6 +14,7 @@
 #include <cstring>
 #include <fstream>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1152,6 +1153,92 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     run_middle<T>(E, n - 1, dz, gamma, st);
     z_step<T>(E, d, dz, gamma, 0.5 * dz, st);
     field_out<T>(E, d, E.psi, field, st);
+  }
+  check_launch();
+}
+
+// ---- the entry point that allocates nothing ----
+// dec_bpm_propagate_noalloc keeps its two state buffers and the persistent
+// launch's neighbour flags in this file-scope array instead of the handle's
+// buffers.  Each device holds its own copy for the life of the process, and
+// every call on a device shares it.  In host code the array's name is only a
+// host-side stand-in: kernels get the device address that hipGetSymbolAddress
+// returned for the current device, looked up once per device.
+constexpr size_t kScratchBytes = size_t(12) << 20;
+constexpr size_t kScratchFlagBytes = size_t(64) << 10;  // flags of up to 16384 tiles
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[64] = {};
+
+static unsigned char* scratch_address() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) fail(DEC_BPM_EINVAL, "device ordinal beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = p;
+  }
+  return static_cast<unsigned char*>(g_scratch_dev[dev]);
+}
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Argument checks of the no-allocation variant beyond dec_bpm_propagate's.
+static void check_noalloc(const Engine& E) {
+  if (E.F != 1 || !(E.has_step || E.has_step4))
+    fail(DEC_BPM_EINVAL,
+         "dec_bpm_propagate_noalloc runs the one-field step tiles only (not for rows of more than 12 neighbours, "
+         "L^3, L^4 or a non-Kerr response)");
+  const size_t need = 2 * round256(size_t(E.n_rows) * E.cplx_size());
+  if (need > kScratchBytes - kScratchFlagBytes) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "dec_bpm_propagate_noalloc: the state needs %zu bytes; the static scratch holds %zu",
+                  need, kScratchBytes - kScratchFlagBytes);
+    fail(DEC_BPM_EINVAL, buf);
+  }
+  if (size_t(E.ptiles().n_tiles) * sizeof(int32_t) > kScratchFlagBytes)
+    fail(DEC_BPM_EINVAL, "dec_bpm_propagate_noalloc: too many tiles for the static flag area");
+}
+
+// dec_bpm_propagate on the static scratch: the persistent launch (mode 3) or
+// one tile kernel per step, launched directly (no graph), no allocation.
+template <typename T>
+static void propagate_noalloc_t(Engine& E, void* field, double dz, int64_t n, double gamma, hipStream_t st) {
+  if (n == 0) return;
+  const DevOps<T> d = E.ops<T>();
+  unsigned char* base = scratch_address();
+  int32_t* flags = reinterpret_cast<int32_t*>(base);
+  void* b0 = base + kScratchFlagBytes;
+  void* b1 = base + kScratchFlagBytes + round256(size_t(E.n_rows) * E.cplx_size());
+  const int mode = mode_of<T>(E);
+  if (mode == 3 && n <= (int64_t(1) << 30)) {
+    launch_zero_i32(E.ptiles().n_tiles, flags, st);  // a kernel, not a memset (safe inside captured graphs)
+    PersistIO io;
+    io.in = field;
+    io.out = field;
+    io.perm = E.perm;
+    io.tau_first = io.tau_last = 0.5 * dz;
+    const hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, flags,
+                                           E.flag, int32_t(n), E.spin_limit, dz, gamma, E.pblock(), st, 0, io);
+    if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+  } else {
+    const TileOps<T> ts = E.stp.template ops<T>();
+    launch_kerr_tile<T>(d, ts, field, E.perm, b0, 0.5 * dz, gamma, E.sblock(), st);
+    void* cur = b0;
+    void* nxt = b1;
+    for (int64_t k = 0; k < n; ++k) {
+      const bool last = k == n - 1;
+      void* out = last ? field : nxt;
+      const double tau = last ? 0.5 * dz : dz;
+      if (E.has_step4)
+        launch_step_b4<T>(d, ts, cur, out, dz, tau, gamma, E.sblock(), st, last ? E.perm : nullptr, E.flag);
+      else
+        launch_step<T>(d, ts, cur, out, dz, tau, gamma, E.sblock(), st, last ? E.perm : nullptr, E.flag);
+      std::swap(cur, nxt);
+    }
   }
   check_launch();
 }
@@ -2297,6 +2384,18 @@ int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, doub
   need(h);
   decbpm::check_prop_args(h->E, field, dz, n_steps, gamma);
   decbpm::propagate(h->E, field, dz, n_steps, gamma, as_stream(stream));
+  ABI_CATCH
+}
+
+int dec_bpm_propagate_noalloc(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream) {
+  ABI_TRY
+  need(h);
+  decbpm::check_prop_args(h->E, field, dz, n_steps, gamma);
+  decbpm::check_noalloc(h->E);
+  if (h->E.dtype == DEC_BPM_C64)
+    decbpm::propagate_noalloc_t<float>(h->E, field, dz, n_steps, gamma, as_stream(stream));
+  else
+    decbpm::propagate_noalloc_t<double>(h->E, field, dz, n_steps, gamma, as_stream(stream));
   ABI_CATCH
 }
 
