@@ -108,9 +108,9 @@ class Mesh:
     def close(self):
         """Release the handle's device memory now (idempotent); the object is unusable afterwards."""
         h = getattr(self, "_h", None)
+        self._h = None
         if h is not None and h.value:
             self._destroy(h)
-        self._h = ctypes.c_void_p()
 
     def __del__(self):
         self.close()
@@ -351,9 +351,9 @@ class Batch:
     def close(self):
         """Release the batch's device memory now (idempotent)."""
         h = getattr(self, "_h", None)
+        self._h = None
         if h is not None and h.value:
             self._destroy(h)
-        self._h = ctypes.c_void_p()
 
     def __del__(self):
         self.close()

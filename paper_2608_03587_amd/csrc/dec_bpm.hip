@@ -121,6 +121,10 @@ struct Engine {
   int tile_size = 512;
   int tile_block = 256;
   DevTiles tl, bt, stp;  // two-kernel tiles (3 rings), batched tiles, one-kernel-step tiles (5 rings)
+  // batches: one-field step tiles over every mesh's rows, for the field-loop
+  // step (launch mode 6: a workgroup per tile steps all fields in turn)
+  DevTiles sfl;
+  bool has_sfl = false;
   bool has_step = false;
   bool has_step4 = false;  // the step tiles hold the beta4 layout (eight or nine rings)
   bool pml = false;        // complex-stretched L (perfectly matched layer): one-kernel step only
@@ -203,6 +207,16 @@ struct Engine {
     if (b >= mc) return std::min(1024, b);
     return std::min(dtype == DEC_BPM_C128 ? 640 : 1024, b);
   }
+
+  // threads per workgroup of the field-loop step (as sblock, on its tiles)
+  int fblock() const {
+    const int mc = sfl.max_compute;
+    const int b = std::max(tile_block, ((mc + 1) / 2 + 63) / 64 * 64);
+    if (b >= mc) return std::min(1024, b);
+    return std::min(dtype == DEC_BPM_C128 ? 640 : 1024, b);
+  }
+  // the field-loop kernel stages at most three state slots per thread
+  bool use_sfl() const { return has_sfl && F > 1 && sfl.max_slots <= 3 * fblock(); }
 
   const DevTiles& ptiles() const { return pst_own ? pst : stp; }
   // threads per workgroup of the persistent kernel: as the step kernels on the
@@ -594,6 +608,27 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
   E.has_persist = true;
 }
 
+// Batched path, field-loop step: the one-field step tiles (five rings, four
+// for the lumped Kerr term) over the concatenated rows of every mesh; a tile
+// may straddle two meshes (the operator is block diagonal, so its halo holds
+// only rows of the meshes it covers).
+template <typename T>
+static void build_field_tiles(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
+                              const std::vector<double>& alw, const std::vector<double>& amw, bool dec) {
+  if (E.wmax > 12 || E.beta4 != 0.0) return;
+  const int rings = 4 + (dec ? 1 : 0);
+  const size_t lds_max = sizeof(T) == 8 ? 100 * 1024 : 63 * 1024;
+  const int max_compute = sizeof(T) == 8 ? 2 * 640 : 2 * 1024;
+  HostTiles H;
+  for (int ts = 1024; ts >= 64; ts /= 2) {
+    if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H, true, E.sort_ring0)) continue;
+    if (size_t(H.max_slots) * 7 * sizeof(T) > lds_max || H.max_compute > max_compute) continue;
+    upload_tiles<T>(E, H, dec, E.n_rows, E.sfl);
+    E.has_sfl = true;
+    return;
+  }
+}
+
 // Batched path: tiles of one halo ring whose field values (all F fields of
 // every slot) are staged in LDS by one workgroup; rows per tile so that a
 // workgroup has at most 1024 threads of 32 bytes of fields each.
@@ -759,6 +794,7 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   if (pml && !E.has_step)
     fail(DEC_BPM_EINVAL, "PML: the mesh needs the one-kernel step tiles (rows of at most 12 neighbours)");
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  if (E.F > 1 && !E.general()) build_field_tiles<T>(E, arp, acol, alw, amw, any_dec);
   if (E.has_step && E.F == 1 && !pml) {  // kept for the adaptive integrator's tiles
     E.adj.arp = std::move(arp);
     E.adj.col = std::move(acol);
@@ -768,7 +804,7 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   }
   const size_t nv = size_t(n) * E.F;
   E.psi = E.dalloc(nv * 2 * sizeof(T));
-  if (E.has_tiles || E.has_step || E.has_step4) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
+  if (E.has_tiles || E.has_step || E.has_step4 || E.has_sfl) E.psi2 = E.dalloc(nv * 2 * sizeof(T));
   E.ya = E.dalloc(nv * 2 * sizeof(T));
   E.yb = E.dalloc(nv * 2 * sizeof(T));
   E.t = (E.beta4 != 0.0 || E.general()) ? E.dalloc(nv * 2 * sizeof(T)) : nullptr;
@@ -927,8 +963,11 @@ static void fused_mid(const Engine& E, const DevOps<T>& d, const TileOps<T>& tl,
 // of them, 4 = one tile kernel per step with the beta4 term (modes whose tiles
 // are missing fall back to the row kernels).  Mode 5, one unsplit RK4 step per
 // tile kernel, is only requested explicitly (dec_bpm_propagate_unsplit).
+// Mode 6 (batches, fused = 3): one field-loop tile kernel per step over a
+// field-major device layout.
 template <typename T>
 static int mode_of(Engine& E) {
+  if (E.F > 1 && E.fused == 3 && E.use_sfl()) return 6;  // batches: the field-loop step
   if (E.pml) return use_persist<T>(E) ? 3 : 2;   // complex L: the one-kernel step or the persistent launch
   if (E.general()) return 0;                      // L^3, L^4 or a non-Kerr response: five kernels
   if (E.has_step4) return E.fused >= 2 ? 4 : 0;  // beta4: its one-kernel step or the five kernels
@@ -943,7 +982,7 @@ static void* state_before(const Engine& E, int mode, int64_t k) {
   if (mode == 0) return E.psi;
   const bool odd = k % 2;
   if (mode == 1) return odd ? E.psi : E.psi2;
-  return odd ? E.psi2 : E.psi;  // modes 2 to 5
+  return odd ? E.psi2 : E.psi;  // modes 2 to 6
 }
 
 template <typename T>
@@ -959,6 +998,9 @@ static void middle_step(const Engine& E, const DevOps<T>& d, int mode, int64_t k
   } else if (mode == 4) {
     launch_step_b4<T>(d, E.stp.template ops<T>(), state_before(E, 4, k), state_before(E, 4, k + 1), dz, dz, gamma,
                       E.sblock(), st);
+  } else if (mode == 6) {
+    launch_step_fields<T>(d, E.sfl.template ops<T>(), state_before(E, 6, k), state_before(E, 6, k + 1), dz, dz, gamma,
+                          E.fblock(), st);
   } else {  // 5: unsplit RK4
     launch_unsplit<T>(d, E.stp.template ops<T>(), state_before(E, 5, k), state_before(E, 5, k + 1), dz, gamma,
                       E.sblock(), st);
@@ -971,7 +1013,7 @@ static int graph_steps(const Engine& E, int mode) { return mode ? std::max(2, E.
 
 template <typename T>
 static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, int mode) {
-  const int tb = mode == 1 ? E.tblock() : (mode >= 2 ? E.sblock() : 0);
+  const int tb = mode == 1 ? E.tblock() : (mode == 6 ? E.fblock() : (mode >= 2 ? E.sblock() : 0));
   for (auto& g : E.graphs)
     if (g.dz == dz && g.gamma == gamma && g.spg == E.spg && g.block == E.block && g.xcd == E.xcd &&
         g.fused == mode && g.tile_block == tb)
@@ -1108,8 +1150,18 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
   const int mode = mode_of<T>(E);
   // one-field step tiles read the caller's field and write the result through the permutation
   const bool io_tiles = mode >= 2 && E.F == 1;
-  if (!io_tiles) field_in<T>(E, d, field, E.psi, st);
-  if (mode == 1) {
+  if (!io_tiles && mode != 6) field_in<T>(E, d, field, E.psi, st);
+  if (mode == 6) {
+    // field-major device layout: NL(dz/2) of every field, n - 1 merged steps,
+    // then LIN(dz) + NL(dz/2), back to the caller's layout
+    const TileOps<T> tf = E.sfl.template ops<T>();
+    launch_bperm<T>(d, E.bcbase, E.bfcount, field, E.psi2, false, nullptr, E.block, st, true);
+    launch_kerr_fields<T>(d, tf, E.psi2, E.psi, 0.5 * dz, gamma, E.fblock(), st);
+    void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
+    void* nxt = cur == E.psi ? E.psi2 : E.psi;
+    launch_step_fields<T>(d, tf, cur, nxt, dz, 0.5 * dz, gamma, E.fblock(), st);
+    launch_bperm<T>(d, E.bcbase, E.bfcount, nxt, field, true, E.flag, E.block, st, true);
+  } else if (mode == 1) {
     const TileOps<T> tl = E.tiles<T>();
     // NL(dz/2) + stage 1: state -> psi2, y1 -> ya
     launch_fused<T>(d, tl, FUSED_NL_S1, nullptr, E.psi, E.psi2, E.ya, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
@@ -1806,7 +1858,7 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
   HIP_OK(hipEventCreate(&e1));
   for (int kind = 0; kind < DEC_BPM_NUM_KERNELS; ++kind) {
     const bool tile_kind = kind == DEC_BPM_K_TILE_A || kind == DEC_BPM_K_TILE_B;
-    if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step && !E.has_step4) ||
+    if ((tile_kind && !E.has_tiles) || (kind == DEC_BPM_K_STEP && !E.has_step && !E.has_step4 && !E.use_sfl()) ||
         (kind == DEC_BPM_K_UNSPLIT && (!E.has_step || E.F != 1)) ||
         (kind == DEC_BPM_K_DP5 && !(E.has_step && E.F == 1 && ensure_dp5_tiles<T>(E))) ||
         (kind == DEC_BPM_K_MODE && !(E.has_step && E.F == 1)) ||
@@ -1907,7 +1959,10 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
         launch_fused<T>(d, tl, FUSED_S4_NL_S1, E.yb, E.psi, E.psi2, E.ya, nullptr, dz, dz, gamma, E.tblock(), E.cap);
       if (kind == DEC_BPM_K_TILE_B)
         launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, E.psi, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), E.cap);
-      if (kind == DEC_BPM_K_STEP && E.has_step4)
+      if (kind == DEC_BPM_K_STEP && E.use_sfl() && (mode_of<T>(E) == 6 || !E.has_step))
+        launch_step_fields<T>(d, E.sfl.template ops<T>(), r % 2 ? E.psi2 : E.psi, r % 2 ? E.psi : E.psi2, dz, dz,
+                              gamma, E.fblock(), E.cap);
+      else if (kind == DEC_BPM_K_STEP && E.has_step4)
         launch_step_b4<T>(d, E.stp.template ops<T>(), r % 2 ? E.psi2 : E.psi, r % 2 ? E.psi : E.psi2, dz, dz,
                           gamma, E.sblock(), E.cap);
       else if (kind == DEC_BPM_K_STEP)
@@ -1967,7 +2022,7 @@ static bool tune_cache_lookup(Engine& E) {
       E.block = b;
       E.spg = s;
       E.xcd = x;
-      E.fused = (E.has_tiles || E.has_btiles || E.has_step || E.has_step4) ? fu : 0;
+      E.fused = (E.has_tiles || E.has_btiles || E.has_step || E.has_step4 || E.has_sfl) ? fu : 0;
       E.tile_block = tb;
       return true;
     }
@@ -2016,6 +2071,8 @@ static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
       if (E.has_persist && s == 32)  // one launch runs every step: steps per graph do not apply
         for (int tb : {256, 512, 1024}) cands.push_back({3, E.block, tb, s, x});
       if (E.has_btiles) cands.push_back({1, E.block, E.tile_block, s, x});
+      if (E.has_sfl && E.F > 1)
+        for (int tb : {256, 512, 1024}) cands.push_back({3, E.block, tb, s, x});
     }
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
@@ -2029,7 +2086,7 @@ static void autotune_t(Engine& E, double dz, double gamma, hipStream_t st) {
     E.tile_block = c.tile_block;
     E.spg = c.spg;
     E.xcd = c.xcd;
-    if (c.fused == 3 && !persist_fits<T>(E)) continue;
+    if (c.fused == 3 && (E.F > 1 ? !E.use_sfl() : !persist_fits<T>(E))) continue;
     launch_fill<T>(d0, E.psi, 0.3, 0.1, 256, st);
     if (E.psi2) launch_fill<T>(d0, E.psi2, 0.3, 0.1, 256, st);
     launch_fill<T>(d0, E.ya, 0.3, 0.1, 256, st);
@@ -2735,7 +2792,7 @@ int dec_bpm_batch_autotune(dec_bpm_batch_t b, double dz, double gamma, void* str
 static void get_tuning(const Engine& E, dec_bpm_tuning* t) {
   t->block_size = E.block;
   t->steps_per_graph = E.spg;
-  t->fused = (E.has_tiles || E.has_btiles || E.has_step || E.has_step4) ? E.fused : 0;
+  t->fused = (E.has_tiles || E.has_btiles || E.has_step || E.has_step4 || E.has_sfl) ? E.fused : 0;
   t->tile_block = E.has_tiles ? E.tblock() : E.tile_block;
   t->xcd_remap = E.xcd;
 }

@@ -304,10 +304,11 @@ __global__ void k_perm_out(DevOps<T> d, const int32_t* __restrict__ perm, const 
 // row * F + f; the caller's is cbase[row] + f for the first fcount[row]
 // fields of the row's mesh, and the device's further fields (padding up to F)
 // are zero on the way in and dropped on the way out.
+// fmaj: the device layout is field-major (field f of row r at f * n_rows + r).
 template <typename T>
 __global__ void k_bperm_in(int64_t n_rows, int32_t F, const int64_t* __restrict__ cbase,
                            const int32_t* __restrict__ fcount, const typename CT<T>::C* __restrict__ src,
-                           typename CT<T>::C* __restrict__ dst) {
+                           typename CT<T>::C* __restrict__ dst, int fmaj) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= n_rows * F) return;
   const int64_t row = idx / F;
@@ -315,19 +316,19 @@ __global__ void k_bperm_in(int64_t n_rows, int32_t F, const int64_t* __restrict_
   typename CT<T>::C v;
   v.x = v.y = T(0);
   if (f < fcount[row]) v = src[cbase[row] + f];
-  dst[idx] = v;
+  dst[fmaj ? int64_t(f) * n_rows + row : idx] = v;
 }
 
 template <typename T>
 __global__ void k_bperm_out(int64_t n_rows, int32_t F, const int64_t* __restrict__ cbase,
                             const int32_t* __restrict__ fcount, const typename CT<T>::C* __restrict__ src,
-                            typename CT<T>::C* __restrict__ dst, int* flag) {
+                            typename CT<T>::C* __restrict__ dst, int* flag, int fmaj) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= n_rows * F) return;
   const int64_t row = idx / F;
   const int32_t f = int32_t(idx - row * F);
   if (f >= fcount[row]) return;
-  const auto v = src[idx];
+  const auto v = src[fmaj ? int64_t(f) * n_rows + row : idx];
   if (!(d_finite(v.x) && d_finite(v.y))) atomicOr(flag, 1);
   dst[cbase[row] + f] = v;
 }
@@ -1168,6 +1169,10 @@ struct CplxAoS {
 // threads (up to 170 VGPRs per lane instead of 128; no spills).  The
 // persistent kernel keeps the 1024 bound: there, keeping every tile resident
 // (more waves per CU) matters more than the spills.
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
 template <typename T, int J>
 struct StepBound {
   static constexpr int value = (sizeof(T) == 8 && J >= 2) ? 640 : 1024;
@@ -1368,9 +1373,11 @@ struct StepTile {
   // thread of the workgroup must call it (it holds barriers).  A thread keeps
   // the values of its own slots (the state, the latest stage, |b|^2 phi) in
   // registers; LDS serves the neighbour gathers only.
-  template <typename V, typename Out, typename Rec>
+  // after_p() runs once P is no longer read (after the first barrier): a
+  // caller may start refilling P from there.
+  template <typename V, typename Out, typename Rec, typename AfterP = NoHook>
   __device__ void step(const DevOps<T>& d, const V& P, const V& X, const V& Y, T* S, T h, T tau, T gamma, Out out,
-                       Rec rec) const {
+                       Rec rec, AfterP after_p = AfterP()) const {
     const int B = blockDim.x;
     C p[J], cur[J];
     T so[J];
@@ -1385,6 +1392,7 @@ struct StepTile {
       }
     }
     __syncthreads();
+    after_p();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int i = threadIdx.x + j * B;
@@ -1435,7 +1443,7 @@ struct StepTile {
   }
 
   // NL(tau) alone of a field held in the caller's vertex order (row r at
-  // src[perm[r]]), for the owned rows: |psi|^2 phi(w, tau) is staged in S on
+  // src[perm[r]]; device order if perm is null), for the owned rows: |psi|^2 phi(w, tau) is staged in S on
   // rings 0..1 (the reach of the M gather; ring 0 for the lumped form), then
   // out(slot, r, value) receives each owned row's result.  Every thread of the
   // workgroup must call it (it holds a barrier).
@@ -1450,7 +1458,7 @@ struct StepTile {
     for (int j = 0; j < J; ++j) {
       const int i = threadIdx.x + j * B;
       if (i < nS) {
-        p[j] = src[perm[rr[j]]];
+        p[j] = src[perm ? perm[rr[j]] : rr[j]];
         so[j] = (p[j].x * p[j].x + p[j].y * p[j].y) * phi_w(ww[j], tau);
         S[i] = so[j];
       }
@@ -1970,6 +1978,82 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_kerr_tile(DevOps<T
   StepTile<T, KMAX, DEC, J, CL> st;
   st.init(d, tl, tile, true);
   st.kerr_from(d, src, perm, S, tau, gamma, [&](int, int32_t r, const C& v) { dst[r] = v; });
+}
+
+// One z step of every field of a batch on one-field step tiles.  The device
+// layout is field-major (field f of row r at f * n_rows + r).  The workgroup
+// of a tile loads the operator rows into registers once and steps the nf
+// fields one after another; the next field's state is fetched into registers
+// while the current one runs its later stages (P is last read by stage 1)
+// and moved into P after it.
+template <typename T, int KMAX, bool DEC, int J, int LS>
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_fields(DevOps<T> d, TileOps<T> tl,
+                                                                          const typename CT<T>::C* __restrict__ in,
+                                                                          typename CT<T>::C* __restrict__ out, T h,
+                                                                          T tau, T gamma, int32_t nf) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  const int B = blockDim.x;
+  C* base = reinterpret_cast<C*>(smem);
+  const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS};
+  T* S = reinterpret_cast<T*>(base + 3 * MS);
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile);
+  int32_t pr[LS];
+#pragma unroll
+  for (int l = 0; l < LS; ++l) {
+    const int i = threadIdx.x + l * B;
+    pr[l] = i < st.nLoad ? st.slot_row(i) : -1;
+  }
+#pragma unroll
+  for (int l = 0; l < LS; ++l)
+    if (pr[l] >= 0) P.put(threadIdx.x + l * B, in[pr[l]]);
+  __syncthreads();
+  for (int32_t f = 0; f < nf; ++f) {
+    st.opaque_neighbours();
+    const int64_t off = int64_t(f) * d.n_rows;
+    const bool more = f + 1 < nf;
+    C pv[LS];
+    st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out[off + r] = v; },
+            [](int, int32_t, const C&) {},
+            [&]() {
+              if (more) {
+#pragma unroll
+                for (int l = 0; l < LS; ++l)
+                  if (pr[l] >= 0) pv[l] = in[off + d.n_rows + pr[l]];
+              }
+            });
+    if (more) {
+#pragma unroll
+      for (int l = 0; l < LS; ++l)
+        if (pr[l] >= 0) P.put(threadIdx.x + l * B, pv[l]);
+    }
+    __syncthreads();
+  }
+}
+
+// NL(tau) of every field of a batch (field-major device layout) on one-field
+// step tiles, as k_kerr_tile does for one field: the first half step.
+template <typename T, int KMAX, bool DEC, int J>
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_kerr_fields(DevOps<T> d, TileOps<T> tl,
+                                                                          const typename CT<T>::C* __restrict__ in,
+                                                                          typename CT<T>::C* __restrict__ out, T tau,
+                                                                          T gamma, int32_t nf) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  T* S = reinterpret_cast<T*>(smem);
+  StepTile<T, KMAX, DEC, J> st;
+  st.init(d, tl, tile, true);
+  for (int32_t f = 0; f < nf; ++f) {
+    const int64_t off = int64_t(f) * d.n_rows;
+    st.kerr_from(d, in + off, nullptr, S, tau, gamma, [&](int, int32_t r, const C& v) { out[off + r] = v; });
+    __syncthreads();
+  }
 }
 
 // One whole z step for a batched handle: workgroup b handles step tile
@@ -2908,31 +2992,31 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
         }
       }
     __syncthreads();
-    const bool fin = io.out != nullptr && s == n_steps - 1;  // the result goes to the caller's field
+    if (io.out != nullptr && s == n_steps - 1) {  // the last step: the result goes to the caller's field
+      if constexpr (BODY == 0)
+        st.step(d, P, X, Y, S, h, io.tau_last, gamma,
+                [&](int, int32_t r, const C& v) { put_result(io.out, io.perm, status, r, v); },
+                [](int, int32_t, const C&) {});
+      else
+        st.step_unsplit(d, UA, UB, USA, USB, h, gamma,
+                        [&](int, int32_t r, const C& v) { put_result(io.out, io.perm, status, r, v); });
+      break;
+    }
     if constexpr (BODY == 0) {
-      st.step(d, P, X, Y, S, h, fin ? io.tau_last : h, gamma,
+      st.step(d, P, X, Y, S, h, h, gamma,
               [&](int i, int32_t r, const C& v) {
-                if (fin) {
-                  put_result(io.out, io.perm, status, r, v);
-                } else {
-                  coherent_store(dst + r, v);
-                  P.put(i, v);  // the next step's owned state
-                }
+                coherent_store(dst + r, v);
+                P.put(i, v);  // the next step's owned state
               },
               [](int, int32_t, const C&) {});
     } else {
       // the last stage reads B only, so the owned state can go back into A
       st.step_unsplit(d, UA, UB, USA, USB, h, gamma, [&](int i, int32_t r, const C& v) {
-        if (fin) {
-          put_result(io.out, io.perm, status, r, v);
-        } else {
-          coherent_store(dst + r, v);
-          UA[i] = v;
-          USA[i] = v.x * v.x + v.y * v.y;
-        }
+        coherent_store(dst + r, v);
+        UA[i] = v;
+        USA[i] = v.x * v.x + v.y * v.y;
       });
     }
-    if (fin) break;
     wait_stores();
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(flags + tile, need + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -3825,14 +3909,64 @@ void launch_perm_out(const DevOps<T>& d, const int32_t* perm, const void* src, v
 
 template <typename T>
 void launch_bperm(const DevOps<T>& d, const int64_t* cbase, const int32_t* fcount, const void* src, void* dst,
-                  bool out, int* flag, int block, hipStream_t st) {
+                  bool out, int* flag, int block, hipStream_t st, bool field_major) {
   const unsigned g = grid_for(d.n_rows * d.F, block, 0);
   if (out)
     hipLaunchKernelGGL((k_bperm_out<T>), dim3(g), dim3(block), 0, st, d.n_rows, d.F, cbase, fcount,
-                       DECBPM_C(T, src), DECBPM_M(T, dst), flag);
+                       DECBPM_C(T, src), DECBPM_M(T, dst), flag, int(field_major));
   else
     hipLaunchKernelGGL((k_bperm_in<T>), dim3(g), dim3(block), 0, st, d.n_rows, d.F, cbase, fcount,
-                       DECBPM_C(T, src), DECBPM_M(T, dst));
+                       DECBPM_C(T, src), DECBPM_M(T, dst), int(field_major));
+}
+
+template <typename T>
+void launch_step_fields(const DevOps<T>& d, const TileOps<T>& tl, const void* in, void* out, double h, double tau,
+                        double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
+  const int J = (tl.max_compute + block - 1) / block;
+  const int LS = (tl.max_slots + block - 1) / block;
+  const int32_t nf = d.F;
+  // the operator rows take J slots per thread; the state LS (at most three slots of every ring)
+#define DECBPM_SF(KM, DEC, JJ, LL)                                                                                    \
+  hipLaunchKernelGGL((k_step_fields<T, KM, DEC, JJ, LL>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in),   \
+                     DECBPM_M(T, out), T(h), T(tau), T(gamma), nf)
+#define DECBPM_SF_J(KM, DEC)                                                           \
+  if (J <= 1) {                                                                        \
+    if (LS <= 2) DECBPM_SF(KM, DEC, 1, 2); else DECBPM_SF(KM, DEC, 1, 3);                \
+  } else {                                                                             \
+    if (LS <= 2) DECBPM_SF(KM, DEC, 2, 2); else DECBPM_SF(KM, DEC, 2, 3);                \
+  }
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_SF_J(8, true) } else { DECBPM_SF_J(8, false) }
+  } else {
+    if (dec) { DECBPM_SF_J(12, true) } else { DECBPM_SF_J(12, false) }
+  }
+#undef DECBPM_SF_J
+#undef DECBPM_SF
+}
+
+template <typename T>
+void launch_kerr_fields(const DevOps<T>& d, const TileOps<T>& tl, const void* in, void* out, double tau,
+                        double gamma, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * sizeof(T);
+  const int J = (tl.max_compute + block - 1) / block;
+  const int32_t nf = d.F;
+#define DECBPM_KF(KM, DEC, JJ)                                                                                   \
+  hipLaunchKernelGGL((k_kerr_fields<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in),  \
+                     DECBPM_M(T, out), T(tau), T(gamma), nf)
+#define DECBPM_KF_J(KM, DEC) \
+  if (J <= 1) DECBPM_KF(KM, DEC, 1); else DECBPM_KF(KM, DEC, 2);
+  const bool dec = tl.lmw != nullptr;
+  if (kmax_of(d.wmax) == 8) {
+    if (dec) { DECBPM_KF_J(8, true) } else { DECBPM_KF_J(8, false) }
+  } else {
+    if (dec) { DECBPM_KF_J(12, true) } else { DECBPM_KF_J(12, false) }
+  }
+#undef DECBPM_KF_J
+#undef DECBPM_KF
 }
 
 template <typename T>
@@ -3960,7 +4094,11 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
   template void launch_kerr_tile<T>(const DevOps<T>&, const TileOps<T>&, const void*, const int32_t*, void*,      \
                                     double, double, int, hipStream_t);                                           \
   template void launch_bperm<T>(const DevOps<T>&, const int64_t*, const int32_t*, const void*, void*, bool, int*,  \
-                                int, hipStream_t);                                                               \
+                                int, hipStream_t, bool);                                                         \
+  template void launch_step_fields<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double,     \
+                                      double, int, hipStream_t);                                                 \
+  template void launch_kerr_fields<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, int, \
+                                      hipStream_t);                                                              \
   template int persist_capacity<T>(const DevOps<T>&, const TileOps<T>&, int, int);                                \
   template void launch_step_b4<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, double, \
                                   int, hipStream_t, const int32_t*, int*);                                       \

@@ -190,9 +190,21 @@ void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi
 // device element (row, f) is caller element cbase[row] + f when
 // f < fcount[row]; other device fields are zero in (out = false) and dropped
 // out (out = true, which also sets bit 0 of *flag for a non-finite value).
+// field_major: the device layout is field f of row r at f * n_rows + r
+// instead of r * F + f.
 template <typename T>
 void launch_bperm(const DevOps<T>& d, const int64_t* cbase, const int32_t* fcount, const void* src, void* dst,
-                  bool out, int* flag, int block, hipStream_t st);
+                  bool out, int* flag, int block, hipStream_t st, bool field_major = false);
+// Every field of a batch (d.F fields, field-major device layout) on one-field
+// step tiles: one merged z step (LIN(h) then NL(tau)), and NL(tau) alone.
+// One workgroup per tile steps the fields one after another with the
+// operator rows kept in registers.
+template <typename T>
+void launch_step_fields(const DevOps<T>& d, const TileOps<T>& tl, const void* in, void* out, double h, double tau,
+                        double gamma, int block, hipStream_t st);
+template <typename T>
+void launch_kerr_fields(const DevOps<T>& d, const TileOps<T>& tl, const void* in, void* out, double tau,
+                        double gamma, int block, hipStream_t st);
 // NL(tau) of the caller's field (caller order: row r at src[perm[r]]) into
 // the device-order buffer dst, on the step tiles (any ring count): the first
 // half step of a propagate, with the persistent launch's per-row arithmetic.

@@ -736,29 +736,35 @@ def test_batched_equals_plain(dtype):
     meshes = [lib_mesh(x, dtype) for x in ws]
     batch = api.Batch(meshes, 4)
     packed0 = batch.pack([dev(x.u0, dtype) for x in ws])
-    # LDS-tiled batched stage kernels and the batched one-kernel step vs the
-    # row-parallel kernels: identical per-row formulas
+    # LDS-tiled batched stage kernels, the batched one-kernel step and the field-loop
+    # step (one-field tiles, every field in turn) vs the row-parallel kernels:
+    # identical per-row formulas
     runs = {}
-    for fused in (0, 1, 2):
+    for fused in (0, 1, 2, 3):
         batch.tuning = {"fused": fused}
         assert batch.tuning["fused"] == fused
         pk = packed0.clone()
         batch.propagate(pk, ws[0].dz, ws[0].n_steps, 1.0)
+        batch.check_finite()
         runs[fused] = pk
-    for fused in (1, 2):
+        if fused >= 2:
+            assert batch.time_kernels(ws[0].dz, 1.0, reps=5)["step"]["ms"] > 0  # the mode's tiles exist
+    for fused in (1, 2, 3):
         assert rel(host(runs[fused]), host(runs[0])) < (1e-13 if dtype == "c128" else 1e-6), fused
-    times = batch.time_kernels(ws[0].dz, 1.0, reps=5)
-    assert times["step"]["ms"] > 0  # the batched step tiles exist
-    outs = batch.unpack(runs[1])
     tol = 1e-12 if dtype == "c128" else 1e-6  # same per-row formulas; only FMA contraction may differ
-    for m, x, o in zip(meshes, ws, outs):
-        for f in range(4):
-            for fused in (0, 1, 2, 3):
-                m.tuning = {"fused": fused}
-                single = dev(x.u0[f], dtype)
-                m.propagate(single, x.dz, x.n_steps, 1.0)
-                err = rel(host(o[f].contiguous()), host(single))
-                assert err < tol, (fused, err)
+    for bf in (1, 3):
+        outs = batch.unpack(runs[bf])
+        for m, x, o in zip(meshes, ws, outs):
+            for f in range(4):
+                for fused in (0, 1, 2, 3):
+                    m.tuning = {"fused": fused}
+                    single = dev(x.u0[f], dtype)
+                    m.propagate(single, x.dz, x.n_steps, 1.0)
+                    err = rel(host(o[f].contiguous()), host(single))
+                    assert err < tol, (bf, fused, err)
+                    if bf == 3 and fused >= 2:  # the same one-field step arithmetic
+                        assert torch.equal(o[f].contiguous(), single), (fused, f)
+    outs = batch.unpack(runs[1])
     # and one field against the oracle
     ops = oracle_ops(ws[1])
     ref = S.propagate(ws[1].u0[2], ops, ws[1].dz, ws[1].n_steps, 1.0)
@@ -782,10 +788,11 @@ def test_batched_uneven_field_counts(dtype):
     buf = torch.full((batch.n_elems + 2 * guard,), 3.5 - 1.5j, dtype=fields[0].dtype, device=DEV)
     buf[guard:guard + batch.n_elems] = batch.pack(fields)
     packed = buf[guard:guard + batch.n_elems]
-    for fused in (0, 1, 2):
+    for fused in (0, 1, 2, 3):
         batch.tuning = {"fused": fused}
         pk = packed.clone()
         batch.propagate(pk, ws[0].dz, ws[0].n_steps, 1.0)
+        batch.check_finite()
         outs = batch.unpack(pk)
         tol = 1e-12 if dtype == "c128" else 1e-6
         for m, x, o, c in zip(meshes, ws, outs, counts):
