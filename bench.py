@@ -130,8 +130,45 @@ def dominant_kernel_roofline(mode, kt, n_vert=None, dtype="c64", nl="dec", beta4
             "kernels_frac": {c: v["bytes"] / (v["ms"] * 1e-3) / 8e12 for c, v in kt.items() if v["ms"] > 0}}
 
 
+def profile_batched(args, api, W, torch, dev, tdt):
+    """The batched workload alone, for rocprofv3: warm-up, then the timed batched propagate."""
+    ws = W.batched_pcf()
+    F = ws[0].u0.shape[0]
+    meshes = [api.Mesh(x.mesh.xy, x.mesh.tri, x.index_tri, x.absorber, dtype=args.dtype) for x in ws]
+    batch = api.Batch(meshes, F)
+    if args.tuning:
+        batch.tuning = json.loads(args.tuning)
+    else:
+        batch.autotune(ws[0].dz, 1.0)
+    p0 = batch.pack([torch.from_numpy(x.u0).to(dev, tdt) for x in ws])
+    p = p0.clone()
+    batch.propagate(p, ws[0].dz, args.warmup, 1.0)
+    p = p0.clone()
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    batch.propagate(p, ws[0].dz, args.steps, 1.0)
+    s1.record()
+    torch.cuda.synchronize()
+    batch.check_finite()
+    if args.calibrate_copy:  # a plain copy of known size, for scaling the traffic counters
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    vf = sum(x.mesh.n_vert for x in ws) * F
+    print(json.dumps({"profile_only": True, "path": "batched", "vertex_fields": vf, "units": args.steps,
+                      "us_per_unit": s0.elapsed_time(s1) * 1e3 / args.steps, "tuning": batch.tuning}))
+    batch.close()
+    for m in meshes:
+        m.close()
+
+
 def profile_path(args, api, W, torch, dev, tdt):
     """One path alone, for rocprofv3: warm-up, then the timed call; prints one JSON line."""
+    if args.profile_path == "batched":
+        return profile_batched(args, api, W, torch, dev, tdt)
     w = W.vortex_beta4() if args.profile_path == "vortex_beta4" else W.step_index()
     pml = (35.0, 40.0, 1.0) if args.profile_path == "pml" else None
     m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, None if pml else w.absorber, dtype=args.dtype, p1=w.p1,
@@ -164,6 +201,12 @@ def profile_path(args, api, W, torch, dev, tdt):
     units = args.steps
     if args.profile_path == "adaptive":
         units = info["accepted"] + info["rejected"]
+    if args.calibrate_copy:  # a plain copy of known size, for scaling the traffic counters
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps({"profile_only": True, "path": args.profile_path, "vertices": w.mesh.n_vert,
                       "units": units, "us_per_unit": s0.elapsed_time(s1) * 1e3 / units, "tuning": m.tuning}))
     m.close()  # release device memory and graphs before the interpreter (and a profiler) shuts down
@@ -174,7 +217,7 @@ def measured_traffic(cls):
     counter summary, if it was taken on the current kernel sources (else None)."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"k_{cls}_step_index_250k_pmc.md")
+    path = os.path.join(ROOT, "profiles", f"k_{cls}_step_index_250k.md")
     src = os.path.join(ROOT, "paper_2608_03587_amd", "csrc", "kernels.hip")
     try:
         text = open(path).read()
@@ -199,10 +242,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="only the timed propagation (for rocprofv3)")
-    ap.add_argument("--profile-path", default="split", choices=["split", "vortex_beta4", "pml", "adaptive", "mode"],
+    ap.add_argument("--profile-path", default="split",
+                    choices=["split", "vortex_beta4", "pml", "adaptive", "mode", "batched"],
                     help="with --profile: which path to run (split: the step-index propagate; vortex_beta4: the "
                          "1M-vertex beta4 launch; pml: the step-index launch with the layer; adaptive: the "
-                         "Dormand-Prince run over --steps dz; mode: --steps mode-solver iterations)")
+                         "Dormand-Prince run over --steps dz; mode: --steps mode-solver iterations; batched: the "
+                         "8-mesh, 256-field batch)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="with --profile: also run a 256 MiB device copy (traffic counter calibration)")
     ap.add_argument("--tuning", default="", help="fixed launch shape as JSON (skips autotuning), e.g. the "
