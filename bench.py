@@ -288,9 +288,9 @@ def main():
 
     def timed_propagate(m, dtype, steps, warmup):
         u0 = torch.from_numpy(w.u0).to(dev, tdt[dtype])
-        f = u0.clone()
+        f = u0.clone()  # the warm-up runs on the buffer the timed call uses, so it is resident and mapped
         m.propagate(f, w.dz, warmup, w.gamma)
-        f = u0.clone()
+        f.copy_(u0)
         stream = torch.cuda.current_stream()
         torch.cuda.synchronize()
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -446,9 +446,9 @@ def main():
         except Exception as e:  # noqa: BLE001
             extras["general"] = {"error": repr(e)}
         try:
-            extras["conditioning"] = bench_conditioning(api, w, torch, dev, tdt, args.steps)
+            extras["full_length_parity"] = bench_full_length(api, w, torch, dev, tdt)
         except Exception as e:  # noqa: BLE001
-            extras["conditioning"] = {"error": repr(e)}
+            extras["full_length_parity"] = {"error": repr(e)}
         try:
             extras["batched"] = bench_batched(api, W, torch, dev, tdt)
         except Exception as e:  # noqa: BLE001
@@ -542,13 +542,16 @@ def bench_batched(api, W, torch, dev, tdt):
            "plain_ms_extrapolated": t_plain, "speedup_vs_plain": t_plain / t_b, "tuning": batch.tuning,
            "kernel": cls, "kernel_us": kt["ms"] * 1e3,
            "kernel_GBps": kt["bytes"] / (kt["ms"] * 1e-3) / 1e9, "kernel_frac_hbm": kt["bytes"] / (kt["ms"] * 1e-3) / 8e12,
+           # the field-loop step runs the plain one-kernel step's arithmetic (bitwise equal to the
+           # tuned plain propagate); the stage kernels run the row kernels' (bitwise equal to those)
+           "batched_equals_tuned_plain_bitwise": max_rel == 0.0,
            "batched_equals_unfused_plain_bitwise": same, "max_rel_vs_unfused_plain": max_rel_unfused,
            "max_rel_vs_tuned_plain": max_rel, f"max_rel_vs_tuned_plain_after_{short}_steps": prefix_rel,
            "largest_mesh_field0_c64_vs_c128_full_length": c64_vs_c128,
            "fields": F * len(ws), "vertex_fields": vf, "steps": n_steps,
            "note": "plain = 8 fields (one per mesh) timed at full length x 32"}
     log(f"[bench] batched: {res['vertex_field_steps_per_s']:.3e} vertex-field z-steps/s, "
-        f"{res['speedup_vs_plain']:.1f}x plain, bitwise equal {same}")
+        f"{res['speedup_vs_plain']:.1f}x plain, bitwise equal to tuned plain {max_rel == 0.0}")
     return res
 
 
@@ -876,42 +879,30 @@ def bench_mode(api, w, torch, dev, tdt, with_oracle):
     return out
 
 
-def bench_conditioning(api, w, torch, dev, tdt, steps):
-    """How well-posed the complex64 gate is on the step-index launch (supercritical power): the
-    amplification kappa of a 1e-7 relative input perturbation in complex128 (whose per-step
-    agreement with the FP64 oracle is at the 1e-15 level, so it stands in for two oracle runs), and
-    the complex64 vs complex128 distance along the run."""
+def bench_full_length(api, w, torch, dev, tdt):
+    """Parity at the workload's final z against the stored FP64 oracle fields, and the oracle's own
+    conditioning probe of the launch (both written by tests/golden/make_references.py, which calls
+    only the oracle): complex128 over all steps, complex64 to the largest z where the oracle run
+    perturbed by one FP32 unit roundoff per step stays within a tenth of the complex64 gate."""
     import numpy as np
 
-    m128 = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype="c128", p1=w.p1, beta4=w.beta4)
-    m64 = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype="c64", p1=w.p1, beta4=w.beta4)
-    eps = 1e-7
-    noise = np.random.default_rng(7).standard_normal(w.u0.shape)
-    u_pert = w.u0 * (1 + eps * noise)
-    chunk = max(1, steps // 10)
-    a = torch.from_numpy(w.u0).to(dev, tdt["c128"])
-    b = torch.from_numpy(u_pert).to(dev, tdt["c128"])
-    c = torch.from_numpy(w.u0).to(dev, tdt["c64"])
-    rel = lambda x, y: float(torch.linalg.norm(x.to(torch.complex128) - y) / torch.linalg.norm(y))  # noqa: E731
-    r0 = rel(b, a)
-    rows, done, last_ok = [], 0, 0
-    while done < steps:
-        k = min(chunk, steps - done)
-        for m, f in ((m128, a), (m128, b), (m64, c)):
-            m.propagate(f, w.dz, k, w.gamma)
-        done += k
-        torch.cuda.synchronize()
-        kappa = rel(b, a) / r0
-        d64 = rel(c, a)
-        rows.append({"step": done, "z": done * w.dz, "kappa": kappa, "c64_vs_c128": d64})
-        if d64 < 1e-4:
-            last_ok = done
-    res = {"input_perturbation_rel": r0, "kappa_final": rows[-1]["kappa"], "c64_vs_c128_final": rows[-1]["c64_vs_c128"],
-           "kappa_times_6e-8": rows[-1]["kappa"] * 6e-8, "largest_step_c64_within_1e-4": last_ok,
-           "note": "propagated in chunks of %d steps (the merged half steps at chunk ends are exact)" % chunk,
-           "trace": rows}
-    log(f"[bench] conditioning: kappa {res['kappa_final']:.3g}, c64 vs c128 at the end {res['c64_vs_c128_final']:.3g}, "
-        f"c64 within 1e-4 up to step {last_ok}")
+    z = np.load(os.path.join(ROOT, "tests", "golden", "ref_step_index.npz"))
+    res = {"source": "tests/golden/ref_step_index.npz (FP64 oracle)",
+           "oracle_probe": {"steps": z["probe_steps"].tolist(), "kappa_input_1e-7": z["kappa"].tolist(),
+                            "delta_fp32_noise": z["delta64"].tolist(), "delta_fp64_noise": z["delta128"].tolist()}}
+    for dtype, n, ref, gate in (("c128", int(z["s_end"]), z["psi_end"], 1e-10),
+                                ("c64", int(z["s64"]), z["psi64"].astype(np.complex128), 1e-4)):
+        m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=dtype, p1=w.p1, beta4=w.beta4)
+        m.autotune(w.dz, w.gamma)
+        f = torch.from_numpy(w.u0).to(dev, tdt[dtype])
+        m.propagate(f, w.dz, n, w.gamma)
+        m.check_finite()
+        got = f.cpu().numpy().astype(np.complex128)
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        res[dtype] = {"steps": n, "z": n * w.dz, "rel_l2_vs_oracle": err, "gate": gate, "pass": err <= gate,
+                      "max_vertex_rel": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))}
+        m.close()
+        log(f"[bench] full length {dtype}: {n} steps, rel L2 vs oracle {err:.3e} (gate {gate:g})")
     return res
 
 
