@@ -48,6 +48,7 @@ struct DevTiles {
   void* llw = nullptr;
   void* lmw = nullptr;
   void* llwi = nullptr;  // imaginary part of the L weights (PML handles), else null
+  uint8_t* dep = nullptr;  // step layout: depth of each owned slot (see HostTiles)
   int64_t entries = 0, slots = 0;
   int32_t ext_stride = 0, lsl_stride = 0, hdr_stride = 8;
 
@@ -69,6 +70,7 @@ struct DevTiles {
     t.llw = static_cast<const T*>(llw);
     t.lmw = static_cast<const T*>(lmw);
     t.llwi = static_cast<const T*>(llwi);
+    t.dep = dep;
     return t;
   }
 };
@@ -333,6 +335,9 @@ struct HostTiles {
   std::vector<int32_t> hdr, ext, lsl;
   std::vector<int64_t> ebase;
   std::vector<uint16_t> lcol;
+  // step layout: per slot, the graph distance of an owned row to the nearest
+  // row the tile does not own (capped at 7; 0 for halo slots), at the ext stride
+  std::vector<uint8_t> dep;
   std::vector<double> llw, lmw, llwi;
   int32_t max_slots = 0, max_compute = 0;
   int32_t ext_stride = 0, lsl_stride = 0;  // step layout: fixed per-tile strides
@@ -362,6 +367,7 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
   std::vector<int32_t> slot_of(n, -1);
   std::vector<int32_t> slots, ring;
   std::vector<std::vector<int32_t>> ext_t, lsl_t;
+  std::vector<std::vector<uint8_t>> dep_t;
   if (step_layout) {
     ext_t.resize(H.nt);
     lsl_t.resize(H.nt);
@@ -406,6 +412,30 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
         b += cnt[k];
       }
       for (size_t i = 0; i < slots.size(); ++i) slot_of[slots[i]] = int32_t(i);
+    }
+    if (step_layout) {  // depth of each owned slot: breadth-first from the ring-1 rows inwards
+      std::vector<uint8_t> dd(slots.size(), 0);
+      std::vector<int32_t> frontier, next;
+      const int n0 = cnt[0];
+      for (int i = n0; i < n0 + cnt[1]; ++i) frontier.push_back(slots[i]);
+      std::vector<uint8_t> seen(slots.size(), 0);
+      for (int i = n0; i < int(slots.size()); ++i) seen[i] = 1;
+      for (uint8_t dist = 1; dist <= 7 && !frontier.empty(); ++dist) {
+        next.clear();
+        for (int32_t r : frontier)
+          for (int64_t e = arp[r]; e < arp[r + 1]; ++e) {
+            const int32_t q = slot_of[acol[e]];
+            if (q >= 0 && q < n0 && !seen[q]) {
+              seen[q] = 1;
+              dd[q] = dist;
+              next.push_back(acol[e]);
+            }
+          }
+        frontier.swap(next);
+      }
+      for (int i = 0; i < n0; ++i)
+        if (!seen[i]) dd[i] = 7;  // farther than 7 (or a tile without halo)
+      dep_t.push_back(std::move(dd));
     }
     int32_t* h = &H.hdr[t * H.hdr_stride];
     if (step_layout) {  // cumulative counts of rings 0..k, ring count (offsets come from the strides)
@@ -467,9 +497,11 @@ static bool make_tiles(int64_t n, const std::vector<int64_t>& arp, const std::ve
     H.lsl_stride = std::max<int32_t>(1, (H.lsl_stride + 15) / 16 * 16);
     H.ext.assign(size_t(H.nt) * H.ext_stride, 0);
     H.lsl.assign(size_t(H.nt) * H.lsl_stride, 0);
+    H.dep.assign(size_t(H.nt) * H.ext_stride, 0);
     for (int64_t t = 0; t < H.nt; ++t) {
       std::copy(ext_t[t].begin(), ext_t[t].end(), H.ext.begin() + t * H.ext_stride);
       std::copy(lsl_t[t].begin(), lsl_t[t].end(), H.lsl.begin() + t * H.lsl_stride);
+      std::copy(dep_t[t].begin(), dep_t[t].end(), H.dep.begin() + t * H.ext_stride);
     }
   }
   if (H.ext.empty()) H.ext.push_back(0);
@@ -490,6 +522,10 @@ static void upload_tiles(Engine& E, const HostTiles& H, bool dec, int64_t n, Dev
   D.lsl = static_cast<int32_t*>(p);
   upload(E, p, H.lcol);
   D.lcol = static_cast<uint16_t*>(p);
+  if (!H.dep.empty()) {
+    upload(E, p, H.dep);
+    D.dep = static_cast<uint8_t*>(p);
+  }
   std::vector<T> w(H.llw.begin(), H.llw.end());
   upload(E, D.llw, w);
   if (!H.llwi.empty()) {

@@ -1202,6 +1202,7 @@ struct StepTile {
   int wd[J];  // slice width (wave-uniform)
   int32_t rr[J];
   T vv[J], ww[J], md[J];
+  uint32_t dpk;  // depth of each register slot's row, 8 bits per slot (split step only)
 
   __device__ int32_t slot_row(int i) const { return ext[i]; }
   __device__ int nb(int j, int k) const { return q[j][k]; }
@@ -1222,6 +1223,15 @@ struct StepTile {
     nNL = hd[0];
     const int nRows = kerr_only ? hd[1] : n1;
     const int B = blockDim.x;
+    dpk = 0;
+    if (tl.dep != nullptr) {
+      const uint8_t* dp = tl.dep + tile * int64_t(tl.ext_stride);
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int i = threadIdx.x + j * B;
+        if (i < nNL) dpk |= uint32_t(dp[i]) << (8 * j);
+      }
+    }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int i = threadIdx.x + j * B;
@@ -1440,6 +1450,129 @@ struct StepTile {
         out(i, rr[j], r);
       }
     }
+  }
+
+  // The z step split around the neighbour wait of the persistent launch.
+  // Before mid(), every stage is computed on the owned slots whose inputs are
+  // owned rows of the previous state: stage k (k = 1..4) where the row's
+  // distance to the nearest row the tile does not own is at least k + 1, the
+  // Kerr flow where it is at least 6 (5 for the lumped form, whose gather is
+  // the row itself).  mid() waits for the neighbour tiles and stages the halo
+  // (false: the wait gave up, the step is abandoned).  After it, every other
+  // slot.  Per slot the operations and their order are those of step(), so
+  // the result is the same.  out_deep(slot, row, value) receives the owned
+  // rows finished before the wait (no other tile reads them: their distance
+  // exceeds the five halo rings), out(slot, row, value) the rest.
+  template <typename V, typename OutDeep, typename Out, typename Mid>
+  __device__ bool step_split(const DevOps<T>& d, const V& P, const V& X, const V& Y, T* S, T h, T tau, T gamma,
+                             OutDeep out_deep, Out out, Mid mid) const {
+    const int B = blockDim.x;
+    constexpr int KD = DEC ? 6 : 5;
+    C p[J], cur[J];
+    T so[J];
+    auto early = [&](int i, int j, int lim) { return i < nNL && int((dpk >> (8 * j)) & 0xffu) >= lim; };
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (early(i, j, 2)) {
+        p[j] = P.get(i);
+        cur[j] = stage(d, P, p[j], p[j], j, T(0.25) * h);  // y1
+        Y.put(i, cur[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (early(i, j, 3)) {
+        cur[j] = stage(d, Y, cur[j], p[j], j, h / T(3));  // y2
+        X.put(i, cur[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (early(i, j, 4)) {
+        cur[j] = stage(d, X, cur[j], p[j], j, T(0.5) * h);  // y3
+        Y.put(i, cur[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (early(i, j, 5)) {  // state before the Kerr substep
+        cur[j] = stage(d, Y, cur[j], p[j], j, h);
+        so[j] = (cur[j].x * cur[j].x + cur[j].y * cur[j].y) * phi_w(ww[j], tau);
+        S[i] = so[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (early(i, j, KD)) out_deep(i, rr[j], kerr_of(d, S, j, cur[j], so[j], tau, gamma));
+    }
+    if (!mid()) return false;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n1 && !early(i, j, 2)) {
+        p[j] = P.get(i);
+        cur[j] = stage(d, P, p[j], p[j], j, T(0.25) * h);  // y1
+        Y.put(i, cur[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n2 && !early(i, j, 3)) {
+        cur[j] = stage(d, Y, cur[j], p[j], j, h / T(3));  // y2
+        X.put(i, cur[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n3 && !early(i, j, 4)) {
+        cur[j] = stage(d, X, cur[j], p[j], j, T(0.5) * h);  // y3
+        Y.put(i, cur[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < n4 && !early(i, j, 5)) {
+        cur[j] = stage(d, Y, cur[j], p[j], j, h);
+        so[j] = (cur[j].x * cur[j].x + cur[j].y * cur[j].y) * phi_w(ww[j], tau);
+        S[i] = so[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < nNL && !early(i, j, KD)) out(i, rr[j], kerr_of(d, S, j, cur[j], so[j], tau, gamma));
+    }
+    return true;
+  }
+
+  // The Kerr/absorber flow of register slot j (state b, its |b|^2 phi in so),
+  // the neighbours' |.|^2 phi from S: step()'s last phase for one slot.
+  __device__ C kerr_of(const DevOps<T>& d, const T* S, int j, const C& b, T so_j, T tau, T gamma) const {
+    T th = md[j] * so_j;
+    if constexpr (DEC) th = msum_w<KMAX>(wd[j], S, j, th);
+    const T damp = d_exp(-ww[j] * tau);
+    T sn, cs;
+    d_sincos(gamma * th, &sn, &cs);
+    C r;
+    r.x = damp * (b.x * cs - b.y * sn);
+    r.y = damp * (b.x * sn + b.y * cs);
+    return r;
   }
 
   // NL(tau) alone of a field held in the caller's vertex order (row r at
@@ -2945,38 +3078,38 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
     wait_stores();
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(flags + tile, io.base + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else if constexpr (BODY == 0) {  // the starting state is in buf0: its owned rows into P
+#pragma unroll
+    for (int l = 0; l < LS; ++l)
+      if (pr[l] >= 0 && int(threadIdx.x) + l * B < st.nNL) P.put(threadIdx.x + l * B, coherent_load(buf0 + pr[l]));
   }
   __syncthreads();
-  for (int32_t s = 0; s < n_steps; ++s) {
-    st.opaque_neighbours();
-    const C* src = (s & 1) ? buf1 : buf0;
-    C* dst = (s & 1) ? buf0 : buf1;
-    const int32_t need = io.base + s + (pro ? 1 : 0);  // flag of the state step s reads
-    if (s > 0 || pro) {
-      if (threadIdx.x < 64) {  // one wave polls all neighbour flags at once
-        // lanes without a neighbour poll this tile's own flag, which already
-        // holds the value (published at the end of the previous step)
-        const int32_t* fl = flags + (int(threadIdx.x) < n_nb ? nb_s[threadIdx.x] : int32_t(tile));
-        bool ok = true;
-        for (int32_t spins = 0;; ++spins) {
-          if (__all(__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need)) break;
-          if (spins >= spin_limit) {
-            ok = false;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
+  // wait until every neighbour tile has published `need`; false if the wait gave up
+  auto wait_nb = [&](int32_t need) -> bool {
+    if (threadIdx.x < 64) {  // one wave polls all neighbour flags at once
+      // lanes without a neighbour poll this tile's own flag, which already
+      // holds the value (published at the end of the previous step)
+      const int32_t* fl = flags + (int(threadIdx.x) < n_nb ? nb_s[threadIdx.x] : int32_t(tile));
+      bool ok = true;
+      for (int32_t spins = 0;; ++spins) {
+        if (__all(__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need)) break;
+        if (spins >= spin_limit) {
+          ok = false;
+          break;
         }
-        if (threadIdx.x == 0) {
-          abort_s = ok ? 0 : 1;
-          if (!ok) __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        __builtin_amdgcn_s_sleep(1);
       }
-      __syncthreads();
-      if (abort_s) return;
+      if (threadIdx.x == 0) {
+        abort_s = ok ? 0 : 1;
+        if (!ok) __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
-    // stage the state: the owned slots (ring 0) stay in LDS from the previous
-    // step (or the prologue), so only the halo is loaded
-    const int first = (s == 0 && !pro) ? 0 : st.nNL;
+    __syncthreads();
+    return !abort_s;
+  };
+  // stage slots first.. of the state in src: the owned slots (ring 0) stay in
+  // LDS from the previous step (or the prologue), so only the halo is loaded
+  auto stage_state = [&](const C* src, int first) {
     C pv[LS];  // issue every load before the first use
 #pragma unroll
     for (int l = 0; l < LS; ++l)
@@ -2992,24 +3125,48 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
         }
       }
     __syncthreads();
-    if (io.out != nullptr && s == n_steps - 1) {  // the last step: the result goes to the caller's field
-      if constexpr (BODY == 0)
-        st.step(d, P, X, Y, S, h, io.tau_last, gamma,
-                [&](int, int32_t r, const C& v) { put_result(io.out, io.perm, status, r, v); },
-                [](int, int32_t, const C&) {});
-      else
+  };
+  for (int32_t s = 0; s < n_steps; ++s) {
+    st.opaque_neighbours();
+    const C* src = (s & 1) ? buf1 : buf0;
+    C* dst = (s & 1) ? buf0 : buf1;
+    const int32_t need = io.base + s + (pro ? 1 : 0);  // flag of the state step s reads
+    const bool fin = io.out != nullptr && s == n_steps - 1;  // the last step: the result goes to the caller's field
+    if constexpr (BODY == 0) {
+      // the split step: the owned rows that need no halo are stepped while the
+      // neighbours finish; the rest after the wait
+      auto mid = [&]() -> bool {
+        if ((s > 0 || pro) && !wait_nb(need)) return false;
+        stage_state(src, st.nNL);
+        return true;
+      };
+      if (fin) {
+        auto res = [&](int, int32_t r, const C& v) { put_result(io.out, io.perm, status, r, v); };
+        if (!st.step_split(d, P, X, Y, S, h, io.tau_last, gamma, res, res, mid)) return;
+        break;
+      }
+      // rows deeper than the halo rings are read by no other tile: they stay in
+      // LDS, and reach the state buffer only when the launch ends there
+      const bool keep = io.out == nullptr && s == n_steps - 1;
+      if (!st.step_split(d, P, X, Y, S, h, h, gamma,
+                         [&](int i, int32_t r, const C& v) {
+                           if (keep) dst[r] = v;
+                           P.put(i, v);
+                         },
+                         [&](int i, int32_t r, const C& v) {
+                           coherent_store(dst + r, v);
+                           P.put(i, v);  // the next step's owned state
+                         },
+                         mid))
+        return;
+    } else {
+      if ((s > 0 || pro) && !wait_nb(need)) return;
+      stage_state(src, s == 0 ? 0 : st.nNL);
+      if (fin) {
         st.step_unsplit(d, UA, UB, USA, USB, h, gamma,
                         [&](int, int32_t r, const C& v) { put_result(io.out, io.perm, status, r, v); });
-      break;
-    }
-    if constexpr (BODY == 0) {
-      st.step(d, P, X, Y, S, h, h, gamma,
-              [&](int i, int32_t r, const C& v) {
-                coherent_store(dst + r, v);
-                P.put(i, v);  // the next step's owned state
-              },
-              [](int, int32_t, const C&) {});
-    } else {
+        break;
+      }
       // the last stage reads B only, so the owned state can go back into A
       st.step_unsplit(d, UA, UB, USA, USB, h, gamma, [&](int i, int32_t r, const C& v) {
         coherent_store(dst + r, v);

@@ -64,6 +64,8 @@ struct TileOps {
   const T* llw;
   const T* lmw;             // nullptr for the lumped nonlinearity
   const T* llwi;            // imaginary part of the L weights (complex-stretched L), else nullptr
+  const uint8_t* dep;       // step layout: per slot (ext stride), an owned row's graph distance to
+                            // the nearest row the tile does not own (capped at 7); 0 for halo slots
   int32_t ext_stride;       // step layout: per-tile stride of ext (every slot listed) and of lsl;
   int32_t lsl_stride;       // 0: classic layout (offsets in the header, ring 0 implicit)
   int32_t hdr_stride;       // ints per tile header (8 classic, 16 step layout)
