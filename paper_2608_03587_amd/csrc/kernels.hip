@@ -1189,7 +1189,12 @@ struct StepBound {
 // wave-uniform width, padded entries pointing at their own slot with weight 0.
 // CL: the L weights are complex (a perfectly matched layer stretches the
 // Hodge stars); their imaginary parts ride in a second register array.
-template <typename T, int KMAX, bool DEC, int J, bool CL = false>
+// LM: the M weights of the owned slots sit in LDS (TS x KP words, entry k of
+// slot i at i * KP + k with the odd row length KP = KMAX | 1, so that the 64
+// lanes of a wave reading entry k hit distinct banks and each entry is an
+// immediate offset from one address per slot) instead of registers, for
+// kernels that hold more per-slot state than the register file leaves room for.
+template <typename T, int KMAX, bool DEC, int J, bool CL = false, bool LM = false>
 struct StepTile {
   using C = typename CT<T>::C;
   int nLoad, n1, n2, n3, n4, nNL;
@@ -1198,7 +1203,9 @@ struct StepTile {
   int q[J][KMAX];  // neighbour slots
   T cl[J][KMAX];
   T cli[J][CL ? KMAX : 1];
-  T cm[J][DEC ? KMAX : 1];
+  T cm[J][(DEC && !LM) ? KMAX : 1];
+  T* cml;  // LM: the LDS table of the M weights
+  static constexpr int KP = KMAX | 1;
   int wd[J];  // slice width (wave-uniform)
   int32_t rr[J];
   T vv[J], ww[J], md[J];
@@ -1209,7 +1216,10 @@ struct StepTile {
 
   // kerr_only: load the rows the NL substep alone needs (rings 0..1, the
   // reach of the M gather), not every compute slot's
-  __device__ void init(const DevOps<T>& d, const TileOps<T>& tl, int64_t tile, bool kerr_only = false) {
+  // m_lds (LM): where the M weight table goes; it is read after the caller's next barrier
+  __device__ void init(const DevOps<T>& d, const TileOps<T>& tl, int64_t tile, bool kerr_only = false,
+                       T* m_lds = nullptr) {
+    cml = m_lds;
     hd = tl.hdr + int64_t(tl.hdr_stride) * tile;  // hd[k]: slots in rings 0..k; hd[15]: rings
     ext = tl.ext + tile * int64_t(tl.ext_stride);
     const int32_t* __restrict__ lsl = tl.lsl + tile * int64_t(tl.lsl_stride);
@@ -1256,16 +1266,28 @@ struct StepTile {
         if (k < w) {
           q[j][k] = tl.lcol[base + 64 * k];
           cl[j][k] = tl.llw[base + 64 * k];
-          if (DEC) cm[j][k] = tl.lmw[base + 64 * k];
+          if constexpr (DEC && LM) {
+            if (i < nNL) cml[i * KP + k] = tl.lmw[base + 64 * k];
+          } else if constexpr (DEC) {
+            cm[j][k] = tl.lmw[base + 64 * k];
+          }
           if constexpr (CL) cli[j][k] = tl.llwi[base + 64 * k];
         } else {
           q[j][k] = i < n1 ? i : 0;
           cl[j][k] = T(0);
-          if (DEC) cm[j][k] = T(0);
+          if constexpr (DEC && !LM) cm[j][k] = T(0);
           if constexpr (CL) cli[j][k] = T(0);
         }
       }
     }
+  }
+
+  // M weight k of register slot j (an owned slot when LM)
+  __device__ T mw(int j, int k) const {
+    if constexpr (LM)
+      return cml[(int(threadIdx.x) + j * int(blockDim.x)) * KP + k];
+    else
+      return cm[j][k];
   }
 
   // Tells the compiler the neighbour slots may change here, so that a loop
@@ -1313,7 +1335,7 @@ struct StepTile {
 #pragma unroll
     for (int k = 0; k < N; ++k) sq[k] = S[nb(j, k)];
 #pragma unroll
-    for (int k = 0; k < N; ++k) th += cm[j][k] * sq[k];
+    for (int k = 0; k < N; ++k) th += mw(j, k) * sq[k];
     return th;
   }
   template <int N>
@@ -1334,8 +1356,8 @@ struct StepTile {
     for (int k = 0; k < N; ++k) sq[k] = SM[nb(j, k)];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      th += cm[j][k] * sq[k].x;
-      mm += cm[j][k] * sq[k].y;
+      th += mw(j, k) * sq[k].x;
+      mm += mw(j, k) * sq[k].y;
     }
   }
   template <int N>
@@ -2114,57 +2136,73 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_kerr_tile(DevOps<T
 }
 
 // One z step of every field of a batch on one-field step tiles.  The device
-// layout is field-major (field f of row r at f * n_rows + r).  The workgroup
-// of a tile loads the operator rows into registers once and steps the nf
-// fields one after another; the next field's state is fetched into registers
-// while the current one runs its later stages (P is last read by stage 1)
-// and moved into P after it.
-template <typename T, int KMAX, bool DEC, int J, int LS>
+// layout is field-major (field f of row r at f * n_rows + r).  The work is
+// the n_tiles * nf (tile, field) pairs in tile-major order, cut into n_wg
+// contiguous runs of equal length, one per workgroup, so that every
+// workgroup does the same number of field steps whatever the tile count.
+// Along its run a workgroup loads a tile's operator rows into registers once
+// and steps that tile's fields one after another; the next field's state is
+// fetched into registers while the current one runs its later stages (P is
+// last read by stage 1) and moved into P after it.  LM: the M weights are
+// kept in LDS after S (the per-field state leaves them no room in registers).
+template <typename T, int KMAX, bool DEC, int J, int LS, bool LM>
 __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_fields(DevOps<T> d, TileOps<T> tl,
                                                                           const typename CT<T>::C* __restrict__ in,
                                                                           typename CT<T>::C* __restrict__ out, T h,
-                                                                          T tau, T gamma, int32_t nf) {
+                                                                          T tau, T gamma, int32_t nf, int32_t n_wg) {
   using C = typename CT<T>::C;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int64_t tile = logical_block(d.xcd_remap);
-  if (tile >= tl.n_tiles) return;
+  const int64_t wg = logical_block(d.xcd_remap);
+  if (wg >= n_wg) return;
   const int MS = tl.max_slots;
   const int B = blockDim.x;
   C* base = reinterpret_cast<C*>(smem);
   const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS};
   T* S = reinterpret_cast<T*>(base + 3 * MS);
-  StepTile<T, KMAX, DEC, J> st;
-  st.init(d, tl, tile);
-  int32_t pr[LS];
+  const int64_t units = int64_t(tl.n_tiles) * nf;
+  int64_t u = wg * units / n_wg;
+  const int64_t u_end = (wg + 1) * units / n_wg;
+  while (u < u_end) {
+    const int64_t tile = u / nf;
+    const int32_t f0 = int32_t(u - tile * nf);
+    const int32_t f1 = int32_t(f0 + (u_end - u < nf - f0 ? u_end - u : nf - f0));
+    StepTile<T, KMAX, DEC, J, false, LM> st;
+    st.init(d, tl, tile, false, S + MS);
+    int32_t pr[LS];
 #pragma unroll
-  for (int l = 0; l < LS; ++l) {
-    const int i = threadIdx.x + l * B;
-    pr[l] = i < st.nLoad ? st.slot_row(i) : -1;
-  }
-#pragma unroll
-  for (int l = 0; l < LS; ++l)
-    if (pr[l] >= 0) P.put(threadIdx.x + l * B, in[pr[l]]);
-  __syncthreads();
-  for (int32_t f = 0; f < nf; ++f) {
-    st.opaque_neighbours();
-    const int64_t off = int64_t(f) * d.n_rows;
-    const bool more = f + 1 < nf;
-    C pv[LS];
-    st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out[off + r] = v; },
-            [](int, int32_t, const C&) {},
-            [&]() {
-              if (more) {
-#pragma unroll
-                for (int l = 0; l < LS; ++l)
-                  if (pr[l] >= 0) pv[l] = in[off + d.n_rows + pr[l]];
-              }
-            });
-    if (more) {
-#pragma unroll
-      for (int l = 0; l < LS; ++l)
-        if (pr[l] >= 0) P.put(threadIdx.x + l * B, pv[l]);
+    for (int l = 0; l < LS; ++l) {
+      const int i = threadIdx.x + l * B;
+      pr[l] = i < st.nLoad ? st.slot_row(i) : -1;
     }
+    const int64_t off0 = int64_t(f0) * d.n_rows;
+#pragma unroll
+    for (int l = 0; l < LS; ++l)
+      if (pr[l] >= 0) P.put(threadIdx.x + l * B, in[off0 + pr[l]]);
     __syncthreads();
+    for (int32_t f = f0; f < f1; ++f) {
+      st.opaque_neighbours();
+      const int64_t off = int64_t(f) * d.n_rows;
+      const bool more = f + 1 < f1;
+      C pv[LS];
+      st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out[off + r] = v; },
+              [](int, int32_t, const C&) {},
+              [&]() {
+                if (more) {
+#pragma unroll
+                  for (int l = 0; l < LS; ++l)
+                    if (pr[l] >= 0) pv[l] = in[off + d.n_rows + pr[l]];
+                }
+              });
+      if (more) {
+#pragma unroll
+        for (int l = 0; l < LS; ++l)
+          if (pr[l] >= 0) P.put(threadIdx.x + l * B, pv[l]);
+      }
+      // P is complete for the next field, or every read of this tile's LDS
+      // is done before the next tile's load overwrites it
+      __syncthreads();
+    }
+    u += f1 - f0;
   }
 }
 
@@ -4076,27 +4114,58 @@ void launch_bperm(const DevOps<T>& d, const int64_t* cbase, const int32_t* fcoun
                        DECBPM_C(T, src), DECBPM_M(T, dst), int(field_major));
 }
 
+// Workgroups of `kernel` resident on the whole device at once (compute units
+// times the blocks one unit holds), at least one.
+template <typename K>
+int resident_workgroups(K kernel, int block, size_t shmem) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    ncu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, shmem) != hipSuccess) per = 1;
+  return (ncu > 0 ? ncu : 1) * (per > 0 ? per : 1);
+}
+
 template <typename T>
 void launch_step_fields(const DevOps<T>& d, const TileOps<T>& tl, const void* in, void* out, double h, double tau,
                         double gamma, int block, hipStream_t st) {
-  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
-  const size_t shmem = size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
+  const size_t shmem0 = size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
   const int J = (tl.max_compute + block - 1) / block;
   const int LS = (tl.max_slots + block - 1) / block;
   const int32_t nf = d.F;
-  // the operator rows take J slots per thread; the state LS (at most three slots of every ring)
-#define DECBPM_SF(KM, DEC, JJ, LL)                                                                                    \
-  hipLaunchKernelGGL((k_step_fields<T, KM, DEC, JJ, LL>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in),   \
-                     DECBPM_M(T, out), T(h), T(tau), T(gamma), nf)
+  const int64_t units = int64_t(tl.n_tiles) * nf;
+  int dev = 0, lds_cap = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    lds_cap = 0;
+  // the M weights go to LDS (TS x (KMAX | 1) after S) where they fit
+  auto lm_bytes = [&](int km) { return size_t(km | 1) * size_t(tl.TS) * sizeof(T); };
+  // the operator rows take J slots per thread; the state LS (at most three slots of every ring).
+  // One wave of workgroups, each given the same number of (tile, field) steps.
+#define DECBPM_SF(KM, DEC, JJ, LL)                                                                                \
+  do {                                                                                                            \
+    const bool lm = DEC && shmem0 + lm_bytes(KM) <= size_t(lds_cap);                                              \
+    auto* kern = lm ? &k_step_fields<T, KM, DEC, JJ, LL, true> : &k_step_fields<T, KM, DEC, JJ, LL, false>;       \
+    const size_t shmem = shmem0 + (lm ? lm_bytes(KM) : 0);                                                        \
+    const int64_t res = resident_workgroups(kern, block, shmem);                                                  \
+    const int32_t n_wg = int32_t(units < res ? units : res);                                                      \
+    const unsigned g = grid_for(int64_t(n_wg) * block, block, d.xcd_remap);                                       \
+    hipLaunchKernelGGL(kern, dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in), DECBPM_M(T, out), T(h),     \
+                       T(tau), T(gamma), nf, n_wg);                                                               \
+  } while (0)
 #define DECBPM_SF_J(KM, DEC)                                                           \
   if (J <= 1) {                                                                        \
     if (LS <= 2) DECBPM_SF(KM, DEC, 1, 2); else DECBPM_SF(KM, DEC, 1, 3);                \
   } else {                                                                             \
     if (LS <= 2) DECBPM_SF(KM, DEC, 2, 2); else DECBPM_SF(KM, DEC, 2, 3);                \
   }
+  // rows of up to 10 entries (most meshes of degree 9 or 10) get their own
+  // unroll: two fewer registers per slot and table than the 12-wide form
   const bool dec = tl.lmw != nullptr;
   if (kmax_of(d.wmax) == 8) {
     if (dec) { DECBPM_SF_J(8, true) } else { DECBPM_SF_J(8, false) }
+  } else if (d.wmax <= 10) {
+    if (dec) { DECBPM_SF_J(10, true) } else { DECBPM_SF_J(10, false) }
   } else {
     if (dec) { DECBPM_SF_J(12, true) } else { DECBPM_SF_J(12, false) }
   }
