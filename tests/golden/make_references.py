@@ -6,6 +6,10 @@ workload per process, e.g.::
 
     OMP_NUM_THREADS=1 python tests/golden/make_references.py step_index
 
+The stored vortex reference was made with ``vortex_beta4 --stop-after-crossing
+--max-seconds 18000`` (the march ends at the first probe past the complex64
+limit, step 4900 of 10000, after about 8000 s on one core).
+
 What each run stores (``tests/golden/ref_<name>.npz`` plus a text summary):
 
 * The oracle's field along z, marched by its own Strang step, and beside it
@@ -100,9 +104,12 @@ def _march(conn, psi0, ops, dz, n_steps, gamma, probe, amp, seed):
     conn.close()
 
 
-def conditioning_run(name, ops, u0, dz, n_steps, gamma, probe, log, probes, max_seconds=None):
+def conditioning_run(name, ops, u0, dz, n_steps, gamma, probe, log, probes, max_seconds=None,
+                     stop_after_crossing=False):
     """March the launch and its perturbed copies; return the probe history and
-    the snapshots at the largest well-posed steps of each precision."""
+    the snapshots at the largest well-posed steps of each precision.  The march
+    ends at n_steps, after max_seconds, or (stop_after_crossing) at the first
+    probe where every probed precision is past its limit."""
     ctx = mp.get_context("fork")
     pipes, procs = {}, []
     for k in probes:
@@ -143,6 +150,8 @@ def conditioning_run(name, ops, u0, dz, n_steps, gamma, probe, log, probes, max_
         log(f"{name}: step {step:6d} z={step * dz:.4f} kappa={kappa:.3e} delta64={d64:.3e} delta128={d128:.3e} "
             f"power={power:.6f} ({el:.0f} s)")
         stop = max_seconds is not None and el > max_seconds
+        if stop_after_crossing and all(crossed[t] for t in wanted if wanted[t]):
+            stop = True
         for k in probes:
             pipes[k].send("stop" if stop else "go")
         if stop:
@@ -171,12 +180,13 @@ def _store(name, arrays, log):
     log(f"wrote {os.path.relpath(path, ROOT)} ({os.path.getsize(path) / 1e6:.1f} MB)")
 
 
-def _one(name, w, u0, probe, log, probes=("input", "noise64", "noise128"), max_seconds=None):
+def _one(name, w, u0, probe, log, probes=("input", "noise64", "noise128"), max_seconds=None,
+         stop_after_crossing=False):
     ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, chi_tri=w.chi_tri, p1=w.p1, beta4=w.beta4)
     log(f"{name}: N={w.mesh.n_vert} dz={w.dz} steps={w.n_steps} gamma={w.gamma} beta4={w.beta4} "
         f"power0={float(np.sum(ops.H0 * np.abs(u0) ** 2)):.6f} probe every {probe}")
     hist, snap, crossed = conditioning_run(name, ops, u0, w.dz, w.n_steps, w.gamma, probe, log, probes,
-                                           max_seconds=max_seconds)
+                                           max_seconds=max_seconds, stop_after_crossing=stop_after_crossing)
     out = {
         "probe_steps": hist[:, 0].astype(np.int64),
         "kappa": hist[:, 1],
@@ -209,17 +219,19 @@ def main():
     ap.add_argument("name", choices=["step_index", "vortex_beta4", "batched_pcf", "adjoint_replica"])
     ap.add_argument("--mesh", type=int, default=None, help="batched_pcf: one mesh index (0-7)")
     ap.add_argument("--max-seconds", type=float, default=None)
+    ap.add_argument("--stop-after-crossing", action="store_true",
+                    help="end the march once every probed precision is past its limit")
     a = ap.parse_args()
     if a.name == "step_index":
         log, f = _writer("step_index")
         w = W.step_index()
         _store("step_index", _one("step_index", w, w.u0, 250, log), log)
     elif a.name == "vortex_beta4":
-        # complex64 only (the workload's precision); the march stops at --max-seconds
+        # complex64 only (the workload's precision)
         log, f = _writer("vortex_beta4")
         w = W.vortex_beta4()
         _store("vortex_beta4", _one("vortex_beta4", w, w.u0, 100, log, probes=("input", "noise64"),
-                                    max_seconds=a.max_seconds), log)
+                                    max_seconds=a.max_seconds, stop_after_crossing=a.stop_after_crossing), log)
     elif a.name == "batched_pcf":
         ws = W.batched_pcf()
         idx = range(len(ws)) if a.mesh is None else [a.mesh]
