@@ -64,7 +64,7 @@ COPY_BYTES = 256 << 20
 _DOMINANT = {0: ("stage", "k_stage (RK4 stage: L gather + stage update)", 4),
              1: ("tile_a", "k_fused (stage 4 + Kerr/absorber + next stage 1 on 3-ring LDS tiles)", 1),
              2: ("step", "k_step (whole z step: 4 RK4 stages + Kerr/absorber on 5-ring LDS tiles)", 1),
-             3: ("persist", "k_persist (persistent cooperative z stepping on resident 5-ring LDS tiles, "
+             3: ("persist", "k_persist (persistent z stepping on resident 5-ring LDS tiles, "
                             "operator rows in registers; time and algorithmic bytes per z step)", 1)}
 
 

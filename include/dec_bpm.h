@@ -407,15 +407,21 @@ int dec_bpm_batch_check_finite(dec_bpm_batch_t b, void* stream);
  * runs the whole z step (four stages + Kerr/absorber) as one kernel on tiles
  * with five halo rings (four for the lumped nonlinearity; with the beta4 term
  * two rings per stage: nine, or eight); fused = 3 (without the beta4 term)
- * runs all middle steps of a propagate in one persistent cooperative launch on
- * those tiles, every tile resident with its operator rows in registers, tiles
- * synchronising with their neighbour tiles only (available when all tiles fit
- * on the device at once; otherwise, and with the beta4 term, fused = 3 runs
- * as fused = 2).  A handle that has no tiles for the requested mode runs the
- * unfused kernels.  A persistent neighbour wait that exceeds its bound
- * (DEC_BPM_SPIN_LIMIT polls, default 2^20) leaves the launch early and makes
- * the next
- * dec_bpm_check_finite report DEC_BPM_ENONFINITE.
+ * runs a whole propagate in one persistent launch on those tiles, every tile
+ * resident with its operator rows in registers, tiles synchronising with their
+ * neighbour tiles only (available when all tiles fit on the device at once;
+ * otherwise, and with the beta4 term, fused = 3 runs as fused = 2).  The
+ * persistent launch is an ordinary one (about 12 us less per call than a
+ * cooperative launch): its workgroups are all resident once earlier work on
+ * the device has drained, and persistent launches of this process on
+ * different streams are ordered one after another.  Work that keeps compute
+ * units busy for longer than the wait bound (another process's persistent
+ * kernel, say) can make it give up; DEC_BPM_COOPERATIVE=1 in the environment
+ * at handle creation selects the cooperative launch, whose residency the
+ * runtime guarantees.  A handle that has no tiles for the requested mode runs
+ * the unfused kernels.  A persistent neighbour wait that exceeds its bound
+ * (DEC_BPM_SPIN_LIMIT polls, default 2^20, of the order of a second) leaves the launch
+ * early and makes the next dec_bpm_check_finite report DEC_BPM_ENONFINITE.
  */
 typedef struct {
   int32_t block_size;       /* threads per workgroup of the unfused kernels      */

@@ -146,6 +146,9 @@ struct Engine {
   DevTiles pst;
   bool pst_own = false;
   int spin_limit = 1 << 20;
+  // persistent step launches: cooperative (the runtime guarantees residency,
+  // about 12 us more per launch) or ordinary (ordered across streams, below)
+  bool coop = false;
   int persist_cap_block = -1, persist_cap = 0;  // resident workgroups at that block size
   int persist_cap_block_u = -1, persist_cap_u = 0;  // the same for the unsplit RK4 body
   int mode_cap_block = -1, mode_cap = 0;            // and for the persistent mode iteration
@@ -317,6 +320,7 @@ static void env_defaults(Engine& E) {
   if (const char* s = std::getenv("DEC_BPM_BLOCK")) E.block = std::max(64, std::min(1024, std::atoi(s)));
   if (const char* s = std::getenv("DEC_BPM_STEPS_PER_GRAPH")) E.spg = std::max(1, std::atoi(s));
   if (const char* s = std::getenv("DEC_BPM_XCD_REMAP")) E.xcd = std::atoi(s) ? 1 : 0;
+  if (const char* s = std::getenv("DEC_BPM_COOPERATIVE")) E.coop = std::atoi(s) != 0;
 }
 
 template <typename T>
@@ -685,6 +689,28 @@ static void build_batch_tiles(Engine& E, const std::vector<int64_t>& arp, const 
 }
 
 // Build the device engine from one or more assembled meshes (concatenated).
+// Ordinary launches of the persistent step are ordered across the process's
+// streams: a launch on a stream other than the device's previous one first
+// waits for that launch (two partly resident grids could otherwise wait on
+// each other until their bounded waits give up).  On one stream the order is
+// the stream's own.  The event is created with the handle, so that launching
+// allocates nothing.
+struct PersistOrder {
+  std::mutex mu;
+  hipEvent_t ev = nullptr;
+  hipStream_t last = nullptr;
+  bool has = false;
+};
+static PersistOrder g_porder[64];
+
+static void persist_order_init() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lock(g_porder[dev].mu);
+  if (!g_porder[dev].ev) HIP_OK(hipEventCreateWithFlags(&g_porder[dev].ev, hipEventDisableTiming));
+}
+
 template <typename T>
 static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshes, const std::vector<int>& lumped) {
   int64_t n = 0;
@@ -852,6 +878,7 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   E.flag = static_cast<int*>(E.dalloc(sizeof(int)));
   HIP_OK(hipMemset(E.flag, 0, sizeof(int)));
   HIP_OK(hipStreamCreateWithFlags(&E.cap, hipStreamNonBlocking));
+  persist_order_init();
   E.on_device = true;
 }
 
@@ -1106,6 +1133,29 @@ static void check_prop_args(const Engine& E, const void* field, double dz, int64
   if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
 }
 
+template <typename T>
+static hipError_t run_persist(Engine& E, const TileOps<T>& tl, void* b0, void* b1, int32_t* flags, int32_t n,
+                              double dz, double gamma, hipStream_t st, int body, const PersistIO& io) {
+  const DevOps<T> d = E.ops<T>();
+  int dev = 0;
+  if (!E.coop && hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64 && g_porder[dev].ev) {
+    PersistOrder& o = g_porder[dev];
+    std::lock_guard<std::mutex> lock(o.mu);
+    if (o.has && o.last != st) {
+      const hipError_t w = hipStreamWaitEvent(st, o.ev, 0);
+      if (w != hipSuccess) return w;
+    }
+    const hipError_t e = launch_persist<T>(d, tl, E.nb_ptr, E.nb_list, b0, b1, flags, E.flag, n, E.spin_limit, dz,
+                                           gamma, E.pblock(), st, body, io, false);
+    if (e != hipSuccess) return e;
+    o.last = st;
+    o.has = true;
+    return hipEventRecord(o.ev, st);
+  }
+  return launch_persist<T>(d, tl, E.nb_ptr, E.nb_list, b0, b1, flags, E.flag, n, E.spin_limit, dz, gamma, E.pblock(),
+                           st, body, io, true);
+}
+
 // Flag base of a persistent launch of n steps (it publishes at most
 // base + n + 1).  The flags are cleared only when the count would pass 2^30
 // or another kernel has used them.
@@ -1134,8 +1184,8 @@ static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipSt
       const int32_t k = int32_t(std::min(chunk, count - done));
       void* b0 = state_before(E, 5, done);
       void* b1 = b0 == E.psi ? E.psi2 : E.psi;
-      hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, E.pflags, E.flag,
-                                       k, E.spin_limit, dz, gamma, E.pblock(), st, 1, persist_io(E, k, st));
+      hipError_t e = run_persist<T>(E, E.ptiles().template ops<T>(), b0, b1, E.pflags, k, dz, gamma, st, 1,
+                                    persist_io(E, k, st));
       if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     }
     return state_before(E, 5, count);
@@ -1146,8 +1196,8 @@ static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipSt
       const int32_t k = int32_t(std::min(chunk, count - done));
       void* b0 = state_before(E, 3, done);
       void* b1 = b0 == E.psi ? E.psi2 : E.psi;
-      hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, E.pflags, E.flag,
-                                       k, E.spin_limit, dz, gamma, E.pblock(), st, 0, persist_io(E, k, st));
+      hipError_t e = run_persist<T>(E, E.ptiles().template ops<T>(), b0, b1, E.pflags, k, dz, gamma, st, 0,
+                                    persist_io(E, k, st));
       if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     }
     return state_before(E, 3, count);
@@ -1214,9 +1264,8 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     io.out = field;
     io.perm = E.perm;
     io.tau_first = io.tau_last = 0.5 * dz;
-    const hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, E.psi, E.psi2,
-                                           E.pflags, E.flag, int32_t(n), E.spin_limit, dz, gamma, E.pblock(), st, 0,
-                                           io);
+    const hipError_t e =
+        run_persist<T>(E, E.ptiles().template ops<T>(), E.psi, E.psi2, E.pflags, int32_t(n), dz, gamma, st, 0, io);
     if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
   } else if (io_tiles) {
     // NL(dz/2) of the caller's field into psi (on the step tiles: the same
@@ -1309,8 +1358,8 @@ static void propagate_noalloc_t(Engine& E, void* field, double dz, int64_t n, do
     io.out = field;
     io.perm = E.perm;
     io.tau_first = io.tau_last = 0.5 * dz;
-    const hipError_t e = launch_persist<T>(d, E.ptiles().template ops<T>(), E.nb_ptr, E.nb_list, b0, b1, flags,
-                                           E.flag, int32_t(n), E.spin_limit, dz, gamma, E.pblock(), st, 0, io);
+    const hipError_t e =
+        run_persist<T>(E, E.ptiles().template ops<T>(), b0, b1, flags, int32_t(n), dz, gamma, st, 0, io);
     if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
   } else {
     const TileOps<T> ts = E.stp.template ops<T>();
@@ -1922,12 +1971,10 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
         }
         return r;
       };
-      HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, 2, E.spin_limit, dz, gamma,
-                               E.pblock(), st, body, io(2)));  // warm-up
+      HIP_OK(run_persist<T>(E, sp, E.psi, E.psi2, E.pflags, 2, dz, gamma, st, body, io(2)));  // warm-up
       const PersistIO timed = io(steps);
       HIP_OK(hipEventRecord(e0, st));
-      HIP_OK(launch_persist<T>(d, sp, E.nb_ptr, E.nb_list, E.psi, E.psi2, E.pflags, E.flag, steps, E.spin_limit, dz,
-                               gamma, E.pblock(), st, body, timed));
+      HIP_OK(run_persist<T>(E, sp, E.psi, E.psi2, E.pflags, steps, dz, gamma, st, body, timed));
       HIP_OK(hipEventRecord(e1, st));
       HIP_OK(hipEventSynchronize(e1));
       float t = 0;

@@ -1216,9 +1216,11 @@ struct StepTile {
 
   // kerr_only: load the rows the NL substep alone needs (rings 0..1, the
   // reach of the M gather), not every compute slot's
-  // m_lds (LM): where the M weight table goes; it is read after the caller's next barrier
+  // m_lds (LM): where the M weight table goes; it is read after the caller's next barrier.
+  // m_owned: only the owned slots get M weights and M_pp (the split step's Kerr
+  // substep runs on them alone; the unsplit kernels gather M on the halo too)
   __device__ void init(const DevOps<T>& d, const TileOps<T>& tl, int64_t tile, bool kerr_only = false,
-                       T* m_lds = nullptr) {
+                       T* m_lds = nullptr, bool m_owned = false) {
     cml = m_lds;
     hd = tl.hdr + int64_t(tl.hdr_stride) * tile;  // hd[k]: slots in rings 0..k; hd[15]: rings
     ext = tl.ext + tile * int64_t(tl.ext_stride);
@@ -1254,7 +1256,7 @@ struct StepTile {
         rr[j] = r;
         vv[j] = d.v[r];
         ww[j] = d.w[r];
-        md[j] = d.mdiag[r];
+        if (!m_owned || i < nNL) md[j] = d.mdiag[r];
         const int32_t info = lsl[i >> 6];
         w = info & 0xff;
         base = ebase + (info >> 8) + (i & 63);
@@ -1269,7 +1271,7 @@ struct StepTile {
           if constexpr (DEC && LM) {
             if (i < nNL) cml[i * KP + k] = tl.lmw[base + 64 * k];
           } else if constexpr (DEC) {
-            cm[j][k] = tl.lmw[base + 64 * k];
+            cm[j][k] = (!m_owned || i < nNL) ? tl.lmw[base + 64 * k] : T(0);
           }
           if constexpr (CL) cli[j][k] = tl.llwi[base + 64 * k];
         } else {
@@ -2109,7 +2111,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step(DevOps<T> d, 
   const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS};
   T* S = reinterpret_cast<T*>(base + 3 * MS);
   StepTile<T, KMAX, DEC, J, CL> st;
-  st.init(d, tl, tile);
+  st.init(d, tl, tile, false, nullptr, true);
   for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P.put(i, in_psi[st.slot_row(i)]);
   __syncthreads();
   st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { put_result(out_psi, out_perm, flag, r, v); },
@@ -2167,7 +2169,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_fields(DevOps
     const int32_t f0 = int32_t(u - tile * nf);
     const int32_t f1 = int32_t(f0 + (u_end - u < nf - f0 ? u_end - u : nf - f0));
     StepTile<T, KMAX, DEC, J, false, LM> st;
-    st.init(d, tl, tile, false, S + MS);
+    st.init(d, tl, tile, false, S + MS, true);
     int32_t pr[LS];
 #pragma unroll
     for (int l = 0; l < LS; ++l) {
@@ -2829,7 +2831,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_b4(DevOps<T> 
   const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS}, Tb{base + 3 * MS};
   T* S = reinterpret_cast<T*>(base + 4 * MS);
   StepTile<T, KMAX, DEC, J> st;
-  st.init(d, tl, tile);
+  st.init(d, tl, tile, false, nullptr, true);
   for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P.put(i, in_psi[st.slot_row(i)]);
   __syncthreads();
   st.step_b4(d, P, X, Y, Tb, S, h, tau, gamma,
@@ -2855,7 +2857,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_rec(DevOps<T>
   const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS};
   T* S = reinterpret_cast<T*>(base + 3 * MS);
   StepTile<T, KMAX, DEC, J> st;
-  st.init(d, tl, tile);
+  st.init(d, tl, tile, false, nullptr, true);
   for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P.put(i, in_psi[st.slot_row(i)]);
   __syncthreads();
   st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out_psi[r] = v; },
@@ -3097,7 +3099,7 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
   T* USA = reinterpret_cast<T*>(base + 2 * MS);
   T* USB = USA + MS;
   StepTile<T, KMAX, DEC, J, CL> st;
-  st.init(d, tl, tile);
+  st.init(d, tl, tile, false, nullptr, BODY == 0);
   int32_t pr[LS];  // rows of this thread's state slots
 #pragma unroll
   for (int l = 0; l < LS; ++l) {
@@ -4069,7 +4071,7 @@ template <typename T>
 hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_t* nb_ptr, const int32_t* nb_list,
                           void* buf0, void* buf1, int32_t* flags, int32_t* status, int32_t n_steps,
                           int32_t spin_limit, double h, double gamma, int block, hipStream_t st, int body,
-                          const PersistIO& io) {
+                          const PersistIO& io, bool coop) {
   using C = typename CT<T>::C;
   const void* k = persist_kernel<T>(d, tl, block, body);
   if (!k) return hipErrorInvalidDeviceFunction;
@@ -4083,7 +4085,8 @@ hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_
                     T(io.tau_last)};
   void* args[] = {&dd, &tt, const_cast<int32_t**>(&nb_ptr), const_cast<int32_t**>(&nb_list), &b0, &b1, &flags, &status,
                   &n_steps, &spin_limit, &th, &tg, &pa};
-  return hipLaunchCooperativeKernel(k, dim3(g), dim3(block), args, unsigned(persist_lds<T>(tl)), st);
+  if (coop) return hipLaunchCooperativeKernel(k, dim3(g), dim3(block), args, unsigned(persist_lds<T>(tl)), st);
+  return hipLaunchKernel(k, dim3(g), dim3(block), args, size_t(persist_lds<T>(tl)), st);
 }
 
 template <typename T>
@@ -4351,7 +4354,7 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                    double, double, int, hipStream_t);                                            \
   template hipError_t launch_persist<T>(const DevOps<T>&, const TileOps<T>&, const int32_t*, const int32_t*, void*, \
                                         void*, int32_t*, int32_t*, int32_t, int32_t, double, double, int,        \
-                                        hipStream_t, int, const PersistIO&);                                     \
+                                        hipStream_t, int, const PersistIO&, bool);                                     \
   template void launch_bstage<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*, void*, \
                                  double, void*, double, hipStream_t);                                            \
   template void launch_blap<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, hipStream_t);           \

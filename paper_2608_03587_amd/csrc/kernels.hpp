@@ -326,22 +326,25 @@ struct PersistIO {
   double tau_first = 0.0, tau_last = 0.0;
 };
 
-// Persistent z stepping (n_steps steps in one cooperative launch, one
-// resident workgroup per tile of the five-ring step tiles).  nb_ptr/nb_list:
-// per tile, the other tiles owning its halo rows.  flags: n_tiles ints that
-// only grow (see PersistIO::base).  status: bit 1 is set if a neighbour wait
-// timed out.  Returns the launch status (the launch fails if the tiles cannot
-// all be resident).  persist_capacity: resident workgroups the device holds
-// for this kernel at `block` threads (0 if the tiles do not fit the kernel).
-// body: 0 the merged split step (LIN(h) then NL(h)), 1 one unsplit RK4 step
-// of the whole right-hand side.
+// Persistent z stepping (n_steps steps in one launch, one resident
+// workgroup per tile of the five-ring step tiles).  nb_ptr/nb_list: per tile,
+// the other tiles owning its halo rows.  flags: n_tiles ints that only grow
+// (see PersistIO::base).  status: bit 1 is set if a neighbour wait timed out.
+// coop: a cooperative launch (the runtime guarantees that every workgroup is
+// resident at once, and fails the launch otherwise); else an ordinary launch
+// of a grid that persist_capacity says fits, whose workgroups all become
+// resident once earlier work on the device has drained (the bounded waits
+// cover the time until then).  persist_capacity: resident workgroups the
+// device holds for this kernel at `block` threads (0 if the tiles do not fit
+// the kernel).  body: 0 the merged split step (LIN(h) then NL(h)), 1 one
+// unsplit RK4 step of the whole right-hand side.
 template <typename T>
 int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block, int body = 0);
 template <typename T>
 hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_t* nb_ptr, const int32_t* nb_list,
                           void* buf0, void* buf1, int32_t* flags, int32_t* status, int32_t n_steps,
                           int32_t spin_limit, double h, double gamma, int block, hipStream_t st, int body,
-                          const PersistIO& io);
+                          const PersistIO& io, bool coop = true);
 // n ints set to 0
 void launch_zero_i32(int64_t n, int32_t* x, hipStream_t st);
 

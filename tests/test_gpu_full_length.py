@@ -169,7 +169,7 @@ def test_step_index_full_length(dtype):
 
 def test_persistent_launch_bitwise_over_the_full_length():
     """The persistent launch (all 5000 steps, the prologue and the last half step in one
-    cooperative launch) gives the one-kernel-per-step path's bits on the full mesh."""
+    launch) gives the one-kernel-per-step path's bits on the full mesh."""
     w = workload("step_index")
     m = lib_mesh(w, "c64")
     outs = {}

@@ -991,7 +991,7 @@ def test_one_kernel_step_matches_unfused_and_oracle(dtype, nl):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("nl", ["dec", "lumped"])
 def test_persistent_launch_matches_step_kernel_and_oracle(dtype, nl):
-    """All middle steps in one persistent cooperative launch (operator rows in
+    """All middle steps in one persistent launch (operator rows in
     registers, neighbour-tile flags instead of kernel boundaries) against the
     one-kernel step (same arithmetic: bitwise) and the oracle."""
     w = case("step_index", n_vert=20000, n_steps=10)
@@ -1025,6 +1025,45 @@ def test_persistent_launch_matches_step_kernel_and_oracle(dtype, nl):
         g = u.clone()
         m.propagate(g, w.dz, 37, w.gamma)
         assert np.array_equal(host(f), host(g)), (tb, x)
+
+
+@pytest.mark.gpu
+def test_persistent_launches_on_two_streams_and_cooperative(monkeypatch):
+    """The persistent step is an ordinary launch whose workgroups must all be
+    resident: launches of two handles on two streams, queued back to back with
+    no host synchronisation, are ordered by the library and give the bits of
+    the same launches on one stream; the cooperative launch
+    (DEC_BPM_COOPERATIVE=1) gives them too."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    u = dev(w.u0, "c64")
+    ms = [lib_mesh(w, "c64", "dec") for _ in range(2)]
+    for m in ms:
+        m.tuning = {"fused": 3}
+        assert m.time_kernels(w.dz, w.gamma, reps=20)["persist"]["ms"] > 0
+    ref = u.clone()
+    ms[0].propagate(ref, w.dz, 57, w.gamma)
+    ref = host(ref)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    fs = [u.clone(), u.clone()]
+    torch.cuda.synchronize()
+    for rep in range(6):  # 6 x 57 steps alternating between the streams, then compare
+        for i in (0, 1):
+            with torch.cuda.stream(streams[i]):
+                if rep:
+                    fs[i].copy_(u)
+                ms[i].propagate(fs[i], w.dz, 57, w.gamma, stream=streams[i])
+    torch.cuda.synchronize()
+    for m, f in zip(ms, fs):
+        m.check_finite()
+        assert np.array_equal(host(f), ref)
+    monkeypatch.setenv("DEC_BPM_COOPERATIVE", "1")
+    mc = lib_mesh(w, "c64", "dec")
+    monkeypatch.delenv("DEC_BPM_COOPERATIVE")
+    mc.tuning = {"fused": 3}
+    g = u.clone()
+    mc.propagate(g, w.dz, 57, w.gamma)
+    mc.check_finite()
+    assert np.array_equal(host(g), ref)
 
 
 @pytest.mark.gpu
