@@ -104,11 +104,15 @@ typedef struct {
    * DEC_BPM_N_SATURABLE: I / (1 + I / nl_param), nl_param = I_s > 0;
    * DEC_BPM_N_CUBIC_QUINTIC: I - nl_param I^2, nl_param >= 0).  The Kerr
    * substep stays the exact flow: Theta = M (integral over the substep of
-   * N(|psi|^2 e^{-2 w z}), in closed form).  p3 or p4 non-zero, or a non-Kerr
-   * response, runs the five-kernel path (fused = 0; the L powers by Horner
-   * in extra gather launches); the checkpointed forward and adjoint, the tile
-   * paths, apply(H), batches, unsplit, adaptive and find_mode return EINVAL,
-   * and diagnostics report a NaN Hamiltonian. */
+   * N(|psi|^2 e^{-2 w z}), in closed form).  A non-Kerr response runs on
+   * every split-step launch mode (the tile kernels' Kerr phase takes the
+   * flow integral of the response).  p3 or p4 non-zero runs the five-kernel
+   * path (fused = 0; the L powers by Horner in extra gather launches: the
+   * tile halos cover at most two products per stage).  With either, the
+   * checkpointed forward and adjoint, apply(H), batches, unsplit, adaptive
+   * and find_mode return EINVAL (their kernels are written for the Kerr
+   * right-hand side and terms up to L^2), and diagnostics report a NaN
+   * Hamiltonian. */
   double p3, p4;
   int32_t nl_kind;
   double nl_param;
@@ -237,8 +241,8 @@ int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, doub
  * 12 MiB that each device holds until the process ends, and every kernel is
  * launched directly (no graph is instantiated).  No hipMalloc, hipFree or
  * allocating library routine is called.  Limits: one-field handles with the
- * step tiles (EINVAL for rows of more than 12 neighbours, L^3, L^4 or a
- * non-Kerr response), and 2 n_vert complex values of the handle's dtype at
+ * step tiles (EINVAL for rows of more than 12 neighbours, L^3 or L^4), and
+ * 2 n_vert complex values of the handle's dtype at
  * most 12 MiB - 64 KiB (about 786k vertices in complex64, 393k in
  * complex128; EINVAL beyond, with the sizes in the message).  Every call on a
  * device shares that device's array, which keeps the last call's contents:

@@ -239,8 +239,13 @@ struct Engine {
     return std::min(1024, std::max(tile_block, need));
   }
 
-  // terms beyond the kernels' fused forms (L^3, L^4, a non-Kerr response): five-kernel path only
+  // L^3, L^4 or a non-Kerr response: the entry points written for the Kerr
+  // right-hand side and terms up to L^2 refuse these handles
   bool general() const { return p3 != 0.0 || p4 != 0.0 || nk != DEC_BPM_N_KERR; }
+  // terms beyond L^2: the tile kernels' halos cover at most two products per
+  // stage, so these run the five-kernel path; a non-Kerr response alone does
+  // not (the tile kernels' Kerr phase takes the response's flow integral)
+  bool high_order() const { return p3 != 0.0 || p4 != 0.0; }
 
   size_t real_size() const { return dtype == DEC_BPM_C64 ? 4 : 8; }
   size_t cplx_size() const { return 2 * real_size(); }
@@ -851,8 +856,8 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
     upload(E, p, fcount);
     E.bfcount = static_cast<int32_t*>(p);
   }
-  if (E.F == 1 && E.beta4 == 0.0 && !pml && !E.general()) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
-  if (!E.general()) build_step_tiles<T>(E, arp, acol, alw, amw, any_dec, pml ? &alwi : nullptr);
+  if (E.F == 1 && E.beta4 == 0.0 && !pml && !E.high_order()) build_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  if (!E.high_order()) build_step_tiles<T>(E, arp, acol, alw, amw, any_dec, pml ? &alwi : nullptr);
   if (pml && !E.has_step)
     fail(DEC_BPM_EINVAL, "PML: the mesh needs the one-kernel step tiles (rows of at most 12 neighbours)");
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
@@ -890,7 +895,7 @@ static void build_engine(Engine& E, const std::vector<const Assembled*>& meshes,
     build_engine_t<double>(E, meshes, lumped);
   if (E.fused < 0) E.fused = (E.has_step || E.has_step4) ? 2 : ((E.has_tiles || E.has_btiles) ? 1 : 0);
   if (E.pml) E.fused = 2;
-  if (E.general()) E.fused = 0;
+  if (E.high_order()) E.fused = 0;
 }
 
 static void check_launch() {
@@ -1032,7 +1037,7 @@ template <typename T>
 static int mode_of(Engine& E) {
   if (E.F > 1 && E.fused == 3 && E.use_sfl()) return 6;  // batches: the field-loop step
   if (E.pml) return use_persist<T>(E) ? 3 : 2;   // complex L: the one-kernel step or the persistent launch
-  if (E.general()) return 0;                      // L^3, L^4 or a non-Kerr response: five kernels
+  if (E.high_order()) return 0;                   // L^3, L^4: five kernels
   if (E.has_step4) return E.fused >= 2 ? 4 : 0;  // beta4: its one-kernel step or the five kernels
   if (use_persist<T>(E)) return 3;
   if (E.fused == 3 && E.has_step) return 2;
@@ -1328,7 +1333,7 @@ static void check_noalloc(const Engine& E) {
   if (E.F != 1 || !(E.has_step || E.has_step4))
     fail(DEC_BPM_EINVAL,
          "dec_bpm_propagate_noalloc runs the one-field step tiles only (not for rows of more than 12 neighbours, "
-         "L^3, L^4 or a non-Kerr response)");
+         "L^3 or L^4)");
   const size_t need = 2 * round256(size_t(E.n_rows) * E.cplx_size());
   if (need > kScratchBytes - kScratchFlagBytes) {
     char buf[200];
@@ -2887,8 +2892,8 @@ static void set_tuning(Engine& E, const dec_bpm_tuning* t) {
     fail(DEC_BPM_EINVAL, "bad tuning");
   if (E.pml && t->fused != 2 && t->fused != 3)
     fail(DEC_BPM_EINVAL, "a PML handle runs the one-kernel step or the persistent launch only (fused = 2 or 3)");
-  if (E.general() && t->fused != 0)
-    fail(DEC_BPM_EINVAL, "L^3, L^4 or a non-Kerr response run the five-kernel path only (fused = 0)");
+  if (E.high_order() && t->fused != 0)
+    fail(DEC_BPM_EINVAL, "L^3 and L^4 terms run the five-kernel path only (fused = 0)");
   E.block = t->block_size;
   E.spg = t->steps_per_graph;
   E.fused = t->fused;

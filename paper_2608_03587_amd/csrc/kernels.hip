@@ -997,7 +997,7 @@ __global__ void __launch_bounds__(1024) k_fused(DevOps<T> d, TileOps<T> tl, cons
     if (i < nP) {
       const C p = in_psi[r];
       P[i] = p;
-      if (KIND == FUSED_NL_S1) S[i] = (p.x * p.x + p.y * p.y) * phi_w(d.w[r], tau);
+      if (KIND == FUSED_NL_S1) S[i] = nl_int(d, p.x * p.x + p.y * p.y, d.w[r], tau);
     }
   }
   // registers: the operator rows of this thread's compute slots (all phases use prefixes of [0, nA))
@@ -1089,7 +1089,7 @@ __global__ void __launch_bounds__(1024) k_fused(DevOps<T> d, TileOps<T> tl, cons
       if (i < nA) {
         const C o = stage(X, P, j, i, h);
         Y[i] = o;
-        S[i] = (o.x * o.x + o.y * o.y) * phi_w(ww[j], tau);
+        S[i] = nl_int(d, o.x * o.x + o.y * o.y, ww[j], tau);
         if (out_rec && i < c0) out_rec[rr[j]] = o;  // state before the Kerr substep (adjoint recompute)
       }
     }
@@ -1452,7 +1452,7 @@ struct StepTile {
       const int i = threadIdx.x + j * B;
       if (i < n4) {  // state before the Kerr substep
         cur[j] = stage(d, Y, cur[j], p[j], j, h);
-        so[j] = (cur[j].x * cur[j].x + cur[j].y * cur[j].y) * phi_w(ww[j], tau);
+        so[j] = nl_int(d, cur[j].x * cur[j].x + cur[j].y * cur[j].y, ww[j], tau);
         S[i] = so[j];
         if (i < nNL) rec(3, rr[j], cur[j]);
       }
@@ -1528,7 +1528,7 @@ struct StepTile {
       const int i = threadIdx.x + j * B;
       if (early(i, j, 5)) {  // state before the Kerr substep
         cur[j] = stage(d, Y, cur[j], p[j], j, h);
-        so[j] = (cur[j].x * cur[j].x + cur[j].y * cur[j].y) * phi_w(ww[j], tau);
+        so[j] = nl_int(d, cur[j].x * cur[j].x + cur[j].y * cur[j].y, ww[j], tau);
         S[i] = so[j];
       }
     }
@@ -1572,7 +1572,7 @@ struct StepTile {
       const int i = threadIdx.x + j * B;
       if (i < n4 && !early(i, j, 5)) {
         cur[j] = stage(d, Y, cur[j], p[j], j, h);
-        so[j] = (cur[j].x * cur[j].x + cur[j].y * cur[j].y) * phi_w(ww[j], tau);
+        so[j] = nl_int(d, cur[j].x * cur[j].x + cur[j].y * cur[j].y, ww[j], tau);
         S[i] = so[j];
       }
     }
@@ -1616,7 +1616,7 @@ struct StepTile {
       const int i = threadIdx.x + j * B;
       if (i < nS) {
         p[j] = src[perm ? perm[rr[j]] : rr[j]];
-        so[j] = (p[j].x * p[j].x + p[j].y * p[j].y) * phi_w(ww[j], tau);
+        so[j] = nl_int(d, p[j].x * p[j].x + p[j].y * p[j].y, ww[j], tau);
         S[i] = so[j];
       }
     }
@@ -1689,7 +1689,7 @@ struct StepTile {
           cur[j] = y;
           if (k < 3) Vout.put(i, y);
           else {
-            so[j] = (y.x * y.x + y.y * y.y) * phi_w(ww[j], tau);
+            so[j] = nl_int(d, y.x * y.x + y.y * y.y, ww[j], tau);
             S[i] = so[j];
           }
         }

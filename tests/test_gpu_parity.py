@@ -513,12 +513,12 @@ def test_pml_absorbs_on_the_gpu():
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("response,param,p3,p4", [("kerr", 0.0, -4e-3, 1e-3), ("saturable", 0.8, 0.0, 0.0),
+@pytest.mark.parametrize("response,param,p3,p4", [("kerr", 0.0, -4e-3, 1e-3), ("saturable", 0.8, 2e-3, 0.0),
                                                    ("cubic_quintic", 0.25, 2e-3, 0.0)])
 def test_general_operator_sum_and_responses_match_oracle(dtype, response, param, p3, p4):
-    """Eq. 1 in full on the five-kernel path: terms up to p4 L^4 (Horner gathers) and the
-    saturable and cubic-quintic Kerr responses (closed-form flow integrals), against the
-    oracle's split scheme on the step-index replica (89k vertices, with absorber), plus
+    """Eq. 1 in full on the five-kernel path: terms up to p4 L^4 (Horner gathers) with the
+    Kerr, saturable and cubic-quintic responses (closed-form flow integrals), against the
+    oracle's split scheme on the step-index replica (20k vertices, with absorber), plus
     the Kerr substep and the linear step alone."""
     w = case("step_index", n_vert=20000, n_steps=10)
     kw = dict(p3=p3, p4=p4, nl_kind=response, nl_param=param)
@@ -552,6 +552,46 @@ def test_general_operator_sum_and_responses_match_oracle(dtype, response, param,
     with pytest.raises(api.DecBpmError) as e:
         m.propagate_unsplit(u.clone(), dz, 1, w.gamma)
     assert e.value.code == B.EINVAL
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("response,param", [("saturable", 0.8), ("cubic_quintic", 0.25)])
+@pytest.mark.parametrize("beta4", [0.0, 2e-3])
+def test_responses_on_every_split_step_mode(dtype, response, param, beta4):
+    """The saturable and cubic-quintic responses without terms beyond L^2 run on every
+    split-step launch mode (the tile kernels' Kerr phase takes the response's flow
+    integral): five kernels, two tile kernels, one kernel per step (with beta4: the beta4
+    step) and the persistent launch, each against the oracle; the persistent launch
+    equals the one-kernel step bitwise, and so does the first half step of the
+    persistent prologue."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    kw = dict(nl_kind=response, nl_param=param)
+    ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, beta4=beta4, **kw)
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=dtype, p1=w.p1, beta4=beta4,
+                 response=response, response_param=param)
+    assert m.tuning["fused"] == 2
+    dz = min(w.dz, 0.9 * 2.5 / m.spectral_radius())  # beta4 L^2 raises the spectral radius
+    u0 = 1.5 * w.u0
+    u = dev(u0, dtype)
+    tol = 1e-12 if dtype == "c128" else 2e-5
+    modes = (0, 2) if beta4 else (0, 1, 2, 3)
+    say("responses", dtype, response, "beta4", beta4, "dz", dz)
+    outs = {}
+    for n in (1, 9):
+        ref = S.propagate(u0, ops, dz, n, w.gamma)
+        for fused in modes:
+            m.tuning = {"fused": fused}
+            if fused == 3:
+                assert m.time_kernels(dz, w.gamma, reps=10)["persist"]["ms"] > 0
+            f = u.clone()
+            m.propagate(f, dz, n, w.gamma)
+            m.check_finite()
+            outs[(n, fused)] = host(f)
+            err = rel(outs[(n, fused)], ref)
+            say(f"  fused {fused} steps {n}: rel {err:.3e}")
+            assert err < tol, (fused, n, err)
+        if 3 in modes:
+            assert np.array_equal(outs[(n, 3)], outs[(n, 2)]), n
 
 
 def test_full_size_pml_and_mode_iterations():
