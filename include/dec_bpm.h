@@ -198,7 +198,8 @@ int dec_bpm_vertex_tiles(dec_bpm_t h, int32_t* tile, int32_t* rows_per_tile);
  * averaging of "Discrete Hodge star", unit coupling; derived, the paper gives
  * no coupling).  dn_dev is a device array of n_vert doubles in caller order,
  * or NULL to reset to 0.  Synchronises (dn is also folded into the stability
- * bound on the host).  Errors: EINVAL (misaligned pointer), EUNSTABLE is
+ * bound on the host, and a digest of its values identifies the operator to
+ * the adjoint: installing the same values again restores the same operator).  Errors: EINVAL (misaligned pointer), EUNSTABLE is
  * reported by the next propagate if dn pushes dz rho(H_lin) past the margin.
  */
 int dec_bpm_set_index_perturbation(dec_bpm_t h, const double* dn_dev, void* stream);
@@ -352,7 +353,11 @@ int dec_bpm_overlap(dec_bpm_t h, const void* a, const void* b, double* re, doubl
  * dec_bpm_forward_checkpointed propagates `field` in place like
  * dec_bpm_propagate and stores the checkpoints in the workspace.
  * dec_bpm_adjoint takes grad_out = dJ/dpsi(z_L) and, using the checkpoints of
- * the matching forward call (same dz, n_steps, gamma, every, dn), returns
+ * the matching forward call (the forward call on this handle that last wrote
+ * this workspace, with the same dz, n_steps, gamma and every, and an index
+ * perturbation of the same values installed now as then; the handle keeps
+ * the 64 most recent forward calls, one per workspace, so that several
+ * forwards may precede their adjoints), returns
  * grad_field0 = dJ/dpsi(0) (complex, caller order) and, if grad_dn is not
  * NULL, grad_dn = dJ/d(dn) (double[n_vert], caller order).  Each segment
  * between checkpoints is recomputed forward, storing its stage vectors, then

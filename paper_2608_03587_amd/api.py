@@ -100,6 +100,7 @@ class Mesh:
                                  None if W is None else _ptr(W, ctypes.c_double), ctypes.byref(opt),
                                  ctypes.byref(h)))
         self._h = h
+        self._dn = None  # the installed index perturbation (a private copy), or None
         self._destroy = L.dec_bpm_destroy
         self.n_vert = xy.shape[0]
         self.n_tri = tri.shape[0]
@@ -258,13 +259,17 @@ class Mesh:
         return complex(re.value, im.value)
 
     def set_index_perturbation(self, dn, stream=None):
+        """Install the per-vertex index perturbation dn (float64 CUDA tensor, caller
+        order) or None; the library copies its values."""
         if dn is None:
             B.check(B.lib().dec_bpm_set_index_perturbation(self._h, None, _stream(stream)))
+            self._dn = None
             return
         if dn.device.type != "cuda" or dn.dtype != torch.float64 or not dn.is_contiguous() or \
                 dn.numel() != self.n_vert:
             raise TypeError("dn must be a contiguous float64 CUDA tensor with one entry per vertex")
         B.check(B.lib().dec_bpm_set_index_perturbation(self._h, ctypes.c_void_p(dn.data_ptr()), _stream(stream)))
+        self._dn = dn.detach().clone()
 
     def workspace_size(self, n_steps, every=0) -> int:
         s = ctypes.c_size_t()
@@ -413,18 +418,29 @@ class DecBpmFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u0, dn, mesh, dz, n_steps, gamma, every):
-        mesh.set_index_perturbation(None if dn is None else dn.detach())
-        u = u0.detach().clone()
-        ws = torch.empty(mesh.workspace_size(n_steps, every), dtype=torch.uint8, device=u0.device)
-        mesh.forward_checkpointed(u, dz, n_steps, gamma, ws, every)
-        ctx.mesh, ctx.ws, ctx.args = mesh, ws, (dz, n_steps, gamma, every)
-        ctx.has_dn = dn is not None
+        # the mesh keeps the perturbation it had: dn is installed for this call only
+        prev = mesh._dn
+        dn_c = None if dn is None else dn.detach().clone()
+        mesh.set_index_perturbation(dn_c)
+        try:
+            u = u0.detach().clone()
+            ws = torch.empty(mesh.workspace_size(n_steps, every), dtype=torch.uint8, device=u0.device)
+            mesh.forward_checkpointed(u, dz, n_steps, gamma, ws, every)
+        finally:
+            mesh.set_index_perturbation(prev)
+        ctx.mesh, ctx.ws, ctx.args, ctx.dn = mesh, ws, (dz, n_steps, gamma, every), dn_c
         return u
 
     @staticmethod
     def backward(ctx, g):
         dz, n_steps, gamma, every = ctx.args
-        g0, gdn = ctx.mesh.adjoint(g.contiguous(), dz, n_steps, gamma, ctx.ws, every, want_dn=ctx.has_dn)
+        mesh = ctx.mesh
+        prev = mesh._dn
+        mesh.set_index_perturbation(ctx.dn)  # the forward's operator (same values, same digest)
+        try:
+            g0, gdn = mesh.adjoint(g.contiguous(), dz, n_steps, gamma, ctx.ws, every, want_dn=ctx.dn is not None)
+        finally:
+            mesh.set_index_perturbation(prev)
         return g0, gdn, None, None, None, None, None
 
 

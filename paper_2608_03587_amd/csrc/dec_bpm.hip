@@ -193,14 +193,19 @@ struct Engine {
   hipStream_t cap = nullptr;
   std::vector<GraphEntry> graphs;
   std::vector<void*> allocs;
-  // record of the last checkpointed forward (validated by the adjoint)
-  struct {
+  // records of the recent checkpointed forwards, one per workspace (validated
+  // by the adjoint; the oldest is dropped beyond kMaxCkpt)
+  struct CkptRec {
     const void* ws = nullptr;
     double dz = 0, gamma = 0;
     int64_t n = -1, every = 0;
-    uint64_t dn_version = 0;
-  } ckpt;
-  uint64_t dn_version = 0;
+    uint64_t dn_digest = 0;
+  };
+  static constexpr size_t kMaxCkpt = 64;
+  std::vector<CkptRec> ckpts;
+  // digest of the installed index perturbation's values (0: none), so that
+  // installing the same values again restores the same operator identity
+  uint64_t dn_digest = 0;
 
   // threads per workgroup of the step-tile kernels: the requested count if it
   // covers every compute slot once (one slot per thread), else at least half of
@@ -2416,6 +2421,7 @@ int dec_bpm_set_index_perturbation(dec_bpm_t h, const double* dn_dev, void* stre
   if (!E.on_device) fail(DEC_BPM_ENODEVICE, "handle was created host-only");
   hipStream_t st = as_stream(stream);
   double mx = 0.0;
+  uint64_t digest = 0;
   if (dn_dev) {
     std::vector<double> host(E.n_rows);
     HIP_OK(hipMemcpyAsync(host.data(), dn_dev, E.n_rows * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2424,6 +2430,11 @@ int dec_bpm_set_index_perturbation(dec_bpm_t h, const double* dn_dev, void* stre
       if (!std::isfinite(x)) fail(DEC_BPM_EINVAL, "index perturbation has a non-finite entry");
       mx = std::max(mx, std::fabs(x));
     }
+    // FNV-1a over the values' bytes; 0 is kept for "none"
+    digest = 1469598103934665603ull;
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(host.data());
+    for (size_t i = 0; i < host.size() * sizeof(double); ++i) digest = (digest ^ b[i]) * 1099511628211ull;
+    if (digest == 0) digest = 1;
   }
   if (E.dtype == DEC_BPM_C64)
     decbpm::launch_set_v<float>(E.n_rows, static_cast<const float*>(E.v0), dn_dev, E.perm, static_cast<float*>(E.v),
@@ -2434,7 +2445,7 @@ int dec_bpm_set_index_perturbation(dec_bpm_t h, const double* dn_dev, void* stre
   decbpm::check_launch();
   HIP_OK(hipStreamSynchronize(st));
   E.dn_max = mx;
-  E.dn_version++;
+  E.dn_digest = digest;
   ABI_CATCH
 }
 
@@ -2739,12 +2750,18 @@ int dec_bpm_forward_checkpointed(dec_bpm_t h, void* field, double dz, int64_t n_
     decbpm::forward_ckpt_t<float>(E, field, dz, n_steps, gamma, every, ws, as_stream(stream));
   else
     decbpm::forward_ckpt_t<double>(E, field, dz, n_steps, gamma, every, ws, as_stream(stream));
-  E.ckpt.ws = workspace;
-  E.ckpt.dz = dz;
-  E.ckpt.gamma = gamma;
-  E.ckpt.n = n_steps;
-  E.ckpt.every = L.S;
-  E.ckpt.dn_version = E.dn_version;
+  Engine::CkptRec rec;
+  rec.ws = workspace;
+  rec.dz = dz;
+  rec.gamma = gamma;
+  rec.n = n_steps;
+  rec.every = L.S;
+  rec.dn_digest = E.dn_digest;
+  auto& cs = E.ckpts;
+  cs.erase(std::remove_if(cs.begin(), cs.end(), [&](const Engine::CkptRec& c) { return c.ws == workspace; }),
+           cs.end());
+  if (cs.size() >= Engine::kMaxCkpt) cs.erase(cs.begin());
+  cs.push_back(rec);
   ABI_CATCH
 }
 
@@ -2760,8 +2777,10 @@ int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_step
   const auto L = decbpm::ws_layout(E, n_steps, every);
   if (!workspace || ws_bytes < L.total)
     fail(DEC_BPM_EWORKSPACE, "workspace needs " + std::to_string(L.total) + " bytes");
-  if (E.ckpt.ws != workspace || E.ckpt.dz != dz || E.ckpt.gamma != gamma || E.ckpt.n != n_steps ||
-      E.ckpt.every != L.S || E.ckpt.dn_version != E.dn_version)
+  const auto rec = std::find_if(E.ckpts.begin(), E.ckpts.end(),
+                                [&](const Engine::CkptRec& c) { return c.ws == workspace; });
+  if (rec == E.ckpts.end() || rec->dz != dz || rec->gamma != gamma || rec->n != n_steps || rec->every != L.S ||
+      rec->dn_digest != E.dn_digest)
     fail(DEC_BPM_EWORKSPACE, "workspace does not hold the checkpoints of a matching forward call");
   char* ws = static_cast<char*>(workspace);
   hipStream_t st = as_stream(stream);

@@ -902,6 +902,53 @@ def test_autograd_function_and_finite_differences():
         assert abs(float(fd_n - an_n)) < 1e-6 * abs(float(fd_n))
 
 
+def test_autograd_calls_leave_the_mesh_as_they_found_it():
+    """propagate_with_grad installs its index perturbation for its own forward and
+    backward only: several forwards may precede their backwards (in any order) and give
+    the gradients of one call at a time, bitwise; a plain propagate afterwards sees the
+    perturbation the mesh had before (none, or the one the caller installed)."""
+    w = W.adjoint_mmf(n_vert=3000, n_steps=10)
+    n = 12
+    m = lib_mesh(w, "c128")
+    tgt = dev(w.extra["target"], "c128")
+    h0 = torch.from_numpy(oracle_ops(w).H0).to(DEV)
+    dns = [torch.from_numpy(w.extra["dn"]).to(DEV), torch.from_numpy(0.5 * w.extra["dn"][::-1].copy()).to(DEV)]
+
+    def obj(u):
+        c = (h0 * tgt.conj() * u).sum()
+        return (c.conj() * c).real
+
+    def leaves(d):
+        return dev(w.u0, "c128").requires_grad_(True), d.clone().requires_grad_(True)
+
+    refs = []
+    for d in dns:
+        u0, dd = leaves(d)
+        obj(api.propagate_with_grad(m, u0, dd, w.dz, n, w.gamma)).backward()
+        refs.append((host(u0.grad), dd.grad.cpu().numpy()))
+    a, b = leaves(dns[0]), leaves(dns[1])
+    ja = obj(api.propagate_with_grad(m, a[0], a[1], w.dz, n, w.gamma))
+    jb = obj(api.propagate_with_grad(m, b[0], b[1], w.dz, n, w.gamma))
+    f = dev(w.u0, "c128")
+    m.propagate(f, w.dz, n, w.gamma)
+    g = dev(w.u0, "c128")
+    lib_mesh(w, "c128").propagate(g, w.dz, n, w.gamma)
+    assert np.array_equal(host(f), host(g))  # no perturbation left behind
+    jb.backward()
+    ja.backward()
+    for (u0, dd), (gu, gd) in zip((a, b), refs):
+        assert np.array_equal(host(u0.grad), gu) and np.array_equal(dd.grad.cpu().numpy(), gd)
+    m.set_index_perturbation(dns[1])
+    f1 = dev(w.u0, "c128")
+    m.propagate(f1, w.dz, n, w.gamma)
+    u0, dd = leaves(dns[0])
+    obj(api.propagate_with_grad(m, u0, dd, w.dz, n, w.gamma)).backward()
+    assert np.array_equal(host(u0.grad), refs[0][0])
+    f2 = dev(w.u0, "c128")
+    m.propagate(f2, w.dz, n, w.gamma)
+    assert np.array_equal(host(f1), host(f2))  # the caller's perturbation is back
+
+
 def test_adjoint_full_size_directional_derivatives():
     """The full 498k-vertex multimode-fibre adjoint workload in the bench's launch configuration
     (autotuned), 40 steps with 7-step checkpoints: the adjoint's field and index gradients
