@@ -91,13 +91,14 @@ typedef struct {
    * (s_r/s_t) tt^T (s_r = 1 + i sigma, s_t = r~/r, taken at each triangle's
    * centroid); v, M and the power keep the real H0.  pml_sigma = 0: none.
    * Needs 0 < pml_r0 < pml_r1, no beta4 term and rows of at most 12
-   * neighbours; the handle then runs dec_bpm_propagate on the one-kernel step
-   * (fused = 2) or, in complex64 when every tile fits at once, the persistent
-   * launch (fused = 3), and kerr_step/diagnostics (Hamiltonian NaN); every entry point
-   * that applies a real L (apply, linear_step, unsplit, adaptive, find_mode,
-   * checkpointed forward and adjoint, batches) returns EINVAL.  The stability
-   * check uses the unstretched operator's spectral radius, which bounds the
-   * stretched one's. */
+   * neighbours; the handle then runs dec_bpm_propagate and
+   * dec_bpm_propagate_unsplit on the one-kernel step (fused = 2) or, in
+   * complex64 when every tile fits at once, the persistent launch (fused = 3),
+   * dec_bpm_propagate_adaptive on its trial tiles with complex weights, and
+   * kerr_step/diagnostics (Hamiltonian NaN); the entry points whose kernels
+   * apply a real L (apply, linear_step, find_mode, checkpointed forward and
+   * adjoint, batches) return EINVAL.  The stability check uses the
+   * unstretched operator's spectral radius, which bounds the stretched one's. */
   double pml_r0, pml_r1, pml_sigma;
   /* Eq. 1 in full: H_lin = p1 L + beta4 L^2 + p3 L^3 + p4 L^4 - diag(v), and
    * the Kerr response N(I) in place of I = |psi|^2 (DEC_BPM_N_KERR, default;

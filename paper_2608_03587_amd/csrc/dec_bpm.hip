@@ -160,6 +160,7 @@ struct Engine {
     std::vector<int64_t> arp;
     std::vector<int32_t> col;
     std::vector<double> lw, mw;
+    std::vector<double> lwi;  // imaginary parts of the L weights (a PML), else empty
     bool dec = false;
   } adj;
   bool dp5_tried = false, has_dp5 = false;
@@ -867,11 +868,12 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
     fail(DEC_BPM_EINVAL, "PML: the mesh needs the one-kernel step tiles (rows of at most 12 neighbours)");
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
   if (E.F > 1 && !E.general()) build_field_tiles<T>(E, arp, acol, alw, amw, any_dec);
-  if (E.has_step && E.F == 1 && !pml) {  // kept for the adaptive integrator's tiles
+  if (E.has_step && E.F == 1) {  // kept for the adaptive integrator's tiles
     E.adj.arp = std::move(arp);
     E.adj.col = std::move(acol);
     E.adj.lw = std::move(alw);
     E.adj.mw = std::move(amw);
+    if (pml) E.adj.lwi = std::move(alwi);
     E.adj.dec = any_dec;
   }
   const size_t nv = size_t(n) * E.F;
@@ -1421,7 +1423,9 @@ static bool ensure_dp5_tiles(Engine& E) {
   const int max_compute = (sizeof(T) == 8 || E.dp5_one_slot) ? 1024 : 2048;
   HostTiles H;
   for (int ts = E.dp5_tile; ts >= 64; ts /= 2) {
-    if (!make_tiles(E.n_rows, E.adj.arp, E.adj.col, E.adj.lw, E.adj.mw, ts, 7, 7, H, true, E.sort_ring0)) continue;
+    if (!make_tiles(E.n_rows, E.adj.arp, E.adj.col, E.adj.lw, E.adj.mw, ts, 7, 7, H, true, E.sort_ring0,
+                    E.adj.lwi.empty() ? nullptr : &E.adj.lwi))
+      continue;
     if (size_t(H.max_slots) * 6 * sizeof(T) > lds_max || H.max_compute > max_compute) continue;
     upload_tiles<T>(E, H, E.adj.dec, E.n_rows, E.dp5);
     E.has_dp5 = true;
@@ -2559,7 +2563,6 @@ int dec_bpm_propagate_unsplit(dec_bpm_t h, void* field, double dz, int64_t n_ste
   ABI_TRY
   need(h);
   decbpm::no_general(h->E, "dec_bpm_propagate_unsplit");
-  decbpm::no_pml(h->E, "dec_bpm_propagate_unsplit");
   decbpm::check_prop_args(h->E, field, dz, n_steps, gamma);
   if (!h->E.has_step || h->E.F != 1)
     fail(DEC_BPM_EINVAL,
@@ -2578,7 +2581,6 @@ int dec_bpm_propagate_adaptive(dec_bpm_t h, void* field, double z_end, double h0
   ABI_TRY
   need(h);
   decbpm::no_general(h->E, "dec_bpm_propagate_adaptive");
-  decbpm::no_pml(h->E, "dec_bpm_propagate_adaptive");
   Engine& E = h->E;
   if (n_accepted) *n_accepted = 0;
   if (n_rejected) *n_rejected = 0;

@@ -2256,7 +2256,7 @@ __global__ void __launch_bounds__(1024) k_bstep(DevOps<T> d, TileOps<T> tl, cons
 }
 
 // One unsplit classical RK4 step per tile (the Kerr term inside every stage).
-template <typename T, int KMAX, bool DEC, int J>
+template <typename T, int KMAX, bool DEC, int J, bool CL = false>
 __global__ void __launch_bounds__((StepBound<T, J>::value)) k_rk4u(DevOps<T> d, TileOps<T> tl,
                                                                   const typename CT<T>::C* __restrict__ in_psi,
                                                                   typename CT<T>::C* __restrict__ out_psi, T h,
@@ -2270,7 +2270,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_rk4u(DevOps<T> d, 
   C* Bv = A + MS;
   T* SA = reinterpret_cast<T*>(Bv + MS);
   T* SB = SA + MS;
-  StepTile<T, KMAX, DEC, J> st;
+  StepTile<T, KMAX, DEC, J, CL> st;
   st.init(d, tl, tile);
   for (int i = threadIdx.x; i < st.hd[4]; i += blockDim.x) {
     const C v = in_psi[st.slot_row(i)];
@@ -2390,7 +2390,7 @@ __device__ inline void dp5_decide(Dp5Ctl* ctl, double sumsq, double inv_n) {
 // the squared error norm (agent-scope store, acknowledged before it counts
 // itself in); the workgroup that arrives last sums the shares in tile order,
 // runs the controller and resets the arrival count for the next trial.
-template <typename T, int KMAX, bool DEC, int J>
+template <typename T, int KMAX, bool DEC, int J, bool CL = false>
 __global__ void __launch_bounds__(1024) k_dp5(DevOps<T> d, TileOps<T> tl, typename CT<T>::C* x0,
                                               typename CT<T>::C* x1, Dp5Ctl* ctl, double* __restrict__ partial,
                                               uint32_t* __restrict__ arrivals, T gamma, T rtol, T atol,
@@ -2410,7 +2410,7 @@ __global__ void __launch_bounds__(1024) k_dp5(DevOps<T> d, TileOps<T> tl, typena
   C* Bv = A + MS;
   T* SA = reinterpret_cast<T*>(Bv + MS);
   T* SB = SA + MS;
-  StepTile<T, KMAX, DEC, J> st;
+  StepTile<T, KMAX, DEC, J, CL> st;
   st.init(d, tl, tile);
   for (int i = threadIdx.x; i < st.hd[7]; i += blockDim.x) {
     const C v = in_psi[st.slot_row(i)];
@@ -2455,7 +2455,7 @@ __global__ void __launch_bounds__(1024) k_dp5(DevOps<T> d, TileOps<T> tl, typena
 // The global wait orders the buffer reuse (a trial writes x[1 - cur], which no
 // tile still reads) and the shares alternate between two halves of `partial`
 // (2 * n_tiles doubles).
-template <typename T, int KMAX, bool DEC, int J>
+template <typename T, int KMAX, bool DEC, int J, bool CL = false>
 __global__ void __launch_bounds__(1024) k_dp5_persist(DevOps<T> d, TileOps<T> tl, typename CT<T>::C* x0,
                                                       typename CT<T>::C* x1, Dp5Ctl* ctl, double* __restrict__ partial,
                                                       int32_t* flags, int32_t* status, int32_t spin_limit, T gamma,
@@ -2473,7 +2473,7 @@ __global__ void __launch_bounds__(1024) k_dp5_persist(DevOps<T> d, TileOps<T> tl
   C* Bv = A + MS;
   T* SA = reinterpret_cast<T*>(Bv + MS);
   T* SB = SA + MS;
-  StepTile<T, KMAX, DEC, J> st;
+  StepTile<T, KMAX, DEC, J, CL> st;
   st.init(d, tl, tile);
   if (threadIdx.x == 0) cs = *ctl;
   __syncthreads();
@@ -3763,9 +3763,14 @@ void launch_dp5(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
   const size_t shmem = size_t(tl.max_slots) * 2 * (sizeof(C) + sizeof(T));
   const int J = (tl.max_compute + block - 1) / block;
-#define DECBPM_DP5(KM, DEC, JJ)                                                                                   \
-  hipLaunchKernelGGL((k_dp5<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, static_cast<C*>(x0),         \
+#define DECBPM_DP5C(KM, DEC, JJ, CLX)                                                                              \
+  hipLaunchKernelGGL((k_dp5<T, KM, DEC, JJ, CLX>), dim3(g), dim3(block), shmem, st, d, tl, static_cast<C*>(x0),     \
                      static_cast<C*>(x1), ctl, partial, arrivals, T(gamma), T(rtol), T(atol), inv_n)
+  // complex L weights (a PML): the imaginary parts in a second register array
+  const bool cl = tl.llwi != nullptr;
+#define DECBPM_DP5(KM, DEC, JJ)           \
+  if (cl) DECBPM_DP5C(KM, DEC, JJ, true); \
+  else DECBPM_DP5C(KM, DEC, JJ, false)
   // complex128 tiles keep every compute slot on its own thread (J = 1): two
   // slots of rows with 12 neighbours need more than the 128 registers of a
   // 1024-thread workgroup, and halving the workgroup costs more than the spills
@@ -3781,6 +3786,7 @@ void launch_dp5(const DevOps<T>& d, const TileOps<T>& tl, void* x0, void* x1, Dp
   }
 #undef DECBPM_DP5_J
 #undef DECBPM_DP5
+#undef DECBPM_DP5C
 }
 
 #if DECBPM_PART & 1
@@ -3822,7 +3828,9 @@ template <typename T>
 static const void* dp5_persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block) {
   const int J = (tl.max_compute + block - 1) / block;
   const bool dec = tl.lmw != nullptr;
-#define DECBPM_DP(KM, DEC, JJ) reinterpret_cast<const void*>(&k_dp5_persist<T, KM, DEC, JJ>)
+#define DECBPM_DP(KM, DEC, JJ)                                                        \
+  (tl.llwi != nullptr ? reinterpret_cast<const void*>(&k_dp5_persist<T, KM, DEC, JJ, true>) \
+                      : reinterpret_cast<const void*>(&k_dp5_persist<T, KM, DEC, JJ, false>))
 #define DECBPM_DP_J(KM, DEC) return J <= 1 ? DECBPM_DP(KM, DEC, 1) : DECBPM_DP(KM, DEC, 2);
   if (kmax_of(d.wmax) == 8) {
     if (dec) { DECBPM_DP_J(8, true) } else { DECBPM_DP_J(8, false) }
@@ -3916,9 +3924,13 @@ void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
   const size_t shmem = size_t(tl.max_slots) * 2 * (sizeof(typename CT<T>::C) + sizeof(T));
   const int J = (tl.max_compute + block - 1) / block;
-#define DECBPM_RK4U(KM, DEC, JJ)                                                                               \
-  hipLaunchKernelGGL((k_rk4u<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi),     \
+#define DECBPM_RK4UC(KM, DEC, JJ, CLX)                                                                           \
+  hipLaunchKernelGGL((k_rk4u<T, KM, DEC, JJ, CLX>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi), \
                      DECBPM_M(T, out_psi), T(h), T(gamma))
+  const bool cl = tl.llwi != nullptr;  // complex L weights (a PML)
+#define DECBPM_RK4U(KM, DEC, JJ)           \
+  if (cl) DECBPM_RK4UC(KM, DEC, JJ, true); \
+  else DECBPM_RK4UC(KM, DEC, JJ, false)
 #define DECBPM_RK4U_J(KM, DEC) \
   if (J <= 1) DECBPM_RK4U(KM, DEC, 1); else DECBPM_RK4U(KM, DEC, 2);
   const bool dec = tl.lmw != nullptr;
@@ -3929,6 +3941,7 @@ void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi
   }
 #undef DECBPM_RK4U_J
 #undef DECBPM_RK4U
+#undef DECBPM_RK4UC
 }
 
 template <typename T>
@@ -4019,13 +4032,14 @@ void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_i
 #undef DECBPM_STEPA
 }
 
-// Persistent kernel instance for a body; tiles with complex L weights have one
-// for the split-step body in complex64 only (nullptr otherwise).
+// Persistent kernel instance for a body; tiles with complex L weights have
+// instances in complex64 only (nullptr otherwise).
 template <typename T, int KM, bool DEC, int JJ>
 static const void* persist_instance(int body, bool cl) {
   if (cl) {
     if constexpr (sizeof(T) == 4) {
-      if (body == 0) return reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0, true>);
+      return body ? reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 1, true>)
+                  : reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0, true>);
     }
     return nullptr;
   }

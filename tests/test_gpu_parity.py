@@ -441,8 +441,8 @@ def test_pml_step_matches_oracle(dtype):
     the 89k-vertex step-index mesh: the one-kernel step with complex L weights against the
     oracle's split scheme on the stretched operators, for step counts that mix graph
     replays and eager steps; in complex64 the persistent launch with complex weights gives
-    the one-kernel step's bits; the handle refuses other launch modes and real-L entry
-    points."""
+    the one-kernel step's bits; the handle refuses the two-kernel mode and the entry
+    points whose kernels apply a real L."""
     w = case("step_index", n_vert=20000, n_steps=10)
     pml = (35.0, 40.0, 1.0)
     ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, None, pml=pml)
@@ -480,6 +480,53 @@ def test_pml_step_matches_oracle(dtype):
     P, E = m.diagnostics(u.clone(), w.gamma)
     assert P > 0 and math.isnan(E)
     assert m.time_kernels(w.dz, w.gamma, reps=10)["step"]["ms"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_pml_unsplit_and_adaptive_match_oracle(dtype):
+    """The paper's own integrators with the perfectly matched layer (complex L weights in
+    the unsplit RK4 and Dormand-Prince trial kernels): the unsplit RK4 step (one kernel per
+    step; in complex64 also the persistent launch, equal to it to rounding) and the adaptive
+    pair against the oracle's runs on the stretched operators (in complex128 with the
+    same accepted and rejected counts)."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    pml = (35.0, 40.0, 1.0)
+    ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, None, pml=pml)
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, None, dtype=dtype, pml=pml)
+    u = dev(w.u0, dtype)
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    for n in (1, 9):
+        ref = US.propagate_rk4(w.u0, ops, w.dz, n, w.gamma)
+        m.tuning = {"fused": 2}
+        f = u.clone()
+        m.propagate_unsplit(f, w.dz, n, w.gamma)
+        m.check_finite()
+        err = rel(host(f), ref)
+        say("pml unsplit", dtype, n, err)
+        assert err < tol, (n, err)
+        if dtype == "c64":
+            m.tuning = {"fused": 3}
+            assert m.time_kernels(w.dz, w.gamma, reps=10)["unsplit_persist"]["ms"] > 0
+            g = u.clone()
+            m.propagate_unsplit(g, w.dz, n, w.gamma)
+            m.check_finite()
+            # the persistent body keeps the owned |v|^2 from the previous step where the tile
+            # kernel recomputes it on load: the two may differ by that sum's contraction (ulps)
+            assert rel(host(g), host(f)) < 1e-6, (n, rel(host(g), host(f)))
+            m.tuning = {"fused": 2}
+    rtol, atol = (1e-9, 1e-11) if dtype == "c128" else (1e-5, 1e-7)
+    m.tuning = {"fused": 2}
+    for z_end, h0 in ((12 * w.dz, w.dz), (6 * w.dz, 30 * w.dz)):
+        f = u.clone()
+        st = m.propagate_adaptive(f, z_end, h0, w.gamma, rtol=rtol, atol=atol)
+        m.check_finite()
+        ref, rs = US.propagate_dp54(w.u0, ops, z_end, h0, w.gamma, rtol=rtol, atol=atol)
+        err = rel(host(f), ref)
+        say("pml adaptive", dtype, z_end, h0, st, rs, err)
+        assert st["z"] == z_end
+        if dtype == "c128":
+            assert (st["accepted"], st["rejected"]) == (rs["accepted"], rs["rejected"])
+        assert err < GATE[dtype], (z_end, h0, err)
 
 
 def test_pml_absorbs_on_the_gpu():

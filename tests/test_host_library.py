@@ -214,7 +214,8 @@ def test_workspace_size_grows_like_sqrt_n_checkpoints():
 def test_pml_host_assembly_matches_the_oracle():
     """The library's stretched stiffness (P1 form |t| grad^T Lambda grad, accumulated per
     triangle) and dual areas against the oracle's Whitney-Galerkin stretched stars; the
-    entry points that apply a real L refuse a PML handle; bad layer options are refused."""
+    entry points whose kernels apply a real L refuse a PML handle (the unsplit and
+    adaptive integrators take it); bad layer options are refused."""
     import scipy.sparse as sp
 
     mesh = M.disk_mesh(6.0, 0.4, 9)
@@ -232,7 +233,7 @@ def test_pml_host_assembly_matches_the_oracle():
     assert np.abs(ex["h0"] - ops.H0).max() < 1e-13 * ops.H0.max()
     lib = B.lib()
     fake = ctypes.c_void_p(1 << 20)
-    assert lib.dec_bpm_propagate_unsplit(m.handle, fake, 1e-3, 1, 1.0, None) == B.EINVAL
+    assert lib.dec_bpm_propagate_unsplit(m.handle, fake, 1e-3, 1, 1.0, None) == B.ENODEVICE  # takes a PML
     assert lib.dec_bpm_linear_step(m.handle, fake, 1e-3, None) == B.EINVAL
     assert lib.dec_bpm_propagate(m.handle, fake, 1e-3, 1, 1.0, None) == B.ENODEVICE
     plain = api.Mesh(mesh.xy, mesh.tri, dtype="c128", host_only=True)
