@@ -108,8 +108,11 @@ typedef struct {
    * N(|psi|^2 e^{-2 w z}), in closed form).  A non-Kerr response runs on
    * every split-step launch mode (the tile kernels' Kerr phase takes the
    * flow integral of the response).  p3 or p4 non-zero runs the five-kernel
-   * path (fused = 0; the L powers by Horner in extra gather launches: the
-   * tile halos cover at most two products per stage).  With either, the
+   * path (fused = 0: the split step's tile kernels cover at most two products
+   * per stage); its RK4 stages then run as one tile kernel each, the operator
+   * sum by Horner in LDS on tiles of four halo rings (three without p4), or,
+   * with DEC_BPM_GEN_TILES=0 in the environment at handle creation, as chains
+   * of gather launches.  With either, the
    * checkpointed forward and adjoint, apply(H), batches, unsplit, adaptive
    * and find_mode return EINVAL (their kernels are written for the Kerr
    * right-hand side and terms up to L^2), and diagnostics report a NaN

@@ -127,6 +127,17 @@ struct Engine {
   // step (launch mode 6: a workgroup per tile steps all fields in turn)
   DevTiles sfl;
   bool has_sfl = false;
+  // L^3 or L^4: tiles of D halo rings (D = 4 with p4, else 3) for the RK4
+  // stages of the operator sum (one tile kernel per stage)
+  DevTiles gtl;
+  bool has_gtl = false;
+  bool gen_tiles = true;  // DEC_BPM_GEN_TILES=0: the gather-kernel chain instead
+  int gblock() const {
+    const int mc = gtl.max_compute;
+    const int b = std::max(tile_block, ((mc + 1) / 2 + 63) / 64 * 64);
+    if (b >= mc) return std::min(1024, b);
+    return std::min(dtype == DEC_BPM_C128 ? 640 : 1024, b);
+  }
   bool has_step = false;
   bool has_step4 = false;  // the step tiles hold the beta4 layout (eight or nine rings)
   bool pml = false;        // complex-stretched L (perfectly matched layer): one-kernel step only
@@ -332,6 +343,7 @@ static void env_defaults(Engine& E) {
   if (const char* s = std::getenv("DEC_BPM_STEPS_PER_GRAPH")) E.spg = std::max(1, std::atoi(s));
   if (const char* s = std::getenv("DEC_BPM_XCD_REMAP")) E.xcd = std::atoi(s) ? 1 : 0;
   if (const char* s = std::getenv("DEC_BPM_COOPERATIVE")) E.coop = std::atoi(s) != 0;
+  if (const char* s = std::getenv("DEC_BPM_GEN_TILES")) E.gen_tiles = std::atoi(s) != 0;
 }
 
 template <typename T>
@@ -659,6 +671,26 @@ static void build_step_tiles(Engine& E, const std::vector<int64_t>& arp, const s
   E.has_persist = true;
 }
 
+// Operator sums with L^3 or L^4: tiles of D halo rings (D = 4 with p4, else
+// 3), three complex vectors per slot in LDS (the stage input and two Horner
+// intermediates), for one tile kernel per RK4 stage.
+template <typename T>
+static void build_gen_tiles(Engine& E, const std::vector<int64_t>& arp, const std::vector<int32_t>& acol,
+                            const std::vector<double>& alw, const std::vector<double>& amw) {
+  if (!E.high_order() || !E.gen_tiles || E.F != 1 || E.wmax > 12) return;
+  const int rings = E.p4 != 0.0 ? 4 : 3;
+  const size_t lds_max = sizeof(T) == 8 ? 100 * 1024 : 63 * 1024;  // three complex vectors per slot
+  const int max_compute = sizeof(T) == 8 ? 2 * 640 : 2 * 1024;
+  HostTiles H;
+  for (int ts = 1024; ts >= 64; ts /= 2) {
+    if (!make_tiles(E.n_rows, arp, acol, alw, amw, ts, rings, rings, H, true, E.sort_ring0)) continue;
+    if (size_t(H.max_slots) * 6 * sizeof(T) > lds_max || H.max_compute > max_compute) continue;
+    upload_tiles<T>(E, H, false, E.n_rows, E.gtl);
+    E.has_gtl = true;
+    return;
+  }
+}
+
 // Batched path, field-loop step: the one-field step tiles (five rings, four
 // for the lumped Kerr term) over the concatenated rows of every mesh; a tile
 // may straddle two meshes (the operator is block diagonal, so its halo holds
@@ -868,6 +900,7 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
     fail(DEC_BPM_EINVAL, "PML: the mesh needs the one-kernel step tiles (rows of at most 12 neighbours)");
   if (E.F > 1) build_batch_tiles<T>(E, arp, acol, alw, amw, any_dec);
   if (E.F > 1 && !E.general()) build_field_tiles<T>(E, arp, acol, alw, amw, any_dec);
+  build_gen_tiles<T>(E, arp, acol, alw, amw);
   if (E.has_step && E.F == 1) {  // kept for the adaptive integrator's tiles
     E.adj.arp = std::move(arp);
     E.adj.col = std::move(acol);
@@ -952,6 +985,13 @@ static void lin_step(const Engine& E, const DevOps<T>& d, const void* in, void* 
   const void* xs[4] = {in, y1, y2, y3};
   void* ys[4] = {y1, y2, y3, out};
   const double cs[4] = {dz / 4, dz / 3, dz / 2, dz};
+  if ((E.p3 != 0.0 || E.p4 != 0.0) && E.has_gtl) {
+    // one tile kernel per stage: the Horner chain of the operator sum in LDS
+    const TileOps<T> tg = E.gtl.template ops<T>();
+    for (int k = 0; k < 4; ++k)
+      launch_hstage<T>(d, tg, xs[k], in, ys[k], cs[k], E.p3, E.p4, k == 3 ? s_out : nullptr, tau_s, E.gblock(), st);
+    return;
+  }
   if (E.p3 != 0.0 || E.p4 != 0.0) {
     // sum_n p_n L^n x = L U with U = p1 x + L(p2 x + L(p3 x + p4 L x)) by Horner;
     // the beta4 stage with p1 -> 0, beta4 -> 1 and t = U applies the last L

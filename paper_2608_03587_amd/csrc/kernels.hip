@@ -2281,6 +2281,87 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_rk4u(DevOps<T> d, 
   st.step_unsplit(d, A, Bv, SA, SB, h, gamma, [&](int, int32_t r, const C& v) { out_psi[r] = v; });
 }
 
+// One RK4 stage of Eq. 1's operator sum with terms up to p4 L^4 on tiles of
+// D halo rings (D = 4 with p4, else 3): out = base + coef (-i)(sum_n p_n L^n x
+// - V x) on the owned rows, the powers of L by Horner on the LDS-staged x,
+// t_D = p_D x, t_n = p_n x + L t_{n+1}, sum = L t_1; each product shrinks the
+// valid region by one ring.  With s_out, the stage's result also gives the
+// next Kerr substep's integral N-integral(|out|^2, w, tau_s).
+template <typename T, int KMAX, int J>
+__global__ void __launch_bounds__((StepBound<T, J>::value)) k_hstage(DevOps<T> d, TileOps<T> tl,
+                                                                    const typename CT<T>::C* __restrict__ x,
+                                                                    const typename CT<T>::C* __restrict__ base,
+                                                                    typename CT<T>::C* __restrict__ out, T coef,
+                                                                    T p3, T p4, T* __restrict__ s_out, T tau_s) {
+  using C = typename CT<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t tile = logical_block(d.xcd_remap);
+  if (tile >= tl.n_tiles) return;
+  const int MS = tl.max_slots;
+  const int B = blockDim.x;
+  C* sm = reinterpret_cast<C*>(smem);
+  const CplxAoS<T> X{sm}, TA{sm + MS}, TB{sm + 2 * MS};
+  StepTile<T, KMAX, false, J> st;
+  st.init(d, tl, tile);
+  const int D = st.hd[15];  // rings of the tile: the number of products
+  for (int i = threadIdx.x; i < st.nLoad; i += B) X.put(i, x[st.slot_row(i)]);
+  const T pc[5] = {T(0), d.p1, d.beta4, p3, p4};
+  C xv[J], tv[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    xv[j] = i < st.n1 ? x[st.slot_row(i)] : C{T(0), T(0)};
+    tv[j].x = pc[D] * xv[j].x;
+    tv[j].y = pc[D] * xv[j].y;
+  }
+  __syncthreads();
+  // product k (k = 1..D-1): t_{D-k} = p_{D-k} x + L t_{D-k+1} on rings 0..D-k;
+  // the first product gathers x itself (t_D = p_D x), scaled afterwards
+  for (int k = 1; k < D; ++k) {
+    const CplxAoS<T>& src = k == 1 ? X : (k % 2 ? TB : TA);
+    const CplxAoS<T>& dst = k % 2 ? TA : TB;
+    const int nk = st.hd[D - k];
+    const T pn = pc[D - k];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int i = threadIdx.x + j * B;
+      if (i < nk) {
+        T ar = T(0), ai = T(0);
+        if (k == 1) {
+          st.template lsum_w<KMAX>(st.wd[j], src, j, xv[j], ar, ai);
+          ar *= pc[D];
+          ai *= pc[D];
+        } else {
+          st.template lsum_w<KMAX>(st.wd[j], src, j, tv[j], ar, ai);
+        }
+        tv[j].x = pn * xv[j].x + ar;
+        tv[j].y = pn * xv[j].y + ai;
+        dst.put(i, tv[j]);
+      }
+    }
+    __syncthreads();
+  }
+  // the last product on the owned rows: h = L t_1 - V x, out = base + coef (-i) h
+  const CplxAoS<T>& last = (D - 1) % 2 ? TA : TB;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + j * B;
+    if (i < st.nNL) {
+      T ar = T(0), ai = T(0);
+      st.template lsum_w<KMAX>(st.wd[j], last, j, tv[j], ar, ai);
+      const int32_t r = st.rr[j];
+      const T hr = ar - st.vv[j] * xv[j].x;
+      const T hi = ai - st.vv[j] * xv[j].y;
+      const C b = base[r];
+      C o;
+      o.x = b.x + coef * hi;
+      o.y = b.y - coef * hr;
+      out[r] = o;
+      if (s_out) s_out[r] = nl_int(d, o.x * o.x + o.y * o.y, st.ww[j], tau_s);
+    }
+  }
+}
+
 // ---- device-coherent access between workgroups of one launch ----
 // Device-coherent (agent scope) element access for state exchanged between
 // workgroups of one persistent launch, which may run on different XCDs.
@@ -3945,6 +4026,23 @@ void launch_unsplit(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi
 }
 
 template <typename T>
+void launch_hstage(const DevOps<T>& d, const TileOps<T>& tl, const void* x, const void* base, void* out, double coef,
+                   double p3, double p4, void* s_out, double tau_s, int block, hipStream_t st) {
+  const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
+  const size_t shmem = size_t(tl.max_slots) * 3 * sizeof(typename CT<T>::C);
+  const int J = (tl.max_compute + block - 1) / block;
+#define DECBPM_HS(KM, JJ)                                                                                        \
+  hipLaunchKernelGGL((k_hstage<T, KM, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, x),             \
+                     DECBPM_C(T, base), DECBPM_M(T, out), T(coef), T(p3), T(p4), static_cast<T*>(s_out), T(tau_s))
+  if (kmax_of(d.wmax) == 8) {
+    if (J <= 1) DECBPM_HS(8, 1); else DECBPM_HS(8, 2);
+  } else {
+    if (J <= 1) DECBPM_HS(12, 1); else DECBPM_HS(12, 2);
+  }
+#undef DECBPM_HS
+}
+
+template <typename T>
 void launch_step_b4(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, double h,
                     double tau, double gamma, int block, hipStream_t st, const int32_t* out_perm, int* flag) {
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
@@ -4347,6 +4445,8 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                   int, hipStream_t, const int32_t*, int*);                                       \
   template void launch_unsplit<T>(const DevOps<T>&, const TileOps<T>&, const void*, void*, double, double, int,    \
                                   hipStream_t);                                                                  \
+  template void launch_hstage<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, void*, double,    \
+                                 double, double, void*, double, int, hipStream_t);                               \
   template void launch_lapc<T>(const DevOps<T>&, const void*, const void*, double, double, void*, int,         \
                                hipStream_t);                                                                     \
   template void launch_dp5<T>(const DevOps<T>&, const TileOps<T>&, void*, void*, Dp5Ctl*, double*, uint32_t*,     \

@@ -213,6 +213,13 @@ void launch_kerr_fields(const DevOps<T>& d, const TileOps<T>& tl, const void* in
 template <typename T>
 void launch_kerr_tile(const DevOps<T>& d, const TileOps<T>& tl, const void* src, const int32_t* perm, void* dst,
                       double tau, double gamma, int block, hipStream_t st);
+// One RK4 stage of the operator sum with terms up to p4 L^4 on tiles of D
+// halo rings (D = 4 with p4, else 3): out = base + coef (-i)(sum_n p_n L^n x
+// - V x) on the owned rows (p1 and p2 = beta4 from d), by Horner in LDS; with
+// s_out also the Kerr substep's integral of |out|^2 over tau_s.
+template <typename T>
+void launch_hstage(const DevOps<T>& d, const TileOps<T>& tl, const void* x, const void* base, void* out, double coef,
+                   double p3, double p4, void* s_out, double tau_s, int block, hipStream_t st);
 // One step of classical RK4 on the whole right-hand side (the Kerr term and
 // the absorber inside every stage) on the five-ring step tiles (four rings are
 // used: one per stage).

@@ -562,16 +562,22 @@ def test_pml_absorbs_on_the_gpu():
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("response,param,p3,p4", [("kerr", 0.0, -4e-3, 1e-3), ("saturable", 0.8, 2e-3, 0.0),
                                                    ("cubic_quintic", 0.25, 2e-3, 0.0)])
-def test_general_operator_sum_and_responses_match_oracle(dtype, response, param, p3, p4):
-    """Eq. 1 in full on the five-kernel path: terms up to p4 L^4 (Horner gathers) with the
-    Kerr, saturable and cubic-quintic responses (closed-form flow integrals), against the
-    oracle's split scheme on the step-index replica (20k vertices, with absorber), plus
-    the Kerr substep and the linear step alone."""
+@pytest.mark.parametrize("stage_tiles", ["1", "0"])
+def test_general_operator_sum_and_responses_match_oracle(dtype, response, param, p3, p4, stage_tiles,
+                                                         monkeypatch):
+    """Eq. 1 in full: terms up to p4 L^4 with the Kerr, saturable and cubic-quintic
+    responses (closed-form flow integrals), on the five-kernel path whose RK4 stages run
+    as one tile kernel each (the Horner chain of the operator sum in LDS) or, with
+    DEC_BPM_GEN_TILES=0, as chains of gather kernels; against the oracle's split scheme
+    on the step-index replica (20k vertices, with absorber), plus the Kerr substep and
+    the linear step alone."""
     w = case("step_index", n_vert=20000, n_steps=10)
     kw = dict(p3=p3, p4=p4, nl_kind=response, nl_param=param)
     ops = dec.assemble(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, p1=w.p1, beta4=2e-3, **kw)
+    monkeypatch.setenv("DEC_BPM_GEN_TILES", stage_tiles)
     m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=dtype, p1=w.p1, beta4=2e-3, p3=p3, p4=p4,
                  response=response, response_param=param)
+    monkeypatch.delenv("DEC_BPM_GEN_TILES")
     assert m.tuning["fused"] == 0
     dz = 0.9 * 2.5 / m.spectral_radius()
     u0 = 1.5 * w.u0
