@@ -234,7 +234,10 @@ int dec_bpm_linear_step(dec_bpm_t h, void* field, double dz, void* stream);
  * (caller order).  gamma is the Kerr coefficient (Eq. 1 normalised, q_NL).
  * n_steps == 0 is a no-op.  Errors: EINVAL, EUNSTABLE, EHIP, ENODEVICE.
  * NaN/Inf in the result are flagged on the device and reported by
- * dec_bpm_check_finite.
+ * dec_bpm_check_finite.  On a stream being captured into a HIP graph the
+ * call launches one kernel per step (no persistent launch, no graph of its
+ * own): the persistent launch's neighbour flags take values that grow from
+ * call to call, which a replayed graph would not follow.
  */
 int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream);
 
@@ -253,7 +256,9 @@ int dec_bpm_propagate(dec_bpm_t h, void* field, double dz, int64_t n_steps, doub
  * device shares that device's array, which keeps the last call's contents:
  * calls that overlap on one device (other streams, other threads, other
  * handles) race and must be serialised by the caller.  The flags are cleared
- * by a kernel at each call.  Other errors as dec_bpm_propagate.
+ * by a kernel at each call, so the call may be captured into a HIP graph
+ * (persistent launch included) and the graph replayed.  Other errors as
+ * dec_bpm_propagate.
  */
 int dec_bpm_propagate_noalloc(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma, void* stream);
 

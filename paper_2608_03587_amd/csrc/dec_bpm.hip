@@ -1189,23 +1189,30 @@ template <typename T>
 static hipError_t run_persist(Engine& E, const TileOps<T>& tl, void* b0, void* b1, int32_t* flags, int32_t n,
                               double dz, double gamma, hipStream_t st, int body, const PersistIO& io) {
   const DevOps<T> d = E.ops<T>();
+  auto launch = [&](bool coop) {
+    return launch_persist<T>(d, tl, E.nb_ptr, E.nb_list, b0, b1, flags, E.flag, n, E.spin_limit, dz, gamma,
+                             E.pblock(), st, body, io, coop);
+  };
+  if (E.coop) return launch(true);
+  // a stream being captured into a graph keeps the graph's order: events
+  // recorded outside the capture cannot be waited on inside it
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
   int dev = 0;
-  if (!E.coop && hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64 && g_porder[dev].ev) {
-    PersistOrder& o = g_porder[dev];
-    std::lock_guard<std::mutex> lock(o.mu);
-    if (o.has && o.last != st) {
-      const hipError_t w = hipStreamWaitEvent(st, o.ev, 0);
-      if (w != hipSuccess) return w;
-    }
-    const hipError_t e = launch_persist<T>(d, tl, E.nb_ptr, E.nb_list, b0, b1, flags, E.flag, n, E.spin_limit, dz,
-                                           gamma, E.pblock(), st, body, io, false);
-    if (e != hipSuccess) return e;
-    o.last = st;
-    o.has = true;
-    return hipEventRecord(o.ev, st);
+  if (cap != hipStreamCaptureStatusNone || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 ||
+      !g_porder[dev].ev)
+    return launch(false);
+  PersistOrder& o = g_porder[dev];
+  std::lock_guard<std::mutex> lock(o.mu);
+  if (o.has && o.last != st) {
+    const hipError_t w = hipStreamWaitEvent(st, o.ev, 0);
+    if (w != hipSuccess) return w;
   }
-  return launch_persist<T>(d, tl, E.nb_ptr, E.nb_list, b0, b1, flags, E.flag, n, E.spin_limit, dz, gamma, E.pblock(),
-                           st, body, io, true);
+  const hipError_t e = launch(false);
+  if (e != hipSuccess) return e;
+  o.last = st;
+  o.has = true;
+  return hipEventRecord(o.ev, st);
 }
 
 // Flag base of a persistent launch of n steps (it publishes at most
@@ -1222,8 +1229,15 @@ static PersistIO persist_io(Engine& E, int64_t n, hipStream_t st) {
   return io;
 }
 
+// Whether work on the stream is being captured into a graph.
+static bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
+}
+
 // Middle steps (merged NL(dz)) through graph replays, then the remainder
-// eagerly; returns the buffer holding the state.
+// eagerly (all eagerly on a stream being captured: the caller's graph holds
+// the launches); returns the buffer holding the state.
 template <typename T>
 static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st, int mode = -1) {
   const DevOps<T> d = E.ops<T>();
@@ -1256,7 +1270,7 @@ static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipSt
   }
   const int gs = graph_steps(E, mode);
   int64_t done = 0;
-  if (E.spg > 1 && count >= gs) {
+  if (E.spg > 1 && count >= gs && !capturing(st)) {
     hipGraphExec_t ex = get_graph<T>(E, dz, gamma, mode);
     for (; done + gs <= count; done += gs) HIP_OK(hipGraphLaunch(ex, st));
   }
@@ -1285,7 +1299,11 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
   if (n == 0) return;
   const DevOps<T> d = E.ops<T>();
   const int B = E.block;
-  const int mode = mode_of<T>(E);
+  int mode = mode_of<T>(E);
+  // on a stream being captured into a graph, one kernel per step instead of the
+  // persistent launch: its neighbour flags take values that grow from call to
+  // call, which a replayed graph would not follow
+  if (mode == 3 && capturing(st)) mode = 2;
   // one-field step tiles read the caller's field and write the result through the permutation
   const bool io_tiles = mode >= 2 && E.F == 1;
   if (!io_tiles && mode != 6) field_in<T>(E, d, field, E.psi, st);
@@ -1295,7 +1313,7 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     const TileOps<T> tf = E.sfl.template ops<T>();
     launch_bperm<T>(d, E.bcbase, E.bfcount, field, E.psi2, false, nullptr, E.block, st, true);
     launch_kerr_fields<T>(d, tf, E.psi2, E.psi, 0.5 * dz, gamma, E.fblock(), st);
-    void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
+    void* cur = run_middle<T>(E, n - 1, dz, gamma, st, mode);
     void* nxt = cur == E.psi ? E.psi2 : E.psi;
     launch_step_fields<T>(d, tf, cur, nxt, dz, 0.5 * dz, gamma, E.fblock(), st);
     launch_bperm<T>(d, E.bcbase, E.bfcount, nxt, field, true, E.flag, E.block, st, true);
@@ -1303,7 +1321,7 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     const TileOps<T> tl = E.tiles<T>();
     // NL(dz/2) + stage 1: state -> psi2, y1 -> ya
     launch_fused<T>(d, tl, FUSED_NL_S1, nullptr, E.psi, E.psi2, E.ya, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
-    void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
+    void* cur = run_middle<T>(E, n - 1, dz, gamma, st, mode);
     void* nxt = cur == E.psi ? E.psi2 : E.psi;
     launch_fused<T>(d, tl, FUSED_S2_S3, E.ya, cur, nullptr, E.yb, nullptr, dz, dz, gamma, E.tblock(), st);
     launch_fused<T>(d, tl, FUSED_S4_NL, E.yb, cur, nxt, nullptr, nullptr, dz, 0.5 * dz, gamma, E.tblock(), st);
@@ -1324,7 +1342,7 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
     // per-row arithmetic as the persistent launch), n-1 merged steps, then
     // LIN(dz) + NL(dz/2) straight into the caller's field
     launch_kerr_tile<T>(d, E.stp.template ops<T>(), field, E.perm, E.psi, 0.5 * dz, gamma, E.sblock(), st);
-    void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
+    void* cur = run_middle<T>(E, n - 1, dz, gamma, st, mode);
     if (mode == 4)
       launch_step_b4<T>(d, E.stp.template ops<T>(), cur, field, dz, 0.5 * dz, gamma, E.sblock(), st, E.perm, E.flag);
     else
@@ -1332,14 +1350,14 @@ static void propagate_t(Engine& E, void* field, double dz, int64_t n, double gam
   } else if (mode >= 2) {  // batched step tiles
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
     launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
-    void* cur = run_middle<T>(E, n - 1, dz, gamma, st);
+    void* cur = run_middle<T>(E, n - 1, dz, gamma, st, mode);
     void* nxt = cur == E.psi ? E.psi2 : E.psi;
     launch_step<T>(d, E.stp.template ops<T>(), cur, nxt, dz, 0.5 * dz, gamma, E.sblock(), st);
     field_out<T>(E, d, nxt, field, st);
   } else {
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
     do_kerr<T>(E, d, E.psi, E.psi, E.s, 0.5 * dz, gamma, st);
-    run_middle<T>(E, n - 1, dz, gamma, st);
+    run_middle<T>(E, n - 1, dz, gamma, st, mode);
     z_step<T>(E, d, dz, gamma, 0.5 * dz, st);
     field_out<T>(E, d, E.psi, field, st);
   }

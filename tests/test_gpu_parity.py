@@ -1207,6 +1207,49 @@ def test_persistent_launches_on_two_streams_and_cooperative(monkeypatch):
 
 
 @pytest.mark.gpu
+def test_propagate_captured_in_a_graph():
+    """dec_bpm_propagate captured into a HIP graph (a handle tuned for the persistent
+    launch runs one kernel per step while its stream is being captured: the persistent
+    flags grow from call to call, which a replay would not follow) and
+    dec_bpm_propagate_noalloc (the persistent launch, its flags cleared by a kernel in
+    every call): each graph replayed three times, with eager propagation and
+    synchronisation between the replays, and every replay equal to the eager result."""
+    w = case("step_index", n_vert=20000, n_steps=10)
+    m = lib_mesh(w, "c64")
+    m.tuning = {"fused": 3}
+    assert m.time_kernels(w.dz, w.gamma, reps=10)["persist"]["ms"] > 0
+    u = dev(w.u0, "c64")
+    n = 9
+    ref = u.clone()
+    m.propagate(ref, w.dz, n, w.gamma)
+    ref = host(ref)
+    for call in (m.propagate, m.propagate_noalloc):
+        f = u.clone()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):  # an eager call on the capture stream first
+            call(f, w.dz, n, w.gamma, stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(f), ref)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            call(f, w.dz, n, w.gamma, stream=s)
+        for rep in range(3):
+            f.copy_(u)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(host(f), ref), (call.__name__, rep)
+            h = u.clone()
+            m.propagate(h, w.dz, n, w.gamma)  # eager work between the replays
+            torch.cuda.synchronize()
+            assert np.array_equal(host(h), ref)
+        m.check_finite()
+        del g
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_results_do_not_depend_on_the_tiling(dtype, monkeypatch):
     """Cutting the mesh into tiles of other row counts (not powers of two, so
