@@ -1242,9 +1242,12 @@ template <typename T>
 static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipStream_t st, int mode = -1) {
   const DevOps<T> d = E.ops<T>();
   if (mode < 0) mode = mode_of<T>(E);
+  // a captured graph takes one kernel per step: the persistent flags grow from call to call
+  const bool cap = capturing(st);
+  if (mode == 3 && cap) mode = 2;
   // unsplit RK4 on the resident tiles; not on complex128's own persistent tiles, where the
   // unsplit body's register spills make it slower than one tile kernel per step
-  if (mode == 5 && E.fused == 3 && !E.pst_own && persist_fits<T>(E, 1)) {
+  if (mode == 5 && E.fused == 3 && !E.pst_own && !cap && persist_fits<T>(E, 1)) {
     const int64_t chunk = int64_t(1) << 30;
     for (int64_t done = 0; done < count; done += chunk) {
       const int32_t k = int32_t(std::min(chunk, count - done));
@@ -1270,7 +1273,7 @@ static void* run_middle(Engine& E, int64_t count, double dz, double gamma, hipSt
   }
   const int gs = graph_steps(E, mode);
   int64_t done = 0;
-  if (E.spg > 1 && count >= gs && !capturing(st)) {
+  if (E.spg > 1 && count >= gs && !cap) {
     hipGraphExec_t ex = get_graph<T>(E, dz, gamma, mode);
     for (; done + gs <= count; done += gs) HIP_OK(hipGraphLaunch(ex, st));
   }

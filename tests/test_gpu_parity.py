@@ -1208,22 +1208,33 @@ def test_persistent_launches_on_two_streams_and_cooperative(monkeypatch):
 
 @pytest.mark.gpu
 def test_propagate_captured_in_a_graph():
-    """dec_bpm_propagate captured into a HIP graph (a handle tuned for the persistent
-    launch runs one kernel per step while its stream is being captured: the persistent
-    flags grow from call to call, which a replay would not follow) and
-    dec_bpm_propagate_noalloc (the persistent launch, its flags cleared by a kernel in
-    every call): each graph replayed three times, with eager propagation and
-    synchronisation between the replays, and every replay equal to the eager result."""
+    """dec_bpm_propagate and dec_bpm_propagate_unsplit captured into a HIP graph (a handle
+    tuned for the persistent launch runs one kernel per step while its stream is being
+    captured: the persistent flags grow from call to call, which a replay would not
+    follow) and dec_bpm_propagate_noalloc (the persistent launch, its flags cleared by a
+    kernel in every call): each graph replayed three times, with eager calls and
+    synchronisation between the replays, and every replay equal to the eager result
+    (the unsplit integrator on one kernel per step, whose eager calls replay the
+    library's own graphs)."""
     w = case("step_index", n_vert=20000, n_steps=10)
     m = lib_mesh(w, "c64")
     m.tuning = {"fused": 3}
     assert m.time_kernels(w.dz, w.gamma, reps=10)["persist"]["ms"] > 0
     u = dev(w.u0, "c64")
     n = 9
-    ref = u.clone()
-    m.propagate(ref, w.dz, n, w.gamma)
-    ref = host(ref)
-    for call in (m.propagate, m.propagate_noalloc):
+    # the unsplit integrator on one kernel per step (fused = 2): its persistent body and
+    # its per-step kernel agree to rounding only
+    fused = {"propagate": 3, "propagate_noalloc": 3, "propagate_unsplit": 2}
+    refs = {}
+    for call in (m.propagate, m.propagate_unsplit):
+        m.tuning = {"fused": fused[call.__name__]}
+        r = u.clone()
+        call(r, w.dz, n, w.gamma)
+        refs[call.__name__] = host(r)
+    refs["propagate_noalloc"] = refs["propagate"]
+    for call in (m.propagate, m.propagate_noalloc, m.propagate_unsplit):
+        m.tuning = {"fused": fused[call.__name__]}
+        ref = refs[call.__name__]
         f = u.clone()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -1242,7 +1253,7 @@ def test_propagate_captured_in_a_graph():
             torch.cuda.synchronize()
             assert np.array_equal(host(f), ref), (call.__name__, rep)
             h = u.clone()
-            m.propagate(h, w.dz, n, w.gamma)  # eager work between the replays
+            call(h, w.dz, n, w.gamma)  # eager work between the replays
             torch.cuda.synchronize()
             assert np.array_equal(host(h), ref)
         m.check_finite()
