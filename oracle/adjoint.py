@@ -10,7 +10,8 @@ means ``dJ = sum_p Re(conj(g_p) dpsi_p)``.
 
 * Objective ``J = |c|^2`` with ``c = sum_p H0_p conj(t_p) psi_p(z_L)``, whose
   gradient is ``g = 2 c H0 t``.
-* Linear map ``y = A x`` (complex matrix): ``g_x = A^H g_y``.  For one RK4 stage
+* Linear map ``y = A x`` (complex matrix): ``g_x = A^H g_y`` (with the complex L of
+  a perfectly matched layer, ``A^H`` conjugates as well as transposes).  For one RK4 stage
   ``k = A z`` with ``A = -i (H_lin - diag(dn) + ...)``, ``dk/d dn_p = i z_p e_p``,
   so ``dJ/d dn_p += Re(conj(g_k,p) i z_p)``.
 * Kerr/absorber flow ``psi' = E psi`` with ``E = e^{-w tau} e^{i gamma Theta}``,
@@ -56,8 +57,8 @@ def lin_rk4_adjoint(psi_in, g_out, h, ops):
     def A(x):
         return -1j * ops.apply_H(x)
 
-    def AH(x):  # (-i H)^H = i H^T
-        return 1j * ops.apply_HT(x)
+    def AH(x):  # (-i H)^H = i H^H, H^H x = conj(H^T conj(x)) (H^T for a real L)
+        return 1j * np.conj(ops.apply_HT(np.conj(x)))
 
     # forward stage inputs z_j (k_j = A z_j)
     z1 = psi_in
@@ -100,11 +101,13 @@ def gradients(psi0, target, ops, dz, n_steps, gamma):
 
     ``g_dn`` is the gradient with respect to a per-vertex perturbation added to
     the vertex potential ``v`` (``ops`` already holds the current ``v``).
-    Written for the Kerr response and H_lin = p1 L + beta4 L^2 - diag(v)."""
+    Written for the Kerr response and H_lin = p1 L + beta4 L^2 - diag(v), with a real
+    L or the complex-stretched L of a perfectly matched layer (the objective, v and M
+    keep the real H0)."""
     from .stepper import lin_rk4, nl_flow
 
-    if ops.nl_kind != "kerr" or ops.p3 != 0.0 or ops.p4 != 0.0 or np.iscomplexobj(ops.L.data):
-        raise NotImplementedError("the adjoint covers the Kerr response, terms up to L^2 and a real L")
+    if ops.nl_kind != "kerr" or ops.p3 != 0.0 or ops.p4 != 0.0:
+        raise NotImplementedError("the adjoint covers the Kerr response and terms up to L^2")
 
     h = dz
     states = []  # (x0, x1, x2) per step: step input, after NL(h/2), after LIN

@@ -73,6 +73,50 @@ def test_full_gradient_matches_central_differences(beta4):
         assert abs(fd - float(g_dn @ e)) < 1e-6 * abs(fd), (fd, float(g_dn @ e))
 
 
+def _pml_ops(seed):
+    mesh = M.disk_mesh(4.0, 0.5, seed)
+    V = F.step_index_tri(mesh.xy, mesh.tri, 1.5, 0.8)
+    pml = (2.5, 4.0, 1.5)
+    return mesh, V, pml, dec.assemble(mesh.xy, mesh.tri, index_tri=V, pml=pml)
+
+
+def test_pml_linear_step_dot_product_identity():
+    """With the complex-stretched L of a perfectly matched layer the adjoint of the RK4
+    step must conjugate as well as transpose: a transposing-only adjoint fails this."""
+    mesh, V, pml, ops = _pml_ops(5)
+    assert np.iscomplexobj(ops.L.data)
+    rng = np.random.default_rng(5)
+    x, y = _rand(rng, ops.n), _rand(rng, ops.n)
+    h = 0.01
+    lhs = _rdot(y, S.lin_rk4(x, h, ops))
+    g, _ = A.lin_rk4_adjoint(x, y, h, ops)
+    assert abs(lhs - _rdot(g, x)) < 1e-12 * abs(lhs)
+
+
+def test_pml_full_gradient_matches_central_differences():
+    mesh, V, pml, ops = _pml_ops(6)
+    rng = np.random.default_rng(6)
+    u0 = F.gaussian(mesh.xy, 1.0, 1.0) * np.exp(2j * mesh.xy[:, 0])  # an outgoing beam reaches the layer
+    target = F.gaussian(mesh.xy, 1.0, 0.9, centre=(0.4, 0.0)) * np.exp(0.7j)
+    dz, n, gamma = 2e-3, 12, 1.0
+    J, g_u, g_dn = A.gradients(u0, target, ops, dz, n, gamma)
+
+    def run(u, dv):
+        o = dec.assemble(mesh.xy, mesh.tri, index_tri=V, pml=pml, dn=dv)
+        return A.objective(S.propagate(u, o, dz, n, gamma), target, o)
+
+    zero = np.zeros(ops.n)
+    assert abs(run(u0, zero) - J) < 1e-14 * J
+    eps = 1e-5
+    for k in range(3):
+        d = _rand(rng, ops.n)
+        fd = (run(u0 + eps * d, zero) - run(u0 - eps * d, zero)) / (2 * eps)
+        assert abs(fd - _rdot(g_u, d)) < 1e-6 * abs(fd), (fd, _rdot(g_u, d))
+        e = rng.normal(size=ops.n)
+        fd = (run(u0, 1e-4 * e) - run(u0, -1e-4 * e)) / 2e-4
+        assert abs(fd - float(g_dn @ e)) < 1e-6 * abs(fd), (fd, float(g_dn @ e))
+
+
 def test_objective_gradient_convention():
     """g = dJ/dRe + i dJ/dIm (checked on J = |<t, psi>|^2 by real finite differences)."""
     mesh, ops, rng = _ops(4)
