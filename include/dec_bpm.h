@@ -94,11 +94,12 @@ typedef struct {
    * neighbours; the handle then runs dec_bpm_propagate and
    * dec_bpm_propagate_unsplit on the one-kernel step (fused = 2) or, in
    * complex64 when every tile fits at once, the persistent launch (fused = 3),
-   * dec_bpm_propagate_adaptive on its trial tiles with complex weights, and
-   * kerr_step/diagnostics (Hamiltonian NaN); the entry points whose kernels
-   * apply a real L (apply, linear_step, find_mode, checkpointed forward and
-   * adjoint, batches) return EINVAL.  The stability check uses the
-   * unstretched operator's spectral radius, which bounds the stretched one's. */
+   * dec_bpm_propagate_adaptive on its trial tiles with complex weights,
+   * kerr_step/diagnostics (Hamiltonian NaN), and the checkpointed forward
+   * and adjoint on the one-kernel step tiles; the entry points whose kernels
+   * apply a real L (apply, linear_step, find_mode, batches) return EINVAL.
+   * The stability check uses the unstretched operator's spectral radius,
+   * which bounds the stretched one's. */
   double pml_r0, pml_r1, pml_sigma;
   /* Eq. 1 in full: H_lin = p1 L + beta4 L^2 + p3 L^3 + p4 L^4 - diag(v), and
    * the Kerr response N(I) in place of I = |psi|^2 (DEC_BPM_N_KERR, default;
@@ -370,7 +371,11 @@ int dec_bpm_overlap(dec_bpm_t h, const void* a, const void* b, double* re, doubl
  * grad_field0 = dJ/dpsi(0) (complex, caller order) and, if grad_dn is not
  * NULL, grad_dn = dJ/d(dn) (double[n_vert], caller order).  Each segment
  * between checkpoints is recomputed forward, storing its stage vectors, then
- * swept backward.  Errors: EINVAL, EWORKSPACE, EUNSTABLE, EHIP.
+ * swept backward.  With a perfectly matched layer (complex L~ = H0~^{-1} K~)
+ * the reverse sweep applies conj(L~) in the variables conj(H0~)^{-1} g (the
+ * Kerr adjoint and the objective keep the real H0); both calls then need the
+ * one-kernel step tiles, and a handle without them returns EINVAL.
+ * Errors: EINVAL, EWORKSPACE, EUNSTABLE, EHIP.
  */
 int dec_bpm_workspace_size(dec_bpm_t h, int64_t n_steps, int64_t every, size_t* bytes);
 int dec_bpm_forward_checkpointed(dec_bpm_t h, void* field, double dz, int64_t n_steps, double gamma,

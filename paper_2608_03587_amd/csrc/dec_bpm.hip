@@ -110,6 +110,7 @@ struct Engine {
   void* lw = nullptr;
   void* mw = nullptr;
   void* mdiag = nullptr;
+  void* sig = nullptr;  // PML: sigma_p = H0~_p / H0_p (complex, device order), else null
   void* v = nullptr;
   void* v0 = nullptr;
   void* w = nullptr;
@@ -801,6 +802,8 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   // a perfectly matched layer makes L complex: c_pq = -K~_pq / H0~_p
   const bool pml = meshes.size() == 1 && !meshes[0]->kp_re.empty();
   E.pml = pml;
+  std::vector<T> sig;  // PML: sigma_p = H0~_p / H0_p per row (device order), interleaved complex
+  if (pml) sig.resize(size_t(2) * n);
   acol.reserve(E.nnz_off);
   alw.reserve(E.nnz_off);
   amw.reserve(E.nnz_off);
@@ -813,6 +816,10 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
     perm[r] = int32_t(off + p);
     h0[r] = hp;
     h0c[off + p] = hp;
+    if (pml) {
+      sig[2 * r] = T(a.h0p_re[p] / hp);
+      sig[2 * r + 1] = T(a.h0p_im[p] / hp);
+    }
     v0[r] = T(a.v[p]);
     w[r] = T(a.w[p]);
     // neighbours sorted by device column
@@ -871,6 +878,7 @@ static void build_engine_t(Engine& E, const std::vector<const Assembled*>& meshe
   upload(E, E.lw, lw);
   if (any_dec) upload(E, E.mw, mw);
   upload(E, E.mdiag, mdiag);
+  if (pml) upload(E, E.sig, sig);
   upload(E, E.v0, v0);
   upload(E, E.v, v0);
   upload(E, E.w, w);
@@ -1156,6 +1164,14 @@ static hipGraphExec_t get_graph(Engine& E, double dz, double gamma, int mode) {
 // written for the Kerr response and terms up to L^2 refuse the general ones.
 static void no_pml(const Engine& E, const char* what) {
   if (E.pml) fail(DEC_BPM_EINVAL, std::string(what) + ": not available on a handle with a PML (complex L)");
+}
+
+// With a PML the adjoint runs on the one-kernel step tiles only (their
+// complex-weight instances); a handle without them refuses it.
+static void pml_adjoint_ok(const Engine& E, const char* what) {
+  if (!E.pml) return;
+  const bool ok = E.dtype == DEC_BPM_C64 ? use_step_adjoint<float>(E) : use_step_adjoint<double>(E);
+  if (!ok) fail(DEC_BPM_EINVAL, std::string(what) + ": a PML needs the one-kernel step tiles, which this mesh lacks");
 }
 static void no_general(const Engine& E, const char* what) {
   if (E.general())
@@ -1911,7 +1927,7 @@ static void adjoint_step_t(Engine& E, const void* grad_out, double dz, int64_t n
                          gamma, SB, st);
     for (int64_t j = m; j >= 1; --j) {
       launch_step_adj<T>(d, sp, lam, A(j), Bv(j), Y(j, 2), Y(j, 1), Y(j, 0), A(j - 1), other, gdn, dz,
-                         (n0 + j < n) ? dz : 0.5 * dz, gamma, SB, st);
+                         (n0 + j < n) ? dz : 0.5 * dz, gamma, E.sig, SB, st);
       std::swap(lam, other);
     }
   }
@@ -2800,8 +2816,8 @@ int dec_bpm_forward_checkpointed(dec_bpm_t h, void* field, double dz, int64_t n_
   ABI_TRY
   need(h);
   decbpm::no_general(h->E, "dec_bpm_forward_checkpointed");
-  decbpm::no_pml(h->E, "dec_bpm_forward_checkpointed");
   Engine& E = h->E;
+  decbpm::pml_adjoint_ok(E, "dec_bpm_forward_checkpointed");
   decbpm::check_prop_args(E, field, dz, n_steps, gamma);
   if (every < 0) fail(DEC_BPM_EINVAL, "every must be >= 0");
   const auto L = decbpm::ws_layout(E, n_steps, every);
@@ -2833,8 +2849,8 @@ int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_step
   ABI_TRY
   need(h);
   decbpm::no_general(h->E, "dec_bpm_adjoint");
-  decbpm::no_pml(h->E, "dec_bpm_adjoint");
   Engine& E = h->E;
+  decbpm::pml_adjoint_ok(E, "dec_bpm_adjoint");
   decbpm::check_prop_args(E, grad_field0, dz, n_steps, gamma);
   if (!grad_out) fail(DEC_BPM_EINVAL, "grad_out is NULL");
   const auto L = decbpm::ws_layout(E, n_steps, every);

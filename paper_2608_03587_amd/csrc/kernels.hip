@@ -1284,6 +1284,17 @@ struct StepTile {
     }
   }
 
+  // Conjugates the complex L weights held in registers (CL): the adjoint of a
+  // complex-stretched L in the conj(H0~)^{-1} g variables applies conj(L).
+  __device__ void conj_l() {
+    if constexpr (CL) {
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) cli[j][k] = -cli[j][k];
+    }
+  }
+
   // M weight k of register slot j (an owned slot when LM)
   __device__ T mw(int j, int k) const {
     if constexpr (LM)
@@ -2921,7 +2932,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_b4(DevOps<T> 
 
 // The one-kernel step that also records, for the adjoint's forward recompute,
 // the stage vectors y1, y2, y3 and the state before the Kerr substep.
-template <typename T, int KMAX, bool DEC, int J>
+template <typename T, int KMAX, bool DEC, int J, bool CL = false>
 __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_rec(DevOps<T> d, TileOps<T> tl,
                                                    const typename CT<T>::C* __restrict__ in_psi,
                                                    typename CT<T>::C* __restrict__ out_psi,
@@ -2937,7 +2948,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_rec(DevOps<T>
   C* base = reinterpret_cast<C*>(smem);
   const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS};
   T* S = reinterpret_cast<T*>(base + 3 * MS);
-  StepTile<T, KMAX, DEC, J> st;
+  StepTile<T, KMAX, DEC, J, CL> st;
   st.init(d, tl, tile, false, nullptr, true);
   for (int i = threadIdx.x; i < st.nLoad; i += blockDim.x) P.put(i, in_psi[st.slot_row(i)]);
   __syncthreads();
@@ -2957,8 +2968,9 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_rec(DevOps<T>
 // H0 Re(i [h conj(lam_b) y3 + h/2 conj(u1) y2 + h/3 conj(u2) y1 + h/4 conj(u3) a0]).
 // Inputs: lam' (adjoint of the state a after the step), a, the state b before
 // the Kerr substep, the step's y1..y3 and its input state a0.  lam_out must not
-// alias lam_in (other tiles read lam_in's halo).
-template <typename T, int KMAX, bool DEC, int J>
+// alias lam_in (other tiles read lam_in's halo).  CL (complex L weights of a
+// perfectly matched layer) also takes sig = H0~ / H0 per row (device order).
+template <typename T, int KMAX, bool DEC, int J, bool CL = false>
 __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T> d, TileOps<T> tl,
                                                    const typename CT<T>::C* __restrict__ lam_in,
                                                    const typename CT<T>::C* __restrict__ fa,
@@ -2968,7 +2980,8 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
                                                    const typename CT<T>::C* __restrict__ y1,
                                                    const typename CT<T>::C* __restrict__ fa0,
                                                    typename CT<T>::C* __restrict__ lam_out,
-                                                   double* __restrict__ gdn, T h, T tau, T gamma) {
+                                                   double* __restrict__ gdn, T h, T tau, T gamma,
+                                                   const typename CT<T>::C* __restrict__ sig) {
   using C = typename CT<T>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t tile = logical_block(d.xcd_remap);
@@ -2978,8 +2991,26 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
   C* LB = reinterpret_cast<C*>(smem);  // lam' -> lam_b -> u2
   C* U = LB + MS;                      // b -> u1 -> u3
   C* SM = U + MS;                      // (|b|^2 phi, mu) per slot
-  StepTile<T, KMAX, DEC, J> st;
+  StepTile<T, KMAX, DEC, J, CL> st;
   st.init(d, tl, tile);
+  st.conj_l();
+  // CL (a perfectly matched layer, L~ = H0~^{-1} K~): the Kerr adjoint runs in
+  // the lam = H0^{-1} g variables (M and the objective keep the real H0), the
+  // linear chain in lam~ = conj(H0~)^{-1} g = lam / conj(sigma), where it
+  // applies conj(L~); sigma = H0~ / H0 per row (1 outside the layer)
+  auto to_tilde = [&](const C& l, const C& sg) {  // l / conj(sg)
+    const T n2 = sg.x * sg.x + sg.y * sg.y;
+    C o;
+    o.x = (l.x * sg.x - l.y * sg.y) / n2;
+    o.y = (l.y * sg.x + l.x * sg.y) / n2;
+    return o;
+  };
+  auto from_tilde = [&](const C& l, const C& sg) {  // conj(sg) l
+    C o;
+    o.x = sg.x * l.x + sg.y * l.y;
+    o.y = sg.x * l.y - sg.y * l.x;
+    return o;
+  };
   int cr[5];  // slots in rings 0..k
 #pragma unroll
   for (int k = 0; k < 5; ++k) cr[k] = st.hd[k];
@@ -3008,16 +3039,23 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
       C o;
       o.x = damp * (cs * l.x + sn * l.y) + two_phi_mm * bb.x;
       o.y = damp * (cs * l.y - sn * l.x) + two_phi_mm * bb.y;
+      if constexpr (CL) o = to_tilde(o, sig[r]);
       LB[i] = o;
     }
   }
   // owned rows: forward vectors and the gradient accumulator
   C fy3[J], fy2[J], fy1[J], fa0r[J];
+  C sg[J];  // CL: sigma of the slot's row (rings 0..4)
   double h0[J], g0[J], gd[J];  // H0, gradient so far, this step's sum of Re(i conj(u) y) terms
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int i = threadIdx.x + j * B;
     h0[j] = g0[j] = gd[j] = 0.0;
+    if constexpr (CL) {
+      sg[j].x = T(1);
+      sg[j].y = T(0);
+      if (i < cr[4]) sg[j] = sig[st.rr[j]];
+    }
     if (i < cr[0]) {
       const int32_t r = st.rr[j];
       fy3[j] = y3[r];
@@ -3029,8 +3067,12 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
     }
   }
   __syncthreads();
-  // Re(i conj(u) y) = -(u.x y.y - u.y y.x)
-  auto rdn = [](const C& u, const C& y) { return -(double(u.x) * y.y - double(u.y) * y.x); };
+  // Re(i conj(u) y) = -(u.x y.y - u.y y.x), u taken back to the lam variables
+  auto rdn = [&](const C& ut, const C& y, int j) {
+    C u = ut;
+    if constexpr (CL) u = from_tilde(ut, sg[j]);
+    return -(double(u.x) * y.y - double(u.y) * y.x);
+  };
   C cur[J], acc[J];
   if constexpr (DEC) {
 #pragma unroll
@@ -3049,6 +3091,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
         C o;
         o.x = damp * (cs * l.x + sn * l.y) + two_phi_mm * p.x;
         o.y = damp * (cs * l.y - sn * l.x) + two_phi_mm * p.y;
+        if constexpr (CL) o = to_tilde(o, sg[j]);
         cur[j] = o;
         LB[i] = o;  // only this thread reads LB[i] and U[i] in this phase
       }
@@ -3068,7 +3111,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
       const C u1 = st.link(d, CplxAoS<T>{LB}, cur[j], j, -h);
       U[i] = u1;
       if (i < cr[0]) {
-        gd[j] += double(h) * rdn(cur[j], fy3[j]) + 0.5 * double(h) * rdn(u1, fy2[j]);
+        gd[j] += double(h) * rdn(cur[j], fy3[j], j) + 0.5 * double(h) * rdn(u1, fy2[j], j);
         acc[j].x = cur[j].x + u1.x;
         acc[j].y = cur[j].y + u1.y;
       }
@@ -3083,7 +3126,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
       const C u2 = st.link(d, CplxAoS<T>{U}, cur[j], j, T(-0.5) * h);
       LB[i] = u2;
       if (i < cr[0]) {
-        gd[j] += double(h) / 3.0 * rdn(u2, fy1[j]);
+        gd[j] += double(h) / 3.0 * rdn(u2, fy1[j], j);
         acc[j].x += u2.x;
         acc[j].y += u2.y;
       }
@@ -3098,7 +3141,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
       const C u3 = st.link(d, CplxAoS<T>{LB}, cur[j], j, -h / T(3));
       U[i] = u3;
       if (i < cr[0]) {
-        gd[j] += 0.25 * double(h) * rdn(u3, fa0r[j]);
+        gd[j] += 0.25 * double(h) * rdn(u3, fa0r[j], j);
         acc[j].x += u3.x;
         acc[j].y += u3.y;
       }
@@ -3114,6 +3157,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
       C l;
       l.x = acc[j].x + u4.x;
       l.y = acc[j].y + u4.y;
+      if constexpr (CL) l = from_tilde(l, sg[j]);
       lam_out[st.rr[j]] = l;
       gdn[st.rr[j]] = g0[j] + h0[j] * gd[j];
     }
@@ -3121,8 +3165,9 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
 }
 
 // ---- persistent z stepping on resident tiles ----
-// n_steps z steps in one launch, one workgroup per tile, all resident
-// (cooperative launch).  The operator rows stay in registers for the whole
+// n_steps z steps in one launch, one workgroup per tile, all resident (an
+// ordinary launch of a grid that fits, or a cooperative one).  The operator
+// rows stay in registers for the whole
 // launch; per step only the state crosses memory.  The state alternates
 // between buf0 (before even steps) and buf1.  Flags only grow: a tile
 // publishes flags[tile] = base + k once the state its step k - 1 produced is
@@ -3147,7 +3192,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
 // BODY 0: the merged split step; BODY 1: one unsplit classical RK4 step of the
 // whole right-hand side (the stage inputs and their |.|^2 double-buffered in
 // the same LDS; the owned state and its |.|^2 written back after the step).
-// CL: complex L weights (a perfectly matched layer), split-step body only.
+// CL: complex L weights (a perfectly matched layer), in complex64.
 template <typename T>
 struct PersistArgs {
   using C = typename CT<T>::C;
@@ -4091,12 +4136,15 @@ void launch_step_rec(const DevOps<T>& d, const TileOps<T>& tl, const void* in_ps
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
   const size_t shmem = size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
   const int J = (tl.max_compute + block - 1) / block;
-#define DECBPM_STEPR(KM, DEC, JJ)                                                                              \
-  hipLaunchKernelGGL((k_step_rec<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, in_psi), \
-                     DECBPM_M(T, out_psi), DECBPM_M(T, y1), DECBPM_M(T, y2), DECBPM_M(T, y3), DECBPM_M(T, b),   \
-                     T(h), T(tau), T(gamma))
+#define DECBPM_STEPRC(KM, DEC, JJ, CLX)                                                                           \
+  hipLaunchKernelGGL((k_step_rec<T, KM, DEC, JJ, CLX>), dim3(g), dim3(block), shmem, st, d, tl,                  \
+                     DECBPM_C(T, in_psi), DECBPM_M(T, out_psi), DECBPM_M(T, y1), DECBPM_M(T, y2), DECBPM_M(T, y3), \
+                     DECBPM_M(T, b), T(h), T(tau), T(gamma))
+#define DECBPM_STEPR(KM, DEC, JJ)                       \
+  if (tl.llwi) DECBPM_STEPRC(KM, DEC, JJ, true); \
+  else DECBPM_STEPRC(KM, DEC, JJ, false)
 #define DECBPM_STEPR_J(KM, DEC) \
-  if (J <= 1) DECBPM_STEPR(KM, DEC, 1); else DECBPM_STEPR(KM, DEC, 2);
+  if (J <= 1) { DECBPM_STEPR(KM, DEC, 1); } else { DECBPM_STEPR(KM, DEC, 2); }
   const bool dec = tl.lmw != nullptr;
   if (kmax_of(d.wmax) == 8) {
     if (dec) { DECBPM_STEPR_J(8, true) } else { DECBPM_STEPR_J(8, false) }
@@ -4105,21 +4153,26 @@ void launch_step_rec(const DevOps<T>& d, const TileOps<T>& tl, const void* in_ps
   }
 #undef DECBPM_STEPR_J
 #undef DECBPM_STEPR
+#undef DECBPM_STEPRC
 }
 
 template <typename T>
 void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_in, const void* fa, const void* fb,
                      const void* y3, const void* y2, const void* y1, const void* fa0, void* lam_out, double* gdn,
-                     double h, double tau, double gamma, int block, hipStream_t st) {
+                     double h, double tau, double gamma, const void* sig, int block, hipStream_t st) {
   const unsigned g = grid_for(int64_t(tl.n_tiles) * block, block, d.xcd_remap);
   const size_t shmem = size_t(tl.max_slots) * 3 * sizeof(typename CT<T>::C);
   const int J = (tl.max_compute + block - 1) / block;
-#define DECBPM_STEPA(KM, DEC, JJ)                                                                              \
-  hipLaunchKernelGGL((k_step_adj<T, KM, DEC, JJ>), dim3(g), dim3(block), shmem, st, d, tl, DECBPM_C(T, lam_in), \
-                     DECBPM_C(T, fa), DECBPM_C(T, fb), DECBPM_C(T, y3), DECBPM_C(T, y2), DECBPM_C(T, y1),       \
-                     DECBPM_C(T, fa0), DECBPM_M(T, lam_out), gdn, T(h), T(tau), T(gamma))
+#define DECBPM_STEPAC(KM, DEC, JJ, CLX)                                                                          \
+  hipLaunchKernelGGL((k_step_adj<T, KM, DEC, JJ, CLX>), dim3(g), dim3(block), shmem, st, d, tl,                 \
+                     DECBPM_C(T, lam_in), DECBPM_C(T, fa), DECBPM_C(T, fb), DECBPM_C(T, y3), DECBPM_C(T, y2),   \
+                     DECBPM_C(T, y1), DECBPM_C(T, fa0), DECBPM_M(T, lam_out), gdn, T(h), T(tau), T(gamma),     \
+                     DECBPM_C(T, sig))
+#define DECBPM_STEPA(KM, DEC, JJ)                       \
+  if (tl.llwi) DECBPM_STEPAC(KM, DEC, JJ, true); \
+  else DECBPM_STEPAC(KM, DEC, JJ, false)
 #define DECBPM_STEPA_J(KM, DEC) \
-  if (J <= 1) DECBPM_STEPA(KM, DEC, 1); else DECBPM_STEPA(KM, DEC, 2);
+  if (J <= 1) { DECBPM_STEPA(KM, DEC, 1); } else { DECBPM_STEPA(KM, DEC, 2); }
   const bool dec = tl.lmw != nullptr;
   if (kmax_of(d.wmax) == 8) {
     if (dec) { DECBPM_STEPA_J(8, true) } else { DECBPM_STEPA_J(8, false) }
@@ -4128,6 +4181,7 @@ void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_i
   }
 #undef DECBPM_STEPA_J
 #undef DECBPM_STEPA
+#undef DECBPM_STEPAC
 }
 
 // Persistent kernel instance for a body; tiles with complex L weights have
@@ -4465,7 +4519,7 @@ void launch_zero_f64(int64_t n, double* x, int block, hipStream_t st) {
                                    void*, double, double, double, int, hipStream_t);                             \
   template void launch_step_adj<T>(const DevOps<T>&, const TileOps<T>&, const void*, const void*, const void*,     \
                                    const void*, const void*, const void*, const void*, void*, double*, double,   \
-                                   double, double, int, hipStream_t);                                            \
+                                   double, double, const void*, int, hipStream_t);                               \
   template hipError_t launch_persist<T>(const DevOps<T>&, const TileOps<T>&, const int32_t*, const int32_t*, void*, \
                                         void*, int32_t*, int32_t*, int32_t, int32_t, double, double, int,        \
                                         hipStream_t, int, const PersistIO&, bool);                                     \

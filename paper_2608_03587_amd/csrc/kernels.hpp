@@ -309,11 +309,12 @@ template <typename T>
 void launch_step_rec(const DevOps<T>& d, const TileOps<T>& tl, const void* in_psi, void* out_psi, void* y1, void* y2,
                      void* y3, void* b, double h, double tau, double gamma, int block, hipStream_t st);
 // One reverse z step of the adjoint on the step tiles (lam_out must not alias
-// lam_in; gdn accumulates in place).
+// lam_in; gdn accumulates in place).  sig: H0~ / H0 per row (device order) for
+// tiles with complex L weights (a perfectly matched layer), else unused.
 template <typename T>
 void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_in, const void* fa, const void* fb,
                      const void* y3, const void* y2, const void* y1, const void* fa0, void* lam_out, double* gdn,
-                     double h, double tau, double gamma, int block, hipStream_t st);
+                     double h, double tau, double gamma, const void* sig, int block, hipStream_t st);
 
 // Where a persistent launch takes its state from and puts its result.
 // in: the caller's field (caller order, row r at in[perm[r]]); the launch
