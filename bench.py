@@ -596,6 +596,26 @@ def bench_adjoint(api, W, torch, dev, tdt):
            "vertices": w.mesh.n_vert, "steps": n, "objective": abs(c) ** 2,
            "grad_finite": bool(torch.isfinite(torch.view_as_real(g0)).all() and torch.isfinite(gdn).all())}
     log(f"[bench] adjoint: {t_a / t_f:.2f}x forward (checkpointed fwd + adjoint {res['total_over_forward']:.2f}x)")
+    # the whole run stored (every = n_steps: about five field vectors per step of device memory)
+    # instead of recomputed from sqrt(N) checkpoints: the same gradients, bitwise
+    ws_all = torch.empty(m.workspace_size(n, n), dtype=torch.uint8, device=dev)
+    g2 = u0.clone()
+    torch.cuda.synchronize()
+    ev[2].record()
+    m.forward_checkpointed(g2, dz, n, w.gamma, ws_all, n)
+    ev[3].record()
+    ev[4].record()
+    g0_all, gdn_all = m.adjoint(gout, dz, n, w.gamma, ws_all, n)
+    ev[5].record()
+    torch.cuda.synchronize()
+    t_c2, t_a2 = ev[2].elapsed_time(ev[3]), ev[4].elapsed_time(ev[5])
+    res["run_stored"] = {"checkpointed_forward_ms": t_c2, "adjoint_ms": t_a2, "total_over_forward": (t_c2 + t_a2) / t_f,
+                         "workspace_GB": ws_all.numel() / 2**30,
+                         "equals_sqrt_checkpoints_bitwise": bool(torch.equal(g2, g) and torch.equal(g0_all, g0)
+                                                                 and torch.equal(gdn_all, gdn))}
+    del ws_all
+    log(f"[bench] adjoint with the run stored: checkpointed fwd + adjoint "
+        f"{res['run_stored']['total_over_forward']:.2f}x forward ({res['run_stored']['workspace_GB']:.1f} GB)")
     # the complex64 gradients against central differences of the complex128 forward, over the whole
     # run, along 4 random field and 4 random index directions
     m.close()

@@ -371,7 +371,11 @@ int dec_bpm_overlap(dec_bpm_t h, const void* a, const void* b, double* re, doubl
  * grad_field0 = dJ/dpsi(0) (complex, caller order) and, if grad_dn is not
  * NULL, grad_dn = dJ/d(dn) (double[n_vert], caller order).  Each segment
  * between checkpoints is recomputed forward, storing its stage vectors, then
- * swept backward.  With a perfectly matched layer (complex L~ = H0~^{-1} K~)
+ * swept backward.  On the one-kernel step tiles the forward call already
+ * stores the last segment's stage vectors, so the adjoint call that follows
+ * it recomputes every segment but that one; with every >= n_steps the workspace
+ * holds the whole run (about five field vectors per step) and the adjoint
+ * recomputes nothing, trading device memory for the recompute.  With a perfectly matched layer (complex L~ = H0~^{-1} K~)
  * the reverse sweep applies conj(L~) in the variables conj(H0~)^{-1} g (the
  * Kerr adjoint and the objective keep the real H0); both calls then need the
  * one-kernel step tiles, and a handle without them returns EINVAL.

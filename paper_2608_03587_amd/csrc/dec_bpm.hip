@@ -141,7 +141,7 @@ struct Engine {
   }
   bool has_step = false;
   bool has_step4 = false;  // the step tiles hold the beta4 layout (eight or nine rings)
-  bool pml = false;        // complex-stretched L (perfectly matched layer): one-kernel step only
+  bool pml = false;        // complex-stretched L (perfectly matched layer): step-tile kernels only
   int step_tile = 1024;  // rows per tile of the one-kernel step (largest that fits)
   bool sort_ring0 = true;  // step tiles: order the owned rows by degree too
   // persistent stepping on the step tiles: neighbour-tile lists, flags, wait bound
@@ -213,6 +213,7 @@ struct Engine {
     double dz = 0, gamma = 0;
     int64_t n = -1, every = 0;
     uint64_t dn_digest = 0;
+    bool last_recorded = false;  // the workspace holds the last segment's stage vectors
   };
   static constexpr size_t kMaxCkpt = 64;
   std::vector<CkptRec> ckpts;
@@ -1778,8 +1779,11 @@ static WsLayout ws_layout(const Engine& E, int64_t n_steps, int64_t every) {
   return L;
 }
 
+// Returns whether the call recorded the last segment's stage vectors (the
+// one-kernel step path does: the reverse sweep starts there without
+// recomputing it; with every >= n_steps that is the whole run).
 template <typename T>
-static void forward_ckpt_t(Engine& E, void* field, double dz, int64_t n, double gamma, int64_t every, char* ws,
+static bool forward_ckpt_t(Engine& E, void* field, double dz, int64_t n, double gamma, int64_t every, char* ws,
                            hipStream_t st) {
   const WsLayout L = ws_layout(E, n, every);
   const DevOps<T> d = E.ops<T>();
@@ -1792,16 +1796,29 @@ static void forward_ckpt_t(Engine& E, void* field, double dz, int64_t n, double 
     launch_prep_s<T>(d, E.psi, E.s, 0.5 * dz, B, st);
     launch_kerr<T>(d, E.psi, E.psi, E.s, 0.5 * dz, gamma, B, st);
     launch_copy<T>(E.n_rows, E.psi, ws + L.ck, B, st);
+    // the last segment's states, stage vectors and pre-Kerr states go where
+    // the adjoint's recompute of that segment would put them
+    const int64_t n0 = (L.K - 1) * L.S;
+    auto A = [&](int64_t j) -> void* { return ws + L.sa + size_t(j) * vb; };
+    auto Y = [&](int64_t j, int k) -> void* { return ws + L.sy + size_t(3 * (j - 1) + k) * vb; };
+    auto Bv = [&](int64_t j) -> void* { return ws + L.sb + size_t(j - 1) * vb; };
     void* cur = E.psi;
     void* nxt = E.psi2;
     for (int64_t k = 1; k <= n; ++k) {
-      launch_step<T>(d, sp, cur, nxt, dz, k < n ? dz : 0.5 * dz, gamma, E.sblock(), st);
+      const double tau = k < n ? dz : 0.5 * dz;
+      if (k > n0) {
+        const int64_t j = k - n0;
+        launch_step_rec<T>(d, sp, cur, A(j), Y(j, 0), Y(j, 1), Y(j, 2), Bv(j), dz, tau, gamma, E.sblock(), st);
+        cur = A(j);
+        continue;
+      }
+      launch_step<T>(d, sp, cur, nxt, dz, tau, gamma, E.sblock(), st);
       std::swap(cur, nxt);
       if (k % L.S == 0 && k / L.S < L.K) launch_copy<T>(E.n_rows, cur, ws + L.ck + size_t(k / L.S) * vb, B, st);
     }
     launch_perm_out<T>(d, E.perm, cur, field, 0, E.flag, B, st);
     check_launch();
-    return;
+    return true;
   }
   if (n > 0 && E.has_tiles && E.fused != 0) {
     const TileOps<T> tl = E.tiles<T>();
@@ -1822,7 +1839,7 @@ static void forward_ckpt_t(Engine& E, void* field, double dz, int64_t n, double 
     }
     launch_perm_out<T>(d, E.perm, cur, field, 0, E.flag, B, st);
     check_launch();
-    return;
+    return false;
   }
   if (n > 0) {
     launch_copy<T>(E.n_rows, E.psi, ws + L.x0, B, st);
@@ -1836,6 +1853,7 @@ static void forward_ckpt_t(Engine& E, void* field, double dz, int64_t n, double 
   }
   launch_perm_out<T>(d, E.perm, E.psi, field, 0, E.flag, B, st);
   check_launch();
+  return false;
 }
 
 template <typename T>
@@ -1904,7 +1922,7 @@ static void adjoint_t(Engine& E, const void* grad_out, double dz, int64_t n, dou
 // tile launches per step.
 template <typename T>
 static void adjoint_step_t(Engine& E, const void* grad_out, double dz, int64_t n, double gamma, int64_t every,
-                           char* ws, void* grad0, double* grad_dn, hipStream_t st) {
+                           char* ws, void* grad0, double* grad_dn, bool last_recorded, hipStream_t st) {
   const WsLayout L = ws_layout(E, n, every);
   const DevOps<T> d = E.ops<T>();
   const TileOps<T> sp = E.stp.template ops<T>();
@@ -1922,7 +1940,9 @@ static void adjoint_step_t(Engine& E, const void* grad_out, double dz, int64_t n
     const int64_t n0 = seg * L.S, n1 = std::min(n, (seg + 1) * L.S), m = n1 - n0;
     char* ck = ws + L.ck + size_t(seg) * vb;
     auto A = [&](int64_t j) -> void* { return j == 0 ? static_cast<void*>(ck) : ws + L.sa + size_t(j) * vb; };
-    for (int64_t j = 1; j <= m; ++j)  // recompute the segment, recording the stage vectors
+    // recompute the segment, recording the stage vectors (the forward call
+    // recorded the last one)
+    for (int64_t j = 1; j <= m && !(last_recorded && seg == L.K - 1); ++j)
       launch_step_rec<T>(d, sp, A(j - 1), A(j), Y(j, 0), Y(j, 1), Y(j, 2), Bv(j), dz, (n0 + j < n) ? dz : 0.5 * dz,
                          gamma, SB, st);
     for (int64_t j = m; j >= 1; --j) {
@@ -2825,10 +2845,9 @@ int dec_bpm_forward_checkpointed(dec_bpm_t h, void* field, double dz, int64_t n_
     fail(DEC_BPM_EWORKSPACE, "workspace needs " + std::to_string(L.total) + " bytes");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) fail(DEC_BPM_EWORKSPACE, "workspace must be 256-byte aligned");
   char* ws = static_cast<char*>(workspace);
-  if (E.dtype == DEC_BPM_C64)
-    decbpm::forward_ckpt_t<float>(E, field, dz, n_steps, gamma, every, ws, as_stream(stream));
-  else
-    decbpm::forward_ckpt_t<double>(E, field, dz, n_steps, gamma, every, ws, as_stream(stream));
+  const bool recorded = E.dtype == DEC_BPM_C64
+                            ? decbpm::forward_ckpt_t<float>(E, field, dz, n_steps, gamma, every, ws, as_stream(stream))
+                            : decbpm::forward_ckpt_t<double>(E, field, dz, n_steps, gamma, every, ws, as_stream(stream));
   Engine::CkptRec rec;
   rec.ws = workspace;
   rec.dz = dz;
@@ -2836,6 +2855,7 @@ int dec_bpm_forward_checkpointed(dec_bpm_t h, void* field, double dz, int64_t n_
   rec.n = n_steps;
   rec.every = L.S;
   rec.dn_digest = E.dn_digest;
+  rec.last_recorded = recorded;
   auto& cs = E.ckpts;
   cs.erase(std::remove_if(cs.begin(), cs.end(), [&](const Engine::CkptRec& c) { return c.ws == workspace; }),
            cs.end());
@@ -2863,16 +2883,20 @@ int dec_bpm_adjoint(dec_bpm_t h, const void* grad_out, double dz, int64_t n_step
     fail(DEC_BPM_EWORKSPACE, "workspace does not hold the checkpoints of a matching forward call");
   char* ws = static_cast<char*>(workspace);
   hipStream_t st = as_stream(stream);
+  const bool step = E.dtype == DEC_BPM_C64 ? decbpm::use_step_adjoint<float>(E) : decbpm::use_step_adjoint<double>(E);
+  const bool recorded = step && rec->last_recorded;
+  // a recompute overwrites the segment store: the last segment's record then no longer holds
+  if (!(recorded && L.K == 1)) rec->last_recorded = false;
   if (E.dtype == DEC_BPM_C64) {
-    if (decbpm::use_step_adjoint<float>(E))
-      decbpm::adjoint_step_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
+    if (step)
+      decbpm::adjoint_step_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, recorded, st);
     else if (decbpm::adjoint_fused_ok<float>(E))
       decbpm::adjoint_fused_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
     else
       decbpm::adjoint_t<float>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
   } else {
-    if (decbpm::use_step_adjoint<double>(E))
-      decbpm::adjoint_step_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
+    if (step)
+      decbpm::adjoint_step_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, recorded, st);
     else if (decbpm::adjoint_fused_ok<double>(E))
       decbpm::adjoint_fused_t<double>(E, grad_out, dz, n_steps, gamma, every, ws, grad_field0, grad_dn, st);
     else

@@ -926,6 +926,43 @@ def test_adjoint_matches_oracle_gradients(dtype):
     assert rel(gdn.cpu().numpy(), gdn_ref) < tol, rel(gdn.cpu().numpy(), gdn_ref)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_with_the_run_stored_and_repeated_calls(dtype):
+    """The checkpointed forward stores the last segment's stage vectors, so the adjoint
+    skips that segment's recompute; with every = n_steps it stores the whole run and
+    recomputes nothing.  The gradients with 5-step segments and with the run stored agree
+    bitwise (the recording step kernel is the plain step plus stores), a second adjoint
+    call on the same workspace gives the first one's bits (with several segments the
+    first call's recompute has overwritten the stored one, so the second recomputes it),
+    and both agree with the oracle."""
+    w = W.adjoint_mmf(n_vert=3000, n_steps=10)
+    n = 24
+    dn = w.extra["dn"]
+    ops = oracle_ops(w, dn=dn)
+    J, g_ref, gdn_ref = OA.gradients(w.u0, w.extra["target"], ops, w.dz, n, w.gamma)
+    m = lib_mesh(w, dtype)
+    assert m.tuning["fused"] >= 2  # the step-tile adjoint
+    m.set_index_perturbation(torch.from_numpy(dn).to(DEV))
+    tgt = dev(w.extra["target"], dtype)
+    h0 = torch.from_numpy(ops.H0).to(DEV)
+    out = {}
+    for every in (5, n):
+        say("adjoint every", dtype, every)
+        wsp = torch.empty(m.workspace_size(n, every), dtype=torch.uint8, device=DEV)
+        u = dev(w.u0, dtype)
+        m.forward_checkpointed(u, w.dz, n, w.gamma, wsp, every)
+        c = m.overlap(tgt, u)
+        gout = (2 * c * h0 * tgt.to(torch.complex128)).to(u.dtype)
+        first = m.adjoint(gout, w.dz, n, w.gamma, wsp, every)
+        second = m.adjoint(gout, w.dz, n, w.gamma, wsp, every)
+        assert torch.equal(first[0], second[0]) and torch.equal(first[1], second[1])
+        out[every] = (host(u), host(first[0]), first[1].cpu().numpy())
+    assert np.array_equal(out[5][0], out[n][0])
+    assert np.array_equal(out[5][1], out[n][1]) and np.array_equal(out[5][2], out[n][2])
+    tol = 1e-9 if dtype == "c128" else 1e-4
+    assert rel(out[n][1], g_ref) < tol and rel(out[n][2], gdn_ref) < tol
+
+
 @pytest.mark.parametrize("dtype,nl", [("c128", "dec"), ("c64", "dec"), ("c128", "lumped")])
 def test_pml_adjoint_matches_oracle_gradients(dtype, nl):
     """The adjoint with a perfectly matched layer (complex L weights on the step tiles):
