@@ -165,10 +165,55 @@ def profile_batched(args, api, W, torch, dev, tdt):
         m.close()
 
 
+def profile_adjoint(args, api, W, torch, dev, tdt):
+    """The adjoint workload (500k-vertex multimode fibre, --dtype) with the whole run stored:
+    the checkpointed forward (one recording step kernel per step) and the reverse sweep (one
+    adjoint step kernel per step) over --steps steps, after a warm-up pair of --warmup steps."""
+    w = W.adjoint_mmf()
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, w.absorber, dtype=args.dtype)
+    if args.tuning:
+        m.tuning = json.loads(args.tuning)
+    else:
+        m.autotune(w.dz, w.gamma)
+    m.set_index_perturbation(torch.from_numpy(w.extra["dn"]).to(dev))
+    u0 = torch.from_numpy(w.u0).to(dev, tdt)
+    tgt = torch.from_numpy(w.extra["target"]).to(dev, tdt)
+    h0 = torch.from_numpy(m.export_operators()["h0"]).to(dev)
+    ws = torch.empty(m.workspace_size(max(args.steps, args.warmup), max(args.steps, args.warmup)),
+                     dtype=torch.uint8, device=dev)
+
+    def run(k):
+        f = u0.clone()
+        m.forward_checkpointed(f, w.dz, k, w.gamma, ws, k)
+        c = m.overlap(tgt, f)
+        return m.adjoint((2 * c * h0 * tgt.to(torch.complex128)).to(tdt), w.dz, k, w.gamma, ws, k)
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    g0, gdn = run(args.steps)
+    s1.record()
+    torch.cuda.synchronize()
+    ok = bool(torch.isfinite(torch.view_as_real(g0)).all() and torch.isfinite(gdn).all())
+    if args.calibrate_copy:  # a plain copy of known size, for scaling the traffic counters
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    print(json.dumps({"profile_only": True, "path": "adjoint", "vertices": w.mesh.n_vert, "units": args.steps,
+                      "us_per_unit": s0.elapsed_time(s1) * 1e3 / args.steps, "grad_finite": ok,
+                      "tuning": m.tuning}))
+    m.close()
+
+
 def profile_path(args, api, W, torch, dev, tdt):
     """One path alone, for rocprofv3: warm-up, then the timed call; prints one JSON line."""
     if args.profile_path == "batched":
         return profile_batched(args, api, W, torch, dev, tdt)
+    if args.profile_path == "adjoint":
+        return profile_adjoint(args, api, W, torch, dev, tdt)
     w = W.vortex_beta4() if args.profile_path == "vortex_beta4" else W.step_index()
     pml = (35.0, 40.0, 1.0) if args.profile_path == "pml" else None
     m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, None if pml else w.absorber, dtype=args.dtype, p1=w.p1,
@@ -243,11 +288,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="only the timed propagation (for rocprofv3)")
     ap.add_argument("--profile-path", default="split",
-                    choices=["split", "vortex_beta4", "pml", "adaptive", "mode", "batched"],
+                    choices=["split", "vortex_beta4", "pml", "adaptive", "mode", "batched", "adjoint"],
                     help="with --profile: which path to run (split: the step-index propagate; vortex_beta4: the "
                          "1M-vertex beta4 launch; pml: the step-index launch with the layer; adaptive: the "
                          "Dormand-Prince run over --steps dz; mode: --steps mode-solver iterations; batched: the "
-                         "8-mesh, 256-field batch)")
+                         "8-mesh, 256-field batch; adjoint: checkpointed forward and adjoint of the 500k-vertex "
+                         "fibre over --steps steps, the whole run stored)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="with --profile: also run a 256 MiB device copy (traffic counter calibration)")
     ap.add_argument("--tuning", default="", help="fixed launch shape as JSON (skips autotuning), e.g. the "
