@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "kernels.hpp"
 
@@ -1162,6 +1163,8 @@ struct CplxAoS {
   C* p;
   __device__ C get(int i) const { return p[i]; }
   __device__ void put(int i, const C& v) const { p[i] = v; }
+  // the element at byte offset off (a neighbour slot held pre-scaled)
+  __device__ C get_b(int off) const { return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(p) + off); }
 };
 // Threads per workgroup the step-tile kernels are compiled for.  With two
 // compute slots per thread the complex128 kernels hold twice the operator
@@ -1194,9 +1197,15 @@ struct StepBound {
 // lanes of a wave reading entry k hit distinct banks and each entry is an
 // immediate offset from one address per slot) instead of registers, for
 // kernels that hold more per-slot state than the register file leaves room for.
-template <typename T, int KMAX, bool DEC, int J, bool CL = false, bool LM = false>
+template <typename T, int KMAX, bool DEC, int J, bool CL = false, bool LM = false, bool BO = false>
 struct StepTile {
   using C = typename CT<T>::C;
+  // BO: neighbour slots held as byte offsets into a complex LDS buffer
+  // (slot * sizeof(C)) and the real per-slot buffer S laid out at the same
+  // stride, so that with buffers at constant LDS offsets a gather needs no
+  // address arithmetic (the offset goes into the LDS instruction)
+  static constexpr int QSC = BO ? int(sizeof(C)) : 1;
+  static constexpr int SST = BO ? 2 : 1;  // elements of T per S slot
   int nLoad, n1, n2, n3, n4, nNL;
   const int32_t* hd;
   const int32_t* ext;
@@ -1266,7 +1275,7 @@ struct StepTile {
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) {
         if (k < w) {
-          q[j][k] = tl.lcol[base + 64 * k];
+          q[j][k] = tl.lcol[base + 64 * k] * QSC;
           cl[j][k] = tl.llw[base + 64 * k];
           if constexpr (DEC && LM) {
             if (i < nNL) cml[i * KP + k] = tl.lmw[base + 64 * k];
@@ -1275,7 +1284,7 @@ struct StepTile {
           }
           if constexpr (CL) cli[j][k] = tl.llwi[base + 64 * k];
         } else {
-          q[j][k] = i < n1 ? i : 0;
+          q[j][k] = (i < n1 ? i : 0) * QSC;
           cl[j][k] = T(0);
           if constexpr (DEC && !LM) cm[j][k] = T(0);
           if constexpr (CL) cli[j][k] = T(0);
@@ -1318,7 +1327,12 @@ struct StepTile {
   __device__ void lsum_n(const V& V_, int j, const C& vr, T& ar, T& ai) const {
     C vq[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) vq[k] = V_.get(nb(j, k));
+    for (int k = 0; k < N; ++k) {
+      if constexpr (BO)
+        vq[k] = V_.get_b(nb(j, k));
+      else
+        vq[k] = V_.get(nb(j, k));
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const T dx = vr.x - vq[k].x, dy = vr.y - vq[k].y;
@@ -1346,7 +1360,12 @@ struct StepTile {
   __device__ T msum_n(const T* S, int j, T th) const {
     T sq[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) sq[k] = S[nb(j, k)];
+    for (int k = 0; k < N; ++k) {
+      if constexpr (BO)
+        sq[k] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(S) + nb(j, k));
+      else
+        sq[k] = S[nb(j, k)];
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) th += mw(j, k) * sq[k];
     return th;
@@ -1366,7 +1385,12 @@ struct StepTile {
   __device__ void msum2_n(const C* SM, int j, T& th, T& mm) const {
     C sq[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) sq[k] = SM[nb(j, k)];
+    for (int k = 0; k < N; ++k) {
+      if constexpr (BO)
+        sq[k] = *reinterpret_cast<const C*>(reinterpret_cast<const char*>(SM) + nb(j, k));
+      else
+        sq[k] = SM[nb(j, k)];
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       th += mw(j, k) * sq[k].x;
@@ -1464,7 +1488,7 @@ struct StepTile {
       if (i < n4) {  // state before the Kerr substep
         cur[j] = stage(d, Y, cur[j], p[j], j, h);
         so[j] = nl_int(d, cur[j].x * cur[j].x + cur[j].y * cur[j].y, ww[j], tau);
-        S[i] = so[j];
+        S[i * SST] = so[j];
         if (i < nNL) rec(3, rr[j], cur[j]);
       }
     }
@@ -1540,7 +1564,7 @@ struct StepTile {
       if (early(i, j, 5)) {  // state before the Kerr substep
         cur[j] = stage(d, Y, cur[j], p[j], j, h);
         so[j] = nl_int(d, cur[j].x * cur[j].x + cur[j].y * cur[j].y, ww[j], tau);
-        S[i] = so[j];
+        S[i * SST] = so[j];
       }
     }
     __syncthreads();
@@ -1584,7 +1608,7 @@ struct StepTile {
       if (i < n4 && !early(i, j, 5)) {
         cur[j] = stage(d, Y, cur[j], p[j], j, h);
         so[j] = nl_int(d, cur[j].x * cur[j].x + cur[j].y * cur[j].y, ww[j], tau);
-        S[i] = so[j];
+        S[i * SST] = so[j];
       }
     }
     __syncthreads();
@@ -1628,7 +1652,7 @@ struct StepTile {
       if (i < nS) {
         p[j] = src[perm ? perm[rr[j]] : rr[j]];
         so[j] = nl_int(d, p[j].x * p[j].x + p[j].y * p[j].y, ww[j], tau);
-        S[i] = so[j];
+        S[i * SST] = so[j];
       }
     }
     __syncthreads();
@@ -1701,7 +1725,7 @@ struct StepTile {
           if (k < 3) Vout.put(i, y);
           else {
             so[j] = nl_int(d, y.x * y.x + y.y * y.y, ww[j], tau);
-            S[i] = so[j];
+            S[i * SST] = so[j];
           }
         }
       }
@@ -1830,7 +1854,7 @@ struct StepTile {
 #pragma unroll
         for (int f = 0; f < VF; ++f)
           so[j].v[f] = (cur[j].v[f].x * cur[j].v[f].x + cur[j].v[f].y * cur[j].v[f].y) * ph;
-        S[i] = so[j];
+        S[i * SST] = so[j];
       }
     }
     __syncthreads();
@@ -3193,6 +3217,13 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
 // whole right-hand side (the stage inputs and their |.|^2 double-buffered in
 // the same LDS; the owned state and its |.|^2 written back after the step).
 // CL: complex L weights (a perfectly matched layer), in complex64.
+// FX (split-step body, complex64): the LDS buffers at constant offsets of
+// kPersistFixSlots slots each and the neighbour slots held as byte offsets, so
+// that the gathers of every phase carry their buffer's offset in the LDS
+// instruction instead of an address computed per neighbour; for tiles of at
+// most that many slots.
+constexpr int kPersistFixSlots = 2560;
+
 template <typename T>
 struct PersistArgs {
   using C = typename CT<T>::C;
@@ -3203,7 +3234,7 @@ struct PersistArgs {
   T tau_first, tau_last;
 };
 
-template <typename T, int KMAX, bool DEC, int J, int LS, int BODY, bool CL = false>
+template <typename T, int KMAX, bool DEC, int J, int LS, int BODY, bool CL = false, bool FX = false>
 __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, const int32_t* __restrict__ nb_ptr,
                                                   const int32_t* __restrict__ nb_list, typename CT<T>::C* buf0,
                                                   typename CT<T>::C* buf1, int32_t* flags, int32_t* status,
@@ -3215,16 +3246,21 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
   __shared__ int32_t abort_s;
   const int64_t tile = logical_block(d.xcd_remap);
   if (tile >= tl.n_tiles) return;
-  const int MS = tl.max_slots;
+  static_assert(!FX || (BODY == 0 && sizeof(T) == 4), "the fixed layout is for the complex64 split step");
+  const int MS = FX ? kPersistFixSlots : tl.max_slots;
   const int B = blockDim.x;
   C* base = reinterpret_cast<C*>(smem);
+  if constexpr (FX) {  // static LDS: its address is a constant the gathers can carry
+    __shared__ __align__(16) unsigned char fx_lds[4 * kPersistFixSlots * sizeof(C)];
+    base = reinterpret_cast<C*>(fx_lds);
+  }
   const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS};
   T* S = reinterpret_cast<T*>(base + 3 * MS);
   C* UA = base;  // BODY 1: stage buffers A, B and their |.|^2
   C* UB = base + MS;
   T* USA = reinterpret_cast<T*>(base + 2 * MS);
   T* USB = USA + MS;
-  StepTile<T, KMAX, DEC, J, CL> st;
+  StepTile<T, KMAX, DEC, J, CL, false, FX> st;
   st.init(d, tl, tile, false, nullptr, BODY == 0);
   int32_t pr[LS];  // rows of this thread's state slots
 #pragma unroll
@@ -4187,7 +4223,12 @@ void launch_step_adj(const DevOps<T>& d, const TileOps<T>& tl, const void* lam_i
 // Persistent kernel instance for a body; tiles with complex L weights have
 // instances in complex64 only (nullptr otherwise).
 template <typename T, int KM, bool DEC, int JJ>
-static const void* persist_instance(int body, bool cl) {
+static const void* persist_instance(int body, bool cl, bool fx) {
+  if constexpr (sizeof(T) == 4) {
+    if (fx && body == 0)
+      return cl ? reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0, true, true>)
+                : reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0, false, true>);
+  }
   if (cl) {
     if constexpr (sizeof(T) == 4) {
       return body ? reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 1, true>)
@@ -4199,13 +4240,30 @@ static const void* persist_instance(int body, bool cl) {
               : reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0>);
 }
 
+// DEC_BPM_PERSIST_FIXED=0 keeps the runtime-sized LDS layout everywhere (read
+// once per process).
+static bool persist_fixed_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("DEC_BPM_PERSIST_FIXED");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+// Whether the persistent launch of a body takes the fixed LDS layout.
+template <typename T>
+static bool persist_fixed(const TileOps<T>& tl, int body) {
+  return sizeof(T) == 4 && body == 0 && tl.max_slots <= kPersistFixSlots && persist_fixed_enabled();
+}
+
 // Kernel instance of the persistent step for a tile set and block size.
 template <typename T>
 static const void* persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int block, int body) {
   const int J = (tl.max_compute + block - 1) / block;
   const bool dec = tl.lmw != nullptr;
   const bool cl = tl.llwi != nullptr;
-#define DECBPM_PK(KM, DEC, JJ) persist_instance<T, KM, DEC, JJ>(body, cl)
+  const bool fx = persist_fixed<T>(tl, body);
+#define DECBPM_PK(KM, DEC, JJ) persist_instance<T, KM, DEC, JJ>(body, cl, fx)
 #define DECBPM_PK_J(KM, DEC) return J <= 1 ? DECBPM_PK(KM, DEC, 1) : DECBPM_PK(KM, DEC, 2);
   if (kmax_of(d.wmax) == 8) {
     if (dec) { DECBPM_PK_J(8, true) } else { DECBPM_PK_J(8, false) }
@@ -4217,7 +4275,10 @@ static const void* persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int 
 }
 
 template <typename T>
-size_t persist_lds(const TileOps<T>& tl) {
+size_t persist_lds(const TileOps<T>& tl, int body) {
+  // the fixed layout is static LDS of the kernel (four buffers of kPersistFixSlots
+  // complex-sized slots, S at the complex stride): no dynamic LDS
+  if (persist_fixed<T>(tl, body)) return 0;
   return size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
 }
 
@@ -4229,7 +4290,8 @@ int persist_capacity(const DevOps<T>& d, const TileOps<T>& tl, int block, int bo
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, persist_lds<T>(tl)) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, persist_lds<T>(tl, body)) != hipSuccess)
+    return 0;
   return cus * per_cu;
 }
 
@@ -4251,8 +4313,8 @@ hipError_t launch_persist(const DevOps<T>& d, const TileOps<T>& tl, const int32_
                     T(io.tau_last)};
   void* args[] = {&dd, &tt, const_cast<int32_t**>(&nb_ptr), const_cast<int32_t**>(&nb_list), &b0, &b1, &flags, &status,
                   &n_steps, &spin_limit, &th, &tg, &pa};
-  if (coop) return hipLaunchCooperativeKernel(k, dim3(g), dim3(block), args, unsigned(persist_lds<T>(tl)), st);
-  return hipLaunchKernel(k, dim3(g), dim3(block), args, size_t(persist_lds<T>(tl)), st);
+  if (coop) return hipLaunchCooperativeKernel(k, dim3(g), dim3(block), args, unsigned(persist_lds<T>(tl, body)), st);
+  return hipLaunchKernel(k, dim3(g), dim3(block), args, size_t(persist_lds<T>(tl, body)), st);
 }
 
 template <typename T>
