@@ -1166,6 +1166,32 @@ struct CplxAoS {
   // the element at byte offset off (a neighbour slot held pre-scaled)
   __device__ C get_b(int off) const { return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(p) + off); }
 };
+
+// Fixed LDS layout of the complex64 persistent split step (template flag FX):
+// the per-slot buffers sit at constant offsets of kFixSlots slots each in
+// static LDS, and the neighbour slots are held as byte offsets (StepTile BO),
+// so that every gather carries its buffer's offset in the LDS instruction
+// instead of an address computed per neighbour.  For tiles of at most
+// kFixSlots slots; two workgroups with four such buffers fit one compute
+// unit's LDS.  (The one-kernel step, its adjoint pair and the batched field
+// loop measured no faster with it, so they keep the runtime-sized layout.)
+constexpr int kFixSlots = 2432;
+
+// DEC_BPM_FIXED_LDS=0 keeps the runtime-sized LDS layout everywhere (read once
+// per process).
+static bool fixed_lds_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("DEC_BPM_FIXED_LDS");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+// Whether a complex64 tile set takes the fixed layout.
+template <typename T>
+static bool fixed_lds(const TileOps<T>& tl) {
+  return sizeof(T) == 4 && tl.max_slots <= kFixSlots && fixed_lds_enabled();
+}
 // Threads per workgroup the step-tile kernels are compiled for.  With two
 // compute slots per thread the complex128 kernels hold twice the operator
 // registers of the complex64 ones, so their workgroups are capped at 640
@@ -3217,12 +3243,7 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_adj(DevOps<T>
 // whole right-hand side (the stage inputs and their |.|^2 double-buffered in
 // the same LDS; the owned state and its |.|^2 written back after the step).
 // CL: complex L weights (a perfectly matched layer), in complex64.
-// FX (split-step body, complex64): the LDS buffers at constant offsets of
-// kPersistFixSlots slots each and the neighbour slots held as byte offsets, so
-// that the gathers of every phase carry their buffer's offset in the LDS
-// instruction instead of an address computed per neighbour; for tiles of at
-// most that many slots.
-constexpr int kPersistFixSlots = 2560;
+// FX (split-step body, complex64): the fixed LDS layout (see kFixSlots).
 
 template <typename T>
 struct PersistArgs {
@@ -3247,11 +3268,11 @@ __global__ void __launch_bounds__(1024) k_persist(DevOps<T> d, TileOps<T> tl, co
   const int64_t tile = logical_block(d.xcd_remap);
   if (tile >= tl.n_tiles) return;
   static_assert(!FX || (BODY == 0 && sizeof(T) == 4), "the fixed layout is for the complex64 split step");
-  const int MS = FX ? kPersistFixSlots : tl.max_slots;
+  const int MS = FX ? kFixSlots : tl.max_slots;
   const int B = blockDim.x;
   C* base = reinterpret_cast<C*>(smem);
   if constexpr (FX) {  // static LDS: its address is a constant the gathers can carry
-    __shared__ __align__(16) unsigned char fx_lds[4 * kPersistFixSlots * sizeof(C)];
+    __shared__ __align__(16) unsigned char fx_lds[4 * kFixSlots * sizeof(C)];
     base = reinterpret_cast<C*>(fx_lds);
   }
   const CplxAoS<T> P{base}, X{base + MS}, Y{base + 2 * MS};
@@ -4240,20 +4261,10 @@ static const void* persist_instance(int body, bool cl, bool fx) {
               : reinterpret_cast<const void*>(&k_persist<T, KM, DEC, JJ, 3, 0>);
 }
 
-// DEC_BPM_PERSIST_FIXED=0 keeps the runtime-sized LDS layout everywhere (read
-// once per process).
-static bool persist_fixed_enabled() {
-  static const bool on = [] {
-    const char* e = std::getenv("DEC_BPM_PERSIST_FIXED");
-    return !(e && e[0] == '0');
-  }();
-  return on;
-}
-
 // Whether the persistent launch of a body takes the fixed LDS layout.
 template <typename T>
 static bool persist_fixed(const TileOps<T>& tl, int body) {
-  return sizeof(T) == 4 && body == 0 && tl.max_slots <= kPersistFixSlots && persist_fixed_enabled();
+  return body == 0 && fixed_lds<T>(tl);
 }
 
 // Kernel instance of the persistent step for a tile set and block size.
@@ -4276,7 +4287,7 @@ static const void* persist_kernel(const DevOps<T>& d, const TileOps<T>& tl, int 
 
 template <typename T>
 size_t persist_lds(const TileOps<T>& tl, int body) {
-  // the fixed layout is static LDS of the kernel (four buffers of kPersistFixSlots
+  // the fixed layout is static LDS of the kernel (four buffers of kFixSlots
   // complex-sized slots, S at the complex stride): no dynamic LDS
   if (persist_fixed<T>(tl, body)) return 0;
   return size_t(tl.max_slots) * (3 * sizeof(typename CT<T>::C) + sizeof(T));
