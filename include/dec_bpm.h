@@ -449,6 +449,10 @@ int dec_bpm_batch_check_finite(dec_bpm_batch_t b, void* stream);
  * the unfused kernels.  A persistent neighbour wait that exceeds its bound
  * (DEC_BPM_SPIN_LIMIT polls, default 2^20, of the order of a second) leaves the launch
  * early and makes the next dec_bpm_check_finite report DEC_BPM_ENONFINITE.
+ * In complex64 the persistent split step keeps its per-slot buffers at fixed
+ * offsets in static LDS (tiles of at most 2432 slots); DEC_BPM_FIXED_LDS=0 in
+ * the environment (read once per process) selects the runtime-sized layout,
+ * with the same results bit for bit.
  */
 typedef struct {
   int32_t block_size;       /* threads per workgroup of the unfused kernels      */

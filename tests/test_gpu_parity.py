@@ -1225,6 +1225,51 @@ def test_one_kernel_step_matches_unfused_and_oracle(dtype, nl):
     assert times["step"]["ms"] > 0
 
 
+_LAYOUT_RUN = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_2608_03587_amd import api
+from paper_2608_03587_amd.inputs import workloads as W
+w = W.step_index(n_vert=20000, n_steps=10)
+out = {}
+for pml in (None, (35.0, 40.0, 1.0)):
+    m = api.Mesh(w.mesh.xy, w.mesh.tri, w.index_tri, None if pml else w.absorber, dtype="c64", pml=pml)
+    m.tuning = {"fused": 3, "tile_block": 1024, "xcd_remap": 1}
+    assert m.time_kernels(w.dz, w.gamma, reps=5)["persist"]["ms"] > 0
+    f = torch.from_numpy(w.u0).to("cuda", torch.complex64)
+    m.propagate(f, w.dz, 57, w.gamma)
+    torch.cuda.synchronize()
+    out["pml" if pml else "absorber"] = f.cpu().numpy()
+    m.close()
+np.savez(sys.argv[2], **out)
+print("layout run done", flush=True)
+"""
+
+
+def test_persistent_fixed_lds_layout_matches_runtime_layout(tmp_path):
+    """The complex64 persistent split step with its per-slot buffers at constant offsets
+    in static LDS and the neighbour slots held as byte offsets (the default) gives the
+    bits of the runtime-sized layout (DEC_BPM_FIXED_LDS=0), with the absorber and with
+    the layer's complex weights.  Each layout runs in a process of its own (the switch
+    is read once per process)."""
+    import os
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = {}
+    for env in ("0", "1"):
+        say("layout run", env)
+        out = str(tmp_path / f"layout_{env}.npz")
+        r = subprocess.run([sys.executable, "-c", _LAYOUT_RUN, root, out], capture_output=True, text=True,
+                           timeout=300, env=dict(os.environ, DEC_BPM_FIXED_LDS=env))
+        assert r.returncode == 0, (env, r.stdout[-2000:], r.stderr[-3000:])
+        res[env] = np.load(out)
+    for k in ("absorber", "pml"):
+        assert np.array_equal(res["0"][k], res["1"][k]), k
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("nl", ["dec", "lumped"])
 def test_persistent_launch_matches_step_kernel_and_oracle(dtype, nl):
