@@ -296,7 +296,10 @@ int dec_bpm_propagate_unsplit(dec_bpm_t h, void* field, double dz, int64_t n_ste
  * accepted state and the counters are filled.  EHIP, ENODEVICE.  When the
  * handle's launch mode is the persistent one and every trial tile fits on the
  * device at once, the whole run is one cooperative launch; a tile whose wait
- * for the others exceeds the spin limit then ends the run with EHIP.
+ * for the others exceeds the spin limit then ends the run with EHIP.  If the
+ * runtime refuses the cooperative launch (it enqueues nothing then), the run
+ * takes the per-trial kernels; dec_bpm_find_mode does the same with its
+ * per-iteration kernels, and dec_bpm_time_kernels reports such a path as 0.
  */
 int dec_bpm_propagate_adaptive(dec_bpm_t h, void* field, double z_end, double h0, double gamma, double rtol,
                                double atol, int64_t max_attempts, int64_t* n_accepted, int64_t* n_rejected,

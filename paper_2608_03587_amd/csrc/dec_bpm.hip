@@ -1615,15 +1615,20 @@ static AdaptiveResult propagate_adaptive_t(Engine& E, void* field, double z_end,
   Dp5Ctl c{};
   c.h_abs = h0;
   int64_t launched = 0;
-  // every seven-ring tile resident: the whole run in one cooperative launch
+  // every seven-ring tile resident: the whole run in one cooperative launch;
+  // a cooperative launch the runtime refuses (nothing was enqueued) leaves the
+  // run to the per-trial kernels
   if (E.fused == 3 && dp5_persist_fits<T>(E)) {
     const hipError_t e = launch_dp5_persist<T>(d, tl, E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5flags, E.flag,
                                                E.spin_limit, gamma, rtol, atol, inv_n, blk, st);
-    if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
-    HIP_OK(hipMemcpyAsync(&c, E.dp5ctl, sizeof(Dp5Ctl), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    if (!c.done) fail(DEC_BPM_EHIP, "adaptive run: a tile's wait for the others timed out");
-    launched = max_attempts;
+    if (e == hipSuccess) {
+      HIP_OK(hipMemcpyAsync(&c, E.dp5ctl, sizeof(Dp5Ctl), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      if (!c.done) fail(DEC_BPM_EHIP, "adaptive run: a tile's wait for the others timed out");
+      launched = max_attempts;
+    } else {
+      (void)hipGetLastError();
+    }
   }
   for (; launched < max_attempts;) {
     // trials still expected at the current step size; the first chunk is short,
@@ -1708,15 +1713,19 @@ static ModeResult find_mode_t(Engine& E, void* field, double power, double dtau,
   int64_t launched = 0;
   int K = 8;
   // every step tile resident: the whole iteration in one cooperative launch (complex64 tiles)
+  // (a refused cooperative launch enqueues nothing: the per-iteration kernels take over)
   if (E.fused == 3 && mode_persist_fits<T>(E)) {
     E.pepoch = INT32_MAX;  // the mode launch counts its iterations in the same flags
     const hipError_t e = launch_mode_persist<T>(d, tl, E.psi, E.psi2, E.modectl, E.modepart, E.pflags, E.flag,
                                                 E.spin_limit, dtau, gamma, blk, st);
-    if (e != hipSuccess) fail(DEC_BPM_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
-    HIP_OK(hipMemcpyAsync(&c, E.modectl, sizeof(ModeCtl), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    if (!c.done) fail(DEC_BPM_EHIP, "mode solver: a tile's wait for the others timed out");
-    launched = max_iter;
+    if (e == hipSuccess) {
+      HIP_OK(hipMemcpyAsync(&c, E.modectl, sizeof(ModeCtl), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      if (!c.done) fail(DEC_BPM_EHIP, "mode solver: a tile's wait for the others timed out");
+      launched = max_iter;
+    } else {
+      (void)hipGetLastError();
+    }
   }
   for (; launched < max_iter;) {
     const int64_t left = max_iter - launched;
@@ -2098,12 +2107,19 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       const TileOps<T> tp = E.dp5.template ops<T>();
       const int blk = dp5_block(E);
       const int trials = std::max(reps, 200);
-      for (int pass = 0; pass < 2; ++pass) {  // warm-up, then timed
+      bool refused = false;  // a cooperative launch the runtime refuses: reported as 0, like an absent path
+      for (int pass = 0; pass < 2 && !refused; ++pass) {  // warm-up, then timed
         const int n = pass ? trials : 2;
         launch_dp5_init(E.dp5ctl, E.dp5arr, 1e300, dz, n, 1.0, st);
         if (pass) HIP_OK(hipEventRecord(e0, st));
-        HIP_OK(launch_dp5_persist<T>(d, tp, E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5flags, E.flag, E.spin_limit,
-                                     gamma, 1e-6, 1e-8, 1.0 / double(E.n_rows), blk, st));
+        refused = launch_dp5_persist<T>(d, tp, E.psi, E.psi2, E.dp5ctl, E.dp5part, E.dp5flags, E.flag, E.spin_limit,
+                                        gamma, 1e-6, 1e-8, 1.0 / double(E.n_rows), blk, st) != hipSuccess;
+      }
+      if (refused) {
+        (void)hipGetLastError();
+        if (ms) ms[kind] = 0.0;
+        if (bytes) bytes[kind] = by[kind];
+        continue;
       }
       HIP_OK(hipEventRecord(e1, st));
       HIP_OK(hipEventSynchronize(e1));
@@ -2117,13 +2133,20 @@ static void time_kernels_t(Engine& E, double dz, double gamma, int reps, double*
       ensure_mode_ctl(E);
       const TileOps<T> ts = E.stp.template ops<T>();
       const int iters = std::max(reps, 200);
-      for (int pass = 0; pass < 2; ++pass) {  // warm-up, then timed
+      bool refused = false;  // as for the adaptive run's launch
+      for (int pass = 0; pass < 2 && !refused; ++pass) {  // warm-up, then timed
         launch_diag<T>(d, E.psi, 0.0, E.partials, E.n_red_blocks, E.red_out, st);
         launch_mode_init(E.modectl, E.modearr, E.red_out, 1.0, 0.0, pass ? iters : 2, st);
         if (pass) HIP_OK(hipEventRecord(e0, st));
         E.pepoch = INT32_MAX;  // the mode launch counts its iterations in the same flags
-        HIP_OK(launch_mode_persist<T>(d, ts, E.psi, E.psi2, E.modectl, E.modepart, E.pflags, E.flag, E.spin_limit,
-                                      dz, gamma, E.sblock(), st));
+        refused = launch_mode_persist<T>(d, ts, E.psi, E.psi2, E.modectl, E.modepart, E.pflags, E.flag,
+                                         E.spin_limit, dz, gamma, E.sblock(), st) != hipSuccess;
+      }
+      if (refused) {
+        (void)hipGetLastError();
+        if (ms) ms[kind] = 0.0;
+        if (bytes) bytes[kind] = by[kind];
+        continue;
       }
       HIP_OK(hipEventRecord(e1, st));
       HIP_OK(hipEventSynchronize(e1));
