@@ -1469,10 +1469,12 @@ struct StepTile {
   // the values of its own slots (the state, the latest stage, |b|^2 phi) in
   // registers; LDS serves the neighbour gathers only.
   // after_p() runs once P is no longer read (after the first barrier): a
-  // caller may start refilling P from there.
-  template <typename V, typename Out, typename Rec, typename AfterP = NoHook>
+  // caller may start refilling P from there.  before_nl() runs before the
+  // barrier that opens the Kerr phase: what it writes to P is visible to
+  // every thread after that barrier.
+  template <typename V, typename Out, typename Rec, typename AfterP = NoHook, typename BeforeNL = NoHook>
   __device__ void step(const DevOps<T>& d, const V& P, const V& X, const V& Y, T* S, T h, T tau, T gamma, Out out,
-                       Rec rec, AfterP after_p = AfterP()) const {
+                       Rec rec, AfterP after_p = AfterP(), BeforeNL before_nl = BeforeNL()) const {
     const int B = blockDim.x;
     C p[J], cur[J];
     T so[J];
@@ -1518,6 +1520,7 @@ struct StepTile {
         if (i < nNL) rec(3, rr[j], cur[j]);
       }
     }
+    before_nl();
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -2206,8 +2209,10 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_kerr_tile(DevOps<T
 // Along its run a workgroup loads a tile's operator rows into registers once
 // and steps that tile's fields one after another; the next field's state is
 // fetched into registers while the current one runs its later stages (P is
-// last read by stage 1) and moved into P after it.  LM: the M weights are
-// kept in LDS after S (the per-field state leaves them no room in registers).
+// last read by stage 1) and moved into P before the Kerr phase's barrier, so
+// that consecutive fields of a tile need no barrier between them.  LM: the M
+// weights are kept in LDS after S (the per-field state leaves them no room in
+// registers).
 template <typename T, int KMAX, bool DEC, int J, int LS, bool LM>
 __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_fields(DevOps<T> d, TileOps<T> tl,
                                                                           const typename CT<T>::C* __restrict__ in,
@@ -2247,6 +2252,9 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_fields(DevOps
       const int64_t off = int64_t(f) * d.n_rows;
       const bool more = f + 1 < f1;
       C pv[LS];
+      // the next field's state: fetched into registers once P is free, put
+      // into P before the Kerr phase's barrier (which then orders it before
+      // the next field's first gather)
       st.step(d, P, X, Y, S, h, tau, gamma, [&](int, int32_t r, const C& v) { out[off + r] = v; },
               [](int, int32_t, const C&) {},
               [&]() {
@@ -2255,15 +2263,19 @@ __global__ void __launch_bounds__((StepBound<T, J>::value)) k_step_fields(DevOps
                   for (int l = 0; l < LS; ++l)
                     if (pr[l] >= 0) pv[l] = in[off + d.n_rows + pr[l]];
                 }
-              });
-      if (more) {
+              },
+              [&]() {
+                if (more) {
 #pragma unroll
-        for (int l = 0; l < LS; ++l)
-          if (pr[l] >= 0) P.put(threadIdx.x + l * B, pv[l]);
-      }
-      // P is complete for the next field, or every read of this tile's LDS
-      // is done before the next tile's load overwrites it
-      __syncthreads();
+                  for (int l = 0; l < LS; ++l)
+                    if (pr[l] >= 0) P.put(threadIdx.x + l * B, pv[l]);
+                }
+              });
+      // every read of this tile's LDS is done before the next tile's load
+      // overwrites it (the next field of the same tile needs no barrier here:
+      // its first phase reads P, complete since the Kerr phase's barrier, and
+      // writes Y, which this field's Kerr phase does not read)
+      if (!more) __syncthreads();
     }
     u += f1 - f0;
   }
